@@ -1,0 +1,102 @@
+"""Structured (Friedrichs-Keller) triangulations of the unit square.
+
+The vertex and triangle numbering follows the paper's ``domainSquare``
+description (Sec. 3.1.2 and the routine register): vertices on an
+(n+1) x (n+1) grid numbered with the y index fastest, every square cell
+split along the diagonal from (x+h, y) to (x, y+h), all "lower-left"
+triangles first and all "upper-right" triangles after them, every triangle
+counter-clockwise.  Boundary kinds are given per local edge, local edge n
+lying opposite local vertex n (Fig. 3, eq:gammaMap).
+"""
+import numpy as np
+
+INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
+
+# side ids as in the paper's domainSquare: 1 south, 2 east, 3 north, 4 west
+SOUTH, EAST, NORTH, WEST = 1, 2, 3, 4
+
+
+def fk_square(n):
+    """Return (coordV [numV x 2], V0T [K x 3] int32, 0-based) for n x n cells."""
+    h = 1.0 / n
+    g = np.arange(n + 1) * h
+    # vertex index v = i + (n+1) j  <->  (x_j, y_i)
+    X, Y = np.meshgrid(g, g, indexing="xy")          # X[i, j] = x_j, Y[i, j] = y_i
+    coordV = np.stack([X.T.reshape(-1), Y.T.reshape(-1)], axis=1)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    base = (i + (n + 1) * j).T.reshape(-1)          # j outer, i inner
+    lower = np.stack([base, base + n + 1, base + 1], axis=1)
+    upper = np.stack([base + n + 1, base + n + 2, base + 1], axis=1)
+    V0T = np.concatenate([lower, upper], axis=0).astype(np.int32)
+    return coordV.astype(np.float64), V0T
+
+
+def jitter(coordV, n, seed, amp=0.2):
+    """Move every interior vertex by i.i.d. U[-amp*h, amp*h] per coordinate."""
+    h = 1.0 / n
+    rng = np.random.default_rng(seed)
+    c = coordV.copy()
+    xs, ys = c[:, 0], c[:, 1]
+    interior = (xs > 0.5 * h) & (xs < 1 - 0.5 * h) & (ys > 0.5 * h) & (ys < 1 - 0.5 * h)
+    d = rng.uniform(-amp * h, amp * h, size=c.shape)
+    c[interior] += d[interior]
+    return c
+
+
+def boundary_sides(coordV, V0T):
+    """Per local edge: 0 if interior, else the side id (1..4) of the boundary edge.
+
+    Local edge n joins local vertices n+1 and n+2 (mod 3)."""
+    K = V0T.shape[0]
+    a = V0T[:, [1, 2, 0]]
+    b = V0T[:, [2, 0, 1]]
+    lo = np.minimum(a, b).astype(np.int64)
+    hi = np.maximum(a, b).astype(np.int64)
+    key = lo * (coordV.shape[0] + 1) + hi
+    flat = key.reshape(-1)
+    _, inv, cnt = np.unique(flat, return_inverse=True, return_counts=True)
+    bnd = (cnt[inv] == 1).reshape(K, 3)
+    mid = 0.5 * (coordV[a] + coordV[b])              # K x 3 x 2
+    side = np.zeros((K, 3), dtype=np.int8)
+    tol = 1e-12
+    side[bnd & (np.abs(mid[..., 1]) < tol)] = SOUTH
+    side[bnd & (np.abs(mid[..., 0] - 1) < tol)] = EAST
+    side[bnd & (np.abs(mid[..., 1] - 1) < tol)] = NORTH
+    side[bnd & (np.abs(mid[..., 0]) < tol)] = WEST
+    if np.any(bnd & (side == 0)):
+        raise ValueError("boundary edge not on a side of the unit square")
+    return side
+
+
+def edge_kinds(coordV, V0T, neumann_sides=()):
+    """Per local edge kind: 0 interior, 1 Dirichlet, 2 Neumann (int8, K x 3)."""
+    side = boundary_sides(coordV, V0T)
+    kind = np.where(side > 0, DIRICHLET, INTERIOR).astype(np.int8)
+    for s in neumann_sides:
+        kind[side == s] = NEUMANN
+    return kind
+
+
+def square_mesh(n, seed=None, neumann_sides=(), amp=0.2):
+    """FK mesh of the unit square with n x n cells, optionally jittered."""
+    coordV, V0T = fk_square(n)
+    if seed is not None:
+        coordV = jitter(coordV, n, seed, amp)
+    return coordV, V0T, edge_kinds(coordV, V0T, neumann_sides)
+
+
+def two_triangle_mesh():
+    """The two-triangle grid of the visualization example (Sec. 3.8, Fig. 6).
+
+    Returns 0-based (coordV, V0T); all edges are boundary edges (Dirichlet)."""
+    s3 = np.sqrt(3.0)
+    coordV = np.array([[0.0, -1.0], [s3, 0.0], [0.0, 1.0], [-s3, 0.0]])
+    V0T = np.array([[3, 0, 2], [0, 1, 2]], dtype=np.int32)
+    kind = np.ones((2, 3), dtype=np.int8)
+    # the shared edge (vertices 0 and 2) is interior in both triangles
+    for k in range(2):
+        for n in range(3):
+            e = {int(V0T[k, (n + 1) % 3]), int(V0T[k, (n + 2) % 3])}
+            if e == {0, 2}:
+                kind[k, n] = INTERIOR
+    return coordV, V0T, kind

@@ -1,0 +1,96 @@
+"""Orthonormal modal basis on the reference triangle (Sec. 2.4.1).
+
+The paper gives the functions up to order two in closed form and up to order
+four in its basis routine.  Here every function is stored as a normalisation
+constant times a polynomial with integer coefficients, expanded by hand from
+the paper's formulas; the gradients are obtained by differentiating those
+polynomials term by term (they are pinned against the paper's printed
+gradient formulas in the tests).
+
+Basis index i is 0-based here (the paper's phi_{i+1}).
+"""
+import numpy as np
+
+# (normalisation, [(coefficient, power of x1, power of x2), ...])
+_TABLE = [
+    (np.sqrt(2.0), [(1, 0, 0)]),
+    (1.0, [(2, 0, 0), (-6, 1, 0)]),
+    (2 * np.sqrt(3.0), [(1, 0, 0), (-1, 1, 0), (-2, 0, 1)]),
+    (np.sqrt(6.0), [(1, 0, 0), (-8, 1, 0), (10, 2, 0)]),
+    (np.sqrt(3.0), [(-1, 0, 0), (-4, 1, 0), (12, 0, 1), (5, 2, 0), (-15, 0, 2)]),
+    (3 * np.sqrt(5.0), [(1, 0, 0), (-4, 1, 0), (-4, 0, 1), (3, 2, 0), (8, 1, 1), (3, 0, 2)]),
+    (2 * np.sqrt(2.0), [(-1, 0, 0), (15, 1, 0), (-45, 2, 0), (35, 3, 0)]),
+    (2 * np.sqrt(6.0), [(-1, 0, 0), (13, 1, 0), (2, 0, 1), (-33, 2, 0), (-24, 1, 1),
+                        (21, 3, 0), (42, 2, 1)]),
+    (2 * np.sqrt(10.0), [(-1, 0, 0), (9, 1, 0), (6, 0, 1), (-15, 2, 0), (-48, 1, 1),
+                         (-6, 0, 2), (7, 3, 0), (42, 2, 1), (42, 1, 2)]),
+    (2 * np.sqrt(14.0), [(-1, 0, 0), (3, 1, 0), (12, 0, 1), (-3, 2, 0), (-24, 1, 1),
+                         (-30, 0, 2), (1, 3, 0), (12, 2, 1), (30, 1, 2), (20, 0, 3)]),
+    (np.sqrt(10.0), [(1, 0, 0), (-24, 1, 0), (126, 2, 0), (-224, 3, 0), (126, 4, 0)]),
+    (np.sqrt(30.0), [(1, 0, 0), (-22, 1, 0), (-2, 0, 1), (105, 2, 0), (42, 1, 1),
+                     (-168, 3, 0), (-168, 2, 1), (84, 4, 0), (168, 3, 1)]),
+    (5 * np.sqrt(2.0), [(1, 0, 0), (-18, 1, 0), (-6, 0, 1), (69, 2, 0), (102, 1, 1),
+                        (6, 0, 2), (-88, 3, 0), (-312, 2, 1), (-96, 1, 2), (36, 4, 0),
+                        (216, 3, 1), (216, 2, 2)]),
+    (np.sqrt(70.0), [(1, 0, 0), (-12, 1, 0), (-12, 0, 1), (30, 2, 0), (132, 1, 1),
+                     (30, 0, 2), (-28, 3, 0), (-228, 2, 1), (-300, 1, 2), (-20, 0, 3),
+                     (9, 4, 0), (108, 3, 1), (270, 2, 2), (180, 1, 3)]),
+    (3 * np.sqrt(10.0), [(1, 0, 0), (-4, 1, 0), (-20, 0, 1), (6, 2, 0), (60, 1, 1),
+                         (90, 0, 2), (-4, 3, 0), (-60, 2, 1), (-180, 1, 2), (-140, 0, 3),
+                         (1, 4, 0), (20, 3, 1), (90, 2, 2), (140, 1, 3), (70, 0, 4)]),
+]
+
+MAX_P = 4
+
+
+def num_basis(p):
+    """N = (p+1)(p+2)/2 local degrees of freedom (Sec. 2.4.1)."""
+    return (p + 1) * (p + 2) // 2
+
+
+def order_of(N):
+    """Inverse of num_basis."""
+    p = int(round((np.sqrt(8 * N + 1) - 3) / 2))
+    assert num_basis(p) == N
+    return p
+
+
+def degree(i):
+    """Total polynomial degree of basis function i (0-based)."""
+    return max(a + b for _, a, b in _TABLE[i][1])
+
+
+def phi(i, x1, x2):
+    """phi_hat_{i+1}(x1, x2) on the reference triangle."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    s, terms = _TABLE[i]
+    out = np.zeros(np.broadcast(x1, x2).shape)
+    for c, a, b in terms:
+        out = out + c * x1 ** a * x2 ** b
+    return s * out
+
+
+def grad_phi(i, m, x1, x2):
+    """Component m (0 -> d/dx1, 1 -> d/dx2) of grad phi_hat_{i+1}."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    s, terms = _TABLE[i]
+    out = np.zeros(np.broadcast(x1, x2).shape)
+    for c, a, b in terms:
+        if m == 0 and a > 0:
+            out = out + c * a * x1 ** (a - 1) * x2 ** b
+        elif m == 1 and b > 0:
+            out = out + c * b * x1 ** a * x2 ** (b - 1)
+    return s * out
+
+
+def phi_all(N, x1, x2):
+    """[len(x) x N] matrix of all basis functions at the points."""
+    return np.stack([phi(i, x1, x2) for i in range(N)], axis=-1)
+
+
+def grad_phi_all(N, x1, x2):
+    """[len(x) x N x 2] gradients of all basis functions at the points."""
+    return np.stack([np.stack([grad_phi(i, m, x1, x2) for m in range(2)], axis=-1)
+                     for i in range(N)], axis=-2)

@@ -1,0 +1,181 @@
+"""Solver-level pins of the oracle: exactness, convergence, the paper's examples."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from inputs.fields import TABLE2, Workload
+from inputs.meshes import EAST, NORTH, SOUTH, WEST, square_mesh, two_triangle_mesh
+from oracle import basis
+from oracle.ldg import (Blocks, Problem, full_residual, l2_error, project, schur_matrix,
+                        step_schur)
+from oracle.mesh import Grid
+from oracle.refelem import RefTensors
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+class PolyWorkload:
+    """c = P(x, y) (1 + a t), d linear; f, c_D, g_N consistent with eq:diffusion:nonmixed."""
+
+    def __init__(self, p, a=1.0, seed=0):
+        rng = np.random.default_rng(seed)
+        self.terms = [(rng.uniform(-1, 1), i, j) for i in range(p + 1) for j in range(p + 1 - i)]
+        self.a = a
+        self.d0, self.d1, self.d2 = 1.3, 0.4, -0.3
+
+    def P(self, x, y, dx=0, dy=0):
+        out = 0 * x
+        for c, i, j in self.terms:
+            if i < dx or j < dy:
+                continue
+            fi = np.prod(range(i - dx + 1, i + 1)) if dx else 1
+            fj = np.prod(range(j - dy + 1, j + 1)) if dy else 1
+            out = out + c * fi * fj * x ** (i - dx) * y ** (j - dy)
+        return out
+
+    def c(self, t, x, y):
+        return self.P(x, y) * (1 + self.a * t)
+
+    def d(self, t, x, y):
+        return self.d0 + self.d1 * x + self.d2 * y
+
+    def f(self, t, x, y):
+        s = 1 + self.a * t
+        lap = self.P(x, y, 2, 0) + self.P(x, y, 0, 2)
+        dgc = self.d1 * self.P(x, y, 1, 0) + self.d2 * self.P(x, y, 0, 1)
+        return self.a * self.P(x, y) - s * (dgc + self.d(t, x, y) * lap)
+
+    def c_D(self, t, x, y):
+        return self.c(t, x, y)
+
+    def g_N(self, t, x, y, n1, n2):
+        s = 1 + self.a * t
+        return -s * (self.P(x, y, 1, 0) * n1 + self.P(x, y, 0, 1) * n2)
+
+    def c0(self, x, y):
+        return self.c(0.0, x, y)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_stationary_patch_exact(p):
+    # c in P_p, linear d, consistent data: the LDG solution is c itself
+    cV, V0T, kind = square_mesh(3, seed=21, neumann_sides=(SOUTH, EAST))
+    pr = Problem(cV, V0T, kind, p)
+    w = PolyWorkload(p, a=0.0, seed=p)
+    C, Z1, Z2 = pr.solve_stationary(w)
+    Cex = project(pr.grid, p, lambda x, y: w.c(0, x, y), pr.refs.hatM, order=2 * p + 2)
+    np.testing.assert_allclose(C, Cex, atol=1e-11)
+    Zex = project(pr.grid, p, lambda x, y: -w.P(x, y, 1, 0), pr.refs.hatM, order=2 * p + 2)
+    np.testing.assert_allclose(Z1, Zex, atol=1e-10)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_implicit_euler_exact_for_linear_in_time(p):
+    # c = P(x)(1+t): implicit Euler reproduces c at every step (eq:fullSystem)
+    cV, V0T, kind = square_mesh(3, seed=31, neumann_sides=(NORTH,))
+    pr = Problem(cV, V0T, kind, p)
+    w = PolyWorkload(p, a=2.0, seed=10 + p)
+    C = pr.initial(w)
+    t, tau = 0.0, 0.05
+    for _ in range(3):
+        t += tau
+        C, Z1, Z2, info = pr.step(C, t, tau, w)
+        assert info["rel_residual"] < 1e-12
+        Cex = project(pr.grid, p, lambda x, y: w.c(t, x, y), pr.refs.hatM, order=2 * p + 2)
+        np.testing.assert_allclose(C, Cex, atol=1e-10)
+
+
+def test_z_history_does_not_enter_the_step():
+    # W has zero Z rows, so Y^{n+1} depends on C^n only
+    cV, V0T, kind = square_mesh(2, seed=3)
+    pr = Problem(cV, V0T, kind, 2)
+    w = PolyWorkload(2, a=1.0)
+    C0 = pr.initial(w)
+    C1, Z1, Z2, info = pr.step(C0, 0.1, 0.1, w)
+    from oracle.ldg import mass_W
+    W = mass_W(info["blocks"])
+    KN = C0.size
+    Ya = np.concatenate([np.zeros(2 * KN), C0.reshape(-1)])
+    Yb = np.concatenate([np.random.default_rng(1).standard_normal(2 * KN), C0.reshape(-1)])
+    np.testing.assert_array_equal(W @ Ya, W @ Yb)
+
+
+@pytest.mark.parametrize("neumann", [(), (SOUTH, NORTH), (EAST, WEST, SOUTH)])
+def test_constant_d_adjointness(neumann):
+    # constant d, exact tensors: B^m = -d (A^m)^T, so the Schur complement is SPD
+    cV, V0T, kind = square_mesh(3, seed=41, neumann_sides=neumann)
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(2)
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = 2.5 / np.sqrt(2)
+    b = Blocks(g, refs, D)
+    for m in range(2):
+        A = (-b.H[m] + b.Q[m] + b.QN[m]).toarray()
+        B = (-b.G[m] + b.R[m] + b.RD[m]).toarray()
+        np.testing.assert_allclose(B, -2.5 * A.T, atol=1e-12)
+    S = schur_matrix(b, g, refs, 1.0, 0.01).toarray()
+    np.testing.assert_allclose(S, S.T, atol=1e-12)
+    assert np.linalg.eigvalsh(S).min() > 0
+
+
+def test_schur_elimination_equals_full_solve():
+    cV, V0T, kind = square_mesh(4, seed=51, neumann_sides=(SOUTH,))
+    pr = Problem(cV, V0T, kind, 2)
+    w = Workload(TABLE2)
+    w.stationary = False                      # time dependent use of the same fields
+    C0 = pr.initial(w)
+    Ca, Z1a, Z2a, _ = pr.step(C0, 0.01, 0.01, w)
+    Cb, Z1b, Z2b, info = step_schur(pr, C0, 0.01, 0.01, w)
+    np.testing.assert_allclose(Cb, Ca, atol=1e-12)
+    np.testing.assert_allclose(Z1b, Z1a, atol=1e-10)
+    np.testing.assert_allclose(Z2b, Z2a, atol=1e-10)
+    assert full_residual(pr, info["blocks"], info["data"], 0.01, C0, Cb, Z1b, Z2b) < 1e-12
+
+
+def _table2_errors(p, levels):
+    w = Workload(TABLE2)
+    errs = []
+    for j in levels:
+        n = 3 * 2 ** j
+        cV, V0T, kind = square_mesh(n, neumann_sides=(SOUTH, NORTH))
+        pr = Problem(cV, V0T, kind, p)
+        C, _, _ = pr.solve_stationary(w)
+        errs.append(l2_error(pr.grid, C, lambda x, y: w.c(0, x, y)))
+    return errs
+
+
+@pytest.mark.parametrize("p,levels", [(1, [1, 2, 3]), (2, [1, 2, 3]), (3, [0, 1, 2]), (4, [0, 1, 2])])
+def test_table2_convergence_rates(p, levels):
+    # Table 2: order p+1 for p >= 1 (the paper's asymptotic rates: 2.00, 3.04, 4.01, 4.94)
+    with open(os.path.join(GOLDEN, "table2.json")) as fh:
+        tab = json.load(fh)
+    errs = _table2_errors(p, levels)
+    rate = np.log(errs[-2] / errs[-1]) / np.log(2)
+    assert abs(rate - tab["final_rate"][str(p)]) < 0.35, (errs, rate)
+
+
+def test_table2_p0_stagnates():
+    # Table 2, p = 0: the error does not decay (stays near 0.1)
+    errs = _table2_errors(0, [2, 3, 4])
+    assert min(errs) > 0.08
+    rate = np.log(errs[-2] / errs[-1]) / np.log(2)
+    assert rate < 0.5
+
+
+def test_fig7_projection_ranges():
+    # Sec. 3.8 / Fig. 7: ranges of the projected function at the Lagrange nodes
+    with open(os.path.join(GOLDEN, "fig7_ranges.json")) as fh:
+        ranges = json.load(fh)["ranges"]
+    cV, V0T, kind = two_triangle_mesh()
+    g = Grid(cV, V0T, kind)
+    fAlg = lambda x, y: np.where(x < 0, x ** 2 - y ** 2 - 1, -x ** 2 - y ** 2 + 1)
+    nodes = {1: ([1 / 3], [1 / 3]), 3: ([0, 1, 0], [0, 0, 1]),
+             6: ([0, 1, 0, 0.5, 0, 0.5], [0, 0, 1, 0.5, 0.5, 0])}
+    for N, (lo, hi) in zip((1, 3, 6), ranges):
+        p = basis.order_of(N)
+        D = project(g, p, fAlg, RefTensors(p).hatM, order=6)
+        L1, L2 = nodes[N]
+        vals = D @ basis.phi_all(N, np.array(L1, float), np.array(L2, float)).T
+        assert abs(vals.min() - lo) < 1e-12 and abs(vals.max() - hi) < 1e-12, (N, vals)
