@@ -1,0 +1,203 @@
+/*
+ * ldg.h -- C ABI of the MI355X (gfx950) LDG diffusion hot path.
+ *
+ * Method: local discontinuous Galerkin discretisation of the 2D diffusion
+ * equation  dt c - div(d grad c) = f  with Dirichlet/Neumann data (Sec. 1.3,
+ * eq:diffusion:nonmixed) in the mixed form z = -grad c (Sec. 2.2), modal
+ * orthonormal bases of order p = 0..4 (Sec. 2.4.1), the global block system
+ * eq:timeDepSystem and one implicit Euler step per call (eq:fullSystem):
+ *     (W + dt A(t+dt)) Y = W Y^n + dt V(t+dt),   Y = [Z1; Z2; C].
+ * The linear system of each step is solved by right-preconditioned restarted
+ * GMRES on the system for C obtained by eliminating Z (M is block diagonal,
+ * M_k = 2|T_k| I, eq:hatM), stopping on the relative residual of the full
+ * 3KN system.
+ *
+ * Conventions
+ *   - Element k, basis index i (0-based): vectors are "element-major",
+ *     value (k, i) at k*N + i, N = (p+1)(p+2)/2.  Outputs keep the caller's
+ *     element order.
+ *   - Local edge n of triangle k joins its local vertices n+1 and n+2 (mod 3)
+ *     (edge n lies opposite vertex n, Fig. 3 and eq:gammaMap).
+ *   - Triangles must be counter-clockwise (det B_k = 2|T_k| > 0, Sec. 3.2).
+ *   - "device" pointers are HIP device memory on the context's device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns every pointer it
+ *     passes; the library never keeps or frees caller memory after a call.
+ *   - All device work is enqueued on options.stream (a hipStream_t, NULL =
+ *     the default stream).  Calls that return numbers to the host
+ *     synchronise that stream.
+ *   - Every entry point returns an ldg_status; nothing throws or aborts
+ *     across the ABI.  ldg_last_error() describes the last failure of a
+ *     context.
+ */
+#ifndef LDG_H
+#define LDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldg_ctx ldg_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  LDG_OK = 0,
+  LDG_EINVAL = -1,    /* bad argument: NULL pointer, p outside 0..4, eta <= 0, dt <= 0, ... */
+  LDG_EMESH = -2,     /* orientation, conformity or edge kinds inconsistent */
+  LDG_ENOMEM = -3,    /* device allocation failed */
+  LDG_EDEVICE = -4,   /* a HIP call failed */
+  LDG_ENOCONV = -5,   /* the solver did not reach rtol; the state is not advanced */
+  LDG_EUNSUPPORTED = -6
+} ldg_status;
+
+typedef enum { LDG_FP64 = 0, LDG_MIXED_FP32 = 1, LDG_MIXED_BF16 = 2 } ldg_precision;
+typedef enum { LDG_PC_BLOCK_JACOBI = 0, LDG_PC_GNN = 1 } ldg_precond;
+typedef enum { LDG_EDGE_INTERIOR = 0, LDG_EDGE_DIRICHLET = 1, LDG_EDGE_NEUMANN = 2 } ldg_edge_kind;
+
+typedef struct {
+  int p;              /* polynomial order 0..4 (assert in the main script) */
+  double eta;         /* penalty eta > 0 (prob:semidiscrete), default 1 */
+  int precision;      /* ldg_precision, default LDG_FP64 */
+  int precond;        /* ldg_precond, default LDG_PC_BLOCK_JACOBI */
+  double rtol;        /* relative residual of the full system, default 1e-8 */
+  int restart;        /* GMRES restart length m, default 30 */
+  int max_iters;      /* total Krylov iterations per step, default 5000 */
+  void* stream;       /* hipStream_t for all device work */
+} ldg_options;
+
+typedef struct {
+  int64_t K;          /* triangles */
+  int N;              /* local basis functions */
+  int R;              /* volume quadrature points per triangle (projection rule, order max(2p,1)) */
+  int R1;             /* Gauss points per boundary edge (order 2p+1) */
+  int64_t n_bnd;      /* boundary edges */
+  int64_t E_int;      /* interior edges */
+} ldg_sizes;
+
+typedef struct {
+  int iters;           /* Krylov iterations of the step (inner ones in the mixed modes) */
+  int restarts;        /* GMRES cycles */
+  int ir_steps;        /* outer refinement sweeps (mixed modes), 0 in FP64 */
+  int fallbacks;       /* preconditioner fallbacks taken */
+  double rel_residual; /* ||b - (W + dt A) Y|| / ||b|| of the full system, FP64 */
+  double t;            /* time level reached */
+} ldg_step_info;
+
+/* Fill *opt with the defaults listed above. */
+ldg_status ldg_options_default(ldg_options* opt);
+
+/*
+ * Build a context from a triangulation (Sec. 3.1, Table 1).
+ *   coordV    host, numV x 2 vertex coordinates
+ *   V0T       host, K x 3 counter-clockwise vertex indices, 0-based
+ *   edge_kind host, K x 3 ldg_edge_kind per local edge
+ * Computes the grid lists and the reference tensors once (convention 1 of
+ * Sec. 3: stationary data is computed only once), uploads them and
+ * allocates every device buffer the steps need.  The state starts at t = 0
+ * with C = 0.  Errors: EINVAL, EMESH (non-positive area, an edge shared by
+ * more than two triangles or traversed twice in one direction, a kind that
+ * disagrees with the topology), ENOMEM, EDEVICE.
+ */
+ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, int64_t K,
+                      const int8_t* edge_kind, const ldg_options* opt, ldg_ctx** out);
+void ldg_destroy(ldg_ctx* ctx);
+const char* ldg_last_error(const ldg_ctx* ctx);
+ldg_status ldg_get_sizes(const ldg_ctx* ctx, ldg_sizes* out);
+
+/*
+ * Physical coordinates of the points where the caller samples its data.
+ *   kind 0: volume points of the projection rule, layout [R][K]
+ *           (point r of triangle k at r*K + k);
+ *   kind 1: Gauss points of the boundary edges, layout [R1][n_bnd], the
+ *           boundary edges ordered by (triangle, local edge);
+ *   kind 2: (boundary only) exterior unit normal at those points.
+ * x, y: device, caller-allocated with the sizes above.
+ */
+ldg_status ldg_quad_points(ldg_ctx* ctx, int kind, double* x, double* y);
+
+/*
+ * L2 projection (Sec. 3.4): out = samples * (w o phi_hat) M_hat^{-1}, one
+ * N-vector per triangle.  samples: device [R][K] values of a function at
+ * the kind-0 points; out: device K x N, element-major.
+ */
+ldg_status ldg_project(ldg_ctx* ctx, const double* samples, double* out);
+
+/* Set the state: C (K x N, element-major) and the time level t. */
+ldg_status ldg_set_state(ldg_ctx* ctx, const double* C, int on_device, double t);
+/* Initial state as the L2 projection of c0 sampled at the kind-0 points. */
+ldg_status ldg_set_initial_samples(ldg_ctx* ctx, const double* c0_samples, double t0);
+
+/*
+ * One implicit Euler step t -> t + dt (eq:fullSystem, data at t + dt):
+ *   d, f    device [R][K]     diffusion coefficient and source at the kind-0 points
+ *   cD, gN  device [R1][n_bnd] Dirichlet / Neumann data at the kind-1 points
+ *           (values on edges of the other kind are ignored; gN may be NULL
+ *           when there is no Neumann edge, cD when there is no Dirichlet edge)
+ * Runs projection, block assembly, preconditioner setup, the Krylov solve
+ * and the recovery of Z on the device.  On LDG_ENOCONV the state is left
+ * unchanged and *info describes the failed solve.
+ */
+ldg_status ldg_step_sampled(ldg_ctx* ctx, double dt, const double* d, const double* f,
+                            const double* cD, const double* gN, ldg_step_info* info);
+
+/* Current C, Z1, Z2 (K x N each, element-major, caller's element order). Any may be NULL. */
+ldg_status ldg_get_solution(ldg_ctx* ctx, double* C, double* Z1, double* Z2, int on_device);
+
+/* ---- entry points of the individual steps of the path (used by the tests) ---- */
+
+/*
+ * Assemble the D-dependent blocks (Sec. 3.6.3, 3.6.6, 3.6.7) from a
+ * projected coefficient D (device, K x N):
+ *   slot 0, 1: B^m_kk = -G^m_k + R^{m,diag}_k + R^m_{D,k}        (m = 1, 2)
+ *   slot 2+n : U_kn = 1/2 |E_kn| sum_l D_{k+ l} R_hat_off(:,:,l,n,n+),
+ *              so that R^m_{k k+} = nu^m_kn U_kn (eq:globR:offdiag);
+ *              zero for boundary edges.
+ * The blocks stay in the context; ldg_get_blocks copies them out as
+ * device K x 5 x N x N (element, slot, row i, column j).
+ */
+ldg_status ldg_assemble(ldg_ctx* ctx, const double* D);
+ldg_status ldg_get_blocks(ldg_ctx* ctx, double* out);
+
+/*
+ * Operator of the eliminated system with the blocks of the last
+ * ldg_assemble: y = M C + dt (eta (S + S_D) C - sum_m B^m M^{-1} A^m C),
+ * A^m = -H^m + Q^m + Q^m_N, B^m = -G^m + R^m + R^m_D (eq:timeDepSystem).
+ * C, y: device K x N.
+ */
+ldg_status ldg_apply_schur(ldg_ctx* ctx, double dt, const double* C, double* y);
+
+/*
+ * Full operator of eq:fullSystem: out = (W + dt A) Y for Y = [Z1; Z2; C]
+ * (device, 3 K N, each part element-major), blocks of the last ldg_assemble.
+ */
+ldg_status ldg_apply_full(ldg_ctx* ctx, double dt, const double* Y, double* out);
+
+/*
+ * Block-Jacobi preconditioner: inverses of the K diagonal N x N blocks of
+ * the eliminated operator above (device, K x N x N), for step size dt.
+ */
+ldg_status ldg_bj_setup(ldg_ctx* ctx, double dt);
+ldg_status ldg_get_bj(ldg_ctx* ctx, double* out);
+
+/*
+ * Synthetic benchmark data: samples of the analytic fields of a workload at
+ * the kind-0 / kind-1 points at time t (not part of the method; it stands in
+ * for a caller's coefficient functions).
+ *   kind   1: d = 1 + sin(pi x) cos(pi y) exp(-t)/2
+ *          2: d = exp(sin(2 pi x) sin(2 pi y)/2) (1 + t/10)
+ *          3: d = blocks[bx, by]           (piecewise constant)
+ *          4: d = blocks[bx, by] (1 + sin(t)/10)
+ *          5: d = exp(x + y), stationary c
+ *   c = cos(7x) cos(7y) exp(-t) (kind 5: without exp(-t)), f = dt c - div(d grad c)
+ *   (inside each block for kinds 3, 4), c_D = c, g_N = -grad c . nu.
+ *   blocks: device nb x nb (bx major), cells per block side `block`,
+ *   n_cells cells per side of the unit square.  Any output may be NULL.
+ */
+ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* blocks, int nb,
+                               int block, int n_cells, double* d, double* f, double* cD,
+                               double* gN, double* c0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDG_H */

@@ -1,0 +1,562 @@
+// C ABI of the LDG library: context, data upload, one implicit Euler step
+// (projection, assembly, preconditioner, restarted GMRES, recovery of Z).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace ldg;
+
+struct ldg_ctx {
+  std::string err;
+  ldg_options opt{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  int p = 0, N = 1, NN = 1, NP = 1, R = 1, R1 = 1;
+  int64_t K = 0, Kpad = 0, nbnd = 0, nbe = 0, Eint = 0, nvec = 0;
+  RefData ref;
+  Geo geo{};
+  std::vector<void*> allocs;
+  // geometry
+  double *area2 = nullptr, *B = nullptr, *a1 = nullptr, *elen = nullptr, *nu = nullptr;
+  int32_t *nbr = nullptr, *bidx = nullptr, *belem = nullptr, *bk = nullptr;
+  int8_t *nbrn = nullptr, *kind = nullptr, *bn = nullptr;
+  // reference data
+  double *refs = nullptr, *Tg = nullptr, *Trd = nullptr, *Tro = nullptr;
+  double *Wvol = nullptr, *qvol = nullptr, *Wb = nullptr, *ws = nullptr, *sb = nullptr;
+  // state and work, element-fastest layout
+  double *C = nullptr, *Z1 = nullptr, *Z2 = nullptr, *D = nullptr, *F = nullptr;
+  double *J1 = nullptr, *J2 = nullptr, *KDN = nullptr, *b3 = nullptr;
+  double *r = nullptr, *w = nullptr, *z = nullptr, *u = nullptr, *X = nullptr;
+  double *tZ1 = nullptr, *tZ2 = nullptr, *tmp = nullptr;
+  double *blocks = nullptr, *bj = nullptr, *V = nullptr;
+  double *hdev = nullptr, *ydev = nullptr;
+  int* status = nullptr;
+  Reducer red, red2;
+  double* host_buf = nullptr;  // pinned
+  int mmax = 0;
+  double t = 0.0;
+  bool blocks_ready = false;
+};
+
+namespace {
+
+ldg_status fail(ldg_ctx* c, ldg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, LDG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+ldg_status dalloc(ldg_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, LDG_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return LDG_OK;
+}
+
+template <class T>
+ldg_status upload(ldg_ctx* c, T* dst, const std::vector<T>& src) {
+  if (src.empty()) return LDG_OK;
+  HIPCHK(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+  return LDG_OK;
+}
+
+#define TRY(expr)                      \
+  do {                                 \
+    ldg_status s_ = (expr);            \
+    if (s_ != LDG_OK) return s_;       \
+  } while (0)
+
+ldg_status check_launch(ldg_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, LDG_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LDG_OK;
+}
+
+ldg_status sync(ldg_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LDG_OK;
+}
+
+// ---- operator pieces -------------------------------------------------------
+// y = M x + tau (eta S' x + sum_m B^m Zx^m), Zx^m = -M^{-1}(A^m x + [J^m])
+void apply_op(ldg_ctx* c, double tau, const double* x, bool with_j, double* Zx1, double* Zx2,
+              double* y) {
+  launch_grad(c->N, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr, Zx1,
+              Zx2, c->st);
+  launch_div(c->N, c->geo, c->refs, c->blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y, c->st);
+}
+
+// host copy of Reducer results
+ldg_status fetch(ldg_ctx* c, const double* dev, int n, double* host) {
+  HIPCHK(c, hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  return LDG_OK;
+}
+
+ldg_status dot_self(ldg_ctx* c, const double* x, double* out) {
+  launch_dots(c->red, c->nvec, 0, nullptr, 0, x, c->st);
+  TRY(check_launch(c));
+  return fetch(c, c->red.result, 1, out);
+}
+
+// ---- restarted, right-preconditioned GMRES on the eliminated system ---------
+// Solves for C: b3 - [M C + tau(eta S' C + sum_m B^m Z^m(C))] = 0 with
+// Z^m(C) = -M^{-1}(A^m C + J^m_D); the residual is that of row block 3 of
+// the full system, rows 1 and 2 holding exactly by the recovery of Z.
+ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
+  const int64_t n = c->nvec;
+  const int m = c->opt.restart;
+  const double target = c->opt.rtol * bnorm;
+  std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  double* hb = c->host_buf;
+  int iters = 0, cycles = 0;
+  double beta = 0.0;
+  // true residual of the start value
+  apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
+  launch_axpby(n, 1.0, c->b3, -1.0, c->w, c->st);   // w = b3 - F(X)
+  TRY(dot_self(c, c->w, hb));
+  beta = std::sqrt(hb[0]);
+  while (true) {
+    if (!std::isfinite(beta)) return fail(c, LDG_ENOCONV, "non-finite residual");
+    if (beta <= target) break;
+    if (iters >= c->opt.max_iters) break;
+    ++cycles;
+    // V0 = w / beta
+    launch_axpby(n, 1.0 / beta, c->w, 0.0, c->V, c->st);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = c->V + (int64_t)j * n;
+      double* vn = c->V + (int64_t)(j + 1) * n;
+      launch_bj_apply(c->N, c->geo, c->bj, vj, nullptr, 0, c->z, c->st);
+      apply_op(c, tau, c->z, false, c->tZ1, c->tZ2, vn);
+      // classical Gram-Schmidt with one conditional re-orthogonalisation
+      launch_dots(c->red, n, j + 1, c->V, n, vn, c->st);
+      launch_update(c->red2, n, j + 1, c->V, n, c->red.result, vn, c->st);
+      TRY(check_launch(c));
+      HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      TRY(sync(c));
+      double wn0 = std::sqrt(hb[j + 1]);
+      double wn = std::sqrt(hb[m + 2]);
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i];
+      if (wn < 0.7 * wn0) {
+        launch_dots(c->red, n, j + 1, c->V, n, vn, c->st);
+        launch_update(c->red2, n, j + 1, c->V, n, c->red.result, vn, c->st);
+        HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
+        TRY(sync(c));
+        for (int i = 0; i <= j; ++i) H[i * m + j] += hb[i];
+        wn = std::sqrt(hb[m + 2]);
+      }
+      H[(j + 1) * m + j] = wn;
+      if (wn > 0.0) launch_axpby(n, 1.0 / wn, vn, 0.0, vn, c->st);
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[j * m + j], b = H[(j + 1) * m + j];
+      const double rr = std::hypot(a, b);
+      cs[j] = rr > 0.0 ? a / rr : 1.0;
+      sn[j] = rr > 0.0 ? b / rr : 0.0;
+      H[j * m + j] = rr;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++iters;
+      jend = j + 1;
+      if (!std::isfinite(g[j + 1])) return fail(c, LDG_ENOCONV, "non-finite Krylov residual");
+      if (std::fabs(g[j + 1]) <= target || iters >= c->opt.max_iters || wn == 0.0) break;
+    }
+    // y = H^{-1} g, X += P^{-1} V y
+    for (int i = jend - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
+      y[i] = s / H[i * m + i];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, c->st));
+    launch_lincomb(n, jend, c->V, n, c->ydev, c->u, c->st);
+    launch_bj_apply(c->N, c->geo, c->bj, c->u, nullptr, 0, c->z, c->st);
+    launch_axpby(n, 1.0, c->z, 1.0, c->X, c->st);
+    // true residual
+    apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
+    launch_axpby(n, 1.0, c->b3, -1.0, c->w, c->st);
+    TRY(dot_self(c, c->w, hb));
+    beta = std::sqrt(hb[0]);
+  }
+  info->iters = iters;
+  info->restarts = cycles;
+  info->rel_residual = beta / bnorm;
+  if (!(beta <= target))
+    return fail(c, LDG_ENOCONV, "GMRES reached " + std::to_string(iters) +
+                                    " iterations at relative residual " +
+                                    std::to_string(beta / bnorm));
+  return LDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ldg_status ldg_options_default(ldg_options* o) {
+  if (!o) return LDG_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->p = 1;
+  o->eta = 1.0;
+  o->precision = LDG_FP64;
+  o->precond = LDG_PC_BLOCK_JACOBI;
+  o->rtol = 1e-8;
+  o->restart = 30;
+  o->max_iters = 5000;
+  o->stream = nullptr;
+  return LDG_OK;
+}
+
+const char* ldg_last_error(const ldg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void ldg_destroy(ldg_ctx* c) {
+  if (!c) return;
+  if (c->st) hipStreamSynchronize(c->st);
+  for (void* p : c->allocs) hipFree(p);
+  if (c->host_buf) hipHostFree(c->host_buf);
+  delete c;
+}
+
+ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, int64_t K,
+                      const int8_t* edge_kind, const ldg_options* opt, ldg_ctx** out) {
+  if (!out) return LDG_EINVAL;
+  *out = nullptr;
+  if (!coordV || !V0T || !edge_kind || !opt) return LDG_EINVAL;
+  if (opt->p < 0 || opt->p > 4 || !(opt->eta > 0.0) || !(opt->rtol > 0.0) || opt->restart < 1 ||
+      opt->restart > 200 || opt->max_iters < 1)
+    return LDG_EINVAL;
+  if (opt->precision != LDG_FP64 || opt->precond != LDG_PC_BLOCK_JACOBI) return LDG_EUNSUPPORTED;
+  ldg_ctx* c = new ldg_ctx();
+  *out = c;
+  c->opt = *opt;
+  c->st = static_cast<hipStream_t>(opt->stream);
+  HIPCHK(c, hipGetDevice(&c->device));
+  HostMesh hm;
+  bool mesh_err = false;
+  const std::string msg = build_mesh(coordV, numV, V0T, K, edge_kind, hm, &mesh_err);
+  if (!msg.empty()) return fail(c, mesh_err ? LDG_EMESH : LDG_EINVAL, msg);
+  c->ref = build_refdata(opt->p);
+  const RefData& rf = c->ref;
+  for (int i = 0; i < rf.N; ++i)
+    for (int j = 0; j < rf.N; ++j)
+      if (std::fabs(rf.M[i * rf.N + j] - (i == j ? 1.0 : 0.0)) > 1e-12)
+        return fail(c, LDG_EINVAL, "reference mass matrix is not the identity");
+  c->p = opt->p;
+  c->N = rf.N;
+  c->NN = rf.NN;
+  c->NP = npairs(rf.N);
+  c->R = rf.R;
+  c->R1 = rf.R1;
+  c->K = hm.K;
+  c->Kpad = hm.Kpad;
+  c->nbnd = (int64_t)hm.bedge_k.size();
+  c->nbe = (int64_t)hm.belem.size();
+  c->Eint = hm.E_int;
+  c->nvec = c->Kpad * c->N;
+  c->mmax = opt->restart;
+  const int64_t Kp = c->Kpad;
+  const int N = c->N, NN = c->NN;
+  // geometry
+  TRY(dalloc(c, &c->area2, Kp));
+  TRY(dalloc(c, &c->B, 4 * Kp));
+  TRY(dalloc(c, &c->a1, 2 * Kp));
+  TRY(dalloc(c, &c->elen, 3 * Kp));
+  TRY(dalloc(c, &c->nu, 6 * Kp));
+  TRY(dalloc(c, &c->nbr, 3 * Kp));
+  TRY(dalloc(c, &c->bidx, 3 * Kp));
+  TRY(dalloc(c, &c->nbrn, 3 * Kp));
+  TRY(dalloc(c, &c->kind, 3 * Kp));
+  TRY(dalloc(c, &c->belem, c->nbe));
+  TRY(dalloc(c, &c->bk, c->nbnd));
+  TRY(dalloc(c, &c->bn, c->nbnd));
+  TRY(upload(c, c->area2, hm.area2));
+  TRY(upload(c, c->B, hm.B));
+  TRY(upload(c, c->a1, hm.a1));
+  TRY(upload(c, c->elen, hm.elen));
+  TRY(upload(c, c->nu, hm.nu));
+  TRY(upload(c, c->nbr, hm.nbr));
+  TRY(upload(c, c->bidx, hm.bidx));
+  TRY(upload(c, c->nbrn, hm.nbrn));
+  TRY(upload(c, c->kind, hm.kind));
+  TRY(upload(c, c->belem, hm.belem));
+  TRY(upload(c, c->bk, hm.bedge_k));
+  TRY(upload(c, c->bn, hm.bedge_n));
+  c->geo = Geo{c->K, c->Kpad, c->area2, c->B, c->a1, c->elen, c->nu, c->nbr, c->nbrn, c->kind, c->bidx};
+  // reference data
+  std::vector<double> refs(14 * NN), Tg(2 * N * NN), Trd(3 * N * NN), Tro(9 * N * NN);
+  for (int f = 0; f < NN; ++f) {
+    refs[0 * NN + f] = rf.H[0][f];
+    refs[1 * NN + f] = rf.H[1][f];
+    for (int n = 0; n < 3; ++n) refs[(2 + n) * NN + f] = rf.Sd[n][f];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) refs[(5 + 3 * a + b) * NN + f] = rf.So[a][b][f];
+  }
+  for (int m = 0; m < 2; ++m) std::copy(rf.G[m].begin(), rf.G[m].end(), Tg.begin() + m * N * NN);
+  for (int n = 0; n < 3; ++n) std::copy(rf.Rd[n].begin(), rf.Rd[n].end(), Trd.begin() + n * N * NN);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      std::copy(rf.Ro[a][b].begin(), rf.Ro[a][b].end(), Tro.begin() + (3 * a + b) * N * NN);
+  std::vector<double> Wvol(c->R * N), qv(2 * c->R), Wb(3 * c->R1 * N);
+  for (int r = 0; r < c->R; ++r) {
+    qv[2 * r] = rf.q1[r];
+    qv[2 * r + 1] = rf.q2[r];
+    for (int i = 0; i < N; ++i) Wvol[r * N + i] = rf.w[r] * phi_hat(i, rf.q1[r], rf.q2[r]);
+  }
+  for (int n = 0; n < 3; ++n)
+    for (int r = 0; r < c->R1; ++r) {
+      const double s = rf.s[r];
+      double x1 = n == 0 ? 1.0 - s : (n == 1 ? 0.0 : s);
+      double x2 = n == 0 ? s : (n == 1 ? 1.0 - s : 0.0);
+      for (int i = 0; i < N; ++i) Wb[(n * c->R1 + r) * N + i] = phi_hat(i, x1, x2);
+    }
+  TRY(dalloc(c, &c->refs, refs.size()));
+  TRY(dalloc(c, &c->Tg, Tg.size()));
+  TRY(dalloc(c, &c->Trd, Trd.size()));
+  TRY(dalloc(c, &c->Tro, Tro.size()));
+  TRY(dalloc(c, &c->Wvol, Wvol.size()));
+  TRY(dalloc(c, &c->qvol, qv.size()));
+  TRY(dalloc(c, &c->Wb, Wb.size()));
+  TRY(dalloc(c, &c->ws, rf.ws.size()));
+  TRY(dalloc(c, &c->sb, rf.s.size()));
+  TRY(upload(c, c->refs, refs));
+  TRY(upload(c, c->Tg, Tg));
+  TRY(upload(c, c->Trd, Trd));
+  TRY(upload(c, c->Tro, Tro));
+  TRY(upload(c, c->Wvol, Wvol));
+  TRY(upload(c, c->qvol, qv));
+  TRY(upload(c, c->Wb, Wb));
+  TRY(upload(c, c->ws, rf.ws));
+  TRY(upload(c, c->sb, rf.s));
+  // state and work vectors
+  const int64_t nv = c->nvec;
+  double** vecs[] = {&c->C, &c->Z1, &c->Z2, &c->D, &c->F, &c->J1, &c->J2, &c->KDN, &c->b3,
+                     &c->r, &c->w, &c->z, &c->u, &c->X, &c->tZ1, &c->tZ2, &c->tmp};
+  for (double** v : vecs) {
+    TRY(dalloc(c, v, nv));
+    HIPCHK(c, hipMemsetAsync(*v, 0, nv * sizeof(double), c->st));
+  }
+  TRY(dalloc(c, &c->blocks, (size_t)Kp * NSLOT * c->NP * 2));
+  TRY(dalloc(c, &c->bj, (size_t)Kp * c->NP * 2));
+  TRY(dalloc(c, &c->V, (size_t)(c->mmax + 1) * nv));
+  TRY(dalloc(c, &c->hdev, c->mmax + 2));
+  TRY(dalloc(c, &c->ydev, c->mmax + 2));
+  TRY(dalloc(c, &c->status, 1));
+  c->red.nblk = c->red2.nblk = krylov_nblk(nv);
+  c->red.maxv = c->red2.maxv = c->mmax + 1;
+  TRY(dalloc(c, &c->red.partials, (size_t)(c->mmax + 2) * c->red.nblk));
+  TRY(dalloc(c, &c->red.result, c->mmax + 2));
+  TRY(dalloc(c, &c->red2.partials, (size_t)c->red2.nblk));
+  TRY(dalloc(c, &c->red2.result, 1));
+  HIPCHK(c, hipHostMalloc((void**)&c->host_buf, (2 * c->mmax + 8) * sizeof(double)));
+  TRY(sync(c));
+  c->t = 0.0;
+  c->err.clear();
+  return LDG_OK;
+}
+
+ldg_status ldg_get_sizes(const ldg_ctx* c, ldg_sizes* o) {
+  if (!c || !o) return LDG_EINVAL;
+  o->K = c->K;
+  o->N = c->N;
+  o->R = c->R;
+  o->R1 = c->R1;
+  o->n_bnd = c->nbnd;
+  o->E_int = c->Eint;
+  return LDG_OK;
+}
+
+ldg_status ldg_quad_points(ldg_ctx* c, int kind, double* x, double* y) {
+  if (!c || !x || !y || kind < 0 || kind > 2) return fail(c, LDG_EINVAL, "bad arguments");
+  if (kind == 0)
+    launch_sample_vol(c->geo, c->R, c->qvol, 0, 0.0, nullptr, 1, 1.0, nullptr, nullptr, nullptr, x,
+                      y, c->st);
+  else
+    launch_sample_bnd(c->geo, c->R1, c->sb, c->nbnd, c->bk, c->bn, kind == 2 ? -1 : 0, 0.0,
+                      nullptr, 1, 1.0, nullptr, nullptr, x, y, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_project(ldg_ctx* c, const double* samples, double* out) {
+  if (!c || !samples || !out) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_project(c->N, c->K, c->Kpad, c->R, samples, c->Wvol, c->tmp, c->st);
+  launch_from_tiled(c->K, c->N, c->tmp, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_set_state(ldg_ctx* c, const double* C, int on_device, double t) {
+  if (!c || !C) return fail(c, LDG_EINVAL, "bad arguments");
+  const double* src = C;
+  if (!on_device) {
+    HIPCHK(c, hipMemcpyAsync(c->u, C, c->K * c->N * sizeof(double), hipMemcpyHostToDevice, c->st));
+    src = c->u;
+  }
+  launch_to_tiled(c->K, c->Kpad, c->N, src, c->C, c->st);
+  c->t = t;
+  TRY(check_launch(c));
+  return sync(c);
+}
+
+ldg_status ldg_set_initial_samples(ldg_ctx* c, const double* c0, double t0) {
+  if (!c || !c0) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_project(c->N, c->K, c->Kpad, c->R, c0, c->Wvol, c->C, c->st);
+  c->t = t0;
+  return check_launch(c);
+}
+
+ldg_status ldg_get_solution(ldg_ctx* c, double* C, double* Z1, double* Z2, int on_device) {
+  if (!c) return LDG_EINVAL;
+  const size_t bytes = c->K * c->N * sizeof(double);
+  double* srcs[3] = {c->C, c->Z1, c->Z2};
+  double* dsts[3] = {C, Z1, Z2};
+  for (int q = 0; q < 3; ++q) {
+    if (!dsts[q]) continue;
+    if (on_device) {
+      launch_from_tiled(c->K, c->N, srcs[q], dsts[q], c->st);
+    } else {
+      launch_from_tiled(c->K, c->N, srcs[q], c->u, c->st);
+      HIPCHK(c, hipMemcpyAsync(dsts[q], c->u, bytes, hipMemcpyDeviceToHost, c->st));
+    }
+  }
+  TRY(check_launch(c));
+  return sync(c);
+}
+
+ldg_status ldg_assemble(ldg_ctx* c, const double* Dem) {
+  if (!c || !Dem) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
+  launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+  c->blocks_ready = true;
+  return check_launch(c);
+}
+
+ldg_status ldg_get_blocks(ldg_ctx* c, double* out) {
+  if (!c || !out) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_export_blocks(c->K, c->N, NSLOT, c->blocks, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_apply_schur(ldg_ctx* c, double dt, const double* Cem, double* y) {
+  if (!c || !Cem || !y || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
+  launch_to_tiled(c->K, c->Kpad, c->N, Cem, c->u, c->st);
+  apply_op(c, dt, c->u, false, c->tZ1, c->tZ2, c->w);
+  launch_from_tiled(c->K, c->N, c->w, y, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_apply_full(ldg_ctx* c, double dt, const double* Y, double* out) {
+  if (!c || !Y || !out || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
+  const int64_t KN = c->K * c->N;
+  launch_to_tiled(c->K, c->Kpad, c->N, Y, c->z, c->st);            // Z1
+  launch_to_tiled(c->K, c->Kpad, c->N, Y + KN, c->r, c->st);       // Z2
+  launch_to_tiled(c->K, c->Kpad, c->N, Y + 2 * KN, c->u, c->st);   // C
+  launch_grad(c->N, c->geo, c->refs, c->u, nullptr, nullptr, c->tZ1, c->tZ2, c->st);
+  launch_zrows(c->geo, c->N, c->z, c->tZ1, dt, c->w, c->st);
+  launch_from_tiled(c->K, c->N, c->w, out, c->st);
+  launch_zrows(c->geo, c->N, c->r, c->tZ2, dt, c->w, c->st);
+  launch_from_tiled(c->K, c->N, c->w, out + KN, c->st);
+  launch_div(c->N, c->geo, c->refs, c->blocks, c->u, c->z, c->r, 1.0, dt, c->opt.eta, c->w, c->st);
+  launch_from_tiled(c->K, c->N, c->w, out + 2 * KN, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_bj_setup(ldg_ctx* c, double dt) {
+  if (!c || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->st));
+  launch_bj_setup(c->N, c->geo, c->refs, c->blocks, dt, c->opt.eta, c->bj, c->status, c->st);
+  TRY(check_launch(c));
+  int st = 0;
+  HIPCHK(c, hipMemcpyAsync(c->host_buf, c->status, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  std::memcpy(&st, c->host_buf, sizeof(int));
+  if (st) return fail(c, LDG_ENOCONV, "zero pivot in a block-Jacobi block");
+  return LDG_OK;
+}
+
+ldg_status ldg_get_bj(ldg_ctx* c, double* out) {
+  if (!c || !out) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_export_blocks(c->K, c->N, 1, c->bj, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double* f,
+                            const double* cD, const double* gN, ldg_step_info* info) {
+  if (!c || !d || !f || !info || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  std::memset(info, 0, sizeof(*info));
+  const double tau = dt;
+  const int64_t n = c->nvec;
+  // a1: projections and boundary data at t + dt
+  launch_project(c->N, c->K, c->Kpad, c->R, d, c->Wvol, c->D, c->st);
+  launch_project(c->N, c->K, c->Kpad, c->R, f, c->Wvol, c->F, c->st);
+  launch_boundary(c->N, c->geo, c->nbe, c->belem, c->R1, c->Wb, c->ws, cD, gN, c->nbnd, c->D,
+                  c->opt.eta, c->J1, c->J2, c->KDN, c->st);
+  // a2, a3: D-dependent blocks
+  launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+  c->blocks_ready = true;
+  TRY(check_launch(c));
+  // a4: preconditioner
+  TRY(ldg_bj_setup(c, tau));
+  // right-hand side and its full-system norm
+  launch_rhs(c->geo, c->N, c->C, c->KDN, c->F, tau, c->b3, c->st);
+  double nb3 = 0.0, nj1 = 0.0, nj2 = 0.0;
+  TRY(dot_self(c, c->b3, &nb3));
+  TRY(dot_self(c, c->J1, &nj1));
+  TRY(dot_self(c, c->J2, &nj2));
+  const double bnorm = std::sqrt(nb3 + tau * tau * (nj1 + nj2));
+  // a6: Krylov solve starting from C^n
+  HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  ldg_status s = gmres(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
+  info->t = c->t;
+  if (s != LDG_OK) return s;
+  // a10: accept; Z from the last residual evaluation of X
+  HIPCHK(c, hipMemcpyAsync(c->C, c->X, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->Z1, c->tZ1, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->Z2, c->tZ2, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->t += dt;
+  info->t = c->t;
+  TRY(check_launch(c));
+  return sync(c);
+}
+
+ldg_status ldg_sample_workload(ldg_ctx* c, int kind, double t, const double* blocks, int nb,
+                               int block, int n_cells, double* d, double* f, double* cD,
+                               double* gN, double* c0) {
+  if (!c || kind < 1 || kind > 5) return fail(c, LDG_EINVAL, "bad workload kind");
+  if ((kind == 3 || kind == 4) && (!blocks || nb < 1 || block < 1 || n_cells < 1))
+    return fail(c, LDG_EINVAL, "block field needs blocks, nb, block, n_cells");
+  const double hb = (kind == 3 || kind == 4) ? (double)block / n_cells : 1.0;
+  if (d || f || c0)
+    launch_sample_vol(c->geo, c->R, c->qvol, kind, t, blocks, nb, hb, d, f, c0, nullptr, nullptr,
+                      c->st);
+  if (cD || gN)
+    launch_sample_bnd(c->geo, c->R1, c->sb, c->nbnd, c->bk, c->bn, kind, t, blocks, nb, hb, cD, gN,
+                      nullptr, nullptr, c->st);
+  return check_launch(c);
+}
+
+}  // extern "C"

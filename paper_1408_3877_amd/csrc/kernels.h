@@ -1,0 +1,63 @@
+// Launchers of the device kernels (host side), all asynchronous on `st`.
+#pragma once
+#include "ldg_internal.h"
+
+namespace ldg {
+
+void launch_project(int N, int64_t K, int64_t Kpad, int R, const double* samples, const double* W,
+                    double* out, hipStream_t st);
+void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int R1,
+                     const double* Wb, const double* ws, const double* cD, const double* gN,
+                     int64_t nbnd, const double* D, double eta, double* J1, double* J2,
+                     double* KDN, hipStream_t st);
+void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, const double* Trd,
+                     const double* Tro, double* blocks, hipStream_t st);
+void launch_grad(int N, const Geo& g, const double* refs, const double* C, const double* J1,
+                 const double* J2, double* Z1, double* Z2, hipStream_t st);
+void launch_div(int N, const Geo& g, const double* refs, const double* blocks, const double* C,
+                const double* Z1, const double* Z2, double alpha, double tau, double eta,
+                double* y, hipStream_t st);
+void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
+                     double eta, double* bj, int* status, hipStream_t st);
+void launch_bj_apply(int N, const Geo& g, const double* bj, double* v, const double* scale_inv,
+                     int write_back, double* z, hipStream_t st);
+void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
+                     hipStream_t st);
+void launch_from_tiled(int64_t K, int N, const double* src, double* dst, hipStream_t st);
+void launch_export_blocks(int64_t K, int N, int ns, const double* src, double* dst,
+                          hipStream_t st);
+void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* blk,
+                       int nb, double hb, double* d, double* f, double* c0, double* xo, double* yo,
+                       hipStream_t st);
+void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, const int32_t* bk,
+                       const int8_t* bn, int kind, double t, const double* blk, int nb, double hb,
+                       double* cD, double* gN, double* xo, double* yo, hipStream_t st);
+
+// Krylov vector kernels (kernels_krylov.hip); n = vector length, V = basis
+// with vectors at V + j*ldv.  Reductions are two-stage and fixed-order.
+struct Reducer {
+  double* partials = nullptr;   // [(maxv+1) * nblk]
+  double* result = nullptr;     // [maxv+1] device
+  int nblk = 0;
+  int maxv = 0;
+};
+int krylov_nblk(int64_t n);
+// result[j] = <V_j, w> for j < nv, result[nv] = <w, w>
+void launch_dots(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
+                 const double* w, hipStream_t st);
+// w -= sum_j h[j] V_j (h device); result[0] = <w, w> afterwards
+void launch_update(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
+                   const double* h, double* w, hipStream_t st);
+// u = sum_j y[j] V_j (y device)
+void launch_lincomb(int64_t n, int nv, const double* V, int64_t ldv, const double* y, double* u,
+                    hipStream_t st);
+// y = a x + b y
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+// b3 = 2|T| C + tau (KDN + 2|T| F) in the tiled layout
+void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,
+                double tau, double* b3, hipStream_t st);
+// out = s * area2 * (Za - Zb) per element (full-operator rows 1, 2)
+void launch_zrows(const Geo& g, int N, const double* Za, const double* Zb, double s, double* out,
+                  hipStream_t st);
+
+}  // namespace ldg

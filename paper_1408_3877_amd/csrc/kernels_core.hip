@@ -1,0 +1,743 @@
+// Element kernels of the LDG hot path on gfx950 (wave64).
+//
+// Work is owner-computes per triangle: one lane per triangle in the
+// element-fastest layouts of ldg_internal.h, so a wave touches 64
+// consecutive triangles and every block or vector load of a wave is one
+// contiguous run (double2 per lane for the stored blocks).  The small
+// reference matrices (H_hat, S_hat_diag, S_hat_offdiag) live in LDS.
+#include "kernels.h"
+
+namespace ldg {
+
+namespace {
+
+constexpr int NREF = 14;  // H1, H2, Sd[3], So[3][3]
+__device__ inline int ref_h(int m) { return m; }
+__device__ inline int ref_sd(int n) { return 2 + n; }
+__device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
+
+template <int N>
+__device__ inline void load_refs(double* sm, const double* __restrict__ g) {
+  for (int t = threadIdx.x; t < NREF * N * N; t += blockDim.x) sm[t] = g[t];
+  __syncthreads();
+}
+
+// acc[i] += sum_j A[i][j] x[j] with A row-major in LDS
+template <int N>
+__device__ inline void mv_add(const double* __restrict__ A, const double* x, double* acc,
+                              double scale) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += A[i * N + j] * x[j];
+    acc[i] += scale * s;
+  }
+}
+
+template <int N>
+__device__ inline void load_vec(const double* __restrict__ v, int64_t k, double* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = v[vidx(k, i, N)];
+}
+
+template <int N>
+__device__ inline void store_vec(double* __restrict__ v, int64_t k, const double* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[vidx(k, i, N)] = x[i];
+}
+
+// acc += Blk(k, s) z for a stored block in the pair layout
+template <int N>
+__device__ inline void block_mv(const double* __restrict__ blocks, int64_t k, int s, int ns,
+                                const double* z, double* acc) {
+  constexpr int NN = N * N;
+  constexpr int NP = npairs(N);
+#pragma unroll
+  for (int pr = 0; pr < NP; ++pr) {
+    const double2 b = *reinterpret_cast<const double2*>(blocks + pidx(k, s, pr, ns, NP));
+    const int f0 = 2 * pr, f1 = 2 * pr + 1;
+    acc[f0 / N] += b.x * z[f0 % N];
+    if (f1 < NN) acc[f1 / N] += b.y * z[f1 % N];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// L2 projection (Sec. 3.4): out_k = sum_r samples[r][k] w_r phi(q_r)  (M_hat = I)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_project(int64_t K, int64_t Kpad, int R,
+                                                 const double* __restrict__ samples,
+                                                 const double* __restrict__ W,
+                                                 double* __restrict__ out) {
+  extern __shared__ double sW[];
+  for (int t = threadIdx.x; t < R * N; t += blockDim.x) sW[t] = W[t];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpad) return;
+  double acc[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = 0.0;
+  if (k < K) {
+    for (int r = 0; r < R; ++r) {
+      const double s = samples[(int64_t)r * K + k];
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] += sW[r * N + i] * s;
+    }
+  }
+  store_vec<N>(out, k, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary data (Sec. 3.6.9-3.6.11): J^m_D, eta K_D - K_N per boundary triangle
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_boundary(Geo g, int64_t nbe,
+                                                  const int32_t* __restrict__ belem, int R1,
+                                                  const double* __restrict__ Wb,
+                                                  const double* __restrict__ ws,
+                                                  const double* __restrict__ cD,
+                                                  const double* __restrict__ gN, int64_t nbnd,
+                                                  const double* __restrict__ D, double eta,
+                                                  double* __restrict__ J1,
+                                                  double* __restrict__ J2,
+                                                  double* __restrict__ KDN) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbe) return;
+  const int64_t k = belem[idx];
+  const int64_t Kp = g.Kpad;
+  double j1[N], j2[N], kd[N], kn[N], Dk[N];
+  load_vec<N>(D, k, Dk);
+#pragma unroll
+  for (int i = 0; i < N; ++i) j1[i] = j2[i] = kd[i] = kn[i] = 0.0;
+  for (int n = 0; n < 3; ++n) {
+    const int b = g.bidx[n * Kp + k];
+    if (b < 0) continue;
+    const int kind = g.kind[n * Kp + k];
+    const double L = g.elen[n * Kp + k];
+    const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
+    if (kind == LDG_EDGE_DIRICHLET && cD != nullptr) {
+      for (int r = 0; r < R1; ++r) {
+        const double wc = ws[r] * cD[(int64_t)r * nbnd + b];
+        const double* P = Wb + (n * R1 + r) * N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const double t = wc * P[i];
+          j1[i] += nu1 * L * t;
+          j2[i] += nu2 * L * t;
+          kd[i] += t;
+        }
+      }
+    } else if (kind == LDG_EDGE_NEUMANN && gN != nullptr) {
+      for (int r = 0; r < R1; ++r) {
+        const double* P = Wb + (n * R1 + r) * N;
+        double dh = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) dh += Dk[l] * P[l];
+        const double wg = ws[r] * gN[(int64_t)r * nbnd + b] * dh * L;
+#pragma unroll
+        for (int i = 0; i < N; ++i) kn[i] += wg * P[i];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    J1[vidx(k, i, N)] = j1[i];
+    J2[vidx(k, i, N)] = j2[i];
+    KDN[vidx(k, i, N)] = eta * kd[i] - kn[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block assembly, FP64 on the vector ALU (one lane per triangle).
+//   slot m   : B^m_kk = -G^m_k + sum_n c_n nu^m_kn |E_kn| sum_l D_kl R_hat_diag(:,:,l,n)
+//              c_n = 1/2 interior, 1 Dirichlet, 0 Neumann
+//   slot 2+n : U_kn = 1/2 |E_kn| sum_l D_{k+ l} R_hat_off(:,:,l,n,n+)   (interior edges)
+// Tensors are stored [l][f], f = i*N + j.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_assemble_valu(Geo g, const double* __restrict__ D,
+                                                       const double* __restrict__ Tg,
+                                                       const double* __restrict__ Trd,
+                                                       const double* __restrict__ Tro,
+                                                       double* __restrict__ blocks) {
+  constexpr int NN = N * N;
+  constexpr int NP = npairs(N);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  if (k >= g.K) {
+    for (int s = 0; s < NSLOT; ++s)
+      for (int pr = 0; pr < NP; ++pr)
+        *reinterpret_cast<double2*>(blocks + pidx(k, s, pr, NSLOT, NP)) = make_double2(0.0, 0.0);
+    return;
+  }
+  const int64_t Kp = g.Kpad;
+  double Dk[N], Dn[3][N];
+  load_vec<N>(D, k, Dk);
+  int npl[3];
+  double wr[2][3], uo[3];
+  const double B11 = g.B[k], B12 = g.B[Kp + k], B21 = g.B[2 * Kp + k], B22 = g.B[3 * Kp + k];
+  // -G^1 = -(B22 G1 - B21 G2), -G^2 = -(-B12 G1 + B11 G2)
+  const double wg[2][2] = {{-B22, B21}, {B12, -B11}};
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int kind = g.kind[n * Kp + k];
+    const double L = g.elen[n * Kp + k];
+    const double c = kind == LDG_EDGE_INTERIOR ? 0.5 : (kind == LDG_EDGE_DIRICHLET ? 1.0 : 0.0);
+    wr[0][n] = c * g.nu[(2 * n) * Kp + k] * L;
+    wr[1][n] = c * g.nu[(2 * n + 1) * Kp + k] * L;
+    const int kp = g.nbr[n * Kp + k];
+    npl[n] = kp >= 0 ? g.nbrn[n * Kp + k] : 0;
+    uo[n] = kp >= 0 ? 0.5 * L : 0.0;
+    if (kp >= 0) {
+      load_vec<N>(D, kp, Dn[n]);
+    } else {
+#pragma unroll
+      for (int l = 0; l < N; ++l) Dn[n][l] = 0.0;
+    }
+  }
+  for (int pr = 0; pr < NP; ++pr) {
+    double out[NSLOT][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = 2 * pr + h;
+      if (f >= NN) {
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) out[s][h] = 0.0;
+        continue;
+      }
+      double g0 = 0.0, g1 = 0.0, rd[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        g0 += Dk[l] * Tg[l * NN + f];
+        g1 += Dk[l] * Tg[(N + l) * NN + f];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+          rd[n] += Dk[l] * Trd[(n * N + l) * NN + f];
+          u[n] += Dn[n][l] * Tro[((3 * n + npl[n]) * N + l) * NN + f];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        out[m][h] = wg[m][0] * g0 + wg[m][1] * g1 + wr[m][0] * rd[0] + wr[m][1] * rd[1] +
+                    wr[m][2] * rd[2];
+#pragma unroll
+      for (int n = 0; n < 3; ++n) out[2 + n][h] = uo[n] * u[n];
+    }
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      *reinterpret_cast<double2*>(blocks + pidx(k, s, pr, NSLOT, NP)) =
+          make_double2(out[s][0], out[s][1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient half of the operator: Z^m = -M^{-1} (A^m C + J^m),
+//   A^m = -H^m + Q^m + Q^m_N (eq:timeDepSystem), M^{-1} = 1/(2|T_k|) on T_k.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
+                                              const double* __restrict__ C,
+                                              const double* __restrict__ J1,
+                                              const double* __restrict__ J2,
+                                              double* __restrict__ Z1, double* __restrict__ Z2) {
+  __shared__ double sm[NREF * N * N];
+  load_refs<N>(sm, refs);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  double a1[N], a2[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) a1[i] = a2[i] = 0.0;
+  if (k >= g.K) {
+    store_vec<N>(Z1, k, a1);
+    store_vec<N>(Z2, k, a2);
+    return;
+  }
+  const int64_t Kp = g.Kpad;
+  double c[N];
+  load_vec<N>(C, k, c);
+  const double B11 = g.B[k], B12 = g.B[Kp + k], B21 = g.B[2 * Kp + k], B22 = g.B[3 * Kp + k];
+  {
+    // -H^1 = -(B22 H1 - B21 H2), -H^2 = -(-B12 H1 + B11 H2)   (Sec. 3.6.2)
+    double u1[N], u2[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0.0;
+    mv_add<N>(sm + ref_h(0) * N * N, c, u1, 1.0);
+    mv_add<N>(sm + ref_h(1) * N * N, c, u2, 1.0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] -= B22 * u1[i] - B21 * u2[i];
+      a2[i] -= -B12 * u1[i] + B11 * u2[i];
+    }
+  }
+  for (int n = 0; n < 3; ++n) {
+    const int kind = g.kind[n * Kp + k];
+    if (kind == LDG_EDGE_DIRICHLET) continue;
+    const double L = g.elen[n * Kp + k];
+    const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
+    const double cq = (kind == LDG_EDGE_INTERIOR ? 0.5 : 1.0) * L;
+    double s[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = 0.0;
+    mv_add<N>(sm + ref_sd(n) * N * N, c, s, cq);
+    if (kind == LDG_EDGE_INTERIOR) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      const int np = g.nbrn[n * Kp + k];
+      double cp[N];
+      load_vec<N>(C, kp, cp);
+      mv_add<N>(sm + ref_so(n, np) * N * N, cp, s, 0.5 * L);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] += nu1 * s[i];
+      a2[i] += nu2 * s[i];
+    }
+  }
+  if (J1 != nullptr) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] += J1[vidx(k, i, N)];
+      a2[i] += J2[vidx(k, i, N)];
+    }
+  }
+  const double inv = -1.0 / g.area2[k];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    a1[i] *= inv;
+    a2[i] *= inv;
+  }
+  store_vec<N>(Z1, k, a1);
+  store_vec<N>(Z2, k, a2);
+}
+
+// ---------------------------------------------------------------------------
+// Divergence half: y = alpha M C + tau (eta (S + S_D) C + sum_m B^m Z^m),
+//   B^m = -G^m + R^m + R^m_D with the stored blocks, R^m_{k k+} = nu^m U_kn.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
+                                             const double* __restrict__ blocks,
+                                             const double* __restrict__ C,
+                                             const double* __restrict__ Z1,
+                                             const double* __restrict__ Z2, double alpha,
+                                             double tau, double eta, double* __restrict__ y) {
+  __shared__ double sm[NREF * N * N];
+  load_refs<N>(sm, refs);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  double t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = 0.0;
+  if (k >= g.K) {
+    store_vec<N>(y, k, t);
+    return;
+  }
+  const int64_t Kp = g.Kpad;
+  double c[N], z[N];
+  load_vec<N>(C, k, c);
+  for (int n = 0; n < 3; ++n) {
+    const int kind = g.kind[n * Kp + k];
+    if (kind == LDG_EDGE_NEUMANN) continue;
+    mv_add<N>(sm + ref_sd(n) * N * N, c, t, eta);       // (1/|E|) |E| S_hat_diag
+    if (kind == LDG_EDGE_INTERIOR) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      const int np = g.nbrn[n * Kp + k];
+      double cp[N];
+      load_vec<N>(C, kp, cp);
+      mv_add<N>(sm + ref_so(n, np) * N * N, cp, t, -eta);
+    }
+  }
+  load_vec<N>(Z1, k, z);
+  block_mv<N>(blocks, k, 0, NSLOT, z, t);
+  load_vec<N>(Z2, k, z);
+  block_mv<N>(blocks, k, 1, NSLOT, z, t);
+  for (int n = 0; n < 3; ++n) {
+    const int64_t kp = g.nbr[n * Kp + k];
+    if (kp < 0) continue;
+    const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
+#pragma unroll
+    for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
+    block_mv<N>(blocks, k, 2 + n, NSLOT, z, t);
+  }
+  const double a2 = alpha * g.area2[k];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = a2 * c[i] + tau * t[i];
+  store_vec<N>(y, k, t);
+}
+
+// ---------------------------------------------------------------------------
+// Block-Jacobi setup: the diagonal block of the eliminated operator,
+//   P_k = 2|T_k| I + tau [ eta S'_kk - (1/2|T_k|) sum_m B^m_kk A^m_kk
+//                          + sum_{n interior} |E_kn| / (2 * 2|T_k+|) U_kn S_hat_off(:,:,n+,n) ],
+// then its inverse by Gauss-Jordan elimination.  Sixteen lanes per triangle,
+// lane i owns row i; pivot rows travel by lane shuffles.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restrict__ refs,
+                                                  const double* __restrict__ blocks, double tau,
+                                                  double eta, double* __restrict__ bj,
+                                                  int* __restrict__ status) {
+  constexpr int NN = N * N;
+  constexpr int NP = npairs(N);
+  __shared__ double sm[NREF * N * N];
+  load_refs<N>(sm, refs);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid >> 4;
+  const int i = (int)(gid & 15);
+  const bool elem_ok = k < g.K;
+  const bool row_ok = elem_ok && i < N;
+  const int64_t Kp = g.Kpad;
+  const int64_t kk = elem_ok ? k : 0;
+  double a[N], b[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) { a[c] = 0.0; b[c] = (c == i) ? 1.0 : 0.0; }
+  if (row_ok) {
+    const double area2 = g.area2[kk];
+    const double B11 = g.B[kk], B12 = g.B[Kp + kk], B21 = g.B[2 * Kp + kk], B22 = g.B[3 * Kp + kk];
+    double acc[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc[c] = 0.0;
+    int kind[3];
+    double L[3], nu[3][2];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      kind[n] = g.kind[n * Kp + kk];
+      L[n] = g.elen[n * Kp + kk];
+      nu[n][0] = g.nu[(2 * n) * Kp + kk];
+      nu[n][1] = g.nu[(2 * n + 1) * Kp + kk];
+      if (kind[n] != LDG_EDGE_NEUMANN) {
+        const double* S = sm + ref_sd(n) * NN;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc[c] += eta * S[i * N + c];
+      }
+    }
+    // - (1/2|T|) sum_m (row i of B^m) A^m,
+    // A^m = -(b1 H1 + b2 H2) + sum_n q_n nu^m_n |E_n| Sd_n, q = 1/2 interior, 1 Neumann
+    const double hb[2][2] = {{B22, -B21}, {-B12, B11}};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      double brow[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const int f = i * N + j;
+        brow[j] = blocks[pidx(kk, m, f >> 1, NSLOT, NP) + (f & 1)];
+      }
+      double coef[5];
+      coef[0] = -hb[m][0];
+      coef[1] = -hb[m][1];
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const double q = kind[n] == LDG_EDGE_INTERIOR ? 0.5 : (kind[n] == LDG_EDGE_NEUMANN ? 1.0 : 0.0);
+        coef[2 + n] = q * nu[n][m] * L[n];
+      }
+      const double sc = -1.0 / area2;
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        if (coef[t] == 0.0) continue;
+        const double* A = sm + t * NN;   // H1, H2, Sd0, Sd1, Sd2
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s += brow[j] * A[j * N + c];
+          acc[c] += sc * coef[t] * s;
+        }
+      }
+    }
+    // neighbour paths
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int64_t kp = g.nbr[n * Kp + kk];
+      if (kp < 0) continue;
+      const int np = g.nbrn[n * Kp + kk];
+      const double sc = L[n] / (2.0 * g.area2[kp]);
+      double urow[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const int f = i * N + j;
+        urow[j] = blocks[pidx(kk, 2 + n, f >> 1, NSLOT, NP) + (f & 1)];
+      }
+      const double* S = sm + ref_so(np, n) * NN;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += urow[j] * S[j * N + c];
+        acc[c] += sc * s;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) a[c] = (c == i ? area2 : 0.0) + tau * acc[c];
+  }
+  // Gauss-Jordan without pivoting within the 16-lane group
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const double piv = __shfl(a[c], c, 16);
+    bad |= !(fabs(piv) > 0.0);
+    const double ip = 1.0 / piv;
+    double ra[N], rb[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      ra[j] = __shfl(a[j], c, 16) * ip;
+      rb[j] = __shfl(b[j], c, 16) * ip;
+    }
+    const double fct = a[c];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (i == c) {
+        a[j] = ra[j];
+        b[j] = rb[j];
+      } else {
+        a[j] -= fct * ra[j];
+        b[j] -= fct * rb[j];
+      }
+    }
+  }
+  if (row_ok && bad) atomicOr(status, 1);
+  if (k < g.Kpad && i < N) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int f = i * N + j;
+      bj[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = elem_ok ? b[j] : 0.0;
+    }
+    if (i == N - 1 && (NN & 1)) bj[pidx(k, 0, NP - 1, 1, NP) + 1] = 0.0;
+  }
+}
+
+// z = P^{-1} (scale * v); optionally v <- scale * v
+template <int N>
+__global__ void __launch_bounds__(256) k_bj_apply(Geo g, const double* __restrict__ bj,
+                                                  double* __restrict__ v,
+                                                  const double* __restrict__ scale_inv,
+                                                  int write_back, double* __restrict__ z) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  const double sc = scale_inv ? 1.0 / scale_inv[0] : 1.0;
+  double x[N], acc[N];
+  load_vec<N>(v, k, x);
+#pragma unroll
+  for (int i = 0; i < N; ++i) { x[i] *= sc; acc[i] = 0.0; }
+  if (write_back) store_vec<N>(v, k, x);
+  block_mv<N>(bj, k, 0, 1, x, acc);
+  store_vec<N>(z, k, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion and export
+// ---------------------------------------------------------------------------
+__global__ void k_to_tiled(int64_t K, int64_t Kpad, int N, const double* __restrict__ src,
+                           double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Kpad * N) return;
+  const int64_t k = t / N;
+  const int i = (int)(t % N);
+  dst[vidx(k, i, N)] = k < K ? src[t] : 0.0;
+}
+
+__global__ void k_from_tiled(int64_t K, int N, const double* __restrict__ src,
+                             double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * N) return;
+  const int64_t k = t / N;
+  const int i = (int)(t % N);
+  dst[t] = src[vidx(k, i, N)];
+}
+
+__global__ void k_export_blocks(int64_t K, int N, int ns, const double* __restrict__ src,
+                                double* __restrict__ dst) {
+  const int NN = N * N;
+  const int NP = npairs(N);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * ns * NN) return;
+  const int64_t k = t / (ns * NN);
+  const int rem = (int)(t % (ns * NN));
+  const int s = rem / NN, f = rem % NN;
+  dst[t] = src[pidx(k, s, f >> 1, ns, NP) + (f & 1)];
+}
+
+// ---------------------------------------------------------------------------
+// Synthetic workloads: analytic d, f, c_D, g_N, c0 at quadrature points
+// ---------------------------------------------------------------------------
+namespace {
+struct Fields { double d, f, c; double gcx, gcy; };
+
+__device__ Fields eval_fields(int kind, double t, double x, double y, const double* blk, int nb,
+                              double hb) {
+  Fields F;
+  const double e = kind == 5 ? 1.0 : exp(-t);
+  const double cx = cos(7.0 * x), cy = cos(7.0 * y), sx = sin(7.0 * x), sy = sin(7.0 * y);
+  F.c = cx * cy * e;
+  F.gcx = -7.0 * sx * cy * e;
+  F.gcy = -7.0 * cx * sy * e;
+  double dx = 0.0, dy = 0.0;
+  const double pi = 3.14159265358979323846;
+  if (kind == 1) {
+    F.d = 1.0 + 0.5 * sin(pi * x) * cos(pi * y) * exp(-t);
+    const double a = 0.5 * exp(-t) * pi;
+    dx = a * cos(pi * x) * cos(pi * y);
+    dy = -a * sin(pi * x) * sin(pi * y);
+  } else if (kind == 2) {
+    F.d = exp(0.5 * sin(2 * pi * x) * sin(2 * pi * y)) * (1.0 + 0.1 * t);
+    dx = F.d * pi * cos(2 * pi * x) * sin(2 * pi * y);
+    dy = F.d * pi * sin(2 * pi * x) * cos(2 * pi * y);
+  } else if (kind == 3 || kind == 4) {
+    long bx = (long)floor(x / hb), by = (long)floor(y / hb);
+    bx = bx < 0 ? 0 : (bx > nb - 1 ? nb - 1 : bx);
+    by = by < 0 ? 0 : (by > nb - 1 ? nb - 1 : by);
+    F.d = blk[bx * nb + by] * (kind == 4 ? 1.0 + 0.1 * sin(t) : 1.0);
+  } else {
+    F.d = exp(x + y);
+    dx = dy = F.d;
+  }
+  const double dtc = kind == 5 ? 0.0 : -F.c;
+  F.f = dtc - (dx * F.gcx + dy * F.gcy) + 98.0 * F.d * F.c;
+  return F;
+}
+}  // namespace
+
+__global__ void k_sample_vol(Geo g, int R, const double* __restrict__ q, int kind, double t,
+                             const double* __restrict__ blk, int nb, double hb,
+                             double* __restrict__ d, double* __restrict__ f,
+                             double* __restrict__ c0, double* __restrict__ xo,
+                             double* __restrict__ yo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)R * g.K) return;
+  const int r = (int)(idx / g.K);
+  const int64_t k = idx % g.K;
+  const int64_t Kp = g.Kpad;
+  const double q1 = q[2 * r], q2 = q[2 * r + 1];
+  const double x = g.a1[k] + g.B[k] * q1 + g.B[Kp + k] * q2;
+  const double y = g.a1[Kp + k] + g.B[2 * Kp + k] * q1 + g.B[3 * Kp + k] * q2;
+  if (xo) { xo[idx] = x; yo[idx] = y; }
+  if (!(d || f || c0)) return;
+  const Fields F = eval_fields(kind, t, x, y, blk, nb, hb);
+  if (d) d[idx] = F.d;
+  if (f) f[idx] = F.f;
+  if (c0) c0[idx] = eval_fields(kind, 0.0, x, y, blk, nb, hb).c;
+}
+
+__global__ void k_sample_bnd(Geo g, int R1, const double* __restrict__ s, int64_t nbnd,
+                             const int32_t* __restrict__ bk, const int8_t* __restrict__ bn,
+                             int kind, double t, const double* __restrict__ blk, int nb, double hb,
+                             double* __restrict__ cD, double* __restrict__ gN,
+                             double* __restrict__ xo, double* __restrict__ yo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)R1 * nbnd) return;
+  const int r = (int)(idx / nbnd);
+  const int64_t b = idx % nbnd;
+  const int64_t k = bk[b];
+  const int n = bn[b];
+  const int64_t Kp = g.Kpad;
+  const double sr = s[r];
+  double q1, q2;   // reference edge n from vertex n+1 to vertex n+2
+  if (n == 0) { q1 = 1.0 - sr; q2 = sr; }
+  else if (n == 1) { q1 = 0.0; q2 = 1.0 - sr; }
+  else { q1 = sr; q2 = 0.0; }
+  const double x = g.a1[k] + g.B[k] * q1 + g.B[Kp + k] * q2;
+  const double y = g.a1[Kp + k] + g.B[2 * Kp + k] * q1 + g.B[3 * Kp + k] * q2;
+  const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
+  if (xo) {
+    if (kind < 0) { xo[idx] = nu1; yo[idx] = nu2; }
+    else { xo[idx] = x; yo[idx] = y; }
+  }
+  if (kind <= 0 || !(cD || gN)) return;
+  const Fields F = eval_fields(kind, t, x, y, blk, nb, hb);
+  if (cD) cD[idx] = F.c;
+  if (gN) gN[idx] = -(F.gcx * nu1 + F.gcy * nu2);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+}
+
+#define LDG_SWITCH_N(N, CALL)                                   \
+  switch (N) {                                                  \
+    case 1: { constexpr int NT = 1; CALL; } break;              \
+    case 3: { constexpr int NT = 3; CALL; } break;              \
+    case 6: { constexpr int NT = 6; CALL; } break;              \
+    case 10: { constexpr int NT = 10; CALL; } break;            \
+    case 15: { constexpr int NT = 15; CALL; } break;            \
+    default: break;                                             \
+  }
+
+void launch_project(int N, int64_t K, int64_t Kpad, int R, const double* samples, const double* W,
+                    double* out, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_project<NT><<<nblk(Kpad, 256), 256, R * NT * sizeof(double), st>>>(
+                      K, Kpad, R, samples, W, out)));
+}
+
+void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int R1,
+                     const double* Wb, const double* ws, const double* cD, const double* gN,
+                     int64_t nbnd, const double* D, double eta, double* J1, double* J2,
+                     double* KDN, hipStream_t st) {
+  if (nbe == 0) return;
+  LDG_SWITCH_N(N, (k_boundary<NT><<<nblk(nbe, 256), 256, 0, st>>>(g, nbe, belem, R1, Wb, ws, cD,
+                                                                   gN, nbnd, D, eta, J1, J2, KDN)));
+}
+
+void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, const double* Trd,
+                     const double* Tro, double* blocks, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_assemble_valu<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, D, Tg, Trd, Tro,
+                                                                            blocks)));
+}
+
+void launch_grad(int N, const Geo& g, const double* refs, const double* C, const double* J1,
+                 const double* J2, double* Z1, double* Z2, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_grad<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, refs, C, J1, J2, Z1, Z2)));
+}
+
+void launch_div(int N, const Geo& g, const double* refs, const double* blocks, const double* C,
+                const double* Z1, const double* Z2, double alpha, double tau, double eta,
+                double* y, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_div<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, refs, blocks, C, Z1, Z2,
+                                                                 alpha, tau, eta, y)));
+}
+
+void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
+                     double eta, double* bj, int* status, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_bj_setup<NT><<<nblk(g.Kpad * 16, 256), 256, 0, st>>>(g, refs, blocks, tau,
+                                                                          eta, bj, status)));
+}
+
+void launch_bj_apply(int N, const Geo& g, const double* bj, double* v, const double* scale_inv,
+                     int write_back, double* z, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_bj_apply<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, bj, v, scale_inv,
+                                                                      write_back, z)));
+}
+
+void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
+                     hipStream_t st) {
+  k_to_tiled<<<nblk(Kpad * N, 256), 256, 0, st>>>(K, Kpad, N, src, dst);
+}
+
+void launch_from_tiled(int64_t K, int N, const double* src, double* dst, hipStream_t st) {
+  k_from_tiled<<<nblk(K * N, 256), 256, 0, st>>>(K, N, src, dst);
+}
+
+void launch_export_blocks(int64_t K, int N, int ns, const double* src, double* dst,
+                          hipStream_t st) {
+  k_export_blocks<<<nblk(K * ns * N * N, 256), 256, 0, st>>>(K, N, ns, src, dst);
+}
+
+void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* blk,
+                       int nb, double hb, double* d, double* f, double* c0, double* xo, double* yo,
+                       hipStream_t st) {
+  k_sample_vol<<<nblk((int64_t)R * g.K, 256), 256, 0, st>>>(g, R, q, kind, t, blk, nb, hb, d, f,
+                                                             c0, xo, yo);
+}
+
+void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, const int32_t* bk,
+                       const int8_t* bn, int kind, double t, const double* blk, int nb, double hb,
+                       double* cD, double* gN, double* xo, double* yo, hipStream_t st) {
+  if (nbnd == 0) return;
+  k_sample_bnd<<<nblk((int64_t)R1 * nbnd, 256), 256, 0, st>>>(g, R1, s, nbnd, bk, bn, kind, t, blk,
+                                                               nb, hb, cD, gN, xo, yo);
+}
+
+}  // namespace ldg

@@ -1,0 +1,235 @@
+"""ctypes binding of include/ldg.h with the same entry-point names.
+
+Argument marshalling only: numpy arrays for host inputs, torch tensors on the
+GPU for device buffers (``data_ptr()``), the current torch stream as the HIP
+stream.  Every step of the method runs inside libldg.so.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+LDG_FP64, LDG_MIXED_FP32, LDG_MIXED_BF16 = 0, 1, 2
+LDG_PC_BLOCK_JACOBI, LDG_PC_GNN = 0, 1
+STATUS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOCONV",
+          -6: "EUNSUPPORTED"}
+
+
+class LdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("p", C.c_int), ("eta", C.c_double), ("precision", C.c_int),
+                ("precond", C.c_int), ("rtol", C.c_double), ("restart", C.c_int),
+                ("max_iters", C.c_int), ("stream", C.c_void_p)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("K", C.c_int64), ("N", C.c_int), ("R", C.c_int), ("R1", C.c_int),
+                ("n_bnd", C.c_int64), ("E_int", C.c_int64)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("ir_steps", C.c_int),
+                ("fallbacks", C.c_int), ("rel_residual", C.c_double), ("t", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_SIGS = {
+    "ldg_options_default": [C.POINTER(Options)],
+    "ldg_create": [_P, C.c_int64, _P, C.c_int64, _P, C.POINTER(Options), C.POINTER(_P)],
+    "ldg_get_sizes": [_P, C.POINTER(Sizes)],
+    "ldg_quad_points": [_P, C.c_int, _P, _P],
+    "ldg_project": [_P, _P, _P],
+    "ldg_set_state": [_P, _P, C.c_int, C.c_double],
+    "ldg_set_initial_samples": [_P, _P, C.c_double],
+    "ldg_step_sampled": [_P, C.c_double, _P, _P, _P, _P, C.POINTER(StepInfo)],
+    "ldg_get_solution": [_P, _P, _P, _P, C.c_int],
+    "ldg_assemble": [_P, _P],
+    "ldg_get_blocks": [_P, _P],
+    "ldg_apply_schur": [_P, C.c_double, _P, _P],
+    "ldg_apply_full": [_P, C.c_double, _P, _P],
+    "ldg_bj_setup": [_P, C.c_double],
+    "ldg_get_bj": [_P, _P],
+    "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P,
+                            _P, _P],
+}
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(HERE, "libldg.so")
+
+
+def load_library():
+    """Load libldg.so from this package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError("libldg.so is not built; run `python -m paper_1408_3877_amd.build`")
+    lib = C.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.ldg_destroy.argtypes = [_P]
+    lib.ldg_destroy.restype = None
+    lib.ldg_last_error.argtypes = [_P]
+    lib.ldg_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One LDG context: a mesh, an order p and the solver options."""
+
+    def __init__(self, coordV, V0T, edge_kind, p, eta=1.0, precision=LDG_FP64,
+                 precond=LDG_PC_BLOCK_JACOBI, rtol=1e-8, restart=30, max_iters=5000,
+                 device=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the LDG library runs on the device only")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        coordV = np.ascontiguousarray(coordV, dtype=np.float64)
+        V0T = np.ascontiguousarray(V0T, dtype=np.int32)
+        kind = np.ascontiguousarray(edge_kind, dtype=np.int8)
+        opt = Options()
+        self.lib.ldg_options_default(C.byref(opt))
+        opt.p, opt.eta, opt.precision, opt.precond = p, eta, precision, precond
+        opt.rtol, opt.restart, opt.max_iters = rtol, restart, max_iters
+        with torch.cuda.device(self.device):
+            opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+            h = C.c_void_p()
+            code = self.lib.ldg_create(coordV.ctypes.data, coordV.shape[0], V0T.ctypes.data,
+                                       V0T.shape[0], kind.ctypes.data, C.byref(opt), C.byref(h))
+        self.h = h
+        if code != 0:
+            msg = self.lib.ldg_last_error(h).decode() if h.value else ""
+            if h.value:
+                self.lib.ldg_destroy(h)
+            self.h = None
+            raise LdgError(code, msg)
+        s = Sizes()
+        self._check(self.lib.ldg_get_sizes(self.h, C.byref(s)))
+        self.K, self.N, self.R, self.R1 = s.K, s.N, s.R, s.R1
+        self.n_bnd, self.E_int = s.n_bnd, s.E_int
+        self.p = p
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, code):
+        if code != 0:
+            raise LdgError(code, self.lib.ldg_last_error(self.h).decode())
+
+    def _dev(self, x, shape=None):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(np.asarray(x, dtype=np.float64))
+        x = x.to(device=self.device, dtype=t.float64).contiguous()
+        if shape is not None:
+            assert tuple(x.shape) == tuple(shape), (x.shape, shape)
+        return x
+
+    def _empty(self, *shape):
+        return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ldg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ---------------------------------------------------------
+    def quad_points(self, kind):
+        n = self.R * self.K if kind == 0 else self.R1 * self.n_bnd
+        x, y = self._empty(max(n, 1)), self._empty(max(n, 1))
+        self._check(self.lib.ldg_quad_points(self.h, kind, _ptr(x), _ptr(y)))
+        return x[:n], y[:n]
+
+    def project(self, samples):
+        s = self._dev(samples, (self.R * self.K,))
+        out = self._empty(self.K, self.N)
+        self._check(self.lib.ldg_project(self.h, _ptr(s), _ptr(out)))
+        return out
+
+    def set_state(self, Cm, t):
+        Cd = self._dev(Cm, (self.K, self.N))
+        self._check(self.lib.ldg_set_state(self.h, _ptr(Cd), 1, float(t)))
+
+    def set_initial_samples(self, c0, t0=0.0):
+        s = self._dev(c0, (self.R * self.K,))
+        self._check(self.lib.ldg_set_initial_samples(self.h, _ptr(s), float(t0)))
+
+    def step_sampled(self, dt, d, f, cD=None, gN=None):
+        info = StepInfo()
+        code = self.lib.ldg_step_sampled(self.h, float(dt), _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
+                                         C.byref(info))
+        self._check(code)
+        return info.as_dict()
+
+    def get_solution(self):
+        Cm, Z1, Z2 = self._empty(self.K, self.N), self._empty(self.K, self.N), self._empty(self.K, self.N)
+        self._check(self.lib.ldg_get_solution(self.h, _ptr(Cm), _ptr(Z1), _ptr(Z2), 1))
+        return Cm, Z1, Z2
+
+    def assemble(self, D):
+        Dd = self._dev(D, (self.K, self.N))
+        self._check(self.lib.ldg_assemble(self.h, _ptr(Dd)))
+
+    def get_blocks(self):
+        out = self._empty(self.K, 5, self.N, self.N)
+        self._check(self.lib.ldg_get_blocks(self.h, _ptr(out)))
+        return out
+
+    def apply_schur(self, dt, Cm):
+        Cd = self._dev(Cm, (self.K, self.N))
+        y = self._empty(self.K, self.N)
+        self._check(self.lib.ldg_apply_schur(self.h, float(dt), _ptr(Cd), _ptr(y)))
+        return y
+
+    def apply_full(self, dt, Y):
+        Yd = self._dev(Y, (3 * self.K * self.N,))
+        out = self._empty(3 * self.K * self.N)
+        self._check(self.lib.ldg_apply_full(self.h, float(dt), _ptr(Yd), _ptr(out)))
+        return out
+
+    def bj_setup(self, dt):
+        self._check(self.lib.ldg_bj_setup(self.h, float(dt)))
+
+    def get_bj(self):
+        out = self._empty(self.K, self.N, self.N)
+        self._check(self.lib.ldg_get_bj(self.h, _ptr(out)))
+        return out
+
+    def sample_workload(self, kind, t, blocks=None, block=8, n_cells=1, want=("d", "f", "cD", "gN")):
+        bl = None if blocks is None else self._dev(np.ascontiguousarray(blocks, np.float64).reshape(-1))
+        nb = 0 if blocks is None else int(np.asarray(blocks).shape[0])
+        nv, nbd = self.R * self.K, self.R1 * self.n_bnd
+        out = {}
+        for name, n in (("d", nv), ("f", nv), ("cD", nbd), ("gN", nbd), ("c0", nv)):
+            out[name] = self._empty(max(n, 1))[:n] if name in want else None
+        self._check(self.lib.ldg_sample_workload(
+            self.h, int(kind), float(t), _ptr(bl), nb, int(block), int(n_cells), _ptr(out["d"]),
+            _ptr(out["f"]), _ptr(out["cD"]), _ptr(out["gN"]), _ptr(out["c0"])))
+        return out

@@ -1,0 +1,159 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Inputs are seeded: meshes and fields from the `inputs` package, random
+coefficient vectors from numpy generators; nothing the oracle consumes is
+produced by the GPU.  Sizes span one partial tile (K < 64), several tiles
+with a ragged tail, every order p = 0..4, all edge kinds.
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import LOGNORMAL, LOGNORMAL_T, SMOOTH1, SMOOTH2, TABLE2
+from inputs.meshes import EAST, NORTH, SOUTH, WEST, square_mesh
+from oracle.ldg import Blocks, Problem, minv_blocks, schur_matrix, system, mass_W
+from tests.gpu_common import rel_l2, to_np, workload
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (n cells, jitter seed, Neumann sides, p)
+    (5, 101, (SOUTH,), 0),
+    (5, 102, (), 1),
+    (9, 103, (SOUTH, NORTH), 2),
+    (9, 104, (EAST,), 3),
+    (5, 105, (WEST, NORTH), 4),
+    (9, 106, (), 4),
+]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _solver(coordV, V0T, kind, p, **kw):
+    from paper_1408_3877_amd import Solver
+    return Solver(coordV, V0T, kind, p, **kw)
+
+
+@pytest.mark.parametrize("n,seed,neu,p", CASES)
+def test_projection_and_quad_points(torch_mod, n, seed, neu, p):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
+    pr = Problem(cV, V0T, kind, p)
+    s = _solver(cV, V0T, kind, p)
+    w = workload(SMOOTH2, n)
+    t = 0.37
+    smp = s.sample_workload(2, t)
+    D = to_np(s.project(smp["d"]))
+    F = to_np(s.project(smp["f"]))
+    data = pr.data(w, t)
+    assert rel_l2(pr.grid.areaT, D, data["D"]) < 1e-13
+    assert rel_l2(pr.grid.areaT, F, data["F"]) < 1e-13
+    x, y = s.quad_points(0)
+    assert x.numel() == s.R * s.K
+
+
+@pytest.mark.parametrize("n,seed,neu,p", CASES)
+def test_blocks(torch_mod, n, seed, neu, p):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(seed)
+    D = rng.standard_normal((pr.grid.numT, pr.N))
+    s = _solver(cV, V0T, kind, p)
+    s.assemble(D)
+    blk = to_np(s.get_blocks())
+    b = Blocks(pr.grid, pr.refs, D)
+    g = pr.grid
+    N = pr.N
+    Bm = [(-b.G[m] + b.R[m] + b.RD[m]).tocsr() for m in range(2)]
+    err, ref = 0.0, 0.0
+    for k in range(g.numT):
+        sl = slice(k * N, (k + 1) * N)
+        for m in range(2):
+            want = Bm[m][sl, sl].toarray()
+            err = max(err, np.abs(blk[k, m] - want).max())
+            ref = max(ref, np.abs(want).max())
+        for nn in range(3):
+            kp = g.kp[k, nn]
+            if kp < 0:
+                assert np.all(blk[k, 2 + nn] == 0)
+                continue
+            slp = slice(kp * N, (kp + 1) * N)
+            # sum_m nu^m R^m_{k k+} = U_kn
+            want = sum(g.nuE0T[k, nn, m] * Bm[m][sl, slp].toarray() for m in range(2))
+            err = max(err, np.abs(blk[k, 2 + nn] - want).max())
+    assert err <= 1e-12 * max(ref, 1.0), (err, ref)
+
+
+@pytest.mark.parametrize("n,seed,neu,p", CASES)
+def test_apply_and_preconditioner(torch_mod, n, seed, neu, p):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(seed + 7)
+    K, N = pr.grid.numT, pr.N
+    D = 1.0 + 0.3 * rng.standard_normal((K, N))
+    Cv = rng.standard_normal((K, N))
+    dt = 0.013
+    s = _solver(cV, V0T, kind, p)
+    s.assemble(D)
+    b = Blocks(pr.grid, pr.refs, D)
+    S = schur_matrix(b, pr.grid, pr.refs, 1.0, dt)
+    want = (S @ Cv.reshape(-1)).reshape(K, N)
+    got = to_np(s.apply_schur(dt, Cv))
+    assert rel_l2(pr.grid.areaT, got, want) < 1e-12
+    # full 3KN operator (W + dt A) Y
+    Y = rng.standard_normal(3 * K * N)
+    full = (mass_W(b) + dt * system(b, 1.0)) @ Y
+    gotf = to_np(s.apply_full(dt, Y))
+    assert np.linalg.norm(gotf - full) <= 1e-12 * np.linalg.norm(full)
+    # block-Jacobi: inverses of the diagonal blocks of S
+    s.bj_setup(dt)
+    bj = to_np(s.get_bj())
+    Sd = S.toarray() if K * N < 3000 else None
+    for k in range(K):
+        sl = slice(k * N, (k + 1) * N)
+        blkS = Sd[sl, sl] if Sd is not None else S[sl, sl].toarray()
+        inv = np.linalg.inv(blkS)
+        assert np.abs(bj[k] - inv).max() <= 1e-10 * np.abs(inv).max(), k
+
+
+def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
+    pr = Problem(cV, V0T, kind, p)
+    w = workload(wkind, n, seed=seed, sigma=sigma, block=block)
+    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000)
+    gk = {SMOOTH1: 1, SMOOTH2: 2, LOGNORMAL: 3, LOGNORMAL_T: 4, TABLE2: 5}[wkind]
+    blocks = getattr(w, "blocks", None)
+    smp0 = s.sample_workload(gk, t0, blocks=blocks, block=block, n_cells=n, want=("c0",))
+    s.set_initial_samples(smp0["c0"], t0)
+    C = pr.initial(w)
+    assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-13
+    t = t0
+    worst = 0.0
+    for _ in range(steps):
+        t += dt
+        smp = s.sample_workload(gk, t, blocks=blocks, block=block, n_cells=n)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        assert info["rel_residual"] <= 1e-13
+        C, Z1, Z2, oi = pr.step(C, t, dt, w)
+        Cg, Z1g, Z2g = (to_np(x) for x in s.get_solution())
+        worst = max(worst, rel_l2(pr.grid.areaT, Cg, C))
+        zerr = rel_l2(pr.grid.areaT, np.stack([Z1g, Z2g]), np.stack([Z1, Z2]))
+        assert zerr < 1e-9, zerr
+    return worst
+
+
+def test_steps_config1(torch_mod):
+    # 8 x 8 cells, p = 1, smooth d, manufactured c, Dirichlet, 10 steps of 0.01
+    assert _run_steps(1, 8, None, (), SMOOTH1, 10, 0.01) < 1e-10
+
+
+@pytest.mark.parametrize("p,n,seed,neu,wk", [
+    (2, 6, 201, (SOUTH, NORTH), TABLE2),
+    (3, 5, 202, (), SMOOTH2),
+    (4, 5, 203, (EAST,), LOGNORMAL_T),
+    (0, 7, 204, (), SMOOTH1),
+])
+def test_steps_small(torch_mod, p, n, seed, neu, wk):
+    assert _run_steps(p, n, seed, neu, wk, 3, 0.02, block=2) < 1e-10
