@@ -1,0 +1,205 @@
+"""Throughput of the LDG implicit Euler step on one MI355X.
+
+One "step" is one implicit Euler step of the whole hot path: sampling the
+coefficient data at the quadrature points, L2 projection, block assembly,
+block-Jacobi setup, the Krylov solve to the relative residual of the full
+3KN system, recovery of Z.  Metric: DOF*steps/s with DOF = 3KN (C, Z1, Z2).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config combined-p4-1024]
+
+Prints one JSON line (rank 0).  Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from inputs.fields import (LOGNORMAL, LOGNORMAL_T, SMOOTH1, SMOOTH2, Workload,  # noqa: E402
+                           lognormal_blocks, triangle_values)
+from inputs.meshes import square_mesh  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+# The five workloads: mesh of n x n cells (2 n^2 triangles), order p, data.
+CONFIGS = {
+    "plain-p1-8": dict(n=8, p=1, jitter=None, kind=SMOOTH1, dt=1e-2),
+    "plain-p2-64": dict(n=64, p=2, jitter=1002, kind=SMOOTH2, dt=1e-3),
+    "mixed-p4-512": dict(n=512, p=4, jitter=1003, kind=SMOOTH2, dt=1e-4),
+    "learned-p3-256": dict(n=256, p=3, jitter=1004, kind=LOGNORMAL, sigma=1.5, field_seed=4100,
+                           dt=1e-4),
+    "combined-p4-1024": dict(n=1024, p=4, jitter=1005, kind=LOGNORMAL_T, sigma=1.0,
+                             field_seed=5000, dt=1e-4),
+}
+DEFAULT = "combined-p4-1024"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(cfg):
+    coordV, V0T, kind = square_mesh(cfg["n"], seed=cfg["jitter"])
+    dT = None
+    if cfg["kind"] in (LOGNORMAL, LOGNORMAL_T):
+        blocks = lognormal_blocks(cfg["n"], cfg["field_seed"], cfg["sigma"], block=8)
+        dT = triangle_values(blocks, cfg["n"], block=8)
+    return coordV, V0T, kind, dT
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1408_3877_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1408_3877_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is absent or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, seconds_hint=True):
+    """The oracle (direct sparse solve of the full system) on a bounded sample
+    of the same workload family: 16 x 16 cells, same p, same fields, 2 steps."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ldg import Problem
+    n = 16
+    coordV, V0T, kind = square_mesh(n, seed=cfg["jitter"])
+    if cfg["kind"] in (LOGNORMAL, LOGNORMAL_T):
+        w = Workload(cfg["kind"], n_cells=n,
+                     blocks=lognormal_blocks(n, cfg["field_seed"], cfg["sigma"], block=8), block=8)
+    else:
+        w = Workload(cfg["kind"])
+    steps = 2
+    with threadpool_limits(1):
+        pr = Problem(coordV, V0T, kind, cfg["p"])
+        C = pr.initial(w)
+        t = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t += cfg["dt"]
+            C, _, _, _ = pr.step(C, t, cfg["dt"], w)
+        el = time.perf_counter() - t0
+    dof = 3 * pr.grid.numT * pr.N
+    return {"value": dof * steps / el, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%dx%d-cell mesh of the same family (K=%d, p=%d, DOF=%d), %d steps, "
+                      "sparse direct solve, %.1f s" % (n, n, pr.grid.numT, cfg["p"], dof, steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default=DEFAULT, choices=sorted(CONFIGS))
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1408_3877_amd import Solver
+    cfg = CONFIGS[args.config]
+    log("[bench] config %s: building inputs" % args.config)
+    coordV, V0T, kind, dT = make_inputs(cfg)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
+               max_iters=20000)
+    log("[bench] context: K=%d N=%d (%.1f s)" % (s.K, s.N, time.perf_counter() - t0))
+    gk = cfg["kind"]
+    s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
+    t = 0.0
+    dt = cfg["dt"]
+    infos = []
+
+    def one_step():
+        nonlocal t
+        t += dt
+        smp = s.sample_workload(gk, t, dT=dT)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        return info
+
+    for i in range(args.warmup):
+        info = one_step()
+        log("[bench] warmup %d: iters=%d rel_res=%.2e" % (i, info["iters"], info["rel_residual"]))
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        info = one_step()
+        infos.append(info)
+        log("[bench] step %d: iters=%d restarts=%d rel_res=%.2e" %
+            (i, info["iters"], info["restarts"], info["rel_residual"]))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stats = s.kernel_stats()
+    s.set_timing(False)
+    dof = 3 * s.K * s.N
+    value = dof * args.steps / el
+    dv = stats["div"]
+    ach = dv["bytes"] / (dv["total_ms"] * 1e-3) / 1e9 if dv["total_ms"] > 0 else 0.0
+    per_launch = dv["bytes"] / max(dv["launches"], 1)
+    traffic = measured_traffic(args.config)
+    res = {
+        "metric": "DOF*steps/s (p=4, 2M tris) to 1e-8 rel res",
+        "value": value,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
+                   "dt": dt, "rtol": args.rtol, "solver": "fp64 block-Jacobi GMRES(%d)" % args.restart,
+                   "iters_per_step": sum(i["iters"] for i in infos) / len(infos)},
+        "roofline": {"bound": "hbm", "kernel": "k_div (operator apply, stored blocks)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "avg_launch_ms": dv["total_ms"] / max(dv["launches"], 1),
+                     "traffic": traffic},
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                        "GB/s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                        if v["total_ms"] > 0 else None} for k, v in stats.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        res["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

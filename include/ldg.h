@@ -53,6 +53,14 @@ typedef enum {
 typedef enum { LDG_FP64 = 0, LDG_MIXED_FP32 = 1, LDG_MIXED_BF16 = 2 } ldg_precision;
 typedef enum { LDG_PC_BLOCK_JACOBI = 0, LDG_PC_GNN = 1 } ldg_precond;
 typedef enum { LDG_EDGE_INTERIOR = 0, LDG_EDGE_DIRICHLET = 1, LDG_EDGE_NEUMANN = 2 } ldg_edge_kind;
+/*
+ * Krylov method of a step.  With a coefficient that is constant on every
+ * triangle (only the first mode of D non-zero) the blocks satisfy
+ * B^m = -(A^m)^T diag(d) and the eliminated operator is symmetric positive
+ * definite, so LDG_KRYLOV_AUTO uses preconditioned conjugate gradients;
+ * otherwise (or if CG breaks down) restarted GMRES.
+ */
+typedef enum { LDG_KRYLOV_AUTO = 0, LDG_KRYLOV_GMRES = 1, LDG_KRYLOV_CG = 2 } ldg_krylov;
 
 typedef struct {
   int p;              /* polynomial order 0..4 (assert in the main script) */
@@ -63,6 +71,7 @@ typedef struct {
   int restart;        /* GMRES restart length m, default 30 */
   int max_iters;      /* total Krylov iterations per step, default 5000 */
   void* stream;       /* hipStream_t for all device work */
+  int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
 } ldg_options;
 
 typedef struct {
@@ -78,7 +87,8 @@ typedef struct {
   int iters;           /* Krylov iterations of the step (inner ones in the mixed modes) */
   int restarts;        /* GMRES cycles */
   int ir_steps;        /* outer refinement sweeps (mixed modes), 0 in FP64 */
-  int fallbacks;       /* preconditioner fallbacks taken */
+  int fallbacks;       /* fallbacks taken (CG -> GMRES, learned -> block-Jacobi) */
+  int krylov;          /* ldg_krylov actually used by the step */
   double rel_residual; /* ||b - (W + dt A) Y|| / ||b|| of the full system, FP64 */
   double t;            /* time level reached */
 } ldg_step_info;
@@ -143,6 +153,33 @@ ldg_status ldg_step_sampled(ldg_ctx* ctx, double dt, const double* d, const doub
 /* Current C, Z1, Z2 (K x N each, element-major, caller's element order). Any may be NULL. */
 ldg_status ldg_get_solution(ldg_ctx* ctx, double* C, double* Z1, double* Z2, int on_device);
 
+/*
+ * Kernel timing with HIP events recorded around each launch on the
+ * context's stream (off by default; the events cost a few microseconds per
+ * launch).  Statistics accumulate from the call that switches timing on.
+ * bytes: algorithmic HBM bytes of all timed launches (every operand read
+ * or written once, stored blocks counted with their N*N values, neighbour
+ * gathers not counted); flops likewise.
+ */
+typedef enum {
+  LDG_K_DIV = 0,       /* divergence half of the operator: streams the stored blocks */
+  LDG_K_GRAD = 1,      /* gradient half of the operator */
+  LDG_K_BJ_APPLY = 2,  /* block-Jacobi application */
+  LDG_K_ASSEMBLE = 3,  /* block assembly */
+  LDG_K_BJ_SETUP = 4,  /* block-Jacobi setup and inversion */
+  LDG_K_KRYLOV = 5,    /* Gram-Schmidt dots, updates, vector updates */
+  LDG_K_PROJECT = 6,   /* projections and boundary data */
+  LDG_K_COUNT = 7
+} ldg_kernel_id;
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double bytes;
+  double flops;
+} ldg_kernel_stat;
+ldg_status ldg_set_timing(ldg_ctx* ctx, int on);
+ldg_status ldg_get_kernel_stat(ldg_ctx* ctx, int kernel, ldg_kernel_stat* out);
+
 /* ---- entry points of the individual steps of the path (used by the tests) ---- */
 
 /*
@@ -185,17 +222,17 @@ ldg_status ldg_get_bj(ldg_ctx* ctx, double* out);
  * for a caller's coefficient functions).
  *   kind   1: d = 1 + sin(pi x) cos(pi y) exp(-t)/2
  *          2: d = exp(sin(2 pi x) sin(2 pi y)/2) (1 + t/10)
- *          3: d = blocks[bx, by]           (piecewise constant)
- *          4: d = blocks[bx, by] (1 + sin(t)/10)
+ *          3: d = dT[k] on triangle k          (piecewise constant)
+ *          4: d = dT[k] (1 + sin(t)/10)
  *          5: d = exp(x + y), stationary c
- *   c = cos(7x) cos(7y) exp(-t) (kind 5: without exp(-t)), f = dt c - div(d grad c)
- *   (inside each block for kinds 3, 4), c_D = c, g_N = -grad c . nu.
- *   blocks: device nb x nb (bx major), cells per block side `block`,
- *   n_cells cells per side of the unit square.  Any output may be NULL.
+ *   c = cos(7x) cos(7y) exp(-t) (kind 5: without exp(-t)),
+ *   f = dt c - div(d grad c) (inside each triangle for kinds 3, 4),
+ *   c_D = c, g_N = -grad c . nu, c0 = c at t = 0.
+ *   dT: device, K values (kinds 3, 4 only, else NULL).  Any output may be NULL;
+ *   layouts as in ldg_quad_points.
  */
-ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* blocks, int nb,
-                               int block, int n_cells, double* d, double* f, double* cD,
-                               double* gN, double* c0);
+ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* dT, double* d,
+                               double* f, double* cD, double* gN, double* c0);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ SMOOTH1, SMOOTH2, LOGNORMAL, LOGNORMAL_T, TABLE2 = 1, 2, 3, 4, 5
 
 def lognormal_blocks(n_cells, seed, sigma, block=8, contrast=1e3):
     """Block values exp(sigma*clip(xi, +-a)), a = ln(contrast)/(2 sigma), one per
-    block x block cells of the unjittered n_cells x n_cells grid."""
+    block x block cells of the n_cells x n_cells grid, indexed [bx, by]."""
     nb = -(-n_cells // block)
     rng = np.random.default_rng(seed)
     xi = rng.standard_normal((nb, nb))
@@ -25,14 +25,28 @@ def lognormal_blocks(n_cells, seed, sigma, block=8, contrast=1e3):
     return np.exp(sigma * np.clip(xi, -a, a))       # [bx, by]
 
 
+def triangle_values(blocks, n_cells, block=8):
+    """Value of the block field on every triangle of the n_cells x n_cells
+    Friedrichs-Keller mesh: a triangle takes the value of the block of cells
+    its cell belongs to, so the field jumps only across mesh edges."""
+    from .meshes import fk_cells
+    ix, iy = fk_cells(n_cells)
+    return np.ascontiguousarray(blocks[ix // block, iy // block], np.float64)
+
+
 class Workload:
-    """Coefficient d, source f, boundary data c_D, g_N and exact c of one problem."""
+    """Coefficient d, source f, boundary data c_D, g_N and exact c of one problem.
+
+    Block-field kinds (LOGNORMAL, LOGNORMAL_T) are constant on each triangle:
+    d(t, x, y) is then called with point arrays whose rows are the triangles
+    of the mesh in order ([K x R])."""
 
     def __init__(self, kind, n_cells=1, blocks=None, block=8):
         self.kind = kind
         self.n_cells = n_cells
         self.blocks = None if blocks is None else np.ascontiguousarray(blocks, np.float64)
         self.block = block
+        self.dT = None if blocks is None else triangle_values(self.blocks, n_cells, block)
         self.stationary = kind == TABLE2
 
     # --- exact solution and its derivatives -------------------------------
@@ -47,11 +61,10 @@ class Workload:
 
     # --- diffusion coefficient and its gradient ----------------------------
     def _block_value(self, x, y):
-        hb = self.block / self.n_cells
-        nb = self.blocks.shape[0]
-        bx = np.clip(np.floor(x / hb).astype(np.int64), 0, nb - 1)
-        by = np.clip(np.floor(y / hb).astype(np.int64), 0, nb - 1)
-        return self.blocks[bx, by]
+        x = np.asarray(x)
+        if x.ndim == 0 or x.shape[0] != self.dT.shape[0]:
+            raise ValueError("block fields are sampled triangle by triangle: rows must be the K triangles")
+        return self.dT.reshape((-1,) + (1,) * (x.ndim - 1)) * np.ones_like(x)
 
     def d(self, t, x, y):
         if self.kind == SMOOTH1:

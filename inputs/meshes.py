@@ -31,6 +31,14 @@ def fk_square(n):
     return coordV.astype(np.float64), V0T
 
 
+def fk_cells(n):
+    """(ix, iy): the square cell of every triangle of fk_square(n) (x index, y index)."""
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    iy = i.T.reshape(-1)                              # j outer, i inner
+    ix = j.T.reshape(-1)
+    return np.concatenate([ix, ix]), np.concatenate([iy, iy])
+
+
 def jitter(coordV, n, seed, amp=0.2):
     """Move every interior vertex by i.i.d. U[-amp*h, amp*h] per coordinate."""
     h = 1.0 / n

@@ -38,6 +38,13 @@ struct ldg_ctx {
   int mmax = 0;
   double t = 0.0;
   bool blocks_ready = false;
+  // kernel timing
+  struct Pending { int id; hipEvent_t a, b; double bytes, flops; };
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  std::vector<Pending> pending;
+  ldg_kernel_stat stats[LDG_K_COUNT] = {};
+  int64_t n_sd = 0, n_nd = 0;   // local edges that are not Neumann / not Dirichlet
 };
 
 namespace {
@@ -87,18 +94,110 @@ ldg_status check_launch(ldg_ctx* c) {
   return LDG_OK;
 }
 
+hipEvent_t ev_get(ldg_ctx* c) {
+  if (!c->evpool.empty()) {
+    hipEvent_t e = c->evpool.back();
+    c->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records HIP events around the launches of its scope when timing is on.
+struct Timed {
+  ldg_ctx* c;
+  int id;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  Timed(ldg_ctx* c_, int id_, double bytes_, double flops_) : c(c_), id(id_), bytes(bytes_), flops(flops_) {
+    if (c->timing) {
+      a = ev_get(c);
+      if (a) hipEventRecord(a, c->st);
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = ev_get(c);
+    if (!b) return;
+    hipEventRecord(b, c->st);
+    c->pending.push_back({id, a, b, bytes, flops});
+  }
+};
+
+void drain_events(ldg_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& s = c->stats[p.id];
+      s.launches += 1;
+      s.total_ms += ms;
+      s.bytes += p.bytes;
+      s.flops += p.flops;
+    }
+    c->evpool.push_back(p.a);
+    c->evpool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
 ldg_status sync(ldg_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->st));
+  if (!c->pending.empty()) drain_events(c);
   return LDG_OK;
+}
+
+// algorithmic bytes / flops of the FP64 kernels (each operand once)
+double div_bytes(const ldg_ctx* c) {
+  const double NN = (double)c->N * c->N;
+  return 8.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 8.0 * 4.0 * c->N * c->K + 74.0 * c->K;
+}
+double div_flops(const ldg_ctx* c) {
+  const double NN = (double)c->N * c->N;
+  return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 2.0 * NN * (c->n_sd + 2.0 * c->Eint) +
+         2.0 * c->N * c->K;
+}
+double grad_bytes(const ldg_ctx* c, bool with_j) {
+  return 8.0 * (with_j ? 5.0 : 3.0) * c->N * c->K + 130.0 * c->K;
+}
+double grad_flops(const ldg_ctx* c) {
+  const double NN = (double)c->N * c->N;
+  return 2.0 * NN * (2.0 * c->K + c->n_nd + 2.0 * c->Eint) + 6.0 * c->N * c->K;
 }
 
 // ---- operator pieces -------------------------------------------------------
 // y = M x + tau (eta S' x + sum_m B^m Zx^m), Zx^m = -M^{-1}(A^m x + [J^m])
 void apply_op(ldg_ctx* c, double tau, const double* x, bool with_j, double* Zx1, double* Zx2,
               double* y) {
-  launch_grad(c->N, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr, Zx1,
-              Zx2, c->st);
+  {
+    Timed tm(c, LDG_K_GRAD, grad_bytes(c, with_j), grad_flops(c));
+    launch_grad(c->N, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr, Zx1,
+                Zx2, c->st);
+  }
+  Timed tm(c, LDG_K_DIV, div_bytes(c), div_flops(c));
   launch_div(c->N, c->geo, c->refs, c->blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y, c->st);
+}
+
+void bj_apply(ldg_ctx* c, double* v, double* z) {
+  const double NN = (double)c->N * c->N;
+  Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
+  launch_bj_apply(c->N, c->geo, c->bj, v, nullptr, 0, z, c->st);
+}
+
+void kdots(ldg_ctx* c, int nv, const double* V, const double* w) {
+  Timed tm(c, LDG_K_KRYLOV, 8.0 * (nv + 1) * c->nvec, 2.0 * (nv + 1) * c->nvec);
+  launch_dots(c->red, c->nvec, nv, V, c->nvec, w, c->st);
+}
+
+void kupdate(ldg_ctx* c, int nv, const double* V, const double* h, double* w) {
+  Timed tm(c, LDG_K_KRYLOV, 8.0 * (nv + 2) * c->nvec, 2.0 * (nv + 1) * c->nvec);
+  launch_update(c->red2, c->nvec, nv, V, c->nvec, h, w, c->st);
+}
+
+void kaxpby(ldg_ctx* c, double a, const double* x, double b, double* y) {
+  Timed tm(c, LDG_K_KRYLOV, 8.0 * (b == 0.0 ? 2.0 : 3.0) * c->nvec, 2.0 * c->nvec);
+  launch_axpby(c->nvec, a, x, b, y, c->st);
 }
 
 // host copy of Reducer results
@@ -109,7 +208,7 @@ ldg_status fetch(ldg_ctx* c, const double* dev, int n, double* host) {
 }
 
 ldg_status dot_self(ldg_ctx* c, const double* x, double* out) {
-  launch_dots(c->red, c->nvec, 0, nullptr, 0, x, c->st);
+  kdots(c, 0, nullptr, x);
   TRY(check_launch(c));
   return fetch(c, c->red.result, 1, out);
 }
@@ -128,7 +227,7 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
   double beta = 0.0;
   // true residual of the start value
   apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
-  launch_axpby(n, 1.0, c->b3, -1.0, c->w, c->st);   // w = b3 - F(X)
+  kaxpby(c, 1.0, c->b3, -1.0, c->w);   // w = b3 - F(X)
   TRY(dot_self(c, c->w, hb));
   beta = std::sqrt(hb[0]);
   while (true) {
@@ -137,18 +236,18 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
     if (iters >= c->opt.max_iters) break;
     ++cycles;
     // V0 = w / beta
-    launch_axpby(n, 1.0 / beta, c->w, 0.0, c->V, c->st);
+    kaxpby(c, 1.0 / beta, c->w, 0.0, c->V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       double* vj = c->V + (int64_t)j * n;
       double* vn = c->V + (int64_t)(j + 1) * n;
-      launch_bj_apply(c->N, c->geo, c->bj, vj, nullptr, 0, c->z, c->st);
+      bj_apply(c, vj, c->z);
       apply_op(c, tau, c->z, false, c->tZ1, c->tZ2, vn);
       // classical Gram-Schmidt with one conditional re-orthogonalisation
-      launch_dots(c->red, n, j + 1, c->V, n, vn, c->st);
-      launch_update(c->red2, n, j + 1, c->V, n, c->red.result, vn, c->st);
+      kdots(c, j + 1, c->V, vn);
+      kupdate(c, j + 1, c->V, c->red.result, vn);
       TRY(check_launch(c));
       HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, c->st));
       HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -157,8 +256,8 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
       double wn = std::sqrt(hb[m + 2]);
       for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i];
       if (wn < 0.7 * wn0) {
-        launch_dots(c->red, n, j + 1, c->V, n, vn, c->st);
-        launch_update(c->red2, n, j + 1, c->V, n, c->red.result, vn, c->st);
+        kdots(c, j + 1, c->V, vn);
+        kupdate(c, j + 1, c->V, c->red.result, vn);
         HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
         TRY(sync(c));
@@ -166,7 +265,7 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
         wn = std::sqrt(hb[m + 2]);
       }
       H[(j + 1) * m + j] = wn;
-      if (wn > 0.0) launch_axpby(n, 1.0 / wn, vn, 0.0, vn, c->st);
+      if (wn > 0.0) kaxpby(c, 1.0 / wn, vn, 0.0, vn);
       // Givens rotations
       for (int i = 0; i < j; ++i) {
         const double a = H[i * m + j], b = H[(i + 1) * m + j];
@@ -193,12 +292,15 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
       y[i] = s / H[i * m + i];
     }
     HIPCHK(c, hipMemcpyAsync(c->ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, c->st));
-    launch_lincomb(n, jend, c->V, n, c->ydev, c->u, c->st);
-    launch_bj_apply(c->N, c->geo, c->bj, c->u, nullptr, 0, c->z, c->st);
-    launch_axpby(n, 1.0, c->z, 1.0, c->X, c->st);
+    {
+      Timed tm(c, LDG_K_KRYLOV, 8.0 * (jend + 1) * n, 2.0 * jend * n);
+      launch_lincomb(n, jend, c->V, n, c->ydev, c->u, c->st);
+    }
+    bj_apply(c, c->u, c->z);
+    kaxpby(c, 1.0, c->z, 1.0, c->X);
     // true residual
     apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
-    launch_axpby(n, 1.0, c->b3, -1.0, c->w, c->st);
+    kaxpby(c, 1.0, c->b3, -1.0, c->w);
     TRY(dot_self(c, c->w, hb));
     beta = std::sqrt(hb[0]);
   }
@@ -209,6 +311,94 @@ ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
     return fail(c, LDG_ENOCONV, "GMRES reached " + std::to_string(iters) +
                                     " iterations at relative residual " +
                                     std::to_string(beta / bnorm));
+  return LDG_OK;
+}
+
+// ---- preconditioned conjugate gradients (symmetric positive definite case) --
+// Same system and residual as gmres(); returns LDG_EUNSUPPORTED when a
+// curvature p^T A p <= 0 shows the operator is not positive definite.
+ldg_status cg(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
+  const int64_t n = c->nvec;
+  const double target = c->opt.rtol * bnorm;
+  double* hb = c->host_buf;
+  double* x = c->X;
+  double* r = c->r;
+  double* z = c->z;
+  double* p = c->u;
+  double* q = c->w;
+  int iters = 0, restarts = 0;
+  double rnorm = 0.0;
+  bool fresh = true;   // recompute the true residual and restart the recurrence
+  double rz = 0.0;
+  while (true) {
+    if (fresh) {
+      ++restarts;
+      apply_op(c, tau, x, true, c->tZ1, c->tZ2, q);
+      {
+        Timed tm(c, LDG_K_KRYLOV, 24.0 * n, 2.0 * n);
+        launch_axpby(n, 1.0, c->b3, 0.0, r, c->st);
+        launch_axpby(n, -1.0, q, 1.0, r, c->st);
+      }
+      TRY(dot_self(c, r, hb));
+      rnorm = std::sqrt(hb[0]);
+      if (!std::isfinite(rnorm)) return fail(c, LDG_ENOCONV, "non-finite residual");
+      if (rnorm <= target || iters >= c->opt.max_iters) break;
+      {
+        const double NN = (double)c->N * c->N;
+        Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
+        launch_bj_apply_dot(c->N, c->geo, c->bj, r, z, c->red, c->st);
+      }
+      TRY(fetch(c, c->red.result, 1, hb));
+      rz = hb[0];
+      HIPCHK(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+      fresh = false;
+    }
+    apply_op(c, tau, p, false, c->tZ1, c->tZ2, q);
+    kdots(c, 1, p, q);
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double pq = hb[0];
+    if (!(pq > 0.0) || !(rz > 0.0))
+      return fail(c, LDG_EUNSUPPORTED, "operator is not positive definite for CG");
+    const double alpha = rz / pq;
+    {
+      Timed tm(c, LDG_K_KRYLOV, 48.0 * n, 6.0 * n);
+      launch_cg_update(c->red2, n, alpha, p, q, x, r, c->st);
+    }
+    TRY(fetch(c, c->red2.result, 1, hb));
+    rnorm = std::sqrt(hb[0]);
+    ++iters;
+    if (!std::isfinite(rnorm)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
+    if (rnorm <= target || iters >= c->opt.max_iters) {
+      fresh = true;   // confirm with the true residual
+      continue;
+    }
+    {
+      const double NN = (double)c->N * c->N;
+      Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
+      launch_bj_apply_dot(c->N, c->geo, c->bj, r, z, c->red, c->st);
+    }
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double rz_new = hb[0];
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    kaxpby(c, 1.0, z, beta, p);
+  }
+  info->iters = iters;
+  info->restarts = restarts;
+  info->rel_residual = rnorm / bnorm;
+  if (!(rnorm <= target))
+    return fail(c, LDG_ENOCONV, "CG reached " + std::to_string(iters) +
+                                    " iterations at relative residual " +
+                                    std::to_string(rnorm / bnorm));
+  return LDG_OK;
+}
+
+// true when D has no within-element variation (relative to its mean part)
+ldg_status coefficient_is_elementwise_constant(ldg_ctx* c, bool* yes) {
+  launch_mode_norms(c->N, c->geo, c->D, c->red, c->st);
+  TRY(check_launch(c));
+  TRY(fetch(c, c->red.result, 2, c->host_buf));
+  *yes = c->host_buf[1] <= 1e-24 * c->host_buf[0];
   return LDG_OK;
 }
 
@@ -227,6 +417,7 @@ ldg_status ldg_options_default(ldg_options* o) {
   o->restart = 30;
   o->max_iters = 5000;
   o->stream = nullptr;
+  o->krylov = LDG_KRYLOV_AUTO;
   return LDG_OK;
 }
 
@@ -235,6 +426,8 @@ const char* ldg_last_error(const ldg_ctx* c) { return c ? c->err.c_str() : "null
 void ldg_destroy(ldg_ctx* c) {
   if (!c) return;
   if (c->st) hipStreamSynchronize(c->st);
+  for (auto& p : c->pending) { c->evpool.push_back(p.a); c->evpool.push_back(p.b); }
+  for (hipEvent_t e : c->evpool) hipEventDestroy(e);
   for (void* p : c->allocs) hipFree(p);
   if (c->host_buf) hipHostFree(c->host_buf);
   delete c;
@@ -246,7 +439,8 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   *out = nullptr;
   if (!coordV || !V0T || !edge_kind || !opt) return LDG_EINVAL;
   if (opt->p < 0 || opt->p > 4 || !(opt->eta > 0.0) || !(opt->rtol > 0.0) || opt->restart < 1 ||
-      opt->restart > 200 || opt->max_iters < 1)
+      opt->restart > 200 || opt->max_iters < 1 || opt->krylov < LDG_KRYLOV_AUTO ||
+      opt->krylov > LDG_KRYLOV_CG)
     return LDG_EINVAL;
   if (opt->precision != LDG_FP64 || opt->precond != LDG_PC_BLOCK_JACOBI) return LDG_EUNSUPPORTED;
   ldg_ctx* c = new ldg_ctx();
@@ -277,6 +471,10 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   c->Eint = hm.E_int;
   c->nvec = c->Kpad * c->N;
   c->mmax = opt->restart;
+  for (int64_t k = 0; k < 3 * K; ++k) {
+    c->n_sd += edge_kind[k] != LDG_EDGE_NEUMANN;
+    c->n_nd += edge_kind[k] != LDG_EDGE_DIRICHLET;
+  }
   const int64_t Kp = c->Kpad;
   const int N = c->N, NN = c->NN;
   // geometry
@@ -366,9 +564,15 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(dalloc(c, &c->status, 1));
   c->red.nblk = c->red2.nblk = krylov_nblk(nv);
   c->red.maxv = c->red2.maxv = c->mmax + 1;
-  TRY(dalloc(c, &c->red.partials, (size_t)(c->mmax + 2) * c->red.nblk));
+  {
+    size_t np = (size_t)(c->mmax + 2) * c->red.nblk;
+    const size_t nbj = (size_t)(Kp / 256 + 1);
+    if (np < nbj) np = nbj;
+    if (np < 2048) np = 2048;
+    TRY(dalloc(c, &c->red.partials, np));
+  }
   TRY(dalloc(c, &c->red.result, c->mmax + 2));
-  TRY(dalloc(c, &c->red2.partials, (size_t)c->red2.nblk));
+  TRY(dalloc(c, &c->red2.partials, (size_t)c->red2.nblk + 2048));
   TRY(dalloc(c, &c->red2.result, 1));
   HIPCHK(c, hipHostMalloc((void**)&c->host_buf, (2 * c->mmax + 8) * sizeof(double)));
   TRY(sync(c));
@@ -391,11 +595,11 @@ ldg_status ldg_get_sizes(const ldg_ctx* c, ldg_sizes* o) {
 ldg_status ldg_quad_points(ldg_ctx* c, int kind, double* x, double* y) {
   if (!c || !x || !y || kind < 0 || kind > 2) return fail(c, LDG_EINVAL, "bad arguments");
   if (kind == 0)
-    launch_sample_vol(c->geo, c->R, c->qvol, 0, 0.0, nullptr, 1, 1.0, nullptr, nullptr, nullptr, x,
-                      y, c->st);
+    launch_sample_vol(c->geo, c->R, c->qvol, 0, 0.0, nullptr, nullptr, nullptr, nullptr, x, y,
+                      c->st);
   else
     launch_sample_bnd(c->geo, c->R1, c->sb, c->nbnd, c->bk, c->bn, kind == 2 ? -1 : 0, 0.0,
-                      nullptr, 1, 1.0, nullptr, nullptr, x, y, c->st);
+                      nullptr, nullptr, x, y, c->st);
   return check_launch(c);
 }
 
@@ -488,7 +692,12 @@ ldg_status ldg_bj_setup(ldg_ctx* c, double dt) {
   if (!c || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
   if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->st));
-  launch_bj_setup(c->N, c->geo, c->refs, c->blocks, dt, c->opt.eta, c->bj, c->status, c->st);
+  {
+    const double NN = (double)c->NN;
+    Timed tm(c, LDG_K_BJ_SETUP, 8.0 * NN * (3.0 * c->K + 2.0 * c->Eint),
+             2.0 * NN * c->N * (11.0 * c->K + 2.0 * c->Eint));
+    launch_bj_setup(c->N, c->geo, c->refs, c->blocks, dt, c->opt.eta, c->bj, c->status, c->st);
+  }
   TRY(check_launch(c));
   int st = 0;
   HIPCHK(c, hipMemcpyAsync(c->host_buf, c->status, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -511,12 +720,21 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   const double tau = dt;
   const int64_t n = c->nvec;
   // a1: projections and boundary data at t + dt
-  launch_project(c->N, c->K, c->Kpad, c->R, d, c->Wvol, c->D, c->st);
-  launch_project(c->N, c->K, c->Kpad, c->R, f, c->Wvol, c->F, c->st);
-  launch_boundary(c->N, c->geo, c->nbe, c->belem, c->R1, c->Wb, c->ws, cD, gN, c->nbnd, c->D,
-                  c->opt.eta, c->J1, c->J2, c->KDN, c->st);
+  {
+    Timed tm(c, LDG_K_PROJECT, 2.0 * 8.0 * (c->R + c->N) * c->K,
+             2.0 * 2.0 * c->R * c->N * (double)c->K);
+    launch_project(c->N, c->K, c->Kpad, c->R, d, c->Wvol, c->D, c->st);
+    launch_project(c->N, c->K, c->Kpad, c->R, f, c->Wvol, c->F, c->st);
+    launch_boundary(c->N, c->geo, c->nbe, c->belem, c->R1, c->Wb, c->ws, cD, gN, c->nbnd, c->D,
+                    c->opt.eta, c->J1, c->J2, c->KDN, c->st);
+  }
   // a2, a3: D-dependent blocks
-  launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+  {
+    const double NN = (double)c->NN;
+    Timed tm(c, LDG_K_ASSEMBLE, 8.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 8.0 * c->N * c->K,
+             2.0 * NN * c->N * (5.0 * c->K + 2.0 * c->Eint));
+    launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+  }
   c->blocks_ready = true;
   TRY(check_launch(c));
   // a4: preconditioner
@@ -529,8 +747,24 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   TRY(dot_self(c, c->J2, &nj2));
   const double bnorm = std::sqrt(nb3 + tau * tau * (nj1 + nj2));
   // a6: Krylov solve starting from C^n
+  bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
+  if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
   HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  ldg_status s = gmres(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
+  ldg_status s = LDG_EUNSUPPORTED;
+  if (use_cg) {
+    info->krylov = LDG_KRYLOV_CG;
+    s = cg(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
+    if (s == LDG_EUNSUPPORTED) {   // not SPD after all: fall back to GMRES from C^n
+      info->fallbacks += 1;
+      HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    }
+  }
+  if (s == LDG_EUNSUPPORTED) {
+    info->krylov = LDG_KRYLOV_GMRES;
+    const int fb = info->fallbacks;
+    s = gmres(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
+    info->fallbacks = fb;
+  }
   info->t = c->t;
   if (s != LDG_OK) return s;
   // a10: accept; Z from the last residual evaluation of X
@@ -543,19 +777,30 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   return sync(c);
 }
 
-ldg_status ldg_sample_workload(ldg_ctx* c, int kind, double t, const double* blocks, int nb,
-                               int block, int n_cells, double* d, double* f, double* cD,
-                               double* gN, double* c0) {
+ldg_status ldg_set_timing(ldg_ctx* c, int on) {
+  if (!c) return LDG_EINVAL;
+  TRY(sync(c));
+  c->timing = on != 0;
+  for (auto& s : c->stats) s = ldg_kernel_stat{};
+  return LDG_OK;
+}
+
+ldg_status ldg_get_kernel_stat(ldg_ctx* c, int kernel, ldg_kernel_stat* out) {
+  if (!c || !out || kernel < 0 || kernel >= LDG_K_COUNT) return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(sync(c));
+  *out = c->stats[kernel];
+  return LDG_OK;
+}
+
+ldg_status ldg_sample_workload(ldg_ctx* c, int kind, double t, const double* dT, double* d,
+                               double* f, double* cD, double* gN, double* c0) {
   if (!c || kind < 1 || kind > 5) return fail(c, LDG_EINVAL, "bad workload kind");
-  if ((kind == 3 || kind == 4) && (!blocks || nb < 1 || block < 1 || n_cells < 1))
-    return fail(c, LDG_EINVAL, "block field needs blocks, nb, block, n_cells");
-  const double hb = (kind == 3 || kind == 4) ? (double)block / n_cells : 1.0;
+  if ((kind == 3 || kind == 4) && !dT) return fail(c, LDG_EINVAL, "block field needs dT");
   if (d || f || c0)
-    launch_sample_vol(c->geo, c->R, c->qvol, kind, t, blocks, nb, hb, d, f, c0, nullptr, nullptr,
-                      c->st);
+    launch_sample_vol(c->geo, c->R, c->qvol, kind, t, dT, d, f, c0, nullptr, nullptr, c->st);
   if (cD || gN)
-    launch_sample_bnd(c->geo, c->R1, c->sb, c->nbnd, c->bk, c->bn, kind, t, blocks, nb, hb, cD, gN,
-                      nullptr, nullptr, c->st);
+    launch_sample_bnd(c->geo, c->R1, c->sb, c->nbnd, c->bk, c->bn, kind, t, cD, gN, nullptr,
+                      nullptr, c->st);
   return check_launch(c);
 }
 

@@ -26,12 +26,11 @@ void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* 
 void launch_from_tiled(int64_t K, int N, const double* src, double* dst, hipStream_t st);
 void launch_export_blocks(int64_t K, int N, int ns, const double* src, double* dst,
                           hipStream_t st);
-void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* blk,
-                       int nb, double hb, double* d, double* f, double* c0, double* xo, double* yo,
-                       hipStream_t st);
+void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* dT,
+                       double* d, double* f, double* c0, double* xo, double* yo, hipStream_t st);
 void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, const int32_t* bk,
-                       const int8_t* bn, int kind, double t, const double* blk, int nb, double hb,
-                       double* cD, double* gN, double* xo, double* yo, hipStream_t st);
+                       const int8_t* bn, int kind, double t, double* cD, double* gN, double* xo,
+                       double* yo, hipStream_t st);
 
 // Krylov vector kernels (kernels_krylov.hip); n = vector length, V = basis
 // with vectors at V + j*ldv.  Reductions are two-stage and fixed-order.
@@ -56,6 +55,14 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 // b3 = 2|T| C + tau (KDN + 2|T| F) in the tiled layout
 void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,
                 double tau, double* b3, hipStream_t st);
+// CG: x += a p, r -= a q; result[0] = <r, r> afterwards
+void launch_cg_update(const Reducer& r, int64_t n, double a, const double* p, const double* q,
+                      double* x, double* rv, hipStream_t st);
+// z = P^{-1} r (block Jacobi); result[0] = <r, z>
+void launch_bj_apply_dot(int N, const Geo& g, const double* bj, const double* rv, double* z,
+                         const Reducer& red, hipStream_t st);
+// result[0] = sum_k D_k0^2, result[1] = sum_k sum_{i>0} D_ki^2
+void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st);
 // out = s * area2 * (Za - Zb) per element (full-operator rows 1, 2)
 void launch_zrows(const Geo& g, int N, const double* Za, const double* Zb, double s, double* out,
                   hipStream_t st);

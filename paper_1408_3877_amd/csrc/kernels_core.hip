@@ -525,6 +525,32 @@ __global__ void __launch_bounds__(256) k_bj_apply(Geo g, const double* __restric
   store_vec<N>(z, k, acc);
 }
 
+// z = P^{-1} r and per-block partial sums of <r, z> (reduced by k_reduce_partials)
+template <int N>
+__global__ void __launch_bounds__(256) k_bj_apply_dot(Geo g, const double* __restrict__ bj,
+                                                      const double* __restrict__ r,
+                                                      double* __restrict__ z,
+                                                      double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (k < g.Kpad) {
+    double x[N], acc[N];
+    load_vec<N>(r, k, x);
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0.0;
+    block_mv<N>(bj, k, 0, 1, x, acc);
+    store_vec<N>(z, k, acc);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += x[i] * acc[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // ---------------------------------------------------------------------------
 // Layout conversion and export
 // ---------------------------------------------------------------------------
@@ -564,8 +590,8 @@ __global__ void k_export_blocks(int64_t K, int N, int ns, const double* __restri
 namespace {
 struct Fields { double d, f, c; double gcx, gcy; };
 
-__device__ Fields eval_fields(int kind, double t, double x, double y, const double* blk, int nb,
-                              double hb) {
+// dT: the coefficient value of the triangle (block-field kinds 3, 4)
+__device__ Fields eval_fields(int kind, double t, double x, double y, double dT) {
   Fields F;
   const double e = kind == 5 ? 1.0 : exp(-t);
   const double cx = cos(7.0 * x), cy = cos(7.0 * y), sx = sin(7.0 * x), sy = sin(7.0 * y);
@@ -584,10 +610,7 @@ __device__ Fields eval_fields(int kind, double t, double x, double y, const doub
     dx = F.d * pi * cos(2 * pi * x) * sin(2 * pi * y);
     dy = F.d * pi * sin(2 * pi * x) * cos(2 * pi * y);
   } else if (kind == 3 || kind == 4) {
-    long bx = (long)floor(x / hb), by = (long)floor(y / hb);
-    bx = bx < 0 ? 0 : (bx > nb - 1 ? nb - 1 : bx);
-    by = by < 0 ? 0 : (by > nb - 1 ? nb - 1 : by);
-    F.d = blk[bx * nb + by] * (kind == 4 ? 1.0 + 0.1 * sin(t) : 1.0);
+    F.d = dT * (kind == 4 ? 1.0 + 0.1 * sin(t) : 1.0);
   } else {
     F.d = exp(x + y);
     dx = dy = F.d;
@@ -599,8 +622,8 @@ __device__ Fields eval_fields(int kind, double t, double x, double y, const doub
 }  // namespace
 
 __global__ void k_sample_vol(Geo g, int R, const double* __restrict__ q, int kind, double t,
-                             const double* __restrict__ blk, int nb, double hb,
-                             double* __restrict__ d, double* __restrict__ f,
+                             const double* __restrict__ dT, double* __restrict__ d,
+                             double* __restrict__ f,
                              double* __restrict__ c0, double* __restrict__ xo,
                              double* __restrict__ yo) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -613,16 +636,16 @@ __global__ void k_sample_vol(Geo g, int R, const double* __restrict__ q, int kin
   const double y = g.a1[Kp + k] + g.B[2 * Kp + k] * q1 + g.B[3 * Kp + k] * q2;
   if (xo) { xo[idx] = x; yo[idx] = y; }
   if (!(d || f || c0)) return;
-  const Fields F = eval_fields(kind, t, x, y, blk, nb, hb);
+  const double dv = dT ? dT[k] : 0.0;
+  const Fields F = eval_fields(kind, t, x, y, dv);
   if (d) d[idx] = F.d;
   if (f) f[idx] = F.f;
-  if (c0) c0[idx] = eval_fields(kind, 0.0, x, y, blk, nb, hb).c;
+  if (c0) c0[idx] = eval_fields(kind, 0.0, x, y, dv).c;
 }
 
 __global__ void k_sample_bnd(Geo g, int R1, const double* __restrict__ s, int64_t nbnd,
                              const int32_t* __restrict__ bk, const int8_t* __restrict__ bn,
-                             int kind, double t, const double* __restrict__ blk, int nb, double hb,
-                             double* __restrict__ cD, double* __restrict__ gN,
+                             int kind, double t, double* __restrict__ cD, double* __restrict__ gN,
                              double* __restrict__ xo, double* __restrict__ yo) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)R1 * nbnd) return;
@@ -644,7 +667,7 @@ __global__ void k_sample_bnd(Geo g, int R1, const double* __restrict__ s, int64_
     else { xo[idx] = x; yo[idx] = y; }
   }
   if (kind <= 0 || !(cD || gN)) return;
-  const Fields F = eval_fields(kind, t, x, y, blk, nb, hb);
+  const Fields F = eval_fields(kind, t, x, y, 1.0);
   if (cD) cD[idx] = F.c;
   if (gN) gN[idx] = -(F.gcx * nu1 + F.gcy * nu2);
 }
@@ -711,6 +734,15 @@ void launch_bj_apply(int N, const Geo& g, const double* bj, double* v, const dou
                                                                       write_back, z)));
 }
 
+void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st);
+
+void launch_bj_apply_dot(int N, const Geo& g, const double* bj, const double* rv, double* z,
+                         const Reducer& red, hipStream_t st) {
+  const unsigned nb = nblk(g.Kpad, 256);
+  LDG_SWITCH_N(N, (k_bj_apply_dot<NT><<<nb, 256, 0, st>>>(g, bj, rv, z, red.partials)));
+  reduce_partials((int)nb, red.partials, red.result, st);
+}
+
 void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
                      hipStream_t st) {
   k_to_tiled<<<nblk(Kpad * N, 256), 256, 0, st>>>(K, Kpad, N, src, dst);
@@ -725,19 +757,18 @@ void launch_export_blocks(int64_t K, int N, int ns, const double* src, double* d
   k_export_blocks<<<nblk(K * ns * N * N, 256), 256, 0, st>>>(K, N, ns, src, dst);
 }
 
-void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* blk,
-                       int nb, double hb, double* d, double* f, double* c0, double* xo, double* yo,
-                       hipStream_t st) {
-  k_sample_vol<<<nblk((int64_t)R * g.K, 256), 256, 0, st>>>(g, R, q, kind, t, blk, nb, hb, d, f,
-                                                             c0, xo, yo);
+void launch_sample_vol(const Geo& g, int R, const double* q, int kind, double t, const double* dT,
+                       double* d, double* f, double* c0, double* xo, double* yo, hipStream_t st) {
+  k_sample_vol<<<nblk((int64_t)R * g.K, 256), 256, 0, st>>>(g, R, q, kind, t, dT, d, f, c0, xo,
+                                                             yo);
 }
 
 void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, const int32_t* bk,
-                       const int8_t* bn, int kind, double t, const double* blk, int nb, double hb,
-                       double* cD, double* gN, double* xo, double* yo, hipStream_t st) {
+                       const int8_t* bn, int kind, double t, double* cD, double* gN, double* xo,
+                       double* yo, hipStream_t st) {
   if (nbnd == 0) return;
-  k_sample_bnd<<<nblk((int64_t)R1 * nbnd, 256), 256, 0, st>>>(g, R1, s, nbnd, bk, bn, kind, t, blk,
-                                                               nb, hb, cD, gN, xo, yo);
+  k_sample_bnd<<<nblk((int64_t)R1 * nbnd, 256), 256, 0, st>>>(g, R1, s, nbnd, bk, bn, kind, t, cD,
+                                                               gN, xo, yo);
 }
 
 }  // namespace ldg

@@ -141,6 +141,61 @@ __global__ void k_zrows(Geo g, int N, const double* __restrict__ Za, const doubl
   out[t] = s * a2 * (Za[t] - Zb[t]);
 }
 
+__global__ void __launch_bounds__(KB) k_cg_update(int64_t n, double a,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ q,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[KB / 64];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < KITEMS; ++t) {
+    const int64_t i = base + (int64_t)t * KB;
+    if (i < n) {
+      x[i] += a * p[i];
+      const double ri = r[i] - a * q[i];
+      r[i] = ri;
+      s += ri * ri;
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(KB) k_mode_norms(int64_t Kpad, int N, const double* __restrict__ D,
+                                                   double* __restrict__ partials, int nblk) {
+  __shared__ double red[KB / 64];
+  double s0 = 0.0, s1 = 0.0;
+  const int64_t n = Kpad * N;
+  for (int64_t t = (int64_t)blockIdx.x * KB + threadIdx.x; t < n; t += (int64_t)nblk * KB) {
+    const int i = (int)((t / 64) % N);
+    const double v = D[t];
+    if (i == 0) s0 += v * v; else s1 += v * v;
+  }
+  s0 = block_sum(s0, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) partials[nblk + blockIdx.x] = s1;
+}
+
+void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st) {
+  k_reduce<<<1, KB, 0, st>>>(nblk, partials, result);
+}
+
+void launch_cg_update(const Reducer& r, int64_t n, double a, const double* p, const double* q,
+                      double* x, double* rv, hipStream_t st) {
+  const int nb = krylov_nblk(n);
+  k_cg_update<<<nb, KB, 0, st>>>(n, a, p, q, x, rv, r.partials);
+  k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+}
+
+void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st) {
+  const int nb = red.nblk < 1024 ? red.nblk : 1024;
+  k_mode_norms<<<nb, KB, 0, st>>>(g.Kpad, N, D, red.partials, nb);
+  k_reduce<<<2, KB, 0, st>>>(nb, red.partials, red.result);
+}
+
 void launch_dots(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
                  const double* w, hipStream_t st) {
   const int nb = krylov_nblk(n);

@@ -26,7 +26,7 @@ class LdgError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("p", C.c_int), ("eta", C.c_double), ("precision", C.c_int),
                 ("precond", C.c_int), ("rtol", C.c_double), ("restart", C.c_int),
-                ("max_iters", C.c_int), ("stream", C.c_void_p)]
+                ("max_iters", C.c_int), ("stream", C.c_void_p), ("krylov", C.c_int)]
 
 
 class Sizes(C.Structure):
@@ -34,9 +34,18 @@ class Sizes(C.Structure):
                 ("n_bnd", C.c_int64), ("E_int", C.c_int64)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
+KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project"]
+
+
 class StepInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("ir_steps", C.c_int),
-                ("fallbacks", C.c_int), ("rel_residual", C.c_double), ("t", C.c_double)]
+                ("fallbacks", C.c_int), ("krylov", C.c_int), ("rel_residual", C.c_double),
+                ("t", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -59,8 +68,9 @@ _SIGS = {
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
     "ldg_get_bj": [_P, _P],
-    "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P,
-                            _P, _P],
+    "ldg_set_timing": [_P, C.c_int],
+    "ldg_get_kernel_stat": [_P, C.c_int, C.POINTER(KernelStat)],
+    "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, _P, _P, _P, _P, _P],
 }
 
 _lib = None
@@ -100,7 +110,7 @@ class Solver:
 
     def __init__(self, coordV, V0T, edge_kind, p, eta=1.0, precision=LDG_FP64,
                  precond=LDG_PC_BLOCK_JACOBI, rtol=1e-8, restart=30, max_iters=5000,
-                 device=None):
+                 krylov=0, device=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -113,7 +123,7 @@ class Solver:
         opt = Options()
         self.lib.ldg_options_default(C.byref(opt))
         opt.p, opt.eta, opt.precision, opt.precond = p, eta, precision, precond
-        opt.rtol, opt.restart, opt.max_iters = rtol, restart, max_iters
+        opt.rtol, opt.restart, opt.max_iters, opt.krylov = rtol, restart, max_iters, krylov
         with torch.cuda.device(self.device):
             opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
             h = C.c_void_p()
@@ -222,14 +232,25 @@ class Solver:
         self._check(self.lib.ldg_get_bj(self.h, _ptr(out)))
         return out
 
-    def sample_workload(self, kind, t, blocks=None, block=8, n_cells=1, want=("d", "f", "cD", "gN")):
-        bl = None if blocks is None else self._dev(np.ascontiguousarray(blocks, np.float64).reshape(-1))
-        nb = 0 if blocks is None else int(np.asarray(blocks).shape[0])
+    def set_timing(self, on):
+        self._check(self.lib.ldg_set_timing(self.h, int(bool(on))))
+
+    def kernel_stats(self):
+        out = {}
+        for i, name in enumerate(KERNELS):
+            st = KernelStat()
+            self._check(self.lib.ldg_get_kernel_stat(self.h, i, C.byref(st)))
+            out[name] = {"launches": st.launches, "total_ms": st.total_ms, "bytes": st.bytes,
+                         "flops": st.flops}
+        return out
+
+    def sample_workload(self, kind, t, dT=None, want=("d", "f", "cD", "gN")):
+        dTd = None if dT is None else self._dev(dT, (self.K,))
         nv, nbd = self.R * self.K, self.R1 * self.n_bnd
         out = {}
         for name, n in (("d", nv), ("f", nv), ("cD", nbd), ("gN", nbd), ("c0", nv)):
             out[name] = self._empty(max(n, 1))[:n] if name in want else None
         self._check(self.lib.ldg_sample_workload(
-            self.h, int(kind), float(t), _ptr(bl), nb, int(block), int(n_cells), _ptr(out["d"]),
-            _ptr(out["f"]), _ptr(out["cD"]), _ptr(out["gN"]), _ptr(out["c0"])))
+            self.h, int(kind), float(t), _ptr(dTd), _ptr(out["d"]), _ptr(out["f"]),
+            _ptr(out["cD"]), _ptr(out["gN"]), _ptr(out["c0"])))
         return out

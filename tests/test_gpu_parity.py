@@ -118,14 +118,15 @@ def test_apply_and_preconditioner(torch_mod, n, seed, neu, p):
         assert np.abs(bj[k] - inv).max() <= 1e-10 * np.abs(inv).max(), k
 
 
-def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0):
+def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0, krylov=0,
+               expect_krylov=None):
     cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
     pr = Problem(cV, V0T, kind, p)
     w = workload(wkind, n, seed=seed, sigma=sigma, block=block)
-    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000)
+    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000, krylov=krylov)
     gk = {SMOOTH1: 1, SMOOTH2: 2, LOGNORMAL: 3, LOGNORMAL_T: 4, TABLE2: 5}[wkind]
-    blocks = getattr(w, "blocks", None)
-    smp0 = s.sample_workload(gk, t0, blocks=blocks, block=block, n_cells=n, want=("c0",))
+    dT = getattr(w, "dT", None)
+    smp0 = s.sample_workload(gk, t0, dT=dT, want=("c0",))
     s.set_initial_samples(smp0["c0"], t0)
     C = pr.initial(w)
     assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-13
@@ -133,9 +134,11 @@ def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0):
     worst = 0.0
     for _ in range(steps):
         t += dt
-        smp = s.sample_workload(gk, t, blocks=blocks, block=block, n_cells=n)
+        smp = s.sample_workload(gk, t, dT=dT)
         info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
         assert info["rel_residual"] <= 1e-13
+        if expect_krylov is not None:
+            assert info["krylov"] == expect_krylov and info["fallbacks"] == 0, info
         C, Z1, Z2, oi = pr.step(C, t, dt, w)
         Cg, Z1g, Z2g = (to_np(x) for x in s.get_solution())
         worst = max(worst, rel_l2(pr.grid.areaT, Cg, C))
@@ -157,3 +160,14 @@ def test_steps_config1(torch_mod):
 ])
 def test_steps_small(torch_mod, p, n, seed, neu, wk):
     assert _run_steps(p, n, seed, neu, wk, 3, 0.02, block=2) < 1e-10
+
+
+@pytest.mark.parametrize("p,n,seed,neu,wk,krylov,expect", [
+    (4, 6, 301, (), LOGNORMAL_T, 0, 2),         # auto picks CG for an element-wise constant d
+    (3, 9, 302, (SOUTH,), LOGNORMAL, 1, 1),     # GMRES forced on the same kind of data
+    (2, 9, 303, (), SMOOTH2, 0, 1),             # auto picks GMRES when d varies inside triangles
+    (1, 10, 304, (EAST, WEST), LOGNORMAL, 2, 2),
+])
+def test_krylov_selection(torch_mod, p, n, seed, neu, wk, krylov, expect):
+    assert _run_steps(p, n, seed, neu, wk, 2, 0.05, block=3, krylov=krylov,
+                      expect_krylov=expect) < 1e-10

@@ -120,6 +120,32 @@ def test_constant_d_adjointness(neumann):
     assert np.linalg.eigvalsh(S).min() > 0
 
 
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_elementwise_constant_d_gives_spd_operator(p):
+    # d constant on every triangle: B^m = -(A^m)^T diag(d), so the eliminated
+    # operator M + tau(eta S' + sum_m A^mT diag(d) M^-1 A^m) is SPD (CG applies)
+    cV, V0T, kind = square_mesh(4, seed=61, neumann_sides=(NORTH,))
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(p)
+    rng = np.random.default_rng(p)
+    d = np.exp(2.0 * rng.standard_normal(g.numT))
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = d / np.sqrt(2)
+    b = Blocks(g, refs, D)
+    N = refs.N
+    for m in range(2):
+        A = (-b.H[m] + b.Q[m] + b.QN[m]).toarray()
+        B = (-b.G[m] + b.R[m] + b.RD[m]).toarray()
+        np.testing.assert_allclose(B, -A.T * np.repeat(d, N)[None, :], atol=1e-11 * d.max())
+    S = schur_matrix(b, g, refs, 1.0, 0.05).toarray()
+    np.testing.assert_allclose(S, S.T, atol=1e-13 * np.abs(S).max())
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() > 0
+    # a coefficient varying inside the triangles breaks the symmetry
+    D[:, 1] = 0.1
+    S2 = schur_matrix(Blocks(g, refs, D), g, refs, 1.0, 0.05).toarray()
+    assert np.abs(S2 - S2.T).max() > 1e-6 * np.abs(S2).max()
+
+
 def test_schur_elimination_equals_full_solve():
     cV, V0T, kind = square_mesh(4, seed=51, neumann_sides=(SOUTH,))
     pr = Problem(cV, V0T, kind, 2)
