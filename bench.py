@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--config", default=DEFAULT, choices=sorted(CONFIGS))
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="inner-solve precision (fp32/bf16: mixed with FP64 refinement)")
+    ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
@@ -125,8 +128,9 @@ def main():
     coordV, V0T, kind, dT = make_inputs(cfg)
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
+    prec = {"fp64": 0, "fp32": 1, "bf16": 2}[args.precision]
     s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
-               max_iters=20000)
+               max_iters=20000, precision=prec, inner_rtol=args.inner_rtol)
     log("[bench] context: K=%d N=%d (%.1f s)" % (s.K, s.N, time.perf_counter() - t0))
     gk = cfg["kind"]
     s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
@@ -157,8 +161,9 @@ def main():
     for i in range(args.steps):
         info = one_step()
         infos.append(info)
-        log("[bench] step %d: iters=%d restarts=%d rel_res=%.2e" %
-            (i, info["iters"], info["restarts"], info["rel_residual"]))
+        log("[bench] step %d: iters=%d sweeps=%d fallbacks=%d krylov=%d rel_res=%.2e" %
+            (i, info["iters"], info["restarts"], info["fallbacks"], info["krylov"],
+             info["rel_residual"]))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     stats = s.kernel_stats()
@@ -167,6 +172,8 @@ def main():
     value = dof * args.steps / el
     dv = stats["div"]
     ach = dv["bytes"] / (dv["total_ms"] * 1e-3) / 1e9 if dv["total_ms"] > 0 else 0.0
+    # the roofline is reported for the FP64 operator apply; in the mixed modes the
+    # launches mix FP64 residual applies and low-precision inner applies
     per_launch = dv["bytes"] / max(dv["launches"], 1)
     traffic = measured_traffic(args.config)
     res = {
@@ -180,11 +187,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
-                   "dt": dt, "rtol": args.rtol, "solver": "fp64 block-Jacobi GMRES(%d)" % args.restart,
-                   "iters_per_step": sum(i["iters"] for i in infos) / len(infos)},
+                   "dt": dt, "rtol": args.rtol,
+                   "solver": "%s block-Jacobi %s%s" % (
+                       args.precision, "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
+                       "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol),
+                   "iters_per_step": sum(i["iters"] for i in infos) / len(infos),
+                   "fallbacks": sum(i["fallbacks"] for i in infos)},
         "roofline": {"bound": "hbm", "kernel": "k_div (operator apply, stored blocks)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,

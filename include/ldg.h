@@ -50,6 +50,14 @@ typedef enum {
   LDG_EUNSUPPORTED = -6
 } ldg_status;
 
+/*
+ * LDG_FP64: everything in FP64.  Mixed modes: the state, the residual of the
+ * full system and the refinement correction stay FP64; each refinement
+ * sweep solves A d = r with FP32 vectors (FP64 inner products), the stored
+ * blocks in FP32 or BF16 and FP32 arithmetic, and a FP32 block-Jacobi.  A
+ * sweep that fails to halve the residual moves the inner solve one
+ * precision up (BF16 -> FP32 -> FP64), counted in ldg_step_info.fallbacks.
+ */
 typedef enum { LDG_FP64 = 0, LDG_MIXED_FP32 = 1, LDG_MIXED_BF16 = 2 } ldg_precision;
 typedef enum { LDG_PC_BLOCK_JACOBI = 0, LDG_PC_GNN = 1 } ldg_precond;
 typedef enum { LDG_EDGE_INTERIOR = 0, LDG_EDGE_DIRICHLET = 1, LDG_EDGE_NEUMANN = 2 } ldg_edge_kind;
@@ -72,6 +80,7 @@ typedef struct {
   int max_iters;      /* total Krylov iterations per step, default 5000 */
   void* stream;       /* hipStream_t for all device work */
   int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
+  double inner_rtol;  /* mixed modes: relative tolerance of each inner solve, default 1e-3 */
 } ldg_options;
 
 typedef struct {

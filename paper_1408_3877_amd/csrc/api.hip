@@ -31,6 +31,12 @@ struct ldg_ctx {
   double *r = nullptr, *w = nullptr, *z = nullptr, *u = nullptr, *X = nullptr;
   double *tZ1 = nullptr, *tZ2 = nullptr, *tmp = nullptr;
   double *blocks = nullptr, *bj = nullptr, *V = nullptr;
+  double *d64 = nullptr, *u2 = nullptr, *iz1 = nullptr, *iz2 = nullptr;
+  // mixed modes: FP32 work vectors, low-precision blocks, FP32 block-Jacobi
+  float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+  float *u32 = nullptr, *tz1_32 = nullptr, *tz2_32 = nullptr, *V32 = nullptr;
+  void *blocks_f32 = nullptr, *blocks_bf16 = nullptr, *bj_f32 = nullptr;
+  bool blocks_f32_ready = false;
   double *hdev = nullptr, *ydev = nullptr;
   int* status = nullptr;
   Reducer red, red2;
@@ -148,56 +154,68 @@ ldg_status sync(ldg_ctx* c) {
   return LDG_OK;
 }
 
-// algorithmic bytes / flops of the FP64 kernels (each operand once)
-double div_bytes(const ldg_ctx* c) {
+// ---- one precision level of the solver ------------------------------------
+// vt: vector storage, bt: stored-block storage; work vectors of that level.
+struct Level {
+  int vt = VT_F64, bt = BT_F64;
+  const void* blocks = nullptr;
+  const void* bj = nullptr;
+  void *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *d = nullptr, *u = nullptr;
+  void *tz1 = nullptr, *tz2 = nullptr, *V = nullptr;
+  double vbytes = 8.0, bbytes = 8.0;   // bytes per vector / block entry
+};
+
+double div_bytes(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
-  return 8.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 8.0 * 4.0 * c->N * c->K + 74.0 * c->K;
+  return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + L.vbytes * 4.0 * c->N * c->K + 74.0 * c->K;
 }
 double div_flops(const ldg_ctx* c) {
   const double NN = (double)c->N * c->N;
   return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 2.0 * NN * (c->n_sd + 2.0 * c->Eint) +
          2.0 * c->N * c->K;
 }
-double grad_bytes(const ldg_ctx* c, bool with_j) {
-  return 8.0 * (with_j ? 5.0 : 3.0) * c->N * c->K + 130.0 * c->K;
+double grad_bytes(const ldg_ctx* c, const Level& L, bool with_j) {
+  return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + 130.0 * c->K;
 }
 double grad_flops(const ldg_ctx* c) {
   const double NN = (double)c->N * c->N;
   return 2.0 * NN * (2.0 * c->K + c->n_nd + 2.0 * c->Eint) + 6.0 * c->N * c->K;
 }
 
-// ---- operator pieces -------------------------------------------------------
-// y = M x + tau (eta S' x + sum_m B^m Zx^m), Zx^m = -M^{-1}(A^m x + [J^m])
-void apply_op(ldg_ctx* c, double tau, const double* x, bool with_j, double* Zx1, double* Zx2,
-              double* y) {
+// y = M x + tau (eta S' x + sum_m B^m Z^m(x)), Z^m(x) = -M^{-1}(A^m x [+ J^m])
+void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j, void* Zx1,
+              void* Zx2, void* y) {
   {
-    Timed tm(c, LDG_K_GRAD, grad_bytes(c, with_j), grad_flops(c));
-    launch_grad(c->N, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr, Zx1,
-                Zx2, c->st);
+    Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c));
+    launch_grad(c->N, L.vt, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
+                Zx1, Zx2, c->st);
   }
-  Timed tm(c, LDG_K_DIV, div_bytes(c), div_flops(c));
-  launch_div(c->N, c->geo, c->refs, c->blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y, c->st);
+  Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c));
+  launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y,
+             c->st);
 }
 
-void bj_apply(ldg_ctx* c, double* v, double* z) {
+void bj_apply(ldg_ctx* c, const Level& L, const void* r, void* z, bool dot) {
   const double NN = (double)c->N * c->N;
-  Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
-  launch_bj_apply(c->N, c->geo, c->bj, v, nullptr, 0, z, c->st);
+  const double bb = L.vt == VT_F64 ? 8.0 : 4.0;   // the preconditioner is FP32 in the mixed modes
+  Timed tm(c, LDG_K_BJ_APPLY, (bb * NN + 2.0 * L.vbytes * c->N) * c->K, 2.0 * NN * c->K);
+  launch_bj_apply(c->N, L.vt, L.vt == VT_F64 ? BT_F64 : BT_F32, c->geo, L.bj, r, z,
+                  dot ? &c->red : nullptr, c->st);
 }
 
-void kdots(ldg_ctx* c, int nv, const double* V, const double* w) {
-  Timed tm(c, LDG_K_KRYLOV, 8.0 * (nv + 1) * c->nvec, 2.0 * (nv + 1) * c->nvec);
-  launch_dots(c->red, c->nvec, nv, V, c->nvec, w, c->st);
+void kdots(ldg_ctx* c, const Level& L, int nv, const void* V, const void* w) {
+  Timed tm(c, LDG_K_KRYLOV, L.vbytes * (nv + 1) * c->nvec, 2.0 * (nv + 1) * c->nvec);
+  launch_dots(L.vt, c->red, c->nvec, nv, V, c->nvec, w, c->st);
 }
 
-void kupdate(ldg_ctx* c, int nv, const double* V, const double* h, double* w) {
-  Timed tm(c, LDG_K_KRYLOV, 8.0 * (nv + 2) * c->nvec, 2.0 * (nv + 1) * c->nvec);
-  launch_update(c->red2, c->nvec, nv, V, c->nvec, h, w, c->st);
+void kupdate(ldg_ctx* c, const Level& L, int nv, const void* V, const double* h, void* w) {
+  Timed tm(c, LDG_K_KRYLOV, L.vbytes * (nv + 2) * c->nvec, 2.0 * (nv + 1) * c->nvec);
+  launch_update(L.vt, c->red2, c->nvec, nv, V, c->nvec, h, w, c->st);
 }
 
-void kaxpby(ldg_ctx* c, double a, const double* x, double b, double* y) {
-  Timed tm(c, LDG_K_KRYLOV, 8.0 * (b == 0.0 ? 2.0 : 3.0) * c->nvec, 2.0 * c->nvec);
-  launch_axpby(c->nvec, a, x, b, y, c->st);
+void kaxpby(ldg_ctx* c, const Level& L, double a, const void* x, double b, void* y) {
+  Timed tm(c, LDG_K_KRYLOV, L.vbytes * (b == 0.0 ? 2.0 : 3.0) * c->nvec, 2.0 * c->nvec);
+  launch_axpby(L.vt, c->nvec, a, x, b, y, c->st);
 }
 
 // host copy of Reducer results
@@ -207,189 +225,244 @@ ldg_status fetch(ldg_ctx* c, const double* dev, int n, double* host) {
   return LDG_OK;
 }
 
-ldg_status dot_self(ldg_ctx* c, const double* x, double* out) {
-  kdots(c, 0, nullptr, x);
+ldg_status norm2(ldg_ctx* c, const Level& L, const void* x, double* out) {
+  kdots(c, L, 0, nullptr, x);
   TRY(check_launch(c));
   return fetch(c, c->red.result, 1, out);
 }
 
-// ---- restarted, right-preconditioned GMRES on the eliminated system ---------
-// Solves for C: b3 - [M C + tau(eta S' C + sum_m B^m Z^m(C))] = 0 with
-// Z^m(C) = -M^{-1}(A^m C + J^m_D); the residual is that of row block 3 of
-// the full system, rows 1 and 2 holding exactly by the recovery of Z.
-ldg_status gmres(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
-  const int64_t n = c->nvec;
-  const int m = c->opt.restart;
-  const double target = c->opt.rtol * bnorm;
-  std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
-  double* hb = c->host_buf;
-  int iters = 0, cycles = 0;
-  double beta = 0.0;
-  // true residual of the start value
-  apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
-  kaxpby(c, 1.0, c->b3, -1.0, c->w);   // w = b3 - F(X)
-  TRY(dot_self(c, c->w, hb));
-  beta = std::sqrt(hb[0]);
-  while (true) {
-    if (!std::isfinite(beta)) return fail(c, LDG_ENOCONV, "non-finite residual");
-    if (beta <= target) break;
-    if (iters >= c->opt.max_iters) break;
-    ++cycles;
-    // V0 = w / beta
-    kaxpby(c, 1.0 / beta, c->w, 0.0, c->V);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
-      double* vj = c->V + (int64_t)j * n;
-      double* vn = c->V + (int64_t)(j + 1) * n;
-      bj_apply(c, vj, c->z);
-      apply_op(c, tau, c->z, false, c->tZ1, c->tZ2, vn);
-      // classical Gram-Schmidt with one conditional re-orthogonalisation
-      kdots(c, j + 1, c->V, vn);
-      kupdate(c, j + 1, c->V, c->red.result, vn);
-      TRY(check_launch(c));
-      HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
-      TRY(sync(c));
-      double wn0 = std::sqrt(hb[j + 1]);
-      double wn = std::sqrt(hb[m + 2]);
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i];
-      if (wn < 0.7 * wn0) {
-        kdots(c, j + 1, c->V, vn);
-        kupdate(c, j + 1, c->V, c->red.result, vn);
-        HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
-        TRY(sync(c));
-        for (int i = 0; i <= j; ++i) H[i * m + j] += hb[i];
-        wn = std::sqrt(hb[m + 2]);
-      }
-      H[(j + 1) * m + j] = wn;
-      if (wn > 0.0) kaxpby(c, 1.0 / wn, vn, 0.0, vn);
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * b;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      const double a = H[j * m + j], b = H[(j + 1) * m + j];
-      const double rr = std::hypot(a, b);
-      cs[j] = rr > 0.0 ? a / rr : 1.0;
-      sn[j] = rr > 0.0 ? b / rr : 0.0;
-      H[j * m + j] = rr;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++iters;
-      jend = j + 1;
-      if (!std::isfinite(g[j + 1])) return fail(c, LDG_ENOCONV, "non-finite Krylov residual");
-      if (std::fabs(g[j + 1]) <= target || iters >= c->opt.max_iters || wn == 0.0) break;
-    }
-    // y = H^{-1} g, X += P^{-1} V y
-    for (int i = jend - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
-      y[i] = s / H[i * m + i];
-    }
-    HIPCHK(c, hipMemcpyAsync(c->ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, c->st));
-    {
-      Timed tm(c, LDG_K_KRYLOV, 8.0 * (jend + 1) * n, 2.0 * jend * n);
-      launch_lincomb(n, jend, c->V, n, c->ydev, c->u, c->st);
-    }
-    bj_apply(c, c->u, c->z);
-    kaxpby(c, 1.0, c->z, 1.0, c->X);
-    // true residual
-    apply_op(c, tau, c->X, true, c->tZ1, c->tZ2, c->w);
-    kaxpby(c, 1.0, c->b3, -1.0, c->w);
-    TRY(dot_self(c, c->w, hb));
-    beta = std::sqrt(hb[0]);
-  }
-  info->iters = iters;
-  info->restarts = cycles;
-  info->rel_residual = beta / bnorm;
-  if (!(beta <= target))
-    return fail(c, LDG_ENOCONV, "GMRES reached " + std::to_string(iters) +
-                                    " iterations at relative residual " +
-                                    std::to_string(beta / bnorm));
-  return LDG_OK;
+Level level64(ldg_ctx* c) {
+  Level L;
+  L.vt = VT_F64;
+  L.bt = BT_F64;
+  L.blocks = c->blocks;
+  L.bj = c->bj;
+  L.r = c->r; L.z = c->z; L.p = c->u; L.q = c->w; L.d = c->d64; L.u = c->u2;
+  L.tz1 = c->iz1; L.tz2 = c->iz2; L.V = c->V;
+  L.vbytes = 8.0;
+  L.bbytes = 8.0;
+  return L;
 }
 
-// ---- preconditioned conjugate gradients (symmetric positive definite case) --
-// Same system and residual as gmres(); returns LDG_EUNSUPPORTED when a
-// curvature p^T A p <= 0 shows the operator is not positive definite.
-ldg_status cg(ldg_ctx* c, double tau, double bnorm, ldg_step_info* info) {
-  const int64_t n = c->nvec;
-  const double target = c->opt.rtol * bnorm;
+Level level_lo(ldg_ctx* c, int bt) {
+  Level L;
+  L.vt = VT_F32;
+  L.bt = bt;
+  L.blocks = bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32;
+  L.bj = c->bj_f32;
+  L.r = c->r32; L.z = c->z32; L.p = c->p32; L.q = c->q32; L.d = c->d32; L.u = c->u32;
+  L.tz1 = c->tz1_32; L.tz2 = c->tz2_32; L.V = c->V32;
+  L.vbytes = 4.0;
+  L.bbytes = bt == BT_BF16 ? 2.0 : 4.0;
+  return L;
+}
+
+// ---- inner solvers: A d = r at level L, d from zero --------------------------
+// Preconditioned CG.  *not_spd is set when a curvature p^T A p <= 0 appears.
+ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
+                    bool* not_spd) {
   double* hb = c->host_buf;
-  double* x = c->X;
-  double* r = c->r;
-  double* z = c->z;
-  double* p = c->u;
-  double* q = c->w;
-  int iters = 0, restarts = 0;
-  double rnorm = 0.0;
-  bool fresh = true;   // recompute the true residual and restart the recurrence
-  double rz = 0.0;
-  while (true) {
-    if (fresh) {
-      ++restarts;
-      apply_op(c, tau, x, true, c->tZ1, c->tZ2, q);
-      {
-        Timed tm(c, LDG_K_KRYLOV, 24.0 * n, 2.0 * n);
-        launch_axpby(n, 1.0, c->b3, 0.0, r, c->st);
-        launch_axpby(n, -1.0, q, 1.0, r, c->st);
-      }
-      TRY(dot_self(c, r, hb));
-      rnorm = std::sqrt(hb[0]);
-      if (!std::isfinite(rnorm)) return fail(c, LDG_ENOCONV, "non-finite residual");
-      if (rnorm <= target || iters >= c->opt.max_iters) break;
-      {
-        const double NN = (double)c->N * c->N;
-        Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
-        launch_bj_apply_dot(c->N, c->geo, c->bj, r, z, c->red, c->st);
-      }
-      TRY(fetch(c, c->red.result, 1, hb));
-      rz = hb[0];
-      HIPCHK(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-      fresh = false;
-    }
-    apply_op(c, tau, p, false, c->tZ1, c->tZ2, q);
-    kdots(c, 1, p, q);
+  *not_spd = false;
+  kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
+  bj_apply(c, L, L.r, L.z, true);
+  TRY(fetch(c, c->red.result, 1, hb));
+  double rz = hb[0];
+  kaxpby(c, L, 1.0, L.z, 0.0, L.p);
+  int it = 0;
+  while (it < maxit) {
+    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q);
+    kdots(c, L, 1, L.p, L.q);
     TRY(fetch(c, c->red.result, 1, hb));
     const double pq = hb[0];
-    if (!(pq > 0.0) || !(rz > 0.0))
-      return fail(c, LDG_EUNSUPPORTED, "operator is not positive definite for CG");
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      *not_spd = true;
+      break;
+    }
     const double alpha = rz / pq;
     {
-      Timed tm(c, LDG_K_KRYLOV, 48.0 * n, 6.0 * n);
-      launch_cg_update(c->red2, n, alpha, p, q, x, r, c->st);
+      Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
+      launch_cg_update(L.vt, c->red2, c->nvec, alpha, L.p, L.q, L.d, L.r, c->st);
     }
     TRY(fetch(c, c->red2.result, 1, hb));
-    rnorm = std::sqrt(hb[0]);
-    ++iters;
-    if (!std::isfinite(rnorm)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
-    if (rnorm <= target || iters >= c->opt.max_iters) {
-      fresh = true;   // confirm with the true residual
-      continue;
-    }
-    {
-      const double NN = (double)c->N * c->N;
-      Timed tm(c, LDG_K_BJ_APPLY, 8.0 * (NN + 2.0 * c->N) * c->K, 2.0 * NN * c->K);
-      launch_bj_apply_dot(c->N, c->geo, c->bj, r, z, c->red, c->st);
-    }
+    ++it;
+    const double rn = std::sqrt(hb[0]);
+    if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
+    if (rn <= tol_abs) break;
+    bj_apply(c, L, L.r, L.z, true);
     TRY(fetch(c, c->red.result, 1, hb));
     const double rz_new = hb[0];
     const double beta = rz_new / rz;
     rz = rz_new;
-    kaxpby(c, 1.0, z, beta, p);
+    kaxpby(c, L, 1.0, L.z, beta, L.p);
+  }
+  *iters = it;
+  return LDG_OK;
+}
+
+// One cycle of right-preconditioned GMRES(m) with classical Gram-Schmidt and
+// one conditional re-orthogonalisation; rnorm = ||r||.
+ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, double tol_abs,
+                       int maxit, int* iters) {
+  const int64_t n = c->nvec;
+  const int m = std::min(c->opt.restart, maxit);
+  const size_t es = L.vt == VT_F64 ? 8 : 4;
+  std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), y(m);
+  double* hb = c->host_buf;
+  char* V = static_cast<char*>(L.V);
+  kaxpby(c, L, 1.0 / rnorm, L.r, 0.0, V);
+  g[0] = rnorm;
+  int jend = 0;
+  for (int j = 0; j < m; ++j) {
+    void* vj = V + (size_t)j * n * es;
+    void* vn = V + (size_t)(j + 1) * n * es;
+    bj_apply(c, L, vj, L.z, false);
+    apply_op(c, L, tau, L.z, false, L.tz1, L.tz2, vn);
+    kdots(c, L, j + 1, V, vn);
+    kupdate(c, L, j + 1, V, c->red.result, vn);
+    TRY(check_launch(c));
+    HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    TRY(sync(c));
+    const double wn0 = std::sqrt(hb[j + 1]);
+    double wn = std::sqrt(hb[m + 2]);
+    for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i];
+    if (wn < 0.7 * wn0) {
+      kdots(c, L, j + 1, V, vn);
+      kupdate(c, L, j + 1, V, c->red.result, vn);
+      HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      TRY(sync(c));
+      for (int i = 0; i <= j; ++i) H[i * m + j] += hb[i];
+      wn = std::sqrt(hb[m + 2]);
+    }
+    H[(j + 1) * m + j] = wn;
+    if (wn > 0.0) kaxpby(c, L, 1.0 / wn, vn, 0.0, vn);
+    for (int i = 0; i < j; ++i) {
+      const double a = H[i * m + j], b = H[(i + 1) * m + j];
+      H[i * m + j] = cs[i] * a + sn[i] * b;
+      H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double rr = std::hypot(a, b);
+    cs[j] = rr > 0.0 ? a / rr : 1.0;
+    sn[j] = rr > 0.0 ? b / rr : 0.0;
+    H[j * m + j] = rr;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    jend = j + 1;
+    if (!std::isfinite(g[j + 1])) return fail(c, LDG_ENOCONV, "non-finite Krylov residual");
+    if (std::fabs(g[j + 1]) <= tol_abs || wn == 0.0) break;
+  }
+  for (int i = jend - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
+    y[i] = s / H[i * m + i];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, c->st));
+  {
+    Timed tm(c, LDG_K_KRYLOV, L.vbytes * (jend + 1) * n, 2.0 * jend * n);
+    launch_lincomb(L.vt, n, jend, V, n, c->ydev, L.u, c->st);
+  }
+  bj_apply(c, L, L.u, L.d, false);
+  *iters = jend;
+  return LDG_OK;
+}
+
+// ---- the step's solve: FP64 refinement around the inner solver ---------------
+// Unknown C of the eliminated system, residual r = b3 - F(C) with
+// F(C) = M C + tau(eta S' C + sum_m B^m Z^m(C)), Z^m(C) = -M^{-1}(A^m C + J^m_D):
+// the row-3 residual of the full 3KN system, rows 1 and 2 holding exactly by
+// the recovery of Z.  Each sweep: FP64 residual, inner solve A d = r at the
+// working precision, C += d in FP64.  In FP64 the inner solve targets the
+// final tolerance (one sweep per GMRES cycle, or a CG run confirmed by the
+// true residual); in the mixed modes it targets inner_rtol relative.
+ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_step_info* info) {
+  const int64_t n = c->nvec;
+  const double target = c->opt.rtol * bnorm;
+  const Level L64 = level64(c);
+  Level L = c->opt.precision == LDG_FP64
+                ? L64
+                : level_lo(c, c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32);
+  double* hb = c->host_buf;
+  int iters = 0, sweeps = 0;
+  double beta = 0.0, beta_prev = 0.0;
+  bool cg_mode = use_cg;
+  info->krylov = cg_mode ? LDG_KRYLOV_CG : LDG_KRYLOV_GMRES;
+  while (true) {
+    apply_op(c, L64, tau, c->X, true, c->tZ1, c->tZ2, c->w);
+    {
+      Timed tm(c, LDG_K_KRYLOV, 24.0 * n, 2.0 * n);
+      launch_axpby(VT_F64, n, 1.0, c->b3, -1.0, c->w, c->st);   // w = b3 - F(X)
+    }
+    TRY(norm2(c, L64, c->w, hb));
+    beta = std::sqrt(hb[0]);
+    if (!std::isfinite(beta)) return fail(c, LDG_ENOCONV, "non-finite residual");
+    if (beta <= target || iters >= c->opt.max_iters) break;
+    if (L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev) {
+      // refinement stagnates at this precision: BF16 -> FP32 -> FP64
+      info->fallbacks += 1;
+      if (L.bt == BT_BF16) {
+        if (!c->blocks_f32_ready) {
+          launch_convert_blocks(BT_F32, c->Kpad, c->N, NSLOT, c->blocks, c->blocks_f32, c->st);
+          c->blocks_f32_ready = true;
+        }
+        L = level_lo(c, BT_F32);
+      } else {
+        L = L64;
+      }
+    }
+    beta_prev = beta;
+    ++sweeps;
+    int it = 0;
+    double scale;
+    if (L.vt == VT_F64) {
+      HIPCHK(c, hipMemcpyAsync(L.r, c->w, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+      scale = 1.0;
+      const int left = c->opt.max_iters - iters;
+      if (cg_mode) {
+        bool not_spd = false;
+        TRY(inner_cg(c, L, tau, 0.9 * target, left, &it, &not_spd));
+        if (not_spd) {
+          info->fallbacks += 1;
+          cg_mode = false;
+          info->krylov = LDG_KRYLOV_GMRES;
+        }
+      }
+      if (!cg_mode && it == 0) TRY(inner_gmres(c, L, tau, beta, 0.9 * target, left, &it));
+    } else {
+      {
+        Timed tm(c, LDG_K_KRYLOV, 12.0 * n, (double)n);
+        launch_cast(VT_F64, VT_F32, n, 1.0 / beta, c->w, L.r, c->st);
+      }
+      scale = beta;
+      const double tol = std::max(c->opt.inner_rtol, 0.5 * target / beta);
+      const int left = c->opt.max_iters - iters;
+      if (cg_mode) {
+        bool not_spd = false;
+        TRY(inner_cg(c, L, tau, tol, left, &it, &not_spd));
+        if (not_spd) {
+          info->fallbacks += 1;
+          cg_mode = false;
+          info->krylov = LDG_KRYLOV_GMRES;
+        }
+      }
+      if (!cg_mode && it == 0) TRY(inner_gmres(c, L, tau, 1.0, tol, left, &it));
+    }
+    iters += it;
+    {
+      Timed tm(c, LDG_K_KRYLOV, (L.vbytes + 16.0) * n, 2.0 * n);
+      launch_axpy_into64(L.vt, n, scale, L.d, c->X, c->st);
+    }
   }
   info->iters = iters;
-  info->restarts = restarts;
-  info->rel_residual = rnorm / bnorm;
-  if (!(rnorm <= target))
-    return fail(c, LDG_ENOCONV, "CG reached " + std::to_string(iters) +
+  info->restarts = sweeps;
+  info->ir_steps = c->opt.precision == LDG_FP64 ? 0 : sweeps;
+  info->rel_residual = beta / bnorm;
+  if (!(beta <= target))
+    return fail(c, LDG_ENOCONV, "solver reached " + std::to_string(iters) +
                                     " iterations at relative residual " +
-                                    std::to_string(rnorm / bnorm));
+                                    std::to_string(beta / bnorm));
   return LDG_OK;
 }
 
@@ -418,6 +491,7 @@ ldg_status ldg_options_default(ldg_options* o) {
   o->max_iters = 5000;
   o->stream = nullptr;
   o->krylov = LDG_KRYLOV_AUTO;
+  o->inner_rtol = 1e-3;
   return LDG_OK;
 }
 
@@ -442,7 +516,10 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       opt->restart > 200 || opt->max_iters < 1 || opt->krylov < LDG_KRYLOV_AUTO ||
       opt->krylov > LDG_KRYLOV_CG)
     return LDG_EINVAL;
-  if (opt->precision != LDG_FP64 || opt->precond != LDG_PC_BLOCK_JACOBI) return LDG_EUNSUPPORTED;
+  if (opt->precision < LDG_FP64 || opt->precision > LDG_MIXED_BF16) return LDG_EINVAL;
+  if (opt->precision != LDG_FP64 && !(opt->inner_rtol > 0.0 && opt->inner_rtol < 1.0))
+    return LDG_EINVAL;
+  if (opt->precond != LDG_PC_BLOCK_JACOBI) return LDG_EUNSUPPORTED;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
   c->opt = *opt;
@@ -550,8 +627,9 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(upload(c, c->sb, rf.s));
   // state and work vectors
   const int64_t nv = c->nvec;
-  double** vecs[] = {&c->C, &c->Z1, &c->Z2, &c->D, &c->F, &c->J1, &c->J2, &c->KDN, &c->b3,
-                     &c->r, &c->w, &c->z, &c->u, &c->X, &c->tZ1, &c->tZ2, &c->tmp};
+  double** vecs[] = {&c->C,  &c->Z1, &c->Z2, &c->D,   &c->F,   &c->J1,  &c->J2,  &c->KDN,
+                     &c->b3, &c->r,  &c->w,  &c->z,   &c->u,   &c->X,   &c->tZ1, &c->tZ2,
+                     &c->tmp, &c->d64, &c->u2, &c->iz1, &c->iz2};
   for (double** v : vecs) {
     TRY(dalloc(c, v, nv));
     HIPCHK(c, hipMemsetAsync(*v, 0, nv * sizeof(double), c->st));
@@ -559,6 +637,23 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(dalloc(c, &c->blocks, (size_t)Kp * NSLOT * c->NP * 2));
   TRY(dalloc(c, &c->bj, (size_t)Kp * c->NP * 2));
   TRY(dalloc(c, &c->V, (size_t)(c->mmax + 1) * nv));
+  if (opt->precision != LDG_FP64) {
+    float** v32[] = {&c->r32, &c->z32, &c->p32, &c->q32, &c->d32, &c->u32, &c->tz1_32, &c->tz2_32};
+    for (float** v : v32) {
+      TRY(dalloc(c, v, nv));
+      HIPCHK(c, hipMemsetAsync(*v, 0, nv * sizeof(float), c->st));
+    }
+    TRY(dalloc(c, &c->V32, (size_t)(c->mmax + 1) * nv));
+    char* p8 = nullptr;
+    TRY(dalloc(c, &p8, block_bytes(BT_F32, Kp, N, NSLOT)));
+    c->blocks_f32 = p8;
+    TRY(dalloc(c, &p8, block_bytes(BT_F32, Kp, N, 1)));
+    c->bj_f32 = p8;
+    if (opt->precision == LDG_MIXED_BF16) {
+      TRY(dalloc(c, &p8, block_bytes(BT_BF16, Kp, N, NSLOT)));
+      c->blocks_bf16 = p8;
+    }
+  }
   TRY(dalloc(c, &c->hdev, c->mmax + 2));
   TRY(dalloc(c, &c->ydev, c->mmax + 2));
   TRY(dalloc(c, &c->status, 1));
@@ -666,7 +761,7 @@ ldg_status ldg_apply_schur(ldg_ctx* c, double dt, const double* Cem, double* y) 
   if (!c || !Cem || !y || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
   if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
   launch_to_tiled(c->K, c->Kpad, c->N, Cem, c->u, c->st);
-  apply_op(c, dt, c->u, false, c->tZ1, c->tZ2, c->w);
+  apply_op(c, level64(c), dt, c->u, false, c->tZ1, c->tZ2, c->w);
   launch_from_tiled(c->K, c->N, c->w, y, c->st);
   return check_launch(c);
 }
@@ -678,12 +773,13 @@ ldg_status ldg_apply_full(ldg_ctx* c, double dt, const double* Y, double* out) {
   launch_to_tiled(c->K, c->Kpad, c->N, Y, c->z, c->st);            // Z1
   launch_to_tiled(c->K, c->Kpad, c->N, Y + KN, c->r, c->st);       // Z2
   launch_to_tiled(c->K, c->Kpad, c->N, Y + 2 * KN, c->u, c->st);   // C
-  launch_grad(c->N, c->geo, c->refs, c->u, nullptr, nullptr, c->tZ1, c->tZ2, c->st);
+  launch_grad(c->N, VT_F64, c->geo, c->refs, c->u, nullptr, nullptr, c->tZ1, c->tZ2, c->st);
   launch_zrows(c->geo, c->N, c->z, c->tZ1, dt, c->w, c->st);
   launch_from_tiled(c->K, c->N, c->w, out, c->st);
   launch_zrows(c->geo, c->N, c->r, c->tZ2, dt, c->w, c->st);
   launch_from_tiled(c->K, c->N, c->w, out + KN, c->st);
-  launch_div(c->N, c->geo, c->refs, c->blocks, c->u, c->z, c->r, 1.0, dt, c->opt.eta, c->w, c->st);
+  launch_div(c->N, VT_F64, BT_F64, c->geo, c->refs, c->blocks, c->u, c->z, c->r, 1.0, dt,
+             c->opt.eta, c->w, c->st);
   launch_from_tiled(c->K, c->N, c->w, out + 2 * KN, c->st);
   return check_launch(c);
 }
@@ -742,29 +838,24 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   // right-hand side and its full-system norm
   launch_rhs(c->geo, c->N, c->C, c->KDN, c->F, tau, c->b3, c->st);
   double nb3 = 0.0, nj1 = 0.0, nj2 = 0.0;
-  TRY(dot_self(c, c->b3, &nb3));
-  TRY(dot_self(c, c->J1, &nj1));
-  TRY(dot_self(c, c->J2, &nj2));
+  TRY(norm2(c, level64(c), c->b3, &nb3));
+  TRY(norm2(c, level64(c), c->J1, &nj1));
+  TRY(norm2(c, level64(c), c->J2, &nj2));
   const double bnorm = std::sqrt(nb3 + tau * tau * (nj1 + nj2));
-  // a6: Krylov solve starting from C^n
+  // low-precision copies for the inner solves of the mixed modes
+  if (c->opt.precision != LDG_FP64) {
+    Timed tm(c, LDG_K_ASSEMBLE, 8.0 * c->NN * (3.0 * c->K + 2.0 * c->Eint), 0.0);
+    const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
+    launch_convert_blocks(bt, c->Kpad, c->N, NSLOT, c->blocks,
+                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
+    launch_convert_blocks(BT_F32, c->Kpad, c->N, 1, c->bj, c->bj_f32, c->st);
+    c->blocks_f32_ready = bt == BT_F32;
+  }
+  // a6, a7: Krylov solve (with FP64 refinement) starting from C^n
   bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
   HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  ldg_status s = LDG_EUNSUPPORTED;
-  if (use_cg) {
-    info->krylov = LDG_KRYLOV_CG;
-    s = cg(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
-    if (s == LDG_EUNSUPPORTED) {   // not SPD after all: fall back to GMRES from C^n
-      info->fallbacks += 1;
-      HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    }
-  }
-  if (s == LDG_EUNSUPPORTED) {
-    info->krylov = LDG_KRYLOV_GMRES;
-    const int fb = info->fallbacks;
-    s = gmres(c, tau, bnorm > 0.0 ? bnorm : 1.0, info);
-    info->fallbacks = fb;
-  }
+  ldg_status s = solve_step(c, tau, bnorm > 0.0 ? bnorm : 1.0, use_cg, info);
   info->t = c->t;
   if (s != LDG_OK) return s;
   // a10: accept; Z from the last residual evaluation of X

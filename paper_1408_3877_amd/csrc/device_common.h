@@ -1,0 +1,102 @@
+// Device helpers shared by the kernels: tiled layouts, block storage types,
+// BF16 rounding.  Included by .hip sources only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ldg_internal.h"
+
+namespace ldg {
+
+// ---- stored N x N blocks: 16 bytes per lane and load ----------------------
+// Block entry f = i*N + j of (triangle k, slot s) lives in group g = f / W at
+//   [k/64][s][g][k%64][f%W],  W = 16 bytes / sizeof(storage type).
+using bf16 = uint16_t;
+
+template <class BT> struct Blk;
+template <> struct Blk<double> {
+  static constexpr int W = 2;
+  template <class T>
+  __device__ static inline void load(const double* p, T* v) {
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    v[0] = (T)x.x;
+    v[1] = (T)x.y;
+  }
+};
+template <> struct Blk<float> {
+  static constexpr int W = 4;
+  template <class T>
+  __device__ static inline void load(const float* p, T* v) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = (T)x.x;
+    v[1] = (T)x.y;
+    v[2] = (T)x.z;
+    v[3] = (T)x.w;
+  }
+};
+template <> struct Blk<bf16> {
+  static constexpr int W = 8;
+  template <class T>
+  __device__ static inline void load(const bf16* p, T* v) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = (T)__uint_as_float(w[q] << 16);
+      v[2 * q + 1] = (T)__uint_as_float(w[q] & 0xffff0000u);
+    }
+  }
+};
+
+__host__ __device__ constexpr int ngroups(int N, int W) { return (N * N + W - 1) / W; }
+
+__host__ __device__ inline int64_t bgidx(int64_t k, int s, int g, int ns, int ng, int W) {
+  return ((((k >> 6) * ns + s) * (int64_t)ng + g) * TILE + (k & 63)) * W;
+}
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs; NaN kept quiet)
+__device__ inline bf16 to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (bf16)0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+
+template <class BT> __device__ inline BT from_double(double x);
+template <> __device__ inline double from_double<double>(double x) { return x; }
+template <> __device__ inline float from_double<float>(double x) { return (float)x; }
+template <> __device__ inline bf16 from_double<bf16>(double x) { return to_bf16((float)x); }
+
+// acc += Blk(k, s) z, one lane per triangle, fully unrolled over the block
+template <int N, class BT, class T>
+__device__ inline void block_mv(const BT* __restrict__ blocks, int64_t k, int s, int ns,
+                                const T* z, T* acc) {
+  constexpr int W = Blk<BT>::W;
+  constexpr int NN = N * N;
+  constexpr int NG = ngroups(N, W);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    T v[W];
+    Blk<BT>::load(blocks + bgidx(k, s, g, ns, NG, W), v);
+#pragma unroll
+    for (int h = 0; h < W; ++h) {
+      const int f = g * W + h;
+      if (f < NN) acc[f / N] += v[h] * z[f % N];
+    }
+  }
+}
+
+template <int N, class T>
+__device__ inline void load_vec(const T* __restrict__ v, int64_t k, T* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = v[vidx(k, i, N)];
+}
+
+template <int N, class T>
+__device__ inline void store_vec(T* __restrict__ v, int64_t k, const T* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[vidx(k, i, N)] = x[i];
+}
+
+}  // namespace ldg

@@ -12,15 +12,25 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
                      double* KDN, hipStream_t st);
 void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, const double* Trd,
                      const double* Tro, double* blocks, hipStream_t st);
-void launch_grad(int N, const Geo& g, const double* refs, const double* C, const double* J1,
-                 const double* J2, double* Z1, double* Z2, hipStream_t st);
-void launch_div(int N, const Geo& g, const double* refs, const double* blocks, const double* C,
-                const double* Z1, const double* Z2, double alpha, double tau, double eta,
-                double* y, hipStream_t st);
+// vector storage (VT_*) and block storage (BT_*) precisions
+enum { VT_F64 = 0, VT_F32 = 1 };
+enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2 };
+
+// kernels_apply.hip
+void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
+                 const void* J2, void* Z1, void* Z2, hipStream_t st);
+void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
+                const void* C, const void* Z1, const void* Z2, double alpha, double tau,
+                double eta, void* y, hipStream_t st);
+struct Reducer;
+// z = P^{-1} r; with red != NULL also red->result[0] = <r, z>
+void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
+                     const Reducer* red, hipStream_t st);
+void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* src, void* dst,
+                           hipStream_t st);
+size_t block_bytes(int bt, int64_t Kpad, int N, int ns);
 void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
                      double eta, double* bj, int* status, hipStream_t st);
-void launch_bj_apply(int N, const Geo& g, const double* bj, double* v, const double* scale_inv,
-                     int write_back, double* z, hipStream_t st);
 void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
                      hipStream_t st);
 void launch_from_tiled(int64_t K, int N, const double* src, double* dst, hipStream_t st);
@@ -33,36 +43,40 @@ void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, cons
                        double* yo, hipStream_t st);
 
 // Krylov vector kernels (kernels_krylov.hip); n = vector length, V = basis
-// with vectors at V + j*ldv.  Reductions are two-stage and fixed-order.
+// with vectors at V + j*ldv; vt selects the vector storage type.  Inner
+// products accumulate in FP64; reductions are two-stage and fixed-order.
 struct Reducer {
-  double* partials = nullptr;   // [(maxv+1) * nblk]
-  double* result = nullptr;     // [maxv+1] device
+  double* partials = nullptr;
+  double* result = nullptr;     // device
   int nblk = 0;
   int maxv = 0;
 };
 int krylov_nblk(int64_t n);
+void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st);
 // result[j] = <V_j, w> for j < nv, result[nv] = <w, w>
-void launch_dots(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
-                 const double* w, hipStream_t st);
+void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
+                 const void* w, hipStream_t st);
 // w -= sum_j h[j] V_j (h device); result[0] = <w, w> afterwards
-void launch_update(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
-                   const double* h, double* w, hipStream_t st);
+void launch_update(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
+                   const double* h, void* w, hipStream_t st);
 // u = sum_j y[j] V_j (y device)
-void launch_lincomb(int64_t n, int nv, const double* V, int64_t ldv, const double* y, double* u,
-                    hipStream_t st);
+void launch_lincomb(int vt, int64_t n, int nv, const void* V, int64_t ldv, const double* y,
+                    void* u, hipStream_t st);
 // y = a x + b y
-void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y, hipStream_t st);
+// CG: x += a p, r -= a q; result[0] = <r, r> afterwards
+void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
+                      void* x, void* rv, hipStream_t st);
+// out = a * in across precisions
+void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, void* out,
+                 hipStream_t st);
+// y += a x with y FP64
+void launch_axpy_into64(int vt, int64_t n, double a, const void* x, double* y, hipStream_t st);
+// result[0] = sum_k D_k0^2, result[1] = sum_k sum_{i>0} D_ki^2
+void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st);
 // b3 = 2|T| C + tau (KDN + 2|T| F) in the tiled layout
 void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,
                 double tau, double* b3, hipStream_t st);
-// CG: x += a p, r -= a q; result[0] = <r, r> afterwards
-void launch_cg_update(const Reducer& r, int64_t n, double a, const double* p, const double* q,
-                      double* x, double* rv, hipStream_t st);
-// z = P^{-1} r (block Jacobi); result[0] = <r, z>
-void launch_bj_apply_dot(int N, const Geo& g, const double* bj, const double* rv, double* z,
-                         const Reducer& red, hipStream_t st);
-// result[0] = sum_k D_k0^2, result[1] = sum_k sum_{i>0} D_ki^2
-void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st);
 // out = s * area2 * (Za - Zb) per element (full-operator rows 1, 2)
 void launch_zrows(const Geo& g, int N, const double* Za, const double* Zb, double s, double* out,
                   hipStream_t st);

@@ -1,0 +1,301 @@
+// Operator application and block-Jacobi application, templated on the
+// vector type T (double, or float for the inner solves of the mixed modes)
+// and the storage type BT of the stored blocks (double, float, bf16), with
+// arithmetic and accumulation in T.  One lane per triangle.
+//
+// Gradient half:   Z^m = -M^{-1} (A^m C + J^m),  A^m = -H^m + Q^m + Q^m_N
+// Divergence half: y = alpha M C + tau (eta (S + S_D) C + sum_m B^m Z^m),
+//                  B^m = -G^m + R^m + R^m_D   (eq:timeDepSystem)
+// H, Q, S enter through the reference matrices H_hat, S_hat_diag, S_hat_off
+// (Sec. 3.6.2, 3.6.4, 3.6.5) kept in LDS; G and R through the stored blocks.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace ldg {
+
+namespace {
+
+constexpr int NREF = 14;  // H1, H2, Sd[3], So[3][3]
+__device__ inline int ref_h(int m) { return m; }
+__device__ inline int ref_sd(int n) { return 2 + n; }
+__device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
+
+template <int N, class T>
+__device__ inline void load_refs(T* sm, const double* __restrict__ g) {
+  for (int t = threadIdx.x; t < NREF * N * N; t += blockDim.x) sm[t] = (T)g[t];
+  __syncthreads();
+}
+
+template <int N, class T>
+__device__ inline void mv_add(const T* __restrict__ A, const T* x, T* acc, T scale) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += A[i * N + j] * x[j];
+    acc[i] += scale * s;
+  }
+}
+
+}  // namespace
+
+template <int N, class T>
+__global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
+                                              const T* __restrict__ C, const T* __restrict__ J1,
+                                              const T* __restrict__ J2, T* __restrict__ Z1,
+                                              T* __restrict__ Z2) {
+  __shared__ T sm[NREF * N * N];
+  load_refs<N, T>(sm, refs);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  T a1[N], a2[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) a1[i] = a2[i] = 0;
+  if (k >= g.K) {
+    store_vec<N, T>(Z1, k, a1);
+    store_vec<N, T>(Z2, k, a2);
+    return;
+  }
+  const int64_t Kp = g.Kpad;
+  T c[N];
+  load_vec<N, T>(C, k, c);
+  const T B11 = (T)g.B[k], B12 = (T)g.B[Kp + k], B21 = (T)g.B[2 * Kp + k], B22 = (T)g.B[3 * Kp + k];
+  {
+    // -H^1 = -(B22 H1 - B21 H2), -H^2 = -(-B12 H1 + B11 H2)   (Sec. 3.6.2)
+    T u1[N], u2[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0;
+    mv_add<N, T>(sm + ref_h(0) * N * N, c, u1, (T)1);
+    mv_add<N, T>(sm + ref_h(1) * N * N, c, u2, (T)1);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] -= B22 * u1[i] - B21 * u2[i];
+      a2[i] -= -B12 * u1[i] + B11 * u2[i];
+    }
+  }
+  for (int n = 0; n < 3; ++n) {
+    const int kind = g.kind[n * Kp + k];
+    if (kind == LDG_EDGE_DIRICHLET) continue;
+    const T L = (T)g.elen[n * Kp + k];
+    const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+    const T cq = (kind == LDG_EDGE_INTERIOR ? (T)0.5 : (T)1) * L;
+    T s[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = 0;
+    mv_add<N, T>(sm + ref_sd(n) * N * N, c, s, cq);
+    if (kind == LDG_EDGE_INTERIOR) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      const int np = g.nbrn[n * Kp + k];
+      T cp[N];
+      load_vec<N, T>(C, kp, cp);
+      mv_add<N, T>(sm + ref_so(n, np) * N * N, cp, s, (T)0.5 * L);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] += nu1 * s[i];
+      a2[i] += nu2 * s[i];
+    }
+  }
+  if (J1 != nullptr) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a1[i] += J1[vidx(k, i, N)];
+      a2[i] += J2[vidx(k, i, N)];
+    }
+  }
+  const T inv = (T)(-1.0 / g.area2[k]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    a1[i] *= inv;
+    a2[i] *= inv;
+  }
+  store_vec<N, T>(Z1, k, a1);
+  store_vec<N, T>(Z2, k, a2);
+}
+
+template <int N, class T, class BT>
+__global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
+                                             const BT* __restrict__ blocks,
+                                             const T* __restrict__ C, const T* __restrict__ Z1,
+                                             const T* __restrict__ Z2, double alpha, double tau,
+                                             double eta, T* __restrict__ y) {
+  __shared__ T sm[NREF * N * N];
+  load_refs<N, T>(sm, refs);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  T t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = 0;
+  if (k >= g.K) {
+    store_vec<N, T>(y, k, t);
+    return;
+  }
+  const int64_t Kp = g.Kpad;
+  T c[N], z[N];
+  load_vec<N, T>(C, k, c);
+  for (int n = 0; n < 3; ++n) {
+    const int kind = g.kind[n * Kp + k];
+    if (kind == LDG_EDGE_NEUMANN) continue;
+    mv_add<N, T>(sm + ref_sd(n) * N * N, c, t, (T)eta);   // (1/|E|) |E| S_hat_diag
+    if (kind == LDG_EDGE_INTERIOR) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      const int np = g.nbrn[n * Kp + k];
+      T cp[N];
+      load_vec<N, T>(C, kp, cp);
+      mv_add<N, T>(sm + ref_so(n, np) * N * N, cp, t, (T)(-eta));
+    }
+  }
+  load_vec<N, T>(Z1, k, z);
+  block_mv<N, BT, T>(blocks, k, 0, NSLOT, z, t);
+  load_vec<N, T>(Z2, k, z);
+  block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
+  for (int n = 0; n < 3; ++n) {
+    const int64_t kp = g.nbr[n * Kp + k];
+    if (kp < 0) continue;
+    const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+#pragma unroll
+    for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
+    block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
+  }
+  const T a2 = (T)(alpha * g.area2[k]);
+  const T tt = (T)tau;
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = a2 * c[i] + tt * t[i];
+  store_vec<N, T>(y, k, t);
+}
+
+// z = P^{-1} r; with `partials`, also per-block sums of <r, z> in FP64
+template <int N, class T, class BT>
+__global__ void __launch_bounds__(256) k_bj_apply(Geo g, const BT* __restrict__ bj,
+                                                  const T* __restrict__ r, T* __restrict__ z,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (k < g.Kpad) {
+    T x[N], acc[N];
+    load_vec<N, T>(r, k, x);
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0;
+    block_mv<N, BT, T>(bj, k, 0, 1, x, acc);
+    store_vec<N, T>(z, k, acc);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += (double)x[i] * (double)acc[i];
+  }
+  if (partials == nullptr) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// low-precision copies of stored blocks: dst (BT layout) <- src (double layout)
+template <class BT>
+__global__ void k_convert_blocks(int64_t Kpad, int N, int ns, const double* __restrict__ src,
+                                 BT* __restrict__ dst) {
+  const int NN = N * N;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int W = Blk<BT>::W;
+  const int NG = ngroups(N, W);
+  const int NGd = ngroups(N, 2);
+  if (t >= Kpad * ns * NG * W) return;
+  // t enumerates the destination in storage order
+  const int h = (int)(t % W);
+  const int64_t e = (t / W) % TILE;
+  const int64_t rest = t / (W * TILE);
+  const int gg = (int)(rest % NG);
+  const int64_t rest2 = rest / NG;
+  const int s = (int)(rest2 % ns);
+  const int64_t tile = rest2 / ns;
+  const int64_t k = tile * TILE + e;
+  const int f = gg * W + h;
+  const double v = f < NN ? src[bgidx(k, s, f / 2, ns, NGd, 2) + (f & 1)] : 0.0;
+  dst[t] = from_double<BT>(v);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+}
+
+#define LDG_SWITCH_N(N, CALL)                                   \
+  switch (N) {                                                  \
+    case 1: { constexpr int NT = 1; CALL; } break;              \
+    case 3: { constexpr int NT = 3; CALL; } break;              \
+    case 6: { constexpr int NT = 6; CALL; } break;              \
+    case 10: { constexpr int NT = 10; CALL; } break;            \
+    case 15: { constexpr int NT = 15; CALL; } break;            \
+    default: break;                                             \
+  }
+
+void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
+                 const void* J2, void* Z1, void* Z2, hipStream_t st) {
+  const unsigned nb = nblk(g.Kpad, 256);
+  if (vt == VT_F64) {
+    LDG_SWITCH_N(N, (k_grad<NT, double><<<nb, 256, 0, st>>>(
+                        g, refs, (const double*)C, (const double*)J1, (const double*)J2,
+                        (double*)Z1, (double*)Z2)));
+  } else {
+    LDG_SWITCH_N(N, (k_grad<NT, float><<<nb, 256, 0, st>>>(
+                        g, refs, (const float*)C, (const float*)J1, (const float*)J2, (float*)Z1,
+                        (float*)Z2)));
+  }
+}
+
+void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
+                const void* C, const void* Z1, const void* Z2, double alpha, double tau,
+                double eta, void* y, hipStream_t st) {
+  const unsigned nb = nblk(g.Kpad, 256);
+  if (vt == VT_F64) {
+    LDG_SWITCH_N(N, (k_div<NT, double, double><<<nb, 256, 0, st>>>(
+                        g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
+                        (const double*)Z2, alpha, tau, eta, (double*)y)));
+  } else if (bt == BT_F32) {
+    LDG_SWITCH_N(N, (k_div<NT, float, float><<<nb, 256, 0, st>>>(
+                        g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
+                        (const float*)Z2, alpha, tau, eta, (float*)y)));
+  } else {
+    LDG_SWITCH_N(N, (k_div<NT, float, bf16><<<nb, 256, 0, st>>>(
+                        g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
+                        (const float*)Z2, alpha, tau, eta, (float*)y)));
+  }
+}
+
+void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
+                     const Reducer* red, hipStream_t st) {
+  const unsigned nb = nblk(g.Kpad, 256);
+  double* parts = red ? red->partials : nullptr;
+  if (vt == VT_F64) {
+    LDG_SWITCH_N(N, (k_bj_apply<NT, double, double><<<nb, 256, 0, st>>>(
+                        g, (const double*)bj, (const double*)r, (double*)z, parts)));
+  } else if (bt == BT_F32) {
+    LDG_SWITCH_N(N, (k_bj_apply<NT, float, float><<<nb, 256, 0, st>>>(
+                        g, (const float*)bj, (const float*)r, (float*)z, parts)));
+  } else {
+    LDG_SWITCH_N(N, (k_bj_apply<NT, float, bf16><<<nb, 256, 0, st>>>(
+                        g, (const bf16*)bj, (const float*)r, (float*)z, parts)));
+  }
+  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+}
+
+void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* src, void* dst,
+                           hipStream_t st) {
+  if (bt == BT_F32) {
+    const int64_t n = Kpad * ns * ngroups(N, 4) * 4;
+    k_convert_blocks<float><<<nblk(n, 256), 256, 0, st>>>(Kpad, N, ns, src, (float*)dst);
+  } else if (bt == BT_BF16) {
+    const int64_t n = Kpad * ns * ngroups(N, 8) * 8;
+    k_convert_blocks<bf16><<<nblk(n, 256), 256, 0, st>>>(Kpad, N, ns, src, (bf16*)dst);
+  }
+}
+
+size_t block_bytes(int bt, int64_t Kpad, int N, int ns) {
+  const int W = bt == BT_F64 ? 2 : (bt == BT_F32 ? 4 : 8);
+  const size_t es = bt == BT_F64 ? 8 : (bt == BT_F32 ? 4 : 2);
+  return (size_t)Kpad * ns * ngroups(N, W) * W * es;
+}
+
+}  // namespace ldg

@@ -5,6 +5,7 @@
 // consecutive triangles and every block or vector load of a wave is one
 // contiguous run (double2 per lane for the stored blocks).  The small
 // reference matrices (H_hat, S_hat_diag, S_hat_offdiag) live in LDS.
+#include "device_common.h"
 #include "kernels.h"
 
 namespace ldg {
@@ -35,33 +36,6 @@ __device__ inline void mv_add(const double* __restrict__ A, const double* x, dou
   }
 }
 
-template <int N>
-__device__ inline void load_vec(const double* __restrict__ v, int64_t k, double* x) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) x[i] = v[vidx(k, i, N)];
-}
-
-template <int N>
-__device__ inline void store_vec(double* __restrict__ v, int64_t k, const double* x) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[vidx(k, i, N)] = x[i];
-}
-
-// acc += Blk(k, s) z for a stored block in the pair layout
-template <int N>
-__device__ inline void block_mv(const double* __restrict__ blocks, int64_t k, int s, int ns,
-                                const double* z, double* acc) {
-  constexpr int NN = N * N;
-  constexpr int NP = npairs(N);
-#pragma unroll
-  for (int pr = 0; pr < NP; ++pr) {
-    const double2 b = *reinterpret_cast<const double2*>(blocks + pidx(k, s, pr, ns, NP));
-    const int f0 = 2 * pr, f1 = 2 * pr + 1;
-    acc[f0 / N] += b.x * z[f0 % N];
-    if (f1 < NN) acc[f1 / N] += b.y * z[f1 % N];
-  }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -87,7 +61,7 @@ __global__ void __launch_bounds__(256) k_project(int64_t K, int64_t Kpad, int R,
       for (int i = 0; i < N; ++i) acc[i] += sW[r * N + i] * s;
     }
   }
-  store_vec<N>(out, k, acc);
+  store_vec<N, double>(out, k, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -109,7 +83,7 @@ __global__ void __launch_bounds__(256) k_boundary(Geo g, int64_t nbe,
   const int64_t k = belem[idx];
   const int64_t Kp = g.Kpad;
   double j1[N], j2[N], kd[N], kn[N], Dk[N];
-  load_vec<N>(D, k, Dk);
+  load_vec<N, double>(D, k, Dk);
 #pragma unroll
   for (int i = 0; i < N; ++i) j1[i] = j2[i] = kd[i] = kn[i] = 0.0;
   for (int n = 0; n < 3; ++n) {
@@ -175,7 +149,7 @@ __global__ void __launch_bounds__(256) k_assemble_valu(Geo g, const double* __re
   }
   const int64_t Kp = g.Kpad;
   double Dk[N], Dn[3][N];
-  load_vec<N>(D, k, Dk);
+  load_vec<N, double>(D, k, Dk);
   int npl[3];
   double wr[2][3], uo[3];
   const double B11 = g.B[k], B12 = g.B[Kp + k], B21 = g.B[2 * Kp + k], B22 = g.B[3 * Kp + k];
@@ -192,7 +166,7 @@ __global__ void __launch_bounds__(256) k_assemble_valu(Geo g, const double* __re
     npl[n] = kp >= 0 ? g.nbrn[n * Kp + k] : 0;
     uo[n] = kp >= 0 ? 0.5 * L : 0.0;
     if (kp >= 0) {
-      load_vec<N>(D, kp, Dn[n]);
+      load_vec<N, double>(D, kp, Dn[n]);
     } else {
 #pragma unroll
       for (int l = 0; l < N; ++l) Dn[n][l] = 0.0;
@@ -231,140 +205,6 @@ __global__ void __launch_bounds__(256) k_assemble_valu(Geo g, const double* __re
       *reinterpret_cast<double2*>(blocks + pidx(k, s, pr, NSLOT, NP)) =
           make_double2(out[s][0], out[s][1]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Gradient half of the operator: Z^m = -M^{-1} (A^m C + J^m),
-//   A^m = -H^m + Q^m + Q^m_N (eq:timeDepSystem), M^{-1} = 1/(2|T_k|) on T_k.
-// ---------------------------------------------------------------------------
-template <int N>
-__global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
-                                              const double* __restrict__ C,
-                                              const double* __restrict__ J1,
-                                              const double* __restrict__ J2,
-                                              double* __restrict__ Z1, double* __restrict__ Z2) {
-  __shared__ double sm[NREF * N * N];
-  load_refs<N>(sm, refs);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.Kpad) return;
-  double a1[N], a2[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) a1[i] = a2[i] = 0.0;
-  if (k >= g.K) {
-    store_vec<N>(Z1, k, a1);
-    store_vec<N>(Z2, k, a2);
-    return;
-  }
-  const int64_t Kp = g.Kpad;
-  double c[N];
-  load_vec<N>(C, k, c);
-  const double B11 = g.B[k], B12 = g.B[Kp + k], B21 = g.B[2 * Kp + k], B22 = g.B[3 * Kp + k];
-  {
-    // -H^1 = -(B22 H1 - B21 H2), -H^2 = -(-B12 H1 + B11 H2)   (Sec. 3.6.2)
-    double u1[N], u2[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0.0;
-    mv_add<N>(sm + ref_h(0) * N * N, c, u1, 1.0);
-    mv_add<N>(sm + ref_h(1) * N * N, c, u2, 1.0);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      a1[i] -= B22 * u1[i] - B21 * u2[i];
-      a2[i] -= -B12 * u1[i] + B11 * u2[i];
-    }
-  }
-  for (int n = 0; n < 3; ++n) {
-    const int kind = g.kind[n * Kp + k];
-    if (kind == LDG_EDGE_DIRICHLET) continue;
-    const double L = g.elen[n * Kp + k];
-    const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
-    const double cq = (kind == LDG_EDGE_INTERIOR ? 0.5 : 1.0) * L;
-    double s[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = 0.0;
-    mv_add<N>(sm + ref_sd(n) * N * N, c, s, cq);
-    if (kind == LDG_EDGE_INTERIOR) {
-      const int64_t kp = g.nbr[n * Kp + k];
-      const int np = g.nbrn[n * Kp + k];
-      double cp[N];
-      load_vec<N>(C, kp, cp);
-      mv_add<N>(sm + ref_so(n, np) * N * N, cp, s, 0.5 * L);
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      a1[i] += nu1 * s[i];
-      a2[i] += nu2 * s[i];
-    }
-  }
-  if (J1 != nullptr) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      a1[i] += J1[vidx(k, i, N)];
-      a2[i] += J2[vidx(k, i, N)];
-    }
-  }
-  const double inv = -1.0 / g.area2[k];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    a1[i] *= inv;
-    a2[i] *= inv;
-  }
-  store_vec<N>(Z1, k, a1);
-  store_vec<N>(Z2, k, a2);
-}
-
-// ---------------------------------------------------------------------------
-// Divergence half: y = alpha M C + tau (eta (S + S_D) C + sum_m B^m Z^m),
-//   B^m = -G^m + R^m + R^m_D with the stored blocks, R^m_{k k+} = nu^m U_kn.
-// ---------------------------------------------------------------------------
-template <int N>
-__global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
-                                             const double* __restrict__ blocks,
-                                             const double* __restrict__ C,
-                                             const double* __restrict__ Z1,
-                                             const double* __restrict__ Z2, double alpha,
-                                             double tau, double eta, double* __restrict__ y) {
-  __shared__ double sm[NREF * N * N];
-  load_refs<N>(sm, refs);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.Kpad) return;
-  double t[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) t[i] = 0.0;
-  if (k >= g.K) {
-    store_vec<N>(y, k, t);
-    return;
-  }
-  const int64_t Kp = g.Kpad;
-  double c[N], z[N];
-  load_vec<N>(C, k, c);
-  for (int n = 0; n < 3; ++n) {
-    const int kind = g.kind[n * Kp + k];
-    if (kind == LDG_EDGE_NEUMANN) continue;
-    mv_add<N>(sm + ref_sd(n) * N * N, c, t, eta);       // (1/|E|) |E| S_hat_diag
-    if (kind == LDG_EDGE_INTERIOR) {
-      const int64_t kp = g.nbr[n * Kp + k];
-      const int np = g.nbrn[n * Kp + k];
-      double cp[N];
-      load_vec<N>(C, kp, cp);
-      mv_add<N>(sm + ref_so(n, np) * N * N, cp, t, -eta);
-    }
-  }
-  load_vec<N>(Z1, k, z);
-  block_mv<N>(blocks, k, 0, NSLOT, z, t);
-  load_vec<N>(Z2, k, z);
-  block_mv<N>(blocks, k, 1, NSLOT, z, t);
-  for (int n = 0; n < 3; ++n) {
-    const int64_t kp = g.nbr[n * Kp + k];
-    if (kp < 0) continue;
-    const double nu1 = g.nu[(2 * n) * Kp + k], nu2 = g.nu[(2 * n + 1) * Kp + k];
-#pragma unroll
-    for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
-    block_mv<N>(blocks, k, 2 + n, NSLOT, z, t);
-  }
-  const double a2 = alpha * g.area2[k];
-#pragma unroll
-  for (int i = 0; i < N; ++i) t[i] = a2 * c[i] + tau * t[i];
-  store_vec<N>(y, k, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -505,50 +345,6 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
     }
     if (i == N - 1 && (NN & 1)) bj[pidx(k, 0, NP - 1, 1, NP) + 1] = 0.0;
   }
-}
-
-// z = P^{-1} (scale * v); optionally v <- scale * v
-template <int N>
-__global__ void __launch_bounds__(256) k_bj_apply(Geo g, const double* __restrict__ bj,
-                                                  double* __restrict__ v,
-                                                  const double* __restrict__ scale_inv,
-                                                  int write_back, double* __restrict__ z) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.Kpad) return;
-  const double sc = scale_inv ? 1.0 / scale_inv[0] : 1.0;
-  double x[N], acc[N];
-  load_vec<N>(v, k, x);
-#pragma unroll
-  for (int i = 0; i < N; ++i) { x[i] *= sc; acc[i] = 0.0; }
-  if (write_back) store_vec<N>(v, k, x);
-  block_mv<N>(bj, k, 0, 1, x, acc);
-  store_vec<N>(z, k, acc);
-}
-
-// z = P^{-1} r and per-block partial sums of <r, z> (reduced by k_reduce_partials)
-template <int N>
-__global__ void __launch_bounds__(256) k_bj_apply_dot(Geo g, const double* __restrict__ bj,
-                                                      const double* __restrict__ r,
-                                                      double* __restrict__ z,
-                                                      double* __restrict__ partials) {
-  __shared__ double red[4];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double s = 0.0;
-  if (k < g.Kpad) {
-    double x[N], acc[N];
-    load_vec<N>(r, k, x);
-#pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = 0.0;
-    block_mv<N>(bj, k, 0, 1, x, acc);
-    store_vec<N>(z, k, acc);
-#pragma unroll
-    for (int i = 0; i < N; ++i) s += x[i] * acc[i];
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -710,17 +506,7 @@ void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, con
                                                                             blocks)));
 }
 
-void launch_grad(int N, const Geo& g, const double* refs, const double* C, const double* J1,
-                 const double* J2, double* Z1, double* Z2, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_grad<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, refs, C, J1, J2, Z1, Z2)));
-}
 
-void launch_div(int N, const Geo& g, const double* refs, const double* blocks, const double* C,
-                const double* Z1, const double* Z2, double alpha, double tau, double eta,
-                double* y, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_div<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, refs, blocks, C, Z1, Z2,
-                                                                 alpha, tau, eta, y)));
-}
 
 void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
                      double eta, double* bj, int* status, hipStream_t st) {
@@ -728,20 +514,6 @@ void launch_bj_setup(int N, const Geo& g, const double* refs, const double* bloc
                                                                           eta, bj, status)));
 }
 
-void launch_bj_apply(int N, const Geo& g, const double* bj, double* v, const double* scale_inv,
-                     int write_back, double* z, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_bj_apply<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, bj, v, scale_inv,
-                                                                      write_back, z)));
-}
-
-void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st);
-
-void launch_bj_apply_dot(int N, const Geo& g, const double* bj, const double* rv, double* z,
-                         const Reducer& red, hipStream_t st) {
-  const unsigned nb = nblk(g.Kpad, 256);
-  LDG_SWITCH_N(N, (k_bj_apply_dot<NT><<<nb, 256, 0, st>>>(g, bj, rv, z, red.partials)));
-  reduce_partials((int)nb, red.partials, red.result, st);
-}
 
 void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
                      hipStream_t st) {

@@ -1,7 +1,9 @@
-// Vector kernels of the Krylov solver: FP64 inner products with a
-// deterministic two-stage reduction (block partials written in a fixed
-// grid order, then summed by one workgroup in a fixed order), the
-// Gram-Schmidt update fused with the norm of its result, and BLAS-1 helpers.
+// Vector kernels of the Krylov solvers, templated on the storage type T of
+// the vectors (double, or float for the inner solves of the mixed modes).
+// Inner products and norms always accumulate in FP64 with a deterministic
+// two-stage reduction: block partials written in a fixed grid order, then
+// summed by one workgroup in a fixed order.
+#include "device_common.h"
 #include "kernels.h"
 
 namespace ldg {
@@ -29,12 +31,16 @@ __device__ inline double block_sum(double v, double* red) {
     for (int w = 0; w < KB / 64; ++w) s += red[w];
   return s;
 }
+
+inline unsigned nblk1(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 int krylov_nblk(int64_t n) { return (int)((n + CHUNK - 1) / CHUNK); }
 
-__global__ void __launch_bounds__(KB) k_dots(int64_t n, int nv, const double* __restrict__ V,
-                                             int64_t ldv, const double* __restrict__ w,
+// partials[j][b] = <V_j, w> on block b (j < nv), partials[nv][b] = <w, w>
+template <class T>
+__global__ void __launch_bounds__(KB) k_dots(int64_t n, int nv, const T* __restrict__ V,
+                                             int64_t ldv, const T* __restrict__ w,
                                              double* __restrict__ partials, int nblk) {
   __shared__ double red[KB / 64];
   const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
@@ -42,15 +48,15 @@ __global__ void __launch_bounds__(KB) k_dots(int64_t n, int nv, const double* __
 #pragma unroll
   for (int t = 0; t < KITEMS; ++t) {
     const int64_t i = base + (int64_t)t * KB;
-    wl[t] = i < n ? w[i] : 0.0;
+    wl[t] = i < n ? (double)w[i] : 0.0;
   }
   for (int j = 0; j < nv; ++j) {
-    const double* Vj = V + j * ldv;
+    const T* Vj = V + j * ldv;
     double s = 0.0;
 #pragma unroll
     for (int t = 0; t < KITEMS; ++t) {
       const int64_t i = base + (int64_t)t * KB;
-      if (i < n) s += Vj[i] * wl[t];
+      if (i < n) s += (double)Vj[i] * wl[t];
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) partials[(int64_t)j * nblk + blockIdx.x] = s;
@@ -62,25 +68,26 @@ __global__ void __launch_bounds__(KB) k_dots(int64_t n, int nv, const double* __
   if (threadIdx.x == 0) partials[(int64_t)nv * nblk + blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const double* __restrict__ V,
+// w -= sum_j h[j] V_j (FP64 arithmetic), partial sums of the new <w, w>
+template <class T>
+__global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const T* __restrict__ V,
                                                int64_t ldv, const double* __restrict__ h,
-                                               double* __restrict__ w,
-                                               double* __restrict__ partials) {
+                                               T* __restrict__ w, double* __restrict__ partials) {
   __shared__ double red[KB / 64];
   const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
   double wl[KITEMS];
 #pragma unroll
   for (int t = 0; t < KITEMS; ++t) {
     const int64_t i = base + (int64_t)t * KB;
-    wl[t] = i < n ? w[i] : 0.0;
+    wl[t] = i < n ? (double)w[i] : 0.0;
   }
   for (int j = 0; j < nv; ++j) {
-    const double* Vj = V + j * ldv;
+    const T* Vj = V + j * ldv;
     const double hj = h[j];
 #pragma unroll
     for (int t = 0; t < KITEMS; ++t) {
       const int64_t i = base + (int64_t)t * KB;
-      if (i < n) wl[t] -= hj * Vj[i];
+      if (i < n) wl[t] -= hj * (double)Vj[i];
     }
   }
   double s = 0.0;
@@ -88,8 +95,9 @@ __global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const double* 
   for (int t = 0; t < KITEMS; ++t) {
     const int64_t i = base + (int64_t)t * KB;
     if (i < n) {
-      w[i] = wl[t];
-      s += wl[t] * wl[t];
+      const T v = (T)wl[t];
+      w[i] = v;
+      s += (double)v * (double)v;
     }
   }
   s = block_sum(s, red);
@@ -107,20 +115,78 @@ __global__ void __launch_bounds__(KB) k_reduce(int nblk, const double* __restric
   if (threadIdx.x == 0) result[j] = s;
 }
 
-__global__ void k_lincomb(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
-                          const double* __restrict__ y, double* __restrict__ u) {
+template <class T>
+__global__ void k_lincomb(int64_t n, int nv, const T* __restrict__ V, int64_t ldv,
+                          const double* __restrict__ y, T* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int j = 0; j < nv; ++j) s += y[j] * V[j * ldv + i];
-  u[i] = s;
+  for (int j = 0; j < nv; ++j) s += y[j] * (double)V[j * ldv + i];
+  u[i] = (T)s;
 }
 
-__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
-                        double* __restrict__ y) {
+template <class T>
+__global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b,
+                        T* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+  y[i] = (T)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
+}
+
+// CG: x += a p, r -= a q, partial sums of the new <r, r>
+template <class T>
+__global__ void __launch_bounds__(KB) k_cg_update(int64_t n, double a, const T* __restrict__ p,
+                                                  const T* __restrict__ q, T* __restrict__ x,
+                                                  T* __restrict__ r,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[KB / 64];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < KITEMS; ++t) {
+    const int64_t i = base + (int64_t)t * KB;
+    if (i < n) {
+      x[i] = (T)((double)x[i] + a * (double)p[i]);
+      const T ri = (T)((double)r[i] - a * (double)q[i]);
+      r[i] = ri;
+      s += (double)ri * (double)ri;
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// precision casts: out = a * in
+template <class Ti, class To>
+__global__ void k_cast_scale(int64_t n, double a, const Ti* __restrict__ in, To* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = (To)(a * (double)in[i]);
+}
+
+// y (FP64) += a * x (any precision)
+template <class T>
+__global__ void k_axpy_into64(int64_t n, double a, const T* __restrict__ x,
+                              double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] += a * (double)x[i];
+}
+
+__global__ void __launch_bounds__(KB) k_mode_norms(int64_t Kpad, int N, const double* __restrict__ D,
+                                                   double* __restrict__ partials, int nblk) {
+  __shared__ double red[KB / 64];
+  double s0 = 0.0, s1 = 0.0;
+  const int64_t n = Kpad * N;
+  for (int64_t t = (int64_t)blockIdx.x * KB + threadIdx.x; t < n; t += (int64_t)nblk * KB) {
+    const int i = (int)((t / 64) % N);
+    const double v = D[t];
+    if (i == 0) s0 += v * v; else s1 += v * v;
+  }
+  s0 = block_sum(s0, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) partials[nblk + blockIdx.x] = s1;
 }
 
 __global__ void k_rhs(Geo g, int N, const double* __restrict__ C, const double* __restrict__ KDN,
@@ -141,53 +207,62 @@ __global__ void k_zrows(Geo g, int N, const double* __restrict__ Za, const doubl
   out[t] = s * a2 * (Za[t] - Zb[t]);
 }
 
-__global__ void __launch_bounds__(KB) k_cg_update(int64_t n, double a,
-                                                  const double* __restrict__ p,
-                                                  const double* __restrict__ q,
-                                                  double* __restrict__ x, double* __restrict__ r,
-                                                  double* __restrict__ partials) {
-  __shared__ double red[KB / 64];
-  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < KITEMS; ++t) {
-    const int64_t i = base + (int64_t)t * KB;
-    if (i < n) {
-      x[i] += a * p[i];
-      const double ri = r[i] - a * q[i];
-      r[i] = ri;
-      s += ri * ri;
-    }
-  }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-__global__ void __launch_bounds__(KB) k_mode_norms(int64_t Kpad, int N, const double* __restrict__ D,
-                                                   double* __restrict__ partials, int nblk) {
-  __shared__ double red[KB / 64];
-  double s0 = 0.0, s1 = 0.0;
-  const int64_t n = Kpad * N;
-  for (int64_t t = (int64_t)blockIdx.x * KB + threadIdx.x; t < n; t += (int64_t)nblk * KB) {
-    const int i = (int)((t / 64) % N);
-    const double v = D[t];
-    if (i == 0) s0 += v * v; else s1 += v * v;
-  }
-  s0 = block_sum(s0, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s0;
-  s1 = block_sum(s1, red);
-  if (threadIdx.x == 0) partials[nblk + blockIdx.x] = s1;
-}
+// ---------------------------------------------------------------------------
+// launchers (vt = VT_F64 / VT_F32 selects T)
+// ---------------------------------------------------------------------------
+#define LDG_VT(vt, CALL)                          \
+  if ((vt) == VT_F64) { using T = double; CALL; } \
+  else { using T = float; CALL; }
 
 void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st) {
   k_reduce<<<1, KB, 0, st>>>(nblk, partials, result);
 }
 
-void launch_cg_update(const Reducer& r, int64_t n, double a, const double* p, const double* q,
-                      double* x, double* rv, hipStream_t st) {
+void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
+                 const void* w, hipStream_t st) {
   const int nb = krylov_nblk(n);
-  k_cg_update<<<nb, KB, 0, st>>>(n, a, p, q, x, rv, r.partials);
+  LDG_VT(vt, (k_dots<T><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, (const T*)w, r.partials, nb)));
+  k_reduce<<<nv + 1, KB, 0, st>>>(nb, r.partials, r.result);
+}
+
+void launch_update(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
+                   const double* h, void* w, hipStream_t st) {
+  const int nb = krylov_nblk(n);
+  LDG_VT(vt, (k_update<T><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, h, (T*)w, r.partials)));
   k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+}
+
+void launch_lincomb(int vt, int64_t n, int nv, const void* V, int64_t ldv, const double* y,
+                    void* u, hipStream_t st) {
+  LDG_VT(vt, (k_lincomb<T><<<nblk1(n), 256, 0, st>>>(n, nv, (const T*)V, ldv, y, (T*)u)));
+}
+
+void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y, hipStream_t st) {
+  LDG_VT(vt, (k_axpby<T><<<nblk1(n), 256, 0, st>>>(n, a, (const T*)x, b, (T*)y)));
+}
+
+void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
+                      void* x, void* rv, hipStream_t st) {
+  const int nb = krylov_nblk(n);
+  LDG_VT(vt, (k_cg_update<T><<<nb, KB, 0, st>>>(n, a, (const T*)p, (const T*)q, (T*)x, (T*)rv,
+                                                r.partials)));
+  k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+}
+
+void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, void* out,
+                 hipStream_t st) {
+  if (vt_in == VT_F64 && vt_out == VT_F32)
+    k_cast_scale<double, float><<<nblk1(n), 256, 0, st>>>(n, a, (const double*)in, (float*)out);
+  else if (vt_in == VT_F32 && vt_out == VT_F64)
+    k_cast_scale<float, double><<<nblk1(n), 256, 0, st>>>(n, a, (const float*)in, (double*)out);
+  else if (vt_in == VT_F64)
+    k_cast_scale<double, double><<<nblk1(n), 256, 0, st>>>(n, a, (const double*)in, (double*)out);
+  else
+    k_cast_scale<float, float><<<nblk1(n), 256, 0, st>>>(n, a, (const float*)in, (float*)out);
+}
+
+void launch_axpy_into64(int vt, int64_t n, double a, const void* x, double* y, hipStream_t st) {
+  LDG_VT(vt, (k_axpy_into64<T><<<nblk1(n), 256, 0, st>>>(n, a, (const T*)x, y)));
 }
 
 void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st) {
@@ -196,37 +271,14 @@ void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red,
   k_reduce<<<2, KB, 0, st>>>(nb, red.partials, red.result);
 }
 
-void launch_dots(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
-                 const double* w, hipStream_t st) {
-  const int nb = krylov_nblk(n);
-  k_dots<<<nb, KB, 0, st>>>(n, nv, V, ldv, w, r.partials, nb);
-  k_reduce<<<nv + 1, KB, 0, st>>>(nb, r.partials, r.result);
-}
-
-void launch_update(const Reducer& r, int64_t n, int nv, const double* V, int64_t ldv,
-                   const double* h, double* w, hipStream_t st) {
-  const int nb = krylov_nblk(n);
-  k_update<<<nb, KB, 0, st>>>(n, nv, V, ldv, h, w, r.partials);
-  k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
-}
-
-void launch_lincomb(int64_t n, int nv, const double* V, int64_t ldv, const double* y, double* u,
-                    hipStream_t st) {
-  k_lincomb<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, nv, V, ldv, y, u);
-}
-
-void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
-  k_axpby<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, x, b, y);
-}
-
 void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,
                 double tau, double* b3, hipStream_t st) {
-  k_rhs<<<(unsigned)((g.Kpad * N + 255) / 256), 256, 0, st>>>(g, N, C, KDN, F, tau, b3);
+  k_rhs<<<nblk1(g.Kpad * N), 256, 0, st>>>(g, N, C, KDN, F, tau, b3);
 }
 
 void launch_zrows(const Geo& g, int N, const double* Za, const double* Zb, double s, double* out,
                   hipStream_t st) {
-  k_zrows<<<(unsigned)((g.Kpad * N + 255) / 256), 256, 0, st>>>(g, N, Za, Zb, s, out);
+  k_zrows<<<nblk1(g.Kpad * N), 256, 0, st>>>(g, N, Za, Zb, s, out);
 }
 
 }  // namespace ldg

@@ -119,11 +119,12 @@ def test_apply_and_preconditioner(torch_mod, n, seed, neu, p):
 
 
 def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0, krylov=0,
-               expect_krylov=None):
+               expect_krylov=None, precision=0, rtol=1e-13, infos=None):
     cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
     pr = Problem(cV, V0T, kind, p)
     w = workload(wkind, n, seed=seed, sigma=sigma, block=block)
-    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000, krylov=krylov)
+    s = _solver(cV, V0T, kind, p, rtol=rtol, restart=40, max_iters=20000, krylov=krylov,
+                precision=precision)
     gk = {SMOOTH1: 1, SMOOTH2: 2, LOGNORMAL: 3, LOGNORMAL_T: 4, TABLE2: 5}[wkind]
     dT = getattr(w, "dT", None)
     smp0 = s.sample_workload(gk, t0, dT=dT, want=("c0",))
@@ -136,7 +137,9 @@ def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0, kr
         t += dt
         smp = s.sample_workload(gk, t, dT=dT)
         info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
-        assert info["rel_residual"] <= 1e-13
+        assert info["rel_residual"] <= rtol
+        if infos is not None:
+            infos.append(info)
         if expect_krylov is not None:
             assert info["krylov"] == expect_krylov and info["fallbacks"] == 0, info
         C, Z1, Z2, oi = pr.step(C, t, dt, w)
@@ -171,3 +174,17 @@ def test_steps_small(torch_mod, p, n, seed, neu, wk):
 def test_krylov_selection(torch_mod, p, n, seed, neu, wk, krylov, expect):
     assert _run_steps(p, n, seed, neu, wk, 2, 0.05, block=3, krylov=krylov,
                       expect_krylov=expect) < 1e-10
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("p,n,seed,neu,wk", [
+    (4, 6, 401, (), LOGNORMAL_T),        # CG inner solves
+    (3, 7, 402, (SOUTH,), SMOOTH2),      # GMRES inner solves
+])
+def test_mixed_precision_refinement(torch_mod, precision, p, n, seed, neu, wk):
+    # FP32 / BF16 inner solves, FP64 residual and correction: the FP64 result
+    infos = []
+    err = _run_steps(p, n, seed, neu, wk, 2, 0.02, block=3, precision=precision, rtol=1e-12,
+                     infos=infos)
+    assert err < 1e-9, err
+    assert all(i["ir_steps"] >= 1 for i in infos)
