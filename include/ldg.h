@@ -203,6 +203,12 @@ ldg_status ldg_get_kernel_stat(ldg_ctx* ctx, int kernel, ldg_kernel_stat* out);
  */
 ldg_status ldg_assemble(ldg_ctx* ctx, const double* D);
 ldg_status ldg_get_blocks(ldg_ctx* ctx, double* out);
+/*
+ * Mixed-precision contexts also contract the blocks at the inner-solve
+ * precision (FP32, or BF16 operands with FP32 accumulation) on the matrix
+ * cores; ldg_get_blocks_lowp copies those out widened to FP64, same layout.
+ */
+ldg_status ldg_get_blocks_lowp(ldg_ctx* ctx, double* out);
 
 /*
  * Operator of the eliminated system with the blocks of the last

@@ -108,3 +108,15 @@ def two_triangle_mesh():
             if e == {0, 2}:
                 kind[k, n] = INTERIOR
     return coordV, V0T, kind
+
+
+def rotate_local_numbering(V0T, kind, seed, fraction=0.5):
+    """Start the counter-clockwise vertex list of a random subset of triangles
+    at another vertex: the mesh is unchanged, the local vertex and edge numbers
+    (and hence the neighbour edge index n+) vary from triangle to triangle."""
+    rng = np.random.default_rng(seed)
+    K = V0T.shape[0]
+    shift = np.where(rng.random(K) < fraction, rng.integers(1, 3, K), 0)
+    idx = (np.arange(3)[None, :] + shift[:, None]) % 3
+    return (np.take_along_axis(V0T, idx, axis=1).astype(np.int32),
+            np.take_along_axis(kind, idx, axis=1).astype(np.int8))

@@ -23,7 +23,7 @@ struct ldg_ctx {
   int32_t *nbr = nullptr, *bidx = nullptr, *belem = nullptr, *bk = nullptr;
   int8_t *nbrn = nullptr, *kind = nullptr, *bn = nullptr;
   // reference data
-  double *refs = nullptr, *Tg = nullptr, *Trd = nullptr, *Tro = nullptr;
+  double* refs = nullptr;
   double *Wvol = nullptr, *qvol = nullptr, *Wb = nullptr, *ws = nullptr, *sb = nullptr;
   // state and work, element-fastest layout
   double *C = nullptr, *Z1 = nullptr, *Z2 = nullptr, *D = nullptr, *F = nullptr;
@@ -36,6 +36,8 @@ struct ldg_ctx {
   float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
   float *u32 = nullptr, *tz1_32 = nullptr, *tz2_32 = nullptr, *V32 = nullptr;
   void *blocks_f32 = nullptr, *blocks_bf16 = nullptr, *bj_f32 = nullptr;
+  // reference tensors in the MFMA operand layouts (FP64, FP32, BF16)
+  void *Tm64 = nullptr, *Tm32 = nullptr, *Tm16 = nullptr;
   bool blocks_f32_ready = false;
   double *hdev = nullptr, *ydev = nullptr;
   int* status = nullptr;
@@ -54,6 +56,13 @@ struct ldg_ctx {
 };
 
 namespace {
+
+uint16_t host_bf16(float x) {   // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
 
 ldg_status fail(ldg_ctx* c, ldg_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -466,6 +475,24 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   return LDG_OK;
 }
 
+ldg_status assemble_lowp(ldg_ctx* c) {
+  const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
+  const double NN = (double)c->NN;
+  {
+    Timed tm(c, LDG_K_ASSEMBLE, (bt == BT_BF16 ? 2.0 : 4.0) * NN * (2.0 * c->K + 2.0 * c->Eint) +
+                                    8.0 * c->N * c->K,
+             2.0 * NN * c->N * (5.0 * c->K + 2.0 * c->Eint));
+    launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
+                         bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
+  }
+  {
+    Timed tm(c, LDG_K_BJ_SETUP, 12.0 * NN * c->K, 0.0);
+    launch_convert_blocks(BT_F32, c->Kpad, c->N, 1, c->bj, c->bj_f32, c->st);
+  }
+  c->blocks_f32_ready = bt == BT_F32;
+  return check_launch(c);
+}
+
 // true when D has no within-element variation (relative to its mean part)
 ldg_status coefficient_is_elementwise_constant(ldg_ctx* c, bool* yes) {
   launch_mode_norms(c->N, c->geo, c->D, c->red, c->st);
@@ -581,7 +608,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(upload(c, c->bn, hm.bedge_n));
   c->geo = Geo{c->K, c->Kpad, c->area2, c->B, c->a1, c->elen, c->nu, c->nbr, c->nbrn, c->kind, c->bidx};
   // reference data
-  std::vector<double> refs(14 * NN), Tg(2 * N * NN), Trd(3 * N * NN), Tro(9 * N * NN);
+  std::vector<double> refs(14 * NN);
   for (int f = 0; f < NN; ++f) {
     refs[0 * NN + f] = rf.H[0][f];
     refs[1 * NN + f] = rf.H[1][f];
@@ -589,11 +616,6 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) refs[(5 + 3 * a + b) * NN + f] = rf.So[a][b][f];
   }
-  for (int m = 0; m < 2; ++m) std::copy(rf.G[m].begin(), rf.G[m].end(), Tg.begin() + m * N * NN);
-  for (int n = 0; n < 3; ++n) std::copy(rf.Rd[n].begin(), rf.Rd[n].end(), Trd.begin() + n * N * NN);
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      std::copy(rf.Ro[a][b].begin(), rf.Ro[a][b].end(), Tro.begin() + (3 * a + b) * N * NN);
   std::vector<double> Wvol(c->R * N), qv(2 * c->R), Wb(3 * c->R1 * N);
   for (int r = 0; r < c->R; ++r) {
     qv[2 * r] = rf.q1[r];
@@ -608,23 +630,52 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       for (int i = 0; i < N; ++i) Wb[(n * c->R1 + r) * N + i] = phi_hat(i, x1, x2);
     }
   TRY(dalloc(c, &c->refs, refs.size()));
-  TRY(dalloc(c, &c->Tg, Tg.size()));
-  TRY(dalloc(c, &c->Trd, Trd.size()));
-  TRY(dalloc(c, &c->Tro, Tro.size()));
   TRY(dalloc(c, &c->Wvol, Wvol.size()));
   TRY(dalloc(c, &c->qvol, qv.size()));
   TRY(dalloc(c, &c->Wb, Wb.size()));
   TRY(dalloc(c, &c->ws, rf.ws.size()));
   TRY(dalloc(c, &c->sb, rf.s.size()));
   TRY(upload(c, c->refs, refs));
-  TRY(upload(c, c->Tg, Tg));
-  TRY(upload(c, c->Trd, Trd));
-  TRY(upload(c, c->Tro, Tro));
   TRY(upload(c, c->Wvol, Wvol));
   TRY(upload(c, c->qvol, qv));
   TRY(upload(c, c->Wb, Wb));
   TRY(upload(c, c->ws, rf.ws));
   TRY(upload(c, c->sb, rf.s));
+  {
+    // tensors t = G1, G2, Rd0..2, Ro(a,b) as A operands: [t][l<16][f] (FP64, FP32)
+    // and [t][f][l<32] (BF16), zero beyond N and N*N
+    const int NFP = (NN + 15) / 16 * 16;
+    std::vector<double> T64((size_t)14 * 16 * NFP, 0.0);
+    std::vector<float> T32((size_t)14 * 16 * NFP, 0.f);
+    std::vector<uint16_t> T16((size_t)14 * NFP * 32, 0);
+    auto tens = [&](int t, int l, int f) -> double {
+      if (t < 2) return rf.G[t][(size_t)l * NN + f];
+      if (t < 5) return rf.Rd[t - 2][(size_t)l * NN + f];
+      const int ab = t - 5;
+      return rf.Ro[ab / 3][ab % 3][(size_t)l * NN + f];
+    };
+    for (int t = 0; t < 14; ++t)
+      for (int l = 0; l < N; ++l)
+        for (int f = 0; f < NN; ++f) {
+          const double v = tens(t, l, f);
+          T64[((size_t)t * 16 + l) * NFP + f] = v;
+          T32[((size_t)t * 16 + l) * NFP + f] = (float)v;
+          T16[((size_t)t * NFP + f) * 32 + l] = host_bf16((float)v);
+        }
+    double* p64 = nullptr;
+    float* p32 = nullptr;
+    uint16_t* p16 = nullptr;
+    TRY(dalloc(c, &p64, T64.size()));
+    TRY(dalloc(c, &p32, T32.size()));
+    TRY(dalloc(c, &p16, T16.size()));
+    TRY(upload(c, p64, T64));
+    TRY(upload(c, p32, T32));
+    TRY(upload(c, p16, T16));
+    TRY(sync(c));
+    c->Tm64 = p64;
+    c->Tm32 = p32;
+    c->Tm16 = p16;
+  }
   // state and work vectors
   const int64_t nv = c->nvec;
   double** vecs[] = {&c->C,  &c->Z1, &c->Z2, &c->D,   &c->F,   &c->J1,  &c->J2,  &c->KDN,
@@ -746,7 +797,12 @@ ldg_status ldg_get_solution(ldg_ctx* c, double* C, double* Z1, double* Z2, int o
 ldg_status ldg_assemble(ldg_ctx* c, const double* Dem) {
   if (!c || !Dem) return fail(c, LDG_EINVAL, "bad arguments");
   launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
-  launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+  launch_assemble_mfma(c->N, BT_F64, c->geo, c->D, c->Tm64, c->blocks, c->st);
+  if (c->opt.precision != LDG_FP64) {
+    const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
+    launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
+                         bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
+  }
   c->blocks_ready = true;
   return check_launch(c);
 }
@@ -754,6 +810,15 @@ ldg_status ldg_assemble(ldg_ctx* c, const double* Dem) {
 ldg_status ldg_get_blocks(ldg_ctx* c, double* out) {
   if (!c || !out) return fail(c, LDG_EINVAL, "bad arguments");
   launch_export_blocks(c->K, c->N, NSLOT, c->blocks, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_get_blocks_lowp(ldg_ctx* c, double* out) {
+  if (!c || !out) return fail(c, LDG_EINVAL, "bad arguments");
+  if (c->opt.precision == LDG_FP64) return fail(c, LDG_EINVAL, "context has no low-precision blocks");
+  const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
+  launch_export_blocks_any(bt, c->K, c->N, NSLOT, bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32,
+                           out, c->st);
   return check_launch(c);
 }
 
@@ -829,7 +894,7 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
     const double NN = (double)c->NN;
     Timed tm(c, LDG_K_ASSEMBLE, 8.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 8.0 * c->N * c->K,
              2.0 * NN * c->N * (5.0 * c->K + 2.0 * c->Eint));
-    launch_assemble(c->N, c->geo, c->D, c->Tg, c->Trd, c->Tro, c->blocks, c->st);
+    launch_assemble_mfma(c->N, BT_F64, c->geo, c->D, c->Tm64, c->blocks, c->st);
   }
   c->blocks_ready = true;
   TRY(check_launch(c));
@@ -842,15 +907,9 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   TRY(norm2(c, level64(c), c->J1, &nj1));
   TRY(norm2(c, level64(c), c->J2, &nj2));
   const double bnorm = std::sqrt(nb3 + tau * tau * (nj1 + nj2));
-  // low-precision copies for the inner solves of the mixed modes
-  if (c->opt.precision != LDG_FP64) {
-    Timed tm(c, LDG_K_ASSEMBLE, 8.0 * c->NN * (3.0 * c->K + 2.0 * c->Eint), 0.0);
-    const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
-    launch_convert_blocks(bt, c->Kpad, c->N, NSLOT, c->blocks,
-                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
-    launch_convert_blocks(BT_F32, c->Kpad, c->N, 1, c->bj, c->bj_f32, c->st);
-    c->blocks_f32_ready = bt == BT_F32;
-  }
+  // the inner solves of the mixed modes: blocks contracted at FP32 or BF16 on
+  // the matrix cores, FP32 copy of the block-Jacobi inverses
+  if (c->opt.precision != LDG_FP64) TRY(assemble_lowp(c));
   // a6, a7: Krylov solve (with FP64 refinement) starting from C^n
   bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));

@@ -10,8 +10,6 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
                      const double* Wb, const double* ws, const double* cD, const double* gN,
                      int64_t nbnd, const double* D, double eta, double* J1, double* J2,
                      double* KDN, hipStream_t st);
-void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, const double* Trd,
-                     const double* Tro, double* blocks, hipStream_t st);
 // vector storage (VT_*) and block storage (BT_*) precisions
 enum { VT_F64 = 0, VT_F32 = 1 };
 enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2 };
@@ -29,6 +27,13 @@ void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const 
 void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* src, void* dst,
                            hipStream_t st);
 size_t block_bytes(int bt, int64_t Kpad, int N, int ns);
+// kernels_assemble_mfma.hip: the 5 D-dependent blocks per triangle on the
+// matrix cores; T = reference tensors in the operand layout of precision bt
+void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const void* T, void* blocks,
+                          hipStream_t st);
+// export stored blocks of any precision as FP64 [K][ns][N][N]
+void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src, double* dst,
+                              hipStream_t st);
 void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
                      double eta, double* bj, int* status, hipStream_t st);
 void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,

@@ -214,6 +214,25 @@ __global__ void k_convert_blocks(int64_t Kpad, int N, int ns, const double* __re
   dst[t] = from_double<BT>(v);
 }
 
+template <class BT>
+__global__ void k_export_any(int64_t K, int N, int ns, const BT* __restrict__ src,
+                             double* __restrict__ dst) {
+  const int NN = N * N;
+  const int W = Blk<BT>::W;
+  const int NG = ngroups(N, W);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * ns * NN) return;
+  const int64_t k = t / (ns * NN);
+  const int rem = (int)(t % (ns * NN));
+  const int s = rem / NN, f = rem % NN;
+  BT v = src[bgidx(k, s, f / W, ns, NG, W) + f % W];
+  if constexpr (sizeof(BT) == 2) {
+    dst[t] = (double)__uint_as_float((uint32_t)v << 16);
+  } else {
+    dst[t] = (double)v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -290,6 +309,14 @@ void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* sr
     const int64_t n = Kpad * ns * ngroups(N, 8) * 8;
     k_convert_blocks<bf16><<<nblk(n, 256), 256, 0, st>>>(Kpad, N, ns, src, (bf16*)dst);
   }
+}
+
+void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src, double* dst,
+                              hipStream_t st) {
+  const unsigned nb = nblk(K * ns * N * N, 256);
+  if (bt == BT_F64) k_export_any<double><<<nb, 256, 0, st>>>(K, N, ns, (const double*)src, dst);
+  else if (bt == BT_F32) k_export_any<float><<<nb, 256, 0, st>>>(K, N, ns, (const float*)src, dst);
+  else k_export_any<bf16><<<nb, 256, 0, st>>>(K, N, ns, (const bf16*)src, dst);
 }
 
 size_t block_bytes(int bt, int64_t Kpad, int N, int ns) {

@@ -125,89 +125,6 @@ __global__ void __launch_bounds__(256) k_boundary(Geo g, int64_t nbe,
 }
 
 // ---------------------------------------------------------------------------
-// Block assembly, FP64 on the vector ALU (one lane per triangle).
-//   slot m   : B^m_kk = -G^m_k + sum_n c_n nu^m_kn |E_kn| sum_l D_kl R_hat_diag(:,:,l,n)
-//              c_n = 1/2 interior, 1 Dirichlet, 0 Neumann
-//   slot 2+n : U_kn = 1/2 |E_kn| sum_l D_{k+ l} R_hat_off(:,:,l,n,n+)   (interior edges)
-// Tensors are stored [l][f], f = i*N + j.
-// ---------------------------------------------------------------------------
-template <int N>
-__global__ void __launch_bounds__(256) k_assemble_valu(Geo g, const double* __restrict__ D,
-                                                       const double* __restrict__ Tg,
-                                                       const double* __restrict__ Trd,
-                                                       const double* __restrict__ Tro,
-                                                       double* __restrict__ blocks) {
-  constexpr int NN = N * N;
-  constexpr int NP = npairs(N);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.Kpad) return;
-  if (k >= g.K) {
-    for (int s = 0; s < NSLOT; ++s)
-      for (int pr = 0; pr < NP; ++pr)
-        *reinterpret_cast<double2*>(blocks + pidx(k, s, pr, NSLOT, NP)) = make_double2(0.0, 0.0);
-    return;
-  }
-  const int64_t Kp = g.Kpad;
-  double Dk[N], Dn[3][N];
-  load_vec<N, double>(D, k, Dk);
-  int npl[3];
-  double wr[2][3], uo[3];
-  const double B11 = g.B[k], B12 = g.B[Kp + k], B21 = g.B[2 * Kp + k], B22 = g.B[3 * Kp + k];
-  // -G^1 = -(B22 G1 - B21 G2), -G^2 = -(-B12 G1 + B11 G2)
-  const double wg[2][2] = {{-B22, B21}, {B12, -B11}};
-#pragma unroll
-  for (int n = 0; n < 3; ++n) {
-    const int kind = g.kind[n * Kp + k];
-    const double L = g.elen[n * Kp + k];
-    const double c = kind == LDG_EDGE_INTERIOR ? 0.5 : (kind == LDG_EDGE_DIRICHLET ? 1.0 : 0.0);
-    wr[0][n] = c * g.nu[(2 * n) * Kp + k] * L;
-    wr[1][n] = c * g.nu[(2 * n + 1) * Kp + k] * L;
-    const int kp = g.nbr[n * Kp + k];
-    npl[n] = kp >= 0 ? g.nbrn[n * Kp + k] : 0;
-    uo[n] = kp >= 0 ? 0.5 * L : 0.0;
-    if (kp >= 0) {
-      load_vec<N, double>(D, kp, Dn[n]);
-    } else {
-#pragma unroll
-      for (int l = 0; l < N; ++l) Dn[n][l] = 0.0;
-    }
-  }
-  for (int pr = 0; pr < NP; ++pr) {
-    double out[NSLOT][2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int f = 2 * pr + h;
-      if (f >= NN) {
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) out[s][h] = 0.0;
-        continue;
-      }
-      double g0 = 0.0, g1 = 0.0, rd[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int l = 0; l < N; ++l) {
-        g0 += Dk[l] * Tg[l * NN + f];
-        g1 += Dk[l] * Tg[(N + l) * NN + f];
-#pragma unroll
-        for (int n = 0; n < 3; ++n) {
-          rd[n] += Dk[l] * Trd[(n * N + l) * NN + f];
-          u[n] += Dn[n][l] * Tro[((3 * n + npl[n]) * N + l) * NN + f];
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-        out[m][h] = wg[m][0] * g0 + wg[m][1] * g1 + wr[m][0] * rd[0] + wr[m][1] * rd[1] +
-                    wr[m][2] * rd[2];
-#pragma unroll
-      for (int n = 0; n < 3; ++n) out[2 + n][h] = uo[n] * u[n];
-    }
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s)
-      *reinterpret_cast<double2*>(blocks + pidx(k, s, pr, NSLOT, NP)) =
-          make_double2(out[s][0], out[s][1]);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Block-Jacobi setup: the diagonal block of the eliminated operator,
 //   P_k = 2|T_k| I + tau [ eta S'_kk - (1/2|T_k|) sum_m B^m_kk A^m_kk
 //                          + sum_{n interior} |E_kn| / (2 * 2|T_k+|) U_kn S_hat_off(:,:,n+,n) ],
@@ -500,11 +417,6 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
                                                                    gN, nbnd, D, eta, J1, J2, KDN)));
 }
 
-void launch_assemble(int N, const Geo& g, const double* D, const double* Tg, const double* Trd,
-                     const double* Tro, double* blocks, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_assemble_valu<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, D, Tg, Trd, Tro,
-                                                                            blocks)));
-}
 
 
 

@@ -65,6 +65,7 @@ _SIGS = {
     "ldg_get_solution": [_P, _P, _P, _P, C.c_int],
     "ldg_assemble": [_P, _P],
     "ldg_get_blocks": [_P, _P],
+    "ldg_get_blocks_lowp": [_P, _P],
     "ldg_apply_schur": [_P, C.c_double, _P, _P],
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
@@ -212,6 +213,11 @@ class Solver:
     def get_blocks(self):
         out = self._empty(self.K, 5, self.N, self.N)
         self._check(self.lib.ldg_get_blocks(self.h, _ptr(out)))
+        return out
+
+    def get_blocks_lowp(self):
+        out = self._empty(self.K, 5, self.N, self.N)
+        self._check(self.lib.ldg_get_blocks_lowp(self.h, _ptr(out)))
         return out
 
     def apply_schur(self, dt, Cm):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from inputs.fields import LOGNORMAL, LOGNORMAL_T, SMOOTH1, SMOOTH2, TABLE2
-from inputs.meshes import EAST, NORTH, SOUTH, WEST, square_mesh
+from inputs.meshes import EAST, NORTH, SOUTH, WEST, rotate_local_numbering, square_mesh
 from oracle.ldg import Blocks, Problem, minv_blocks, schur_matrix, system, mass_W
 from tests.gpu_common import rel_l2, to_np, workload
 
@@ -52,6 +52,65 @@ def test_projection_and_quad_points(torch_mod, n, seed, neu, p):
     assert rel_l2(pr.grid.areaT, F, data["F"]) < 1e-13
     x, y = s.quad_points(0)
     assert x.numel() == s.R * s.K
+
+
+def _oracle_blocks(pr, D):
+    """[K][5][N][N] oracle blocks: B^1_kk, B^2_kk, U_kn = sum_m nu^m_kn R^m_{k k+}."""
+    b = Blocks(pr.grid, pr.refs, D)
+    g, N = pr.grid, pr.N
+    Bm = [(-b.G[m] + b.R[m] + b.RD[m]).tocsr() for m in range(2)]
+    out = np.zeros((g.numT, 5, N, N))
+    for k in range(g.numT):
+        sl = slice(k * N, (k + 1) * N)
+        for m in range(2):
+            out[k, m] = Bm[m][sl, sl].toarray()
+        for nn in range(3):
+            kp = g.kp[k, nn]
+            if kp >= 0:
+                slp = slice(kp * N, (kp + 1) * N)
+                out[k, 2 + nn] = sum(g.nuE0T[k, nn, m] * Bm[m][sl, slp].toarray() for m in range(2))
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 3e-6), (2, 3e-2)])
+@pytest.mark.parametrize("n,seed,p,rotate", [(5, 501, 4, False), (9, 502, 3, True), (6, 503, 2, True)])
+def test_blocks_low_precision_contraction(torch_mod, precision, tol, n, seed, p, rotate):
+    # FP32 / BF16-operand MFMA contractions against the FP64 oracle blocks
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(SOUTH,))
+    if rotate:
+        V0T, kind = rotate_local_numbering(V0T, kind, seed)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(seed)
+    D = 1.0 + 0.5 * rng.standard_normal((pr.grid.numT, pr.N))
+    s = _solver(cV, V0T, kind, p, precision=precision)
+    s.assemble(D)
+    want = _oracle_blocks(pr, D)
+    got = to_np(s.get_blocks_lowp())
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= tol * scale, (np.abs(got - want).max() / scale)
+    assert np.abs(to_np(s.get_blocks()) - want).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,seed,p", [(9, 511, 4), (7, 512, 1), (9, 513, 2)])
+def test_rotated_local_numbering_steps(torch_mod, n, seed, p):
+    # local edge numbers vary per triangle (mixed n+ inside a wave): blocks and steps
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(NORTH,))
+    V0T, kind = rotate_local_numbering(V0T, kind, seed)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(seed)
+    D = rng.standard_normal((pr.grid.numT, pr.N))
+    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000)
+    s.assemble(D)
+    want = _oracle_blocks(pr, D)
+    assert np.abs(to_np(s.get_blocks()) - want).max() <= 1e-12 * np.abs(want).max()
+    w = workload(TABLE2, n)
+    smp0 = s.sample_workload(5, 0.0, want=("c0",))
+    s.set_initial_samples(smp0["c0"], 0.0)
+    C = pr.initial(w)
+    smp = s.sample_workload(5, 0.03)
+    info = s.step_sampled(0.03, smp["d"], smp["f"], smp["cD"], smp["gN"])
+    C, Z1, Z2, _ = pr.step(C, 0.03, 0.03, w)
+    assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
 
 
 @pytest.mark.parametrize("n,seed,neu,p", CASES)
