@@ -209,6 +209,13 @@ ldg_status ldg_get_blocks(ldg_ctx* ctx, double* out);
  * cores; ldg_get_blocks_lowp copies those out widened to FP64, same layout.
  */
 ldg_status ldg_get_blocks_lowp(ldg_ctx* ctx, double* out);
+/*
+ * The FP64 blocks (n x 5 x N x N) or block-Jacobi inverses (n x N x N) of
+ * the n triangles listed in elems (device, 0-based, each < K; not checked
+ * on the device), for sampled checks of large meshes.  out: device.
+ */
+ldg_status ldg_get_blocks_rows(ldg_ctx* ctx, const int32_t* elems, int64_t n, double* out);
+ldg_status ldg_get_bj_rows(ldg_ctx* ctx, const int32_t* elems, int64_t n, double* out);
 
 /*
  * Operator of the eliminated system with the blocks of the last

@@ -49,6 +49,13 @@ class Workload:
         self.dT = None if blocks is None else triangle_values(self.blocks, n_cells, block)
         self.stationary = kind == TABLE2
 
+    def restrict(self, elems):
+        """The same workload seen on the triangles `elems` only (rows of point arrays)."""
+        w = Workload(self.kind)
+        w.n_cells, w.block, w.blocks = self.n_cells, self.block, self.blocks
+        w.dT = None if self.dT is None else self.dT[np.asarray(elems)]
+        return w
+
     # --- exact solution and its derivatives -------------------------------
     def c(self, t, x, y):
         c = np.cos(7 * x) * np.cos(7 * y)

@@ -32,10 +32,10 @@ from .refelem import RefTensors, gamma
 # --------------------------------------------------------------------------
 # L2 projection (Sec. 3.4)
 # --------------------------------------------------------------------------
-def volume_points(grid, p, order=None):
+def volume_points(grid, p, order=None, elems=None):
     """Physical quadrature points [K x R] of the projection rule and its weights."""
     q1, q2, w = triangle_rule(projection_order(p) if order is None else order)
-    X1, X2 = grid.map_to_physical(q1, q2)
+    X1, X2 = grid.map_to_physical(q1, q2, elems)
     return X1, X2, (q1, q2, w)
 
 
@@ -47,9 +47,9 @@ def project_samples(samples, rule, hatM):
     return np.linalg.solve(hatM.T, rhs.T).T
 
 
-def project(grid, p, func, hatM, order=None):
-    """L2 projection of func(x1, x2) onto P_p(T_h)."""
-    X1, X2, rule = volume_points(grid, p, order)
+def project(grid, p, func, hatM, order=None, elems=None):
+    """L2 projection of func(x1, x2) onto P_p(T_h) (rows: all triangles or `elems`)."""
+    X1, X2, rule = volume_points(grid, p, order, elems)
     return project_samples(func(X1, X2), rule, hatM)
 
 
@@ -363,3 +363,32 @@ def full_residual(problem, blocks, data, tau, Cn, C, Z1, Z2):
     Y = np.concatenate([Z1.reshape(-1), Z2.reshape(-1), C.reshape(-1)])
     rhs = W @ Yn + tau * V
     return np.linalg.norm(rhs - (W + tau * A) @ Y) / np.linalg.norm(rhs)
+
+
+def schur_apply_rows(grid, refs, D, C, tau, eta, elems, J=None):
+    """Rows `elems` of M C + tau(eta S' C + sum_m B^m Z^m),  Z^m = -M^{-1}(A^m C [+ J^m]).
+
+    Only the block rows these rows touch are built: B^m, M, S' on `elems`,
+    A^m on `elems` and their neighbours.  Returns (y [len x N], Z [2][len x N])
+    with Z on `elems`."""
+    K, N = grid.numT, refs.N
+    elems = np.asarray(elems)
+    nbr = grid.kp[elems]
+    patch = np.unique(np.concatenate([elems, nbr[nbr >= 0]]))
+    bp = Blocks(grid, refs, None, elems=patch)
+    be = Blocks(grid, refs, D, elems=elems)
+    c = C.reshape(-1)
+    inv = np.linalg.inv(refs.hatM)
+    Zfull = []
+    for m in range(2):
+        AC = ((-bp.H[m] + bp.Q[m] + bp.QN[m]) @ c).reshape(len(patch), N)
+        if J is not None:
+            AC = AC + J[m][patch]
+        Zp = -(AC @ inv.T) / (2 * grid.areaT[patch])[:, None]
+        z = np.zeros((K, N))
+        z[patch] = Zp
+        Zfull.append(z)
+    y = be.M @ c + tau * (eta * ((be.S + be.SD) @ c)
+                          + sum((-be.G[m] + be.R[m] + be.RD[m]) @ Zfull[m].reshape(-1)
+                                for m in range(2)))
+    return y.reshape(len(elems), N), [Zfull[m][elems] for m in range(2)]

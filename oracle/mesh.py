@@ -34,31 +34,34 @@ class Grid:
         vec = self.coordV[ve] - self.coordV[vs]          # [K x 3 x 2]
         self.areaE0T = np.sqrt(vec[..., 0] ** 2 + vec[..., 1] ** 2)
         self.nuE0T = np.stack([vec[..., 1], -vec[..., 0]], axis=-1) / self.areaE0T[..., None]
-        # neighbours through shared vertex pairs
+        # neighbours: local edges with the same vertex pair (sorted by a pair key)
         self.kp = -np.ones((K, 3), dtype=np.int64)
         self.np_ = -np.ones((K, 3), dtype=np.int64)
-        owner = {}
-        for k in range(K):
-            for n in range(3):
-                key = (min(vs[k, n], ve[k, n]), max(vs[k, n], ve[k, n]))
-                owner.setdefault(key, []).append((k, n))
-        for key, lst in owner.items():
-            if len(lst) > 2:
-                raise MeshError("edge shared by more than two triangles")
-            if len(lst) == 2:
-                (k1, n1), (k2, n2) = lst
-                if vs[k1, n1] != ve[k2, n2]:
-                    raise MeshError("neighbouring triangles with inconsistent orientation")
-                self.kp[k1, n1], self.np_[k1, n1] = k2, n2
-                self.kp[k2, n2], self.np_[k2, n2] = k1, n1
+        lo = np.minimum(vs, ve).reshape(-1)
+        hi = np.maximum(vs, ve).reshape(-1)
+        key = lo * (self.coordV.shape[0] + 1) + hi
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        same = ks[1:] == ks[:-1]
+        if np.any(same[1:] & same[:-1]):
+            raise MeshError("edge shared by more than two triangles")
+        first, second = order[:-1][same], order[1:][same]
+        k1, n1 = first // 3, first % 3
+        k2, n2 = second // 3, second % 3
+        if np.any(vs[k1, n1] != ve[k2, n2]):
+            raise MeshError("neighbouring triangles with inconsistent orientation")
+        self.kp[k1, n1], self.np_[k1, n1] = k2, n2
+        self.kp[k2, n2], self.np_[k2, n2] = k1, n1
         interior = self.kp >= 0
         if np.any(interior != (self.kind == INTERIOR)):
             raise MeshError("edge kinds disagree with the topology")
 
-    def map_to_physical(self, x1, x2):
-        """F_k(x_hat) for all k: returns X1, X2 of shape [K x len(x1)]."""
+    def map_to_physical(self, x1, x2, elems=None):
+        """F_k(x_hat) for all k (or the triangles `elems`): X1, X2 of shape [K x len(x1)]."""
         x1 = np.atleast_1d(x1)
         x2 = np.atleast_1d(x2)
-        X1 = self.B[:, 0, 0:1] * x1 + self.B[:, 0, 1:2] * x2 + self.coordV0T[:, 0, 0:1]
-        X2 = self.B[:, 1, 0:1] * x1 + self.B[:, 1, 1:2] * x2 + self.coordV0T[:, 0, 1:2]
+        el = slice(None) if elems is None else np.asarray(elems)
+        B, a = self.B[el], self.coordV0T[el]
+        X1 = B[:, 0, 0:1] * x1 + B[:, 0, 1:2] * x2 + a[:, 0, 0:1]
+        X2 = B[:, 1, 0:1] * x1 + B[:, 1, 1:2] * x2 + a[:, 0, 1:2]
         return X1, X2

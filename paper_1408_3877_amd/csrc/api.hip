@@ -813,6 +813,18 @@ ldg_status ldg_get_blocks(ldg_ctx* c, double* out) {
   return check_launch(c);
 }
 
+ldg_status ldg_get_blocks_rows(ldg_ctx* c, const int32_t* elems, int64_t n, double* out) {
+  if (!c || (n > 0 && (!elems || !out)) || n < 0) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_export_rows(n, elems, c->N, NSLOT, c->blocks, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_get_bj_rows(ldg_ctx* c, const int32_t* elems, int64_t n, double* out) {
+  if (!c || (n > 0 && (!elems || !out)) || n < 0) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_export_rows(n, elems, c->N, 1, c->bj, out, c->st);
+  return check_launch(c);
+}
+
 ldg_status ldg_get_blocks_lowp(ldg_ctx* c, double* out) {
   if (!c || !out) return fail(c, LDG_EINVAL, "bad arguments");
   if (c->opt.precision == LDG_FP64) return fail(c, LDG_EINVAL, "context has no low-precision blocks");

@@ -27,6 +27,9 @@ void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const 
 void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* src, void* dst,
                            hipStream_t st);
 size_t block_bytes(int bt, int64_t Kpad, int N, int ns);
+// FP64 stored blocks of the listed triangles as [n][ns][N][N]
+void launch_export_rows(int64_t n, const int32_t* elems, int N, int ns, const double* src,
+                        double* dst, hipStream_t st);
 // kernels_assemble_mfma.hip: the 5 D-dependent blocks per triangle on the
 // matrix cores; T = reference tensors in the operand layout of precision bt
 void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const void* T, void* blocks,

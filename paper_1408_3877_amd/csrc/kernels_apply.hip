@@ -233,6 +233,19 @@ __global__ void k_export_any(int64_t K, int N, int ns, const BT* __restrict__ sr
   }
 }
 
+// rows of stored blocks for the listed triangles, FP64 [n][ns][N][N]
+__global__ void k_export_rows(int64_t n, const int32_t* __restrict__ elems, int N, int ns,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const int NN = N * N;
+  const int NG = ngroups(N, 2);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ns * NN) return;
+  const int64_t i = t / (ns * NN);
+  const int rem = (int)(t % (ns * NN));
+  const int s = rem / NN, f = rem % NN;
+  dst[t] = src[bgidx(elems[i], s, f / 2, ns, NG, 2) + (f & 1)];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -317,6 +330,12 @@ void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src,
   if (bt == BT_F64) k_export_any<double><<<nb, 256, 0, st>>>(K, N, ns, (const double*)src, dst);
   else if (bt == BT_F32) k_export_any<float><<<nb, 256, 0, st>>>(K, N, ns, (const float*)src, dst);
   else k_export_any<bf16><<<nb, 256, 0, st>>>(K, N, ns, (const bf16*)src, dst);
+}
+
+void launch_export_rows(int64_t n, const int32_t* elems, int N, int ns, const double* src,
+                        double* dst, hipStream_t st) {
+  if (n == 0) return;
+  k_export_rows<<<nblk(n * ns * N * N, 256), 256, 0, st>>>(n, elems, N, ns, src, dst);
 }
 
 size_t block_bytes(int bt, int64_t Kpad, int N, int ns) {

@@ -66,6 +66,8 @@ _SIGS = {
     "ldg_assemble": [_P, _P],
     "ldg_get_blocks": [_P, _P],
     "ldg_get_blocks_lowp": [_P, _P],
+    "ldg_get_blocks_rows": [_P, _P, C.c_int64, _P],
+    "ldg_get_bj_rows": [_P, _P, C.c_int64, _P],
     "ldg_apply_schur": [_P, C.c_double, _P, _P],
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
@@ -214,6 +216,21 @@ class Solver:
         out = self._empty(self.K, 5, self.N, self.N)
         self._check(self.lib.ldg_get_blocks(self.h, _ptr(out)))
         return out
+
+    def _rows(self, fn, elems, ns):
+        e = np.ascontiguousarray(elems, dtype=np.int32)
+        if e.size and (e.min() < 0 or e.max() >= self.K):
+            raise ValueError("element index out of range")
+        ed = self.torch.as_tensor(e).to(self.device)
+        out = self._empty(max(len(e), 1), ns, self.N, self.N)[:len(e)]
+        self._check(fn(self.h, _ptr(ed), len(e), _ptr(out)))
+        return out
+
+    def get_blocks_rows(self, elems):
+        return self._rows(self.lib.ldg_get_blocks_rows, elems, 5)
+
+    def get_bj_rows(self, elems):
+        return self._rows(self.lib.ldg_get_bj_rows, elems, 1)[:, 0]
 
     def get_blocks_lowp(self):
         out = self._empty(self.K, 5, self.N, self.N)

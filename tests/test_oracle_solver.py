@@ -146,6 +146,22 @@ def test_elementwise_constant_d_gives_spd_operator(p):
     assert np.abs(S2 - S2.T).max() > 1e-6 * np.abs(S2).max()
 
 
+def test_row_restricted_schur_apply_matches_global_matrix():
+    # the sampled-rows form used at full size equals rows of the global Schur matrix
+    from oracle.ldg import schur_apply_rows
+    cV, V0T, kind = square_mesh(6, seed=71, neumann_sides=(EAST,))
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(3)
+    rng = np.random.default_rng(5)
+    D = rng.standard_normal((g.numT, refs.N))
+    C = rng.standard_normal((g.numT, refs.N))
+    S = schur_matrix(Blocks(g, refs, D), g, refs, 1.3, 0.02)
+    elems = np.array([0, 7, 19, 40, g.numT - 1])
+    y, Z = schur_apply_rows(g, refs, D, C, 0.02, 1.3, elems)
+    full = (S @ C.reshape(-1)).reshape(g.numT, refs.N)
+    np.testing.assert_allclose(y, full[elems], atol=1e-12 * np.abs(full).max())
+
+
 def test_schur_elimination_equals_full_solve():
     cV, V0T, kind = square_mesh(4, seed=51, neumann_sides=(SOUTH,))
     pr = Problem(cV, V0T, kind, 2)
