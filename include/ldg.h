@@ -178,7 +178,8 @@ typedef enum {
   LDG_K_BJ_SETUP = 4,  /* block-Jacobi setup and inversion */
   LDG_K_KRYLOV = 5,    /* Gram-Schmidt dots, updates, vector updates */
   LDG_K_PROJECT = 6,   /* projections and boundary data */
-  LDG_K_COUNT = 7
+  LDG_K_GNN = 7,       /* graph-network inference and training */
+  LDG_K_COUNT = 8
 } ldg_kernel_id;
 typedef struct {
   int64_t launches;
@@ -255,6 +256,53 @@ ldg_status ldg_get_bj(ldg_ctx* ctx, double* out);
  */
 ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* dT, double* d,
                                double* f, double* cD, double* gN, double* c0);
+
+/*
+ * Learned preconditioner (options.precond = LDG_PC_GNN).  A graph network on
+ * the element graph (nodes: triangles; edges: interior edges, both
+ * directions), FP32, width 32: an encoder, three message-passing layers
+ * (message relu(h_j W_m + e_kj W_e + b_m) summed over neighbours, residual
+ * update h_k += relu([h_k, a_k] W_u + b_u)) and a linear decoder.  Inputs:
+ * r_hat = BJ^{-1} r / rho (rho = RMS of BJ^{-1} r), log mean d, relative
+ * higher modes of D, log area, log(dt d / |T|), eta per triangle; normal,
+ * log edge length, one-hot (n, n+) and log coefficient ratio per edge.  The
+ * preconditioner is P(r) = BJ^{-1} r + rho g(r_hat), used inside flexible
+ * CG; a breakdown returns the step to block-Jacobi CG (fallbacks), and the
+ * FP64 residual of the full system decides convergence as always.  For
+ * nonsymmetric steps (GMRES) block-Jacobi is used and one fallback counted.
+ * Parameters are a flat FP32 vector: W_enc [(2N+3) x 32], b_enc [32], then
+ * per layer W_m [32 x 32], W_e [13 x 32], b_m [32], W_u [64 x 32], b_u [32],
+ * then W_dec [32 x N], b_dec [N] (row-major).
+ */
+ldg_status ldg_gnn_num_params(ldg_ctx* ctx, int64_t* n);
+/* host parameter vector in/out; setting resets the Adam moments */
+ldg_status ldg_gnn_set_params(ldg_ctx* ctx, const float* w, int64_t n);
+ldg_status ldg_gnn_get_params(ldg_ctx* ctx, float* w, int64_t n);
+/* per-triangle and per-edge features from D (device K x N, NULL: last projected) and dt */
+ldg_status ldg_gnn_set_context(ldg_ctx* ctx, const double* D, double dt);
+/* g = network(r_hat): r_hat, g device K x N FP32 */
+ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
+/*
+ * loss = mean over (k, i) of (g_ki - target_ki)^2 and its gradient (device,
+ * n_params floats, may be NULL); the weight gradients are fixed-order FP64
+ * reductions.  ldg_gnn_train_step does the same and one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
+ */
+ldg_status ldg_gnn_loss_grad(ldg_ctx* ctx, const float* rhat, const float* target, float* grad,
+                             double* loss);
+ldg_status ldg_gnn_train_step(ldg_ctx* ctx, const float* rhat, const float* target, double lr,
+                              double* loss);
+/*
+ * Training data from the method's own solves: arm the next ldg_step_sampled
+ * (FP64 block-Jacobi CG) to keep its iterates x_s at the CG iterations
+ * iters[0] < iters[1] < ... (host, nsnap <= 64).  When the step converges to
+ * x*, pair s is e = x* - x_s, r = A e, z = BJ^{-1} r, rho = RMS(z):
+ * rhat_out[s] = z / rho, target_out[s] = (e - z) / rho (device, nsnap x K x N
+ * FP32, element-major).  ldg_gnn_collected reports how many were taken.
+ */
+ldg_status ldg_gnn_collect(ldg_ctx* ctx, int nsnap, const int32_t* iters, float* rhat_out,
+                           float* target_out);
+ldg_status ldg_gnn_collected(ldg_ctx* ctx, int* n);
 
 #ifdef __cplusplus
 }

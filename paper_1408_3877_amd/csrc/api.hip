@@ -46,6 +46,22 @@ struct ldg_ctx {
   int mmax = 0;
   double t = 0.0;
   bool blocks_ready = false;
+  // graph-network preconditioner
+  float *gP = nullptr, *gGrad = nullptr, *gM = nullptr, *gV = nullptr;
+  int64_t gnP = 0;
+  bool gnn_params_set = false, gnn_alloc_inf = false, gnn_alloc_train = false;
+  int gstep = 0;
+  float *gnode = nullptr, *gedge = nullptr, *g_rhat = nullptr, *g_out = nullptr, *g_tgt = nullptr;
+  GnnActs gA;          // inference activations (two buffers alternate)
+  GnnActs gT;          // training activations (all kept)
+  GnnScratch gS;
+  double* g_loss = nullptr;
+  double meanA = 0.0;
+  // collection of (r, e) pairs from the FP64 CG solve of the next step
+  int col_n = 0, col_done = 0, col_taken = 0, col_cap = 0;
+  std::vector<int> col_iters;
+  float *col_rhat = nullptr, *col_tgt = nullptr;
+  double* col_snap = nullptr;
   // kernel timing
   struct Pending { int id; hipEvent_t a, b; double bytes, flops; };
   bool timing = false;
@@ -268,11 +284,23 @@ Level level_lo(ldg_ctx* c, int bt) {
 
 // ---- inner solvers: A d = r at level L, d from zero --------------------------
 // Preconditioned CG.  *not_spd is set when a curvature p^T A p <= 0 appears.
+ldg_status snapshot(ldg_ctx* c, const Level& L, int it) {
+  // iterate X + d of the first FP64 sweep at the requested CG iterations
+  if (c->col_n == 0 || L.vt != VT_F64 || c->col_taken >= c->col_n) return LDG_OK;
+  if (c->col_iters[c->col_taken] != it) return LDG_OK;
+  double* snap = c->col_snap + (size_t)c->col_taken * c->nvec;
+  HIPCHK(c, hipMemcpyAsync(snap, c->X, c->nvec * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  launch_axpy_into64(VT_F64, c->nvec, 1.0, L.d, snap, c->st);
+  c->col_taken += 1;
+  return check_launch(c);
+}
+
 ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
                     bool* not_spd) {
   double* hb = c->host_buf;
   *not_spd = false;
   kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
+  TRY(snapshot(c, L, 0));
   bj_apply(c, L, L.r, L.z, true);
   TRY(fetch(c, c->red.result, 1, hb));
   double rz = hb[0];
@@ -294,6 +322,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     }
     TRY(fetch(c, c->red2.result, 1, hb));
     ++it;
+    TRY(snapshot(c, L, it));
     const double rn = std::sqrt(hb[0]);
     if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
     if (rn <= tol_abs) break;
@@ -378,6 +407,119 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
   return LDG_OK;
 }
 
+// ---- graph-network preconditioner ---------------------------------------------
+ldg_status gnn_alloc(ldg_ctx* c, bool training) {
+  const int64_t nf = c->Kpad * GNN_WIDTH;
+  if (!c->gnn_alloc_inf) {
+    c->gnP = gnn_num_params(c->N);
+    TRY(dalloc(c, &c->gP, c->gnP));
+    TRY(dalloc(c, &c->gnode, c->Kpad * (c->N + 3)));
+    TRY(dalloc(c, &c->gedge, c->Kpad * 3 * GNN_EIN));
+    TRY(dalloc(c, &c->g_rhat, c->nvec));
+    TRY(dalloc(c, &c->g_out, c->nvec));
+    TRY(dalloc(c, &c->g_tgt, c->nvec));
+    float* hb0 = nullptr;
+    float* hb1 = nullptr;
+    TRY(dalloc(c, &hb0, nf));
+    TRY(dalloc(c, &hb1, nf));
+    c->gA.h[0] = hb0; c->gA.h[1] = hb1; c->gA.h[2] = hb0; c->gA.h[3] = hb1;
+    c->gnn_alloc_inf = true;
+  }
+  if (training && !c->gnn_alloc_train) {
+    TRY(dalloc(c, &c->gGrad, c->gnP));
+    TRY(dalloc(c, &c->gM, c->gnP));
+    TRY(dalloc(c, &c->gV, c->gnP));
+    HIPCHK(c, hipMemsetAsync(c->gM, 0, c->gnP * sizeof(float), c->st));
+    HIPCHK(c, hipMemsetAsync(c->gV, 0, c->gnP * sizeof(float), c->st));
+    TRY(dalloc(c, &c->gT.z0, nf));
+    for (int l = 0; l < 4; ++l) TRY(dalloc(c, &c->gT.h[l], nf));
+    for (int l = 0; l < 3; ++l) {
+      TRY(dalloc(c, &c->gT.a[l], nf));
+      TRY(dalloc(c, &c->gT.u[l], nf));
+    }
+    TRY(dalloc(c, &c->gS.dh[0], nf));
+    TRY(dalloc(c, &c->gS.dh[1], nf));
+    TRY(dalloc(c, &c->gS.dhpart, nf));
+    TRY(dalloc(c, &c->gS.da, nf));
+    TRY(dalloc(c, &c->gS.rowA, (size_t)3 * c->K * (2 * GNN_WIDTH + 1)));
+    TRY(dalloc(c, &c->gS.rowB, (size_t)3 * c->K * GNN_WIDTH));
+    TRY(dalloc(c, &c->gS.partials, gnn_partials_size(c->K)));
+    TRY(dalloc(c, &c->g_loss, (size_t)(c->Kpad / 256 + 2)));
+    c->gnn_alloc_train = true;
+  }
+  return LDG_OK;
+}
+
+// z = BJ^{-1} r + rho g(BJ^{-1} r / rho), rho = RMS of BJ^{-1} r  (FP32 network)
+ldg_status gnn_precond(ldg_ctx* c, const Level& L, const void* r, void* z) {
+  bj_apply(c, L, r, z, false);
+  double nz = 0.0;
+  TRY(norm2(c, L, z, &nz));
+  const double rho = std::sqrt(nz / ((double)c->K * c->N));
+  if (!(rho > 0.0)) return LDG_OK;
+  const int64_t n = c->nvec;
+  Timed tm(c, LDG_K_GNN, 0.0, 0.0);
+  launch_cast(L.vt, VT_F32, n, 1.0 / rho, z, c->g_rhat, c->st);
+  launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gA, c->g_out, c->st);
+  if (L.vt == VT_F64)
+    launch_axpy_into64(VT_F32, n, rho, c->g_out, static_cast<double*>(z), c->st);
+  else
+    launch_axpby(VT_F32, n, rho, c->g_out, 1.0, z, c->st);
+  return check_launch(c);
+}
+
+// Flexible CG (one-step A-orthogonalisation) with the learned preconditioner;
+// *broke is set when a curvature or <r, z> <= 0 appears.
+ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
+                     bool* broke) {
+  double* hb = c->host_buf;
+  *broke = false;
+  kaxpby(c, L, 0.0, L.r, 0.0, L.d);
+  TRY(gnn_precond(c, L, L.r, L.z));
+  kdots(c, L, 1, L.r, L.z);
+  TRY(fetch(c, c->red.result, 1, hb));
+  double rz = hb[0];
+  kaxpby(c, L, 1.0, L.z, 0.0, L.p);
+  kdots(c, L, 0, nullptr, L.r);
+  TRY(fetch(c, c->red.result, 1, hb));
+  const double r0 = std::sqrt(hb[0]);
+  int it = 0;
+  while (it < maxit) {
+    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q);
+    kdots(c, L, 1, L.p, L.q);
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double pq = hb[0];
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      *broke = true;
+      break;
+    }
+    const double alpha = rz / pq;
+    {
+      Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
+      launch_cg_update(L.vt, c->red2, c->nvec, alpha, L.p, L.q, L.d, L.r, c->st);
+    }
+    TRY(fetch(c, c->red2.result, 1, hb));
+    ++it;
+    const double rn = std::sqrt(hb[0]);
+    if (!std::isfinite(rn) || (it >= 20 && rn > 0.5 * r0)) {   // breakdown or stagnation
+      *broke = true;
+      break;
+    }
+    if (rn <= tol_abs) break;
+    TRY(gnn_precond(c, L, L.r, L.z));
+    kdots(c, L, 1, L.r, L.z);
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double rz_new = hb[0];
+    kdots(c, L, 1, L.z, L.q);
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double beta = -hb[0] / pq;
+    rz = rz_new;
+    kaxpby(c, L, 1.0, L.z, beta, L.p);
+  }
+  *iters = it;
+  return LDG_OK;
+}
+
 // ---- the step's solve: FP64 refinement around the inner solver ---------------
 // Unknown C of the eliminated system, residual r = b3 - F(C) with
 // F(C) = M C + tau(eta S' C + sum_m B^m Z^m(C)), Z^m(C) = -M^{-1}(A^m C + J^m_D):
@@ -397,6 +539,10 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   int iters = 0, sweeps = 0;
   double beta = 0.0, beta_prev = 0.0;
   bool cg_mode = use_cg;
+  // the learned preconditioner runs inside flexible CG (SPD case); for GMRES
+  // problems it is not used and the step counts one fallback
+  bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode;
+  if (c->opt.precond == LDG_PC_GNN && !cg_mode) info->fallbacks += 1;
   info->krylov = cg_mode ? LDG_KRYLOV_CG : LDG_KRYLOV_GMRES;
   while (true) {
     apply_op(c, L64, tau, c->X, true, c->tZ1, c->tZ2, c->w);
@@ -429,7 +575,14 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       HIPCHK(c, hipMemcpyAsync(L.r, c->w, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
       scale = 1.0;
       const int left = c->opt.max_iters - iters;
-      if (cg_mode) {
+      if (cg_mode && gnn_on) {
+        bool broke = false;
+        TRY(inner_fcg(c, L, tau, 0.9 * target, left, &it, &broke));
+        if (broke) {   // the learned preconditioner failed: block-Jacobi from here on
+          info->fallbacks += 1;
+          gnn_on = false;
+        }
+      } else if (cg_mode) {
         bool not_spd = false;
         TRY(inner_cg(c, L, tau, 0.9 * target, left, &it, &not_spd));
         if (not_spd) {
@@ -447,7 +600,14 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       scale = beta;
       const double tol = std::max(c->opt.inner_rtol, 0.5 * target / beta);
       const int left = c->opt.max_iters - iters;
-      if (cg_mode) {
+      if (cg_mode && gnn_on) {
+        bool broke = false;
+        TRY(inner_fcg(c, L, tau, tol, left, &it, &broke));
+        if (broke) {
+          info->fallbacks += 1;
+          gnn_on = false;
+        }
+      } else if (cg_mode) {
         bool not_spd = false;
         TRY(inner_cg(c, L, tau, tol, left, &it, &not_spd));
         if (not_spd) {
@@ -502,6 +662,35 @@ ldg_status coefficient_is_elementwise_constant(ldg_ctx* c, bool* yes) {
   return LDG_OK;
 }
 
+// (r, e) pairs from the snapshots x_s of the solve just finished (x* = X):
+//   e = x* - x_s, r = A e, z = BJ^{-1} r, rho = RMS(z),
+//   r_hat = z / rho, target = (e - z) / rho  ->  caller buffers, element-major
+ldg_status finish_collect(ldg_ctx* c, double tau) {
+  const int64_t n = c->nvec;
+  const Level L = level64(c);
+  const int64_t KN = c->K * c->N;
+  for (int s = 0; s < c->col_taken; ++s) {
+    const double* snap = c->col_snap + (size_t)s * n;
+    launch_axpby(VT_F64, n, -1.0, snap, 0.0, c->u2, c->st);
+    launch_axpby(VT_F64, n, 1.0, c->X, 1.0, c->u2, c->st);                // e
+    apply_op(c, L, tau, c->u2, false, c->iz1, c->iz2, c->w);               // r = A e
+    bj_apply(c, L, c->w, c->z, false);                                     // z = BJ^{-1} r
+    double nz = 0.0;
+    TRY(norm2(c, L, c->z, &nz));
+    const double rho = std::sqrt(nz / ((double)c->K * c->N));
+    const double ir = rho > 0.0 ? 1.0 / rho : 0.0;
+    launch_cast(VT_F64, VT_F32, n, ir, c->z, c->g_rhat, c->st);
+    launch_axpby(VT_F64, n, -1.0, c->z, 1.0, c->u2, c->st);               // e - z
+    launch_cast(VT_F64, VT_F32, n, ir, c->u2, c->g_tgt, c->st);
+    launch_from_tiled_f(c->K, c->N, c->g_rhat, c->col_rhat + (size_t)s * KN, c->st);
+    launch_from_tiled_f(c->K, c->N, c->g_tgt, c->col_tgt + (size_t)s * KN, c->st);
+  }
+  c->col_done = c->col_taken;
+  c->col_n = 0;
+  TRY(check_launch(c));
+  return sync(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -546,7 +735,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (opt->precision < LDG_FP64 || opt->precision > LDG_MIXED_BF16) return LDG_EINVAL;
   if (opt->precision != LDG_FP64 && !(opt->inner_rtol > 0.0 && opt->inner_rtol < 1.0))
     return LDG_EINVAL;
-  if (opt->precond != LDG_PC_BLOCK_JACOBI) return LDG_EUNSUPPORTED;
+  if (opt->precond != LDG_PC_BLOCK_JACOBI && opt->precond != LDG_PC_GNN) return LDG_EINVAL;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
   c->opt = *opt;
@@ -606,6 +795,11 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(upload(c, c->belem, hm.belem));
   TRY(upload(c, c->bk, hm.bedge_k));
   TRY(upload(c, c->bn, hm.bedge_n));
+  {
+    double sa = 0.0;
+    for (int64_t k = 0; k < c->K; ++k) sa += 0.5 * hm.area2[k];
+    c->meanA = sa / (double)c->K;
+  }
   c->geo = Geo{c->K, c->Kpad, c->area2, c->B, c->a1, c->elen, c->nu, c->nbr, c->nbrn, c->kind, c->bidx};
   // reference data
   std::vector<double> refs(14 * NN);
@@ -901,6 +1095,10 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
     launch_boundary(c->N, c->geo, c->nbe, c->belem, c->R1, c->Wb, c->ws, cD, gN, c->nbnd, c->D,
                     c->opt.eta, c->J1, c->J2, c->KDN, c->st);
   }
+  if (c->opt.precond == LDG_PC_GNN) {
+    if (!c->gnn_params_set) return fail(c, LDG_EINVAL, "learned preconditioner without parameters");
+    launch_gnn_features(c->N, c->geo, c->D, dt, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
+  }
   // a2, a3: D-dependent blocks
   {
     const double NN = (double)c->NN;
@@ -926,9 +1124,14 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
   HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->col_taken = 0;
   ldg_status s = solve_step(c, tau, bnorm > 0.0 ? bnorm : 1.0, use_cg, info);
   info->t = c->t;
-  if (s != LDG_OK) return s;
+  if (s != LDG_OK) {
+    c->col_n = 0;
+    return s;
+  }
+  if (c->col_n > 0) TRY(finish_collect(c, tau));
   // a10: accept; Z from the last residual evaluation of X
   HIPCHK(c, hipMemcpyAsync(c->C, c->X, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->Z1, c->tZ1, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
@@ -937,6 +1140,120 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   info->t = c->t;
   TRY(check_launch(c));
   return sync(c);
+}
+
+ldg_status ldg_gnn_num_params(ldg_ctx* c, int64_t* n) {
+  if (!c || !n) return LDG_EINVAL;
+  *n = gnn_num_params(c->N);
+  return LDG_OK;
+}
+
+ldg_status ldg_gnn_set_params(ldg_ctx* c, const float* w, int64_t n) {
+  if (!c || !w || n != gnn_num_params(c->N)) return fail(c, LDG_EINVAL, "parameter count");
+  TRY(gnn_alloc(c, false));
+  HIPCHK(c, hipMemcpyAsync(c->gP, w, n * sizeof(float), hipMemcpyHostToDevice, c->st));
+  if (c->gnn_alloc_train) {
+    HIPCHK(c, hipMemsetAsync(c->gM, 0, n * sizeof(float), c->st));
+    HIPCHK(c, hipMemsetAsync(c->gV, 0, n * sizeof(float), c->st));
+  }
+  c->gstep = 0;
+  c->gnn_params_set = true;
+  return sync(c);
+}
+
+ldg_status ldg_gnn_get_params(ldg_ctx* c, float* w, int64_t n) {
+  if (!c || !w || n != gnn_num_params(c->N) || !c->gnn_params_set)
+    return fail(c, LDG_EINVAL, "parameter count or no parameters");
+  HIPCHK(c, hipMemcpyAsync(w, c->gP, n * sizeof(float), hipMemcpyDeviceToHost, c->st));
+  return sync(c);
+}
+
+ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
+  if (!c || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(gnn_alloc(c, false));
+  if (Dem) launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
+  launch_gnn_features(c->N, c->geo, c->D, dt, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_gnn_forward(ldg_ctx* c, const float* rhat, float* out) {
+  if (!c || !rhat || !out || !c->gnn_params_set) return fail(c, LDG_EINVAL, "bad arguments");
+  launch_to_tiled_f(c->K, c->Kpad, c->N, rhat, c->g_rhat, c->st);
+  {
+    Timed tm(c, LDG_K_GNN, 0.0, 0.0);
+    launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gA, c->g_out, c->st);
+  }
+  launch_from_tiled_f(c->K, c->N, c->g_out, out, c->st);
+  return check_launch(c);
+}
+
+namespace {
+ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
+  Timed tm(c, LDG_K_GNN, 0.0, 0.0);
+  launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gT, c->g_out, c->st);
+  launch_gnn_backward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->g_tgt, c->gT, c->g_out,
+                      c->gS, c->gGrad, c->g_loss, c->st);
+  const int nb = (int)((c->Kpad + 255) / 256);
+  reduce_partials(nb, c->g_loss, c->g_loss + nb, c->st);
+  TRY(check_launch(c));
+  TRY(fetch(c, c->g_loss + nb, 1, c->host_buf));
+  *loss = c->host_buf[0] / ((double)c->K * c->N);
+  return LDG_OK;
+}
+}  // namespace
+
+ldg_status ldg_gnn_loss_grad(ldg_ctx* c, const float* rhat, const float* target, float* grad,
+                             double* loss) {
+  if (!c || !rhat || !target || !loss || !c->gnn_params_set)
+    return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(gnn_alloc(c, true));
+  launch_to_tiled_f(c->K, c->Kpad, c->N, rhat, c->g_rhat, c->st);
+  launch_to_tiled_f(c->K, c->Kpad, c->N, target, c->g_tgt, c->st);
+  TRY(gnn_loss_grad_tiled(c, loss));
+  if (grad)
+    HIPCHK(c, hipMemcpyAsync(grad, c->gGrad, c->gnP * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+  return sync(c);
+}
+
+ldg_status ldg_gnn_train_step(ldg_ctx* c, const float* rhat, const float* target, double lr,
+                              double* loss) {
+  if (!c || !rhat || !target || !loss || !c->gnn_params_set || !(lr > 0.0))
+    return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(gnn_alloc(c, true));
+  launch_to_tiled_f(c->K, c->Kpad, c->N, rhat, c->g_rhat, c->st);
+  launch_to_tiled_f(c->K, c->Kpad, c->N, target, c->g_tgt, c->st);
+  TRY(gnn_loss_grad_tiled(c, loss));
+  c->gstep += 1;
+  launch_adam(c->gnP, c->gP, c->gGrad, c->gM, c->gV, (float)lr, c->gstep, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_gnn_collect(ldg_ctx* c, int nsnap, const int32_t* iters, float* rhat_out,
+                           float* target_out) {
+  if (!c || nsnap < 1 || nsnap > 64 || !iters || !rhat_out || !target_out)
+    return fail(c, LDG_EINVAL, "bad arguments");
+  for (int s = 0; s < nsnap; ++s)
+    if (iters[s] < 0 || (s > 0 && iters[s] <= iters[s - 1]))
+      return fail(c, LDG_EINVAL, "snapshot iterations must increase");
+  TRY(gnn_alloc(c, false));
+  if (c->col_cap < nsnap) {   // snapshot slots are kept until the context is destroyed
+    double* p = nullptr;
+    TRY(dalloc(c, &p, (size_t)nsnap * c->nvec));
+    c->col_snap = p;
+    c->col_cap = nsnap;
+  }
+  c->col_iters.assign(iters, iters + nsnap);
+  c->col_n = nsnap;
+  c->col_done = 0;
+  c->col_rhat = rhat_out;
+  c->col_tgt = target_out;
+  return LDG_OK;
+}
+
+ldg_status ldg_gnn_collected(ldg_ctx* c, int* n) {
+  if (!c || !n) return LDG_EINVAL;
+  *n = c->col_done;
+  return LDG_OK;
 }
 
 ldg_status ldg_set_timing(ldg_ctx* c, int on) {

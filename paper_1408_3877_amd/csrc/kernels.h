@@ -50,6 +50,41 @@ void launch_sample_bnd(const Geo& g, int R1, const double* s, int64_t nbnd, cons
                        const int8_t* bn, int kind, double t, double* cD, double* gN, double* xo,
                        double* yo, hipStream_t st);
 
+// kernels_gnn.hip: graph-network preconditioner (FP32)
+constexpr int GNN_WIDTH = 32;
+constexpr int GNN_EIN = 13;
+struct GnnActs {
+  float* z0 = nullptr;                      // encoder pre-activation (training only)
+  float* h[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* a[3] = {nullptr, nullptr, nullptr};  // aggregated messages (training only)
+  float* u[3] = {nullptr, nullptr, nullptr};  // update pre-activations (training only)
+};
+struct GnnScratch {
+  float* dh[2] = {nullptr, nullptr};
+  float* dhpart = nullptr;
+  float* da = nullptr;
+  float* rowA = nullptr;      // 3K x (W + EIN + 1) at most
+  float* rowB = nullptr;      // 3K x W at most
+  double* partials = nullptr; // gnn_partials_size(K)
+};
+int64_t gnn_num_params(int N);
+int64_t gnn_off_layer(int N, int l);
+int64_t gnn_off_dec(int N);
+size_t gnn_partials_size(int64_t K);
+void launch_gnn_features(int N, const Geo& g, const double* D, double dt, double eta, double meanA,
+                         float* node, float* edge, hipStream_t st);
+void launch_gnn_forward(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                        const float* rhat, GnnActs& A, float* out, hipStream_t st);
+// gradient of mean (out - target)^2 into grad; loss_partials[b] = sums of squares per block
+void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                         const float* rhat, const float* target, const GnnActs& A, const float* out,
+                         GnnScratch& S, float* grad, double* loss_partials, hipStream_t st);
+void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr, int step,
+                 hipStream_t st);
+void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,
+                       hipStream_t st);
+void launch_from_tiled_f(int64_t K, int N, const float* src, float* dst, hipStream_t st);
+
 // Krylov vector kernels (kernels_krylov.hip); n = vector length, V = basis
 // with vectors at V + j*ldv; vt selects the vector storage type.  Inner
 // products accumulate in FP64; reductions are two-stage and fixed-order.

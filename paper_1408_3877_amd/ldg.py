@@ -40,7 +40,7 @@ class KernelStat(C.Structure):
                 ("flops", C.c_double)]
 
 
-KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project"]
+KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn"]
 
 
 class StepInfo(C.Structure):
@@ -72,6 +72,15 @@ _SIGS = {
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
     "ldg_get_bj": [_P, _P],
+    "ldg_gnn_num_params": [_P, C.POINTER(C.c_int64)],
+    "ldg_gnn_set_params": [_P, _P, C.c_int64],
+    "ldg_gnn_get_params": [_P, _P, C.c_int64],
+    "ldg_gnn_set_context": [_P, _P, C.c_double],
+    "ldg_gnn_forward": [_P, _P, _P],
+    "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
+    "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
+    "ldg_gnn_collect": [_P, C.c_int, _P, _P, _P],
+    "ldg_gnn_collected": [_P, C.POINTER(C.c_int)],
     "ldg_set_timing": [_P, C.c_int],
     "ldg_get_kernel_stat": [_P, C.c_int, C.POINTER(KernelStat)],
     "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, _P, _P, _P, _P, _P],
@@ -256,6 +265,64 @@ class Solver:
         out = self._empty(self.K, self.N, self.N)
         self._check(self.lib.ldg_get_bj(self.h, _ptr(out)))
         return out
+
+    # -- learned preconditioner ------------------------------------------------
+    def gnn_num_params(self):
+        n = C.c_int64()
+        self._check(self.lib.ldg_gnn_num_params(self.h, C.byref(n)))
+        return n.value
+
+    def gnn_set_params(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.lib.ldg_gnn_set_params(self.h, w.ctypes.data, w.size))
+
+    def gnn_get_params(self):
+        w = np.zeros(self.gnn_num_params(), dtype=np.float32)
+        self._check(self.lib.ldg_gnn_get_params(self.h, w.ctypes.data, w.size))
+        return w
+
+    def gnn_set_context(self, D, dt):
+        Dd = None if D is None else self._dev(D, (self.K, self.N))
+        self._check(self.lib.ldg_gnn_set_context(self.h, _ptr(Dd), float(dt)))
+
+    def _f32(self, x):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(np.asarray(x, dtype=np.float32))
+        return x.to(device=self.device, dtype=t.float32).contiguous()
+
+    def gnn_forward(self, rhat):
+        r = self._f32(rhat)
+        out = self.torch.empty_like(r)
+        self._check(self.lib.ldg_gnn_forward(self.h, _ptr(r), _ptr(out)))
+        return out
+
+    def gnn_loss_grad(self, rhat, target):
+        r, t = self._f32(rhat), self._f32(target)
+        g = self.torch.empty(self.gnn_num_params(), dtype=self.torch.float32, device=self.device)
+        loss = C.c_double()
+        self._check(self.lib.ldg_gnn_loss_grad(self.h, _ptr(r), _ptr(t), _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def gnn_train_step(self, rhat, target, lr):
+        r, t = self._f32(rhat), self._f32(target)   # keep both alive across the call
+        loss = C.c_double()
+        self._check(self.lib.ldg_gnn_train_step(self.h, _ptr(r), _ptr(t), float(lr), C.byref(loss)))
+        return loss.value
+
+    def gnn_collect(self, iters):
+        it = np.ascontiguousarray(iters, dtype=np.int32)
+        shape = (len(it), self.K, self.N)
+        r = self.torch.empty(shape, dtype=self.torch.float32, device=self.device)
+        t = self.torch.empty(shape, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.ldg_gnn_collect(self.h, len(it), it.ctypes.data, _ptr(r), _ptr(t)))
+        self._collect_bufs = (r, t)
+        return r, t
+
+    def gnn_collected(self):
+        n = C.c_int()
+        self._check(self.lib.ldg_gnn_collected(self.h, C.byref(n)))
+        return n.value
 
     def set_timing(self, on):
         self._check(self.lib.ldg_set_timing(self.h, int(bool(on))))

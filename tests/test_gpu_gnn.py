@@ -1,0 +1,133 @@
+"""The learned preconditioner on the GPU against the FP64 network oracle.
+
+Forward, loss, gradient and one Adam step match the oracle (FP32 device vs
+FP64 host); training pairs collected from the method's own CG solve satisfy
+BJ^{-1} A (target + r_hat) = r_hat with the oracle's operator; steps with the
+learned preconditioner reach the FP64 tolerance and the oracle's solution,
+and scrambled weights fall back to block-Jacobi.
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import LOGNORMAL, Workload, lognormal_blocks
+from inputs.meshes import NORTH, square_mesh
+from oracle import gnn
+from oracle.ldg import Blocks, Problem, schur_matrix
+from oracle.mesh import Grid
+from oracle.refelem import RefTensors
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, seed, p, **kw):
+    from paper_1408_3877_amd import Solver
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(NORTH,))
+    g = Grid(cV, V0T, kind)
+    N = (p + 1) * (p + 2) // 2
+    rng = np.random.default_rng(seed)
+    D = np.zeros((g.numT, N))
+    D[:, 0] = np.exp(rng.standard_normal(g.numT)) / np.sqrt(2)
+    D[:, 1:] = 0.05 * rng.standard_normal((g.numT, N - 1)) * D[:, :1]
+    s = Solver(cV, V0T, kind, p, **kw)
+    return (cV, V0T, kind), g, D, s, rng
+
+
+def _theta32(N, seed, rng):
+    th = gnn.init_params(N, seed) + 0.02 * rng.standard_normal(gnn.n_params(N))
+    return th.astype(np.float32)
+
+
+@pytest.mark.parametrize("n,seed,p", [(9, 601, 2), (5, 602, 4)])
+def test_forward_loss_gradient_adam(n, seed, p):
+    mesh, g, D, s, rng = _setup(n, seed, p)
+    N = s.N
+    assert s.gnn_num_params() == gnn.n_params(N)
+    th = _theta32(N, seed, rng)
+    s.gnn_set_params(th)
+    np.testing.assert_array_equal(s.gnn_get_params(), th)
+    dt = 1e-3
+    s.gnn_set_context(D, dt)
+    node, edge = gnn.features(g, D, dt, 1.0)
+    rhat = rng.standard_normal((g.numT, N)).astype(np.float32)
+    tgt = rng.standard_normal((g.numT, N)).astype(np.float32)
+    th64 = th.astype(np.float64)
+    want = gnn.forward(th64, g, node, edge, rhat.astype(np.float64))
+    got = to_np(s.gnn_forward(rhat))
+    assert np.abs(got - want).max() <= 2e-4 * np.abs(want).max()
+    L, G = gnn.loss_grad(th64, g, node, edge, rhat.astype(np.float64), tgt.astype(np.float64))
+    Lg, Gg = s.gnn_loss_grad(rhat, tgt)
+    Gg = to_np(Gg)
+    assert abs(Lg - L) <= 1e-5 * L
+    assert np.linalg.norm(Gg - G) <= 2e-4 * np.linalg.norm(G)
+    # first Adam step: lr * g / (|g| + eps) on every well-resolved component
+    lr = 1e-3
+    s.gnn_train_step(rhat, tgt, lr)
+    th1 = s.gnn_get_params().astype(np.float64)
+    want1, _, _ = gnn.adam_step(th64, G, np.zeros_like(G), np.zeros_like(G), 1, lr)
+    big = np.abs(G) > 1e-2 * np.abs(G).max()   # sign(g) steps: away from FP32 noise
+    assert np.abs(th1 - want1)[big].max() <= 1e-5
+
+
+def test_collected_pairs_satisfy_the_operator():
+    n, p, dt = 8, 2, 0.05
+    cV, V0T, kind = square_mesh(n, seed=611)
+    w = Workload(LOGNORMAL, n_cells=n, blocks=lognormal_blocks(n, 612, 1.5, block=4), block=4)
+    from paper_1408_3877_amd import Solver
+    s = Solver(cV, V0T, kind, p, rtol=1e-12, max_iters=20000)
+    s.set_initial_samples(s.sample_workload(3, 0.0, dT=w.dT, want=("c0",))["c0"])
+    iters = [0, 2, 6]
+    rh, tg = s.gnn_collect(iters)
+    smp = s.sample_workload(3, dt, dT=w.dT)
+    info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+    assert info["krylov"] == 2 and s.gnn_collected() == len(iters)
+    pr = Problem(cV, V0T, kind, p)
+    data = pr.data(w, dt)
+    S = schur_matrix(Blocks(pr.grid, pr.refs, data["D"]), pr.grid, pr.refs, 1.0, dt).toarray()
+    K, N = pr.grid.numT, pr.N
+    Sb = np.zeros_like(S)
+    for k in range(K):
+        sl = slice(k * N, (k + 1) * N)
+        Sb[sl, sl] = np.linalg.inv(S[sl, sl])
+    C0 = pr.initial(w)
+    C1, _, _, _ = pr.step(C0, dt, dt, w)
+    for q in range(len(iters)):
+        r_hat = to_np(rh[q]).astype(np.float64).reshape(-1)
+        e_dir = (to_np(tg[q]).astype(np.float64) + to_np(rh[q]).astype(np.float64)).reshape(-1)
+        # BJ^{-1} S e = r_hat, scale free
+        lhs = Sb @ (S @ e_dir)
+        assert np.linalg.norm(lhs - r_hat) <= 1e-5 * np.linalg.norm(r_hat)
+        assert abs(np.sqrt(np.mean(r_hat ** 2)) - 1.0) < 1e-5
+    # the first pair is the step increment C^{n+1} - C^n (direction)
+    inc = (C1 - C0).reshape(-1)
+    e0 = (to_np(tg[0]) + to_np(rh[0])).astype(np.float64).reshape(-1)
+    cos = inc @ e0 / (np.linalg.norm(inc) * np.linalg.norm(e0))
+    assert cos > 1 - 1e-8
+
+
+@pytest.mark.parametrize("scramble", [False, True])
+def test_learned_preconditioner_steps(scramble):
+    n, p, dt = 9, 3, 0.02
+    cV, V0T, kind = square_mesh(n, seed=621)
+    w = Workload(LOGNORMAL, n_cells=n, blocks=lognormal_blocks(n, 622, 1.5, block=3), block=3)
+    from paper_1408_3877_amd import Solver
+    s = Solver(cV, V0T, kind, p, rtol=1e-13, max_iters=20000, precond=1)
+    rng = np.random.default_rng(623)
+    th = _theta32(s.N, 623, rng)
+    if scramble:
+        th = (th * 1e6).astype(np.float32)
+    s.gnn_set_params(th)
+    s.set_initial_samples(s.sample_workload(3, 0.0, dT=w.dT, want=("c0",))["c0"])
+    pr = Problem(cV, V0T, kind, p)
+    C = pr.initial(w)
+    t, fb = 0.0, 0
+    for _ in range(2):
+        t += dt
+        smp = s.sample_workload(3, t, dT=w.dT)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
+        fb += info["fallbacks"]
+        C, _, _, _ = pr.step(C, t, dt, w)
+        assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
+    if scramble:
+        assert fb >= 1
