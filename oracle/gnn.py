@@ -129,14 +129,37 @@ def loss(theta, grid, node, edge, rhat, target):
     return np.mean((g - target) ** 2)
 
 
+def energy_loss(theta, grid, node, edge, rhat, target, S):
+    """(g - t)^T S (g - t) / (t^T S t): the A-norm error of the corrected step
+    relative to the block-Jacobi step (S the eliminated operator)."""
+    d = (forward(theta, grid, node, edge, rhat) - target).reshape(-1)
+    t = target.reshape(-1)
+    return (d @ (S @ d)) / (t @ (S @ t))
+
+
+def energy_loss_grad(theta, grid, node, edge, rhat, target, S):
+    g = forward(theta, grid, node, edge, rhat)
+    d = (g - target).reshape(-1)
+    t = target.reshape(-1)
+    den = t @ (S @ t)
+    Sd = S @ d
+    dg = (2.0 * Sd / den).reshape(g.shape)      # S symmetric
+    return (d @ Sd) / den, backward(theta, grid, node, edge, rhat, dg)
+
+
 def loss_grad(theta, grid, node, edge, rhat, target):
     """(loss, d loss / d theta) by the chain rule through forward()."""
+    g = forward(theta, grid, node, edge, rhat)
+    L = np.mean((g - target) ** 2)
+    return L, backward(theta, grid, node, edge, rhat, 2.0 * (g - target) / g.size)
+
+
+def backward(theta, grid, node, edge, rhat, dg):
+    """d (loss) / d theta given d loss / d g, by the chain rule through forward()."""
     K, N = rhat.shape
     P = unpack(theta, N)
     g, A = forward(theta, grid, node, edge, rhat, keep=True)
-    L = np.mean((g - target) ** 2)
     G = {k: np.zeros_like(v) for k, v in P.items()}
-    dg = 2.0 * (g - target) / g.size
     h3 = A["h"][LAYERS]
     G["W_dec"] = h3.T @ dg
     G["b_dec"] = dg.sum(0)
@@ -165,7 +188,7 @@ def loss_grad(theta, grid, node, edge, rhat, target):
     dz0 = dh * (A["z0"] > 0)
     G["W_enc"] = A["x"].T @ dz0
     G["b_enc"] = dz0.sum(0)
-    return L, pack(G, N)
+    return pack(G, N)
 
 
 def adam_step(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

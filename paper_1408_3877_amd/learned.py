@@ -1,0 +1,186 @@
+"""Training and evaluation of the learned preconditioner on the method's own systems.
+
+    python -m paper_1408_3877_amd.learned --p 3 --n 256 --sigma 1.5 \
+        --train-seeds 4000-4019 --eval-seeds 4100,4101 --out weights.npy
+
+1. Data: for every training field seed, run implicit Euler steps with plain
+   block-Jacobi CG and keep (BJ^{-1} r / rho, (e - BJ^{-1} r) / rho) pairs from
+   CG iterates (ldg_gnn_collect): the systems and solutions the method itself
+   generates.
+2. Training: Adam on the mean squared error, one system sample per step,
+   on the device (ldg_gnn_train_step).
+3. Evaluation: the same steps on held-out fields with block-Jacobi CG and
+   with the learned preconditioner (flexible CG, block-Jacobi fallback);
+   iterations and time per step for both.
+
+Only argument marshalling and the loop live here; every kernel runs in the
+library.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from inputs.fields import LOGNORMAL, lognormal_blocks, triangle_values  # noqa: E402
+from inputs.meshes import square_mesh  # noqa: E402
+
+SNAPS = [0, 1, 2, 3, 5, 8, 12, 18, 27, 40, 60, 90, 135, 200, 300, 450, 675, 1000, 1500, 2250]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def glorot(N, seed, width=32, e_in=13, layers=3):
+    """Initial parameters in the library's flat layout (Glorot-uniform, zero biases)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+
+    def mat(r, c):
+        lim = np.sqrt(6.0 / (r + c))
+        parts.append(rng.uniform(-lim, lim, r * c))
+
+    mat(2 * N + 3, width)
+    parts.append(np.zeros(width))
+    for _ in range(layers):
+        mat(width, width)
+        mat(e_in, width)
+        parts.append(np.zeros(width))
+        mat(2 * width, width)
+        parts.append(np.zeros(width))
+    mat(width, N)
+    parts.append(np.zeros(N))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def field(n, seed, sigma):
+    return triangle_values(lognormal_blocks(n, seed, sigma, block=8), n, block=8)
+
+
+def collect(solver, n, seeds, sigma, steps, dt, snaps=SNAPS, per_step=None):
+    """(rhat, target, D) triples on the device, from BJ-CG steps of every seed."""
+    torch = solver.torch
+    data = []
+    for sd in seeds:
+        dT = field(n, sd, sigma)
+        solver.set_initial_samples(solver.sample_workload(LOGNORMAL, 0.0, dT=dT, want=("c0",))["c0"])
+        D = solver.project(solver.sample_workload(LOGNORMAL, dt, dT=dT, want=("d",))["d"]).clone()
+        t = 0.0
+        for _ in range(steps):
+            t += dt
+            r, tg = solver.gnn_collect(snaps if per_step is None else snaps[:per_step])
+            smp = solver.sample_workload(LOGNORMAL, t, dT=dT)
+            info = solver.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+            m = solver.gnn_collected()
+            for q in range(m):
+                data.append((r[q].clone(), tg[q].clone(), D))
+            log("[collect] seed %d t=%.1e iters=%d pairs=%d total=%d" % (sd, t, info["iters"], m, len(data)))
+        torch.cuda.synchronize()
+    return data
+
+
+def train(solver, data, epochs, lr, dt, seed):
+    rng = np.random.default_rng(seed)
+    losses = []
+    step = 0
+    total = epochs * len(data)
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        acc = 0.0
+        for i in order:
+            r, tg, D = data[i]
+            solver.gnn_set_context(D, dt)
+            lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / total))   # cosine decay
+            acc += solver.gnn_train_step(r, tg, lr_t)
+            step += 1
+        losses.append(acc / len(data))
+        log("[train] epoch %d mean loss %.5f" % (ep, losses[-1]))
+    return losses
+
+
+def evaluate(solver, n, seeds, sigma, steps, dt, use_gnn):
+    """Mean iterations and seconds per step (block-Jacobi or learned)."""
+    torch = solver.torch
+    its, secs, fbs = [], [], 0
+    for sd in seeds:
+        dT = field(n, sd, sigma)
+        solver.set_initial_samples(solver.sample_workload(LOGNORMAL, 0.0, dT=dT, want=("c0",))["c0"])
+        t = 0.0
+        for _ in range(steps):
+            t += dt
+            smp = solver.sample_workload(LOGNORMAL, t, dT=dT)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = solver.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            its.append(info["iters"])
+            fbs += info["fallbacks"]
+    return {"iters_per_step": float(np.mean(its)), "s_per_step": float(np.mean(secs)),
+            "fallbacks": fbs, "steps": len(its)}
+
+
+def seeds_arg(s):
+    if "-" in s:
+        a, b = s.split("-")
+        return list(range(int(a), int(b) + 1))
+    return [int(x) for x in s.split(",")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--jitter", type=int, default=1004)
+    ap.add_argument("--sigma", type=float, default=1.5)
+    ap.add_argument("--dt", type=float, default=1e-4)
+    ap.add_argument("--train-seeds", default="4000-4019")
+    ap.add_argument("--eval-seeds", default="4100,4101")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--eval-steps", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--init-seed", type=int, default=7)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+    import torch
+
+    from . import Solver
+    coordV, V0T, kind = square_mesh(a.n, seed=a.jitter)
+    torch.cuda.set_device(0)
+    sv = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000)
+    sv.gnn_set_params(glorot(sv.N, a.init_seed))
+    t0 = time.perf_counter()
+    data = collect(sv, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = train(sv, data, a.epochs, a.lr, a.dt, a.init_seed)
+    t_train = time.perf_counter() - t0
+    w = sv.gnn_get_params()
+    if a.out:
+        np.save(a.out, w)
+    ev = evaluate(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, False)
+    sg = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
+    sg.gnn_set_params(w)
+    eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
+    rep = {"p": a.p, "K": sv.K, "samples": len(data), "collect_s": t_collect, "train_s": t_train,
+           "epochs": a.epochs, "loss_per_epoch": losses, "block_jacobi": ev, "learned": eg,
+           "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],
+           "time_ratio": eg["s_per_step"] / ev["s_per_step"]}
+    print(json.dumps(rep), flush=True)
+    if a.report:
+        with open(a.report, "w") as fh:
+            json.dump(rep, fh, indent=1)
+    return rep
+
+
+if __name__ == "__main__":
+    main()

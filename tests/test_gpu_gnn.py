@@ -131,3 +131,15 @@ def test_learned_preconditioner_steps(scramble):
         assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
     if scramble:
         assert fb >= 1
+
+
+def test_training_on_method_systems_reduces_loss_and_reports_gain():
+    # a9 in miniature: collect pairs from BJ-CG steps, train, evaluate against BJ
+    from paper_1408_3877_amd import learned
+    rep = learned.main(["--p", "2", "--n", "16", "--jitter", "631", "--sigma", "1.5",
+                        "--train-seeds", "4000-4003", "--eval-seeds", "4100", "--steps", "2",
+                        "--eval-steps", "2", "--epochs", "3", "--dt", "0.002"])
+    print("[learned] %s" % rep)
+    assert rep["samples"] > 20
+    assert rep["loss_per_epoch"][-1] < rep["loss_per_epoch"][0]
+    assert rep["learned"]["steps"] == rep["block_jacobi"]["steps"] == 2

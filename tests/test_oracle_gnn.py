@@ -61,3 +61,28 @@ def test_adam_first_step_closed_form():
     grad = np.array([0.3, -4.0, 1e-9])
     t2, m, v = gnn.adam_step(theta, grad, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(t2, theta - 0.01 * grad / (np.abs(grad) + 1e-8), rtol=1e-12)
+
+
+def test_energy_loss_gradient_matches_finite_differences():
+    from oracle.ldg import Blocks, schur_matrix
+    from oracle.refelem import RefTensors
+    g, node, edge, rhat, target, theta = _setup(1, seed=5)
+    refs = RefTensors(1)
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = 1.0
+    S = schur_matrix(Blocks(g, refs, D), g, refs, 1.0, 0.01).toarray()
+    L, G = gnn.energy_loss_grad(theta, g, node, edge, rhat, target, S)
+    assert abs(L - gnn.energy_loss(theta, g, node, edge, rhat, target, S)) < 1e-13 * L
+    rng = np.random.default_rng(9)
+    eps = 1e-6
+    worst = 0.0
+    for i in rng.choice(theta.size, 200, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd = (gnn.energy_loss(tp, g, node, edge, rhat, target, S)
+              - gnn.energy_loss(tm, g, node, edge, rhat, target, S)) / (2 * eps)
+        worst = max(worst, abs(fd - G[i]) / max(1e-4, abs(G[i])))
+    assert worst < 1e-5, worst
+    # predicting the target exactly gives zero, predicting zero gives one
+    assert gnn.energy_loss(theta, g, node, edge, rhat, target, S) > 0
