@@ -100,7 +100,23 @@ typedef struct {
   int krylov;          /* ldg_krylov actually used by the step */
   double rel_residual; /* ||b - (W + dt A) Y|| / ||b|| of the full system, FP64 */
   double t;            /* time level reached */
+  int learned_iters;   /* iterations run with the learned preconditioner */
+  int guarded_iters;   /* of those, iterations that took the block-Jacobi direction
+                          because <r, P r> < 0.25 <r, BJ^{-1} r> */
+  int fallback_reason; /* ldg_fallback of the last fallback taken */
 } ldg_step_info;
+
+/*
+ * Why a step left its first solver: a curvature p^T A p <= 0 (CG, flexible
+ * CG), <r, P r> <= 0 with the learned preconditioner, a non-finite residual,
+ * no new residual minimum (by 1%) within 200 flexible-CG iterations, a
+ * nonsymmetric step (the learned preconditioner serves CG only), or a mixed
+ * sweep that failed to halve the residual.
+ */
+typedef enum {
+  LDG_FB_NONE = 0, LDG_FB_CURVATURE = 1, LDG_FB_RZ = 2, LDG_FB_NONFINITE = 3,
+  LDG_FB_STAGNATION = 4, LDG_FB_NONSYMMETRIC = 5, LDG_FB_PRECISION = 6
+} ldg_fallback;
 
 /* Fill *opt with the defaults listed above. */
 ldg_status ldg_options_default(ldg_options* opt);
@@ -278,13 +294,25 @@ ldg_status ldg_gnn_num_params(ldg_ctx* ctx, int64_t* n);
 /* host parameter vector in/out; setting resets the Adam moments */
 ldg_status ldg_gnn_set_params(ldg_ctx* ctx, const float* w, int64_t n);
 ldg_status ldg_gnn_get_params(ldg_ctx* ctx, float* w, int64_t n);
+/*
+ * Training loss.  LDG_GNN_LOSS_MSE (default): mean over (k, i) of
+ * (g_ki - target_ki)^2.  LDG_GNN_LOSS_ENERGY: (g - t)^T S (g - t) / (t^T S t)
+ * with S the eliminated operator of the context (coefficient D, step dt), i.e.
+ * the energy-norm error of the corrected step relative to that of the plain
+ * block-Jacobi step; it needs ldg_gnn_set_context after this call, which then
+ * also assembles the FP64 blocks of D (overwriting the solver's) and returns
+ * LDG_EINVAL unless D is constant on every triangle (S symmetric, the case
+ * the learned preconditioner serves).  Unknown values: LDG_EINVAL.
+ */
+typedef enum { LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1 } ldg_gnn_loss;
+ldg_status ldg_gnn_set_loss(ldg_ctx* ctx, int loss);
 /* per-triangle and per-edge features from D (device K x N, NULL: last projected) and dt */
 ldg_status ldg_gnn_set_context(ldg_ctx* ctx, const double* D, double dt);
 /* g = network(r_hat): r_hat, g device K x N FP32 */
 ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
 /*
- * loss = mean over (k, i) of (g_ki - target_ki)^2 and its gradient (device,
- * n_params floats, may be NULL); the weight gradients are fixed-order FP64
+ * loss (as selected by ldg_gnn_set_loss) and its gradient (device, n_params
+ * floats, may be NULL); the weight gradients are fixed-order FP64
  * reductions.  ldg_gnn_train_step does the same and one Adam step
  * (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
  */

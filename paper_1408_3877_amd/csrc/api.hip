@@ -57,6 +57,12 @@ struct ldg_ctx {
   GnnScratch gS;
   double* g_loss = nullptr;
   double meanA = 0.0;
+  // training loss: LDG_GNN_LOSS_MSE or LDG_GNN_LOSS_ENERGY (the latter needs the
+  // FP64 blocks of the context coefficient and its time step)
+  int gloss = 0;
+  double gtau = 0.0;
+  bool g_energy_ready = false;
+  float* g_dout = nullptr;
   // collection of (r, e) pairs from the FP64 CG solve of the next step
   int col_n = 0, col_done = 0, col_taken = 0, col_cap = 0;
   std::vector<int> col_iters;
@@ -445,14 +451,18 @@ ldg_status gnn_alloc(ldg_ctx* c, bool training) {
     TRY(dalloc(c, &c->gS.rowB, (size_t)3 * c->K * GNN_WIDTH));
     TRY(dalloc(c, &c->gS.partials, gnn_partials_size(c->K)));
     TRY(dalloc(c, &c->g_loss, (size_t)(c->Kpad / 256 + 2)));
+    TRY(dalloc(c, &c->g_dout, c->nvec));
     c->gnn_alloc_train = true;
   }
   return LDG_OK;
 }
 
 // z = BJ^{-1} r + rho g(BJ^{-1} r / rho), rho = RMS of BJ^{-1} r  (FP32 network)
-ldg_status gnn_precond(ldg_ctx* c, const Level& L, const void* r, void* z) {
-  bj_apply(c, L, r, z, false);
+// z = P(r) = BJ^{-1} r + rho g(BJ^{-1} r / rho); *rz_bj = <r, BJ^{-1} r>
+ldg_status gnn_precond(ldg_ctx* c, const Level& L, const void* r, void* z, double* rz_bj) {
+  bj_apply(c, L, r, z, true);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  *rz_bj = c->host_buf[0];
   double nz = 0.0;
   TRY(norm2(c, L, z, &nz));
   const double rho = std::sqrt(nz / ((double)c->K * c->N));
@@ -469,20 +479,41 @@ ldg_status gnn_precond(ldg_ctx* c, const Level& L, const void* r, void* z) {
 }
 
 // Flexible CG (one-step A-orthogonalisation) with the learned preconditioner;
-// *broke is set when a curvature or <r, z> <= 0 appears.
-ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
-                     bool* broke) {
-  double* hb = c->host_buf;
-  *broke = false;
-  kaxpby(c, L, 0.0, L.r, 0.0, L.d);
-  TRY(gnn_precond(c, L, L.r, L.z));
+// *broke is set to an ldg_fallback reason when it has to give up.
+// An iteration whose learned direction gives <r, P r> < FCG_GUARD <r, BJ^{-1} r>
+// takes the block-Jacobi direction instead (*guarded counts them).
+ldg_status fcg_direction(ldg_ctx* c, const Level& L, double* rz, int* guarded) {
+  constexpr double FCG_GUARD = 0.25;
+  double rz_bj = 0.0;
+  TRY(gnn_precond(c, L, L.r, L.z, &rz_bj));
   kdots(c, L, 1, L.r, L.z);
-  TRY(fetch(c, c->red.result, 1, hb));
-  double rz = hb[0];
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  *rz = c->host_buf[0];
+  if (!(*rz >= FCG_GUARD * rz_bj)) {
+    bj_apply(c, L, L.r, L.z, true);
+    TRY(fetch(c, c->red.result, 1, c->host_buf));
+    *rz = c->host_buf[0];
+    *guarded += 1;
+  }
+  return LDG_OK;
+}
+
+ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
+                     int* broke, int* guarded) {
+  double* hb = c->host_buf;
+  *broke = LDG_FB_NONE;
+  kaxpby(c, L, 0.0, L.r, 0.0, L.d);
+  TRY(snapshot(c, L, 0));
+  double rz = 0.0;
+  TRY(fcg_direction(c, L, &rz, guarded));
   kaxpby(c, L, 1.0, L.z, 0.0, L.p);
   kdots(c, L, 0, nullptr, L.r);
   TRY(fetch(c, c->red.result, 1, hb));
-  const double r0 = std::sqrt(hb[0]);
+  // stagnation: no new residual minimum (by 1%) within FCG_PLATEAU iterations;
+  // CG residual norms oscillate, so a fixed early reduction is not asked for
+  constexpr int FCG_PLATEAU = 200;
+  double best = std::sqrt(hb[0]);
+  int it_best = 0;
   int it = 0;
   while (it < maxit) {
     apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q);
@@ -490,7 +521,7 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
     TRY(fetch(c, c->red.result, 1, hb));
     const double pq = hb[0];
     if (!(pq > 0.0) || !(rz > 0.0)) {
-      *broke = true;
+      *broke = !(pq > 0.0) ? LDG_FB_CURVATURE : LDG_FB_RZ;
       break;
     }
     const double alpha = rz / pq;
@@ -500,16 +531,23 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
     }
     TRY(fetch(c, c->red2.result, 1, hb));
     ++it;
+    TRY(snapshot(c, L, it));
     const double rn = std::sqrt(hb[0]);
-    if (!std::isfinite(rn) || (it >= 20 && rn > 0.5 * r0)) {   // breakdown or stagnation
-      *broke = true;
+    if (rn < 0.99 * best) {
+      best = rn;
+      it_best = it;
+    }
+    if (!std::isfinite(rn)) {
+      *broke = LDG_FB_NONFINITE;
+      break;
+    }
+    if (it - it_best > FCG_PLATEAU) {
+      *broke = LDG_FB_STAGNATION;
       break;
     }
     if (rn <= tol_abs) break;
-    TRY(gnn_precond(c, L, L.r, L.z));
-    kdots(c, L, 1, L.r, L.z);
-    TRY(fetch(c, c->red.result, 1, hb));
-    const double rz_new = hb[0];
+    double rz_new = 0.0;
+    TRY(fcg_direction(c, L, &rz_new, guarded));
     kdots(c, L, 1, L.z, L.q);
     TRY(fetch(c, c->red.result, 1, hb));
     const double beta = -hb[0] / pq;
@@ -542,7 +580,10 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   // the learned preconditioner runs inside flexible CG (SPD case); for GMRES
   // problems it is not used and the step counts one fallback
   bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode;
-  if (c->opt.precond == LDG_PC_GNN && !cg_mode) info->fallbacks += 1;
+  if (c->opt.precond == LDG_PC_GNN && !cg_mode) {
+    info->fallbacks += 1;
+    info->fallback_reason = LDG_FB_NONSYMMETRIC;
+  }
   info->krylov = cg_mode ? LDG_KRYLOV_CG : LDG_KRYLOV_GMRES;
   while (true) {
     apply_op(c, L64, tau, c->X, true, c->tZ1, c->tZ2, c->w);
@@ -557,6 +598,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
     if (L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev) {
       // refinement stagnates at this precision: BF16 -> FP32 -> FP64
       info->fallbacks += 1;
+      info->fallback_reason = LDG_FB_PRECISION;
       if (L.bt == BT_BF16) {
         if (!c->blocks_f32_ready) {
           launch_convert_blocks(BT_F32, c->Kpad, c->N, NSLOT, c->blocks, c->blocks_f32, c->st);
@@ -576,10 +618,12 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       scale = 1.0;
       const int left = c->opt.max_iters - iters;
       if (cg_mode && gnn_on) {
-        bool broke = false;
-        TRY(inner_fcg(c, L, tau, 0.9 * target, left, &it, &broke));
-        if (broke) {   // the learned preconditioner failed: block-Jacobi from here on
+        int broke = LDG_FB_NONE;
+        TRY(inner_fcg(c, L, tau, 0.9 * target, left, &it, &broke, &info->guarded_iters));
+        info->learned_iters += it;
+        if (broke != LDG_FB_NONE) {   // the learned preconditioner failed: block-Jacobi from here on
           info->fallbacks += 1;
+          info->fallback_reason = broke;
           gnn_on = false;
         }
       } else if (cg_mode) {
@@ -587,6 +631,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
         TRY(inner_cg(c, L, tau, 0.9 * target, left, &it, &not_spd));
         if (not_spd) {
           info->fallbacks += 1;
+          info->fallback_reason = LDG_FB_CURVATURE;
           cg_mode = false;
           info->krylov = LDG_KRYLOV_GMRES;
         }
@@ -601,10 +646,12 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       const double tol = std::max(c->opt.inner_rtol, 0.5 * target / beta);
       const int left = c->opt.max_iters - iters;
       if (cg_mode && gnn_on) {
-        bool broke = false;
-        TRY(inner_fcg(c, L, tau, tol, left, &it, &broke));
-        if (broke) {
+        int broke = LDG_FB_NONE;
+        TRY(inner_fcg(c, L, tau, tol, left, &it, &broke, &info->guarded_iters));
+        info->learned_iters += it;
+        if (broke != LDG_FB_NONE) {
           info->fallbacks += 1;
+          info->fallback_reason = broke;
           gnn_on = false;
         }
       } else if (cg_mode) {
@@ -612,6 +659,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
         TRY(inner_cg(c, L, tau, tol, left, &it, &not_spd));
         if (not_spd) {
           info->fallbacks += 1;
+          info->fallback_reason = LDG_FB_CURVATURE;
           cg_mode = false;
           info->krylov = LDG_KRYLOV_GMRES;
         }
@@ -1173,7 +1221,25 @@ ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
   TRY(gnn_alloc(c, false));
   if (Dem) launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
   launch_gnn_features(c->N, c->geo, c->D, dt, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
+  if (c->gloss == LDG_GNN_LOSS_ENERGY) {
+    // the energy gradient 2 S (g - t) / (t^T S t) needs S symmetric: d constant per triangle
+    bool sym = false;
+    TRY(coefficient_is_elementwise_constant(c, &sym));
+    if (!sym) return fail(c, LDG_EINVAL, "energy loss needs a coefficient constant per triangle");
+    launch_assemble_mfma(c->N, BT_F64, c->geo, c->D, c->Tm64, c->blocks, c->st);
+    c->blocks_ready = true;
+    c->gtau = dt;
+    c->g_energy_ready = true;
+  }
   return check_launch(c);
+}
+
+ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
+  if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY))
+    return fail(c, LDG_EINVAL, "unknown loss");
+  c->gloss = loss;
+  c->g_energy_ready = false;
+  return LDG_OK;
 }
 
 ldg_status ldg_gnn_forward(ldg_ctx* c, const float* rhat, float* out) {
@@ -1188,11 +1254,45 @@ ldg_status ldg_gnn_forward(ldg_ctx* c, const float* rhat, float* out) {
 }
 
 namespace {
+// Energy loss  L = (g - t)^T S (g - t) / (t^T S t)  with S the eliminated
+// operator of the context (symmetric in the case the learned preconditioner
+// serves), so dL/dg = 2 S (g - t) / (t^T S t).  FP64 vectors r, z, w, u are free
+// outside a step.
+ldg_status gnn_energy_dout(ldg_ctx* c, double* loss) {
+  if (!c->g_energy_ready)
+    return fail(c, LDG_EINVAL, "energy loss needs ldg_gnn_set_context after ldg_gnn_set_loss");
+  const Level L = level64(c);
+  const int64_t n = c->nvec;
+  launch_cast(VT_F32, VT_F64, n, 1.0, c->g_out, c->r, c->st);
+  launch_axpy_into64(VT_F32, n, -1.0, c->g_tgt, c->r, c->st);
+  launch_cast(VT_F32, VT_F64, n, 1.0, c->g_tgt, c->z, c->st);
+  apply_op(c, L, c->gtau, c->r, false, L.tz1, L.tz2, c->w);
+  apply_op(c, L, c->gtau, c->z, false, L.tz1, L.tz2, c->u);
+  double num = 0.0, den = 0.0;
+  kdots(c, L, 1, c->r, c->w);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  num = c->host_buf[0];
+  kdots(c, L, 1, c->z, c->u);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  den = c->host_buf[0];
+  if (!(den > 0.0) || !std::isfinite(num))
+    return fail(c, LDG_ENOCONV, "energy loss: target has no positive energy");
+  launch_cast(VT_F64, VT_F32, n, 2.0 / den, c->w, c->g_dout, c->st);
+  *loss = num / den;
+  return LDG_OK;
+}
+
 ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
   Timed tm(c, LDG_K_GNN, 0.0, 0.0);
   launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gT, c->g_out, c->st);
-  launch_gnn_backward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->g_tgt, c->gT, c->g_out,
-                      c->gS, c->gGrad, c->g_loss, c->st);
+  if (c->gloss == LDG_GNN_LOSS_ENERGY) {
+    TRY(gnn_energy_dout(c, loss));
+    launch_gnn_backward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->g_tgt, c->g_dout,
+                        c->gT, c->g_out, c->gS, c->gGrad, c->g_loss, c->st);
+    return check_launch(c);
+  }
+  launch_gnn_backward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->g_tgt, nullptr, c->gT,
+                      c->g_out, c->gS, c->gGrad, c->g_loss, c->st);
   const int nb = (int)((c->Kpad + 255) / 256);
   reduce_partials(nb, c->g_loss, c->g_loss + nb, c->st);
   TRY(check_launch(c));

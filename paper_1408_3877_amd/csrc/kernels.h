@@ -75,10 +75,13 @@ void launch_gnn_features(int N, const Geo& g, const double* D, double dt, double
                          float* node, float* edge, hipStream_t st);
 void launch_gnn_forward(int N, const Geo& g, const float* P, const float* node, const float* edge,
                         const float* rhat, GnnActs& A, float* out, hipStream_t st);
-// gradient of mean (out - target)^2 into grad; loss_partials[b] = sums of squares per block
+// gradient of mean (out - target)^2 into grad, or, when dout is given, of the loss
+// whose gradient with respect to out is dout; loss_partials[b] = sums of
+// (out - target)^2 per block
 void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node, const float* edge,
-                         const float* rhat, const float* target, const GnnActs& A, const float* out,
-                         GnnScratch& S, float* grad, double* loss_partials, hipStream_t st);
+                         const float* rhat, const float* target, const float* dout,
+                         const GnnActs& A, const float* out, GnnScratch& S, float* grad,
+                         double* loss_partials, hipStream_t st);
 void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr, int step,
                  hipStream_t st);
 void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,

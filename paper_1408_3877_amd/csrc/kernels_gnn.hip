@@ -220,11 +220,13 @@ __global__ void __launch_bounds__(256) k_gnn_decode(Geo g, const float* __restri
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-// dg = 2 (g - t) / (K N); dh3 = dg W_dec^T; rows for the W_dec / b_dec gradient;
+// dg = 2 (g - t) / (K N), or dg = dout when the loss gradient with respect to
+// g is given; dh3 = dg W_dec^T; rows for the W_dec / b_dec gradient;
 // per-block partial sums of (g - t)^2 in partials[blockIdx]
 template <int N>
 __global__ void __launch_bounds__(256) k_gnn_decode_bwd(Geo g, const float* __restrict__ gout,
                                                         const float* __restrict__ target,
+                                                        const float* __restrict__ dout,
                                                         const float* __restrict__ h3,
                                                         const float* __restrict__ PD,
                                                         float* __restrict__ dh3,
@@ -243,7 +245,7 @@ __global__ void __launch_bounds__(256) k_gnn_decode_bwd(Geo g, const float* __re
     for (int o = 0; o < N; ++o) {
       const float r = gout[vidx(k, o, N)] - target[vidx(k, o, N)];
       se += (double)r * (double)r;
-      dg[o] = sc * r;
+      dg[o] = dout ? dout[vidx(k, o, N)] : sc * r;
       rowB[k * N + o] = dg[o];
     }
     load_f<W>(h3, k, h);
@@ -518,11 +520,12 @@ size_t gnn_partials_size(int64_t K) {
 }
 
 void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node, const float* edge,
-                         const float* rhat, const float* target, const GnnActs& A, const float* out,
-                         GnnScratch& S, float* grad, double* loss_partials, hipStream_t st) {
+                         const float* rhat, const float* target, const float* dout,
+                         const GnnActs& A, const float* out, GnnScratch& S, float* grad,
+                         double* loss_partials, hipStream_t st) {
   const unsigned nb = nb256(g.Kpad);
   const int64_t K = g.K;
-  LDG_SWITCH_N(N, (k_gnn_decode_bwd<NT><<<nb, 256, 0, st>>>(g, out, target, A.h[3],
+  LDG_SWITCH_N(N, (k_gnn_decode_bwd<NT><<<nb, 256, 0, st>>>(g, out, target, dout, A.h[3],
                                                             P + gnn_off_dec(N), S.dh[0], S.rowA,
                                                             S.rowB, loss_partials)));
   tn_reduce(K, W + 1, N, S.rowA, S.rowB, S.partials, grad + gnn_off_dec(N), st);

@@ -46,7 +46,8 @@ KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project
 class StepInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("ir_steps", C.c_int),
                 ("fallbacks", C.c_int), ("krylov", C.c_int), ("rel_residual", C.c_double),
-                ("t", C.c_double)]
+                ("t", C.c_double), ("learned_iters", C.c_int), ("guarded_iters", C.c_int),
+                ("fallback_reason", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +78,7 @@ _SIGS = {
     "ldg_gnn_get_params": [_P, _P, C.c_int64],
     "ldg_gnn_set_context": [_P, _P, C.c_double],
     "ldg_gnn_forward": [_P, _P, _P],
+    "ldg_gnn_set_loss": [_P, C.c_int],
     "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
     "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
     "ldg_gnn_collect": [_P, C.c_int, _P, _P, _P],
@@ -280,6 +282,11 @@ class Solver:
         w = np.zeros(self.gnn_num_params(), dtype=np.float32)
         self._check(self.lib.ldg_gnn_get_params(self.h, w.ctypes.data, w.size))
         return w
+
+    def gnn_set_loss(self, kind):
+        """0 / "mse": mean squared error; 1 / "energy": energy norm relative to the target's."""
+        k = {"mse": 0, "energy": 1}.get(kind, kind)
+        self._check(self.lib.ldg_gnn_set_loss(self.h, int(k)))
 
     def gnn_set_context(self, D, dt):
         Dd = None if D is None else self._dev(D, (self.K, self.N))

@@ -6,9 +6,12 @@
 1. Data: for every training field seed, run implicit Euler steps with plain
    block-Jacobi CG and keep (BJ^{-1} r / rho, (e - BJ^{-1} r) / rho) pairs from
    CG iterates (ldg_gnn_collect): the systems and solutions the method itself
-   generates.
-2. Training: Adam on the mean squared error, one system sample per step,
-   on the device (ldg_gnn_train_step).
+   generates.  Later rounds add pairs from the iterates of flexible CG with
+   the network trained so far, whose residuals differ from plain CG's.
+2. Training: Adam, one system sample per step, on the device
+   (ldg_gnn_train_step), on the energy-norm error of the corrected step
+   relative to that of the block-Jacobi step (default) or on the mean squared
+   error of the correction.
 3. Evaluation: the same steps on held-out fields with block-Jacobi CG and
    with the learned preconditioner (flexible CG, block-Jacobi fallback);
    iterations and time per step for both.
@@ -108,7 +111,7 @@ def train(solver, data, epochs, lr, dt, seed):
 def evaluate(solver, n, seeds, sigma, steps, dt, use_gnn):
     """Mean iterations and seconds per step (block-Jacobi or learned)."""
     torch = solver.torch
-    its, secs, fbs = [], [], 0
+    its, secs, fbs, lits, why = [], [], 0, 0, []
     for sd in seeds:
         dT = field(n, sd, sigma)
         solver.set_initial_samples(solver.sample_workload(LOGNORMAL, 0.0, dT=dT, want=("c0",))["c0"])
@@ -123,8 +126,12 @@ def evaluate(solver, n, seeds, sigma, steps, dt, use_gnn):
             secs.append(time.perf_counter() - t0)
             its.append(info["iters"])
             fbs += info["fallbacks"]
+            lits += info["learned_iters"]
+            if info["fallbacks"]:
+                why.append(info["fallback_reason"])
+            log("[eval] %s seed %d t=%.1e %s" % ("learned" if use_gnn else "bj", sd, t, info))
     return {"iters_per_step": float(np.mean(its)), "s_per_step": float(np.mean(secs)),
-            "fallbacks": fbs, "steps": len(its)}
+            "fallbacks": fbs, "fallback_reasons": why, "learned_iters": lits, "steps": len(its)}
 
 
 def seeds_arg(s):
@@ -145,10 +152,14 @@ def main(argv=None):
     ap.add_argument("--eval-seeds", default="4100,4101")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--eval-steps", type=int, default=3)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=4, help="epochs per round")
+    ap.add_argument("--rounds", type=int, default=2,
+                    help="collection rounds (1: block-Jacobi solves only)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=7)
+    ap.add_argument("--loss", choices=("energy", "mse"), default="energy")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--weights", default=None, help="skip collection and training, evaluate these")
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     import torch
@@ -157,22 +168,52 @@ def main(argv=None):
     coordV, V0T, kind = square_mesh(a.n, seed=a.jitter)
     torch.cuda.set_device(0)
     sv = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000)
-    sv.gnn_set_params(glorot(sv.N, a.init_seed))
-    t0 = time.perf_counter()
-    data = collect(sv, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
-    t_collect = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    losses = train(sv, data, a.epochs, a.lr, a.dt, a.init_seed)
-    t_train = time.perf_counter() - t0
-    w = sv.gnn_get_params()
+    if a.weights:
+        w = np.load(a.weights).astype(np.float32)
+        data, losses, t_collect, t_train = [], [], 0.0, 0.0
+    else:
+        # round 0 learns from block-Jacobi CG solves; later rounds add the
+        # residuals that flexible CG with the current network produces
+        w = glorot(sv.N, a.init_seed)
+        data, losses, t_collect, t_train = [], [], 0.0, 0.0
+        sl = None
+        for rd in range(a.rounds):
+            src = sv
+            if rd > 0:
+                if sl is None:
+                    sl = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
+                sl.gnn_set_params(w)
+                src = sl
+            t0 = time.perf_counter()
+            data += collect(src, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
+            t_collect += time.perf_counter() - t0
+            sv.gnn_set_params(w)
+            sv.gnn_set_loss(a.loss)
+            t0 = time.perf_counter()
+            losses += train(sv, data, a.epochs, a.lr, a.dt, a.init_seed + rd)
+            t_train += time.perf_counter() - t0
+            w = sv.gnn_get_params()
+        del sl
+    n_samples = len(data)
+    del data[:]
     if a.out:
         np.save(a.out, w)
+    # the training loss on held-out systems (one step per evaluation field)
+    sv.gnn_set_params(w)
+    sv.gnn_set_loss(a.loss)
+    held = collect(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt)
+    hl = []
+    for r, tg, D in held:
+        sv.gnn_set_context(D, a.dt)
+        hl.append(sv.gnn_loss_grad(r, tg)[0])
+    del held[:]
     ev = evaluate(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, False)
     sg = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
     sg.gnn_set_params(w)
     eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
-    rep = {"p": a.p, "K": sv.K, "samples": len(data), "collect_s": t_collect, "train_s": t_train,
-           "epochs": a.epochs, "loss_per_epoch": losses, "block_jacobi": ev, "learned": eg,
+    rep = {"p": a.p, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
+           "epochs": a.epochs, "rounds": a.rounds, "loss": a.loss, "loss_per_epoch": losses,
+           "heldout_loss": float(np.mean(hl)), "block_jacobi": ev, "learned": eg,
            "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],
            "time_ratio": eg["s_per_step"] / ev["s_per_step"]}
     print(json.dumps(rep), flush=True)
