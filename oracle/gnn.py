@@ -32,32 +32,37 @@ def n_in(N):
     return 2 * N + 3
 
 
-def param_shapes(N):
-    """Ordered (name, shape) list of the flat parameter vector."""
+def trunk_shapes(n_input):
+    """(name, shape) list of the encoder and the message-passing layers."""
     W = WIDTH
-    shapes = [("W_enc", (n_in(N), W)), ("b_enc", (W,))]
+    shapes = [("W_enc", (n_input, W)), ("b_enc", (W,))]
     for l in range(LAYERS):
         shapes += [("W_m%d" % l, (W, W)), ("W_e%d" % l, (E_IN, W)), ("b_m%d" % l, (W,)),
                    ("W_u%d" % l, (2 * W, W)), ("b_u%d" % l, (W,))]
-    shapes += [("W_dec", (W, N)), ("b_dec", (N,))]
     return shapes
 
 
-def n_params(N):
-    return sum(int(np.prod(s)) for _, s in param_shapes(N))
+def param_shapes(N):
+    """Ordered (name, shape) list of the flat parameter vector."""
+    return trunk_shapes(n_in(N)) + [("W_dec", (WIDTH, N)), ("b_dec", (N,))]
 
 
-def unpack(theta, N):
+def n_params(N, shapes=None):
+    return sum(int(np.prod(s)) for _, s in (shapes or param_shapes(N)))
+
+
+def unpack(theta, N, shapes=None):
     out, o = {}, 0
-    for name, shp in param_shapes(N):
+    for name, shp in (shapes or param_shapes(N)):
         sz = int(np.prod(shp))
         out[name] = theta[o:o + sz].reshape(shp)
         o += sz
     return out
 
 
-def pack(d, N):
-    return np.concatenate([np.asarray(d[name], np.float64).reshape(-1) for name, _ in param_shapes(N)])
+def pack(d, N, shapes=None):
+    return np.concatenate([np.asarray(d[name], np.float64).reshape(-1)
+                           for name, _ in (shapes or param_shapes(N))])
 
 
 def init_params(N, seed):
@@ -99,8 +104,15 @@ def forward(theta, grid, node, edge, rhat, keep=False):
     """g [K x N]; with keep=True also the activations backward() needs."""
     K, N = rhat.shape
     P = unpack(theta, N)
+    h, acts = trunk_forward(P, grid, np.concatenate([rhat, node], axis=1), edge)
+    g = h @ P["W_dec"] + P["b_dec"]
+    return (g, acts) if keep else g
+
+
+def trunk_forward(P, grid, x, edge):
+    """Node states h [K x 32] after the encoder and the layers, and the activations."""
+    K = x.shape[0]
     relu = lambda z: np.maximum(z, 0.0)
-    x = np.concatenate([rhat, node], axis=1)
     z0 = x @ P["W_enc"] + P["b_enc"]
     h = relu(z0)
     acts = {"x": x, "z0": z0, "h": [h], "p": [], "a": [], "u": []}
@@ -120,8 +132,7 @@ def forward(theta, grid, node, edge, rhat, keep=False):
         acts["a"].append(a)
         acts["u"].append(u)
         acts["h"].append(h)
-    g = h @ P["W_dec"] + P["b_dec"]
-    return (g, acts) if keep else g
+    return h, acts
 
 
 def loss(theta, grid, node, edge, rhat, target):
@@ -163,7 +174,13 @@ def backward(theta, grid, node, edge, rhat, dg):
     h3 = A["h"][LAYERS]
     G["W_dec"] = h3.T @ dg
     G["b_dec"] = dg.sum(0)
-    dh = dg @ P["W_dec"].T
+    trunk_backward(P, grid, edge, A, dg @ P["W_dec"].T, G)
+    return pack(G, N)
+
+
+def trunk_backward(P, grid, edge, A, dh, G):
+    """Accumulate the trunk parameters' gradients into G given d loss / d h3."""
+    K = dh.shape[0]
     for l in reversed(range(LAYERS)):
         h = A["h"][l]
         a = A["a"][l]
@@ -188,7 +205,6 @@ def backward(theta, grid, node, edge, rhat, dg):
     dz0 = dh * (A["z0"] > 0)
     G["W_enc"] = A["x"].T @ dz0
     G["b_enc"] = dz0.sum(0)
-    return pack(G, N)
 
 
 def adam_step(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -1,0 +1,133 @@
+"""Pins of the learned factored preconditioner's oracle (oracle/gnn_factor.py).
+
+The scaled operator has identity diagonal blocks and symmetric neighbour
+blocks; omega = 0 gives block-Jacobi exactly; P is symmetric positive
+definite; the gradient of the energy loss matches central differences; and a
+constant omega of the right sign cuts preconditioned-CG iterations while the
+wrong sign raises them (a sign or index slip in F fails one of these).
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import lognormal_blocks, triangle_values
+from inputs.meshes import NORTH, square_mesh
+from oracle import gnn, gnn_factor as gf
+from oracle.ldg import Blocks, schur_matrix
+from oracle.mesh import Grid
+from oracle.refelem import RefTensors
+
+
+def _system(n, p, seed, ratio=6.5, sigma=1.5, neumann=(NORTH,)):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neumann)
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(p)
+    blk = max(1, n // 4)
+    dT = triangle_values(lognormal_blocks(n, seed + 1, sigma, block=blk), n, block=blk)
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = dT / np.sqrt(2.0)              # d = dT on every triangle (phi_1 = sqrt 2)
+    dt = ratio / n ** 2
+    S = schur_matrix(Blocks(g, refs, D), g, refs, 1.0, dt)
+    return g, D, dt, gf.System(g, S)
+
+
+def _pcg(S, b, P, tol=1e-8, maxit=5000):
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = P @ r
+    d = z.copy()
+    rz = r @ z
+    nb = np.linalg.norm(b)
+    for it in range(1, maxit + 1):
+        q = S @ d
+        a = rz / (d @ q)
+        x += a * d
+        r -= a * q
+        if np.linalg.norm(r) <= tol * nb:
+            return it
+        z = P @ r
+        rzn = r @ z
+        d = z + (rzn / rz) * d
+        rz = rzn
+    return maxit
+
+
+def test_scaled_operator_blocks():
+    g, D, dt, sy = _system(6, 2, 11)
+    N = sy.N
+    Sd = sy.S.toarray()
+    Wd = sy.Wg.toarray()
+    Sh = Wd @ Sd @ Wd.T
+    for k in range(sy.K):
+        assert np.abs(sy.Wk[k].T @ sy.Wk[k] - sy.BJinv[k]).max() <= 1e-12 * np.abs(sy.BJinv[k]).max()
+        assert np.abs(np.tril(sy.Wk[k], -1)).max() == 0.0          # W_k upper triangular
+        assert np.abs(Sh[k * N:(k + 1) * N, k * N:(k + 1) * N] - np.eye(N)).max() < 1e-12
+        for n in range(3):
+            j = g.kp[k, n]
+            if j < 0:
+                continue
+            assert np.abs(sy.O[k, n] - Sh[k * N:(k + 1) * N, j * N:(j + 1) * N]).max() < 1e-12
+            assert np.abs(sy.O[k, n] - sy.O[j, g.np_[k, n]].T).max() < 1e-12
+
+
+def test_zero_omega_is_block_jacobi_and_P_is_spd():
+    g, D, dt, sy = _system(6, 2, 12)
+    P0 = sy.P(np.zeros((sy.K, 3))).toarray()
+    assert np.abs(P0 - sy.BJg.toarray()).max() <= 1e-13 * np.abs(P0).max()
+    rng = np.random.default_rng(3)
+    om = np.where(sy.mask, rng.uniform(0.0, gf.OMEGA_MAX, (sy.K, 3)), 0.0)
+    Pm = sy.P(om).toarray()
+    assert np.abs(Pm - Pm.T).max() <= 1e-13 * np.abs(Pm).max()
+    assert np.linalg.eigvalsh(Pm).min() > 0.0
+
+
+def test_constant_omega_cuts_cg_iterations_and_the_wrong_sign_does_not():
+    g, D, dt, sy = _system(16, 2, 13)
+    rng = np.random.default_rng(4)
+    b = sy.S @ rng.standard_normal(sy.K * sy.N)
+    it_bj = _pcg(sy.S, b, sy.BJg)
+    om = np.where(sy.mask, 0.6, 0.0)
+    it_good = _pcg(sy.S, b, sy.P(om))
+    it_bad = _pcg(sy.S, b, sy.P(-om))
+    assert it_good < 0.75 * it_bj, (it_good, it_bj)
+    assert it_bad > it_bj, (it_bad, it_bj)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_energy_loss_gradient_matches_finite_differences(p):
+    g, D, dt, sy = _system(4, p, 20 + p)
+    N = sy.N
+    node, edge = gnn.features(g, D, dt, 1.0)
+    rng = np.random.default_rng(5 + p)
+    theta = gf.init_params(N, 7) + 0.05 * rng.standard_normal(gf.n_params(N))
+    rhat = rng.standard_normal((sy.K, N))
+    target = rng.standard_normal((sy.K, N))
+    L, G = gf.energy_loss_grad(theta, g, node, edge, sy, rhat, target)
+    assert abs(L - gf.energy_loss(theta, g, node, edge, sy, rhat, target)) <= 1e-12 * L
+    n_head = sum(int(np.prod(s)) for _, s in gf.HEAD)
+    idx = np.concatenate([np.arange(gf.n_params(N) - n_head, gf.n_params(N)),
+                          rng.choice(gf.n_params(N) - n_head, 150, replace=False)])
+    eps = 1e-6
+    worst = 0.0
+    floor = 1e-3 * np.abs(G).max()              # central differences resolve no less
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd = (gf.energy_loss(tp, g, node, edge, sy, rhat, target)
+              - gf.energy_loss(tm, g, node, edge, sy, rhat, target)) / (2 * eps)
+        worst = max(worst, abs(fd - G[i]) / max(floor, abs(G[i])))
+    assert worst < 1e-5, worst
+    assert np.abs(G).max() > 0.0
+
+
+def test_loss_is_one_at_zero_omega():
+    g, D, dt, sy = _system(4, 1, 30)
+    N = sy.N
+    node, edge = gnn.features(g, D, dt, 1.0)
+    theta = gf.init_params(N, 1)
+    P = gnn.unpack(theta, N, gf.param_shapes(N))
+    P["b_o"][...] = -200.0                        # sigmoid underflows: omega = 0
+    rng = np.random.default_rng(8)
+    L = gf.energy_loss(gnn.pack(P, N, gf.param_shapes(N)), g, node, edge, sy,
+                       rng.standard_normal((sy.K, N)), rng.standard_normal((sy.K, N)))
+    assert abs(L - 1.0) < 1e-12
