@@ -195,7 +195,8 @@ typedef enum {
   LDG_K_KRYLOV = 5,    /* Gram-Schmidt dots, updates, vector updates */
   LDG_K_PROJECT = 6,   /* projections and boundary data */
   LDG_K_GNN = 7,       /* graph-network inference and training */
-  LDG_K_COUNT = 8
+  LDG_K_FACTOR = 8,    /* factored learned preconditioner: setup and application */
+  LDG_K_COUNT = 9
 } ldg_kernel_id;
 typedef struct {
   int64_t launches;
@@ -290,6 +291,28 @@ ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* d
  * per layer W_m [32 x 32], W_e [13 x 32], b_m [32], W_u [64 x 32], b_u [32],
  * then W_dec [32 x N], b_dec [N] (row-major).
  */
+/*
+ * Network mode.  LDG_GNN_CORRECTION (default): the residual-correction
+ * network above, applied at every iteration inside flexible CG.
+ * LDG_GNN_FACTOR: a linear, symmetric positive definite preconditioner built
+ * once per system,
+ *   P = W^T (I + F)^T (I + F) W,  W = blockdiag(W_k), W_k^T W_k = BJ_k^{-1}
+ *   (W_k the transposed lower Cholesky factor of the block-Jacobi inverse),
+ *   F_kj = -omega_kn O_kn for j = k+ across edge n,  O_kn = W_k S_kj W_j^T,
+ * with S_kj the blocks of the eliminated operator between triangles sharing
+ * an edge and omega_kn = 0.95 sigmoid(h_k w_hk + h_j w_hj + e_kn w_e
+ * + w_o log ||O_kn||_F + b_o) from the same encoder and three layers fed the
+ * node features only (N + 3 inputs).  Plain preconditioned CG keeps its
+ * optimality with it; a breakdown returns the step to block-Jacobi CG.
+ * Parameters: the trunk as above with W_enc [(N+3) x 32], then w_hk [32],
+ * w_hj [32], w_e [13], w_o, b_o.  Training uses the energy loss of
+ * ldg_gnn_set_loss on the collected pairs, with the error e = target + rhat:
+ * (P r - e)^T S (P r - e) / (BJ^{-1} r - e)^T S (BJ^{-1} r - e), r = S e.
+ * Changing the mode drops the parameters.  Unknown modes: LDG_EINVAL.
+ */
+typedef enum { LDG_GNN_CORRECTION = 0, LDG_GNN_FACTOR = 1 } ldg_gnn_mode;
+ldg_status ldg_gnn_set_mode(ldg_ctx* ctx, int mode);
+/* parameter count of the current mode */
 ldg_status ldg_gnn_num_params(ldg_ctx* ctx, int64_t* n);
 /* host parameter vector in/out; setting resets the Adam moments */
 ldg_status ldg_gnn_set_params(ldg_ctx* ctx, const float* w, int64_t n);
@@ -308,8 +331,17 @@ typedef enum { LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1 } ldg_gnn_loss;
 ldg_status ldg_gnn_set_loss(ldg_ctx* ctx, int loss);
 /* per-triangle and per-edge features from D (device K x N, NULL: last projected) and dt */
 ldg_status ldg_gnn_set_context(ldg_ctx* ctx, const double* D, double dt);
-/* g = network(r_hat): r_hat, g device K x N FP32 */
+/* g = network(r_hat): r_hat, g device K x N FP32 (correction mode) */
 ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
+/*
+ * Factor mode, after ldg_gnn_set_context: omega (device K x 3 FP32, 0 on
+ * boundary edges) from the current parameters, and the factor blocks
+ * (device K x 4 x N x N FP64: W_k, O_k0, O_k1, O_k2 row-major, O on boundary
+ * edges undefined; may be NULL) with log ||O_kn||_F (device K x 3 FP32,
+ * undefined on boundary edges; may be NULL).  The blocks are stored in FP32.
+ */
+ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
+ldg_status ldg_gnn_factor_export(ldg_ctx* ctx, double* blocks, float* lognorm);
 /*
  * loss (as selected by ldg_gnn_set_loss) and its gradient (device, n_params
  * floats, may be NULL); the weight gradients are fixed-order FP64

@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libldg.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["host_ref.cpp", "host_mesh.cpp", "kernels_core.hip", "kernels_apply.hip",
-           "kernels_krylov.hip", "kernels_assemble_mfma.hip", "kernels_gnn.hip", "api.hip"]
+           "kernels_krylov.hip", "kernels_assemble_mfma.hip", "kernels_gnn.hip", "kernels_factor.hip",
+           "api.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -63,6 +63,15 @@ struct ldg_ctx {
   double gtau = 0.0;
   bool g_energy_ready = false;
   float* g_dout = nullptr;
+  // network mode (LDG_GNN_CORRECTION / LDG_GNN_FACTOR) and the factored
+  // preconditioner's buffers: factor blocks (FP32), FP64 W, log ||O||, omega,
+  // d loss / d omega, FP64 and FP32 work vectors
+  int gmode = 0;
+  bool fac_alloc_inf = false, fac_alloc_train = false, fac_on = false;
+  float *fac_blk = nullptr, *fac_lognorm = nullptr, *fac_om = nullptr, *fac_dom = nullptr;
+  double* fac_w64 = nullptr;
+  double* fac_v[8] = {};
+  float *fac_y32 = nullptr, *fac_a32 = nullptr;
   // collection of (r, e) pairs from the FP64 CG solve of the next step
   int col_n = 0, col_done = 0, col_taken = 0, col_cap = 0;
   std::vector<int> col_iters;
@@ -151,14 +160,14 @@ struct Timed {
   Timed(ldg_ctx* c_, int id_, double bytes_, double flops_) : c(c_), id(id_), bytes(bytes_), flops(flops_) {
     if (c->timing) {
       a = ev_get(c);
-      if (a) hipEventRecord(a, c->st);
+      if (a) (void)hipEventRecord(a, c->st);   // timing is best effort
     }
   }
   ~Timed() {
     if (!a) return;
     hipEvent_t b = ev_get(c);
     if (!b) return;
-    hipEventRecord(b, c->st);
+    (void)hipEventRecord(b, c->st);
     c->pending.push_back({id, a, b, bytes, flops});
   }
 };
@@ -301,13 +310,16 @@ ldg_status snapshot(ldg_ctx* c, const Level& L, int it) {
   return check_launch(c);
 }
 
+void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z);
+
 ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
-                    bool* not_spd) {
+                    bool* not_spd, bool factor = false) {
   double* hb = c->host_buf;
   *not_spd = false;
   kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
   TRY(snapshot(c, L, 0));
-  bj_apply(c, L, L.r, L.z, true);
+  if (factor) fac_apply(c, L, L.r, L.z);
+  else bj_apply(c, L, L.r, L.z, true);
   TRY(fetch(c, c->red.result, 1, hb));
   double rz = hb[0];
   kaxpby(c, L, 1.0, L.z, 0.0, L.p);
@@ -332,7 +344,8 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     const double rn = std::sqrt(hb[0]);
     if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
     if (rn <= tol_abs) break;
-    bj_apply(c, L, L.r, L.z, true);
+    if (factor) fac_apply(c, L, L.r, L.z);
+    else bj_apply(c, L, L.r, L.z, true);
     TRY(fetch(c, c->red.result, 1, hb));
     const double rz_new = hb[0];
     const double beta = rz_new / rz;
@@ -414,11 +427,19 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
 }
 
 // ---- graph-network preconditioner ---------------------------------------------
+int64_t gnn_count(const ldg_ctx* c) {
+  return c->gmode == LDG_GNN_FACTOR ? fac_num_params(c->N) : gnn_num_params(c->N);
+}
+
+int64_t gnn_count_max(const ldg_ctx* c) {
+  return std::max(fac_num_params(c->N), gnn_num_params(c->N));
+}
+
 ldg_status gnn_alloc(ldg_ctx* c, bool training) {
   const int64_t nf = c->Kpad * GNN_WIDTH;
+  c->gnP = gnn_count(c);
   if (!c->gnn_alloc_inf) {
-    c->gnP = gnn_num_params(c->N);
-    TRY(dalloc(c, &c->gP, c->gnP));
+    TRY(dalloc(c, &c->gP, gnn_count_max(c)));
     TRY(dalloc(c, &c->gnode, c->Kpad * (c->N + 3)));
     TRY(dalloc(c, &c->gedge, c->Kpad * 3 * GNN_EIN));
     TRY(dalloc(c, &c->g_rhat, c->nvec));
@@ -432,11 +453,12 @@ ldg_status gnn_alloc(ldg_ctx* c, bool training) {
     c->gnn_alloc_inf = true;
   }
   if (training && !c->gnn_alloc_train) {
-    TRY(dalloc(c, &c->gGrad, c->gnP));
-    TRY(dalloc(c, &c->gM, c->gnP));
-    TRY(dalloc(c, &c->gV, c->gnP));
-    HIPCHK(c, hipMemsetAsync(c->gM, 0, c->gnP * sizeof(float), c->st));
-    HIPCHK(c, hipMemsetAsync(c->gV, 0, c->gnP * sizeof(float), c->st));
+    const int64_t pm = gnn_count_max(c);
+    TRY(dalloc(c, &c->gGrad, pm));
+    TRY(dalloc(c, &c->gM, pm));
+    TRY(dalloc(c, &c->gV, pm));
+    HIPCHK(c, hipMemsetAsync(c->gM, 0, pm * sizeof(float), c->st));
+    HIPCHK(c, hipMemsetAsync(c->gV, 0, pm * sizeof(float), c->st));
     TRY(dalloc(c, &c->gT.z0, nf));
     for (int l = 0; l < 4; ++l) TRY(dalloc(c, &c->gT.h[l], nf));
     for (int l = 0; l < 3; ++l) {
@@ -447,7 +469,7 @@ ldg_status gnn_alloc(ldg_ctx* c, bool training) {
     TRY(dalloc(c, &c->gS.dh[1], nf));
     TRY(dalloc(c, &c->gS.dhpart, nf));
     TRY(dalloc(c, &c->gS.da, nf));
-    TRY(dalloc(c, &c->gS.rowA, (size_t)3 * c->K * (2 * GNN_WIDTH + 1)));
+    TRY(dalloc(c, &c->gS.rowA, (size_t)3 * c->K * std::max(2 * GNN_WIDTH + 1, FAC_HEAD)));
     TRY(dalloc(c, &c->gS.rowB, (size_t)3 * c->K * GNN_WIDTH));
     TRY(dalloc(c, &c->gS.partials, gnn_partials_size(c->K)));
     TRY(dalloc(c, &c->g_loss, (size_t)(c->Kpad / 256 + 2)));
@@ -455,6 +477,63 @@ ldg_status gnn_alloc(ldg_ctx* c, bool training) {
     c->gnn_alloc_train = true;
   }
   return LDG_OK;
+}
+
+ldg_status fac_alloc(ldg_ctx* c, bool training) {
+  if (!c->fac_alloc_inf) {
+    TRY(dalloc(c, &c->fac_blk, (size_t)c->Kpad * FAC_SLOTS * ((c->N * c->N + 3) / 4) * 4));
+    TRY(dalloc(c, &c->fac_w64, (size_t)c->Kpad * npairs(c->N) * 2));
+    TRY(dalloc(c, &c->fac_lognorm, (size_t)3 * c->Kpad));
+    TRY(dalloc(c, &c->fac_om, (size_t)3 * c->Kpad));
+    TRY(dalloc(c, &c->fac_dom, (size_t)3 * c->Kpad));
+    TRY(dalloc(c, &c->fac_v[0], c->nvec));
+    TRY(dalloc(c, &c->fac_v[1], c->nvec));
+    TRY(dalloc(c, &c->fac_y32, c->nvec));
+    TRY(dalloc(c, &c->fac_a32, c->nvec));
+    c->fac_alloc_inf = true;
+  }
+  if (training && !c->fac_alloc_train) {
+    for (int q = 2; q < 8; ++q) TRY(dalloc(c, &c->fac_v[q], c->nvec));
+    c->fac_alloc_train = true;
+  }
+  return LDG_OK;
+}
+
+// W, O blocks and log ||O|| of the current FP64 blocks and block-Jacobi inverses
+ldg_status fac_build(ldg_ctx* c, double tau) {
+  TRY(fac_alloc(c, false));
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->st));
+  {
+    const double NN = (double)c->NN;
+    Timed tm(c, LDG_K_FACTOR, 8.0 * NN * (8.0 * c->K), 2.0 * NN * c->N * (8.0 * c->Eint));
+    launch_fac_setup(c->N, c->geo, c->refs, c->blocks, c->bj, tau, c->opt.eta, c->fac_w64,
+                     c->fac_blk, c->fac_lognorm, c->status, c->st);
+  }
+  TRY(check_launch(c));
+  HIPCHK(c, hipMemcpyAsync(c->host_buf, c->status, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  int stv = 0;
+  std::memcpy(&stv, c->host_buf, sizeof(int));
+  if (stv) return fail(c, LDG_ENOCONV, "block-Jacobi inverse without a Cholesky factor");
+  return LDG_OK;
+}
+
+// omega from the network for the current context (inference activations)
+ldg_status fac_omega(ldg_ctx* c) {
+  Timed tm(c, LDG_K_GNN, 0.0, 0.0);
+  launch_fac_omega(c->N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gA, c->fac_om,
+                   c->st);
+  return check_launch(c);
+}
+
+// z = P r (factored) with <r, z> in red.result[0]
+void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z) {
+  const double NN = (double)c->N * c->N;
+  Timed tm(c, LDG_K_FACTOR, (8.0 * 4.0 * NN + 7.0 * L.vbytes * c->N) * c->K,
+           2.0 * 8.0 * NN * c->K);
+  void* y = L.vt == VT_F64 ? (void*)c->fac_v[0] : (void*)c->fac_y32;
+  void* a = L.vt == VT_F64 ? (void*)c->fac_v[1] : (void*)c->fac_a32;
+  launch_fac_apply(c->N, L.vt, c->geo, c->fac_blk, c->fac_om, r, y, a, z, &c->red, c->st);
 }
 
 // z = BJ^{-1} r + rho g(BJ^{-1} r / rho), rho = RMS of BJ^{-1} r  (FP32 network)
@@ -558,6 +637,40 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
   return LDG_OK;
 }
 
+// One inner solve at level L (rnorm = ||r|| for GMRES); a breakdown moves the
+// step to the next solver: learned -> block-Jacobi CG, CG -> GMRES.
+ldg_status inner_solve(ldg_ctx* c, const Level& L, double tau, double tol, int left, double rnorm,
+                       bool* cg_mode, bool* gnn_on, ldg_step_info* info, int* it) {
+  *it = 0;
+  if (*cg_mode && *gnn_on && c->gmode == LDG_GNN_CORRECTION) {
+    int broke = LDG_FB_NONE;
+    TRY(inner_fcg(c, L, tau, tol, left, it, &broke, &info->guarded_iters));
+    info->learned_iters += *it;
+    if (broke != LDG_FB_NONE) {   // the learned preconditioner failed: block-Jacobi from here on
+      info->fallbacks += 1;
+      info->fallback_reason = broke;
+      *gnn_on = false;
+    }
+  } else if (*cg_mode) {
+    const bool factor = *gnn_on;  // the factored preconditioner of this step
+    bool not_spd = false;
+    TRY(inner_cg(c, L, tau, tol, left, it, &not_spd, factor));
+    if (factor) info->learned_iters += *it;
+    if (not_spd) {
+      info->fallbacks += 1;
+      info->fallback_reason = LDG_FB_CURVATURE;
+      if (factor) {
+        *gnn_on = false;
+      } else {
+        *cg_mode = false;
+        info->krylov = LDG_KRYLOV_GMRES;
+      }
+    }
+  }
+  if (!*cg_mode && *it == 0) TRY(inner_gmres(c, L, tau, rnorm, tol, left, it));
+  return LDG_OK;
+}
+
 // ---- the step's solve: FP64 refinement around the inner solver ---------------
 // Unknown C of the eliminated system, residual r = b3 - F(C) with
 // F(C) = M C + tau(eta S' C + sum_m B^m Z^m(C)), Z^m(C) = -M^{-1}(A^m C + J^m_D):
@@ -579,7 +692,8 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   bool cg_mode = use_cg;
   // the learned preconditioner runs inside flexible CG (SPD case); for GMRES
   // problems it is not used and the step counts one fallback
-  bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode;
+  bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode &&
+                (c->gmode == LDG_GNN_CORRECTION || c->fac_on);
   if (c->opt.precond == LDG_PC_GNN && !cg_mode) {
     info->fallbacks += 1;
     info->fallback_reason = LDG_FB_NONSYMMETRIC;
@@ -617,26 +731,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       HIPCHK(c, hipMemcpyAsync(L.r, c->w, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
       scale = 1.0;
       const int left = c->opt.max_iters - iters;
-      if (cg_mode && gnn_on) {
-        int broke = LDG_FB_NONE;
-        TRY(inner_fcg(c, L, tau, 0.9 * target, left, &it, &broke, &info->guarded_iters));
-        info->learned_iters += it;
-        if (broke != LDG_FB_NONE) {   // the learned preconditioner failed: block-Jacobi from here on
-          info->fallbacks += 1;
-          info->fallback_reason = broke;
-          gnn_on = false;
-        }
-      } else if (cg_mode) {
-        bool not_spd = false;
-        TRY(inner_cg(c, L, tau, 0.9 * target, left, &it, &not_spd));
-        if (not_spd) {
-          info->fallbacks += 1;
-          info->fallback_reason = LDG_FB_CURVATURE;
-          cg_mode = false;
-          info->krylov = LDG_KRYLOV_GMRES;
-        }
-      }
-      if (!cg_mode && it == 0) TRY(inner_gmres(c, L, tau, beta, 0.9 * target, left, &it));
+      TRY(inner_solve(c, L, tau, 0.9 * target, left, beta, &cg_mode, &gnn_on, info, &it));
     } else {
       {
         Timed tm(c, LDG_K_KRYLOV, 12.0 * n, (double)n);
@@ -645,26 +740,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       scale = beta;
       const double tol = std::max(c->opt.inner_rtol, 0.5 * target / beta);
       const int left = c->opt.max_iters - iters;
-      if (cg_mode && gnn_on) {
-        int broke = LDG_FB_NONE;
-        TRY(inner_fcg(c, L, tau, tol, left, &it, &broke, &info->guarded_iters));
-        info->learned_iters += it;
-        if (broke != LDG_FB_NONE) {
-          info->fallbacks += 1;
-          info->fallback_reason = broke;
-          gnn_on = false;
-        }
-      } else if (cg_mode) {
-        bool not_spd = false;
-        TRY(inner_cg(c, L, tau, tol, left, &it, &not_spd));
-        if (not_spd) {
-          info->fallbacks += 1;
-          info->fallback_reason = LDG_FB_CURVATURE;
-          cg_mode = false;
-          info->krylov = LDG_KRYLOV_GMRES;
-        }
-      }
-      if (!cg_mode && it == 0) TRY(inner_gmres(c, L, tau, 1.0, tol, left, &it));
+      TRY(inner_solve(c, L, tau, tol, left, 1.0, &cg_mode, &gnn_on, info, &it));
     }
     iters += it;
     {
@@ -763,11 +839,11 @@ const char* ldg_last_error(const ldg_ctx* c) { return c ? c->err.c_str() : "null
 
 void ldg_destroy(ldg_ctx* c) {
   if (!c) return;
-  if (c->st) hipStreamSynchronize(c->st);
+  if (c->st) (void)hipStreamSynchronize(c->st);   // teardown: nothing to report to
   for (auto& p : c->pending) { c->evpool.push_back(p.a); c->evpool.push_back(p.b); }
-  for (hipEvent_t e : c->evpool) hipEventDestroy(e);
-  for (void* p : c->allocs) hipFree(p);
-  if (c->host_buf) hipHostFree(c->host_buf);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->host_buf) (void)hipHostFree(c->host_buf);
   delete c;
 }
 
@@ -1171,6 +1247,13 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   // a6, a7: Krylov solve (with FP64 refinement) starting from C^n
   bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
+  // the factored learned preconditioner of this system (SPD case only)
+  c->fac_on = false;
+  if (c->opt.precond == LDG_PC_GNN && c->gmode == LDG_GNN_FACTOR && use_cg) {
+    TRY(fac_build(c, tau));
+    TRY(fac_omega(c));
+    c->fac_on = true;
+  }
   HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   c->col_taken = 0;
   ldg_status s = solve_step(c, tau, bnorm > 0.0 ? bnorm : 1.0, use_cg, info);
@@ -1192,12 +1275,12 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
 
 ldg_status ldg_gnn_num_params(ldg_ctx* c, int64_t* n) {
   if (!c || !n) return LDG_EINVAL;
-  *n = gnn_num_params(c->N);
+  *n = gnn_count(c);
   return LDG_OK;
 }
 
 ldg_status ldg_gnn_set_params(ldg_ctx* c, const float* w, int64_t n) {
-  if (!c || !w || n != gnn_num_params(c->N)) return fail(c, LDG_EINVAL, "parameter count");
+  if (!c || !w || n != gnn_count(c)) return fail(c, LDG_EINVAL, "parameter count");
   TRY(gnn_alloc(c, false));
   HIPCHK(c, hipMemcpyAsync(c->gP, w, n * sizeof(float), hipMemcpyHostToDevice, c->st));
   if (c->gnn_alloc_train) {
@@ -1210,7 +1293,7 @@ ldg_status ldg_gnn_set_params(ldg_ctx* c, const float* w, int64_t n) {
 }
 
 ldg_status ldg_gnn_get_params(ldg_ctx* c, float* w, int64_t n) {
-  if (!c || !w || n != gnn_num_params(c->N) || !c->gnn_params_set)
+  if (!c || !w || n != gnn_count(c) || !c->gnn_params_set)
     return fail(c, LDG_EINVAL, "parameter count or no parameters");
   HIPCHK(c, hipMemcpyAsync(w, c->gP, n * sizeof(float), hipMemcpyDeviceToHost, c->st));
   return sync(c);
@@ -1221,7 +1304,19 @@ ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
   TRY(gnn_alloc(c, false));
   if (Dem) launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
   launch_gnn_features(c->N, c->geo, c->D, dt, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
-  if (c->gloss == LDG_GNN_LOSS_ENERGY) {
+  if (c->gmode == LDG_GNN_FACTOR) {
+    // the factored preconditioner of this system: blocks, block-Jacobi, W and O
+    bool sym = false;
+    TRY(coefficient_is_elementwise_constant(c, &sym));
+    if (!sym) return fail(c, LDG_EINVAL, "the factored preconditioner needs a coefficient "
+                                         "constant per triangle");
+    launch_assemble_mfma(c->N, BT_F64, c->geo, c->D, c->Tm64, c->blocks, c->st);
+    c->blocks_ready = true;
+    TRY(ldg_bj_setup(c, dt));
+    TRY(fac_build(c, dt));
+    c->gtau = dt;
+    c->g_energy_ready = true;
+  } else if (c->gloss == LDG_GNN_LOSS_ENERGY) {
     // the energy gradient 2 S (g - t) / (t^T S t) needs S symmetric: d constant per triangle
     bool sym = false;
     TRY(coefficient_is_elementwise_constant(c, &sym));
@@ -1234,6 +1329,41 @@ ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
   return check_launch(c);
 }
 
+ldg_status ldg_gnn_set_mode(ldg_ctx* c, int mode) {
+  if (!c || (mode != LDG_GNN_CORRECTION && mode != LDG_GNN_FACTOR))
+    return fail(c, LDG_EINVAL, "unknown network mode");
+  if (mode != c->gmode) {
+    c->gmode = mode;
+    c->gnn_params_set = false;
+    c->g_energy_ready = false;
+    c->gnP = gnn_count(c);
+  }
+  return LDG_OK;
+}
+
+ldg_status ldg_gnn_factor_omega(ldg_ctx* c, float* om) {
+  if (!c || !om || c->gmode != LDG_GNN_FACTOR || !c->gnn_params_set || !c->g_energy_ready)
+    return fail(c, LDG_EINVAL, "factor mode, parameters and a context are needed");
+  TRY(fac_omega(c));
+  for (int n = 0; n < 3; ++n)
+    HIPCHK(c, hipMemcpy2DAsync(om + n, 3 * sizeof(float), c->fac_om + n * c->Kpad, sizeof(float),
+                               sizeof(float), c->K, hipMemcpyDeviceToDevice, c->st));
+  return sync(c);
+}
+
+ldg_status ldg_gnn_factor_export(ldg_ctx* c, double* blocks, float* lognorm) {
+  if (!c || c->gmode != LDG_GNN_FACTOR || !c->g_energy_ready)
+    return fail(c, LDG_EINVAL, "factor mode and a context are needed");
+  if (blocks) launch_fac_export(c->K, c->N, c->fac_blk, blocks, c->st);
+  if (lognorm)
+    for (int n = 0; n < 3; ++n)
+      HIPCHK(c, hipMemcpy2DAsync(lognorm + n, 3 * sizeof(float), c->fac_lognorm + n * c->Kpad,
+                                 sizeof(float), sizeof(float), c->K, hipMemcpyDeviceToDevice,
+                                 c->st));
+  TRY(check_launch(c));
+  return sync(c);
+}
+
 ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
   if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY))
     return fail(c, LDG_EINVAL, "unknown loss");
@@ -1244,6 +1374,8 @@ ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
 
 ldg_status ldg_gnn_forward(ldg_ctx* c, const float* rhat, float* out) {
   if (!c || !rhat || !out || !c->gnn_params_set) return fail(c, LDG_EINVAL, "bad arguments");
+  if (c->gmode != LDG_GNN_CORRECTION)
+    return fail(c, LDG_EINVAL, "the factored network maps no residual: ldg_gnn_factor_omega");
   launch_to_tiled_f(c->K, c->Kpad, c->N, rhat, c->g_rhat, c->st);
   {
     Timed tm(c, LDG_K_GNN, 0.0, 0.0);
@@ -1282,7 +1414,49 @@ ldg_status gnn_energy_dout(ldg_ctx* c, double* loss) {
   return LDG_OK;
 }
 
+// Factored preconditioner, energy loss of one pair: e = target + rhat, r = S e,
+//   d = P r - e,  d0 = BJ^{-1} r - e,  loss = d^T S d / d0^T S d0,
+// and d loss / d omega from y = W r, a = (I + F) y, beta = W (2 S d / den),
+// alpha = (I + F) beta.
+ldg_status gnn_factor_loss_grad(ldg_ctx* c, double* loss) {
+  if (!c->g_energy_ready) return fail(c, LDG_EINVAL, "no context set");
+  TRY(fac_alloc(c, true));
+  const Level L = level64(c);
+  const int64_t n = c->nvec;
+  const int N = c->N;
+  double** v = c->fac_v;
+  launch_fac_omega(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT, c->fac_om, c->st);
+  launch_cast(VT_F32, VT_F64, n, 1.0, c->g_tgt, v[0], c->st);
+  launch_axpy_into64(VT_F32, n, 1.0, c->g_rhat, v[0], c->st);            // e
+  apply_op(c, L, c->gtau, v[0], false, L.tz1, L.tz2, v[1]);               // r = S e
+  launch_fac_w(N, c->geo, c->fac_blk, v[1], v[2], c->st);                 // y
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, false, v[2], v[3], c->st);  // a
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, true, v[3], v[4], c->st);   // z = P r
+  launch_axpy_into64(VT_F64, n, -1.0, v[0], v[4], c->st);                 // d
+  apply_op(c, L, c->gtau, v[4], false, L.tz1, L.tz2, v[5]);               // S d
+  kdots(c, L, 1, v[4], v[5]);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  const double num = c->host_buf[0];
+  bj_apply(c, L, v[1], v[6], false);
+  launch_axpy_into64(VT_F64, n, -1.0, v[0], v[6], c->st);                 // d0
+  apply_op(c, L, c->gtau, v[6], false, L.tz1, L.tz2, v[7]);               // S d0
+  kdots(c, L, 1, v[6], v[7]);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  const double den = c->host_buf[0];
+  if (!(den > 0.0) || !std::isfinite(num))
+    return fail(c, LDG_ENOCONV, "energy loss: block-Jacobi error without positive energy");
+  launch_cast(VT_F64, VT_F64, n, 2.0 / den, v[5], v[4], c->st);           // dL/dz
+  launch_fac_w(N, c->geo, c->fac_blk, v[4], v[6], c->st);                 // beta
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, false, v[6], v[7], c->st);  // alpha
+  launch_fac_domega(N, c->geo, c->fac_blk, v[3], v[6], v[7], v[2], c->fac_dom, c->st);
+  launch_fac_omega_backward(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT,
+                            c->fac_om, c->fac_dom, c->gS, c->gGrad, c->st);
+  *loss = num / den;
+  return check_launch(c);
+}
+
 ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
+  if (c->gmode == LDG_GNN_FACTOR) return gnn_factor_loss_grad(c, loss);
   Timed tm(c, LDG_K_GNN, 0.0, 0.0);
   launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gT, c->g_out, c->st);
   if (c->gloss == LDG_GNN_LOSS_ENERGY) {

@@ -87,6 +87,25 @@ __device__ inline void block_mv(const BT* __restrict__ blocks, int64_t k, int s,
   }
 }
 
+// acc += Blk(k, s)^T z
+template <int N, class BT, class T>
+__device__ inline void block_mtv(const BT* __restrict__ blocks, int64_t k, int s, int ns,
+                                 const T* z, T* acc) {
+  constexpr int W = Blk<BT>::W;
+  constexpr int NN = N * N;
+  constexpr int NG = ngroups(N, W);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    T v[W];
+    Blk<BT>::load(blocks + bgidx(k, s, g, ns, NG, W), v);
+#pragma unroll
+    for (int h = 0; h < W; ++h) {
+      const int f = g * W + h;
+      if (f < NN) acc[f % N] += v[h] * z[f / N];
+    }
+  }
+}
+
 template <int N, class T>
 __device__ inline void load_vec(const T* __restrict__ v, int64_t k, T* x) {
 #pragma unroll

@@ -70,6 +70,11 @@ struct GnnScratch {
 int64_t gnn_num_params(int N);
 int64_t gnn_off_layer(int N, int l);
 int64_t gnn_off_dec(int N);
+// the factored preconditioner's network: trunk on node features only, edge head
+constexpr int FAC_HEAD = 2 * GNN_WIDTH + GNN_EIN + 2;
+constexpr float FAC_OMEGA_MAX = 0.95f;
+int64_t fac_num_params(int N);
+int64_t fac_off_head(int N);
 size_t gnn_partials_size(int64_t K);
 void launch_gnn_features(int N, const Geo& g, const double* D, double dt, double eta, double meanA,
                          float* node, float* edge, hipStream_t st);
@@ -82,8 +87,40 @@ void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node,
                          const float* rhat, const float* target, const float* dout,
                          const GnnActs& A, const float* out, GnnScratch& S, float* grad,
                          double* loss_partials, hipStream_t st);
+// d loss / d h3 in S.dh[0] -> trunk gradients (rhat == nullptr: node features only)
+void gnn_trunk_backward(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                        const float* rhat, const GnnActs& A, GnnScratch& S, float* grad,
+                        hipStream_t st);
+// omega [3][Kpad] from the network (activations kept in A when its training slots are set)
+void launch_fac_omega(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                      const float* lognorm, GnnActs& A, float* om, hipStream_t st);
+// gradient of the loss with respect to the parameters given d loss / d omega
+void launch_fac_omega_backward(int N, const Geo& g, const float* P, const float* node,
+                               const float* edge, const float* lognorm, const GnnActs& A,
+                               const float* om, const float* dom, GnnScratch& S, float* grad,
+                               hipStream_t st);
 void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr, int step,
                  hipStream_t st);
+
+// kernels_factor.hip: factor blocks (FP32, FAC_SLOTS per triangle: W_k, O_k0..2)
+constexpr int FAC_SLOTS = 4;
+// W (FP64 scratch w64 and slot 0), O blocks and log ||O||_F from the FP64
+// operator blocks and block-Jacobi inverses; status |= 2 on a failed Cholesky
+void launch_fac_setup(int N, const Geo& g, const double* refs, const double* blocks,
+                      const double* bj, double tau, double eta, double* w64, float* fb,
+                      float* lognorm, int* status, hipStream_t st);
+// z = P r through y, a (work vectors); red: result[0] = <r, z>
+void launch_fac_apply(int N, int vt, const Geo& g, const float* fb, const float* om,
+                      const void* r, void* y, void* a, void* z, const Reducer* red,
+                      hipStream_t st);
+void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double* y,
+                  hipStream_t st);
+// out = (I + F) x, or W^T (I + F)^T x
+void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,
+                  const double* x, double* out, hipStream_t st);
+void launch_fac_domega(int N, const Geo& g, const float* fb, const double* a, const double* beta,
+                       const double* alpha, const double* y, float* dom, hipStream_t st);
+void launch_fac_export(int64_t K, int N, const float* fb, double* out, hipStream_t st);
 void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,
                        hipStream_t st);
 void launch_from_tiled_f(int64_t K, int N, const float* src, float* dst, hipStream_t st);

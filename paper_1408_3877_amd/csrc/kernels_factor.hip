@@ -1,0 +1,405 @@
+// Learned factored preconditioner on the element graph (linear, SPD):
+//
+//   P = W^T (I + F)^T (I + F) W,   W = blockdiag(W_k),  W_k^T W_k = BJ_k^{-1},
+//   F_kj = -omega_kn O_kn  for j = k+ across local edge n,
+//   O_kn = W_k S_kj W_j^T  (the neighbour blocks of the scaled operator W S W^T).
+//
+// W_k = R_k^T with R_k the lower Cholesky factor of the block-Jacobi inverse;
+// omega comes from the graph network (kernels_gnn.hip).  Setup once per
+// system: Cholesky factors (16 lanes per triangle), then the explicit
+// neighbour blocks of the eliminated operator, once per interior edge, with
+// O written to both sides (O_{k+ n+} = O_kn^T exactly after rounding).
+//
+//   S_kj = tau [ -eta S_off(n, n+)
+//                - (|E_kn| / (2 * 2|T_k|)) (sum_m nu^m_kn B^m_kk) S_off(n, n+)
+//                - (1 / 2|T_j|) U_kn (sum_m nu^m_kn A^m_jj) ],
+//   A^m_jj = -H^m_j + sum_n' q_n' nu^m_jn' |E_jn'| S_diag(n'),  q = 1/2 interior, 1 Neumann,
+//
+// the blocks of M + tau (eta (S + S_D) - sum_m B^m M^{-1} A^m) between two
+// triangles sharing an edge (paths through a third triangle next to both
+// exist only around interior vertices of degree three and are left out).
+// Application: three one-lane-per-triangle passes, y = W x, a = (I + F) y,
+// z = W^T (I + F)^T a, the transpose using the stored O_kn as O_{k+ n+}^T.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace ldg {
+
+namespace {
+
+constexpr int NREF = 14;  // H1, H2, Sd[3], So[3][3]
+__device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
+inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class BT>
+__device__ inline void put(BT* __restrict__ fb, int64_t k, int s, int f, int N, double v) {
+  constexpr int Wv = Blk<BT>::W;
+  const int NG = ngroups(N, Wv);
+  fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv] = from_double<BT>(v);
+}
+
+__device__ inline double get64(const double* __restrict__ b, int64_t k, int s, int ns, int f,
+                               int NP) {
+  return b[pidx(k, s, f >> 1, ns, NP) + (f & 1)];
+}
+
+}  // namespace
+
+// W_k = R_k^T, BJ_k^{-1} = R_k R_k^T (lower Cholesky), 16 lanes per triangle,
+// lane i owns row i; padding triangles get the identity.
+template <int N, class BT>
+__global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restrict__ bj,
+                                                  double* __restrict__ w64, BT* __restrict__ fb,
+                                                  int* __restrict__ status) {
+  constexpr int NP = npairs(N);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = gid >> 4;
+  const int i = (int)(gid & 15);
+  const bool elem_ok = k < g.K;
+  const bool row_ok = elem_ok && i < N;
+  double a[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    a[c] = row_ok ? get64(bj, k, 0, 1, i * N + c, NP) : (c == i ? 1.0 : 0.0);
+  // right-looking, branch-free: after column c, lane i holds L[i][c] in a[c] and
+  // the updated a[i][j] for j > c (entries with j > i are don't-cares)
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const double piv = __shfl(a[c], c, 16);
+    bad |= !(piv > 0.0);
+    const double inv = 1.0 / sqrt(piv);
+    const double lic = (i >= c ? 1.0 : 0.0) * a[c] * inv;
+    a[c] = lic;
+#pragma unroll
+    for (int j = c + 1; j < N; ++j) a[j] -= lic * __shfl(lic, j, 16);
+  }
+  if (row_ok && bad) atomicOr(status, 2);
+  if (k < g.Kpad && i < N) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {   // lane i holds R[i][r] = W[r][i]
+      const double v = r <= i ? a[r] : 0.0;
+      const int f = r * N + i;
+      w64[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = v;
+      put<BT>(fb, k, 0, f, N, v);
+    }
+  }
+}
+
+// O_kn for every interior edge once (from the triangle with the smaller index),
+// written to (k, n) and transposed to (k+, n+); lognorm = log ||O_kn||_F on both.
+// 64 threads = 4 triangles x 16 lanes; lane i owns row i.
+template <int N, class BT>
+__global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restrict__ refs,
+                                                    const double* __restrict__ blocks,
+                                                    const double* __restrict__ w64, double tau,
+                                                    double eta, BT* __restrict__ fb,
+                                                    float* __restrict__ lognorm) {
+  constexpr int NN = N * N;
+  constexpr int NP = npairs(N);
+  __shared__ double sm[NREF * NN];
+  __shared__ double t1[4][NN];
+  __shared__ double t2[4][NN];
+  for (int t = threadIdx.x; t < NREF * NN; t += blockDim.x) sm[t] = refs[t];
+  __syncthreads();
+  const int grp = threadIdx.x >> 4;
+  const int i = threadIdx.x & 15;
+  const int ii = i < N ? i : 0;
+  const int64_t k = (int64_t)blockIdx.x * 4 + grp;
+  const bool elem_ok = k < g.K;
+  const int64_t kk = elem_ok ? k : 0;
+  const int64_t Kp = g.Kpad;
+  const double area2k = g.area2[kk];
+  double* T1 = t1[grp];
+  double* T2 = t2[grp];
+  for (int n = 0; n < 3; ++n) {
+    const int64_t jn = elem_ok ? g.nbr[n * Kp + kk] : -1;
+    const bool act = jn > k;
+    const int64_t j = act ? jn : kk;
+    const int npl = act ? g.nbrn[n * Kp + kk] : 0;
+    const double nu1 = g.nu[(2 * n) * Kp + kk], nu2 = g.nu[(2 * n + 1) * Kp + kk];
+    // t1 <- sum_m nu^m_kn A^m_jj (row ii per lane)
+    {
+      const double B11 = g.B[j], B12 = g.B[Kp + j], B21 = g.B[2 * Kp + j], B22 = g.B[3 * Kp + j];
+      double coef[5];
+      coef[0] = -(nu1 * B22 - nu2 * B12);
+      coef[1] = -(-nu1 * B21 + nu2 * B11);
+      for (int q = 0; q < 3; ++q) {
+        const int kd = g.kind[q * Kp + j];
+        const double w = kd == LDG_EDGE_INTERIOR ? 0.5 : (kd == LDG_EDGE_NEUMANN ? 1.0 : 0.0);
+        coef[2 + q] = w * (nu1 * g.nu[(2 * q) * Kp + j] + nu2 * g.nu[(2 * q + 1) * Kp + j]) *
+                      g.elen[q * Kp + j];
+      }
+      if (i < N) {
+        for (int c = 0; c < N; ++c) {
+          double s = 0.0;
+          for (int t = 0; t < 5; ++t) s += coef[t] * sm[t * NN + ii * N + c];
+          T1[ii * N + c] = s;
+        }
+      }
+    }
+    // t2 <- sum_m nu^m_kn B^m_kk (row ii per lane)
+    if (i < N) {
+      for (int c = 0; c < N; ++c)
+        T2[ii * N + c] = nu1 * get64(blocks, kk, 0, NSLOT, ii * N + c, NP) +
+                         nu2 * get64(blocks, kk, 1, NSLOT, ii * N + c, NP);
+    }
+    __syncthreads();
+    // row ii of S_kj in registers
+    double srow[N];
+    {
+      const double* So = sm + ref_so(n, npl) * NN;
+      const double c1 = 0.5 * g.elen[n * Kp + kk] / area2k;
+      const double c2 = 1.0 / g.area2[j];
+#pragma unroll
+      for (int c = 0; c < N; ++c) srow[c] = -eta * So[ii * N + c];
+      for (int l = 0; l < N; ++l) {
+        const double bl = T2[ii * N + l];
+        const double ul = get64(blocks, kk, 2 + n, NSLOT, ii * N + l, NP);
+#pragma unroll
+        for (int c = 0; c < N; ++c) srow[c] -= c1 * bl * So[l * N + c] + c2 * ul * T1[l * N + c];
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c) srow[c] *= tau;
+    }
+    __syncthreads();
+    // t2 <- W_j; row ii of T = S_kj W_j^T
+    if (i < N) {
+      for (int c = 0; c < N; ++c) T2[ii * N + c] = get64(w64, j, 0, 1, ii * N + c, NP);
+    }
+    __syncthreads();
+    {
+      double trow[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) trow[c] = 0.0;
+      for (int l = 0; l < N; ++l) {
+        const double sl = srow[l];
+#pragma unroll
+        for (int c = 0; c < N; ++c) trow[c] += sl * T2[c * N + l];
+      }
+      if (i < N) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) T1[ii * N + c] = trow[c];
+      }
+    }
+    __syncthreads();
+    // row ii of O = W_k T
+    double o[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) o[c] = 0.0;
+    for (int l = 0; l < N; ++l) {
+      const double wl = get64(w64, kk, 0, 1, ii * N + l, NP);
+#pragma unroll
+      for (int c = 0; c < N; ++c) o[c] += wl * T1[l * N + c];
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) nrm += o[c] * o[c];
+    if (i >= N) nrm = 0.0;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 16);
+    if (act && i < N) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        put<BT>(fb, k, 1 + n, ii * N + c, N, o[c]);
+        put<BT>(fb, j, 1 + npl, c * N + ii, N, o[c]);
+      }
+      if (i == 0) {
+        const float ln = (float)log(fmax(sqrt(nrm), 1e-300));
+        lognorm[n * Kp + k] = ln;
+        lognorm[npl * Kp + j] = ln;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// y = W x
+template <int N, class T, class BT>
+__global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BT* __restrict__ fb,
+                                               const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpad) return;
+  T xv[N], acc[N];
+  load_vec<N, T>(x, k, xv);
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = 0;
+  block_mv<N, BT, T>(fb, k, 0, FAC_SLOTS, xv, acc);
+  store_vec<N, T>(y, k, acc);
+}
+
+// out = (I + F) x  (NBR false: omega_kn), or (I + F)^T x  (NBR true: omega_{k+ n+},
+// O_kn standing for O_{k+ n+}^T), followed by out = W^T out when WT.
+// partials (optional): per-block sums of <r, out> for the preconditioned dot.
+template <int N, class T, class BT, bool NBR, bool WT>
+__global__ void __launch_bounds__(256) k_fac_f(Geo g, const BT* __restrict__ fb,
+                                               const float* __restrict__ om,
+                                               const T* __restrict__ x, T* __restrict__ out,
+                                               const T* __restrict__ r,
+                                               double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Kp = g.Kpad;
+  double s = 0.0;
+  if (k < Kp) {
+    T acc[N];
+    load_vec<N, T>(x, k, acc);
+    if (k < g.K) {
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const int64_t j = g.nbr[n * Kp + k];
+        if (j < 0) continue;
+        const float w = NBR ? om[(int64_t)g.nbrn[n * Kp + k] * Kp + j] : om[n * Kp + k];
+        T xj[N];
+        load_vec<N, T>(x, j, xj);
+#pragma unroll
+        for (int i = 0; i < N; ++i) xj[i] *= -(T)w;
+        block_mv<N, BT, T>(fb, k, 1 + n, FAC_SLOTS, xj, acc);
+      }
+    }
+    if (WT) {
+      T o[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] = 0;
+      block_mtv<N, BT, T>(fb, k, 0, FAC_SLOTS, acc, o);
+      store_vec<N, T>(out, k, o);
+      if (partials) {
+        T rv[N];
+        load_vec<N, T>(r, k, rv);
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += (double)rv[i] * (double)o[i];
+      }
+    } else {
+      store_vec<N, T>(out, k, acc);
+    }
+  }
+  if (partials == nullptr) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// d loss / d omega_kn = -(a_k^T O_kn beta_{k+} + alpha_k^T O_kn y_{k+}); 0 off the interior
+template <int N, class BT>
+__global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict__ fb,
+                                                    const double* __restrict__ a,
+                                                    const double* __restrict__ beta,
+                                                    const double* __restrict__ alpha,
+                                                    const double* __restrict__ y,
+                                                    float* __restrict__ dom) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Kp = g.Kpad;
+  if (k >= Kp) return;
+  double ak[N], alk[N];
+  load_vec<N, double>(a, k, ak);
+  load_vec<N, double>(alpha, k, alk);
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int64_t j = k < g.K ? g.nbr[n * Kp + k] : -1;
+    double s = 0.0;
+    if (j >= 0) {
+      double bj[N], yj[N], u1[N], u2[N];
+      load_vec<N, double>(beta, j, bj);
+      load_vec<N, double>(y, j, yj);
+#pragma unroll
+      for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0.0;
+      block_mv<N, BT, double>(fb, k, 1 + n, FAC_SLOTS, bj, u1);
+      block_mv<N, BT, double>(fb, k, 1 + n, FAC_SLOTS, yj, u2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += ak[i] * u1[i] + alk[i] * u2[i];
+    }
+    dom[n * Kp + k] = (float)(-s);
+  }
+}
+
+// export of the factor blocks: out[k][s][i][j] (FP64, row-major)
+template <class BT>
+__global__ void k_fac_export(int64_t K, int N, const BT* __restrict__ fb,
+                             double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int NN = N * N;
+  if (t >= K * FAC_SLOTS * NN) return;
+  const int f = (int)(t % NN);
+  const int s = (int)((t / NN) % FAC_SLOTS);
+  const int64_t k = t / ((int64_t)NN * FAC_SLOTS);
+  constexpr int Wv = Blk<BT>::W;
+  const int NG = ngroups(N, Wv);
+  out[t] = (double)fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define LDG_SWITCH_N(N, CALL)                                   \
+  switch (N) {                                                  \
+    case 1: { constexpr int NT = 1; CALL; } break;              \
+    case 3: { constexpr int NT = 3; CALL; } break;              \
+    case 6: { constexpr int NT = 6; CALL; } break;              \
+    case 10: { constexpr int NT = 10; CALL; } break;            \
+    case 15: { constexpr int NT = 15; CALL; } break;            \
+    default: break;                                             \
+  }
+
+void launch_fac_setup(int N, const Geo& g, const double* refs, const double* blocks,
+                      const double* bj, double tau, double eta, double* w64, float* fb,
+                      float* lognorm, int* status, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_fac_chol<NT, float><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(g, bj, w64, fb,
+                                                                                 status)));
+  LDG_SWITCH_N(N, (k_fac_offdiag<NT, float><<<nbk(g.Kpad, 4), 64, 0, st>>>(
+                      g, refs, blocks, w64, tau, eta, fb, lognorm)));
+}
+
+void launch_fac_apply(int N, int vt, const Geo& g, const float* fb, const float* om,
+                      const void* r, void* y, void* a, void* z, const Reducer* red,
+                      hipStream_t st) {
+  const unsigned nb = nbk(g.Kpad, 256);
+  double* parts = red ? red->partials : nullptr;
+  if (vt == VT_F64) {
+    using T = double;
+    LDG_SWITCH_N(N, (k_fac_w<NT, T, float><<<nb, 256, 0, st>>>(g.Kpad, fb, (const T*)r, (T*)y)));
+    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, false, false><<<nb, 256, 0, st>>>(
+                        g, fb, om, (const T*)y, (T*)a, nullptr, nullptr)));
+    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, true, true><<<nb, 256, 0, st>>>(
+                        g, fb, om, (const T*)a, (T*)z, (const T*)r, parts)));
+  } else {
+    using T = float;
+    LDG_SWITCH_N(N, (k_fac_w<NT, T, float><<<nb, 256, 0, st>>>(g.Kpad, fb, (const T*)r, (T*)y)));
+    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, false, false><<<nb, 256, 0, st>>>(
+                        g, fb, om, (const T*)y, (T*)a, nullptr, nullptr)));
+    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, true, true><<<nb, 256, 0, st>>>(
+                        g, fb, om, (const T*)a, (T*)z, (const T*)r, parts)));
+  }
+  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+}
+
+void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double* y,
+                  hipStream_t st) {
+  LDG_SWITCH_N(N, (k_fac_w<NT, double, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g.Kpad, fb, x,
+                                                                                 y)));
+}
+
+void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,
+                  const double* x, double* out, hipStream_t st) {
+  const unsigned nb = nbk(g.Kpad, 256);
+  if (transpose_and_wt) {
+    LDG_SWITCH_N(N, (k_fac_f<NT, double, float, true, true><<<nb, 256, 0, st>>>(
+                        g, fb, om, x, out, nullptr, nullptr)));
+  } else {
+    LDG_SWITCH_N(N, (k_fac_f<NT, double, float, false, false><<<nb, 256, 0, st>>>(
+                        g, fb, om, x, out, nullptr, nullptr)));
+  }
+}
+
+void launch_fac_domega(int N, const Geo& g, const float* fb, const double* a, const double* beta,
+                       const double* alpha, const double* y, float* dom, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_fac_domega<NT, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g, fb, a, beta,
+                                                                              alpha, y, dom)));
+}
+
+void launch_fac_export(int64_t K, int N, const float* fb, double* out, hipStream_t st) {
+  k_fac_export<float><<<nbk(K * FAC_SLOTS * N * N, 256), 256, 0, st>>>(K, N, fb, out);
+}
+
+}  // namespace ldg

@@ -92,20 +92,21 @@ __global__ void k_gnn_features(Geo g, const double* __restrict__ D, double dt, d
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
-// h0 = relu(x W_enc + b_enc); keeps z0 when z0 != NULL
-template <int N>
+// h0 = relu(x W_enc + b_enc); keeps z0 when z0 != NULL.  NR = N: x = [r_hat, node];
+// NR = 0: x = node (the factored preconditioner's network sees no residual)
+template <int N, int NR>
 __global__ void __launch_bounds__(256) k_gnn_encode(Geo g, const float* __restrict__ rhat,
                                                     const float* __restrict__ node,
                                                     const float* __restrict__ P,
                                                     float* __restrict__ z0, float* __restrict__ h0) {
-  constexpr int NIN = 2 * N + 3;
+  constexpr int NIN = NR + N + 3;
   __shared__ float sw[(NIN + 1) * W];
   load_lds(sw, P, (NIN + 1) * W);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
   float x[NIN];
-  load_f<N>(rhat, k, x);
-  load_f<N + 3>(node, k, x + N);
+  if (NR > 0) load_f<N>(rhat, k, x);
+  load_f<N + 3>(node, k, x + NR);
   float h[W];
 #pragma unroll
   for (int o = 0; o < W; ++o) {
@@ -381,20 +382,20 @@ __global__ void __launch_bounds__(256) k_gnn_layer_bwd2(Geo g, const float* __re
 }
 
 // encoder backward: rows [x_k, 1] and dz0 = dh0 o [z0 > 0]
-template <int N>
+template <int N, int NR>
 __global__ void __launch_bounds__(256) k_gnn_encode_bwd(Geo g, const float* __restrict__ rhat,
                                                         const float* __restrict__ node,
                                                         const float* __restrict__ z0,
                                                         const float* __restrict__ dh0,
                                                         float* __restrict__ rowA,
                                                         float* __restrict__ rowB) {
-  constexpr int NIN = 2 * N + 3;
+  constexpr int NIN = NR + N + 3;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.K) return;
 #pragma unroll
-  for (int i = 0; i < N; ++i) rowA[k * (NIN + 1) + i] = rhat[vidx(k, i, N)];
+  for (int i = 0; i < NR; ++i) rowA[k * (NIN + 1) + i] = rhat[vidx(k, i, N)];
 #pragma unroll
-  for (int i = 0; i < N + 3; ++i) rowA[k * (NIN + 1) + N + i] = node[vidx(k, i, N + 3)];
+  for (int i = 0; i < N + 3; ++i) rowA[k * (NIN + 1) + NR + i] = node[vidx(k, i, N + 3)];
   rowA[k * (NIN + 1) + NIN] = 1.f;
 #pragma unroll
   for (int o = 0; o < W; ++o)
@@ -407,7 +408,7 @@ __global__ void __launch_bounds__(256) k_tn_partial(int64_t rows, int pa, int qb
                                                     const float* __restrict__ B, int rows_per_block,
                                                     double* __restrict__ partials) {
   constexpr int MAXO = 9;   // outputs per thread: up to (2W+1) x W = 2080 per block
-  __shared__ float sA[32 * 72];
+  __shared__ float sA[32 * 80];   // pa <= 80
   __shared__ float sB[32 * 32];
   const int nout = pa * qb;
   double acc[MAXO];
@@ -468,6 +469,100 @@ __global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// edge head of the factored preconditioner
+//   omega_kn = OMEGA_MAX sigmoid(h_k.w_hk + h_{k+}.w_hj + e_kn.w_e + w_o lognorm_kn + b_o)
+// on interior edges, 0 elsewhere; head parameters [w_hk (W), w_hj (W), w_e (EIN), w_o, b_o]
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fac_head(Geo g, const float* __restrict__ h3,
+                                                  const float* __restrict__ edge,
+                                                  const float* __restrict__ lognorm,
+                                                  const float* __restrict__ PH,
+                                                  float* __restrict__ om) {
+  __shared__ float sw[FAC_HEAD];
+  load_lds(sw, PH, FAC_HEAD);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Kp = g.Kpad;
+  if (k >= Kp) return;
+  float hk[W];
+  load_f<W>(h3, k, hk);
+  float base = sw[2 * W + EIN + 1];
+#pragma unroll
+  for (int o = 0; o < W; ++o) base += hk[o] * sw[o];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int64_t j = k < g.K ? g.nbr[n * Kp + k] : -1;
+    float w = 0.f;
+    if (j >= 0) {
+      float a = base + sw[2 * W + EIN] * lognorm[n * Kp + k];
+#pragma unroll
+      for (int o = 0; o < W; ++o) a += h3[vidx(j, o, W)] * sw[W + o];
+#pragma unroll
+      for (int c = 0; c < EIN; ++c) a += edge[vidx(k, n * EIN + c, 3 * EIN)] * sw[2 * W + c];
+      w = FAC_OMEGA_MAX / (1.f + expf(-a));
+    }
+    om[n * Kp + k] = w;
+  }
+}
+
+// da_kn = dom_kn d omega / d a = dom_kn omega (1 - omega / OMEGA_MAX); rows
+// [h_k, h_{k+}, e_kn, lognorm_kn, 1] and da per directed edge (row n K + k) for
+// the head gradient; dh3_k = w_hk sum_n da_kn + w_hj sum_n da_{k+ n+}
+__global__ void __launch_bounds__(256) k_fac_head_bwd(Geo g, const float* __restrict__ h3,
+                                                      const float* __restrict__ edge,
+                                                      const float* __restrict__ lognorm,
+                                                      const float* __restrict__ PH,
+                                                      const float* __restrict__ om,
+                                                      const float* __restrict__ dom,
+                                                      float* __restrict__ dh3,
+                                                      float* __restrict__ rowA,
+                                                      float* __restrict__ rowB) {
+  constexpr int HR = FAC_HEAD;
+  __shared__ float sw[FAC_HEAD];
+  load_lds(sw, PH, FAC_HEAD);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Kp = g.Kpad;
+  const int64_t K = g.K;
+  if (k >= Kp) return;
+  float dh[W];
+#pragma unroll
+  for (int o = 0; o < W; ++o) dh[o] = 0.f;
+  if (k < K) {
+    float hk[W];
+    load_f<W>(h3, k, hk);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int64_t j = g.nbr[n * Kp + k];
+      float* ra = rowA + (n * K + k) * HR;
+      float da = 0.f;
+      if (j >= 0) {
+        const float w = om[n * Kp + k];
+        da = dom[n * Kp + k] * w * (1.f - w / FAC_OMEGA_MAX);
+#pragma unroll
+        for (int o = 0; o < W; ++o) {
+          dh[o] += da * sw[o];
+          ra[o] = hk[o];
+          ra[W + o] = h3[vidx(j, o, W)];
+        }
+#pragma unroll
+        for (int c = 0; c < EIN; ++c) ra[2 * W + c] = edge[vidx(k, n * EIN + c, 3 * EIN)];
+        ra[2 * W + EIN] = lognorm[n * Kp + k];
+        ra[2 * W + EIN + 1] = 1.f;
+        // the neighbour's edge towards k
+        const int64_t jn = g.nbrn[n * Kp + k];
+        const float wj = om[jn * Kp + j];
+        const float daj = dom[jn * Kp + j] * wj * (1.f - wj / FAC_OMEGA_MAX);
+#pragma unroll
+        for (int o = 0; o < W; ++o) dh[o] += daj * sw[W + o];
+      } else {
+        for (int c = 0; c < HR; ++c) ra[c] = 0.f;
+      }
+      rowB[n * K + k] = da;
+    }
+  }
+  store_f<W>(dh3, k, dh);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -484,9 +579,15 @@ inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
     default: break;                                             \
   }
 
-int64_t gnn_num_params(int N) { return (int64_t)(2 * N + 4) * W + 3 * LSZ + (int64_t)(W + 1) * N; }
-int64_t gnn_off_layer(int N, int l) { return (int64_t)(2 * N + 4) * W + (int64_t)l * LSZ; }
+// flat parameter layouts: trunk = [W_enc (nin x W), b_enc, 3 layers], then the
+// node decoder [W_dec (W x N), b_dec] (residual correction, nin = 2N + 3) or the
+// edge head [w_hk (W), w_hj (W), w_e (EIN), w_o, b_o] (factored, nin = N + 3)
+int64_t gnn_off_layer_nin(int nin, int l) { return (int64_t)(nin + 1) * W + (int64_t)l * LSZ; }
+int64_t gnn_num_params(int N) { return gnn_off_layer_nin(2 * N + 3, 3) + (int64_t)(W + 1) * N; }
+int64_t gnn_off_layer(int N, int l) { return gnn_off_layer_nin(2 * N + 3, l); }
 int64_t gnn_off_dec(int N) { return gnn_off_layer(N, 3); }
+int64_t fac_num_params(int N) { return gnn_off_layer_nin(N + 3, 3) + FAC_HEAD; }
+int64_t fac_off_head(int N) { return gnn_off_layer_nin(N + 3, 3); }
 
 void launch_gnn_features(int N, const Geo& g, const double* D, double dt, double eta, double meanA,
                          float* node, float* edge, hipStream_t st) {
@@ -494,13 +595,27 @@ void launch_gnn_features(int N, const Geo& g, const double* D, double dt, double
                                                                      edge)));
 }
 
+namespace {
+// encoder and layers; rhat == nullptr: node features only
+void gnn_trunk(int N, const Geo& g, const float* P, const float* node, const float* edge,
+               const float* rhat, GnnActs& A, hipStream_t st) {
+  const unsigned nb = nb256(g.Kpad);
+  const int nin = (rhat ? N : 0) + N + 3;
+  if (rhat) {
+    LDG_SWITCH_N(N, (k_gnn_encode<NT, NT><<<nb, 256, 0, st>>>(g, rhat, node, P, A.z0, A.h[0])));
+  } else {
+    LDG_SWITCH_N(N, (k_gnn_encode<NT, 0><<<nb, 256, 0, st>>>(g, rhat, node, P, A.z0, A.h[0])));
+  }
+  for (int l = 0; l < 3; ++l)
+    k_gnn_layer<<<nb, 256, 0, st>>>(g, A.h[l], edge, P + gnn_off_layer_nin(nin, l), A.h[l + 1],
+                                    A.a[l], A.u[l]);
+}
+}  // namespace
+
 void launch_gnn_forward(int N, const Geo& g, const float* P, const float* node, const float* edge,
                         const float* rhat, GnnActs& A, float* out, hipStream_t st) {
   const unsigned nb = nb256(g.Kpad);
-  LDG_SWITCH_N(N, (k_gnn_encode<NT><<<nb, 256, 0, st>>>(g, rhat, node, P, A.z0, A.h[0])));
-  for (int l = 0; l < 3; ++l)
-    k_gnn_layer<<<nb, 256, 0, st>>>(g, A.h[l], edge, P + gnn_off_layer(N, l), A.h[l + 1], A.a[l],
-                                    A.u[l]);
+  gnn_trunk(N, g, P, node, edge, rhat, A, st);
   LDG_SWITCH_N(N, (k_gnn_decode<NT><<<nb, 256, 0, st>>>(g, A.h[3], P + gnn_off_dec(N), out)));
 }
 
@@ -529,10 +644,20 @@ void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node,
                                                             P + gnn_off_dec(N), S.dh[0], S.rowA,
                                                             S.rowB, loss_partials)));
   tn_reduce(K, W + 1, N, S.rowA, S.rowB, S.partials, grad + gnn_off_dec(N), st);
+  gnn_trunk_backward(N, g, P, node, edge, rhat, A, S, grad, st);
+}
+
+// from d loss / d h3 in S.dh[0]: the layers' and the encoder's gradients
+void gnn_trunk_backward(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                        const float* rhat, const GnnActs& A, GnnScratch& S, float* grad,
+                        hipStream_t st) {
+  const unsigned nb = nb256(g.Kpad);
+  const int64_t K = g.K;
+  const int nin = (rhat ? N : 0) + N + 3;
   int cur = 0;
   for (int l = 2; l >= 0; --l) {
-    const float* PL = P + gnn_off_layer(N, l);
-    float* gL = grad + gnn_off_layer(N, l);
+    const float* PL = P + gnn_off_layer_nin(nin, l);
+    float* gL = grad + gnn_off_layer_nin(nin, l);
     k_gnn_layer_bwd1<<<nb, 256, 0, st>>>(g, S.dh[cur], A.h[l], A.a[l], A.u[l], PL, S.dhpart,
                                          S.da, S.rowA, S.rowB);
     tn_reduce(K, 2 * W + 1, W, S.rowA, S.rowB, S.partials, gL + (W + EIN + 1) * W, st);
@@ -541,9 +666,14 @@ void launch_gnn_backward(int N, const Geo& g, const float* P, const float* node,
     tn_reduce(3 * K, W + EIN + 1, W, S.rowA, S.rowB, S.partials, gL, st);
     cur = 1 - cur;
   }
-  LDG_SWITCH_N(N, (k_gnn_encode_bwd<NT><<<nb, 256, 0, st>>>(g, rhat, node, A.z0, S.dh[cur], S.rowA,
-                                                            S.rowB)));
-  tn_reduce(K, 2 * N + 4, W, S.rowA, S.rowB, S.partials, grad, st);
+  if (rhat) {
+    LDG_SWITCH_N(N, (k_gnn_encode_bwd<NT, NT><<<nb, 256, 0, st>>>(g, rhat, node, A.z0, S.dh[cur],
+                                                                  S.rowA, S.rowB)));
+  } else {
+    LDG_SWITCH_N(N, (k_gnn_encode_bwd<NT, 0><<<nb, 256, 0, st>>>(g, rhat, node, A.z0, S.dh[cur],
+                                                                 S.rowA, S.rowB)));
+  }
+  tn_reduce(K, nin + 1, W, S.rowA, S.rowB, S.partials, grad, st);
 }
 
 __global__ void k_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* __restrict__ src,
@@ -576,6 +706,22 @@ void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   k_adam<<<nb256(n), 256, 0, st>>>(n, p, gr, m, v, lr, b1, b2, c1, c2, 1e-8f);
+}
+
+void launch_fac_omega(int N, const Geo& g, const float* P, const float* node, const float* edge,
+                      const float* lognorm, GnnActs& A, float* om, hipStream_t st) {
+  gnn_trunk(N, g, P, node, edge, nullptr, A, st);
+  k_fac_head<<<nb256(g.Kpad), 256, 0, st>>>(g, A.h[3], edge, lognorm, P + fac_off_head(N), om);
+}
+
+void launch_fac_omega_backward(int N, const Geo& g, const float* P, const float* node,
+                               const float* edge, const float* lognorm, const GnnActs& A,
+                               const float* om, const float* dom, GnnScratch& S, float* grad,
+                               hipStream_t st) {
+  k_fac_head_bwd<<<nb256(g.Kpad), 256, 0, st>>>(g, A.h[3], edge, lognorm, P + fac_off_head(N),
+                                                  om, dom, S.dh[0], S.rowA, S.rowB);
+  tn_reduce(3 * g.K, FAC_HEAD, 1, S.rowA, S.rowB, S.partials, grad + fac_off_head(N), st);
+  gnn_trunk_backward(N, g, P, node, edge, nullptr, A, S, grad, st);
 }
 
 }  // namespace ldg

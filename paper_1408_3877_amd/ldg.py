@@ -40,7 +40,7 @@ class KernelStat(C.Structure):
                 ("flops", C.c_double)]
 
 
-KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn"]
+KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn", "factor"]
 
 
 class StepInfo(C.Structure):
@@ -78,6 +78,9 @@ _SIGS = {
     "ldg_gnn_get_params": [_P, _P, C.c_int64],
     "ldg_gnn_set_context": [_P, _P, C.c_double],
     "ldg_gnn_forward": [_P, _P, _P],
+    "ldg_gnn_set_mode": [_P, C.c_int],
+    "ldg_gnn_factor_omega": [_P, _P],
+    "ldg_gnn_factor_export": [_P, _P, _P],
     "ldg_gnn_set_loss": [_P, C.c_int],
     "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
     "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
@@ -282,6 +285,24 @@ class Solver:
         w = np.zeros(self.gnn_num_params(), dtype=np.float32)
         self._check(self.lib.ldg_gnn_get_params(self.h, w.ctypes.data, w.size))
         return w
+
+    def gnn_set_mode(self, mode):
+        """0 / "correction": per-iteration residual correction (flexible CG);
+        1 / "factor": linear factored preconditioner built once per system."""
+        m = {"correction": 0, "factor": 1}.get(mode, mode)
+        self._check(self.lib.ldg_gnn_set_mode(self.h, int(m)))
+
+    def gnn_factor_omega(self):
+        om = self.torch.empty((self.K, 3), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.ldg_gnn_factor_omega(self.h, _ptr(om)))
+        return om
+
+    def gnn_factor_export(self):
+        t = self.torch
+        blk = t.empty((self.K, 4, self.N, self.N), dtype=t.float64, device=self.device)
+        ln = t.empty((self.K, 3), dtype=t.float32, device=self.device)
+        self._check(self.lib.ldg_gnn_factor_export(self.h, _ptr(blk), _ptr(ln)))
+        return blk, ln
 
     def gnn_set_loss(self, kind):
         """0 / "mse": mean squared error; 1 / "energy": energy norm relative to the target's."""

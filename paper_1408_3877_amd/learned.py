@@ -9,9 +9,12 @@
    generates.  Later rounds add pairs from the iterates of flexible CG with
    the network trained so far, whose residuals differ from plain CG's.
 2. Training: Adam, one system sample per step, on the device
-   (ldg_gnn_train_step), on the energy-norm error of the corrected step
-   relative to that of the block-Jacobi step (default) or on the mean squared
-   error of the correction.
+   (ldg_gnn_train_step), on the energy-norm error of the preconditioned step
+   relative to that of the block-Jacobi step (default) or, for the
+   residual-correction network, on the mean squared error of the correction.
+   --mode factor (default) trains the factored preconditioner (a linear SPD
+   operator built once per system), --mode correction the per-iteration
+   residual-correction network.
 3. Evaluation: the same steps on held-out fields with block-Jacobi CG and
    with the learned preconditioner (flexible CG, block-Jacobi fallback);
    iterations and time per step for both.
@@ -60,6 +63,32 @@ def glorot(N, seed, width=32, e_in=13, layers=3):
         parts.append(np.zeros(width))
     mat(width, N)
     parts.append(np.zeros(N))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def factor_init(N, seed, width=32, e_in=13, layers=3, omega0=0.6, omega_max=0.95):
+    """Initial parameters of the factored network: Glorot-uniform trunk on the
+    N + 3 node features, a small edge head whose bias gives omega = omega0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+
+    def mat(r, c):
+        lim = np.sqrt(6.0 / (r + c))
+        parts.append(rng.uniform(-lim, lim, r * c))
+
+    mat(N + 3, width)
+    parts.append(np.zeros(width))
+    for _ in range(layers):
+        mat(width, width)
+        mat(e_in, width)
+        parts.append(np.zeros(width))
+        mat(2 * width, width)
+        parts.append(np.zeros(width))
+    for r in (width, width, e_in):
+        lim = np.sqrt(6.0 / (r + 1))
+        parts.append(0.1 * rng.uniform(-lim, lim, r))
+    q = omega0 / omega_max
+    parts.append(np.array([0.0, np.log(q / (1.0 - q))]))
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -158,6 +187,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=7)
     ap.add_argument("--loss", choices=("energy", "mse"), default="energy")
+    ap.add_argument("--mode", choices=("correction", "factor"), default="factor",
+                    help="per-iteration residual correction, or factored preconditioner")
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="skip collection and training, evaluate these")
     ap.add_argument("--report", default=None)
@@ -168,20 +199,28 @@ def main(argv=None):
     coordV, V0T, kind = square_mesh(a.n, seed=a.jitter)
     torch.cuda.set_device(0)
     sv = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000)
+    sv.gnn_set_mode(a.mode)
+    init = factor_init if a.mode == "factor" else glorot
+
+    def learned_solver():
+        s_ = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
+        s_.gnn_set_mode(a.mode)
+        return s_
+
     if a.weights:
         w = np.load(a.weights).astype(np.float32)
         data, losses, t_collect, t_train = [], [], 0.0, 0.0
     else:
         # round 0 learns from block-Jacobi CG solves; later rounds add the
         # residuals that flexible CG with the current network produces
-        w = glorot(sv.N, a.init_seed)
+        w = init(sv.N, a.init_seed)
         data, losses, t_collect, t_train = [], [], 0.0, 0.0
         sl = None
         for rd in range(a.rounds):
             src = sv
             if rd > 0:
                 if sl is None:
-                    sl = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
+                    sl = learned_solver()
                 sl.gnn_set_params(w)
                 src = sl
             t0 = time.perf_counter()
@@ -208,11 +247,11 @@ def main(argv=None):
         hl.append(sv.gnn_loss_grad(r, tg)[0])
     del held[:]
     ev = evaluate(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, False)
-    sg = Solver(coordV, V0T, kind, a.p, rtol=1e-8, max_iters=20000, precond=1)
+    sg = learned_solver()
     sg.gnn_set_params(w)
     eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
     rep = {"p": a.p, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
-           "epochs": a.epochs, "rounds": a.rounds, "loss": a.loss, "loss_per_epoch": losses,
+           "epochs": a.epochs, "rounds": a.rounds, "mode": a.mode, "loss": a.loss, "loss_per_epoch": losses,
            "heldout_loss": float(np.mean(hl)), "block_jacobi": ev, "learned": eg,
            "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],
            "time_ratio": eg["s_per_step"] / ev["s_per_step"]}

@@ -1,0 +1,142 @@
+"""The factored learned preconditioner on the GPU against the FP64 oracle.
+
+The factor blocks (W_k and the scaled neighbour blocks O_kn, stored in FP32),
+log ||O_kn||, the network's omega, and the energy loss with its gradient
+match oracle/gnn_factor.py; steps with the preconditioner reach the FP64
+tolerance and the oracle's solution in fewer CG iterations than
+block-Jacobi; non-finite weights and nonsymmetric steps fall back.
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import LOGNORMAL, SMOOTH1, Workload, lognormal_blocks, triangle_values
+from inputs.meshes import NORTH, square_mesh
+from oracle import gnn, gnn_factor as gf
+from oracle.ldg import Blocks, Problem, schur_matrix
+from oracle.mesh import Grid
+from oracle.refelem import RefTensors
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, p, seed, ratio=6.5):
+    from paper_1408_3877_amd import Solver
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(NORTH,))
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(p)
+    blk = max(1, n // 4)
+    dT = triangle_values(lognormal_blocks(n, seed + 1, 1.5, block=blk), n, block=blk)
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = dT / np.sqrt(2.0)
+    dt = ratio / n ** 2
+    sy = gf.System(g, schur_matrix(Blocks(g, refs, D), g, refs, 1.0, dt))
+    s = Solver(cV, V0T, kind, p)
+    s.gnn_set_mode("factor")
+    return g, D, dt, sy, s
+
+
+def _theta(N, seed):
+    rng = np.random.default_rng(seed)
+    return (gf.init_params(N, seed) + 0.05 * rng.standard_normal(gf.n_params(N))).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 2, 701), (5, 4, 702), (6, 1, 703)])
+def test_factor_blocks_and_omega_match_the_oracle(n, p, seed):
+    g, D, dt, sy, s = _setup(n, p, seed)
+    N = sy.N
+    print("[factor] blocks n=%d p=%d K=%d" % (n, p, sy.K), flush=True)
+    assert s.gnn_num_params() == gf.n_params(N)
+    th = _theta(N, seed)
+    s.gnn_set_params(th)
+    s.gnn_set_context(D, dt)
+    blk, ln = (to_np(x) for x in s.gnn_factor_export())
+    assert np.abs(blk[:, 0] - sy.Wk).max() <= 1e-6 * np.abs(sy.Wk).max()
+    m = sy.mask
+    Og = blk[:, 1:][m]
+    assert np.abs(Og - sy.O[m]).max() <= 2e-6 * np.abs(sy.O).max()
+    assert np.abs(ln[m] - sy.lognorm[m]).max() <= 1e-5
+    node, edge = gnn.features(g, D, dt, 1.0)
+    want = gf.omega(th.astype(np.float64), g, node, edge, sy)
+    got = to_np(s.gnn_factor_omega())
+    assert np.abs(got - want).max() <= 1e-5
+    assert np.all(got[~m] == 0.0)
+
+
+@pytest.mark.parametrize("n,p,seed", [(7, 2, 711), (4, 3, 712)])
+def test_factor_energy_loss_and_gradient(n, p, seed):
+    g, D, dt, sy, s = _setup(n, p, seed)
+    N = sy.N
+    th = _theta(N, seed)
+    s.gnn_set_params(th)
+    s.gnn_set_context(D, dt)
+    rng = np.random.default_rng(seed)
+    rhat = rng.standard_normal((sy.K, N)).astype(np.float32)
+    tgt = rng.standard_normal((sy.K, N)).astype(np.float32)
+    node, edge = gnn.features(g, D, dt, 1.0)
+    L, G = gf.energy_loss_grad(th.astype(np.float64), g, node, edge, sy, rhat.astype(np.float64),
+                               tgt.astype(np.float64))
+    Lg, Gg = s.gnn_loss_grad(rhat, tgt)
+    Gg = to_np(Gg)
+    print("[factor] loss gpu %.8f oracle %.8f" % (Lg, L), flush=True)
+    assert abs(Lg - L) <= 1e-4 * L
+    assert np.linalg.norm(Gg - G) <= 2e-3 * np.linalg.norm(G)
+
+
+def _steps(s, w, pr, C, dt, nsteps):
+    t, out = 0.0, []
+    for _ in range(nsteps):
+        t += dt
+        smp = s.sample_workload(w.kind, t, dT=w.dT)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        C, _, _, _ = pr.step(C, t, dt, w)
+        out.append((info, rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C)))
+    return out
+
+
+@pytest.mark.parametrize("weights", ["init", "nan"])
+def test_factor_preconditioner_steps(weights):
+    from paper_1408_3877_amd import Solver
+    n, p, dt = 12, 2, 0.02
+    cV, V0T, kind = square_mesh(n, seed=721)
+    w = Workload(LOGNORMAL, n_cells=n, blocks=lognormal_blocks(n, 722, 1.5, block=3), block=3)
+    pr = Problem(cV, V0T, kind, p)
+    runs = {}
+    for name, pc in (("bj", 0), ("learned", 1)):
+        s = Solver(cV, V0T, kind, p, rtol=1e-13, max_iters=20000, precond=pc)
+        if pc:
+            s.gnn_set_mode("factor")
+            th = _theta(s.N, 723)
+            if weights == "nan":
+                th = np.full_like(th, np.nan)
+            s.gnn_set_params(th)
+        s.set_initial_samples(s.sample_workload(LOGNORMAL, 0.0, dT=w.dT, want=("c0",))["c0"])
+        runs[name] = _steps(s, w, pr, pr.initial(w), dt, 2)
+        for info, err in runs[name]:
+            print("[factor-steps] %s %s %s err=%.2e" % (weights, name, info, err), flush=True)
+            assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
+            assert err < 1e-10
+    for (ib, _), (il, _) in zip(runs["bj"], runs["learned"]):
+        if weights == "init":
+            assert il["fallbacks"] == 0 and il["learned_iters"] == il["iters"]
+            assert il["iters"] < ib["iters"]
+        else:
+            assert il["fallbacks"] == 1 and il["fallback_reason"] == 1
+            assert il["learned_iters"] == 0
+
+
+def test_factor_nonsymmetric_step_falls_back():
+    from paper_1408_3877_amd import Solver
+    n, p, dt = 6, 2, 0.01
+    cV, V0T, kind = square_mesh(n, seed=731)
+    s = Solver(cV, V0T, kind, p, rtol=1e-12, max_iters=20000, precond=1)
+    s.gnn_set_mode("factor")
+    s.gnn_set_params(_theta(s.N, 731))
+    w = Workload(SMOOTH1)
+    s.set_initial_samples(s.sample_workload(SMOOTH1, 0.0, want=("c0",))["c0"])
+    smp = s.sample_workload(SMOOTH1, dt)
+    info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+    assert info["krylov"] == 1 and info["fallbacks"] == 1 and info["fallback_reason"] == 5
+    pr = Problem(cV, V0T, kind, p)
+    C, _, _, _ = pr.step(pr.initial(w), dt, dt, w)
+    assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
