@@ -307,7 +307,13 @@ ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* d
  * Parameters: the trunk as above with W_enc [(N+3) x 32], then w_hk [32],
  * w_hj [32], w_e [13], w_o, b_o.  Training uses the energy loss of
  * ldg_gnn_set_loss on the collected pairs, with the error e = target + rhat:
- * (P r - e)^T S (P r - e) / (BJ^{-1} r - e)^T S (BJ^{-1} r - e), r = S e.
+ * (P r - e)^T S (P r - e) / (BJ^{-1} r - e)^T S (BJ^{-1} r - e), r = S e,
+ * or, with LDG_GNN_LOSS_FROBENIUS, the factorised-sparse-approximate-inverse
+ * objective for a probe vector w passed as rhat (target unused):
+ * ||(G S G^T - I) w||^2 / ||(W S W^T - I) w||^2, G = (I + F) W; Gaussian
+ * probes make it a Hutchinson estimate of ||G S G^T - I||_F^2 (relative).
+ * The energy loss favours smooth modes alone and can drive omega to its cap;
+ * the Frobenius loss weighs every mode alike.
  * Changing the mode drops the parameters.  Unknown modes: LDG_EINVAL.
  */
 typedef enum { LDG_GNN_CORRECTION = 0, LDG_GNN_FACTOR = 1 } ldg_gnn_mode;
@@ -327,7 +333,9 @@ ldg_status ldg_gnn_get_params(ldg_ctx* ctx, float* w, int64_t n);
  * LDG_EINVAL unless D is constant on every triangle (S symmetric, the case
  * the learned preconditioner serves).  Unknown values: LDG_EINVAL.
  */
-typedef enum { LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1 } ldg_gnn_loss;
+typedef enum {
+  LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1, LDG_GNN_LOSS_FROBENIUS = 2
+} ldg_gnn_loss;
 ldg_status ldg_gnn_set_loss(ldg_ctx* ctx, int loss);
 /* per-triangle and per-edge features from D (device K x N, NULL: last projected) and dt */
 ldg_status ldg_gnn_set_context(ldg_ctx* ctx, const double* D, double dt);

@@ -26,13 +26,20 @@ directed interior edge
 The network runs once per system; every Krylov iteration applies the fixed
 linear P, so preconditioned CG keeps its optimality.
 
-Training (energy loss, on pairs from the method's own CG solves): for an error
-e (scaled by the RMS of BJ^{-1} r) and r = S e,
+Training losses, both 1 at omega = 0:
 
-    loss = (P r - e)^T S (P r - e) / (BJ^{-1} r - e)^T S (BJ^{-1} r - e),
+  Frobenius (the factorised-sparse-approximate-inverse objective): with
+  G = (I + F) W and a probe vector w (Gaussian: a Hutchinson estimate of
+  ||G S G^T - I||_F^2),
+      loss = ||(G S G^T - I) w||^2 / ||(W S W^T - I) w||^2.
 
-the energy-norm error after one preconditioned step relative to block-Jacobi's
-(1 at omega = 0).
+  Energy (on pairs from the method's own CG solves): for an error e (scaled
+  by the RMS of BJ^{-1} r) and r = S e,
+      loss = (P r - e)^T S (P r - e) / (BJ^{-1} r - e)^T S (BJ^{-1} r - e),
+  the energy-norm error after one preconditioned step relative to
+  block-Jacobi's.  Late CG errors are smooth, so this loss rewards amplifying
+  smooth modes and drives omega towards its cap, where I + F comes close to
+  singular on other modes; the Frobenius loss weighs every mode alike.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -195,3 +202,62 @@ def energy_loss_grad(theta, grid, node, edge, sysm, rhat, target):
         np.add.at(dh, j, dn[:, None] * P["w_hj"][None, :])
     gnn.trunk_backward(P, grid, edge, acts, dh, G)
     return L, gnn.pack(G, N, param_shapes(N))
+
+
+def _head_backward(theta, grid, edge, sysm, P, h, acts, sig, dom):
+    """Gradient of the loss from d loss / d omega (K x 3) through head and trunk."""
+    N = sysm.N
+    da = np.where(sysm.mask, dom, 0.0) * OMEGA_MAX * sig * (1.0 - sig)
+    G = {k: np.zeros_like(v_) for k, v_ in P.items()}
+    dh = np.zeros_like(h)
+    for n in range(3):
+        m = sysm.mask[:, n]
+        j = sysm.kp[m, n]
+        dn = da[m, n]
+        G["w_hk"] = G["w_hk"] + h[m].T @ dn
+        G["w_hj"] = G["w_hj"] + h[j].T @ dn
+        G["w_e"] = G["w_e"] + edge[m, n].T @ dn
+        G["w_o"] = G["w_o"] + sysm.lognorm[m, n] @ dn
+        G["b_o"] = G["b_o"] + dn.sum()
+        dh[m] += dn[:, None] * P["w_hk"][None, :]
+        np.add.at(dh, j, dn[:, None] * P["w_hj"][None, :])
+    gnn.trunk_backward(P, grid, edge, acts, dh, G)
+    return gnn.pack(G, N, param_shapes(N))
+
+
+def frobenius_loss(theta, grid, node, edge, sysm, w):
+    """||(G S G^T - I) w||^2 / ||(W S W^T - I) w||^2 for a probe w (K x N)."""
+    w = w.reshape(-1)
+    om = omega(theta, grid, node, edge, sysm)
+    G = (sp.eye(sysm.K * sysm.N) + sysm.F(om)) @ sysm.Wg
+    r = G @ (sysm.S @ (G.T @ w)) - w
+    r0 = sysm.Wg @ (sysm.S @ (sysm.Wg.T @ w)) - w
+    return (r @ r) / (r0 @ r0)
+
+
+def frobenius_loss_grad(theta, grid, node, edge, sysm, w):
+    """(loss, d loss / d theta): with u = G^T w, y = W S u, v = (I + F) y,
+    g = 2 (v - w) / den and beta = W S W^T (I + F)^T g,
+    d loss / d F_kj = g_k y_j^T + w_k beta_j^T."""
+    K, N = sysm.K, sysm.N
+    w = w.reshape(-1)
+    om, (P, h, acts, sig) = omega(theta, grid, node, edge, sysm, keep=True)
+    Fm = sysm.F(om)
+    I = sp.eye(K * N)
+    Wg, S = sysm.Wg, sysm.S
+    u = Wg.T @ ((I + Fm).T @ w)
+    y = Wg @ (S @ u)
+    v = (I + Fm) @ y
+    r0 = Wg @ (S @ (Wg.T @ w)) - w
+    den = r0 @ r0
+    L = ((v - w) @ (v - w)) / den
+    g = 2.0 * (v - w) / den
+    beta = Wg @ (S @ (Wg.T @ ((I + Fm).T @ g)))
+    Wv, Y, Gv, Bv = (x.reshape(K, N) for x in (w, y, g, beta))
+    dom = np.zeros((K, 3))
+    for n in range(3):
+        j = np.where(sysm.mask[:, n], sysm.kp[:, n], 0)
+        Ob = sysm.O[:, n]
+        dom[:, n] = -(np.einsum("ki,kij,kj->k", Gv, Ob, Y[j])
+                      + np.einsum("ki,kij,kj->k", Wv, Ob, Bv[j]))
+    return L, _head_backward(theta, grid, edge, sysm, P, h, acts, sig, dom)

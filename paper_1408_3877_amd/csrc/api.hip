@@ -1365,7 +1365,8 @@ ldg_status ldg_gnn_factor_export(ldg_ctx* c, double* blocks, float* lognorm) {
 }
 
 ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
-  if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY))
+  if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY &&
+             loss != LDG_GNN_LOSS_FROBENIUS))
     return fail(c, LDG_EINVAL, "unknown loss");
   c->gloss = loss;
   c->g_energy_ready = false;
@@ -1455,8 +1456,51 @@ ldg_status gnn_factor_loss_grad(ldg_ctx* c, double* loss) {
   return check_launch(c);
 }
 
+// Factored preconditioner, Frobenius loss for a probe w (the rhat input):
+//   loss = ||(G S G^T - I) w||^2 / ||(W S W^T - I) w||^2,  G = (I + F) W;
+// with u = G^T w, y = W S u, g = 2 ((I + F) y - w) / den and
+// beta = W S W^T (I + F)^T g:  d loss / d F_kj = g_k y_j^T + w_k beta_j^T.
+ldg_status gnn_factor_frob_grad(ldg_ctx* c, double* loss) {
+  if (!c->g_energy_ready) return fail(c, LDG_EINVAL, "no context set");
+  TRY(fac_alloc(c, true));
+  const Level L = level64(c);
+  const int64_t n = c->nvec;
+  const int N = c->N;
+  double** v = c->fac_v;
+  launch_fac_omega(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT, c->fac_om, c->st);
+  launch_cast(VT_F32, VT_F64, n, 1.0, c->g_rhat, v[0], c->st);                // w
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, true, v[0], v[1], c->st);     // u = G^T w
+  apply_op(c, L, c->gtau, v[1], false, L.tz1, L.tz2, v[2]);                    // S u
+  launch_fac_w(N, c->geo, c->fac_blk, v[2], v[3], c->st);                      // y
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, false, v[3], v[4], c->st);    // (I + F) y
+  launch_axpy_into64(VT_F64, n, -1.0, v[0], v[4], c->st);                      // residual
+  kdots(c, L, 1, v[4], v[4]);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  const double num = c->host_buf[0];
+  launch_fac_wt(N, c->geo, c->fac_blk, v[0], v[5], c->st);                     // W^T w
+  apply_op(c, L, c->gtau, v[5], false, L.tz1, L.tz2, v[6]);
+  launch_fac_w(N, c->geo, c->fac_blk, v[6], v[5], c->st);
+  launch_axpy_into64(VT_F64, n, -1.0, v[0], v[5], c->st);                      // (W S W^T - I) w
+  kdots(c, L, 1, v[5], v[5]);
+  TRY(fetch(c, c->red.result, 1, c->host_buf));
+  const double den = c->host_buf[0];
+  if (!(den > 0.0) || !std::isfinite(num))
+    return fail(c, LDG_ENOCONV, "Frobenius loss: zero probe or non-finite value");
+  launch_cast(VT_F64, VT_F64, n, 2.0 / den, v[4], v[5], c->st);                // g
+  launch_fac_f(N, c->geo, c->fac_blk, c->fac_om, true, v[5], v[6], c->st);     // G^T g
+  apply_op(c, L, c->gtau, v[6], false, L.tz1, L.tz2, v[7]);
+  launch_fac_w(N, c->geo, c->fac_blk, v[7], v[6], c->st);                      // beta
+  launch_fac_domega(N, c->geo, c->fac_blk, v[0], v[6], v[5], v[3], c->fac_dom, c->st);
+  launch_fac_omega_backward(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT,
+                            c->fac_om, c->fac_dom, c->gS, c->gGrad, c->st);
+  *loss = num / den;
+  return check_launch(c);
+}
+
 ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
-  if (c->gmode == LDG_GNN_FACTOR) return gnn_factor_loss_grad(c, loss);
+  if (c->gmode == LDG_GNN_FACTOR)
+    return c->gloss == LDG_GNN_LOSS_FROBENIUS ? gnn_factor_frob_grad(c, loss)
+                                              : gnn_factor_loss_grad(c, loss);
   Timed tm(c, LDG_K_GNN, 0.0, 0.0);
   launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gT, c->g_out, c->st);
   if (c->gloss == LDG_GNN_LOSS_ENERGY) {

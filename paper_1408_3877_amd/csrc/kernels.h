@@ -115,6 +115,8 @@ void launch_fac_apply(int N, int vt, const Geo& g, const float* fb, const float*
                       hipStream_t st);
 void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double* y,
                   hipStream_t st);
+void launch_fac_wt(int N, const Geo& g, const float* fb, const double* x, double* y,
+                   hipStream_t st);
 // out = (I + F) x, or W^T (I + F)^T x
 void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,
                   const double* x, double* out, hipStream_t st);

@@ -228,6 +228,20 @@ __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BT* __restric
   store_vec<N, T>(y, k, acc);
 }
 
+// y = W^T x
+template <int N, class T, class BT>
+__global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BT* __restrict__ fb,
+                                                const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpad) return;
+  T xv[N], acc[N];
+  load_vec<N, T>(x, k, xv);
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i] = 0;
+  block_mtv<N, BT, T>(fb, k, 0, FAC_SLOTS, xv, acc);
+  store_vec<N, T>(y, k, acc);
+}
+
 // out = (I + F) x  (NBR false: omega_kn), or (I + F)^T x  (NBR true: omega_{k+ n+},
 // O_kn standing for O_{k+ n+}^T), followed by out = W^T out when WT.
 // partials (optional): per-block sums of <r, out> for the preconditioned dot.
@@ -378,6 +392,12 @@ void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double*
                   hipStream_t st) {
   LDG_SWITCH_N(N, (k_fac_w<NT, double, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g.Kpad, fb, x,
                                                                                  y)));
+}
+
+void launch_fac_wt(int N, const Geo& g, const float* fb, const double* x, double* y,
+                   hipStream_t st) {
+  LDG_SWITCH_N(N, (k_fac_wt<NT, double, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g.Kpad, fb, x,
+                                                                                  y)));
 }
 
 void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,

@@ -13,7 +13,9 @@
    relative to that of the block-Jacobi step (default) or, for the
    residual-correction network, on the mean squared error of the correction.
    --mode factor (default) trains the factored preconditioner (a linear SPD
-   operator built once per system), --mode correction the per-iteration
+   operator built once per system), by default on the Frobenius objective
+   ||G S G^T - I||_F^2 estimated with Gaussian probe vectors on the systems
+   of the method's steps; --mode correction the per-iteration
    residual-correction network.
 3. Evaluation: the same steps on held-out fields with block-Jacobi CG and
    with the learned preconditioner (flexible CG, block-Jacobi fallback);
@@ -137,6 +139,39 @@ def train(solver, data, epochs, lr, dt, seed):
     return losses
 
 
+def systems(solver, n, seeds, sigma, steps, dt):
+    """The projected coefficients of the method's steps (one system per step)."""
+    out = []
+    for sd in seeds:
+        dT = field(n, sd, sigma)
+        t = 0.0
+        for _ in range(steps):
+            t += dt
+            out.append(solver.project(solver.sample_workload(LOGNORMAL, t, dT=dT, want=("d",))["d"]).clone())
+    return out
+
+
+def train_probes(solver, sys_list, epochs, probes, lr, dt, seed):
+    """Adam on the Frobenius loss: every system, `probes` Gaussian probe vectors
+    per visit (drawn here, seeded, and passed in)."""
+    rng = np.random.default_rng(seed)
+    K, N = solver.K, solver.N
+    losses = []
+    step, total = 0, epochs * len(sys_list) * probes
+    for ep in range(epochs):
+        acc = 0.0
+        for i in rng.permutation(len(sys_list)):
+            solver.gnn_set_context(sys_list[i], dt)
+            for _ in range(probes):
+                w = rng.standard_normal((K, N)).astype(np.float32)
+                lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / total))
+                acc += solver.gnn_train_step(w, w, lr_t)
+                step += 1
+        losses.append(acc / (len(sys_list) * probes))
+        log("[train] epoch %d mean loss %.5f" % (ep, losses[-1]))
+    return losses
+
+
 def evaluate(solver, n, seeds, sigma, steps, dt, use_gnn):
     """Mean iterations and seconds per step (block-Jacobi or learned)."""
     torch = solver.torch
@@ -186,13 +221,19 @@ def main(argv=None):
                     help="collection rounds (1: block-Jacobi solves only)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=7)
-    ap.add_argument("--loss", choices=("energy", "mse"), default="energy")
+    ap.add_argument("--loss", choices=("frobenius", "energy", "mse"), default=None,
+                    help="default: frobenius (factor mode), energy (correction mode)")
+    ap.add_argument("--probes", type=int, default=8, help="probe vectors per system visit")
     ap.add_argument("--mode", choices=("correction", "factor"), default="factor",
                     help="per-iteration residual correction, or factored preconditioner")
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="skip collection and training, evaluate these")
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
+    if a.loss is None:
+        a.loss = "frobenius" if a.mode == "factor" else "energy"
+    if a.loss == "frobenius" and a.mode != "factor":
+        ap.error("the Frobenius loss belongs to the factored preconditioner")
     import torch
 
     from . import Solver
@@ -216,7 +257,17 @@ def main(argv=None):
         w = init(sv.N, a.init_seed)
         data, losses, t_collect, t_train = [], [], 0.0, 0.0
         sl = None
-        for rd in range(a.rounds):
+        if a.loss == "frobenius":
+            t0 = time.perf_counter()
+            data = systems(sv, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
+            t_collect = time.perf_counter() - t0
+            sv.gnn_set_params(w)
+            sv.gnn_set_loss(a.loss)
+            t0 = time.perf_counter()
+            losses = train_probes(sv, data, a.epochs, a.probes, a.lr, a.dt, a.init_seed)
+            t_train = time.perf_counter() - t0
+            w = sv.gnn_get_params()
+        for rd in range(a.rounds if a.loss != "frobenius" else 0):
             src = sv
             if rd > 0:
                 if sl is None:
@@ -240,18 +291,26 @@ def main(argv=None):
     # the training loss on held-out systems (one step per evaluation field)
     sv.gnn_set_params(w)
     sv.gnn_set_loss(a.loss)
-    held = collect(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt)
     hl = []
-    for r, tg, D in held:
-        sv.gnn_set_context(D, a.dt)
-        hl.append(sv.gnn_loss_grad(r, tg)[0])
-    del held[:]
+    if a.loss == "frobenius":
+        rng = np.random.default_rng(a.init_seed + 1000)
+        for D in systems(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt):
+            sv.gnn_set_context(D, a.dt)
+            for _ in range(4):
+                pw = rng.standard_normal((sv.K, sv.N)).astype(np.float32)
+                hl.append(sv.gnn_loss_grad(pw, pw)[0])
+    else:
+        held = collect(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt)
+        for r, tg, D in held:
+            sv.gnn_set_context(D, a.dt)
+            hl.append(sv.gnn_loss_grad(r, tg)[0])
+        del held[:]
     ev = evaluate(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, False)
     sg = learned_solver()
     sg.gnn_set_params(w)
     eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
     rep = {"p": a.p, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
-           "epochs": a.epochs, "rounds": a.rounds, "mode": a.mode, "loss": a.loss, "loss_per_epoch": losses,
+           "epochs": a.epochs, "rounds": a.rounds, "mode": a.mode, "loss": a.loss, "probes": a.probes, "loss_per_epoch": losses,
            "heldout_loss": float(np.mean(hl)), "block_jacobi": ev, "learned": eg,
            "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],
            "time_ratio": eg["s_per_step"] / ev["s_per_step"]}

@@ -131,3 +131,57 @@ def test_loss_is_one_at_zero_omega():
     L = gf.energy_loss(gnn.pack(P, N, gf.param_shapes(N)), g, node, edge, sy,
                        rng.standard_normal((sy.K, N)), rng.standard_normal((sy.K, N)))
     assert abs(L - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_frobenius_loss_gradient_matches_finite_differences(p):
+    g, D, dt, sy = _system(4, p, 40 + p)
+    N = sy.N
+    node, edge = gnn.features(g, D, dt, 1.0)
+    rng = np.random.default_rng(15 + p)
+    theta = gf.init_params(N, 9) + 0.05 * rng.standard_normal(gf.n_params(N))
+    w = rng.standard_normal((sy.K, N))
+    L, G = gf.frobenius_loss_grad(theta, g, node, edge, sy, w)
+    assert abs(L - gf.frobenius_loss(theta, g, node, edge, sy, w)) <= 1e-12 * L
+    n_head = sum(int(np.prod(s_)) for _, s_ in gf.HEAD)
+    idx = np.concatenate([np.arange(gf.n_params(N) - n_head, gf.n_params(N)),
+                          rng.choice(gf.n_params(N) - n_head, 150, replace=False)])
+    eps = 1e-6
+    floor = 1e-3 * np.abs(G).max()
+    worst = 0.0
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd = (gf.frobenius_loss(tp, g, node, edge, sy, w)
+              - gf.frobenius_loss(tm, g, node, edge, sy, w)) / (2 * eps)
+        worst = max(worst, abs(fd - G[i]) / max(floor, abs(G[i])))
+    assert worst < 1e-5, worst
+
+
+def test_frobenius_loss_is_the_fsai_functional_in_expectation():
+    # E_w ||(G S G^T - I) w||^2 = ||G S G^T - I||_F^2 for w ~ N(0, I): average
+    # over many probes against the exact Frobenius norms (ratio of the two)
+    g, D, dt, sy = _system(4, 1, 50)
+    N, K = sy.N, sy.K
+    node, edge = gnn.features(g, D, dt, 1.0)
+    theta = gf.init_params(N, 2)
+    om = gf.omega(theta, g, node, edge, sy)
+    Gm = ((np.eye(K * N) + sy.F(om).toarray()) @ sy.Wg.toarray())
+    Sd = sy.S.toarray()
+    num = np.linalg.norm(Gm @ Sd @ Gm.T - np.eye(K * N)) ** 2
+    W = sy.Wg.toarray()
+    den = np.linalg.norm(W @ Sd @ W.T - np.eye(K * N)) ** 2
+    rng = np.random.default_rng(0)
+    nums, dens = [], []
+    for _ in range(400):
+        w = rng.standard_normal(K * N)
+        nums.append(np.sum((Gm @ (Sd @ (Gm.T @ w)) - w) ** 2))
+        dens.append(np.sum((W @ (Sd @ (W.T @ w)) - w) ** 2))
+    assert abs(np.mean(nums) / num - 1) < 0.1
+    assert abs(np.mean(dens) / den - 1) < 0.1
+    # one probe's loss is the ratio the device computes
+    w = rng.standard_normal((K, N))
+    r = Gm @ (Sd @ (Gm.T @ w.reshape(-1))) - w.reshape(-1)
+    r0 = W @ (Sd @ (W.T @ w.reshape(-1))) - w.reshape(-1)
+    assert abs(gf.frobenius_loss(theta, g, node, edge, sy, w) - (r @ r) / (r0 @ r0)) < 1e-12
