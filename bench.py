@@ -2,12 +2,18 @@
 
 One "step" is one implicit Euler step of the whole hot path: sampling the
 coefficient data at the quadrature points, L2 projection, block assembly,
-block-Jacobi setup, the Krylov solve to the relative residual of the full
-3KN system, recovery of Z.  Metric: DOF*steps/s with DOF = 3KN (C, Z1, Z2).
+block-Jacobi setup, the learned preconditioner's setup (network inference and
+factor blocks), the Krylov solve to the relative residual of the full 3KN
+system, recovery of Z.  Metric: DOF*steps/s with DOF = 3KN (C, Z1, Z2).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config combined-p4-1024]
+                  [--precision fp64|fp32|bf16] [--precond bj|learned] [--weights F]
+                  [--no-baseline] [--no-cpu-baseline]
 
-Prints one JSON line (rank 0).  Progress goes to stderr.
+The default run times the mixed-precision (BF16 contractions, FP64
+refinement) solver with the learned factored preconditioner on the combined
+workload, then the plain FP64 block-Jacobi solver on the same workload for
+comparison.  Prints one JSON line (rank 0).  Progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -15,6 +21,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -36,6 +44,9 @@ CONFIGS = {
                              field_seed=5000, dt=1e-4),
 }
 DEFAULT = "combined-p4-1024"
+# trained weights of the factored preconditioner per order (learned.py)
+WEIGHTS = {4: os.path.join(ROOT, "paper_1408_3877_amd", "weights", "factor_p4.npy"),
+           3: os.path.join(ROOT, "paper_1408_3877_amd", "weights", "factor_p3.npy")}
 
 
 def log(*a):
@@ -51,6 +62,64 @@ def make_inputs(cfg):
     return coordV, V0T, kind, dT
 
 
+def dt_of(cfg):
+    return cfg["dt"]
+
+
+def kernel_table(stats):
+    return {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                "GB/s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                if v["total_ms"] > 0 else None} for k, v in stats.items()}
+
+
+def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights, args, label):
+    """Warmup steps, then args.steps timed steps of one solver configuration."""
+    t0 = time.perf_counter()
+    s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
+               max_iters=20000, precision=prec, inner_rtol=args.inner_rtol,
+               precond=1 if learned else 0)
+    if learned:
+        s.gnn_set_mode("factor")
+        s.gnn_set_params(weights)
+    log("[bench] %s: context K=%d N=%d (%.1f s)" % (label, s.K, s.N, time.perf_counter() - t0))
+    gk = cfg["kind"]
+    s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
+    state = {"t": 0.0}
+    dt = cfg["dt"]
+
+    def one_step():
+        state["t"] += dt
+        smp = s.sample_workload(gk, state["t"], dT=dT)
+        return s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+
+    for i in range(args.warmup):
+        info = one_step()
+        log("[bench] %s warmup %d: iters=%d learned=%d rel_res=%.2e" %
+            (label, i, info["iters"], info["learned_iters"], info["rel_residual"]))
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        info = one_step()
+        infos.append(info)
+        log("[bench] %s step %d: iters=%d learned=%d sweeps=%d fallbacks=%d krylov=%d rel_res=%.2e"
+            % (label, i, info["iters"], info["learned_iters"], info["restarts"], info["fallbacks"],
+               info["krylov"], info["rel_residual"]))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stats = s.kernel_stats()
+    s.set_timing(False)
+    return {"solver": s, "elapsed": el, "infos": infos, "stats": stats}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_1408_3877_amd", "csrc"))):
@@ -59,15 +128,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(config, kernel, precision, precond):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when it is absent or the kernels changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    summary, or None when it is absent, for another run, or the kernels
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % config)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if (rec.get("kernel"), rec.get("precision"), rec.get("precond")) != (kernel, precision, precond):
         return None
     return rec.get("bytes_per_launch")
 
@@ -109,16 +181,21 @@ def main():
     ap.add_argument("--config", default=DEFAULT, choices=sorted(CONFIGS))
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+    ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16"],
                     help="inner-solve precision (fp32/bf16: mixed with FP64 refinement)")
+    ap.add_argument("--precond", default="learned", choices=["bj", "learned"],
+                    help="block-Jacobi, or the learned factored preconditioner")
+    ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
+    ap.add_argument("--no-baseline", action="store_true",
+                    help="skip timing the plain FP64 block-Jacobi solver for comparison")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -127,57 +204,40 @@ def main():
     log("[bench] config %s: building inputs" % args.config)
     coordV, V0T, kind, dT = make_inputs(cfg)
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
+    learned = args.precond == "learned"
+    weights = None
+    if learned:
+        path = args.weights or WEIGHTS.get(cfg["p"])
+        if not path or not os.path.exists(path):
+            log("[bench] no trained weights for p=%d (%s)" % (cfg["p"], path))
+            sys.exit(2)
+        weights = np.load(path).astype(np.float32)
     prec = {"fp64": 0, "fp32": 1, "bf16": 2}[args.precision]
-    s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
-               max_iters=20000, precision=prec, inner_rtol=args.inner_rtol)
-    log("[bench] context: K=%d N=%d (%.1f s)" % (s.K, s.N, time.perf_counter() - t0))
-    gk = cfg["kind"]
-    s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
-    t = 0.0
-    dt = cfg["dt"]
-    infos = []
-
-    def one_step():
-        nonlocal t
-        t += dt
-        smp = s.sample_workload(gk, t, dT=dT)
-        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
-        return info
-
-    for i in range(args.warmup):
-        info = one_step()
-        log("[bench] warmup %d: iters=%d rel_res=%.2e" % (i, info["iters"], info["rel_residual"]))
-    if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-    torch.cuda.synchronize()
-    s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        info = one_step()
-        infos.append(info)
-        log("[bench] step %d: iters=%d sweeps=%d fallbacks=%d krylov=%d rel_res=%.2e" %
-            (i, info["iters"], info["restarts"], info["fallbacks"], info["krylov"],
-             info["rel_residual"]))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    stats = s.kernel_stats()
-    s.set_timing(False)
+    run = timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights, args,
+                    "headline")
+    base = None
+    if not args.no_baseline and (prec != 0 or learned):
+        base = timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, 0, False, None, args,
+                         "fp64 block-Jacobi")
+    s, el, infos, stats = run["solver"], run["elapsed"], run["infos"], run["stats"]
     dof = 3 * s.K * s.N
     value = dof * args.steps / el
-    dv = stats["div"]
-    ach = dv["bytes"] / (dv["total_ms"] * 1e-3) / 1e9 if dv["total_ms"] > 0 else 0.0
-    # the roofline is reported for the FP64 operator apply; in the mixed modes the
-    # launches mix FP64 residual applies and low-precision inner applies
-    per_launch = dv["bytes"] / max(dv["launches"], 1)
-    traffic = measured_traffic(args.config)
+    # roofline of the kernel that takes the most time in the timed steps
+    name = max(("div", "factor", "bj_apply", "grad"), key=lambda k: stats[k]["total_ms"])
+    kv = stats[name]
+    ach = kv["bytes"] / (kv["total_ms"] * 1e-3) / 1e9 if kv["total_ms"] > 0 else 0.0
+    per_launch = kv["bytes"] / max(kv["launches"], 1)
+    kernel_desc = {"div": "k_div (operator apply, stored blocks)",
+                   "factor": "k_fac_w + k_fac_f (learned factored preconditioner apply)",
+                   "bj_apply": "k_bj_apply (block-Jacobi apply)",
+                   "grad": "k_grad (operator gradient half)"}[name]
+    traffic = measured_traffic(args.config, name, args.precision, args.precond)
+    solver_desc = "%s %s %s%s" % (
+        args.precision, "learned factored" if learned else "block-Jacobi",
+        "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
+        "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol)
     res = {
-        "metric": "DOF*steps/s (p=4, 2M tris) to 1e-8 rel res",
+        "metric": "DOF·steps/s (p=4, 2M tris) to 1e-8 rel res: plain FP64 vs mixed+learned precond",
         "value": value,
         "unit": "DOF*steps/s",
         "n_gpus": 1,
@@ -190,22 +250,36 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
-                   "dt": dt, "rtol": args.rtol,
-                   "solver": "%s block-Jacobi %s%s" % (
-                       args.precision, "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
-                       "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol),
+                   "dt": dt_of(cfg), "rtol": args.rtol, "solver": solver_desc,
+                   "weights": os.path.relpath(args.weights or WEIGHTS.get(cfg["p"]), ROOT)
+                   if learned else None,
                    "iters_per_step": sum(i["iters"] for i in infos) / len(infos),
-                   "fallbacks": sum(i["fallbacks"] for i in infos)},
-        "roofline": {"bound": "hbm", "kernel": "k_div (operator apply, stored blocks)",
+                   "learned_iters_per_step": sum(i["learned_iters"] for i in infos) / len(infos),
+                   "refinement_sweeps_per_step": sum(i["ir_steps"] for i in infos) / len(infos),
+                   "fallbacks": sum(i["fallbacks"] for i in infos),
+                   "max_rel_residual": max(i["rel_residual"] for i in infos)},
+        "roofline": {"bound": "hbm", "kernel": kernel_desc,
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": per_launch,
-                     "avg_launch_ms": dv["total_ms"] / max(dv["launches"], 1),
+                     "avg_launch_ms": kv["total_ms"] / max(kv["launches"], 1),
                      "traffic": traffic},
-        "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
-                        "GB/s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
-                        if v["total_ms"] > 0 else None} for k, v in stats.items()},
+        "kernels": kernel_table(stats),
     }
+    if base is not None:
+        bs = base["solver"]
+        bv = dof * args.steps / base["elapsed"]
+        bk = base["stats"]["div"]
+        res["baseline_fp64_bj"] = {
+            "value": bv, "ms_per_step": base["elapsed"] * 1e3 / args.steps,
+            "iters_per_step": sum(i["iters"] for i in base["infos"]) / len(base["infos"]),
+            "k_div_GBs": bk["bytes"] / (bk["total_ms"] * 1e-3) / 1e9 if bk["total_ms"] > 0 else None,
+            "kernels": kernel_table(base["stats"])}
+        res["speedup_vs_fp64_bj"] = value / bv
+        # the two solutions agree to the solver tolerance
+        c1 = s.get_solution()[0]
+        c0 = bs.get_solution()[0]
+        res["rel_l2_diff_vs_fp64_bj"] = float(((c1 - c0).norm() / c0.norm()).item())
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(cfg)

@@ -346,9 +346,18 @@ ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
  * boundary edges) from the current parameters, and the factor blocks
  * (device K x 4 x N x N FP64: W_k, O_k0, O_k1, O_k2 row-major, O on boundary
  * edges undefined; may be NULL) with log ||O_kn||_F (device K x 3 FP32,
- * undefined on boundary edges; may be NULL).  The blocks are stored in FP32.
+ * undefined on boundary edges; may be NULL), as stored (see below).
  */
 ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
+/*
+ * Storage of the factor blocks W_k, O_kn: LDG_FAC_BF16 (default; halves the
+ * application's traffic) or LDG_FAC_F32.  P stays exactly symmetric positive
+ * definite in either, the same rounded blocks forming G and G^T; the
+ * solution's accuracy is set by the FP64 residual as always.  Takes effect at
+ * the next factor build (step or ldg_gnn_set_context).
+ */
+typedef enum { LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1 } ldg_fac_storage;
+ldg_status ldg_gnn_factor_storage(ldg_ctx* ctx, int storage);
 ldg_status ldg_gnn_factor_export(ldg_ctx* ctx, double* blocks, float* lognorm);
 /*
  * loss (as selected by ldg_gnn_set_loss) and its gradient (device, n_params

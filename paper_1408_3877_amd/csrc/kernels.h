@@ -102,27 +102,29 @@ void launch_fac_omega_backward(int N, const Geo& g, const float* P, const float*
 void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr, int step,
                  hipStream_t st);
 
-// kernels_factor.hip: factor blocks (FP32, FAC_SLOTS per triangle: W_k, O_k0..2)
+// kernels_factor.hip: factor blocks (FAC_SLOTS per triangle: W_k, O_k0..2) stored
+// as BT_F32 or BT_BF16 (bt), arithmetic in the vector type
 constexpr int FAC_SLOTS = 4;
 // W (FP64 scratch w64 and slot 0), O blocks and log ||O||_F from the FP64
 // operator blocks and block-Jacobi inverses; status |= 2 on a failed Cholesky
-void launch_fac_setup(int N, const Geo& g, const double* refs, const double* blocks,
-                      const double* bj, double tau, double eta, double* w64, float* fb,
+void launch_fac_setup(int N, int bt, const Geo& g, const double* refs, const double* blocks,
+                      const double* bj, double tau, double eta, double* w64, void* fb,
                       float* lognorm, int* status, hipStream_t st);
 // z = P r through y, a (work vectors); red: result[0] = <r, z>
-void launch_fac_apply(int N, int vt, const Geo& g, const float* fb, const float* om,
+void launch_fac_apply(int N, int bt, int vt, const Geo& g, const void* fb, const float* om,
                       const void* r, void* y, void* a, void* z, const Reducer* red,
                       hipStream_t st);
-void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double* y,
+void launch_fac_w(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
                   hipStream_t st);
-void launch_fac_wt(int N, const Geo& g, const float* fb, const double* x, double* y,
+void launch_fac_wt(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
                    hipStream_t st);
 // out = (I + F) x, or W^T (I + F)^T x
-void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,
-                  const double* x, double* out, hipStream_t st);
-void launch_fac_domega(int N, const Geo& g, const float* fb, const double* a, const double* beta,
-                       const double* alpha, const double* y, float* dom, hipStream_t st);
-void launch_fac_export(int64_t K, int N, const float* fb, double* out, hipStream_t st);
+void launch_fac_f(int N, int bt, const Geo& g, const void* fb, const float* om,
+                  bool transpose_and_wt, const double* x, double* out, hipStream_t st);
+void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double* a,
+                       const double* beta, const double* alpha, const double* y, float* dom,
+                       hipStream_t st);
+void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st);
 void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,
                        hipStream_t st);
 void launch_from_tiled_f(int64_t K, int N, const float* src, float* dst, hipStream_t st);

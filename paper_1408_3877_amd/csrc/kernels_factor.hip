@@ -328,21 +328,6 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict_
   }
 }
 
-// export of the factor blocks: out[k][s][i][j] (FP64, row-major)
-template <class BT>
-__global__ void k_fac_export(int64_t K, int N, const BT* __restrict__ fb,
-                             double* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int NN = N * N;
-  if (t >= K * FAC_SLOTS * NN) return;
-  const int f = (int)(t % NN);
-  const int s = (int)((t / NN) % FAC_SLOTS);
-  const int64_t k = t / ((int64_t)NN * FAC_SLOTS);
-  constexpr int Wv = Blk<BT>::W;
-  const int NG = ngroups(N, Wv);
-  out[t] = (double)fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv];
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -356,70 +341,89 @@ __global__ void k_fac_export(int64_t K, int N, const BT* __restrict__ fb,
     default: break;                                             \
   }
 
-void launch_fac_setup(int N, const Geo& g, const double* refs, const double* blocks,
-                      const double* bj, double tau, double eta, double* w64, float* fb,
+#define LDG_SWITCH_BT(BTV, CALL)                                \
+  if ((BTV) == BT_BF16) {                                       \
+    using BTT = bf16;                                           \
+    CALL;                                                       \
+  } else {                                                      \
+    using BTT = float;                                          \
+    CALL;                                                       \
+  }
+
+void launch_fac_setup(int N, int bt, const Geo& g, const double* refs, const double* blocks,
+                      const double* bj, double tau, double eta, double* w64, void* fb,
                       float* lognorm, int* status, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_fac_chol<NT, float><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(g, bj, w64, fb,
-                                                                                 status)));
-  LDG_SWITCH_N(N, (k_fac_offdiag<NT, float><<<nbk(g.Kpad, 4), 64, 0, st>>>(
-                      g, refs, blocks, w64, tau, eta, fb, lognorm)));
+  LDG_SWITCH_BT(bt, {
+    LDG_SWITCH_N(N, (k_fac_chol<NT, BTT><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
+                        g, bj, w64, (BTT*)fb, status)));
+    LDG_SWITCH_N(N, (k_fac_offdiag<NT, BTT><<<nbk(g.Kpad, 4), 64, 0, st>>>(
+                        g, refs, blocks, w64, tau, eta, (BTT*)fb, lognorm)));
+  })
 }
 
-void launch_fac_apply(int N, int vt, const Geo& g, const float* fb, const float* om,
+void launch_fac_apply(int N, int bt, int vt, const Geo& g, const void* fb, const float* om,
                       const void* r, void* y, void* a, void* z, const Reducer* red,
                       hipStream_t st) {
   const unsigned nb = nbk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
-  if (vt == VT_F64) {
-    using T = double;
-    LDG_SWITCH_N(N, (k_fac_w<NT, T, float><<<nb, 256, 0, st>>>(g.Kpad, fb, (const T*)r, (T*)y)));
-    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, false, false><<<nb, 256, 0, st>>>(
-                        g, fb, om, (const T*)y, (T*)a, nullptr, nullptr)));
-    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, true, true><<<nb, 256, 0, st>>>(
-                        g, fb, om, (const T*)a, (T*)z, (const T*)r, parts)));
-  } else {
-    using T = float;
-    LDG_SWITCH_N(N, (k_fac_w<NT, T, float><<<nb, 256, 0, st>>>(g.Kpad, fb, (const T*)r, (T*)y)));
-    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, false, false><<<nb, 256, 0, st>>>(
-                        g, fb, om, (const T*)y, (T*)a, nullptr, nullptr)));
-    LDG_SWITCH_N(N, (k_fac_f<NT, T, float, true, true><<<nb, 256, 0, st>>>(
-                        g, fb, om, (const T*)a, (T*)z, (const T*)r, parts)));
-  }
+  LDG_SWITCH_BT(bt, {
+    const BTT* f = (const BTT*)fb;
+    if (vt == VT_F64) {
+      using T = double;
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BTT><<<nb, 256, 0, st>>>(g.Kpad, f, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, false, false><<<nb, 256, 0, st>>>(
+                          g, f, om, (const T*)y, (T*)a, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, true, true><<<nb, 256, 0, st>>>(
+                          g, f, om, (const T*)a, (T*)z, (const T*)r, parts)));
+    } else {
+      using T = float;
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BTT><<<nb, 256, 0, st>>>(g.Kpad, f, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, false, false><<<nb, 256, 0, st>>>(
+                          g, f, om, (const T*)y, (T*)a, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, true, true><<<nb, 256, 0, st>>>(
+                          g, f, om, (const T*)a, (T*)z, (const T*)r, parts)));
+    }
+  })
   if (red) reduce_partials((int)nb, red->partials, red->result, st);
 }
 
-void launch_fac_w(int N, const Geo& g, const float* fb, const double* x, double* y,
+void launch_fac_w(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
                   hipStream_t st) {
-  LDG_SWITCH_N(N, (k_fac_w<NT, double, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g.Kpad, fb, x,
-                                                                                 y)));
+  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_w<NT, double, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                        g.Kpad, (const BTT*)fb, x, y))))
 }
 
-void launch_fac_wt(int N, const Geo& g, const float* fb, const double* x, double* y,
+void launch_fac_wt(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
                    hipStream_t st) {
-  LDG_SWITCH_N(N, (k_fac_wt<NT, double, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g.Kpad, fb, x,
-                                                                                  y)));
+  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_wt<NT, double, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                        g.Kpad, (const BTT*)fb, x, y))))
 }
 
-void launch_fac_f(int N, const Geo& g, const float* fb, const float* om, bool transpose_and_wt,
-                  const double* x, double* out, hipStream_t st) {
+void launch_fac_f(int N, int bt, const Geo& g, const void* fb, const float* om,
+                  bool transpose_and_wt, const double* x, double* out, hipStream_t st) {
   const unsigned nb = nbk(g.Kpad, 256);
-  if (transpose_and_wt) {
-    LDG_SWITCH_N(N, (k_fac_f<NT, double, float, true, true><<<nb, 256, 0, st>>>(
-                        g, fb, om, x, out, nullptr, nullptr)));
-  } else {
-    LDG_SWITCH_N(N, (k_fac_f<NT, double, float, false, false><<<nb, 256, 0, st>>>(
-                        g, fb, om, x, out, nullptr, nullptr)));
-  }
+  LDG_SWITCH_BT(bt, {
+    const BTT* f = (const BTT*)fb;
+    if (transpose_and_wt) {
+      LDG_SWITCH_N(N, (k_fac_f<NT, double, BTT, true, true><<<nb, 256, 0, st>>>(
+                          g, f, om, x, out, nullptr, nullptr)));
+    } else {
+      LDG_SWITCH_N(N, (k_fac_f<NT, double, BTT, false, false><<<nb, 256, 0, st>>>(
+                          g, f, om, x, out, nullptr, nullptr)));
+    }
+  })
 }
 
-void launch_fac_domega(int N, const Geo& g, const float* fb, const double* a, const double* beta,
-                       const double* alpha, const double* y, float* dom, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_fac_domega<NT, float><<<nbk(g.Kpad, 256), 256, 0, st>>>(g, fb, a, beta,
-                                                                              alpha, y, dom)));
+void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double* a,
+                       const double* beta, const double* alpha, const double* y, float* dom,
+                       hipStream_t st) {
+  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_domega<NT, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                        g, (const BTT*)fb, a, beta, alpha, y, dom))))
 }
 
-void launch_fac_export(int64_t K, int N, const float* fb, double* out, hipStream_t st) {
-  k_fac_export<float><<<nbk(K * FAC_SLOTS * N * N, 256), 256, 0, st>>>(K, N, fb, out);
+// out[k][s][i][j] (FP64, row-major)
+void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st) {
+  launch_export_blocks_any(bt, K, N, FAC_SLOTS, fb, out, st);
 }
 
 }  // namespace ldg

@@ -81,6 +81,7 @@ _SIGS = {
     "ldg_gnn_set_mode": [_P, C.c_int],
     "ldg_gnn_factor_omega": [_P, _P],
     "ldg_gnn_factor_export": [_P, _P, _P],
+    "ldg_gnn_factor_storage": [_P, C.c_int],
     "ldg_gnn_set_loss": [_P, C.c_int],
     "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
     "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
@@ -291,6 +292,10 @@ class Solver:
         1 / "factor": linear factored preconditioner built once per system."""
         m = {"correction": 0, "factor": 1}.get(mode, mode)
         self._check(self.lib.ldg_gnn_set_mode(self.h, int(m)))
+
+    def gnn_factor_storage(self, kind):
+        """"f32" or "bf16" (default) storage of the factor blocks."""
+        self._check(self.lib.ldg_gnn_factor_storage(self.h, {"f32": 0, "bf16": 1}[kind]))
 
     def gnn_factor_omega(self):
         om = self.torch.empty((self.K, 3), dtype=self.torch.float32, device=self.device)

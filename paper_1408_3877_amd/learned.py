@@ -36,7 +36,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from inputs.fields import LOGNORMAL, lognormal_blocks, triangle_values  # noqa: E402
+from inputs.fields import LOGNORMAL, LOGNORMAL_T, lognormal_blocks, triangle_values  # noqa: E402
 from inputs.meshes import square_mesh  # noqa: E402
 
 SNAPS = [0, 1, 2, 3, 5, 8, 12, 18, 27, 40, 60, 90, 135, 200, 300, 450, 675, 1000, 1500, 2250]
@@ -94,6 +94,9 @@ def factor_init(N, seed, width=32, e_in=13, layers=3, omega0=0.6, omega_max=0.95
     return np.concatenate(parts).astype(np.float32)
 
 
+KIND = LOGNORMAL   # field family: LOGNORMAL, or LOGNORMAL_T (times 1 + 0.1 sin t)
+
+
 def field(n, seed, sigma):
     return triangle_values(lognormal_blocks(n, seed, sigma, block=8), n, block=8)
 
@@ -104,13 +107,13 @@ def collect(solver, n, seeds, sigma, steps, dt, snaps=SNAPS, per_step=None):
     data = []
     for sd in seeds:
         dT = field(n, sd, sigma)
-        solver.set_initial_samples(solver.sample_workload(LOGNORMAL, 0.0, dT=dT, want=("c0",))["c0"])
-        D = solver.project(solver.sample_workload(LOGNORMAL, dt, dT=dT, want=("d",))["d"]).clone()
+        solver.set_initial_samples(solver.sample_workload(KIND, 0.0, dT=dT, want=("c0",))["c0"])
+        D = solver.project(solver.sample_workload(KIND, dt, dT=dT, want=("d",))["d"]).clone()
         t = 0.0
         for _ in range(steps):
             t += dt
             r, tg = solver.gnn_collect(snaps if per_step is None else snaps[:per_step])
-            smp = solver.sample_workload(LOGNORMAL, t, dT=dT)
+            smp = solver.sample_workload(KIND, t, dT=dT)
             info = solver.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
             m = solver.gnn_collected()
             for q in range(m):
@@ -147,7 +150,7 @@ def systems(solver, n, seeds, sigma, steps, dt):
         t = 0.0
         for _ in range(steps):
             t += dt
-            out.append(solver.project(solver.sample_workload(LOGNORMAL, t, dT=dT, want=("d",))["d"]).clone())
+            out.append(solver.project(solver.sample_workload(KIND, t, dT=dT, want=("d",))["d"]).clone())
     return out
 
 
@@ -178,11 +181,11 @@ def evaluate(solver, n, seeds, sigma, steps, dt, use_gnn):
     its, secs, fbs, lits, why = [], [], 0, 0, []
     for sd in seeds:
         dT = field(n, sd, sigma)
-        solver.set_initial_samples(solver.sample_workload(LOGNORMAL, 0.0, dT=dT, want=("c0",))["c0"])
+        solver.set_initial_samples(solver.sample_workload(KIND, 0.0, dT=dT, want=("c0",))["c0"])
         t = 0.0
         for _ in range(steps):
             t += dt
-            smp = solver.sample_workload(LOGNORMAL, t, dT=dT)
+            smp = solver.sample_workload(KIND, t, dT=dT)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = solver.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
@@ -211,6 +214,8 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--jitter", type=int, default=1004)
     ap.add_argument("--sigma", type=float, default=1.5)
+    ap.add_argument("--kind", type=int, default=LOGNORMAL, choices=(LOGNORMAL, LOGNORMAL_T),
+                    help="3: block log-normal field, 4: the same times (1 + 0.1 sin t)")
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--train-seeds", default="4000-4019")
     ap.add_argument("--eval-seeds", default="4100,4101")
@@ -230,6 +235,8 @@ def main(argv=None):
     ap.add_argument("--weights", default=None, help="skip collection and training, evaluate these")
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
+    global KIND
+    KIND = a.kind
     if a.loss is None:
         a.loss = "frobenius" if a.mode == "factor" else "energy"
     if a.loss == "frobenius" and a.mode != "factor":
@@ -309,7 +316,7 @@ def main(argv=None):
     sg = learned_solver()
     sg.gnn_set_params(w)
     eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
-    rep = {"p": a.p, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
+    rep = {"p": a.p, "n": a.n, "kind": a.kind, "sigma": a.sigma, "dt": a.dt, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
            "epochs": a.epochs, "rounds": a.rounds, "mode": a.mode, "loss": a.loss, "probes": a.probes, "loss_per_epoch": losses,
            "heldout_loss": float(np.mean(hl)), "block_jacobi": ev, "learned": eg,
            "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],

@@ -20,7 +20,7 @@ from tests.gpu_common import rel_l2, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _setup(n, p, seed, ratio=6.5):
+def _setup(n, p, seed, ratio=6.5, storage="f32"):
     from paper_1408_3877_amd import Solver
     cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(NORTH,))
     g = Grid(cV, V0T, kind)
@@ -33,6 +33,7 @@ def _setup(n, p, seed, ratio=6.5):
     sy = gf.System(g, schur_matrix(Blocks(g, refs, D), g, refs, 1.0, dt))
     s = Solver(cV, V0T, kind, p)
     s.gnn_set_mode("factor")
+    s.gnn_factor_storage(storage)
     return g, D, dt, sy, s
 
 
@@ -61,6 +62,20 @@ def test_factor_blocks_and_omega_match_the_oracle(n, p, seed):
     got = to_np(s.gnn_factor_omega())
     assert np.abs(got - want).max() <= 1e-5
     assert np.all(got[~m] == 0.0)
+
+
+def test_factor_bf16_storage_rounds_the_fp32_blocks():
+    g, D, dt, sy, s = _setup(8, 3, 705, storage="bf16")
+    s.gnn_set_params(_theta(sy.N, 705))
+    s.gnn_set_context(D, dt)
+    blk = to_np(s.gnn_factor_export()[0])
+    m = sy.mask
+    # BF16 carries 8 bits of precision (7 stored): round to nearest (FP64 -> FP32
+    # -> BF16) has relative error <= 2^-8 (1 + 2^-16) per entry, plus the FP64
+    # difference of the two computations for entries that vanish up to rounding
+    for got, want in ((blk[:, 0], sy.Wk), (blk[:, 1:][m], sy.O[m])):
+        bound = 2.0 ** -8 * (1 + 2.0 ** -16) * np.abs(want) + 1e-12 * np.abs(want).max()
+        assert np.all(np.abs(got - want) <= bound), np.max(np.abs(got - want) / bound)
 
 
 @pytest.mark.parametrize("n,p,seed", [(7, 2, 711), (4, 3, 712)])
@@ -113,7 +128,7 @@ def _steps(s, w, pr, C, dt, nsteps):
     return out
 
 
-@pytest.mark.parametrize("weights", ["init", "nan"])
+@pytest.mark.parametrize("weights", ["init", "nan", "init-bf16"])
 def test_factor_preconditioner_steps(weights):
     from paper_1408_3877_amd import Solver
     n, p, dt = 12, 2, 0.02
@@ -125,6 +140,7 @@ def test_factor_preconditioner_steps(weights):
         s = Solver(cV, V0T, kind, p, rtol=1e-13, max_iters=20000, precond=pc)
         if pc:
             s.gnn_set_mode("factor")
+            s.gnn_factor_storage("bf16" if weights.endswith("bf16") else "f32")
             th = _theta(s.N, 723)
             if weights == "nan":
                 th = np.full_like(th, np.nan)
@@ -136,7 +152,7 @@ def test_factor_preconditioner_steps(weights):
             assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
             assert err < 1e-10
     for (ib, _), (il, _) in zip(runs["bj"], runs["learned"]):
-        if weights == "init":
+        if weights.startswith("init"):
             assert il["fallbacks"] == 0 and il["learned_iters"] == il["iters"]
             assert il["iters"] < ib["iters"]
         else:
