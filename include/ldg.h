@@ -342,7 +342,8 @@ ldg_status ldg_gnn_set_context(ldg_ctx* ctx, const double* D, double dt);
 /* g = network(r_hat): r_hat, g device K x N FP32 (correction mode) */
 ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
 /*
- * Factor mode, after ldg_gnn_set_context: omega (device K x 3 FP32, 0 on
+ * Factor mode, after a factor build (ldg_gnn_set_context, or a step with the
+ * learned preconditioner; omega from the features of that system): omega (device K x 3 FP32, 0 on
  * boundary edges) from the current parameters, and the factor blocks
  * (device K x 4 x N x N FP64: W_k, O_k0, O_k1, O_k2 row-major, O on boundary
  * edges undefined; may be NULL) with log ||O_kn||_F (device K x 3 FP32,
@@ -359,6 +360,14 @@ ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
 typedef enum { LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1 } ldg_fac_storage;
 ldg_status ldg_gnn_factor_storage(ldg_ctx* ctx, int storage);
 ldg_status ldg_gnn_factor_export(ldg_ctx* ctx, double* blocks, float* lognorm);
+/*
+ * The same for the triangles elems[0..n) only (device int32, each in [0, K),
+ * else LDG_EINVAL before any launch): blocks device n x 4 x N x N FP64,
+ * lognorm device n x 3 FP32 (may be NULL).  Valid after a factor build (a
+ * step with the learned preconditioner or ldg_gnn_set_context).
+ */
+ldg_status ldg_gnn_factor_export_rows(ldg_ctx* ctx, const int32_t* elems, int64_t n,
+                                      double* blocks, float* lognorm);
 /*
  * loss (as selected by ldg_gnn_set_loss) and its gradient (device, n_params
  * floats, may be NULL); the weight gradients are fixed-order FP64

@@ -126,6 +126,11 @@ class System:
         return (G.T @ G).tocsr()
 
 
+def head_preactivation(P, hk, hj, e, lognorm):
+    """h_k . w_hk + h_j . w_hj + e_kn . w_e + w_o log ||O_kn||_F + b_o (rows of edges)."""
+    return hk @ P["w_hk"] + hj @ P["w_hj"] + e @ P["w_e"] + P["w_o"] * lognorm + P["b_o"]
+
+
 def omega(theta, grid, node, edge, sysm, keep=False):
     """omega [K x 3] (0 on boundary edges) from the network."""
     N = sysm.N
@@ -136,8 +141,7 @@ def omega(theta, grid, node, edge, sysm, keep=False):
     a = np.zeros((grid.numT, 3))
     for n in range(3):
         j = np.where(m[:, n], kp[:, n], 0)
-        a[:, n] = (h @ P["w_hk"] + h[j] @ P["w_hj"] + edge[:, n] @ P["w_e"]
-                   + P["w_o"] * sysm.lognorm[:, n] + P["b_o"])
+        a[:, n] = head_preactivation(P, h, h[j], edge[:, n], sysm.lognorm[:, n])
     sig = 1.0 / (1.0 + np.exp(-a))
     om = np.where(m, OMEGA_MAX * sig, 0.0)
     if keep:

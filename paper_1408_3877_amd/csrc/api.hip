@@ -67,7 +67,7 @@ struct ldg_ctx {
   // preconditioner's buffers: factor blocks (FP32), FP64 W, log ||O||, omega,
   // d loss / d omega, FP64 and FP32 work vectors
   int gmode = 0;
-  bool fac_alloc_inf = false, fac_alloc_train = false, fac_on = false;
+  bool fac_alloc_inf = false, fac_alloc_train = false, fac_on = false, fac_built = false;
   void* fac_blk = nullptr;
   int fac_bt = BT_BF16;   // storage of the factor blocks
   float *fac_lognorm = nullptr, *fac_om = nullptr, *fac_dom = nullptr;
@@ -519,6 +519,7 @@ ldg_status fac_build(ldg_ctx* c, double tau) {
   int stv = 0;
   std::memcpy(&stv, c->host_buf, sizeof(int));
   if (stv) return fail(c, LDG_ENOCONV, "block-Jacobi inverse without a Cholesky factor");
+  c->fac_built = true;
   return LDG_OK;
 }
 
@@ -1352,12 +1353,13 @@ ldg_status ldg_gnn_factor_storage(ldg_ctx* c, int bt) {
     return fail(c, LDG_EINVAL, "factor storage is LDG_FAC_F32 or LDG_FAC_BF16");
   c->fac_bt = bt == LDG_FAC_F32 ? BT_F32 : BT_BF16;
   c->g_energy_ready = false;   // blocks of the old storage are stale
+  c->fac_built = false;
   return LDG_OK;
 }
 
 ldg_status ldg_gnn_factor_omega(ldg_ctx* c, float* om) {
-  if (!c || !om || c->gmode != LDG_GNN_FACTOR || !c->gnn_params_set || !c->g_energy_ready)
-    return fail(c, LDG_EINVAL, "factor mode, parameters and a context are needed");
+  if (!c || !om || c->gmode != LDG_GNN_FACTOR || !c->gnn_params_set || !c->fac_built)
+    return fail(c, LDG_EINVAL, "factor mode, parameters and built factor blocks are needed");
   TRY(fac_omega(c));
   for (int n = 0; n < 3; ++n)
     HIPCHK(c, hipMemcpy2DAsync(om + n, 3 * sizeof(float), c->fac_om + n * c->Kpad, sizeof(float),
@@ -1366,14 +1368,31 @@ ldg_status ldg_gnn_factor_omega(ldg_ctx* c, float* om) {
 }
 
 ldg_status ldg_gnn_factor_export(ldg_ctx* c, double* blocks, float* lognorm) {
-  if (!c || c->gmode != LDG_GNN_FACTOR || !c->g_energy_ready)
-    return fail(c, LDG_EINVAL, "factor mode and a context are needed");
+  if (!c || c->gmode != LDG_GNN_FACTOR || !c->fac_built)
+    return fail(c, LDG_EINVAL, "factor mode and built factor blocks are needed");
   if (blocks) launch_fac_export(c->K, c->N, c->fac_bt, c->fac_blk, blocks, c->st);
   if (lognorm)
     for (int n = 0; n < 3; ++n)
       HIPCHK(c, hipMemcpy2DAsync(lognorm + n, 3 * sizeof(float), c->fac_lognorm + n * c->Kpad,
                                  sizeof(float), sizeof(float), c->K, hipMemcpyDeviceToDevice,
                                  c->st));
+  TRY(check_launch(c));
+  return sync(c);
+}
+
+ldg_status ldg_gnn_factor_export_rows(ldg_ctx* c, const int32_t* elems, int64_t n, double* blocks,
+                                      float* lognorm) {
+  if (!c || !elems || n < 0 || !blocks || c->gmode != LDG_GNN_FACTOR || !c->fac_built)
+    return fail(c, LDG_EINVAL, "factor mode with built factor blocks and a row list are needed");
+  if (n == 0) return LDG_OK;
+  // indices come to the host and are checked against K before a launch reads through them
+  std::vector<int32_t> h(n);
+  HIPCHK(c, hipMemcpyAsync(h.data(), elems, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  TRY(sync(c));
+  for (int32_t k : h)
+    if (k < 0 || k >= c->K) return fail(c, LDG_EINVAL, "row index out of range");
+  launch_fac_export_rows(n, elems, c->N, c->fac_bt, c->Kpad, c->fac_blk, c->fac_lognorm, blocks,
+                         lognorm, c->st);
   TRY(check_launch(c));
   return sync(c);
 }

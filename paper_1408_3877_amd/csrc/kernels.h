@@ -125,6 +125,9 @@ void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double
                        const double* beta, const double* alpha, const double* y, float* dom,
                        hipStream_t st);
 void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st);
+void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, int bt, int64_t Kpad,
+                            const void* fb, const float* lognorm, double* out, float* lnout,
+                            hipStream_t st);
 void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,
                        hipStream_t st);
 void launch_from_tiled_f(int64_t K, int N, const float* src, float* dst, hipStream_t st);

@@ -328,6 +328,30 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict_
   }
 }
 
+// rows of the factor blocks for the triangles elems[0..n): out[r][s][i][j] (FP64),
+// lognorm[r][n] (may be NULL)
+template <class BT>
+__global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, int N, int64_t Kpad,
+                                  const BT* __restrict__ fb, const float* __restrict__ ln,
+                                  double* __restrict__ out, float* __restrict__ lnout) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int NN = N * N;
+  if (t >= n * FAC_SLOTS * NN) return;
+  const int f = (int)(t % NN);
+  const int s = (int)((t / NN) % FAC_SLOTS);
+  const int64_t r = t / ((int64_t)NN * FAC_SLOTS);
+  const int64_t k = elems[r];
+  constexpr int Wv = Blk<BT>::W;
+  const int NG = ngroups(N, Wv);
+  const BT v = fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv];
+  if constexpr (sizeof(BT) == 2) {
+    out[t] = (double)__uint_as_float((uint32_t)v << 16);
+  } else {
+    out[t] = (double)v;
+  }
+  if (lnout && f == 0 && s < 3) lnout[r * 3 + s] = ln[s * Kpad + k];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -424,6 +448,14 @@ void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double
 // out[k][s][i][j] (FP64, row-major)
 void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st) {
   launch_export_blocks_any(bt, K, N, FAC_SLOTS, fb, out, st);
+}
+
+void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, int bt, int64_t Kpad,
+                            const void* fb, const float* lognorm, double* out, float* lnout,
+                            hipStream_t st) {
+  const unsigned nb = nbk(n * FAC_SLOTS * N * N, 256);
+  LDG_SWITCH_BT(bt, (k_fac_export_rows<BTT><<<nb, 256, 0, st>>>(n, elems, N, Kpad, (const BTT*)fb,
+                                                                lognorm, out, lnout)))
 }
 
 }  // namespace ldg

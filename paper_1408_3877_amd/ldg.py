@@ -82,6 +82,7 @@ _SIGS = {
     "ldg_gnn_factor_omega": [_P, _P],
     "ldg_gnn_factor_export": [_P, _P, _P],
     "ldg_gnn_factor_storage": [_P, C.c_int],
+    "ldg_gnn_factor_export_rows": [_P, _P, C.c_int64, _P, _P],
     "ldg_gnn_set_loss": [_P, C.c_int],
     "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
     "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
@@ -307,6 +308,14 @@ class Solver:
         blk = t.empty((self.K, 4, self.N, self.N), dtype=t.float64, device=self.device)
         ln = t.empty((self.K, 3), dtype=t.float32, device=self.device)
         self._check(self.lib.ldg_gnn_factor_export(self.h, _ptr(blk), _ptr(ln)))
+        return blk, ln
+
+    def gnn_factor_export_rows(self, elems):
+        t = self.torch
+        el = t.as_tensor(np.asarray(elems, dtype=np.int32), device=self.device)
+        blk = t.empty((len(el), 4, self.N, self.N), dtype=t.float64, device=self.device)
+        ln = t.empty((len(el), 3), dtype=t.float32, device=self.device)
+        self._check(self.lib.ldg_gnn_factor_export_rows(self.h, _ptr(el), len(el), _ptr(blk), _ptr(ln)))
         return blk, ln
 
     def gnn_set_loss(self, kind):

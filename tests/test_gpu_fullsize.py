@@ -15,6 +15,7 @@ import pytest
 from bench import CONFIGS
 from inputs.fields import LOGNORMAL, LOGNORMAL_T, Workload, lognormal_blocks
 from inputs.meshes import square_mesh
+from oracle import gnn, gnn_factor as gf
 from oracle.ldg import Blocks, boundary_vectors, project, schur_apply_rows
 from oracle.mesh import Grid
 from oracle.refelem import RefTensors
@@ -135,3 +136,78 @@ def test_fullsize_sampled(name, precision):
     assert res_rows <= 2e-8 * bnorm, (res_rows, bnorm)
     for m, Zg in enumerate((Z1, Z2)):
         assert np.abs(Zg[el] - Zo[m]).max() <= 1e-9 * np.abs(Zo[m]).max()
+
+
+def test_fullsize_learned_factor_blocks_and_omega():
+    """The combined workload in bench.py's launch configuration (BF16 inner solves,
+    learned factored preconditioner with the trained weights, BF16 factor blocks):
+    one step, then the factor blocks and omega of sampled triangles against the
+    oracle, which takes the blocks S_kk, S_kj, S_jj of the eliminated operator
+    from row-restricted applies to unit vectors."""
+    import os
+
+    import torch
+
+    from bench import WEIGHTS
+    from paper_1408_3877_amd import Solver
+    cfg = CONFIGS["combined-p4-1024"]
+    p, dt, eta = cfg["p"], cfg["dt"], 1.0
+    coordV, V0T, kind = square_mesh(cfg["n"], seed=cfg["jitter"])
+    w = _workload(cfg)
+    grid = Grid(coordV, V0T, kind)
+    refs = RefTensors(p)
+    K, N = grid.numT, refs.N
+    el = _sample(grid, np.random.default_rng(4343), n=24)
+    el = el[np.all(grid.kp[el] >= 0, axis=1)]           # interior triangles
+    print("[fullsize-factor] K=%d sampled=%d" % (K, len(el)), flush=True)
+    theta = np.load(WEIGHTS[p]).astype(np.float32)
+    s = Solver(coordV, V0T, kind, p, rtol=1e-8, max_iters=20000, precision=2, precond=1)
+    s.gnn_set_mode("factor")
+    s.gnn_set_params(theta)
+    c0 = s.sample_workload(cfg["kind"], 0.0, dT=w.dT, want=("c0",))["c0"]
+    s.set_initial_samples(c0, 0.0)
+    smp = s.sample_workload(cfg["kind"], dt, dT=w.dT)
+    info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+    print("[fullsize-factor] step: %s" % info, flush=True)
+    assert info["rel_residual"] <= 1e-8 and info["fallbacks"] == 0
+    assert info["learned_iters"] == info["iters"] > 0
+    blk, ln = (to_np(x) for x in s.gnn_factor_export_rows(el))
+    om = to_np(s.gnn_factor_omega())[el]
+    # oracle blocks of S around the sample: unit vectors on the sample (self) or on
+    # its n-th neighbours; the sample is >= 5 edges apart, so no two overlap
+    D = project(grid, p, lambda x, y: w.d(dt, x, y), refs.hatM)
+    nb = grid.kp[el]
+    rows = np.unique(np.concatenate([el, nb.reshape(-1)]))
+    pos = {int(k): i for i, k in enumerate(rows)}
+    cols = {}
+    for src in ["self", 0, 1, 2]:
+        tgt = el if src == "self" else nb[:, src]
+        out = np.zeros((len(rows), N, N))
+        for c in range(N):
+            E = np.zeros((K, N))
+            E[tgt, c] = 1.0
+            out[:, :, c] = schur_apply_rows(grid, refs, D, E, dt, eta, rows)[0]
+        cols[src] = out
+    inv = np.linalg.inv
+    Wof = lambda Skk: np.linalg.cholesky(inv(0.5 * (Skk + Skk.T))).T
+    node, edge = gnn.features(grid, D, dt, eta)
+    P = gnn.unpack(theta.astype(np.float64), N, gf.param_shapes(N))
+    h, _ = gnn.trunk_forward(P, grid, node, edge)
+    worst = 0.0
+    for r, k in enumerate(el):
+        Wk = Wof(cols["self"][pos[int(k)]])
+        bound = 2.0 ** -8 * (1 + 2.0 ** -16) * np.abs(Wk) + 1e-10 * np.abs(Wk).max()
+        assert np.all(np.abs(blk[r, 0] - Wk) <= bound)
+        for n in range(3):
+            j = int(nb[r, n])
+            Skj = cols[n][pos[int(k)]]
+            Wj = Wof(cols[n][pos[j]])
+            O = Wk @ Skj @ Wj.T
+            bound = 2.0 ** -8 * (1 + 2.0 ** -16) * np.abs(O) + 1e-9 * np.abs(O).max()
+            worst = max(worst, np.max(np.abs(blk[r, 1 + n] - O) / bound))
+            lno = np.log(np.linalg.norm(O))
+            assert abs(ln[r, n] - lno) <= 1e-5 * max(1.0, abs(lno))
+            a = gf.head_preactivation(P, h[k], h[j], edge[k, n], lno)
+            assert abs(om[r, n] - gf.OMEGA_MAX / (1.0 + np.exp(-a))) <= 1e-4
+    print("[fullsize-factor] worst O error / BF16 bound = %.3f" % worst, flush=True)
+    assert worst <= 1.0

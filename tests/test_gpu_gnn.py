@@ -172,12 +172,32 @@ def test_learned_preconditioner_steps(scramble):
 
 
 def test_training_on_method_systems_reduces_loss_and_reports_gain():
-    # a9 in miniature: collect pairs from BJ-CG steps, train, evaluate against BJ
+    # training in miniature, factored preconditioner (the default): the systems of
+    # the method's steps on four fields, Frobenius loss with Gaussian probes; then
+    # held-out steps with and without the trained network
     from paper_1408_3877_amd import learned
     rep = learned.main(["--p", "2", "--n", "16", "--jitter", "631", "--sigma", "1.5",
                         "--train-seeds", "4000-4003", "--eval-seeds", "4100", "--steps", "2",
                         "--eval-steps", "2", "--epochs", "3", "--dt", "0.002"])
     print("[learned] %s" % rep)
-    assert rep["samples"] > 20
+    assert rep["mode"] == "factor" and rep["loss"] == "frobenius" and rep["samples"] == 8
+    assert rep["loss_per_epoch"][-1] < rep["loss_per_epoch"][0] < 1.0
+    assert rep["heldout_loss"] < 1.0
+    assert rep["learned"]["steps"] == rep["block_jacobi"]["steps"] == 2
+    assert rep["learned"]["fallbacks"] == 0
+    # the gain over the method without the network
+    assert rep["learned"]["iters_per_step"] < 0.8 * rep["block_jacobi"]["iters_per_step"]
+
+
+def test_training_the_correction_network_on_collected_pairs():
+    # the residual-correction network: pairs from block-Jacobi CG iterates of the
+    # method's steps, energy loss; the loss falls and the steps stay exact
+    from paper_1408_3877_amd import learned
+    rep = learned.main(["--mode", "correction", "--p", "2", "--n", "16", "--jitter", "631",
+                        "--sigma", "1.5", "--train-seeds", "4000-4003", "--eval-seeds", "4100",
+                        "--steps", "2", "--eval-steps", "2", "--epochs", "3", "--dt", "0.002",
+                        "--rounds", "1"])
+    print("[learned-correction] %s" % rep)
+    assert rep["samples"] > 20 and rep["loss"] == "energy"
     assert rep["loss_per_epoch"][-1] < rep["loss_per_epoch"][0]
     assert rep["learned"]["steps"] == rep["block_jacobi"]["steps"] == 2
