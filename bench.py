@@ -80,6 +80,7 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
                precond=1 if learned else 0)
     if learned:
         s.gnn_set_mode("factor")
+        s.gnn_factor_storage(args.fac_storage)
         s.gnn_set_params(weights)
     log("[bench] %s: context K=%d N=%d (%.1f s)" % (label, s.K, s.N, time.perf_counter() - t0))
     gk = cfg["kind"]
@@ -103,7 +104,7 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
         b.copy_(a)
         torch.cuda.synchronize()
     torch.cuda.synchronize()
-    s.set_timing(True)
+    s.set_timing(not args.no_kernel_timing)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
@@ -186,6 +187,10 @@ def main():
     ap.add_argument("--precond", default="learned", choices=["bj", "learned"],
                     help="block-Jacobi, or the learned factored preconditioner")
     ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
+    ap.add_argument("--fac-storage", default="fp8", choices=["f32", "bf16", "fp8"],
+                    help="storage of the learned preconditioner's factor blocks")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--no-baseline", action="store_true",
                     help="skip timing the plain FP64 block-Jacobi solver for comparison")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
@@ -223,6 +228,10 @@ def main():
     dof = 3 * s.K * s.N
     value = dof * args.steps / el
     # roofline of the kernel that takes the most time in the timed steps
+    if args.no_kernel_timing:
+        log("[bench] no kernel timing: %.4g DOF*steps/s, %.1f ms per step" %
+            (dof * args.steps / el, el * 1e3 / args.steps))
+        return
     name = max(("div", "factor", "bj_apply", "grad"), key=lambda k: stats[k]["total_ms"])
     kv = stats[name]
     ach = kv["bytes"] / (kv["total_ms"] * 1e-3) / 1e9 if kv["total_ms"] > 0 else 0.0
@@ -231,9 +240,11 @@ def main():
                    "factor": "k_fac_w + k_fac_f (learned factored preconditioner apply)",
                    "bj_apply": "k_bj_apply (block-Jacobi apply)",
                    "grad": "k_grad (operator gradient half)"}[name]
-    traffic = measured_traffic(args.config, name, args.precision, args.precond)
+    traffic = measured_traffic(args.config, name, args.precision,
+                               args.precond + ("-" + args.fac_storage if learned else ""))
     solver_desc = "%s %s %s%s" % (
-        args.precision, "learned factored" if learned else "block-Jacobi",
+        args.precision,
+        "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
         "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
         "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol)
     res = {

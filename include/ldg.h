@@ -351,13 +351,15 @@ ldg_status ldg_gnn_forward(ldg_ctx* ctx, const float* rhat, float* g);
  */
 ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
 /*
- * Storage of the factor blocks W_k, O_kn: LDG_FAC_BF16 (default; halves the
- * application's traffic) or LDG_FAC_F32.  P stays exactly symmetric positive
- * definite in either, the same rounded blocks forming G and G^T; the
- * solution's accuracy is set by the FP64 residual as always.  Takes effect at
- * the next factor build (step or ldg_gnn_set_context).
+ * Storage of the factor blocks: LDG_FAC_FP8 (default; W_k in BF16, O_kn in OCP
+ * E4M3 FP8, round to nearest even; the entries of O_kn, blocks of a symmetric
+ * positive definite matrix with identity diagonal blocks, lie in [-1, 1]),
+ * LDG_FAC_BF16 (both in BF16) or LDG_FAC_F32.  P stays exactly symmetric positive definite in each, the same
+ * rounded blocks forming G and G^T; the solution's accuracy is set by the
+ * FP64 residual as always.  Takes effect at the next factor build (step or
+ * ldg_gnn_set_context).
  */
-typedef enum { LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1 } ldg_fac_storage;
+typedef enum { LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1, LDG_FAC_FP8 = 2 } ldg_fac_storage;
 ldg_status ldg_gnn_factor_storage(ldg_ctx* ctx, int storage);
 ldg_status ldg_gnn_factor_export(ldg_ctx* ctx, double* blocks, float* lognorm);
 /*

@@ -68,8 +68,7 @@ struct ldg_ctx {
   // d loss / d omega, FP64 and FP32 work vectors
   int gmode = 0;
   bool fac_alloc_inf = false, fac_alloc_train = false, fac_on = false, fac_built = false;
-  void* fac_blk = nullptr;
-  int fac_bt = BT_BF16;   // storage of the factor blocks
+  FacStore fac;           // factor blocks W (one slot) and O (three slots)
   float *fac_lognorm = nullptr, *fac_om = nullptr, *fac_dom = nullptr;
   double* fac_w64 = nullptr;
   double* fac_v[8] = {};
@@ -483,9 +482,14 @@ ldg_status gnn_alloc(ldg_ctx* c, bool training) {
 
 ldg_status fac_alloc(ldg_ctx* c, bool training) {
   if (!c->fac_alloc_inf) {
-    float* fb = nullptr;   // sized for FP32 storage (BF16 uses less)
-    TRY(dalloc(c, &fb, (size_t)c->Kpad * FAC_SLOTS * ((c->N * c->N + 3) / 4) * 4));
-    c->fac_blk = fb;
+    // sized for FP32 storage (BF16 and FP8 use less)
+    const size_t per_slot = (size_t)c->Kpad * ((c->N * c->N + 3) / 4) * 4;
+    float* fw = nullptr;
+    float* fo = nullptr;
+    TRY(dalloc(c, &fw, per_slot));
+    TRY(dalloc(c, &fo, 3 * per_slot));
+    c->fac.w = fw;
+    c->fac.o = fo;
     TRY(dalloc(c, &c->fac_w64, (size_t)c->Kpad * npairs(c->N) * 2));
     TRY(dalloc(c, &c->fac_lognorm, (size_t)3 * c->Kpad));
     TRY(dalloc(c, &c->fac_om, (size_t)3 * c->Kpad));
@@ -510,8 +514,8 @@ ldg_status fac_build(ldg_ctx* c, double tau) {
   {
     const double NN = (double)c->NN;
     Timed tm(c, LDG_K_FACTOR, 8.0 * NN * (8.0 * c->K), 2.0 * NN * c->N * (8.0 * c->Eint));
-    launch_fac_setup(c->N, c->fac_bt, c->geo, c->refs, c->blocks, c->bj, tau, c->opt.eta,
-                     c->fac_w64, c->fac_blk, c->fac_lognorm, c->status, c->st);
+    launch_fac_setup(c->N, c->fac, c->geo, c->refs, c->blocks, c->bj, tau, c->opt.eta,
+                     c->fac_w64, c->fac_lognorm, c->status, c->st);
   }
   TRY(check_launch(c));
   HIPCHK(c, hipMemcpyAsync(c->host_buf, c->status, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -534,13 +538,13 @@ ldg_status fac_omega(ldg_ctx* c) {
 // z = P r (factored) with <r, z> in red.result[0]
 void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z) {
   const double NN = (double)c->N * c->N;
-  const double bb = c->fac_bt == BT_BF16 ? 2.0 : 4.0;
-  Timed tm(c, LDG_K_FACTOR, (8.0 * bb * NN + 7.0 * L.vbytes * c->N) * c->K,
+  const double bw = c->fac.wt == BT_F32 ? 4.0 : 2.0;
+  const double bo = c->fac.ot == BT_F32 ? 4.0 : (c->fac.ot == BT_BF16 ? 2.0 : 1.0);
+  Timed tm(c, LDG_K_FACTOR, ((2.0 * bw + 6.0 * bo) * NN + 7.0 * L.vbytes * c->N) * c->K,
            2.0 * 8.0 * NN * c->K);
   void* y = L.vt == VT_F64 ? (void*)c->fac_v[0] : (void*)c->fac_y32;
   void* a = L.vt == VT_F64 ? (void*)c->fac_v[1] : (void*)c->fac_a32;
-  launch_fac_apply(c->N, c->fac_bt, L.vt, c->geo, c->fac_blk, c->fac_om, r, y, a, z, &c->red,
-                   c->st);
+  launch_fac_apply(c->N, c->fac, L.vt, c->geo, c->fac_om, r, y, a, z, &c->red, c->st);
 }
 
 // z = BJ^{-1} r + rho g(BJ^{-1} r / rho), rho = RMS of BJ^{-1} r  (FP32 network)
@@ -1349,9 +1353,10 @@ ldg_status ldg_gnn_set_mode(ldg_ctx* c, int mode) {
 }
 
 ldg_status ldg_gnn_factor_storage(ldg_ctx* c, int bt) {
-  if (!c || (bt != LDG_FAC_F32 && bt != LDG_FAC_BF16))
-    return fail(c, LDG_EINVAL, "factor storage is LDG_FAC_F32 or LDG_FAC_BF16");
-  c->fac_bt = bt == LDG_FAC_F32 ? BT_F32 : BT_BF16;
+  if (!c || (bt != LDG_FAC_F32 && bt != LDG_FAC_BF16 && bt != LDG_FAC_FP8))
+    return fail(c, LDG_EINVAL, "factor storage is LDG_FAC_F32, LDG_FAC_BF16 or LDG_FAC_FP8");
+  c->fac.wt = bt == LDG_FAC_F32 ? BT_F32 : BT_BF16;
+  c->fac.ot = bt == LDG_FAC_F32 ? BT_F32 : (bt == LDG_FAC_BF16 ? BT_BF16 : BT_FP8);
   c->g_energy_ready = false;   // blocks of the old storage are stale
   c->fac_built = false;
   return LDG_OK;
@@ -1370,7 +1375,7 @@ ldg_status ldg_gnn_factor_omega(ldg_ctx* c, float* om) {
 ldg_status ldg_gnn_factor_export(ldg_ctx* c, double* blocks, float* lognorm) {
   if (!c || c->gmode != LDG_GNN_FACTOR || !c->fac_built)
     return fail(c, LDG_EINVAL, "factor mode and built factor blocks are needed");
-  if (blocks) launch_fac_export(c->K, c->N, c->fac_bt, c->fac_blk, blocks, c->st);
+  if (blocks) launch_fac_export(c->K, c->N, c->fac, blocks, c->st);
   if (lognorm)
     for (int n = 0; n < 3; ++n)
       HIPCHK(c, hipMemcpy2DAsync(lognorm + n, 3 * sizeof(float), c->fac_lognorm + n * c->Kpad,
@@ -1391,8 +1396,7 @@ ldg_status ldg_gnn_factor_export_rows(ldg_ctx* c, const int32_t* elems, int64_t 
   TRY(sync(c));
   for (int32_t k : h)
     if (k < 0 || k >= c->K) return fail(c, LDG_EINVAL, "row index out of range");
-  launch_fac_export_rows(n, elems, c->N, c->fac_bt, c->Kpad, c->fac_blk, c->fac_lognorm, blocks,
-                         lognorm, c->st);
+  launch_fac_export_rows(n, elems, c->N, c->fac, c->Kpad, c->fac_lognorm, blocks, lognorm, c->st);
   TRY(check_launch(c));
   return sync(c);
 }
@@ -1463,9 +1467,9 @@ ldg_status gnn_factor_loss_grad(ldg_ctx* c, double* loss) {
   launch_cast(VT_F32, VT_F64, n, 1.0, c->g_tgt, v[0], c->st);
   launch_axpy_into64(VT_F32, n, 1.0, c->g_rhat, v[0], c->st);            // e
   apply_op(c, L, c->gtau, v[0], false, L.tz1, L.tz2, v[1]);               // r = S e
-  launch_fac_w(N, c->fac_bt, c->geo, c->fac_blk, v[1], v[2], c->st);                 // y
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, false, v[2], v[3], c->st);  // a
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, true, v[3], v[4], c->st);   // z = P r
+  launch_fac_w(N, c->fac, c->geo, v[1], v[2], c->st);                 // y
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, false, v[2], v[3], c->st);  // a
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, true, v[3], v[4], c->st);   // z = P r
   launch_axpy_into64(VT_F64, n, -1.0, v[0], v[4], c->st);                 // d
   apply_op(c, L, c->gtau, v[4], false, L.tz1, L.tz2, v[5]);               // S d
   kdots(c, L, 1, v[4], v[5]);
@@ -1480,9 +1484,9 @@ ldg_status gnn_factor_loss_grad(ldg_ctx* c, double* loss) {
   if (!(den > 0.0) || !std::isfinite(num))
     return fail(c, LDG_ENOCONV, "energy loss: block-Jacobi error without positive energy");
   launch_cast(VT_F64, VT_F64, n, 2.0 / den, v[5], v[4], c->st);           // dL/dz
-  launch_fac_w(N, c->fac_bt, c->geo, c->fac_blk, v[4], v[6], c->st);                 // beta
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, false, v[6], v[7], c->st);  // alpha
-  launch_fac_domega(N, c->fac_bt, c->geo, c->fac_blk, v[3], v[6], v[7], v[2], c->fac_dom, c->st);
+  launch_fac_w(N, c->fac, c->geo, v[4], v[6], c->st);                 // beta
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, false, v[6], v[7], c->st);  // alpha
+  launch_fac_domega(N, c->fac, c->geo, v[3], v[6], v[7], v[2], c->fac_dom, c->st);
   launch_fac_omega_backward(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT,
                             c->fac_om, c->fac_dom, c->gS, c->gGrad, c->st);
   *loss = num / den;
@@ -1502,17 +1506,17 @@ ldg_status gnn_factor_frob_grad(ldg_ctx* c, double* loss) {
   double** v = c->fac_v;
   launch_fac_omega(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT, c->fac_om, c->st);
   launch_cast(VT_F32, VT_F64, n, 1.0, c->g_rhat, v[0], c->st);                // w
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, true, v[0], v[1], c->st);     // u = G^T w
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, true, v[0], v[1], c->st);     // u = G^T w
   apply_op(c, L, c->gtau, v[1], false, L.tz1, L.tz2, v[2]);                    // S u
-  launch_fac_w(N, c->fac_bt, c->geo, c->fac_blk, v[2], v[3], c->st);                      // y
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, false, v[3], v[4], c->st);    // (I + F) y
+  launch_fac_w(N, c->fac, c->geo, v[2], v[3], c->st);                      // y
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, false, v[3], v[4], c->st);    // (I + F) y
   launch_axpy_into64(VT_F64, n, -1.0, v[0], v[4], c->st);                      // residual
   kdots(c, L, 1, v[4], v[4]);
   TRY(fetch(c, c->red.result, 1, c->host_buf));
   const double num = c->host_buf[0];
-  launch_fac_wt(N, c->fac_bt, c->geo, c->fac_blk, v[0], v[5], c->st);                     // W^T w
+  launch_fac_wt(N, c->fac, c->geo, v[0], v[5], c->st);                     // W^T w
   apply_op(c, L, c->gtau, v[5], false, L.tz1, L.tz2, v[6]);
-  launch_fac_w(N, c->fac_bt, c->geo, c->fac_blk, v[6], v[5], c->st);
+  launch_fac_w(N, c->fac, c->geo, v[6], v[5], c->st);
   launch_axpy_into64(VT_F64, n, -1.0, v[0], v[5], c->st);                      // (W S W^T - I) w
   kdots(c, L, 1, v[5], v[5]);
   TRY(fetch(c, c->red.result, 1, c->host_buf));
@@ -1520,10 +1524,10 @@ ldg_status gnn_factor_frob_grad(ldg_ctx* c, double* loss) {
   if (!(den > 0.0) || !std::isfinite(num))
     return fail(c, LDG_ENOCONV, "Frobenius loss: zero probe or non-finite value");
   launch_cast(VT_F64, VT_F64, n, 2.0 / den, v[4], v[5], c->st);                // g
-  launch_fac_f(N, c->fac_bt, c->geo, c->fac_blk, c->fac_om, true, v[5], v[6], c->st);     // G^T g
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, true, v[5], v[6], c->st);     // G^T g
   apply_op(c, L, c->gtau, v[6], false, L.tz1, L.tz2, v[7]);
-  launch_fac_w(N, c->fac_bt, c->geo, c->fac_blk, v[7], v[6], c->st);                      // beta
-  launch_fac_domega(N, c->fac_bt, c->geo, c->fac_blk, v[0], v[6], v[5], v[3], c->fac_dom, c->st);
+  launch_fac_w(N, c->fac, c->geo, v[7], v[6], c->st);                      // beta
+  launch_fac_domega(N, c->fac, c->geo, v[0], v[6], v[5], v[3], c->fac_dom, c->st);
   launch_fac_omega_backward(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT,
                             c->fac_om, c->fac_dom, c->gS, c->gGrad, c->st);
   *loss = num / den;

@@ -13,6 +13,7 @@ namespace ldg {
 // Block entry f = i*N + j of (triangle k, slot s) lives in group g = f / W at
 //   [k/64][s][g][k%64][f%W],  W = 16 bytes / sizeof(storage type).
 using bf16 = uint16_t;
+using fp8 = uint8_t;   // OCP E4M3 (gfx950 conversions), factor blocks only
 
 template <class BT> struct Blk;
 template <> struct Blk<double> {
@@ -49,6 +50,22 @@ template <> struct Blk<bf16> {
   }
 };
 
+template <> struct Blk<fp8> {
+  static constexpr int W = 16;
+  template <class T>
+  __device__ static inline void load(const fp8* p, T* v) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    const int w[4] = {(int)x.x, (int)x.y, (int)x.z, (int)x.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[4 * q + 0] = (T)__builtin_amdgcn_cvt_f32_fp8(w[q], 0);
+      v[4 * q + 1] = (T)__builtin_amdgcn_cvt_f32_fp8(w[q], 1);
+      v[4 * q + 2] = (T)__builtin_amdgcn_cvt_f32_fp8(w[q], 2);
+      v[4 * q + 3] = (T)__builtin_amdgcn_cvt_f32_fp8(w[q], 3);
+    }
+  }
+};
+
 __host__ __device__ constexpr int ngroups(int N, int W) { return (N * N + W - 1) / W; }
 
 __host__ __device__ inline int64_t bgidx(int64_t k, int s, int g, int ns, int ng, int W) {
@@ -67,6 +84,13 @@ template <class BT> __device__ inline BT from_double(double x);
 template <> __device__ inline double from_double<double>(double x) { return x; }
 template <> __device__ inline float from_double<float>(double x) { return (float)x; }
 template <> __device__ inline bf16 from_double<bf16>(double x) { return to_bf16((float)x); }
+// round to nearest even E4M3; the conversion does not saturate (448 is the
+// largest finite value), so magnitudes are clamped first
+template <> __device__ inline fp8 from_double<fp8>(double x) {
+  const float f = (float)fmin(fmax(x, -448.0), 448.0);
+  return (fp8)(__builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false) & 0xff);
+}
+__device__ inline float fp8_to_float(fp8 v) { return __builtin_amdgcn_cvt_f32_fp8((int)v, 0); }
 
 // acc += Blk(k, s) z, one lane per triangle, fully unrolled over the block
 template <int N, class BT, class T>

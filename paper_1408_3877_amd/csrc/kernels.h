@@ -12,7 +12,7 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
                      double* KDN, hipStream_t st);
 // vector storage (VT_*) and block storage (BT_*) precisions
 enum { VT_F64 = 0, VT_F32 = 1 };
-enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2 };
+enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2, BT_FP8 = 3 };
 
 // kernels_apply.hip
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
@@ -102,31 +102,37 @@ void launch_fac_omega_backward(int N, const Geo& g, const float* P, const float*
 void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr, int step,
                  hipStream_t st);
 
-// kernels_factor.hip: factor blocks (FAC_SLOTS per triangle: W_k, O_k0..2) stored
-// as BT_F32 or BT_BF16 (bt), arithmetic in the vector type
-constexpr int FAC_SLOTS = 4;
-// W (FP64 scratch w64 and slot 0), O blocks and log ||O||_F from the FP64
+// kernels_factor.hip: factor blocks W_k (one slot, storage wt) and O_k0..2
+// (three slots, storage ot), BT_F32 / BT_BF16 / BT_FP8, arithmetic in the vector type
+constexpr int FAC_SLOTS = 4;   // W_k, O_k0, O_k1, O_k2 in the exports
+struct FacStore {
+  int wt = BT_BF16, ot = BT_FP8;
+  void* w = nullptr;   // W: Kpad x 1 slot
+  void* o = nullptr;   // O: Kpad x 3 slots
+};
+// W (FP64 scratch w64 and the W store), O blocks and log ||O||_F from the FP64
 // operator blocks and block-Jacobi inverses; status |= 2 on a failed Cholesky
-void launch_fac_setup(int N, int bt, const Geo& g, const double* refs, const double* blocks,
-                      const double* bj, double tau, double eta, double* w64, void* fb,
+void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* refs,
+                      const double* blocks, const double* bj, double tau, double eta, double* w64,
                       float* lognorm, int* status, hipStream_t st);
 // z = P r through y, a (work vectors); red: result[0] = <r, z>
-void launch_fac_apply(int N, int bt, int vt, const Geo& g, const void* fb, const float* om,
+void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const float* om,
                       const void* r, void* y, void* a, void* z, const Reducer* red,
                       hipStream_t st);
-void launch_fac_w(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
+void launch_fac_w(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                   hipStream_t st);
-void launch_fac_wt(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
+void launch_fac_wt(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                    hipStream_t st);
 // out = (I + F) x, or W^T (I + F)^T x
-void launch_fac_f(int N, int bt, const Geo& g, const void* fb, const float* om,
-                  bool transpose_and_wt, const double* x, double* out, hipStream_t st);
-void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double* a,
+void launch_fac_f(int N, const FacStore& fs, const Geo& g, const float* om, bool transpose_and_wt,
+                  const double* x, double* out, hipStream_t st);
+void launch_fac_domega(int N, const FacStore& fs, const Geo& g, const double* a,
                        const double* beta, const double* alpha, const double* y, float* dom,
                        hipStream_t st);
-void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st);
-void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, int bt, int64_t Kpad,
-                            const void* fb, const float* lognorm, double* out, float* lnout,
+// out[k][s][i][j] (FP64): s = 0 W_k, s = 1..3 O_k(s-1); rows = all K, or elems[0..n)
+void launch_fac_export(int64_t K, int N, const FacStore& fs, double* out, hipStream_t st);
+void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, const FacStore& fs,
+                            int64_t Kpad, const float* lognorm, double* out, float* lnout,
                             hipStream_t st);
 void launch_to_tiled_f(int64_t K, int64_t Kpad, int N, const float* src, float* dst,
                        hipStream_t st);

@@ -228,6 +228,8 @@ __global__ void k_export_any(int64_t K, int N, int ns, const BT* __restrict__ sr
   BT v = src[bgidx(k, s, f / W, ns, NG, W) + f % W];
   if constexpr (sizeof(BT) == 2) {
     dst[t] = (double)__uint_as_float((uint32_t)v << 16);
+  } else if constexpr (sizeof(BT) == 1) {
+    dst[t] = (double)fp8_to_float(v);
   } else {
     dst[t] = (double)v;
   }
@@ -329,7 +331,8 @@ void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src,
   const unsigned nb = nblk(K * ns * N * N, 256);
   if (bt == BT_F64) k_export_any<double><<<nb, 256, 0, st>>>(K, N, ns, (const double*)src, dst);
   else if (bt == BT_F32) k_export_any<float><<<nb, 256, 0, st>>>(K, N, ns, (const float*)src, dst);
-  else k_export_any<bf16><<<nb, 256, 0, st>>>(K, N, ns, (const bf16*)src, dst);
+  else if (bt == BT_BF16) k_export_any<bf16><<<nb, 256, 0, st>>>(K, N, ns, (const bf16*)src, dst);
+  else k_export_any<fp8><<<nb, 256, 0, st>>>(K, N, ns, (const fp8*)src, dst);
 }
 
 void launch_export_rows(int64_t n, const int32_t* elems, int N, int ns, const double* src,

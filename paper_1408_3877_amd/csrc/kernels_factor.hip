@@ -32,10 +32,20 @@ __device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
 inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class BT>
-__device__ inline void put(BT* __restrict__ fb, int64_t k, int s, int f, int N, double v) {
+__device__ inline void put(BT* __restrict__ fb, int64_t k, int s, int ns, int f, int N, double v) {
   constexpr int Wv = Blk<BT>::W;
   const int NG = ngroups(N, Wv);
-  fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv] = from_double<BT>(v);
+  fb[bgidx(k, s, f / Wv, ns, NG, Wv) + f % Wv] = from_double<BT>(v);
+}
+
+template <class BT>
+__device__ inline double get_any(const BT* __restrict__ fb, int64_t k, int s, int ns, int f, int N) {
+  constexpr int Wv = Blk<BT>::W;
+  const int NG = ngroups(N, Wv);
+  const BT v = fb[bgidx(k, s, f / Wv, ns, NG, Wv) + f % Wv];
+  if constexpr (sizeof(BT) == 2) return (double)__uint_as_float((uint32_t)v << 16);
+  else if constexpr (sizeof(BT) == 1) return (double)fp8_to_float(v);
+  else return (double)v;
 }
 
 __device__ inline double get64(const double* __restrict__ b, int64_t k, int s, int ns, int f,
@@ -81,7 +91,7 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
       const double v = r <= i ? a[r] : 0.0;
       const int f = r * N + i;
       w64[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = v;
-      put<BT>(fb, k, 0, f, N, v);
+      put<BT>(fb, k, 0, 1, f, N, v);
     }
   }
 }
@@ -93,18 +103,22 @@ template <int N, class BT>
 __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restrict__ refs,
                                                     const double* __restrict__ blocks,
                                                     const double* __restrict__ w64, double tau,
-                                                    double eta, BT* __restrict__ fb,
+                                                    double eta, BT* __restrict__ fo,
                                                     float* __restrict__ lognorm) {
+  // every intermediate N x N matrix lives in LDS (one set per triangle of the
+  // block); registers hold scalars only
   constexpr int NN = N * N;
   constexpr int NP = npairs(N);
   __shared__ double sm[NREF * NN];
   __shared__ double t1[4][NN];
   __shared__ double t2[4][NN];
+  __shared__ double t3[4][NN];
   for (int t = threadIdx.x; t < NREF * NN; t += blockDim.x) sm[t] = refs[t];
   __syncthreads();
   const int grp = threadIdx.x >> 4;
   const int i = threadIdx.x & 15;
-  const int ii = i < N ? i : 0;
+  const bool row = i < N;
+  const int ii = row ? i : 0;
   const int64_t k = (int64_t)blockIdx.x * 4 + grp;
   const bool elem_ok = k < g.K;
   const int64_t kk = elem_ok ? k : 0;
@@ -112,111 +126,99 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
   const double area2k = g.area2[kk];
   double* T1 = t1[grp];
   double* T2 = t2[grp];
+  double* T3 = t3[grp];
+#pragma unroll 1
   for (int n = 0; n < 3; ++n) {
     const int64_t jn = elem_ok ? g.nbr[n * Kp + kk] : -1;
     const bool act = jn > k;
     const int64_t j = act ? jn : kk;
     const int npl = act ? g.nbrn[n * Kp + kk] : 0;
     const double nu1 = g.nu[(2 * n) * Kp + kk], nu2 = g.nu[(2 * n + 1) * Kp + kk];
-    // t1 <- sum_m nu^m_kn A^m_jj (row ii per lane)
+    // T1 <- sum_m nu^m_kn A^m_jj;  T2 <- sum_m nu^m_kn B^m_kk (row ii per lane)
     {
       const double B11 = g.B[j], B12 = g.B[Kp + j], B21 = g.B[2 * Kp + j], B22 = g.B[3 * Kp + j];
-      double coef[5];
-      coef[0] = -(nu1 * B22 - nu2 * B12);
-      coef[1] = -(-nu1 * B21 + nu2 * B11);
+      const double c0 = -(nu1 * B22 - nu2 * B12);
+      const double c1 = -(-nu1 * B21 + nu2 * B11);
+      double cq[3];
+#pragma unroll
       for (int q = 0; q < 3; ++q) {
         const int kd = g.kind[q * Kp + j];
         const double w = kd == LDG_EDGE_INTERIOR ? 0.5 : (kd == LDG_EDGE_NEUMANN ? 1.0 : 0.0);
-        coef[2 + q] = w * (nu1 * g.nu[(2 * q) * Kp + j] + nu2 * g.nu[(2 * q + 1) * Kp + j]) *
-                      g.elen[q * Kp + j];
+        cq[q] = w * (nu1 * g.nu[(2 * q) * Kp + j] + nu2 * g.nu[(2 * q + 1) * Kp + j]) *
+                g.elen[q * Kp + j];
       }
-      if (i < N) {
+      if (row) {
+#pragma unroll 1
         for (int c = 0; c < N; ++c) {
-          double s = 0.0;
-          for (int t = 0; t < 5; ++t) s += coef[t] * sm[t * NN + ii * N + c];
-          T1[ii * N + c] = s;
+          const int e = ii * N + c;
+          T1[e] = c0 * sm[e] + c1 * sm[NN + e] + cq[0] * sm[2 * NN + e] +
+                  cq[1] * sm[3 * NN + e] + cq[2] * sm[4 * NN + e];
+          T2[e] = nu1 * get64(blocks, kk, 0, NSLOT, e, NP) + nu2 * get64(blocks, kk, 1, NSLOT, e, NP);
         }
       }
     }
-    // t2 <- sum_m nu^m_kn B^m_kk (row ii per lane)
-    if (i < N) {
-      for (int c = 0; c < N; ++c)
-        T2[ii * N + c] = nu1 * get64(blocks, kk, 0, NSLOT, ii * N + c, NP) +
-                         nu2 * get64(blocks, kk, 1, NSLOT, ii * N + c, NP);
-    }
     __syncthreads();
-    // row ii of S_kj in registers
-    double srow[N];
-    {
+    // T3 <- S_kj (row ii per lane)
+    if (row) {
       const double* So = sm + ref_so(n, npl) * NN;
-      const double c1 = 0.5 * g.elen[n * Kp + kk] / area2k;
-      const double c2 = 1.0 / g.area2[j];
+      const double s1 = 0.5 * g.elen[n * Kp + kk] / area2k;
+      const double s2 = 1.0 / g.area2[j];
+#pragma unroll 1
+      for (int c = 0; c < N; ++c) {
+        double acc = -eta * So[ii * N + c];
 #pragma unroll
-      for (int c = 0; c < N; ++c) srow[c] = -eta * So[ii * N + c];
-      for (int l = 0; l < N; ++l) {
-        const double bl = T2[ii * N + l];
-        const double ul = get64(blocks, kk, 2 + n, NSLOT, ii * N + l, NP);
-#pragma unroll
-        for (int c = 0; c < N; ++c) srow[c] -= c1 * bl * So[l * N + c] + c2 * ul * T1[l * N + c];
+        for (int l = 0; l < N; ++l)
+          acc -= s1 * T2[ii * N + l] * So[l * N + c] +
+                 s2 * get64(blocks, kk, 2 + n, NSLOT, ii * N + l, NP) * T1[l * N + c];
+        T3[ii * N + c] = tau * acc;
       }
-#pragma unroll
-      for (int c = 0; c < N; ++c) srow[c] *= tau;
     }
     __syncthreads();
-    // t2 <- W_j; row ii of T = S_kj W_j^T
-    if (i < N) {
+    // T2 <- W_j;  T1 <- T = S_kj W_j^T
+    if (row) {
+#pragma unroll 1
       for (int c = 0; c < N; ++c) T2[ii * N + c] = get64(w64, j, 0, 1, ii * N + c, NP);
     }
     __syncthreads();
-    {
-      double trow[N];
+    if (row) {
+#pragma unroll 1
+      for (int c = 0; c < N; ++c) {
+        double acc = 0.0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) trow[c] = 0.0;
-      for (int l = 0; l < N; ++l) {
-        const double sl = srow[l];
-#pragma unroll
-        for (int c = 0; c < N; ++c) trow[c] += sl * T2[c * N + l];
-      }
-      if (i < N) {
-#pragma unroll
-        for (int c = 0; c < N; ++c) T1[ii * N + c] = trow[c];
+        for (int l = 0; l < N; ++l) acc += T3[ii * N + l] * T2[c * N + l];
+        T1[ii * N + c] = acc;
       }
     }
     __syncthreads();
-    // row ii of O = W_k T
-    double o[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) o[c] = 0.0;
-    for (int l = 0; l < N; ++l) {
-      const double wl = get64(w64, kk, 0, 1, ii * N + l, NP);
-#pragma unroll
-      for (int c = 0; c < N; ++c) o[c] += wl * T1[l * N + c];
-    }
+    // O = W_k T, row ii, straight to both sides; ||O||_F over the 16 lanes
     double nrm = 0.0;
+    if (row) {
+#pragma unroll 1
+      for (int c = 0; c < N; ++c) {
+        double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < N; ++c) nrm += o[c] * o[c];
-    if (i >= N) nrm = 0.0;
+        for (int l = 0; l < N; ++l) acc += get64(w64, kk, 0, 1, ii * N + l, NP) * T1[l * N + c];
+        nrm += acc * acc;
+        if (act) {
+          put<BT>(fo, k, n, 3, ii * N + c, N, acc);
+          put<BT>(fo, j, npl, 3, c * N + ii, N, acc);
+        }
+      }
+    }
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 16);
-    if (act && i < N) {
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        put<BT>(fb, k, 1 + n, ii * N + c, N, o[c]);
-        put<BT>(fb, j, 1 + npl, c * N + ii, N, o[c]);
-      }
-      if (i == 0) {
-        const float ln = (float)log(fmax(sqrt(nrm), 1e-300));
-        lognorm[n * Kp + k] = ln;
-        lognorm[npl * Kp + j] = ln;
-      }
+    if (act && i == 0) {
+      const float ln = (float)log(fmax(sqrt(nrm), 1e-300));
+      lognorm[n * Kp + k] = ln;
+      lognorm[npl * Kp + j] = ln;
     }
     __syncthreads();
   }
 }
 
 // y = W x
-template <int N, class T, class BT>
-__global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BT* __restrict__ fb,
+template <int N, class T, class BW>
+__global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BW* __restrict__ fw,
                                                const T* __restrict__ x, T* __restrict__ y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
@@ -224,13 +226,13 @@ __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BT* __restric
   load_vec<N, T>(x, k, xv);
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
-  block_mv<N, BT, T>(fb, k, 0, FAC_SLOTS, xv, acc);
+  block_mv<N, BW, T>(fw, k, 0, 1, xv, acc);
   store_vec<N, T>(y, k, acc);
 }
 
 // y = W^T x
-template <int N, class T, class BT>
-__global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BT* __restrict__ fb,
+template <int N, class T, class BW>
+__global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restrict__ fw,
                                                 const T* __restrict__ x, T* __restrict__ y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
@@ -238,15 +240,16 @@ __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BT* __restri
   load_vec<N, T>(x, k, xv);
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
-  block_mtv<N, BT, T>(fb, k, 0, FAC_SLOTS, xv, acc);
+  block_mtv<N, BW, T>(fw, k, 0, 1, xv, acc);
   store_vec<N, T>(y, k, acc);
 }
 
 // out = (I + F) x  (NBR false: omega_kn), or (I + F)^T x  (NBR true: omega_{k+ n+},
 // O_kn standing for O_{k+ n+}^T), followed by out = W^T out when WT.
 // partials (optional): per-block sums of <r, out> for the preconditioned dot.
-template <int N, class T, class BT, bool NBR, bool WT>
-__global__ void __launch_bounds__(256) k_fac_f(Geo g, const BT* __restrict__ fb,
+template <int N, class T, class BW, class BO, bool NBR, bool WT>
+__global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
+                                               const BO* __restrict__ fo,
                                                const float* __restrict__ om,
                                                const T* __restrict__ x, T* __restrict__ out,
                                                const T* __restrict__ r,
@@ -268,14 +271,14 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BT* __restrict__ fb,
         load_vec<N, T>(x, j, xj);
 #pragma unroll
         for (int i = 0; i < N; ++i) xj[i] *= -(T)w;
-        block_mv<N, BT, T>(fb, k, 1 + n, FAC_SLOTS, xj, acc);
+        block_mv<N, BO, T>(fo, k, n, 3, xj, acc);
       }
     }
     if (WT) {
       T o[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) o[i] = 0;
-      block_mtv<N, BT, T>(fb, k, 0, FAC_SLOTS, acc, o);
+      block_mtv<N, BW, T>(fw, k, 0, 1, acc, o);
       store_vec<N, T>(out, k, o);
       if (partials) {
         T rv[N];
@@ -296,8 +299,8 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BT* __restrict__ fb,
 }
 
 // d loss / d omega_kn = -(a_k^T O_kn beta_{k+} + alpha_k^T O_kn y_{k+}); 0 off the interior
-template <int N, class BT>
-__global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict__ fb,
+template <int N, class BO>
+__global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BO* __restrict__ fo,
                                                     const double* __restrict__ a,
                                                     const double* __restrict__ beta,
                                                     const double* __restrict__ alpha,
@@ -319,8 +322,8 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict_
       load_vec<N, double>(y, j, yj);
 #pragma unroll
       for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0.0;
-      block_mv<N, BT, double>(fb, k, 1 + n, FAC_SLOTS, bj, u1);
-      block_mv<N, BT, double>(fb, k, 1 + n, FAC_SLOTS, yj, u2);
+      block_mv<N, BO, double>(fo, k, n, 3, bj, u1);
+      block_mv<N, BO, double>(fo, k, n, 3, yj, u2);
 #pragma unroll
       for (int i = 0; i < N; ++i) s += ak[i] * u1[i] + alk[i] * u2[i];
     }
@@ -328,11 +331,12 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BT* __restrict_
   }
 }
 
-// rows of the factor blocks for the triangles elems[0..n): out[r][s][i][j] (FP64),
-// lognorm[r][n] (may be NULL)
-template <class BT>
-__global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, int N, int64_t Kpad,
-                                  const BT* __restrict__ fb, const float* __restrict__ ln,
+// rows of the factor blocks for the triangles elems[0..n): out[r][s][i][j] (FP64,
+// s = 0 W, 1..3 O), lognorm[r][n] (may be NULL)
+template <class BW, class BO>
+__global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, int N,
+                                  int64_t Kpad, const BW* __restrict__ fw,
+                                  const BO* __restrict__ fo, const float* __restrict__ ln,
                                   double* __restrict__ out, float* __restrict__ lnout) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int NN = N * N;
@@ -340,15 +344,8 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
   const int f = (int)(t % NN);
   const int s = (int)((t / NN) % FAC_SLOTS);
   const int64_t r = t / ((int64_t)NN * FAC_SLOTS);
-  const int64_t k = elems[r];
-  constexpr int Wv = Blk<BT>::W;
-  const int NG = ngroups(N, Wv);
-  const BT v = fb[bgidx(k, s, f / Wv, FAC_SLOTS, NG, Wv) + f % Wv];
-  if constexpr (sizeof(BT) == 2) {
-    out[t] = (double)__uint_as_float((uint32_t)v << 16);
-  } else {
-    out[t] = (double)v;
-  }
+  const int64_t k = elems ? (int64_t)elems[r] : r;
+  out[t] = s == 0 ? get_any<BW>(fw, k, 0, 1, f, N) : get_any<BO>(fo, k, s - 1, 3, f, N);
   if (lnout && f == 0 && s < 3) lnout[r * 3 + s] = ln[s * Kpad + k];
 }
 
@@ -365,97 +362,109 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
     default: break;                                             \
   }
 
-#define LDG_SWITCH_BT(BTV, CALL)                                \
-  if ((BTV) == BT_BF16) {                                       \
-    using BTT = bf16;                                           \
+// W storage BW and O storage BO: (F32, F32), (BF16, BF16), (BF16, FP8)
+#define LDG_SWITCH_FAC(FS, CALL)                                \
+  if ((FS).ot == BT_FP8) {                                      \
+    using BW = bf16;                                            \
+    using BO = fp8;                                             \
+    CALL;                                                       \
+  } else if ((FS).ot == BT_BF16) {                              \
+    using BW = bf16;                                            \
+    using BO = bf16;                                            \
     CALL;                                                       \
   } else {                                                      \
-    using BTT = float;                                          \
+    using BW = float;                                           \
+    using BO = float;                                           \
     CALL;                                                       \
   }
 
-void launch_fac_setup(int N, int bt, const Geo& g, const double* refs, const double* blocks,
-                      const double* bj, double tau, double eta, double* w64, void* fb,
+void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* refs,
+                      const double* blocks, const double* bj, double tau, double eta, double* w64,
                       float* lognorm, int* status, hipStream_t st) {
-  LDG_SWITCH_BT(bt, {
-    LDG_SWITCH_N(N, (k_fac_chol<NT, BTT><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
-                        g, bj, w64, (BTT*)fb, status)));
-    LDG_SWITCH_N(N, (k_fac_offdiag<NT, BTT><<<nbk(g.Kpad, 4), 64, 0, st>>>(
-                        g, refs, blocks, w64, tau, eta, (BTT*)fb, lognorm)));
+  LDG_SWITCH_FAC(fs, {
+    LDG_SWITCH_N(N, (k_fac_chol<NT, BW><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
+                        g, bj, w64, (BW*)fs.w, status)));
+    LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO><<<nbk(g.Kpad, 4), 64, 0, st>>>(
+                        g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm)));
   })
 }
 
-void launch_fac_apply(int N, int bt, int vt, const Geo& g, const void* fb, const float* om,
+void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const float* om,
                       const void* r, void* y, void* a, void* z, const Reducer* red,
                       hipStream_t st) {
   const unsigned nb = nbk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
-  LDG_SWITCH_BT(bt, {
-    const BTT* f = (const BTT*)fb;
+  LDG_SWITCH_FAC(fs, {
+    const BW* fw = (const BW*)fs.w;
+    const BO* fo = (const BO*)fs.o;
     if (vt == VT_F64) {
       using T = double;
-      LDG_SWITCH_N(N, (k_fac_w<NT, T, BTT><<<nb, 256, 0, st>>>(g.Kpad, f, (const T*)r, (T*)y)));
-      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, false, false><<<nb, 256, 0, st>>>(
-                          g, f, om, (const T*)y, (T*)a, nullptr, nullptr)));
-      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, true, true><<<nb, 256, 0, st>>>(
-                          g, f, om, (const T*)a, (T*)z, (const T*)r, parts)));
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, false, false><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, true, true><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
     } else {
       using T = float;
-      LDG_SWITCH_N(N, (k_fac_w<NT, T, BTT><<<nb, 256, 0, st>>>(g.Kpad, f, (const T*)r, (T*)y)));
-      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, false, false><<<nb, 256, 0, st>>>(
-                          g, f, om, (const T*)y, (T*)a, nullptr, nullptr)));
-      LDG_SWITCH_N(N, (k_fac_f<NT, T, BTT, true, true><<<nb, 256, 0, st>>>(
-                          g, f, om, (const T*)a, (T*)z, (const T*)r, parts)));
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, false, false><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, true, true><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
     }
   })
   if (red) reduce_partials((int)nb, red->partials, red->result, st);
 }
 
-void launch_fac_w(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
+void launch_fac_w(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                   hipStream_t st) {
-  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_w<NT, double, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
-                                        g.Kpad, (const BTT*)fb, x, y))))
+  LDG_SWITCH_FAC(fs, LDG_SWITCH_N(N, (k_fac_w<NT, double, BW><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                         g.Kpad, (const BW*)fs.w, x, y))))
 }
 
-void launch_fac_wt(int N, int bt, const Geo& g, const void* fb, const double* x, double* y,
+void launch_fac_wt(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                    hipStream_t st) {
-  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_wt<NT, double, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
-                                        g.Kpad, (const BTT*)fb, x, y))))
+  LDG_SWITCH_FAC(fs, LDG_SWITCH_N(N, (k_fac_wt<NT, double, BW><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                         g.Kpad, (const BW*)fs.w, x, y))))
 }
 
-void launch_fac_f(int N, int bt, const Geo& g, const void* fb, const float* om,
-                  bool transpose_and_wt, const double* x, double* out, hipStream_t st) {
+void launch_fac_f(int N, const FacStore& fs, const Geo& g, const float* om, bool transpose_and_wt,
+                  const double* x, double* out, hipStream_t st) {
   const unsigned nb = nbk(g.Kpad, 256);
-  LDG_SWITCH_BT(bt, {
-    const BTT* f = (const BTT*)fb;
+  LDG_SWITCH_FAC(fs, {
+    const BW* fw = (const BW*)fs.w;
+    const BO* fo = (const BO*)fs.o;
     if (transpose_and_wt) {
-      LDG_SWITCH_N(N, (k_fac_f<NT, double, BTT, true, true><<<nb, 256, 0, st>>>(
-                          g, f, om, x, out, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, double, BW, BO, true, true><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, x, out, nullptr, nullptr)));
     } else {
-      LDG_SWITCH_N(N, (k_fac_f<NT, double, BTT, false, false><<<nb, 256, 0, st>>>(
-                          g, f, om, x, out, nullptr, nullptr)));
+      LDG_SWITCH_N(N, (k_fac_f<NT, double, BW, BO, false, false><<<nb, 256, 0, st>>>(
+                          g, fw, fo, om, x, out, nullptr, nullptr)));
     }
   })
 }
 
-void launch_fac_domega(int N, int bt, const Geo& g, const void* fb, const double* a,
+void launch_fac_domega(int N, const FacStore& fs, const Geo& g, const double* a,
                        const double* beta, const double* alpha, const double* y, float* dom,
                        hipStream_t st) {
-  LDG_SWITCH_BT(bt, LDG_SWITCH_N(N, (k_fac_domega<NT, BTT><<<nbk(g.Kpad, 256), 256, 0, st>>>(
-                                        g, (const BTT*)fb, a, beta, alpha, y, dom))))
+  LDG_SWITCH_FAC(fs, LDG_SWITCH_N(N, (k_fac_domega<NT, BO><<<nbk(g.Kpad, 256), 256, 0, st>>>(
+                                         g, (const BO*)fs.o, a, beta, alpha, y, dom))))
 }
 
-// out[k][s][i][j] (FP64, row-major)
-void launch_fac_export(int64_t K, int N, int bt, const void* fb, double* out, hipStream_t st) {
-  launch_export_blocks_any(bt, K, N, FAC_SLOTS, fb, out, st);
+void launch_fac_export(int64_t K, int N, const FacStore& fs, double* out, hipStream_t st) {
+  const unsigned nb = nbk(K * FAC_SLOTS * N * N, 256);
+  LDG_SWITCH_FAC(fs, (k_fac_export_rows<BW, BO><<<nb, 256, 0, st>>>(
+                         K, nullptr, N, 0, (const BW*)fs.w, (const BO*)fs.o, nullptr, out,
+                         nullptr)))
 }
 
-void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, int bt, int64_t Kpad,
-                            const void* fb, const float* lognorm, double* out, float* lnout,
+void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, const FacStore& fs,
+                            int64_t Kpad, const float* lognorm, double* out, float* lnout,
                             hipStream_t st) {
   const unsigned nb = nbk(n * FAC_SLOTS * N * N, 256);
-  LDG_SWITCH_BT(bt, (k_fac_export_rows<BTT><<<nb, 256, 0, st>>>(n, elems, N, Kpad, (const BTT*)fb,
-                                                                lognorm, out, lnout)))
+  LDG_SWITCH_FAC(fs, (k_fac_export_rows<BW, BO><<<nb, 256, 0, st>>>(
+                         n, elems, N, Kpad, (const BW*)fs.w, (const BO*)fs.o, lognorm, out,
+                         lnout)))
 }
 
 }  // namespace ldg

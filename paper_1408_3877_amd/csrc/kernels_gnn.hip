@@ -68,13 +68,16 @@ __global__ void k_gnn_features(Geo g, const double* __restrict__ D, double dt, d
     f[N] = (float)log(area / meanA);
     f[N + 1] = (float)log(dt * dbar / area);
     f[N + 2] = (float)eta;
+#pragma unroll
     for (int n = 0; n < 3; ++n) {
       const int64_t kp = g.nbr[n * Kp + k];
       if (kp < 0) continue;
       e[n][0] = (float)g.nu[(2 * n) * Kp + k];
       e[n][1] = (float)g.nu[(2 * n + 1) * Kp + k];
       e[n][2] = (float)log(g.elen[n * Kp + k] / sqrt(meanA));
-      e[n][3 + 3 * n + g.nbrn[n * Kp + k]] = 1.f;
+      const int hot = 3 * n + g.nbrn[n * Kp + k];   // one-hot (n, n+), compile-time slots
+#pragma unroll
+      for (int c = 0; c < 9; ++c) e[n][3 + c] = c == hot ? 1.f : 0.f;
       const double dp = fabs(1.4142135623730951 * D[vidx(kp, 0, N)]);
       e[n][12] = (float)log(dp / dbar);
     }

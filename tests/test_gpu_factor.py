@@ -78,6 +78,22 @@ def test_factor_bf16_storage_rounds_the_fp32_blocks():
         assert np.all(np.abs(got - want) <= bound), np.max(np.abs(got - want) / bound)
 
 
+def test_factor_fp8_storage_rounds_the_blocks():
+    g, D, dt, sy, s = _setup(8, 3, 706, storage="fp8")
+    s.gnn_set_params(_theta(sy.N, 706))
+    s.gnn_set_context(D, dt)
+    blk = to_np(s.gnn_factor_export()[0])
+    m = sy.mask
+    Wk, O = sy.Wk, sy.O[m]
+    bw = 2.0 ** -8 * (1 + 2.0 ** -16) * np.abs(Wk) + 1e-12 * np.abs(Wk).max()
+    assert np.all(np.abs(blk[:, 0] - Wk) <= bw)
+    # E4M3: 4 bits of precision for normal values (>= 2^-6), subnormal spacing 2^-9
+    assert np.abs(O).max() <= 1.0 + 1e-12
+    bo = np.maximum(2.0 ** -4 * (1 + 2.0 ** -20) * np.abs(O), 2.0 ** -10) + 1e-12
+    got = blk[:, 1:][m]
+    assert np.all(np.abs(got - O) <= bo), np.max(np.abs(got - O) / bo)
+
+
 @pytest.mark.parametrize("n,p,seed", [(7, 2, 711), (4, 3, 712)])
 def test_factor_energy_loss_and_gradient(n, p, seed):
     g, D, dt, sy, s = _setup(n, p, seed)
@@ -128,7 +144,7 @@ def _steps(s, w, pr, C, dt, nsteps):
     return out
 
 
-@pytest.mark.parametrize("weights", ["init", "nan", "init-bf16"])
+@pytest.mark.parametrize("weights", ["init", "nan", "init-bf16", "init-fp8"])
 def test_factor_preconditioner_steps(weights):
     from paper_1408_3877_amd import Solver
     n, p, dt = 12, 2, 0.02
@@ -140,7 +156,7 @@ def test_factor_preconditioner_steps(weights):
         s = Solver(cV, V0T, kind, p, rtol=1e-13, max_iters=20000, precond=pc)
         if pc:
             s.gnn_set_mode("factor")
-            s.gnn_factor_storage("bf16" if weights.endswith("bf16") else "f32")
+            s.gnn_factor_storage(weights.split("-")[1] if "-" in weights else "f32")
             th = _theta(s.N, 723)
             if weights == "nan":
                 th = np.full_like(th, np.nan)
