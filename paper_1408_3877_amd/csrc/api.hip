@@ -224,8 +224,9 @@ double grad_flops(const ldg_ctx* c) {
 }
 
 // y = M x + tau (eta S' x + sum_m B^m Z^m(x)), Z^m(x) = -M^{-1}(A^m x [+ J^m])
+// y = A x; with dot, also <x, y> into red.result[0] (fused into the divergence half)
 void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j, void* Zx1,
-              void* Zx2, void* y) {
+              void* Zx2, void* y, bool dot = false) {
   {
     Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c));
     launch_grad(c->N, L.vt, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
@@ -233,7 +234,7 @@ void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j
   }
   Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c));
   launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y,
-             c->st);
+             c->st, dot ? &c->red : nullptr);
 }
 
 void bj_apply(ldg_ctx* c, const Level& L, const void* r, void* z, bool dot) {
@@ -326,8 +327,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   kaxpby(c, L, 1.0, L.z, 0.0, L.p);
   int it = 0;
   while (it < maxit) {
-    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q);
-    kdots(c, L, 1, L.p, L.q);
+    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>
     TRY(fetch(c, c->red.result, 1, hb));
     const double pq = hb[0];
     if (!(pq > 0.0) || !(rz > 0.0)) {
@@ -606,8 +606,7 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
   int it_best = 0;
   int it = 0;
   while (it < maxit) {
-    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q);
-    kdots(c, L, 1, L.p, L.q);
+    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>
     TRY(fetch(c, c->red.result, 1, hb));
     const double pq = hb[0];
     if (!(pq > 0.0) || !(rz > 0.0)) {

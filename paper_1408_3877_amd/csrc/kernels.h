@@ -17,10 +17,11 @@ enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2, BT_FP8 = 3 };
 // kernels_apply.hip
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
                  const void* J2, void* Z1, void* Z2, hipStream_t st);
+struct Reducer;
+// red (optional): red->result[0] = <C, y> afterwards
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
                 const void* C, const void* Z1, const void* Z2, double alpha, double tau,
-                double eta, void* y, hipStream_t st);
-struct Reducer;
+                double eta, void* y, hipStream_t st, const Reducer* red = nullptr);
 // z = P^{-1} r; with red != NULL also red->result[0] = <r, z>
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
                      const Reducer* red, hipStream_t st);

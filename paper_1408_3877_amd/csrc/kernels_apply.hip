@@ -113,22 +113,18 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   store_vec<N, T>(Z2, k, a2);
 }
 
+// one triangle of the divergence half; returns <C_k, y_k> for the fused dot
 template <int N, class T, class BT>
-__global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
-                                             const BT* __restrict__ blocks,
-                                             const T* __restrict__ C, const T* __restrict__ Z1,
-                                             const T* __restrict__ Z2, double alpha, double tau,
-                                             double eta, T* __restrict__ y) {
-  __shared__ T sm[NREF * N * N];
-  load_refs<N, T>(sm, refs);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.Kpad) return;
+__device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
+                                 const BT* __restrict__ blocks, const T* __restrict__ C,
+                                 const T* __restrict__ Z1, const T* __restrict__ Z2, double alpha,
+                                 double tau, double eta, T* __restrict__ y, int64_t k) {
   T t[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = 0;
   if (k >= g.K) {
     store_vec<N, T>(y, k, t);
-    return;
+    return 0.0;
   }
   const int64_t Kp = g.Kpad;
   T c[N], z[N];
@@ -159,9 +155,37 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
   }
   const T a2 = (T)(alpha * g.area2[k]);
   const T tt = (T)tau;
+  double dot = 0.0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) t[i] = a2 * c[i] + tt * t[i];
+  for (int i = 0; i < N; ++i) {
+    t[i] = a2 * c[i] + tt * t[i];
+    dot += (double)c[i] * (double)t[i];
+  }
   store_vec<N, T>(y, k, t);
+  return dot;
+}
+
+// y = alpha M C + tau (eta S' C + sum_m B^m Z^m); partials (optional): per-block
+// sums of <C, y>, the CG curvature p^T A p fused into the apply
+template <int N, class T, class BT>
+__global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
+                                             const BT* __restrict__ blocks,
+                                             const T* __restrict__ C, const T* __restrict__ Z1,
+                                             const T* __restrict__ Z2, double alpha, double tau,
+                                             double eta, T* __restrict__ y,
+                                             double* __restrict__ partials) {
+  __shared__ T sm[NREF * N * N];
+  __shared__ double red[4];
+  load_refs<N, T>(sm, refs);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (k < g.Kpad) s = div_row<N, T, BT>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
+  if (partials == nullptr) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // z = P^{-1} r; with `partials`, also per-block sums of <r, z> in FP64
@@ -281,21 +305,23 @@ void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C,
 
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
                 const void* C, const void* Z1, const void* Z2, double alpha, double tau,
-                double eta, void* y, hipStream_t st) {
+                double eta, void* y, hipStream_t st, const Reducer* red) {
   const unsigned nb = nblk(g.Kpad, 256);
+  double* parts = red ? red->partials : nullptr;
   if (vt == VT_F64) {
     LDG_SWITCH_N(N, (k_div<NT, double, double><<<nb, 256, 0, st>>>(
                         g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
-                        (const double*)Z2, alpha, tau, eta, (double*)y)));
+                        (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
   } else if (bt == BT_F32) {
     LDG_SWITCH_N(N, (k_div<NT, float, float><<<nb, 256, 0, st>>>(
                         g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y)));
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   } else {
     LDG_SWITCH_N(N, (k_div<NT, float, bf16><<<nb, 256, 0, st>>>(
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y)));
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   }
+  if (red) reduce_partials((int)nb, red->partials, red->result, st);
 }
 
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
