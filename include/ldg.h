@@ -55,8 +55,11 @@ typedef enum {
  * full system and the refinement correction stay FP64; each refinement
  * sweep solves A d = r with FP32 vectors (FP64 inner products), the stored
  * blocks in FP32 or BF16 and FP32 arithmetic, and a FP32 block-Jacobi.  A
- * sweep that fails to halve the residual moves the inner solve one
- * precision up (BF16 -> FP32 -> FP64), counted in ldg_step_info.fallbacks.
+ * sweep that fails to halve the FP64 residual although the inner solve
+ * reported a reduction at least four times larger (the low-precision operator,
+ * not the Krylov method, limits progress) moves the inner solve one precision
+ * up (BF16 -> FP32 -> FP64), counted in ldg_step_info.fallbacks.  With GMRES
+ * one sweep is one restart cycle.
  */
 typedef enum { LDG_FP64 = 0, LDG_MIXED_FP32 = 1, LDG_MIXED_BF16 = 2 } ldg_precision;
 typedef enum { LDG_PC_BLOCK_JACOBI = 0, LDG_PC_GNN = 1 } ldg_precond;
@@ -111,7 +114,8 @@ typedef struct {
  * CG), <r, P r> <= 0 with the learned preconditioner, a non-finite residual,
  * no new residual minimum (by 1%) within 200 flexible-CG iterations, a
  * nonsymmetric step (the learned preconditioner serves CG only), or a mixed
- * sweep that failed to halve the residual.
+ * sweep that failed to halve the residual while the inner solve reported a
+ * four times larger reduction.
  */
 typedef enum {
   LDG_FB_NONE = 0, LDG_FB_CURVATURE = 1, LDG_FB_RZ = 2, LDG_FB_NONFINITE = 3,

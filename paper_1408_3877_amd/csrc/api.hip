@@ -85,6 +85,7 @@ struct ldg_ctx {
   std::vector<Pending> pending;
   ldg_kernel_stat stats[LDG_K_COUNT] = {};
   int64_t n_sd = 0, n_nd = 0;   // local edges that are not Neumann / not Dirichlet
+  double inner_rho = 1.0;       // residual reduction the last inner solve reported
 };
 
 namespace {
@@ -320,6 +321,10 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   *not_spd = false;
   kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
   TRY(snapshot(c, L, 0));
+  double r0 = 0.0, rlast = 0.0;
+  TRY(norm2(c, L, L.r, &r0));
+  r0 = std::sqrt(r0);
+  rlast = r0;
   if (factor) fac_apply(c, L, L.r, L.z);
   else bj_apply(c, L, L.r, L.z, true);
   TRY(fetch(c, c->red.result, 1, hb));
@@ -344,6 +349,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     TRY(snapshot(c, L, it));
     const double rn = std::sqrt(hb[0]);
     if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
+    rlast = rn;
     if (rn <= tol_abs) break;
     if (factor) fac_apply(c, L, L.r, L.z);
     else bj_apply(c, L, L.r, L.z, true);
@@ -354,6 +360,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     kaxpby(c, L, 1.0, L.z, beta, L.p);
   }
   *iters = it;
+  c->inner_rho = r0 > 0.0 ? rlast / r0 : 1.0;
   return LDG_OK;
 }
 
@@ -424,6 +431,7 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
   }
   bj_apply(c, L, L.u, L.d, false);
   *iters = jend;
+  c->inner_rho = jend > 0 ? std::fabs(g[jend]) / rnorm : 1.0;
   return LDG_OK;
 }
 
@@ -602,7 +610,9 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
   // stagnation: no new residual minimum (by 1%) within FCG_PLATEAU iterations;
   // CG residual norms oscillate, so a fixed early reduction is not asked for
   constexpr int FCG_PLATEAU = 200;
-  double best = std::sqrt(hb[0]);
+  const double r0 = std::sqrt(hb[0]);
+  double rlast = r0;
+  double best = r0;
   int it_best = 0;
   int it = 0;
   while (it < maxit) {
@@ -622,6 +632,7 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
     ++it;
     TRY(snapshot(c, L, it));
     const double rn = std::sqrt(hb[0]);
+    rlast = rn;
     if (rn < 0.99 * best) {
       best = rn;
       it_best = it;
@@ -644,6 +655,7 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
     kaxpby(c, L, 1.0, L.z, beta, L.p);
   }
   *iters = it;
+  c->inner_rho = r0 > 0.0 ? rlast / r0 : 1.0;
   return LDG_OK;
 }
 
@@ -719,8 +731,10 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
     beta = std::sqrt(hb[0]);
     if (!std::isfinite(beta)) return fail(c, LDG_ENOCONV, "non-finite residual");
     if (beta <= target || iters >= c->opt.max_iters) break;
-    if (L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev) {
-      // refinement stagnates at this precision: BF16 -> FP32 -> FP64
+    if (L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev &&
+        beta > 4.0 * c->inner_rho * beta_prev) {
+      // refinement stagnates at this precision (the FP64 residual fell far less
+      // than the inner solve reported): BF16 -> FP32 -> FP64
       info->fallbacks += 1;
       info->fallback_reason = LDG_FB_PRECISION;
       if (L.bt == BT_BF16) {
