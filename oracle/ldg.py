@@ -285,6 +285,15 @@ class Problem:
         return (Y[2 * KN:].reshape(sh), Y[:KN].reshape(sh), Y[KN:2 * KN].reshape(sh),
                 dict(rhs=rhs, lhs=lhs, rel_residual=res, data=data, blocks=b))
 
+    def step_bdf2(self, C, C_prev, t_new, dt, workload, data=None):
+        """Two-step backward differentiation in time (second order), with the
+        space discretisation of the paper's implicit Euler step (Sec. 2.5):
+            W (3/2 Y^{n+1} - 2 Y^n + 1/2 Y^{n-1}) / dt + A^{n+1} Y^{n+1} = V^{n+1},
+        i.e. (W + tau A^{n+1}) Y^{n+1} = W Y* + tau V^{n+1} with tau = 2 dt / 3 and
+        Y* = (4 Y^n - Y^{n-1}) / 3.  W has zero Z rows, so only the C parts of the
+        history enter.  Equal steps dt are assumed."""
+        return self.step((4.0 * C - C_prev) / 3.0, t_new, 2.0 * dt / 3.0, workload, data)
+
     def solve_stationary(self, workload):
         """Solve A Y = V at t = 0 (the verification setting of Sec. 3.7)."""
         data = self.data(workload, 0.0)

@@ -5,7 +5,7 @@ import os
 import numpy as np
 import pytest
 
-from inputs.fields import TABLE2, Workload
+from inputs.fields import SMOOTH1, TABLE2, Workload
 from inputs.meshes import EAST, NORTH, SOUTH, WEST, square_mesh, two_triangle_mesh
 from oracle import basis
 from oracle.ldg import (Blocks, Problem, full_residual, l2_error, project, schur_matrix,
@@ -19,11 +19,14 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 class PolyWorkload:
     """c = P(x, y) (1 + a t), d linear; f, c_D, g_N consistent with eq:diffusion:nonmixed."""
 
-    def __init__(self, p, a=1.0, seed=0):
+    def __init__(self, p, a=1.0, seed=0, b=0.0):
         rng = np.random.default_rng(seed)
         self.terms = [(rng.uniform(-1, 1), i, j) for i in range(p + 1) for j in range(p + 1 - i)]
-        self.a = a
+        self.a, self.b = a, b          # time factor s(t) = 1 + a t + b t^2
         self.d0, self.d1, self.d2 = 1.3, 0.4, -0.3
+
+    def s(self, t):
+        return 1 + self.a * t + self.b * t * t
 
     def P(self, x, y, dx=0, dy=0):
         out = 0 * x
@@ -36,22 +39,22 @@ class PolyWorkload:
         return out
 
     def c(self, t, x, y):
-        return self.P(x, y) * (1 + self.a * t)
+        return self.P(x, y) * self.s(t)
 
     def d(self, t, x, y):
         return self.d0 + self.d1 * x + self.d2 * y
 
     def f(self, t, x, y):
-        s = 1 + self.a * t
+        s = self.s(t)
         lap = self.P(x, y, 2, 0) + self.P(x, y, 0, 2)
         dgc = self.d1 * self.P(x, y, 1, 0) + self.d2 * self.P(x, y, 0, 1)
-        return self.a * self.P(x, y) - s * (dgc + self.d(t, x, y) * lap)
+        return (self.a + 2 * self.b * t) * self.P(x, y) - s * (dgc + self.d(t, x, y) * lap)
 
     def c_D(self, t, x, y):
         return self.c(t, x, y)
 
     def g_N(self, t, x, y, n1, n2):
-        s = 1 + self.a * t
+        s = self.s(t)
         return -s * (self.P(x, y, 1, 0) * n1 + self.P(x, y, 0, 1) * n2)
 
     def c0(self, x, y):
@@ -85,6 +88,60 @@ def test_implicit_euler_exact_for_linear_in_time(p):
         assert info["rel_residual"] < 1e-12
         Cex = project(pr.grid, p, lambda x, y: w.c(t, x, y), pr.refs.hatM, order=2 * p + 2)
         np.testing.assert_allclose(C, Cex, atol=1e-10)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_bdf2_exact_for_quadratic_in_time_and_euler_is_not(p):
+    # c = P(x)(1 + a t + b t^2): the two-step formula differentiates quadratics
+    # exactly, so from exact C^0, C^1 every BDF2 step reproduces c; implicit
+    # Euler does not (its error is dt b P per step)
+    cV, V0T, kind = square_mesh(3, seed=35, neumann_sides=(NORTH, WEST))
+    pr = Problem(cV, V0T, kind, p)
+    w = PolyWorkload(p, a=1.5, seed=40 + p, b=-2.0)
+    dt = 0.05
+    proj = lambda t: project(pr.grid, p, lambda x, y: w.c(t, x, y), pr.refs.hatM, order=2 * p + 2)
+    Cm, C = proj(0.0), proj(dt)
+    t = dt
+    for _ in range(3):
+        t += dt
+        Cn, _, _, info = pr.step_bdf2(C, Cm, t, dt, w)
+        assert info["rel_residual"] < 1e-12
+        np.testing.assert_allclose(Cn, proj(t), atol=1e-10)
+        Cm, C = C, Cn
+    Ce, _, _, _ = pr.step(proj(dt), 2 * dt, dt, w)
+    assert np.abs(Ce - proj(2 * dt)).max() > 1e-4
+
+
+def test_bdf2_converges_at_second_order_in_time():
+    # smooth manufactured data, end time 0.4, dt = 0.4/8 ... 0.4/64 with the same
+    # space discretisation: differences of successive solutions shrink by ~4
+    # under BDF2 (implicit Euler first step) and by ~2 under implicit Euler
+    cV, V0T, kind = square_mesh(4, seed=36)
+    p = 3
+    pr = Problem(cV, V0T, kind, p)
+    w = Workload(SMOOTH1)
+    T = 0.4
+    area = pr.grid.areaT[:, None]
+    norm = lambda X: np.sqrt(np.sum(area * X ** 2))
+    sol2, sol1 = [], []
+    for nsteps in (8, 16, 32, 64):
+        dt = T / nsteps
+        C0 = pr.initial(w)
+        C1, _, _, _ = pr.step(C0, dt, dt, w)
+        Cm, C, Ce, t = C0, C1, C1, dt
+        for _ in range(nsteps - 1):
+            t += dt
+            Cn, _, _, _ = pr.step_bdf2(C, Cm, t, dt, w)
+            Cm, C = C, Cn
+            Ce, _, _, _ = pr.step(Ce, t, dt, w)
+        sol2.append(C)
+        sol1.append(Ce)
+    d2 = [norm(sol2[i] - sol2[i + 1]) for i in range(3)]
+    d1 = [norm(sol1[i] - sol1[i + 1]) for i in range(3)]
+    r2 = [d2[i] / d2[i + 1] for i in range(2)]
+    r1 = [d1[i] / d1[i + 1] for i in range(2)]
+    assert all(3.4 < r < 4.6 for r in r2), (d2, r2)
+    assert all(1.7 < r < 2.3 for r in r1), (d1, r1)
 
 
 def test_z_history_does_not_enter_the_step():
