@@ -88,6 +88,7 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
         s.gnn_set_mode("factor")
         s.gnn_factor_storage(args.fac_storage)
         s.gnn_set_params(weights)
+    s.set_time_scheme(args.time_scheme)
     log("[bench] %s: context K=%d N=%d (%.1f s)" % (label, s.K, s.N, time.perf_counter() - t0))
     gk = cfg["kind"]
     s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
@@ -195,6 +196,8 @@ def main():
     ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
     ap.add_argument("--fac-storage", default="fp8", choices=["f32", "bf16", "fp8"],
                     help="storage of the learned preconditioner's factor blocks")
+    ap.add_argument("--time-scheme", default="euler", choices=["euler", "bdf2"],
+                    help="implicit Euler (the paper's) or two-step backward differentiation")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--no-baseline", action="store_true",
@@ -267,7 +270,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
-                   "dt": dt_of(cfg), "rtol": args.rtol, "solver": solver_desc,
+                   "dt": dt_of(cfg), "rtol": args.rtol, "time_scheme": args.time_scheme,
+                   "solver": solver_desc,
                    "weights": os.path.relpath(args.weights or WEIGHTS.get(cfg["p"]), ROOT)
                    if learned else None,
                    "iters_per_step": sum(i["iters"] for i in infos) / len(infos),

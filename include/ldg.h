@@ -107,6 +107,7 @@ typedef struct {
   int guarded_iters;   /* of those, iterations that took the block-Jacobi direction
                           because <r, P r> < 0.25 <r, BJ^{-1} r> */
   int fallback_reason; /* ldg_fallback of the last fallback taken */
+  int bdf_order;       /* 1: implicit Euler step, 2: two-step backward differentiation */
 } ldg_step_info;
 
 /*
@@ -178,6 +179,23 @@ ldg_status ldg_set_initial_samples(ldg_ctx* ctx, const double* c0_samples, doubl
  */
 ldg_status ldg_step_sampled(ldg_ctx* ctx, double dt, const double* d, const double* f,
                             const double* cD, const double* gN, ldg_step_info* info);
+
+/*
+ * Time scheme of the steps.  LDG_TIME_EULER (default): the implicit Euler step
+ * of Sec. 2.5.  LDG_TIME_BDF2: the second-order two-step backward
+ * differentiation formula with the same space discretisation,
+ *   W (3/2 Y^{n+1} - 2 Y^n + 1/2 Y^{n-1}) / dt + A^{n+1} Y^{n+1} = V^{n+1},
+ * solved as (W + tau A) Y^{n+1} = W Y* + tau V with tau = 2 dt / 3 and
+ * C* = (4 C^n - C^{n-1}) / 3 (W has zero Z rows).  It needs the previous state
+ * at the same dt: every step keeps its starting state; ldg_set_state and
+ * ldg_set_initial_samples clear it, ldg_set_history sets it (device K x N,
+ * element-major, with its step size).  Without it, or after a change of dt,
+ * a step is implicit Euler (ldg_step_info.bdf_order says which).
+ * Unknown schemes: LDG_EINVAL.
+ */
+typedef enum { LDG_TIME_EULER = 0, LDG_TIME_BDF2 = 1 } ldg_time_scheme;
+ldg_status ldg_set_time_scheme(ldg_ctx* ctx, int scheme);
+ldg_status ldg_set_history(ldg_ctx* ctx, const double* C_prev, double dt_prev);
 
 /* Current C, Z1, Z2 (K x N each, element-major, caller's element order). Any may be NULL. */
 ldg_status ldg_get_solution(ldg_ctx* ctx, double* C, double* Z1, double* Z2, int on_device);

@@ -86,6 +86,12 @@ struct ldg_ctx {
   ldg_kernel_stat stats[LDG_K_COUNT] = {};
   int64_t n_sd = 0, n_nd = 0;   // local edges that are not Neumann / not Dirichlet
   double inner_rho = 1.0;       // residual reduction the last inner solve reported
+  // time scheme: implicit Euler, or two-step backward differentiation with the
+  // state of the previous step (kept after every step) and its step size
+  int tscheme = 0;
+  double *Cprev = nullptr, *Cstar = nullptr;
+  bool have_prev = false;
+  double dt_prev = 0.0;
 };
 
 namespace {
@@ -1100,6 +1106,7 @@ ldg_status ldg_project(ldg_ctx* c, const double* samples, double* out) {
 
 ldg_status ldg_set_state(ldg_ctx* c, const double* C, int on_device, double t) {
   if (!c || !C) return fail(c, LDG_EINVAL, "bad arguments");
+  c->have_prev = false;
   const double* src = C;
   if (!on_device) {
     HIPCHK(c, hipMemcpyAsync(c->u, C, c->K * c->N * sizeof(double), hipMemcpyHostToDevice, c->st));
@@ -1113,9 +1120,37 @@ ldg_status ldg_set_state(ldg_ctx* c, const double* C, int on_device, double t) {
 
 ldg_status ldg_set_initial_samples(ldg_ctx* c, const double* c0, double t0) {
   if (!c || !c0) return fail(c, LDG_EINVAL, "bad arguments");
+  c->have_prev = false;
   launch_project(c->N, c->K, c->Kpad, c->R, c0, c->Wvol, c->C, c->st);
   c->t = t0;
   return check_launch(c);
+}
+
+namespace {
+ldg_status hist_alloc(ldg_ctx* c) {
+  if (!c->Cprev) {
+    TRY(dalloc(c, &c->Cprev, c->nvec));
+    TRY(dalloc(c, &c->Cstar, c->nvec));
+  }
+  return LDG_OK;
+}
+}  // namespace
+
+ldg_status ldg_set_time_scheme(ldg_ctx* c, int scheme) {
+  if (!c || (scheme != LDG_TIME_EULER && scheme != LDG_TIME_BDF2))
+    return fail(c, LDG_EINVAL, "unknown time scheme");
+  c->tscheme = scheme;
+  return LDG_OK;
+}
+
+ldg_status ldg_set_history(ldg_ctx* c, const double* Cprev, double dt_prev) {
+  if (!c || !Cprev || !(dt_prev > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(hist_alloc(c));
+  launch_to_tiled(c->K, c->Kpad, c->N, Cprev, c->Cprev, c->st);
+  c->have_prev = true;
+  c->dt_prev = dt_prev;
+  TRY(check_launch(c));
+  return sync(c);
 }
 
 ldg_status ldg_get_solution(ldg_ctx* c, double* C, double* Z1, double* Z2, int on_device) {
@@ -1232,7 +1267,12 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
                             const double* cD, const double* gN, ldg_step_info* info) {
   if (!c || !d || !f || !info || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
   std::memset(info, 0, sizeof(*info));
-  const double tau = dt;
+  TRY(hist_alloc(c));
+  // BDF2 needs the previous state at the same step size; else implicit Euler
+  const bool bdf2 = c->tscheme == LDG_TIME_BDF2 && c->have_prev &&
+                    std::fabs(dt - c->dt_prev) <= 1e-12 * dt;
+  const double tau = bdf2 ? 2.0 * dt / 3.0 : dt;
+  info->bdf_order = bdf2 ? 2 : 1;
   const int64_t n = c->nvec;
   // a1: projections and boundary data at t + dt
   {
@@ -1245,7 +1285,7 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   }
   if (c->opt.precond == LDG_PC_GNN) {
     if (!c->gnn_params_set) return fail(c, LDG_EINVAL, "learned preconditioner without parameters");
-    launch_gnn_features(c->N, c->geo, c->D, dt, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
+    launch_gnn_features(c->N, c->geo, c->D, tau, c->opt.eta, c->meanA, c->gnode, c->gedge, c->st);
   }
   // a2, a3: D-dependent blocks
   {
@@ -1259,7 +1299,14 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   // a4: preconditioner
   TRY(ldg_bj_setup(c, tau));
   // right-hand side and its full-system norm
-  launch_rhs(c->geo, c->N, c->C, c->KDN, c->F, tau, c->b3, c->st);
+  // the history the step starts from: C^n, or (4 C^n - C^{n-1}) / 3 for BDF2
+  const double* Chist = c->C;
+  if (bdf2) {
+    launch_axpby(VT_F64, n, 4.0 / 3.0, c->C, 0.0, c->Cstar, c->st);
+    launch_axpby(VT_F64, n, -1.0 / 3.0, c->Cprev, 1.0, c->Cstar, c->st);
+    Chist = c->Cstar;
+  }
+  launch_rhs(c->geo, c->N, Chist, c->KDN, c->F, tau, c->b3, c->st);
   double nb3 = 0.0, nj1 = 0.0, nj2 = 0.0;
   TRY(norm2(c, level64(c), c->b3, &nb3));
   TRY(norm2(c, level64(c), c->J1, &nj1));
@@ -1287,7 +1334,10 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
     return s;
   }
   if (c->col_n > 0) TRY(finish_collect(c, tau));
-  // a10: accept; Z from the last residual evaluation of X
+  // a10: accept; Z from the last residual evaluation of X; C^n becomes the history
+  HIPCHK(c, hipMemcpyAsync(c->Cprev, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->have_prev = true;
+  c->dt_prev = dt;
   HIPCHK(c, hipMemcpyAsync(c->C, c->X, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->Z1, c->tZ1, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->Z2, c->tZ2, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));

@@ -47,7 +47,7 @@ class StepInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("ir_steps", C.c_int),
                 ("fallbacks", C.c_int), ("krylov", C.c_int), ("rel_residual", C.c_double),
                 ("t", C.c_double), ("learned_iters", C.c_int), ("guarded_iters", C.c_int),
-                ("fallback_reason", C.c_int)]
+                ("fallback_reason", C.c_int), ("bdf_order", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +83,8 @@ _SIGS = {
     "ldg_gnn_factor_export": [_P, _P, _P],
     "ldg_gnn_factor_storage": [_P, C.c_int],
     "ldg_gnn_factor_export_rows": [_P, _P, C.c_int64, _P, _P],
+    "ldg_set_time_scheme": [_P, C.c_int],
+    "ldg_set_history": [_P, _P, C.c_double],
     "ldg_gnn_set_loss": [_P, C.c_int],
     "ldg_gnn_loss_grad": [_P, _P, _P, _P, C.POINTER(C.c_double)],
     "ldg_gnn_train_step": [_P, _P, _P, C.c_double, C.POINTER(C.c_double)],
@@ -218,6 +220,15 @@ class Solver:
                                          C.byref(info))
         self._check(code)
         return info.as_dict()
+
+    def set_time_scheme(self, scheme):
+        """"euler" (0) or "bdf2" (1)."""
+        k = {"euler": 0, "bdf2": 1}.get(scheme, scheme)
+        self._check(self.lib.ldg_set_time_scheme(self.h, int(k)))
+
+    def set_history(self, C_prev, dt_prev):
+        Cd = self._dev(C_prev, (self.K, self.N))
+        self._check(self.lib.ldg_set_history(self.h, _ptr(Cd), float(dt_prev)))
 
     def get_solution(self):
         Cm, Z1, Z2 = self._empty(self.K, self.N), self._empty(self.K, self.N), self._empty(self.K, self.N)

@@ -247,3 +247,65 @@ def test_mixed_precision_refinement(torch_mod, precision, p, n, seed, neu, wk):
                      infos=infos)
     assert err < 1e-9, err
     assert all(i["ir_steps"] >= 1 for i in infos)
+
+
+@pytest.mark.parametrize("p,n,seed,neu,wk", [
+    (2, 6, 801, (NORTH,), SMOOTH1),
+    (3, 6, 802, (), LOGNORMAL),
+])
+def test_bdf2_steps_match_the_oracle(torch_mod, p, n, seed, neu, wk):
+    # first step implicit Euler (no history yet), then two-step BDF; a change of
+    # dt falls back to implicit Euler
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
+    pr = Problem(cV, V0T, kind, p)
+    w = workload(wk, n, seed=seed, sigma=1.5, block=2)
+    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000)
+    s.set_time_scheme("bdf2")
+    gk = {SMOOTH1: 1, LOGNORMAL: 3}[wk]
+    dT = getattr(w, "dT", None)
+    s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"], 0.0)
+    C = pr.initial(w)
+    Cm = None
+    t = 0.0
+    for i, dt in enumerate([0.02, 0.02, 0.02, 0.01]):
+        t += dt
+        smp = s.sample_workload(gk, t, dT=dT)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        order = 2 if i in (1, 2) else 1
+        assert info["bdf_order"] == order and info["rel_residual"] <= 1e-13, info
+        if order == 2:
+            Cn, _, _, _ = pr.step_bdf2(C, Cm, t, dt, w)
+        else:
+            Cn, _, _, _ = pr.step(C, t, dt, w)
+        Cm, C = C, Cn
+        assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_bdf2_exact_for_quadratic_in_time(torch_mod, p):
+    # c = P(x)(1 + a t + b t^2) with linear d, data sampled on the host at the
+    # library's own points: from exact C^0, C^1 every BDF2 step reproduces the
+    # projection of c to rounding
+    from tests.test_oracle_solver import PolyWorkload
+    from oracle.ldg import project
+    cV, V0T, kind = square_mesh(3, seed=35, neumann_sides=(NORTH, WEST))
+    pr = Problem(cV, V0T, kind, p)
+    w = PolyWorkload(p, a=1.5, seed=40 + p, b=-2.0)
+    s = _solver(cV, V0T, kind, p, rtol=1e-13, restart=40, max_iters=20000, krylov=1)
+    xv, yv = (to_np(a) for a in s.quad_points(0))
+    xb, yb = (to_np(a) for a in s.quad_points(1))
+    n1, n2 = (to_np(a) for a in s.quad_points(2))
+    dev = lambda a: torch_mod.as_tensor(np.ascontiguousarray(a), device="cuda")
+    dt = 0.05
+    s.set_state(to_np(s.project(dev(w.c(dt, xv, yv)))), dt)
+    s.set_history(to_np(s.project(dev(w.c(0.0, xv, yv)))), dt)
+    s.set_time_scheme("bdf2")
+    t = dt
+    for _ in range(3):
+        t += dt
+        info = s.step_sampled(dt, dev(w.d(t, xv, yv)), dev(w.f(t, xv, yv)),
+                              dev(w.c_D(t, xb, yb)), dev(w.g_N(t, xb, yb, n1, n2)))
+        assert info["bdf_order"] == 2
+        want = project(pr.grid, p, lambda x, y: w.c(t, x, y), pr.refs.hatM, order=2 * p + 2)
+        got = to_np(s.get_solution()[0])
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
