@@ -78,7 +78,8 @@ typedef struct {
   double eta;         /* penalty eta > 0 (prob:semidiscrete), default 1 */
   int precision;      /* ldg_precision, default LDG_FP64 */
   int precond;        /* ldg_precond, default LDG_PC_BLOCK_JACOBI */
-  double rtol;        /* relative residual of the full system, default 1e-8 */
+  double rtol;        /* relative residual of the full system, default 1e-8; FP64 rounding
+                         bounds what is reachable near 1e-16 ||A|| ||Y|| / ||V|| */
   int restart;        /* GMRES restart length m, default 30 */
   int max_iters;      /* total Krylov iterations per step, default 5000 */
   void* stream;       /* hipStream_t for all device work */
@@ -179,6 +180,22 @@ ldg_status ldg_set_initial_samples(ldg_ctx* ctx, const double* c0_samples, doubl
  */
 ldg_status ldg_step_sampled(ldg_ctx* ctx, double dt, const double* d, const double* f,
                             const double* cD, const double* gN, ldg_step_info* info);
+
+/*
+ * The stationary system A Y = V (eq:fullSystem without the W term; the
+ * verification setting of Sec. 3.7, Table 2), with the same data arguments
+ * as ldg_step_sampled (sampled at whatever time the caller chooses).  Solved
+ * through the same eliminated operator with the mass term dropped,
+ *   eta S' C + sum_m B^m Z^m(C) = K_D,N + M F + sum_m B^m M^{-1} J^m,
+ * by the same Krylov solver, preconditioner and precision options, starting
+ * from C = 0.  The solution becomes the state (C, Z1, Z2); the time level is
+ * unchanged and the BDF2 history is cleared.  info->bdf_order is 0.  A mesh
+ * with no Dirichlet edge (the operator then has the constants in its
+ * kernel): LDG_EINVAL before any launch.  On LDG_ENOCONV the state is left
+ * unchanged.
+ */
+ldg_status ldg_solve_stationary_sampled(ldg_ctx* ctx, const double* d, const double* f,
+                                        const double* cD, const double* gN, ldg_step_info* info);
 
 /*
  * Time scheme of the steps.  LDG_TIME_EULER (default): the implicit Euler step

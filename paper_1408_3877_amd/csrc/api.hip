@@ -1,6 +1,7 @@
 // C ABI of the LDG library: context, data upload, one implicit Euler step
 // (projection, assembly, preconditioner, restarted GMRES, recovery of Z).
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -92,6 +93,7 @@ struct ldg_ctx {
   double *Cprev = nullptr, *Cstar = nullptr;
   bool have_prev = false;
   double dt_prev = 0.0;
+  double alpha = 1.0;   // mass coefficient of the operator (0 for the stationary system)
 };
 
 namespace {
@@ -240,8 +242,8 @@ void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j
                 Zx1, Zx2, c->st);
   }
   Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c));
-  launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, 1.0, tau, c->opt.eta, y,
-             c->st, dot ? &c->red : nullptr);
+  launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, c->alpha, tau, c->opt.eta,
+             y, c->st, dot ? &c->red : nullptr);
 }
 
 void bj_apply(ldg_ctx* c, const Level& L, const void* r, void* z, bool dot) {
@@ -782,10 +784,12 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   info->restarts = sweeps;
   info->ir_steps = c->opt.precision == LDG_FP64 ? 0 : sweeps;
   info->rel_residual = beta / bnorm;
-  if (!(beta <= target))
-    return fail(c, LDG_ENOCONV, "solver reached " + std::to_string(iters) +
-                                    " iterations at relative residual " +
-                                    std::to_string(beta / bnorm));
+  if (!(beta <= target)) {
+    char msg[128];
+    std::snprintf(msg, sizeof(msg), "solver reached %d iterations at relative residual %.3e",
+                  iters, beta / bnorm);
+    return fail(c, LDG_ENOCONV, msg);
+  }
   return LDG_OK;
 }
 
@@ -1246,7 +1250,8 @@ ldg_status ldg_bj_setup(ldg_ctx* c, double dt) {
     const double NN = (double)c->NN;
     Timed tm(c, LDG_K_BJ_SETUP, 8.0 * NN * (3.0 * c->K + 2.0 * c->Eint),
              2.0 * NN * c->N * (11.0 * c->K + 2.0 * c->Eint));
-    launch_bj_setup(c->N, c->geo, c->refs, c->blocks, dt, c->opt.eta, c->bj, c->status, c->st);
+    launch_bj_setup(c->N, c->geo, c->refs, c->blocks, c->alpha, dt, c->opt.eta, c->bj, c->status,
+                    c->st);
   }
   TRY(check_launch(c));
   int st = 0;
@@ -1263,18 +1268,25 @@ ldg_status ldg_get_bj(ldg_ctx* c, double* out) {
   return check_launch(c);
 }
 
-ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double* f,
-                            const double* cD, const double* gN, ldg_step_info* info) {
-  if (!c || !d || !f || !info || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
-  std::memset(info, 0, sizeof(*info));
-  TRY(hist_alloc(c));
-  // BDF2 needs the previous state at the same step size; else implicit Euler
-  const bool bdf2 = c->tscheme == LDG_TIME_BDF2 && c->have_prev &&
-                    std::fabs(dt - c->dt_prev) <= 1e-12 * dt;
-  const double tau = bdf2 ? 2.0 * dt / 3.0 : dt;
-  info->bdf_order = bdf2 ? 2 : 1;
+}  // extern "C"
+
+namespace {
+
+// One linear system of the method at sampled data, solved for C into X from X0:
+//   alpha M C + tau (eta S' C + sum_m B^m Z^m(C)) = alpha M Chist + tau (K_D,N + M F)
+//                                                   + tau sum_m B^m M^{-1} J^m,
+// alpha = 1: an implicit Euler or BDF2 step (Chist its history); alpha = 0,
+// tau = 1: the stationary system A Y = V (no history, Chist unused).
+ldg_status solve_sampled(ldg_ctx* c, double alpha, double tau, const double* Chist,
+                         const double* X0, const double* d, const double* f, const double* cD,
+                         const double* gN, ldg_step_info* info) {
+  struct Scope {   // the mass coefficient holds for this system only
+    ldg_ctx* c;
+    ~Scope() { c->alpha = 1.0; }
+  } scope{c};
+  c->alpha = alpha;
   const int64_t n = c->nvec;
-  // a1: projections and boundary data at t + dt
+  // a1: projections and boundary data
   {
     Timed tm(c, LDG_K_PROJECT, 2.0 * 8.0 * (c->R + c->N) * c->K,
              2.0 * 2.0 * c->R * c->N * (double)c->K);
@@ -1299,14 +1311,7 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   // a4: preconditioner
   TRY(ldg_bj_setup(c, tau));
   // right-hand side and its full-system norm
-  // the history the step starts from: C^n, or (4 C^n - C^{n-1}) / 3 for BDF2
-  const double* Chist = c->C;
-  if (bdf2) {
-    launch_axpby(VT_F64, n, 4.0 / 3.0, c->C, 0.0, c->Cstar, c->st);
-    launch_axpby(VT_F64, n, -1.0 / 3.0, c->Cprev, 1.0, c->Cstar, c->st);
-    Chist = c->Cstar;
-  }
-  launch_rhs(c->geo, c->N, Chist, c->KDN, c->F, tau, c->b3, c->st);
+  launch_rhs(c->geo, c->N, alpha != 0.0 ? Chist : nullptr, c->KDN, c->F, tau, c->b3, c->st);
   double nb3 = 0.0, nj1 = 0.0, nj2 = 0.0;
   TRY(norm2(c, level64(c), c->b3, &nb3));
   TRY(norm2(c, level64(c), c->J1, &nj1));
@@ -1315,7 +1320,7 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
   // the inner solves of the mixed modes: blocks contracted at FP32 or BF16 on
   // the matrix cores, FP32 copy of the block-Jacobi inverses
   if (c->opt.precision != LDG_FP64) TRY(assemble_lowp(c));
-  // a6, a7: Krylov solve (with FP64 refinement) starting from C^n
+  // a6, a7: Krylov solve (with FP64 refinement)
   bool use_cg = c->opt.krylov == LDG_KRYLOV_CG;
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
   // the factored learned preconditioner of this system (SPD case only)
@@ -1325,7 +1330,10 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
     TRY(fac_omega(c));
     c->fac_on = true;
   }
-  HIPCHK(c, hipMemcpyAsync(c->X, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  if (X0)
+    HIPCHK(c, hipMemcpyAsync(c->X, X0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  else
+    HIPCHK(c, hipMemsetAsync(c->X, 0, n * sizeof(double), c->st));
   c->col_taken = 0;
   ldg_status s = solve_step(c, tau, bnorm > 0.0 ? bnorm : 1.0, use_cg, info);
   info->t = c->t;
@@ -1334,15 +1342,66 @@ ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double
     return s;
   }
   if (c->col_n > 0) TRY(finish_collect(c, tau));
-  // a10: accept; Z from the last residual evaluation of X; C^n becomes the history
-  HIPCHK(c, hipMemcpyAsync(c->Cprev, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-  c->have_prev = true;
-  c->dt_prev = dt;
+  return LDG_OK;
+}
+
+// accept X as the state; Z from the last residual evaluation of X
+ldg_status accept_solution(ldg_ctx* c) {
+  const int64_t n = c->nvec;
   HIPCHK(c, hipMemcpyAsync(c->C, c->X, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->Z1, c->tZ1, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->Z2, c->tZ2, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  return LDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ldg_status ldg_step_sampled(ldg_ctx* c, double dt, const double* d, const double* f,
+                            const double* cD, const double* gN, ldg_step_info* info) {
+  if (!c || !d || !f || !info || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  std::memset(info, 0, sizeof(*info));
+  TRY(hist_alloc(c));
+  // BDF2 needs the previous state at the same step size; else implicit Euler
+  const bool bdf2 = c->tscheme == LDG_TIME_BDF2 && c->have_prev &&
+                    std::fabs(dt - c->dt_prev) <= 1e-12 * dt;
+  const double tau = bdf2 ? 2.0 * dt / 3.0 : dt;
+  info->bdf_order = bdf2 ? 2 : 1;
+  const int64_t n = c->nvec;
+  // the history the step starts from: C^n, or (4 C^n - C^{n-1}) / 3 for BDF2
+  const double* Chist = c->C;
+  if (bdf2) {
+    launch_axpby(VT_F64, n, 4.0 / 3.0, c->C, 0.0, c->Cstar, c->st);
+    launch_axpby(VT_F64, n, -1.0 / 3.0, c->Cprev, 1.0, c->Cstar, c->st);
+    Chist = c->Cstar;
+  }
+  // the Krylov solve starts from C^n
+  TRY(solve_sampled(c, 1.0, tau, Chist, c->C, d, f, cD, gN, info));
+  // a10: accept; C^n becomes the history
+  HIPCHK(c, hipMemcpyAsync(c->Cprev, c->C, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->have_prev = true;
+  c->dt_prev = dt;
+  TRY(accept_solution(c));
   c->t += dt;
   info->t = c->t;
+  TRY(check_launch(c));
+  return sync(c);
+}
+
+ldg_status ldg_solve_stationary_sampled(ldg_ctx* c, const double* d, const double* f,
+                                        const double* cD, const double* gN,
+                                        ldg_step_info* info) {
+  if (!c || !d || !f || !info) return fail(c, LDG_EINVAL, "bad arguments");
+  std::memset(info, 0, sizeof(*info));
+  // without a Dirichlet edge the stationary operator has the constants in its kernel
+  if (3 * c->K - c->n_nd == 0)
+    return fail(c, LDG_EINVAL, "stationary solve needs at least one Dirichlet edge");
+  TRY(solve_sampled(c, 0.0, 1.0, nullptr, nullptr, d, f, cD, gN, info));
+  TRY(accept_solution(c));
+  // the stationary state has no previous step: a following BDF2 step starts with Euler
+  c->have_prev = false;
+  info->bdf_order = 0;
   TRY(check_launch(c));
   return sync(c);
 }

@@ -38,8 +38,9 @@ void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const vo
 // export stored blocks of any precision as FP64 [K][ns][N][N]
 void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src, double* dst,
                               hipStream_t st);
-void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
-                     double eta, double* bj, int* status, hipStream_t st);
+// alpha scales the mass term (1 for a time step, 0 for the stationary operator)
+void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double alpha,
+                     double tau, double eta, double* bj, int* status, hipStream_t st);
 void launch_to_tiled(int64_t K, int64_t Kpad, int N, const double* src, double* dst,
                      hipStream_t st);
 void launch_from_tiled(int64_t K, int N, const double* src, double* dst, hipStream_t st);
@@ -171,7 +172,7 @@ void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, voi
 void launch_axpy_into64(int vt, int64_t n, double a, const void* x, double* y, hipStream_t st);
 // result[0] = sum_k D_k0^2, result[1] = sum_k sum_{i>0} D_ki^2
 void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st);
-// b3 = 2|T| C + tau (KDN + 2|T| F) in the tiled layout
+// b3 = 2|T| C + tau (KDN + 2|T| F) in the tiled layout; C = nullptr drops the history term
 void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,
                 double tau, double* b3, hipStream_t st);
 // out = s * area2 * (Za - Zb) per element (full-operator rows 1, 2)

@@ -126,15 +126,15 @@ __global__ void __launch_bounds__(256) k_boundary(Geo g, int64_t nbe,
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi setup: the diagonal block of the eliminated operator,
-//   P_k = 2|T_k| I + tau [ eta S'_kk - (1/2|T_k|) sum_m B^m_kk A^m_kk
+//   P_k = alpha 2|T_k| I + tau [ eta S'_kk - (1/2|T_k|) sum_m B^m_kk A^m_kk
 //                          + sum_{n interior} |E_kn| / (2 * 2|T_k+|) U_kn S_hat_off(:,:,n+,n) ],
 // then its inverse by Gauss-Jordan elimination.  Sixteen lanes per triangle,
 // lane i owns row i; pivot rows travel by lane shuffles.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restrict__ refs,
-                                                  const double* __restrict__ blocks, double tau,
-                                                  double eta, double* __restrict__ bj,
+                                                  const double* __restrict__ blocks, double alpha,
+                                                  double tau, double eta, double* __restrict__ bj,
                                                   int* __restrict__ status) {
   constexpr int NN = N * N;
   constexpr int NP = npairs(N);
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
       }
     }
 #pragma unroll
-    for (int c = 0; c < N; ++c) a[c] = (c == i ? area2 : 0.0) + tau * acc[c];
+    for (int c = 0; c < N; ++c) a[c] = (c == i ? alpha * area2 : 0.0) + tau * acc[c];
   }
   // Gauss-Jordan without pivoting within the 16-lane group
   bool bad = false;
@@ -420,10 +420,10 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
 
 
 
-void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double tau,
-                     double eta, double* bj, int* status, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_bj_setup<NT><<<nblk(g.Kpad * 16, 256), 256, 0, st>>>(g, refs, blocks, tau,
-                                                                          eta, bj, status)));
+void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double alpha,
+                     double tau, double eta, double* bj, int* status, hipStream_t st) {
+  LDG_SWITCH_N(N, (k_bj_setup<NT><<<nblk(g.Kpad * 16, 256), 256, 0, st>>>(
+                      g, refs, blocks, alpha, tau, eta, bj, status)));
 }
 
 

@@ -195,7 +195,7 @@ __global__ void k_rhs(Geo g, int N, const double* __restrict__ C, const double* 
   if (t >= g.Kpad * N) return;
   const int64_t k = (t / (64 * N)) * 64 + (t % 64);
   const double a2 = k < g.K ? g.area2[k] : 0.0;
-  b3[t] = a2 * C[t] + tau * (KDN[t] + a2 * F[t]);
+  b3[t] = (C ? a2 * C[t] : 0.0) + tau * (KDN[t] + a2 * F[t]);
 }
 
 __global__ void k_zrows(Geo g, int N, const double* __restrict__ Za, const double* __restrict__ Zb,

@@ -63,6 +63,7 @@ _SIGS = {
     "ldg_set_state": [_P, _P, C.c_int, C.c_double],
     "ldg_set_initial_samples": [_P, _P, C.c_double],
     "ldg_step_sampled": [_P, C.c_double, _P, _P, _P, _P, C.POINTER(StepInfo)],
+    "ldg_solve_stationary_sampled": [_P, _P, _P, _P, _P, C.POINTER(StepInfo)],
     "ldg_get_solution": [_P, _P, _P, _P, C.c_int],
     "ldg_assemble": [_P, _P],
     "ldg_get_blocks": [_P, _P],
@@ -218,6 +219,15 @@ class Solver:
         info = StepInfo()
         code = self.lib.ldg_step_sampled(self.h, float(dt), _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
                                          C.byref(info))
+        self._check(code)
+        return info.as_dict()
+
+    def solve_stationary_sampled(self, d, f, cD=None, gN=None):
+        """A Y = V from sampled data (no mass term, no history); the solution
+        becomes the state."""
+        info = StepInfo()
+        code = self.lib.ldg_solve_stationary_sampled(self.h, _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
+                                                     C.byref(info))
         self._check(code)
         return info.as_dict()
 
