@@ -10,6 +10,11 @@ system, recovery of Z.  Metric: DOF*steps/s with DOF = 3KN (C, Z1, Z2).
                   [--precision fp64|fp32|bf16] [--precond bj|learned] [--weights F]
                   [--no-baseline] [--no-cpu-baseline]
 
+Two further workloads are not time-step benchmarks of the five sizes: the
+stationary verification problem of Table 2 (`--config table2-p4-96`, one
+"step" is one solve of A Y = V) and the problem of the paper's main script
+(`--config main-p2-8`, h = 1/8, p = 2, steps of pi/20).
+
 The default run times the mixed-precision (BF16 contractions, FP64
 refinement) solver with the learned factored preconditioner on the combined
 workload, then the plain FP64 block-Jacobi solver on the same workload for
@@ -27,9 +32,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from inputs.fields import (LOGNORMAL, LOGNORMAL_T, SMOOTH1, SMOOTH2, Workload,  # noqa: E402
-                           lognormal_blocks, triangle_values)
-from inputs.meshes import square_mesh  # noqa: E402
+from inputs.fields import (LOGNORMAL, LOGNORMAL_T, MAIN, SMOOTH1, SMOOTH2, TABLE2,  # noqa: E402
+                           Workload, lognormal_blocks, triangle_values)
+from inputs.meshes import NORTH, SOUTH, square_mesh  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
@@ -42,6 +47,10 @@ CONFIGS = {
                            dt=1e-4),
     "combined-p4-1024": dict(n=1024, p=4, jitter=1005, kind=LOGNORMAL_T, sigma=1.0,
                              field_seed=5000, dt=1e-4),
+    # stationary solves of the Table 2 problem (h = 1/96), and the main script's problem
+    "table2-p4-96": dict(n=96, p=4, jitter=None, kind=TABLE2, neumann=(SOUTH, NORTH),
+                         stationary=True, dt=0.0, restart=150, max_iters=200000),
+    "main-p2-8": dict(n=8, p=2, jitter=None, kind=MAIN, neumann=(SOUTH, NORTH), dt=np.pi / 20),
 }
 DEFAULT = "combined-p4-1024"
 # trained weights of the factored preconditioner per order (learned.py)
@@ -54,7 +63,8 @@ def log(*a):
 
 
 def make_inputs(cfg):
-    coordV, V0T, kind = square_mesh(cfg["n"], seed=cfg["jitter"])
+    coordV, V0T, kind = square_mesh(cfg["n"], seed=cfg["jitter"],
+                                    neumann_sides=cfg.get("neumann", ()))
     dT = None
     if cfg["kind"] in (LOGNORMAL, LOGNORMAL_T):
         blocks = lognormal_blocks(cfg["n"], cfg["field_seed"], cfg["sigma"], block=8)
@@ -82,7 +92,7 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
     """Warmup steps, then args.steps timed steps of one solver configuration."""
     t0 = time.perf_counter()
     s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
-               max_iters=20000, precision=prec, inner_rtol=args.inner_rtol,
+               max_iters=cfg.get("max_iters", 20000), precision=prec, inner_rtol=args.inner_rtol,
                precond=1 if learned else 0)
     if learned:
         s.gnn_set_mode("factor")
@@ -96,6 +106,9 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
     dt = cfg["dt"]
 
     def one_step():
+        if cfg.get("stationary"):
+            smp = s.sample_workload(gk, 0.0, dT=dT)
+            return s.solve_stationary_sampled(smp["d"], smp["f"], smp["cD"], smp["gN"])
         state["t"] += dt
         smp = s.sample_workload(gk, state["t"], dT=dT)
         return s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
@@ -159,7 +172,7 @@ def cpu_baseline(cfg, seconds_hint=True):
 
     from oracle.ldg import Problem
     n = 16
-    coordV, V0T, kind = square_mesh(n, seed=cfg["jitter"])
+    coordV, V0T, kind = square_mesh(n, seed=cfg["jitter"], neumann_sides=cfg.get("neumann", ()))
     if cfg["kind"] in (LOGNORMAL, LOGNORMAL_T):
         w = Workload(cfg["kind"], n_cells=n,
                      blocks=lognormal_blocks(n, cfg["field_seed"], cfg["sigma"], block=8), block=8)
@@ -168,17 +181,23 @@ def cpu_baseline(cfg, seconds_hint=True):
     steps = 2
     with threadpool_limits(1):
         pr = Problem(coordV, V0T, kind, cfg["p"])
-        C = pr.initial(w)
-        t = 0.0
         t0 = time.perf_counter()
-        for _ in range(steps):
-            t += cfg["dt"]
-            C, _, _, _ = pr.step(C, t, cfg["dt"], w)
+        if cfg.get("stationary"):
+            for _ in range(steps):
+                pr.solve_stationary(w)
+        else:
+            C = pr.initial(w)
+            t = 0.0
+            for _ in range(steps):
+                t += cfg["dt"]
+                C, _, _, _ = pr.step(C, t, cfg["dt"], w)
         el = time.perf_counter() - t0
     dof = 3 * pr.grid.numT * pr.N
-    return {"value": dof * steps / el, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%dx%d-cell mesh of the same family (K=%d, p=%d, DOF=%d), %d steps, "
-                      "sparse direct solve, %.1f s" % (n, n, pr.grid.numT, cfg["p"], dof, steps, el)}
+    what = "solves" if cfg.get("stationary") else "steps"
+    return {"value": dof * steps / el, "unit": "DOF*%s/s" % what, "cores": 1, "kind": "oracle",
+            "sample": "%dx%d-cell mesh of the same family (K=%d, p=%d, DOF=%d), %d %s, "
+                      "sparse direct solve, %.1f s" % (n, n, pr.grid.numT, cfg["p"], dof, steps,
+                                                       what, el)}
 
 
 def main():
@@ -187,12 +206,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default=DEFAULT, choices=sorted(CONFIGS))
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="GMRES restart length (default 30; 150 for the stationary workload)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16"],
                     help="inner-solve precision (fp32/bf16: mixed with FP64 refinement)")
-    ap.add_argument("--precond", default="learned", choices=["bj", "learned"],
-                    help="block-Jacobi, or the learned factored preconditioner")
+    ap.add_argument("--precond", default=None, choices=["bj", "learned"],
+                    help="block-Jacobi, or the learned factored preconditioner (default: learned "
+                         "where trained weights exist for the order and the workload steps in "
+                         "time, else block-Jacobi)")
     ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
     ap.add_argument("--fac-storage", default="fp8", choices=["f32", "bf16", "fp8"],
                     help="storage of the learned preconditioner's factor blocks")
@@ -215,9 +237,14 @@ def main():
 
     from paper_1408_3877_amd import Solver
     cfg = CONFIGS[args.config]
+    if args.restart is None:
+        args.restart = cfg.get("restart", 30)
     log("[bench] config %s: building inputs" % args.config)
     coordV, V0T, kind, dT = make_inputs(cfg)
     torch.cuda.set_device(0)
+    if args.precond is None:
+        args.precond = ("learned" if cfg["p"] in WEIGHTS and not cfg.get("stationary") and
+                        cfg["kind"] in (LOGNORMAL, LOGNORMAL_T) else "bj")
     learned = args.precond == "learned"
     weights = None
     if learned:
@@ -256,10 +283,13 @@ def main():
         "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
         "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
         "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol)
+    stationary = bool(cfg.get("stationary"))
     res = {
-        "metric": "DOF·steps/s (p=4, 2M tris) to 1e-8 rel res: plain FP64 vs mixed+learned precond",
+        "metric": ("DOF·solves/s of the stationary Table 2 problem to 1e-8 rel res" if stationary
+                   else "DOF·steps/s (p=4, 2M tris) to 1e-8 rel res: plain FP64 vs mixed+learned "
+                        "precond"),
         "value": value,
-        "unit": "DOF*steps/s",
+        "unit": "DOF*solves/s" if stationary else "DOF*steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -270,7 +300,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
-                   "dt": dt_of(cfg), "rtol": args.rtol, "time_scheme": args.time_scheme,
+                   "dt": dt_of(cfg), "rtol": args.rtol,
+                   "time_scheme": "stationary" if stationary else args.time_scheme,
                    "solver": solver_desc,
                    "weights": os.path.relpath(args.weights or WEIGHTS.get(cfg["p"]), ROOT)
                    if learned else None,

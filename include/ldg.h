@@ -80,7 +80,7 @@ typedef struct {
   int precond;        /* ldg_precond, default LDG_PC_BLOCK_JACOBI */
   double rtol;        /* relative residual of the full system, default 1e-8; FP64 rounding
                          bounds what is reachable near 1e-16 ||A|| ||Y|| / ||V|| */
-  int restart;        /* GMRES restart length m, default 30 */
+  int restart;        /* GMRES restart length m in 1..200, default 30 */
   int max_iters;      /* total Krylov iterations per step, default 5000 */
   void* stream;       /* hipStream_t for all device work */
   int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
@@ -307,6 +307,10 @@ ldg_status ldg_get_bj(ldg_ctx* ctx, double* out);
  *   c = cos(7x) cos(7y) exp(-t) (kind 5: without exp(-t)),
  *   f = dt c - div(d grad c) (inside each triangle for kinds 3, 4),
  *   c_D = c, g_N = -grad c . nu, c0 = c at t = 0.
+ *   kind   6: the problem of the paper's main script (Sec. 4): d = 1.01 on the
+ *             open square (1/4, 3/4)^2 and 0.01 elsewhere, f = t/10,
+ *             c_D = sin(2 pi y + t), g_N = y, c0 = sin(x) cos(y) (no
+ *             closed-form solution; its Neumann edges lie at y = 0 and 1).
  *   dT: device, K values (kinds 3, 4 only, else NULL).  Any output may be NULL;
  *   layouts as in ldg_quad_points.
  */

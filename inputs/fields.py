@@ -9,10 +9,15 @@ Dirichlet data c_D = c and Neumann data g_N = -grad c . nu.  The
 manufactured solution of the benchmark configurations is
 c = cos(7x) cos(7y) exp(-t); f is derived from it exactly where d is smooth,
 and inside each constant block where d is piecewise constant.
+
+MAIN is the problem of the paper's main script (the template of Sec. 4): a
+discontinuous coefficient (1.01 on the open square (1/4, 3/4)^2, 0.01
+outside), f = 0.1 t, c_D = sin(2 pi y + t), g_N = y, c0 = sin(x) cos(y), with
+Neumann edges at y = 0 and y = 1; it has no closed-form solution.
 """
 import numpy as np
 
-SMOOTH1, SMOOTH2, LOGNORMAL, LOGNORMAL_T, TABLE2 = 1, 2, 3, 4, 5
+SMOOTH1, SMOOTH2, LOGNORMAL, LOGNORMAL_T, TABLE2, MAIN = 1, 2, 3, 4, 5, 6
 
 
 def lognormal_blocks(n_cells, seed, sigma, block=8, contrast=1e3):
@@ -58,6 +63,8 @@ class Workload:
 
     # --- exact solution and its derivatives -------------------------------
     def c(self, t, x, y):
+        if self.kind == MAIN:
+            raise ValueError("the main-script problem has no closed-form solution")
         c = np.cos(7 * x) * np.cos(7 * y)
         return c if self.stationary else c * np.exp(-t)
 
@@ -84,6 +91,9 @@ class Workload:
             return self._block_value(x, y) * (1 + 0.1 * np.sin(t))
         if self.kind == TABLE2:
             return np.exp(x + y)
+        if self.kind == MAIN:
+            inside = (x < 0.75) & (x > 0.25) & (y < 0.75) & (y > 0.25)
+            return inside.astype(np.float64) + 0.01
         raise ValueError(self.kind)
 
     def grad_d(self, t, x, y):
@@ -105,6 +115,8 @@ class Workload:
 
     # --- derived data -------------------------------------------------------
     def f(self, t, x, y):
+        if self.kind == MAIN:
+            return 0.1 * t * np.ones_like(np.asarray(x, dtype=np.float64))
         c = self.c(t, x, y)
         dtc = 0.0 * c if self.stationary else -c
         lap = -98.0 * c
@@ -113,11 +125,17 @@ class Workload:
         return dtc - (dx * gx + dy * gy) - self.d(t, x, y) * lap
 
     def c_D(self, t, x, y):
+        if self.kind == MAIN:
+            return np.sin(2 * np.pi * y + t)
         return self.c(t, x, y)
 
     def g_N(self, t, x, y, nu1, nu2):
+        if self.kind == MAIN:
+            return np.asarray(y, dtype=np.float64) + 0.0 * nu1
         gx, gy = self.grad_c(t, x, y)
         return -(gx * nu1 + gy * nu2)
 
     def c0(self, x, y):
+        if self.kind == MAIN:
+            return np.sin(x) * np.cos(y)
         return self.c(0.0, x, y)

@@ -1063,14 +1063,16 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   c->red.nblk = c->red2.nblk = krylov_nblk(nv);
   c->red.maxv = c->red2.maxv = c->mmax + 1;
   {
-    size_t np = (size_t)(c->mmax + 2) * c->red.nblk;
+    const size_t nb = std::max<size_t>(c->red.nblk, gs_nblk(nv));
+    size_t np = (size_t)(c->mmax + 2) * nb;
     const size_t nbj = (size_t)(Kp / 256 + 1);
     if (np < nbj) np = nbj;
     if (np < 2048) np = 2048;
     TRY(dalloc(c, &c->red.partials, np));
   }
   TRY(dalloc(c, &c->red.result, c->mmax + 2));
-  TRY(dalloc(c, &c->red2.partials, (size_t)c->red2.nblk + 2048));
+  TRY(dalloc(c, &c->red2.partials,
+             std::max<size_t>(c->red2.nblk, gs_nblk(nv)) + 2048));
   TRY(dalloc(c, &c->red2.result, 1));
   HIPCHK(c, hipHostMalloc((void**)&c->host_buf, (2 * c->mmax + 8) * sizeof(double)));
   TRY(sync(c));
@@ -1750,7 +1752,7 @@ ldg_status ldg_get_kernel_stat(ldg_ctx* c, int kernel, ldg_kernel_stat* out) {
 
 ldg_status ldg_sample_workload(ldg_ctx* c, int kind, double t, const double* dT, double* d,
                                double* f, double* cD, double* gN, double* c0) {
-  if (!c || kind < 1 || kind > 5) return fail(c, LDG_EINVAL, "bad workload kind");
+  if (!c || kind < 1 || kind > 6) return fail(c, LDG_EINVAL, "bad workload kind");
   if ((kind == 3 || kind == 4) && !dT) return fail(c, LDG_EINVAL, "block field needs dT");
   if (d || f || c0)
     launch_sample_vol(c->geo, c->R, c->qvol, kind, t, dT, d, f, c0, nullptr, nullptr, c->st);

@@ -150,6 +150,8 @@ struct Reducer {
   int maxv = 0;
 };
 int krylov_nblk(int64_t n);
+// blocks of the Gram-Schmidt kernels (launch_dots, launch_update) for vectors of length n
+int gs_nblk(int64_t n);
 void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st);
 // result[j] = <V_j, w> for j < nv, result[nv] = <w, w>
 void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,

@@ -303,9 +303,19 @@ __global__ void k_export_blocks(int64_t K, int N, int ns, const double* __restri
 namespace {
 struct Fields { double d, f, c; double gcx, gcy; };
 
-// dT: the coefficient value of the triangle (block-field kinds 3, 4)
+// dT: the coefficient value of the triangle (block-field kinds 3, 4).  Kind 6 is
+// the problem of the paper's main script (no closed-form solution; c holds its
+// initial value sin(x) cos(y), the boundary data are set by the edge sampler).
 __device__ Fields eval_fields(int kind, double t, double x, double y, double dT) {
   Fields F;
+  if (kind == 6) {
+    const bool inside = x < 0.75 && x > 0.25 && y < 0.75 && y > 0.25;
+    F.d = (inside ? 1.0 : 0.0) + 0.01;
+    F.f = 0.1 * t;
+    F.c = sin(x) * cos(y);
+    F.gcx = F.gcy = 0.0;
+    return F;
+  }
   const double e = kind == 5 ? 1.0 : exp(-t);
   const double cx = cos(7.0 * x), cy = cos(7.0 * y), sx = sin(7.0 * x), sy = sin(7.0 * y);
   F.c = cx * cy * e;
@@ -380,6 +390,11 @@ __global__ void k_sample_bnd(Geo g, int R1, const double* __restrict__ s, int64_
     else { xo[idx] = x; yo[idx] = y; }
   }
   if (kind <= 0 || !(cD || gN)) return;
+  if (kind == 6) {   // c_D = sin(2 pi y + t), g_N = y
+    if (cD) cD[idx] = sin(2.0 * 3.14159265358979323846 * y + t);
+    if (gN) gN[idx] = y;
+    return;
+  }
   const Fields F = eval_fields(kind, t, x, y, 1.0);
   if (cD) cD[idx] = F.c;
   if (gN) gN[idx] = -(F.gcx * nu1 + F.gcy * nu2);

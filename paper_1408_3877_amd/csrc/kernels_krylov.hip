@@ -37,47 +37,84 @@ inline unsigned nblk1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 int krylov_nblk(int64_t n) { return (int)((n + CHUNK - 1) / CHUNK); }
 
-// partials[j][b] = <V_j, w> on block b (j < nv), partials[nv][b] = <w, w>
-template <class T>
+// Gram-Schmidt kernels (many basis vectors against one vector).  IT items per
+// thread, chosen per vector length so that a launch has at least GS_MIN_BLOCKS
+// blocks: short vectors (small meshes, long GMRES cycles) would otherwise leave
+// most of the chip idle.  gs_items / gs_nblk fix the partition for a length,
+// so the reductions stay deterministic.
+constexpr int GS_MIN_BLOCKS = 2048;
+constexpr int GS_JB = 8;   // basis vectors per block of k_dots
+
+int gs_items(int64_t n) {
+  for (int it = KITEMS; it > 1; it >>= 1)
+    if (n / ((int64_t)KB * it) >= GS_MIN_BLOCKS) return it;
+  return 1;
+}
+
+// partials[j][b] = <V_j, w> on block b (j < nv), partials[nv][b] = <w, w>.
+// Grid (nblk, ceil(nv / GS_JB)): block (b, y) takes the vectors
+// [y GS_JB, min(nv, (y + 1) GS_JB)); the last row also takes <w, w>.
+template <class T, int IT>
 __global__ void __launch_bounds__(KB) k_dots(int64_t n, int nv, const T* __restrict__ V,
                                              int64_t ldv, const T* __restrict__ w,
                                              double* __restrict__ partials, int nblk) {
-  __shared__ double red[KB / 64];
-  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
-  double wl[KITEMS];
+  __shared__ double red[GS_JB + 1][KB / 64];
+  const int64_t base = (int64_t)blockIdx.x * (KB * IT) + threadIdx.x;
+  double wl[IT];
 #pragma unroll
-  for (int t = 0; t < KITEMS; ++t) {
+  for (int t = 0; t < IT; ++t) {
     const int64_t i = base + (int64_t)t * KB;
     wl[t] = i < n ? (double)w[i] : 0.0;
   }
-  for (int j = 0; j < nv; ++j) {
-    const T* Vj = V + j * ldv;
+  const int j0 = blockIdx.y * GS_JB;
+  const bool last = blockIdx.y == gridDim.y - 1;
+  double acc[GS_JB + 1];
+#pragma unroll
+  for (int jj = 0; jj < GS_JB; ++jj) {
     double s = 0.0;
+    const int j = j0 + jj;
+    if (j < nv) {
+      const T* Vj = V + j * ldv;
 #pragma unroll
-    for (int t = 0; t < KITEMS; ++t) {
-      const int64_t i = base + (int64_t)t * KB;
-      if (i < n) s += (double)Vj[i] * wl[t];
+      for (int t = 0; t < IT; ++t) {
+        const int64_t i = base + (int64_t)t * KB;
+        if (i < n) s += (double)Vj[i] * wl[t];
+      }
     }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) partials[(int64_t)j * nblk + blockIdx.x] = s;
+    acc[jj] = s;
   }
-  double s = 0.0;
+  double ww = 0.0;
 #pragma unroll
-  for (int t = 0; t < KITEMS; ++t) s += wl[t] * wl[t];
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) partials[(int64_t)nv * nblk + blockIdx.x] = s;
+  for (int t = 0; t < IT; ++t) ww += wl[t] * wl[t];
+  acc[GS_JB] = ww;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int jj = 0; jj <= GS_JB; ++jj) {
+    const double v = wave_sum(acc[jj]);
+    if (lane == 0) red[jj][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x <= GS_JB) {
+    const int jj = threadIdx.x;
+    const int j = jj < GS_JB ? j0 + jj : nv;
+    if ((jj < GS_JB && j < nv) || (jj == GS_JB && last)) {
+      double s = 0.0;
+      for (int q = 0; q < KB / 64; ++q) s += red[jj][q];
+      partials[(int64_t)j * nblk + blockIdx.x] = s;
+    }
+  }
 }
 
 // w -= sum_j h[j] V_j (FP64 arithmetic), partial sums of the new <w, w>
-template <class T>
+template <class T, int IT>
 __global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const T* __restrict__ V,
                                                int64_t ldv, const double* __restrict__ h,
                                                T* __restrict__ w, double* __restrict__ partials) {
   __shared__ double red[KB / 64];
-  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
-  double wl[KITEMS];
+  const int64_t base = (int64_t)blockIdx.x * (KB * IT) + threadIdx.x;
+  double wl[IT];
 #pragma unroll
-  for (int t = 0; t < KITEMS; ++t) {
+  for (int t = 0; t < IT; ++t) {
     const int64_t i = base + (int64_t)t * KB;
     wl[t] = i < n ? (double)w[i] : 0.0;
   }
@@ -85,14 +122,14 @@ __global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const T* __res
     const T* Vj = V + j * ldv;
     const double hj = h[j];
 #pragma unroll
-    for (int t = 0; t < KITEMS; ++t) {
+    for (int t = 0; t < IT; ++t) {
       const int64_t i = base + (int64_t)t * KB;
       if (i < n) wl[t] -= hj * (double)Vj[i];
     }
   }
   double s = 0.0;
 #pragma unroll
-  for (int t = 0; t < KITEMS; ++t) {
+  for (int t = 0; t < IT; ++t) {
     const int64_t i = base + (int64_t)t * KB;
     if (i < n) {
       const T v = (T)wl[t];
@@ -218,17 +255,33 @@ void reduce_partials(int nblk, const double* partials, double* result, hipStream
   k_reduce<<<1, KB, 0, st>>>(nblk, partials, result);
 }
 
+int gs_nblk(int64_t n) {
+  const int64_t chunk = (int64_t)KB * gs_items(n);
+  return (int)((n + chunk - 1) / chunk);
+}
+
+#define LDG_GS_IT(n, CALL)                                 \
+  switch (gs_items(n)) {                                   \
+    case 8: { constexpr int IT = 8; CALL; } break;         \
+    case 4: { constexpr int IT = 4; CALL; } break;         \
+    case 2: { constexpr int IT = 2; CALL; } break;         \
+    default: { constexpr int IT = 1; CALL; } break;        \
+  }
+
 void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
                  const void* w, hipStream_t st) {
-  const int nb = krylov_nblk(n);
-  LDG_VT(vt, (k_dots<T><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, (const T*)w, r.partials, nb)));
+  const int nb = gs_nblk(n);
+  const dim3 grid(nb, nv > 0 ? (nv + GS_JB - 1) / GS_JB : 1);   // nv = 0: <w, w> only
+  LDG_VT(vt, LDG_GS_IT(n, (k_dots<T, IT><<<grid, KB, 0, st>>>(n, nv, (const T*)V, ldv,
+                                                                (const T*)w, r.partials, nb))));
   k_reduce<<<nv + 1, KB, 0, st>>>(nb, r.partials, r.result);
 }
 
 void launch_update(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
                    const double* h, void* w, hipStream_t st) {
-  const int nb = krylov_nblk(n);
-  LDG_VT(vt, (k_update<T><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, h, (T*)w, r.partials)));
+  const int nb = gs_nblk(n);
+  LDG_VT(vt, LDG_GS_IT(n, (k_update<T, IT><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, h, (T*)w,
+                                                                r.partials))));
   k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
 }
 

@@ -1,0 +1,112 @@
+"""The problem of the paper's main script on the GPU against the oracle.
+
+Discontinuous coefficient (1.01 on (1/4, 3/4)^2, 0.01 elsewhere), f = t/10,
+c_D = sin(2 pi y + t), g_N = y on the south and north sides, c0 = sin(x) cos(y),
+p = 2, h = 1/8, 20 implicit Euler steps to t = pi: every step's C, Z1, Z2
+match the oracle's sparse direct solve.  On the unjittered mesh the square's
+sides are mesh lines, so d is constant on every triangle and the steps run CG;
+on jittered meshes triangles straddle the jump and, where the projection
+sees it, the steps run GMRES.
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import MAIN, Workload
+from inputs.meshes import NORTH, SOUTH, square_mesh
+from oracle.ldg import Problem
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(cV, V0T, kind, p, **kw):
+    from paper_1408_3877_amd import Solver
+    kw.setdefault("restart", 60)
+    kw.setdefault("max_iters", 50000)
+    return Solver(cV, V0T, kind, p, rtol=1e-13, **kw)
+
+
+def test_sampled_data_match_the_workload():
+    cV, V0T, kind = square_mesh(8, seed=401, neumann_sides=(SOUTH, NORTH))
+    s = _solver(cV, V0T, kind, 2)
+    w = Workload(MAIN)
+    t = 0.7
+    smp = s.sample_workload(MAIN, t, want=("d", "f", "cD", "gN", "c0"))
+    x, y = (to_np(v) for v in s.quad_points(0))
+    assert np.array_equal(to_np(smp["d"]), w.d(t, x, y))
+    assert np.allclose(to_np(smp["f"]), w.f(t, x, y), rtol=0, atol=1e-15)
+    assert np.allclose(to_np(smp["c0"]), w.c0(x, y), rtol=0, atol=1e-15)
+    xb, yb = (to_np(v) for v in s.quad_points(1))
+    n1, n2 = (to_np(v) for v in s.quad_points(2))
+    assert np.allclose(to_np(smp["cD"]), w.c_D(t, xb, yb), rtol=0, atol=1e-14)
+    assert np.array_equal(to_np(smp["gN"]), w.g_N(t, xb, yb, n1, n2))
+    pr = Problem(cV, V0T, kind, 2)
+    D = to_np(s.project(smp["d"]))
+    assert rel_l2(pr.grid.areaT, D, pr.data(w, t)["D"]) < 1e-13
+
+
+def _run(n, seed, p, nsteps, dt, **kw):
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(SOUTH, NORTH))
+    w = Workload(MAIN)
+    pr = Problem(cV, V0T, kind, p)
+    s = _solver(cV, V0T, kind, p, **kw)
+    s.set_initial_samples(s.sample_workload(MAIN, 0.0, want=("c0",))["c0"], 0.0)
+    C = pr.initial(w)
+    a = pr.grid.areaT
+    assert rel_l2(a, to_np(s.get_solution()[0]), C) < 1e-13
+    out = []
+    for i in range(1, nsteps + 1):
+        t = i * dt
+        smp = s.sample_workload(MAIN, t)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        C, Z1, Z2, _ = pr.step(C, t, dt, w)
+        Cg, Z1g, Z2g = (to_np(x) for x in s.get_solution())
+        errs = (rel_l2(a, Cg, C), rel_l2(a, Z1g, Z1), rel_l2(a, Z2g, Z2))
+        print("[main] n=%d p=%d step %d krylov=%d iters=%d err C %.2e Z %.2e %.2e"
+              % (n, p, i, info["krylov"], info["iters"], *errs), flush=True)
+        out.append((info, errs))
+    return out
+
+
+def test_main_script_run_matches_the_oracle():
+    # the script's parameters: h = 1/8, p = 2, 20 steps to t = pi
+    for info, errs in _run(8, None, 2, 20, np.pi / 20):
+        assert info["krylov"] == 2 and info["rel_residual"] <= 1e-13   # 2: CG
+        assert max(errs) < 1e-10
+
+
+# Where triangles cut the jump, the L2 projection of the coefficient
+# overshoots and undershoots (for p >= 2 it goes below zero) and the step's
+# operator has an indefinite symmetric part: restarted GMRES then needs a long
+# restart (CPU check, n = 9, p = 4: GMRES(60) stalls near 1e-2, GMRES(200)
+# converges in 4578 iterations)
+@pytest.mark.parametrize("n,seed,p,restart", [(12, 411, 0, 60), (12, 412, 1, 60), (9, 414, 4, 200)])
+def test_main_problem_on_jittered_meshes(n, seed, p, restart):
+    # CG where the projected coefficient happens to be constant on every
+    # triangle (the jump sampled at few points), GMRES elsewhere
+    for info, errs in _run(n, seed, p, 3, np.pi / 20, restart=restart):
+        assert info["krylov"] in (1, 2) and info["rel_residual"] <= 1e-13
+        assert max(errs) < 1e-10
+
+
+def test_main_problem_mixed_precision():
+    for info, errs in _run(12, 415, 2, 2, np.pi / 20, precision=2):
+        assert info["ir_steps"] >= 1 and info["rel_residual"] <= 1e-13
+        assert max(errs) < 1e-10
+
+
+def test_stalled_step_reports_no_convergence_and_keeps_the_state():
+    # n = 10, p = 3: GMRES(60) with block-Jacobi stalls near 1e-1 (CPU check);
+    # the step returns ENOCONV and leaves the state as it was
+    from paper_1408_3877_amd.ldg import LdgError
+    cV, V0T, kind = square_mesh(10, seed=413, neumann_sides=(SOUTH, NORTH))
+    s = _solver(cV, V0T, kind, 3, max_iters=3000)
+    s.set_initial_samples(s.sample_workload(MAIN, 0.0, want=("c0",))["c0"], 0.0)
+    C0 = to_np(s.get_solution()[0])
+    smp = s.sample_workload(MAIN, np.pi / 20)
+    with pytest.raises(LdgError) as e:
+        s.step_sampled(np.pi / 20, smp["d"], smp["f"], smp["cD"], smp["gN"])
+    assert e.value.code == -5
+    assert np.array_equal(to_np(s.get_solution()[0]), C0)
+    smp = s.sample_workload(MAIN, 0.0, want=("c0",))
+    assert np.array_equal(to_np(s.project(smp["c0"])), C0)
