@@ -47,7 +47,8 @@ typedef enum {
   LDG_ENOMEM = -3,    /* device allocation failed */
   LDG_EDEVICE = -4,   /* a HIP call failed */
   LDG_ENOCONV = -5,   /* the solver did not reach rtol; the state is not advanced */
-  LDG_EUNSUPPORTED = -6
+  LDG_EUNSUPPORTED = -6,
+  LDG_EIO = -7        /* a file could not be opened, read or written */
 } ldg_status;
 
 /*
@@ -434,6 +435,62 @@ ldg_status ldg_gnn_train_step(ldg_ctx* ctx, const float* rhat, const float* targ
 ldg_status ldg_gnn_collect(ldg_ctx* ctx, int nsnap, const int32_t* iters, float* rhat_out,
                            float* target_out);
 ldg_status ldg_gnn_collected(ldg_ctx* ctx, int* n);
+
+/* ---- Input and output -------------------------------------------------- */
+
+/*
+ * Read a triangulation from an ASCII MEDIT ".mesh" file, the format Gmsh
+ * writes and the paper's circle-domain generator reads (Sec. 4,
+ * domainCircle): sections Vertices (x y [z] ref, the count of coordinates
+ * set by a Dimension 2 / 3 keyword, default 3), Edges (v1 v2 ID: the boundary
+ * ID of a boundary edge) and Triangles (v1 v2 v3 ref), 1-based vertex
+ * numbers, "#" comments.  Two calls: with coordV, V0T and edge_id NULL it
+ * sets *numV and *K; then, with those values in *numV and *K, it fills
+ *   coordV   host numV x 2
+ *   V0T      host K x 3, 0-based, reordered counter-clockwise where needed
+ *   edge_id  host K x 3, per local edge n (opposite local vertex n): 0 for an
+ *            edge shared by two triangles, the listed ID (> 0) of a boundary
+ *            edge, -1 for a boundary edge the file lists no ID for.
+ * Errors: EIO (the file cannot be opened), EMESH (malformed file, a vertex
+ * number out of range, an edge in more than two triangles, a boundary ID
+ * <= 0), EINVAL (NULL pointers, sizes that differ from the file's).  No
+ * context: ldg_last_error(NULL) gives the text.
+ */
+ldg_status ldg_mesh_read_medit(const char* path, int64_t* numV, int64_t* K, double* coordV,
+                               int32_t* V0T, int32_t* edge_id);
+
+/*
+ * Edge kinds from boundary IDs (the paper's main script marks the edges with
+ * IDs 1 and 3 Neumann, all other boundary edges Dirichlet): ID 0 interior, an
+ * ID in neumann_ids[0..n_neumann) Neumann, any other positive ID Dirichlet;
+ * host arrays of K x 3.  A negative ID: EMESH.
+ */
+ldg_status ldg_edge_kinds_from_ids(int64_t K, const int32_t* edge_id, const int32_t* neumann_ids,
+                                   int n_neumann, int8_t* edge_kind);
+
+/*
+ * Values of a discrete function at the Lagrange points of every triangle
+ * (Sec. 3.8): nL = 1 (p = 0: the barycentre), 3 (p = 1: the vertices) or 6
+ * (p >= 2: the vertices, then the midpoints of the edges opposite vertices
+ * 1, 2, 3; for p > 2 these are point values of the order-p function, the
+ * output holding at most quadratics).  C: device K x N element-major, or NULL
+ * for the current state.  out: device K x nL element-major, or NULL to query
+ * *nL only.
+ */
+ldg_status ldg_lagrange(ldg_ctx* ctx, const double* C, double* out, int* nL);
+
+/*
+ * Write Lagrange values (host K x nL, as ldg_lagrange returns them) as an XML
+ * VTK unstructured-grid file (.vtu) for visualization (Sec. 3.8): every
+ * triangle carries its own points (the function is discontinuous); linear
+ * triangles (VTK type 5) for nL = 1 (the value at all three vertices) and
+ * nL = 3, quadratic triangles (type 22) for nL = 6; Float32 point data named
+ * `name` (no XML special characters).  binary = 0: ASCII with 9 significant
+ * digits; else base64 "binary" arrays (UInt32 byte-count header).  Errors:
+ * EINVAL (nL other than ldg_lagrange's), EIO.
+ */
+ldg_status ldg_write_vtu(ldg_ctx* ctx, const char* path, const char* name, const double* lagr,
+                         int nL, int binary);
 
 #ifdef __cplusplus
 }

@@ -120,3 +120,55 @@ def rotate_local_numbering(V0T, kind, seed, fraction=0.5):
     idx = (np.arange(3)[None, :] + shift[:, None]) % 3
     return (np.take_along_axis(V0T, idx, axis=1).astype(np.int32),
             np.take_along_axis(kind, idx, axis=1).astype(np.int8))
+
+
+def delaunay_square(n, seed, amp=0.35):
+    """Unstructured triangulation of the unit square: the Delaunay
+    triangulation (scipy.spatial) of an (n+1) x (n+1) point grid whose interior
+    points are moved by i.i.d. U[-amp*h, amp*h] per coordinate.  Boundary
+    points stay on the sides.  Returns (coordV, V0T) with counter-clockwise
+    triangles; the connectivity is not the Friedrichs-Keller pattern."""
+    from scipy.spatial import Delaunay
+    h = 1.0 / n
+    g = np.arange(n + 1) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
+    rng = np.random.default_rng(seed)
+    interior = (pts[:, 0] > 0.5 * h) & (pts[:, 0] < 1 - 0.5 * h) & \
+               (pts[:, 1] > 0.5 * h) & (pts[:, 1] < 1 - 0.5 * h)
+    d = rng.uniform(-amp * h, amp * h, size=pts.shape)
+    pts[interior] += d[interior]
+    tri = Delaunay(pts).simplices.astype(np.int32)
+    a, b, c = pts[tri[:, 0]], pts[tri[:, 1]], pts[tri[:, 2]]
+    det = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
+    tri[det < 0] = tri[det < 0][:, [0, 2, 1]]
+    keep = np.abs(det) > 1e-14                       # drop degenerate hull slivers
+    return pts, np.ascontiguousarray(tri[keep])
+
+
+def write_medit(path, coordV, V0T, side_ids, reverse=(), dim=3, comment=None):
+    """Write a triangulation as an ASCII MEDIT .mesh file (the format Gmsh
+    writes): 1-based vertices, the boundary edges with their side ids in
+    "Edges" (side_ids: K x 3 per local edge, 0 interior), the triangles with
+    reference 0; triangles listed in `reverse` are written clockwise."""
+    rev = np.zeros(V0T.shape[0], bool)
+    rev[list(reverse)] = True
+    lines = []
+    if comment:
+        lines.append("# " + comment)
+    lines += ["MeshVersionFormatted 2", "Dimension", str(dim), "Vertices", str(len(coordV))]
+    for x, y in coordV:
+        lines.append(("%r %r 0 0" if dim == 3 else "%r %r 0") % (float(x), float(y)))
+    edges = []
+    for k in range(V0T.shape[0]):
+        for n in range(3):
+            if side_ids[k, n] > 0:
+                edges.append((V0T[k, (n + 1) % 3] + 1, V0T[k, (n + 2) % 3] + 1, side_ids[k, n]))
+    lines += ["Edges", str(len(edges))] + ["%d %d %d" % e for e in edges]
+    lines += ["Triangles", str(V0T.shape[0])]
+    for k, t in enumerate(V0T + 1):
+        t = t[[0, 2, 1]] if rev[k] else t
+        lines.append("%d %d %d 0" % tuple(t))
+    lines.append("End")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")

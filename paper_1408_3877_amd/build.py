@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libldg.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["host_ref.cpp", "host_mesh.cpp", "kernels_core.hip", "kernels_apply.hip",
+SOURCES = ["host_ref.cpp", "host_mesh.cpp", "host_io.cpp", "kernels_core.hip", "kernels_apply.hip",
            "kernels_krylov.hip", "kernels_assemble_mfma.hip", "kernels_gnn.hip", "kernels_factor.hip",
            "api.hip"]
 

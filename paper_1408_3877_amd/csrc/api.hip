@@ -11,6 +11,11 @@ using namespace ldg;
 
 struct ldg_ctx {
   std::string err;
+  // host copies of the mesh (file output) and the basis at the Lagrange points
+  std::vector<double> h_coordV;
+  std::vector<int32_t> h_V0T;
+  int nL = 1;
+  double* phiL = nullptr;   // device [nL][N]
   ldg_options opt{};
   hipStream_t st = nullptr;
   int device = 0;
@@ -851,6 +856,14 @@ ldg_status finish_collect(ldg_ctx* c, double tau) {
 
 }  // namespace
 
+namespace {
+thread_local std::string g_err;   // last failure of a call without a context
+ldg_status fail_noctx(ldg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+}  // namespace
+
 extern "C" {
 
 ldg_status ldg_options_default(ldg_options* o) {
@@ -869,7 +882,10 @@ ldg_status ldg_options_default(ldg_options* o) {
   return LDG_OK;
 }
 
-const char* ldg_last_error(const ldg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* ldg_last_error(const ldg_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_err.empty() ? "null context" : g_err.c_str();
+}
 
 void ldg_destroy(ldg_ctx* c) {
   if (!c) return;
@@ -903,6 +919,8 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   bool mesh_err = false;
   const std::string msg = build_mesh(coordV, numV, V0T, K, edge_kind, hm, &mesh_err);
   if (!msg.empty()) return fail(c, mesh_err ? LDG_EMESH : LDG_EINVAL, msg);
+  c->h_coordV.assign(coordV, coordV + 2 * numV);
+  c->h_V0T.assign(V0T, V0T + 3 * K);
   c->ref = build_refdata(opt->p);
   const RefData& rf = c->ref;
   for (int i = 0; i < rf.N; ++i)
@@ -1060,6 +1078,22 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(dalloc(c, &c->hdev, c->mmax + 2));
   TRY(dalloc(c, &c->ydev, c->mmax + 2));
   TRY(dalloc(c, &c->status, 1));
+  {
+    // Lagrange points of Sec. 3.8: the barycentre (p = 0), the vertices
+    // (p = 1), the vertices and the midpoints of the edges opposite vertices
+    // 1, 2, 3 (p >= 2; for p > 2 the quadratic points, as the VTK output
+    // holds at most quadratic cells)
+    static const double L1[6] = {0.0, 1.0, 0.0, 0.5, 0.0, 0.5};
+    static const double L2[6] = {0.0, 0.0, 1.0, 0.5, 0.5, 0.0};
+    c->nL = c->N == 1 ? 1 : (c->N == 3 ? 3 : 6);
+    std::vector<double> ph((size_t)c->nL * c->N);
+    for (int l = 0; l < c->nL; ++l)
+      for (int i = 0; i < c->N; ++i)
+        ph[(size_t)l * c->N + i] = c->N == 1 ? phi_hat(i, 1.0 / 3.0, 1.0 / 3.0)
+                                             : phi_hat(i, L1[l], L2[l]);
+    TRY(dalloc(c, &c->phiL, ph.size()));
+    TRY(upload(c, c->phiL, ph));
+  }
   c->red.nblk = c->red2.nblk = krylov_nblk(nv);
   c->red.maxv = c->red2.maxv = c->mmax + 1;
   {
@@ -1747,6 +1781,59 @@ ldg_status ldg_get_kernel_stat(ldg_ctx* c, int kernel, ldg_kernel_stat* out) {
   if (!c || !out || kernel < 0 || kernel >= LDG_K_COUNT) return fail(c, LDG_EINVAL, "bad arguments");
   TRY(sync(c));
   *out = c->stats[kernel];
+  return LDG_OK;
+}
+
+ldg_status ldg_lagrange(ldg_ctx* c, const double* C, double* out, int* nL) {
+  if (!c || !nL) return c ? fail(c, LDG_EINVAL, "bad arguments") : LDG_EINVAL;
+  *nL = c->nL;
+  if (!out) return LDG_OK;
+  launch_lagrange(c->K, c->N, c->nL, C ? C : c->C, C == nullptr, c->phiL, out, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_write_vtu(ldg_ctx* c, const char* path, const char* name, const double* lagr,
+                         int nL, int binary) {
+  if (!c || !path || !name || !lagr) return c ? fail(c, LDG_EINVAL, "bad arguments") : LDG_EINVAL;
+  if (nL != c->nL) return fail(c, LDG_EINVAL, "Lagrange values per triangle do not match p");
+  for (const char* q = name; *q; ++q)
+    if (*q == '"' || *q == '<' || *q == '>' || *q == '&')
+      return fail(c, LDG_EINVAL, "the variable name holds an XML special character");
+  const std::string msg = write_vtu(path, name, c->h_coordV, c->h_V0T, c->K, nL, lagr, binary != 0);
+  if (!msg.empty()) return fail(c, LDG_EIO, msg);
+  return LDG_OK;
+}
+
+ldg_status ldg_mesh_read_medit(const char* path, int64_t* numV, int64_t* K, double* coordV,
+                               int32_t* V0T, int32_t* edge_id) {
+  if (!path || !numV || !K) return fail_noctx(LDG_EINVAL, "bad arguments");
+  std::vector<double> cv;
+  std::vector<int32_t> vt, ids;
+  const std::string msg = read_medit(path, cv, vt, ids);
+  if (!msg.empty()) return fail_noctx(msg.rfind("cannot open", 0) == 0 ? LDG_EIO : LDG_EMESH, msg);
+  const bool want = coordV || V0T || edge_id;
+  if (want && (*numV != (int64_t)cv.size() / 2 || *K != (int64_t)vt.size() / 3))
+    return fail_noctx(LDG_EINVAL, "buffer sizes differ from the file's");
+  *numV = (int64_t)cv.size() / 2;
+  *K = (int64_t)vt.size() / 3;
+  if (coordV) std::memcpy(coordV, cv.data(), cv.size() * sizeof(double));
+  if (V0T) std::memcpy(V0T, vt.data(), vt.size() * sizeof(int32_t));
+  if (edge_id) std::memcpy(edge_id, ids.data(), ids.size() * sizeof(int32_t));
+  return LDG_OK;
+}
+
+ldg_status ldg_edge_kinds_from_ids(int64_t K, const int32_t* edge_id, const int32_t* neumann_ids,
+                                   int n_neumann, int8_t* edge_kind) {
+  if (K < 0 || !edge_id || !edge_kind || n_neumann < 0 || (n_neumann > 0 && !neumann_ids))
+    return fail_noctx(LDG_EINVAL, "bad arguments");
+  for (int64_t e = 0; e < 3 * K; ++e) {
+    const int32_t id = edge_id[e];
+    if (id < 0) return fail_noctx(LDG_EMESH, "a boundary edge has no ID");
+    int8_t k = id == 0 ? LDG_EDGE_INTERIOR : LDG_EDGE_DIRICHLET;
+    for (int q = 0; q < n_neumann && id > 0; ++q)
+      if (neumann_ids[q] == id) k = LDG_EDGE_NEUMANN;
+    edge_kind[e] = k;
+  }
   return LDG_OK;
 }
 

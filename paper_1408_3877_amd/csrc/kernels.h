@@ -38,6 +38,9 @@ void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const vo
 // export stored blocks of any precision as FP64 [K][ns][N][N]
 void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src, double* dst,
                               hipStream_t st);
+// out[k][l] = sum_i C(k, i) phiL[l][i] (K x nL, element-major); C tiled or element-major
+void launch_lagrange(int64_t K, int N, int nL, const double* C, bool tiled, const double* phiL,
+                     double* out, hipStream_t st);
 // alpha scales the mass term (1 for a time step, 0 for the stationary operator)
 void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double alpha,
                      double tau, double eta, double* bj, int* status, hipStream_t st);

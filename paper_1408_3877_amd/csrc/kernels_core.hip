@@ -400,6 +400,20 @@ __global__ void k_sample_bnd(Geo g, int R1, const double* __restrict__ s, int64_
   if (gN) gN[idx] = -(F.gcx * nu1 + F.gcy * nu2);
 }
 
+// values at the Lagrange points: out[k][l] = sum_i C(k, i) phiL[l][i], C in
+// the tiled layout (tiled != 0) or element-major
+__global__ void k_lagrange(int64_t K, int N, int nL, const double* __restrict__ C, int tiled,
+                           const double* __restrict__ phiL, double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * nL) return;
+  const int64_t k = idx / nL;
+  const int l = (int)(idx % nL);
+  double s = 0.0;
+  for (int i = 0; i < N; ++i)
+    s += C[tiled ? vidx(k, i, N) : k * N + i] * phiL[l * N + i];
+  out[idx] = s;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -416,6 +430,12 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
     case 15: { constexpr int NT = 15; CALL; } break;            \
     default: break;                                             \
   }
+
+void launch_lagrange(int64_t K, int N, int nL, const double* C, bool tiled, const double* phiL,
+                     double* out, hipStream_t st) {
+  if (K * nL == 0) return;
+  k_lagrange<<<nblk(K * nL, 256), 256, 0, st>>>(K, N, nL, C, tiled ? 1 : 0, phiL, out);
+}
 
 void launch_project(int N, int64_t K, int64_t Kpad, int R, const double* samples, const double* W,
                     double* out, hipStream_t st) {

@@ -74,4 +74,11 @@ struct HostMesh {
 std::string build_mesh(const double* coordV, int64_t numV, const int32_t* V0T, int64_t K,
                        const int8_t* edge_kind, HostMesh& out, bool* is_mesh_error);
 
+// host_io.cpp: MEDIT mesh reader and VTK unstructured-grid writer; "" on success
+std::string read_medit(const char* path, std::vector<double>& coordV, std::vector<int32_t>& V0T,
+                       std::vector<int32_t>& edge_id);
+std::string write_vtu(const char* path, const char* name, const std::vector<double>& coordV,
+                      const std::vector<int32_t>& V0T, int64_t K, int nL, const double* lagr,
+                      bool binary);
+
 }  // namespace ldg

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LDG_FP64, LDG_MIXED_FP32, LDG_MIXED_BF16 = 0, 1, 2
 LDG_PC_BLOCK_JACOBI, LDG_PC_GNN = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOCONV",
-          -6: "EUNSUPPORTED"}
+          -6: "EUNSUPPORTED", -7: "EIO"}
 
 
 class LdgError(RuntimeError):
@@ -94,6 +94,10 @@ _SIGS = {
     "ldg_set_timing": [_P, C.c_int],
     "ldg_get_kernel_stat": [_P, C.c_int, C.POINTER(KernelStat)],
     "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, _P, _P, _P, _P, _P],
+    "ldg_lagrange": [_P, _P, _P, C.POINTER(C.c_int)],
+    "ldg_write_vtu": [_P, C.c_char_p, C.c_char_p, _P, C.c_int, C.c_int],
+    "ldg_mesh_read_medit": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _P, _P, _P],
+    "ldg_edge_kinds_from_ids": [C.c_int64, _P, _P, C.c_int, _P],
 }
 
 _lib = None
@@ -126,6 +130,39 @@ def load_library():
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_noctx(lib, code):
+    if code != 0:
+        raise LdgError(code, lib.ldg_last_error(None).decode())
+
+
+def read_mesh_medit(path):
+    """(coordV numV x 2, V0T K x 3 0-based counter-clockwise, edge_id K x 3) of
+    a MEDIT .mesh file; edge_id is 0 on interior edges, the boundary ID on
+    boundary edges, -1 where the file lists none."""
+    lib = load_library()
+    nv, nk = C.c_int64(0), C.c_int64(0)
+    p = os.fsencode(path)
+    _check_noctx(lib, lib.ldg_mesh_read_medit(p, C.byref(nv), C.byref(nk), None, None, None))
+    coordV = np.zeros((nv.value, 2), np.float64)
+    V0T = np.zeros((nk.value, 3), np.int32)
+    ids = np.zeros((nk.value, 3), np.int32)
+    _check_noctx(lib, lib.ldg_mesh_read_medit(p, C.byref(nv), C.byref(nk), coordV.ctypes.data,
+                                              V0T.ctypes.data, ids.ctypes.data))
+    return coordV, V0T, ids
+
+
+def edge_kinds_from_ids(edge_id, neumann_ids=()):
+    """ldg_edge_kind per local edge: 0 interior, Neumann for the listed IDs,
+    Dirichlet otherwise."""
+    lib = load_library()
+    ids = np.ascontiguousarray(edge_id, np.int32)
+    neu = np.ascontiguousarray(list(neumann_ids) or [0], np.int32)
+    kind = np.zeros(ids.shape, np.int8)
+    _check_noctx(lib, lib.ldg_edge_kinds_from_ids(ids.shape[0], ids.ctypes.data, neu.ctypes.data,
+                                                  len(neumann_ids), kind.ctypes.data))
+    return kind
 
 
 class Solver:
@@ -221,6 +258,22 @@ class Solver:
                                          C.byref(info))
         self._check(code)
         return info.as_dict()
+
+    def lagrange(self, Cm=None):
+        """Values at the Lagrange points (K x nL) of Cm (K x N), or of the state."""
+        nl = C.c_int(0)
+        self._check(self.lib.ldg_lagrange(self.h, None, None, C.byref(nl)))
+        Cd = None if Cm is None else self._dev(Cm, (self.K, self.N))
+        out = self._empty(self.K, nl.value)
+        self._check(self.lib.ldg_lagrange(self.h, _ptr(Cd), _ptr(out), C.byref(nl)))
+        return out
+
+    def write_vtu(self, path, name, lagr, binary=False):
+        """Write Lagrange values (K x nL) as a .vtu file."""
+        v = np.ascontiguousarray(lagr.detach().cpu().numpy() if hasattr(lagr, "detach") else lagr,
+                                 np.float64)
+        self._check(self.lib.ldg_write_vtu(self.h, os.fsencode(path), name.encode(), v.ctypes.data,
+                                           v.shape[1], int(bool(binary))))
 
     def solve_stationary_sampled(self, d, f, cD=None, gN=None):
         """A Y = V from sampled data (no mass term, no history); the solution

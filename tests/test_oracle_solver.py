@@ -265,16 +265,14 @@ def test_table2_p0_stagnates():
 
 def test_fig7_projection_ranges():
     # Sec. 3.8 / Fig. 7: ranges of the projected function at the Lagrange nodes
+    from oracle.io import lagrange_values
     with open(os.path.join(GOLDEN, "fig7_ranges.json")) as fh:
         ranges = json.load(fh)["ranges"]
     cV, V0T, kind = two_triangle_mesh()
     g = Grid(cV, V0T, kind)
     fAlg = lambda x, y: np.where(x < 0, x ** 2 - y ** 2 - 1, -x ** 2 - y ** 2 + 1)
-    nodes = {1: ([1 / 3], [1 / 3]), 3: ([0, 1, 0], [0, 0, 1]),
-             6: ([0, 1, 0, 0.5, 0, 0.5], [0, 0, 1, 0.5, 0.5, 0])}
     for N, (lo, hi) in zip((1, 3, 6), ranges):
         p = basis.order_of(N)
         D = project(g, p, fAlg, RefTensors(p).hatM, order=6)
-        L1, L2 = nodes[N]
-        vals = D @ basis.phi_all(N, np.array(L1, float), np.array(L2, float)).T
+        vals = lagrange_values(D)
         assert abs(vals.min() - lo) < 1e-12 and abs(vals.max() - hi) < 1e-12, (N, vals)
