@@ -99,6 +99,8 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
         s.gnn_factor_storage(args.fac_storage)
         s.gnn_set_params(weights)
     s.set_time_scheme(args.time_scheme)
+    if args.matrix_free:
+        s.set_matrix_free(True)
     log("[bench] %s: context K=%d N=%d (%.1f s)" % (label, s.K, s.N, time.perf_counter() - t0))
     gk = cfg["kind"]
     s.set_initial_samples(s.sample_workload(gk, 0.0, dT=dT, want=("c0",))["c0"])
@@ -220,6 +222,8 @@ def main():
                     help="storage of the learned preconditioner's factor blocks")
     ap.add_argument("--time-scheme", default="euler", choices=["euler", "bdf2"],
                     help="implicit Euler (the paper's) or two-step backward differentiation")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="apply the operator without streaming stored blocks (both runs)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--no-baseline", action="store_true",
@@ -268,14 +272,15 @@ def main():
         log("[bench] no kernel timing: %.4g DOF*steps/s, %.1f ms per step" %
             (dof * args.steps / el, el * 1e3 / args.steps))
         return
-    name = max(("div", "factor", "bj_apply", "grad"), key=lambda k: stats[k]["total_ms"])
+    name = max(("div", "factor", "bj_apply", "grad", "mf"), key=lambda k: stats[k]["total_ms"])
     kv = stats[name]
     ach = kv["bytes"] / (kv["total_ms"] * 1e-3) / 1e9 if kv["total_ms"] > 0 else 0.0
     per_launch = kv["bytes"] / max(kv["launches"], 1)
     kernel_desc = {"div": "k_div (operator apply, stored blocks)",
                    "factor": "k_fac_w + k_fac_f (learned factored preconditioner apply)",
                    "bj_apply": "k_bj_apply (block-Jacobi apply)",
-                   "grad": "k_grad (operator gradient half)"}[name]
+                   "grad": "k_grad (operator gradient half)",
+                   "mf": "k_mf_blocks (matrix-free block terms on the matrix cores)"}[name]
     traffic = measured_traffic(args.config, name, args.precision,
                                args.precond + ("-" + args.fac_storage if learned else ""))
     solver_desc = "%s %s %s%s" % (
@@ -302,6 +307,7 @@ def main():
         "config": {"workload": args.config, "K": s.K, "N": s.N, "p": cfg["p"], "DOF": dof,
                    "dt": dt_of(cfg), "rtol": args.rtol,
                    "time_scheme": "stationary" if stationary else args.time_scheme,
+                   "matrix_free": args.matrix_free,
                    "solver": solver_desc,
                    "weights": os.path.relpath(args.weights or WEIGHTS.get(cfg["p"]), ROOT)
                    if learned else None,

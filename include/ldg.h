@@ -227,7 +227,8 @@ ldg_status ldg_get_solution(ldg_ctx* ctx, double* C, double* Z1, double* Z2, int
  * gathers not counted); flops likewise.
  */
 typedef enum {
-  LDG_K_DIV = 0,       /* divergence half of the operator: streams the stored blocks */
+  LDG_K_DIV = 0,       /* divergence half of the operator: streams the stored blocks
+                          (matrix-free: the terms without blocks) */
   LDG_K_GRAD = 1,      /* gradient half of the operator */
   LDG_K_BJ_APPLY = 2,  /* block-Jacobi application */
   LDG_K_ASSEMBLE = 3,  /* block assembly */
@@ -236,7 +237,8 @@ typedef enum {
   LDG_K_PROJECT = 6,   /* projections and boundary data */
   LDG_K_GNN = 7,       /* graph-network inference and training */
   LDG_K_FACTOR = 8,    /* factored learned preconditioner: setup and application */
-  LDG_K_COUNT = 9
+  LDG_K_MF = 9,        /* matrix-free block terms of the divergence half */
+  LDG_K_COUNT = 10
 } ldg_kernel_id;
 typedef struct {
   int64_t launches;
@@ -245,6 +247,21 @@ typedef struct {
   double flops;
 } ldg_kernel_stat;
 ldg_status ldg_set_timing(ldg_ctx* ctx, int on);
+
+/*
+ * Matrix-free operator apply (on = 1; default 0).  The Krylov iterations then
+ * do not stream the stored D-dependent blocks: the divergence half applies
+ * sum_m B^m Z^m + sum_n U_kn (nu^1 Z^1_k+ + nu^2 Z^2_k+) by contracting the
+ * projected coefficient D (FP64) with the reference tensors G_hat, R_hat_diag
+ * and R_hat_off (Sec. 3.6.3, 3.6.6, 3.6.7) on the matrix cores inside the
+ * apply: one GEMM over the pairs (l, j) per triangle group, with the tensor
+ * as the shared operand and D_kl u_j as the per-triangle one.  FP64 vectors
+ * use FP64 matrix instructions; the FP32 inner solves of the mixed modes use
+ * FP32 ones (FP32 operands and sums, more accurate than BF16 blocks).  The
+ * stored blocks are still assembled once per step for the block-Jacobi and
+ * learned preconditioners.  Takes effect at the next apply.
+ */
+ldg_status ldg_set_matrix_free(ldg_ctx* ctx, int on);
 ldg_status ldg_get_kernel_stat(ldg_ctx* ctx, int kernel, ldg_kernel_stat* out);
 
 /* ---- entry points of the individual steps of the path (used by the tests) ---- */

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libldg.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["host_ref.cpp", "host_mesh.cpp", "host_io.cpp", "kernels_core.hip", "kernels_apply.hip",
-           "kernels_krylov.hip", "kernels_assemble_mfma.hip", "kernels_gnn.hip", "kernels_factor.hip",
+           "kernels_krylov.hip", "kernels_assemble_mfma.hip", "kernels_gnn.hip", "kernels_factor.hip", "kernels_mf.hip",
            "api.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

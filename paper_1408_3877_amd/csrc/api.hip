@@ -99,6 +99,10 @@ struct ldg_ctx {
   bool have_prev = false;
   double dt_prev = 0.0;
   double alpha = 1.0;   // mass coefficient of the operator (0 for the stationary system)
+  // matrix-free apply: the block terms contracted from D on the matrix cores
+  bool mf = false;
+  double* mf64 = nullptr;
+  float* mf32 = nullptr;
 };
 
 namespace {
@@ -229,6 +233,25 @@ double div_flops(const ldg_ctx* c) {
   return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 2.0 * NN * (c->n_sd + 2.0 * c->Eint) +
          2.0 * c->N * c->K;
 }
+// matrix-free apply: the divergence kernel without blocks (C own and three
+// neighbours, Z not read, y written), and the block-term kernel: D own and
+// three neighbours (FP64), Z^1, Z^2 own and three neighbours, C, y read and
+// written, geometry; flops of the useful contraction (8 tensors, N^3 each)
+double mf_div_bytes(const ldg_ctx* c, const Level& L) {
+  return L.vbytes * 5.0 * c->N * c->K + 74.0 * c->K;
+}
+double mf_div_flops(const ldg_ctx* c) {
+  const double NN = (double)c->N * c->N;
+  return 2.0 * NN * (c->n_sd + 2.0 * c->Eint) + 2.0 * c->N * c->K;
+}
+double mf_bytes(const ldg_ctx* c, const Level& L) {
+  return 8.0 * c->N * (c->K + 2.0 * c->Eint) + L.vbytes * c->N * (2.0 * c->K + 4.0 * c->Eint) +
+         L.vbytes * 3.0 * c->N * c->K + 130.0 * c->K;
+}
+double mf_flops(const ldg_ctx* c) {
+  const double N3 = (double)c->N * c->N * c->N;
+  return 2.0 * N3 * (5.0 * c->K + 2.0 * c->Eint);
+}
 double grad_bytes(const ldg_ctx* c, const Level& L, bool with_j) {
   return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + 130.0 * c->K;
 }
@@ -245,6 +268,17 @@ void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j
     Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c));
     launch_grad(c->N, L.vt, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
                 Zx1, Zx2, c->st);
+  }
+  if (c->mf) {
+    {
+      Timed tm(c, LDG_K_DIV, mf_div_bytes(c, L), mf_div_flops(c));
+      launch_div(c->N, L.vt, L.bt, c->geo, c->refs, nullptr, x, Zx1, Zx2, c->alpha, tau,
+                 c->opt.eta, y, c->st, nullptr);
+    }
+    Timed tm(c, LDG_K_MF, mf_bytes(c, L), mf_flops(c));
+    launch_mf_blocks(c->N, L.vt, c->geo, c->D, L.vt == VT_F64 ? (const void*)c->mf64 : c->mf32, x,
+                     Zx1, Zx2, tau, y, dot ? &c->red : nullptr, c->st);
+    return;
   }
   Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c));
   launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, c->alpha, tau, c->opt.eta,
@@ -1099,7 +1133,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   {
     const size_t nb = std::max<size_t>(c->red.nblk, gs_nblk(nv));
     size_t np = (size_t)(c->mmax + 2) * nb;
-    const size_t nbj = (size_t)(Kp / 256 + 1);
+    const size_t nbj = (size_t)(Kp / 64 + 1);   // per-block partials of the apply kernels
     if (np < nbj) np = nbj;
     if (np < 2048) np = 2048;
     TRY(dalloc(c, &c->red.partials, np));
@@ -1774,6 +1808,31 @@ ldg_status ldg_set_timing(ldg_ctx* c, int on) {
   TRY(sync(c));
   c->timing = on != 0;
   for (auto& s : c->stats) s = ldg_kernel_stat{};
+  return LDG_OK;
+}
+
+ldg_status ldg_set_matrix_free(ldg_ctx* c, int on) {
+  if (!c) return LDG_EINVAL;
+  if (on && !c->mf64) {
+    // A-operand tables of the 14 tensors (G1, G2, Rd0..2, Ro(n, n+)), FP64 and FP32
+    const RefData& rf = c->ref;
+    const double* tens[14] = {rf.G[0].data(), rf.G[1].data(), rf.Rd[0].data(), rf.Rd[1].data(),
+                              rf.Rd[2].data()};
+    for (int ab = 0; ab < 9; ++ab) tens[5 + ab] = rf.Ro[ab / 3][ab % 3].data();
+    std::vector<double> t64((size_t)mf_table_size(c->N));
+    mf_build_table(c->N, tens, t64.data());
+    std::vector<float> t32(t64.begin(), t64.end());
+    double* p64 = nullptr;
+    float* p32 = nullptr;
+    TRY(dalloc(c, &p64, t64.size()));
+    TRY(dalloc(c, &p32, t32.size()));
+    TRY(upload(c, p64, t64));
+    TRY(upload(c, p32, t32));
+    TRY(sync(c));
+    c->mf64 = p64;
+    c->mf32 = p32;
+  }
+  c->mf = on != 0;
   return LDG_OK;
 }
 

@@ -38,6 +38,14 @@ void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const vo
 // export stored blocks of any precision as FP64 [K][ns][N][N]
 void launch_export_blocks_any(int bt, int64_t K, int N, int ns, const void* src, double* dst,
                               hipStream_t st);
+// matrix-free block terms: y += tau (sum_m B^m Z^m + sum_n U_kn w_n) with the
+// blocks contracted from D on the matrix cores; table from mf_build_table (FP64,
+// or converted to FP32 for vt = VT_F32); red (optional): <C, y> of the result
+int mf_table_size(int N);
+void mf_build_table(int N, const double* const* tens, double* out);
+void launch_mf_blocks(int N, int vt, const Geo& g, const double* D, const void* table,
+                      const void* C, const void* Z1, const void* Z2, double tau, void* y,
+                      const Reducer* red, hipStream_t st);
 // out[k][l] = sum_i C(k, i) phiL[l][i] (K x nL, element-major); C tiled or element-major
 void launch_lagrange(int64_t K, int N, int nL, const double* C, bool tiled, const double* phiL,
                      double* out, hipStream_t st);

@@ -141,17 +141,19 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
       mv_add<N, T>(sm + ref_so(n, np) * N * N, cp, t, (T)(-eta));
     }
   }
-  load_vec<N, T>(Z1, k, z);
-  block_mv<N, BT, T>(blocks, k, 0, NSLOT, z, t);
-  load_vec<N, T>(Z2, k, z);
-  block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
-  for (int n = 0; n < 3; ++n) {
-    const int64_t kp = g.nbr[n * Kp + k];
-    if (kp < 0) continue;
-    const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+  if (blocks != nullptr) {   // else the block terms come from the matrix-free kernel
+    load_vec<N, T>(Z1, k, z);
+    block_mv<N, BT, T>(blocks, k, 0, NSLOT, z, t);
+    load_vec<N, T>(Z2, k, z);
+    block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
+    for (int n = 0; n < 3; ++n) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      if (kp < 0) continue;
+      const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
 #pragma unroll
-    for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
-    block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
+      for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
+      block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
+    }
   }
   const T a2 = (T)(alpha * g.area2[k]);
   const T tt = (T)tau;

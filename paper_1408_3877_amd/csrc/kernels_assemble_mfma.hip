@@ -23,47 +23,13 @@
 // are computed and each lane keeps its own.
 #include "device_common.h"
 #include "kernels.h"
+#include "mfma_common.h"
 
 namespace ldg {
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef short s8_t __attribute__((ext_vector_type(8)));
 
 namespace {
 
 constexpr int NT_ELEM = 5;   // G1, G2, Rd0, Rd1, Rd2
-constexpr int NT_ALL = 14;   // + Ro[3][3]
-
-template <int PREC> struct Mfma;
-template <> struct Mfma<0> {
-  using A = double; using B = double; using Acc = d4_t; using Out = double;
-  static constexpr int KS = 4;   // l per instruction
-  __device__ static inline Acc run(A a, B b, Acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int r, int q) { return 4 * r + q; }
-};
-template <> struct Mfma<1> {
-  using A = float; using B = float; using Acc = f4_t; using Out = float;
-  static constexpr int KS = 4;
-  __device__ static inline Acc run(A a, B b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int r, int q) { return 4 * q + r; }
-};
-template <> struct Mfma<2> {
-  using A = s8_t; using B = s8_t; using Acc = f4_t; using Out = bf16;
-  static constexpr int KS = 32;
-  __device__ static inline Acc run(A a, B b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int r, int q) { return 4 * q + r; }
-};
-
-template <class T> __device__ inline T zero_acc();
-template <> __device__ inline d4_t zero_acc<d4_t>() { return d4_t{0.0, 0.0, 0.0, 0.0}; }
-template <> __device__ inline f4_t zero_acc<f4_t>() { return f4_t{0.f, 0.f, 0.f, 0.f}; }
 
 // B operand of k-step ks for coefficient vector of triangle kk (or zeros)
 template <int N, int PREC>
@@ -132,17 +98,6 @@ __device__ inline void store_col(typename Mfma<PREC>::Out* __restrict__ blocks, 
     }
   }
   (void)NN;
-}
-
-__device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ inline int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-  return v;
 }
 
 }  // namespace

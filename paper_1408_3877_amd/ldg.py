@@ -40,7 +40,8 @@ class KernelStat(C.Structure):
                 ("flops", C.c_double)]
 
 
-KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn", "factor"]
+KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn", "factor",
+           "mf"]
 
 
 class StepInfo(C.Structure):
@@ -92,6 +93,7 @@ _SIGS = {
     "ldg_gnn_collect": [_P, C.c_int, _P, _P, _P],
     "ldg_gnn_collected": [_P, C.POINTER(C.c_int)],
     "ldg_set_timing": [_P, C.c_int],
+    "ldg_set_matrix_free": [_P, C.c_int],
     "ldg_get_kernel_stat": [_P, C.c_int, C.POINTER(KernelStat)],
     "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, _P, _P, _P, _P, _P],
     "ldg_lagrange": [_P, _P, _P, C.POINTER(C.c_int)],
@@ -258,6 +260,10 @@ class Solver:
                                          C.byref(info))
         self._check(code)
         return info.as_dict()
+
+    def set_matrix_free(self, on=True):
+        """Apply the operator without streaming stored blocks (matrix cores)."""
+        self._check(self.lib.ldg_set_matrix_free(self.h, int(bool(on))))
 
     def lagrange(self, Cm=None):
         """Values at the Lagrange points (K x nL) of Cm (K x N), or of the state."""
