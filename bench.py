@@ -37,6 +37,7 @@ from inputs.fields import (LOGNORMAL, LOGNORMAL_T, MAIN, SMOOTH1, SMOOTH2, TABLE
 from inputs.meshes import NORTH, SOUTH, square_mesh  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # dense matrix-core peaks of the MI355X
 
 # The five workloads: mesh of n x n cells (2 n^2 triangles), order p, data.
 CONFIGS = {
@@ -151,20 +152,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config, kernel, precision, precond):
+def measured_traffic(config, kernel, precision, precond, matrix_free=False):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when it is absent, for another run, or the kernels
-    changed since it was taken."""
+    summaries, or None when absent, for another run, or the kernels changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % config)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    if (rec.get("kernel"), rec.get("precision"), rec.get("precond")) != (kernel, precision, precond):
-        return None
-    return rec.get("bytes_per_launch")
+    for r in rec.get("records", [rec]):
+        if r.get("kernel_source_hash") != kernel_source_hash():
+            continue
+        if (r.get("kernel"), r.get("precision"), r.get("precond"),
+                bool(r.get("matrix_free", False))) == (kernel, precision, precond, matrix_free):
+            return r.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(cfg, seconds_hint=True):
@@ -274,15 +277,31 @@ def main():
         return
     name = max(("div", "factor", "bj_apply", "grad", "mf"), key=lambda k: stats[k]["total_ms"])
     kv = stats[name]
-    ach = kv["bytes"] / (kv["total_ms"] * 1e-3) / 1e9 if kv["total_ms"] > 0 else 0.0
     per_launch = kv["bytes"] / max(kv["launches"], 1)
+    avg_ms = kv["total_ms"] / max(kv["launches"], 1)
     kernel_desc = {"div": "k_div (operator apply, stored blocks)",
                    "factor": "k_fac_w + k_fac_f (learned factored preconditioner apply)",
                    "bj_apply": "k_bj_apply (block-Jacobi apply)",
                    "grad": "k_grad (operator gradient half)",
                    "mf": "k_mf_blocks (matrix-free block terms on the matrix cores)"}[name]
     traffic = measured_traffic(args.config, name, args.precision,
-                               args.precond + ("-" + args.fac_storage if learned else ""))
+                               args.precond + ("-" + args.fac_storage if learned else ""),
+                               args.matrix_free)
+    if name == "mf":
+        # bound by the matrix cores: useful flops of the contraction per launch
+        flops = kv["flops"] / max(kv["launches"], 1)
+        peak = MFMA_PEAK_TFLOPS["fp64" if prec == 0 else "fp32"]
+        ach = flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+        roof = {"bound": "mfma", "kernel": kernel_desc, "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
+                "traffic": traffic}
+    else:
+        ach = kv["bytes"] / (kv["total_ms"] * 1e-3) / 1e9 if kv["total_ms"] > 0 else 0.0
+        roof = {"bound": "hbm", "kernel": kernel_desc, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
+                "traffic": traffic}
     solver_desc = "%s %s %s%s" % (
         args.precision,
         "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
@@ -316,12 +335,7 @@ def main():
                    "refinement_sweeps_per_step": sum(i["ir_steps"] for i in infos) / len(infos),
                    "fallbacks": sum(i["fallbacks"] for i in infos),
                    "max_rel_residual": max(i["rel_residual"] for i in infos)},
-        "roofline": {"bound": "hbm", "kernel": kernel_desc,
-                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": per_launch,
-                     "avg_launch_ms": kv["total_ms"] / max(kv["launches"], 1),
-                     "traffic": traffic},
+        "roofline": roof,
         "kernels": kernel_table(stats),
     }
     if base is not None:
