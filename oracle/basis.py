@@ -8,7 +8,15 @@ polynomials term by term (they are pinned against the paper's printed
 gradient formulas in the tests).
 
 Basis index i is 0-based here (the paper's phi_{i+1}).
+
+A second orthonormal basis of the same spaces, obtained by Gram-Schmidt
+orthonormalisation of the monomials (the alternative the paper mentions in
+Sec. 2.4.1), can be selected with `use("gram-schmidt")`; the method's
+discrete functions do not depend on the basis, which the tests use as a pin.
 """
+import contextlib
+from math import factorial
+
 import numpy as np
 
 # (normalisation, [(coefficient, power of x1, power of x2), ...])
@@ -85,12 +93,64 @@ def grad_phi(i, m, x1, x2):
     return s * out
 
 
+_KIND = ["paper"]
+
+
+@contextlib.contextmanager
+def use(kind):
+    """Select "paper" (the listed functions) or "gram-schmidt" inside a with-block."""
+    if kind not in ("paper", "gram-schmidt"):
+        raise ValueError(kind)
+    old = _KIND[0]
+    _KIND[0] = kind
+    try:
+        yield
+    finally:
+        _KIND[0] = old
+
+
+def _monomials(N):
+    """Exponents (a, b) of x1^a x2^b by total degree, then by power of x2."""
+    p = order_of(N)
+    return [(d - b, b) for d in range(p + 1) for b in range(d + 1)]
+
+
+def _gram_schmidt(N):
+    """L^{-1} with G = L L^T, G_kl = integral of m_k m_l over the reference
+    triangle, whose monomial integrals are a! b! / (a + b + 2)!; the functions
+    L^{-1} m are orthonormal."""
+    mono = _monomials(N)
+    G = np.array([[factorial(a + c) * factorial(b + d) / factorial(a + b + c + d + 2)
+                   for (c, d) in mono] for (a, b) in mono])
+    return np.linalg.inv(np.linalg.cholesky(G)), mono
+
+
+def _gs_all(N, x1, x2, m=None):
+    Linv, mono = _gram_schmidt(N)
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    cols = []
+    for a, b in mono:
+        if m is None:
+            cols.append(x1 ** a * x2 ** b)
+        elif m == 0:
+            cols.append(a * x1 ** max(a - 1, 0) * x2 ** b if a > 0 else 0.0 * x1)
+        else:
+            cols.append(b * x1 ** a * x2 ** max(b - 1, 0) if b > 0 else 0.0 * x1)
+    M = np.stack(np.broadcast_arrays(*cols), axis=-1)
+    return M @ Linv.T
+
+
 def phi_all(N, x1, x2):
     """[len(x) x N] matrix of all basis functions at the points."""
+    if _KIND[0] == "gram-schmidt":
+        return _gs_all(N, x1, x2)
     return np.stack([phi(i, x1, x2) for i in range(N)], axis=-1)
 
 
 def grad_phi_all(N, x1, x2):
     """[len(x) x N x 2] gradients of all basis functions at the points."""
+    if _KIND[0] == "gram-schmidt":
+        return np.stack([_gs_all(N, x1, x2, 0), _gs_all(N, x1, x2, 1)], axis=-1)
     return np.stack([np.stack([grad_phi(i, m, x1, x2) for m in range(2)], axis=-1)
                      for i in range(N)], axis=-2)

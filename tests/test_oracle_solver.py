@@ -276,3 +276,45 @@ def test_fig7_projection_ranges():
         D = project(g, p, fAlg, RefTensors(p).hatM, order=6)
         vals = lagrange_values(D)
         assert abs(vals.min() - lo) < 1e-12 and abs(vals.max() - hi) < 1e-12, (N, vals)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_discrete_functions_do_not_depend_on_the_basis(p):
+    # the same method in a Gram-Schmidt basis of the monomials (Sec. 2.4.1):
+    # every tensor, projection and block changes, the functions c_h, z_h do not
+    from oracle.quadrature import triangle_rule
+    cV, V0T, kind = square_mesh(4, seed=61, neumann_sides=(SOUTH,))
+    w = Workload(SMOOTH1)
+    q1, q2, _ = triangle_rule(2 * p + 2)
+    out = {}
+    for b in ("paper", "gram-schmidt"):
+        with basis.use(b):
+            pr = Problem(cV, V0T, kind, p)
+            C0 = pr.initial(w)
+            C1, Z1, Z2, _ = pr.step(C0, 0.05, 0.05, w)
+            N = pr.N
+            Phi = basis.phi_all(N, q1, q2)
+            out[b] = [X @ Phi.T for X in (C0, C1, Z1, Z2)]
+    for a, g in zip(out["paper"], out["gram-schmidt"]):
+        assert np.abs(a - g).max() <= 1e-9 * np.abs(a).max()
+
+
+def test_step_ignores_the_previous_flux():
+    # W has zero Z rows (eq:fullSystem): perturbing Z^n leaves Y^{n+1} unchanged
+    import scipy.sparse.linalg as spla
+
+    from oracle.ldg import mass_W
+    cV, V0T, kind = square_mesh(3, seed=62, neumann_sides=(NORTH,))
+    pr = Problem(cV, V0T, kind, 2)
+    w = Workload(SMOOTH1)
+    data = pr.data(w, 0.02)
+    b, A, V = pr.assemble(data)
+    W = mass_W(b)
+    KN = pr.grid.numT * pr.N
+    rng = np.random.default_rng(62)
+    C0 = pr.initial(w).reshape(-1)
+    Ys = []
+    for zn in (np.zeros(2 * KN), rng.standard_normal(2 * KN)):
+        Yn = np.concatenate([zn, C0])
+        Ys.append(spla.spsolve((W + 0.02 * A).tocsc(), W @ Yn + 0.02 * V))
+    assert np.abs(Ys[0] - Ys[1]).max() == 0.0
