@@ -20,19 +20,38 @@ __device__ inline int ref_h(int m) { return m; }
 __device__ inline int ref_sd(int n) { return 2 + n; }
 __device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
 
+// FP32 reference matrices in LDS with rows padded to whole 16-byte vectors, so
+// that a row is read with ceil(N / 4) LDS instructions instead of N (measured
+// faster for the FP32 kernels); FP64 rows stay unpadded with scalar reads
+// (the 16-byte form measured slower there)
+template <class T> constexpr int lds_w() { return sizeof(T) == 4 ? 4 : 1; }
+template <int N, class T> constexpr int row_stride() { return (N + lds_w<T>() - 1) / lds_w<T>() * lds_w<T>(); }
+template <int N, class T> constexpr int ref_size() { return NREF * N * row_stride<N, T>(); }
+
 template <int N, class T>
 __device__ inline void load_refs(T* sm, const double* __restrict__ g) {
-  for (int t = threadIdx.x; t < NREF * N * N; t += blockDim.x) sm[t] = (T)g[t];
+  constexpr int RS = row_stride<N, T>();
+  for (int t = threadIdx.x; t < ref_size<N, T>(); t += blockDim.x) {
+    const int row = t / RS, j = t % RS;   // row = matrix * N + i
+    sm[t] = j < N ? (T)g[row * N + j] : (T)0;
+  }
   __syncthreads();
 }
 
 template <int N, class T>
 __device__ inline void mv_add(const T* __restrict__ A, const T* x, T* acc, T scale) {
+  constexpr int W = lds_w<T>(), RS = row_stride<N, T>();
+  typedef T vec __attribute__((ext_vector_type(W)));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T s = 0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) s += A[i * N + j] * x[j];
+    for (int jb = 0; jb < RS / W; ++jb) {
+      const vec v = *reinterpret_cast<const vec*>(A + i * RS + jb * W);
+#pragma unroll
+      for (int e = 0; e < W; ++e)
+        if (jb * W + e < N) s += v[e] * x[jb * W + e];
+    }
     acc[i] += scale * s;
   }
 }
@@ -44,7 +63,7 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
                                               const T* __restrict__ C, const T* __restrict__ J1,
                                               const T* __restrict__ J2, T* __restrict__ Z1,
                                               T* __restrict__ Z2) {
-  __shared__ T sm[NREF * N * N];
+  __shared__ __align__(16) T sm[ref_size<N, T>()];
   load_refs<N, T>(sm, refs);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
@@ -65,8 +84,8 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T u1[N], u2[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0;
-    mv_add<N, T>(sm + ref_h(0) * N * N, c, u1, (T)1);
-    mv_add<N, T>(sm + ref_h(1) * N * N, c, u2, (T)1);
+    mv_add<N, T>(sm + ref_h(0) * N * row_stride<N, T>(), c, u1, (T)1);
+    mv_add<N, T>(sm + ref_h(1) * N * row_stride<N, T>(), c, u2, (T)1);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       a1[i] -= B22 * u1[i] - B21 * u2[i];
@@ -82,13 +101,13 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T s[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] = 0;
-    mv_add<N, T>(sm + ref_sd(n) * N * N, c, s, cq);
+    mv_add<N, T>(sm + ref_sd(n) * N * row_stride<N, T>(), c, s, cq);
     if (kind == LDG_EDGE_INTERIOR) {
       const int64_t kp = g.nbr[n * Kp + k];
       const int np = g.nbrn[n * Kp + k];
       T cp[N];
       load_vec<N, T>(C, kp, cp);
-      mv_add<N, T>(sm + ref_so(n, np) * N * N, cp, s, (T)0.5 * L);
+      mv_add<N, T>(sm + ref_so(n, np) * N * row_stride<N, T>(), cp, s, (T)0.5 * L);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -132,13 +151,13 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
   for (int n = 0; n < 3; ++n) {
     const int kind = g.kind[n * Kp + k];
     if (kind == LDG_EDGE_NEUMANN) continue;
-    mv_add<N, T>(sm + ref_sd(n) * N * N, c, t, (T)eta);   // (1/|E|) |E| S_hat_diag
+    mv_add<N, T>(sm + ref_sd(n) * N * row_stride<N, T>(), c, t, (T)eta);   // (1/|E|) |E| S_hat_diag
     if (kind == LDG_EDGE_INTERIOR) {
       const int64_t kp = g.nbr[n * Kp + k];
       const int np = g.nbrn[n * Kp + k];
       T cp[N];
       load_vec<N, T>(C, kp, cp);
-      mv_add<N, T>(sm + ref_so(n, np) * N * N, cp, t, (T)(-eta));
+      mv_add<N, T>(sm + ref_so(n, np) * N * row_stride<N, T>(), cp, t, (T)(-eta));
     }
   }
   if (blocks != nullptr) {   // else the block terms come from the matrix-free kernel
@@ -176,7 +195,7 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
                                              const T* __restrict__ Z2, double alpha, double tau,
                                              double eta, T* __restrict__ y,
                                              double* __restrict__ partials) {
-  __shared__ T sm[NREF * N * N];
+  __shared__ __align__(16) T sm[ref_size<N, T>()];
   __shared__ double red[4];
   load_refs<N, T>(sm, refs);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
