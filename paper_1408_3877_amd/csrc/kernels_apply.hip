@@ -132,8 +132,9 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   store_vec<N, T>(Z2, k, a2);
 }
 
-// one triangle of the divergence half; returns <C_k, y_k> for the fused dot
-template <int N, class T, class BT>
+// one triangle of the divergence half; returns <C_k, y_k> for the fused dot.
+// BLOCKS = false leaves out the block terms (the matrix-free kernel adds them).
+template <int N, class T, class BT, bool BLOCKS>
 __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
                                  const BT* __restrict__ blocks, const T* __restrict__ C,
                                  const T* __restrict__ Z1, const T* __restrict__ Z2, double alpha,
@@ -160,7 +161,7 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
       mv_add<N, T>(sm + ref_so(n, np) * N * row_stride<N, T>(), cp, t, (T)(-eta));
     }
   }
-  if (blocks != nullptr) {   // else the block terms come from the matrix-free kernel
+  if constexpr (BLOCKS) {
     load_vec<N, T>(Z1, k, z);
     block_mv<N, BT, T>(blocks, k, 0, NSLOT, z, t);
     load_vec<N, T>(Z2, k, z);
@@ -188,7 +189,7 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
 
 // y = alpha M C + tau (eta S' C + sum_m B^m Z^m); partials (optional): per-block
 // sums of <C, y>, the CG curvature p^T A p fused into the apply
-template <int N, class T, class BT>
+template <int N, class T, class BT, bool BLOCKS>
 __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
                                              const BT* __restrict__ blocks,
                                              const T* __restrict__ C, const T* __restrict__ Z1,
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
   load_refs<N, T>(sm, refs);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (k < g.Kpad) s = div_row<N, T, BT>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
+  if (k < g.Kpad) s = div_row<N, T, BT, BLOCKS>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
   if (partials == nullptr) return;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -329,16 +330,26 @@ void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const v
                 double eta, void* y, hipStream_t st, const Reducer* red) {
   const unsigned nb = nblk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
-  if (vt == VT_F64) {
-    LDG_SWITCH_N(N, (k_div<NT, double, double><<<nb, 256, 0, st>>>(
+  if (blocks == nullptr) {   // matrix-free: the terms without blocks
+    if (vt == VT_F64) {
+      LDG_SWITCH_N(N, (k_div<NT, double, double, false><<<nb, 256, 0, st>>>(
+                          g, refs, nullptr, (const double*)C, (const double*)Z1,
+                          (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
+    } else {
+      LDG_SWITCH_N(N, (k_div<NT, float, float, false><<<nb, 256, 0, st>>>(
+                          g, refs, nullptr, (const float*)C, (const float*)Z1, (const float*)Z2,
+                          alpha, tau, eta, (float*)y, parts)));
+    }
+  } else if (vt == VT_F64) {
+    LDG_SWITCH_N(N, (k_div<NT, double, double, true><<<nb, 256, 0, st>>>(
                         g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
                         (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
   } else if (bt == BT_F32) {
-    LDG_SWITCH_N(N, (k_div<NT, float, float><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N(N, (k_div<NT, float, float, true><<<nb, 256, 0, st>>>(
                         g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
                         (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   } else {
-    LDG_SWITCH_N(N, (k_div<NT, float, bf16><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N(N, (k_div<NT, float, bf16, true><<<nb, 256, 0, st>>>(
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
                         (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   }
