@@ -113,6 +113,14 @@ def test_fullsize_sampled(name, precision):
     inv = np.linalg.inv(diag)
     assert np.abs(bjg - inv).max() <= 1e-9 * np.abs(inv).max()
     # (5) one full-size implicit Euler step on the GPU; residual rows by the oracle
+    _step_residual_rows(s, cfg, w, grid, refs, el, dt, eta)
+
+
+def _step_residual_rows(s, cfg, w, grid, refs, el, dt, eta):
+    """One implicit Euler step on the GPU from the projected initial state; the
+    oracle recomputes the full system's residual rows and Z on the sample."""
+    p = cfg["p"]
+    dT = w.dT
     c0 = s.sample_workload(cfg["kind"], 0.0, dT=dT, want=("c0",))["c0"]
     s.set_initial_samples(c0, 0.0)
     C0g = to_np(s.get_solution()[0])
@@ -136,6 +144,35 @@ def test_fullsize_sampled(name, precision):
     assert res_rows <= 2e-8 * bnorm, (res_rows, bnorm)
     for m, Zg in enumerate((Z1, Z2)):
         assert np.abs(Zg[el] - Zo[m]).max() <= 1e-9 * np.abs(Zo[m]).max()
+
+
+def test_fullsize_matrix_free_apply_and_step():
+    # the matrix-free apply at the benchmark's size (combined workload, FP64):
+    # every row against the stored-block apply, sampled rows against the oracle,
+    # and a full-size step whose residual rows the oracle recomputes
+    from paper_1408_3877_amd import Solver
+    cfg = CONFIGS["combined-p4-1024"]
+    p, dt, eta = cfg["p"], cfg["dt"], 1.0
+    coordV, V0T, kind = square_mesh(cfg["n"], seed=cfg["jitter"])
+    w = _workload(cfg)
+    grid = Grid(coordV, V0T, kind)
+    refs = RefTensors(p)
+    K, N = grid.numT, refs.N
+    rng = np.random.default_rng(4343)
+    el = _sample(grid, rng)
+    print("[fullsize-mf] K=%d sampled=%d" % (K, len(el)), flush=True)
+    s = Solver(coordV, V0T, kind, p, rtol=1e-8, restart=30, max_iters=20000)
+    Dr = 1.0 + 0.3 * rng.standard_normal((K, N))
+    s.assemble(Dr)
+    Cr = rng.standard_normal((K, N))
+    ys = to_np(s.apply_schur(dt, Cr))
+    s.set_matrix_free(True)
+    ym = to_np(s.apply_schur(dt, Cr))
+    a = grid.areaT[:, None]
+    assert np.sqrt(np.sum(a * (ym - ys) ** 2) / np.sum(a * ys ** 2)) < 1e-13
+    yo, _ = schur_apply_rows(grid, refs, Dr, Cr, dt, eta, el)
+    assert np.abs(ym[el] - yo).max() <= 1e-12 * np.abs(yo).max()
+    _step_residual_rows(s, cfg, w, grid, refs, el, dt, eta)
 
 
 def test_fullsize_learned_factor_blocks_and_omega():
