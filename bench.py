@@ -221,7 +221,7 @@ def main():
                          "where trained weights exist for the order and the workload steps in "
                          "time, else block-Jacobi)")
     ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
-    ap.add_argument("--fac-storage", default="fp8", choices=["f32", "bf16", "fp8"],
+    ap.add_argument("--fac-storage", default="fp8", choices=["f32", "bf16", "fp8", "fp8w"],
                     help="storage of the learned preconditioner's factor blocks")
     ap.add_argument("--time-scheme", default="euler", choices=["euler", "bdf2"],
                     help="implicit Euler (the paper's) or two-step backward differentiation")
@@ -231,7 +231,9 @@ def main():
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--no-baseline", action="store_true",
                     help="skip timing the plain FP64 block-Jacobi solver for comparison")
-    ap.add_argument("--inner-rtol", type=float, default=1e-3)
+    ap.add_argument("--inner-rtol", type=float, default=1e-2,
+                    help="relative tolerance of each inner solve of the mixed modes (1e-2: fewest "
+                         "CG iterations on the combined workload in a sweep over 1e-4 .. 1e-1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")

@@ -415,12 +415,17 @@ ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
  * Storage of the factor blocks: LDG_FAC_FP8 (default; W_k in BF16, O_kn in OCP
  * E4M3 FP8, round to nearest even; the entries of O_kn, blocks of a symmetric
  * positive definite matrix with identity diagonal blocks, lie in [-1, 1]),
- * LDG_FAC_BF16 (both in BF16) or LDG_FAC_F32.  P stays exactly symmetric positive definite in each, the same
- * rounded blocks forming G and G^T; the solution's accuracy is set by the
- * FP64 residual as always.  Takes effect at the next factor build (step or
+ * LDG_FAC_FP8W (both in E4M3; W_k stored as s_k W8_k with the power of two
+ * s_k = 2^round(log2(max |W_k| / 256)) per triangle, which keeps the block
+ * inside the E4M3 range), LDG_FAC_BF16 (both in BF16) or LDG_FAC_F32.  P
+ * stays exactly symmetric positive definite in each, the same rounded blocks
+ * forming G and G^T; the solution's accuracy is set by the FP64 residual as
+ * always.  Takes effect at the next factor build (step or
  * ldg_gnn_set_context).
  */
-typedef enum { LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1, LDG_FAC_FP8 = 2 } ldg_fac_storage;
+typedef enum {
+  LDG_FAC_F32 = 0, LDG_FAC_BF16 = 1, LDG_FAC_FP8 = 2, LDG_FAC_FP8W = 3
+} ldg_fac_storage;
 ldg_status ldg_gnn_factor_storage(ldg_ctx* ctx, int storage);
 ldg_status ldg_gnn_factor_export(ldg_ctx* ctx, double* blocks, float* lognorm);
 /*

@@ -545,6 +545,7 @@ ldg_status fac_alloc(ldg_ctx* c, bool training) {
     TRY(dalloc(c, &fo, 3 * per_slot));
     c->fac.w = fw;
     c->fac.o = fo;
+    TRY(dalloc(c, &c->fac.ws, (size_t)c->Kpad));
     TRY(dalloc(c, &c->fac_w64, (size_t)c->Kpad * npairs(c->N) * 2));
     TRY(dalloc(c, &c->fac_lognorm, (size_t)3 * c->Kpad));
     TRY(dalloc(c, &c->fac_om, (size_t)3 * c->Kpad));
@@ -593,7 +594,7 @@ ldg_status fac_omega(ldg_ctx* c) {
 // z = P r (factored) with <r, z> in red.result[0]
 void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z) {
   const double NN = (double)c->N * c->N;
-  const double bw = c->fac.wt == BT_F32 ? 4.0 : 2.0;
+  const double bw = c->fac.wt == BT_F32 ? 4.0 : (c->fac.wt == BT_BF16 ? 2.0 : 1.0);
   const double bo = c->fac.ot == BT_F32 ? 4.0 : (c->fac.ot == BT_BF16 ? 2.0 : 1.0);
   Timed tm(c, LDG_K_FACTOR, ((2.0 * bw + 6.0 * bo) * NN + 7.0 * L.vbytes * c->N) * c->K,
            2.0 * 8.0 * NN * c->K);
@@ -1545,9 +1546,10 @@ ldg_status ldg_gnn_set_mode(ldg_ctx* c, int mode) {
 }
 
 ldg_status ldg_gnn_factor_storage(ldg_ctx* c, int bt) {
-  if (!c || (bt != LDG_FAC_F32 && bt != LDG_FAC_BF16 && bt != LDG_FAC_FP8))
-    return fail(c, LDG_EINVAL, "factor storage is LDG_FAC_F32, LDG_FAC_BF16 or LDG_FAC_FP8");
-  c->fac.wt = bt == LDG_FAC_F32 ? BT_F32 : BT_BF16;
+  if (!c || (bt != LDG_FAC_F32 && bt != LDG_FAC_BF16 && bt != LDG_FAC_FP8 && bt != LDG_FAC_FP8W))
+    return fail(c, LDG_EINVAL,
+                "factor storage is LDG_FAC_F32, LDG_FAC_BF16, LDG_FAC_FP8 or LDG_FAC_FP8W");
+  c->fac.wt = bt == LDG_FAC_F32 ? BT_F32 : (bt == LDG_FAC_FP8W ? BT_FP8 : BT_BF16);
   c->fac.ot = bt == LDG_FAC_F32 ? BT_F32 : (bt == LDG_FAC_BF16 ? BT_BF16 : BT_FP8);
   c->g_energy_ready = false;   // blocks of the old storage are stale
   c->fac_built = false;

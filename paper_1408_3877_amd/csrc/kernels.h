@@ -122,6 +122,7 @@ struct FacStore {
   int wt = BT_BF16, ot = BT_FP8;
   void* w = nullptr;   // W: Kpad x 1 slot
   void* o = nullptr;   // O: Kpad x 3 slots
+  float* ws = nullptr; // per-triangle power-of-two scale of W when wt = BT_FP8 (W = ws W8)
 };
 // W (FP64 scratch w64 and the W store), O blocks and log ||O||_F from the FP64
 // operator blocks and block-Jacobi inverses; status |= 2 on a failed Cholesky

@@ -53,6 +53,14 @@ __device__ inline double get64(const double* __restrict__ b, int64_t k, int s, i
   return b[pidx(k, s, f >> 1, ns, NP) + (f & 1)];
 }
 
+// W stored in FP8 carries a power-of-two scale per triangle (W = s W8); the
+// other storages carry none
+template <class BW>
+__device__ inline float wscale(const float* __restrict__ ws, int64_t k) {
+  if constexpr (sizeof(BW) == 1) return ws[k];
+  else return 1.f;
+}
+
 }  // namespace
 
 // W_k = R_k^T, BJ_k^{-1} = R_k R_k^T (lower Cholesky), 16 lanes per triangle,
@@ -60,6 +68,7 @@ __device__ inline double get64(const double* __restrict__ b, int64_t k, int s, i
 template <int N, class BT>
 __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restrict__ bj,
                                                   double* __restrict__ w64, BT* __restrict__ fb,
+                                                  float* __restrict__ ws,
                                                   int* __restrict__ status) {
   constexpr int NP = npairs(N);
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,13 +94,26 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
     for (int j = c + 1; j < N; ++j) a[j] -= lic * __shfl(lic, j, 16);
   }
   if (row_ok && bad) atomicOr(status, 2);
+  // FP8 storage: scale 2^round(log2(max |W_k| / 256)) puts the block's largest
+  // entry in [181, 362], inside the E4M3 range (448)
+  double inv_s = 1.0;
+  if constexpr (sizeof(BT) == 1) {
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) m = fmax(m, (r <= i && i < N) ? fabs(a[r]) : 0.0);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 16));
+    const double sc = m > 0.0 ? exp2(rint(log2(m / 256.0))) : 1.0;
+    inv_s = 1.0 / sc;
+    if (i == 0 && k < g.Kpad) ws[k] = (float)sc;
+  }
   if (k < g.Kpad && i < N) {
 #pragma unroll
     for (int r = 0; r < N; ++r) {   // lane i holds R[i][r] = W[r][i]
       const double v = r <= i ? a[r] : 0.0;
       const int f = r * N + i;
       w64[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = v;
-      put<BT>(fb, k, 0, 1, f, N, v);
+      put<BT>(fb, k, 0, 1, f, N, v * inv_s);
     }
   }
 }
@@ -219,6 +241,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
 // y = W x
 template <int N, class T, class BW>
 __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BW* __restrict__ fw,
+                                               const float* __restrict__ ws,
                                                const T* __restrict__ x, T* __restrict__ y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
@@ -227,12 +250,18 @@ __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BW* __restric
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
   block_mv<N, BW, T>(fw, k, 0, 1, xv, acc);
+  if constexpr (sizeof(BW) == 1) {
+    const T sc = (T)wscale<BW>(ws, k);
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] *= sc;
+  }
   store_vec<N, T>(y, k, acc);
 }
 
 // y = W^T x
 template <int N, class T, class BW>
 __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restrict__ fw,
+                                                const float* __restrict__ ws,
                                                 const T* __restrict__ x, T* __restrict__ y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
@@ -241,6 +270,11 @@ __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restri
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
   block_mtv<N, BW, T>(fw, k, 0, 1, xv, acc);
+  if constexpr (sizeof(BW) == 1) {
+    const T sc = (T)wscale<BW>(ws, k);
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] *= sc;
+  }
   store_vec<N, T>(y, k, acc);
 }
 
@@ -249,6 +283,7 @@ __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restri
 // partials (optional): per-block sums of <r, out> for the preconditioned dot.
 template <int N, class T, class BW, class BO, bool NBR, bool WT>
 __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
+                                               const float* __restrict__ ws,
                                                const BO* __restrict__ fo,
                                                const float* __restrict__ om,
                                                const T* __restrict__ x, T* __restrict__ out,
@@ -279,6 +314,11 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
 #pragma unroll
       for (int i = 0; i < N; ++i) o[i] = 0;
       block_mtv<N, BW, T>(fw, k, 0, 1, acc, o);
+      if constexpr (sizeof(BW) == 1) {
+        const T sc = (T)wscale<BW>(ws, k);
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] *= sc;
+      }
       store_vec<N, T>(out, k, o);
       if (partials) {
         T rv[N];
@@ -336,6 +376,7 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BO* __restrict_
 template <class BW, class BO>
 __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, int N,
                                   int64_t Kpad, const BW* __restrict__ fw,
+                                  const float* __restrict__ ws,
                                   const BO* __restrict__ fo, const float* __restrict__ ln,
                                   double* __restrict__ out, float* __restrict__ lnout) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,7 +386,8 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
   const int s = (int)((t / NN) % FAC_SLOTS);
   const int64_t r = t / ((int64_t)NN * FAC_SLOTS);
   const int64_t k = elems ? (int64_t)elems[r] : r;
-  out[t] = s == 0 ? get_any<BW>(fw, k, 0, 1, f, N) : get_any<BO>(fo, k, s - 1, 3, f, N);
+  out[t] = s == 0 ? get_any<BW>(fw, k, 0, 1, f, N) * (double)wscale<BW>(ws, k)
+                  : get_any<BO>(fo, k, s - 1, 3, f, N);
   if (lnout && f == 0 && s < 3) lnout[r * 3 + s] = ln[s * Kpad + k];
 }
 
@@ -362,9 +404,13 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
     default: break;                                             \
   }
 
-// W storage BW and O storage BO: (F32, F32), (BF16, BF16), (BF16, FP8)
+// W storage BW and O storage BO: (F32, F32), (BF16, BF16), (BF16, FP8), (FP8, FP8)
 #define LDG_SWITCH_FAC(FS, CALL)                                \
-  if ((FS).ot == BT_FP8) {                                      \
+  if ((FS).wt == BT_FP8) {                                      \
+    using BW = fp8;                                             \
+    using BO = fp8;                                             \
+    CALL;                                                       \
+  } else if ((FS).ot == BT_FP8) {                               \
     using BW = bf16;                                            \
     using BO = fp8;                                             \
     CALL;                                                       \
@@ -383,7 +429,7 @@ void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* ref
                       float* lognorm, int* status, hipStream_t st) {
   LDG_SWITCH_FAC(fs, {
     LDG_SWITCH_N(N, (k_fac_chol<NT, BW><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
-                        g, bj, w64, (BW*)fs.w, status)));
+                        g, bj, w64, (BW*)fs.w, fs.ws, status)));
     LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO><<<nbk(g.Kpad, 4), 64, 0, st>>>(
                         g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm)));
   })
@@ -399,18 +445,18 @@ void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const flo
     const BO* fo = (const BO*)fs.o;
     if (vt == VT_F64) {
       using T = double;
-      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, fs.ws, (const T*)r, (T*)y)));
       LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, false, false><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
+                          g, fw, fs.ws, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
       LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, true, true><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
+                          g, fw, fs.ws, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
     } else {
       using T = float;
-      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, (const T*)r, (T*)y)));
+      LDG_SWITCH_N(N, (k_fac_w<NT, T, BW><<<nb, 256, 0, st>>>(g.Kpad, fw, fs.ws, (const T*)r, (T*)y)));
       LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, false, false><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
+                          g, fw, fs.ws, fo, om, (const T*)y, (T*)a, nullptr, nullptr)));
       LDG_SWITCH_N(N, (k_fac_f<NT, T, BW, BO, true, true><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
+                          g, fw, fs.ws, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
     }
   })
   if (red) reduce_partials((int)nb, red->partials, red->result, st);
@@ -419,13 +465,13 @@ void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const flo
 void launch_fac_w(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                   hipStream_t st) {
   LDG_SWITCH_FAC(fs, LDG_SWITCH_N(N, (k_fac_w<NT, double, BW><<<nbk(g.Kpad, 256), 256, 0, st>>>(
-                                         g.Kpad, (const BW*)fs.w, x, y))))
+                                         g.Kpad, (const BW*)fs.w, fs.ws, x, y))))
 }
 
 void launch_fac_wt(int N, const FacStore& fs, const Geo& g, const double* x, double* y,
                    hipStream_t st) {
   LDG_SWITCH_FAC(fs, LDG_SWITCH_N(N, (k_fac_wt<NT, double, BW><<<nbk(g.Kpad, 256), 256, 0, st>>>(
-                                         g.Kpad, (const BW*)fs.w, x, y))))
+                                         g.Kpad, (const BW*)fs.w, fs.ws, x, y))))
 }
 
 void launch_fac_f(int N, const FacStore& fs, const Geo& g, const float* om, bool transpose_and_wt,
@@ -436,10 +482,10 @@ void launch_fac_f(int N, const FacStore& fs, const Geo& g, const float* om, bool
     const BO* fo = (const BO*)fs.o;
     if (transpose_and_wt) {
       LDG_SWITCH_N(N, (k_fac_f<NT, double, BW, BO, true, true><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, x, out, nullptr, nullptr)));
+                          g, fw, fs.ws, fo, om, x, out, nullptr, nullptr)));
     } else {
       LDG_SWITCH_N(N, (k_fac_f<NT, double, BW, BO, false, false><<<nb, 256, 0, st>>>(
-                          g, fw, fo, om, x, out, nullptr, nullptr)));
+                          g, fw, fs.ws, fo, om, x, out, nullptr, nullptr)));
     }
   })
 }
@@ -454,7 +500,7 @@ void launch_fac_domega(int N, const FacStore& fs, const Geo& g, const double* a,
 void launch_fac_export(int64_t K, int N, const FacStore& fs, double* out, hipStream_t st) {
   const unsigned nb = nbk(K * FAC_SLOTS * N * N, 256);
   LDG_SWITCH_FAC(fs, (k_fac_export_rows<BW, BO><<<nb, 256, 0, st>>>(
-                         K, nullptr, N, 0, (const BW*)fs.w, (const BO*)fs.o, nullptr, out,
+                         K, nullptr, N, 0, (const BW*)fs.w, fs.ws, (const BO*)fs.o, nullptr, out,
                          nullptr)))
 }
 
@@ -463,7 +509,7 @@ void launch_fac_export_rows(int64_t n, const int32_t* elems, int N, const FacSto
                             hipStream_t st) {
   const unsigned nb = nbk(n * FAC_SLOTS * N * N, 256);
   LDG_SWITCH_FAC(fs, (k_fac_export_rows<BW, BO><<<nb, 256, 0, st>>>(
-                         n, elems, N, Kpad, (const BW*)fs.w, (const BO*)fs.o, lognorm, out,
+                         n, elems, N, Kpad, (const BW*)fs.w, fs.ws, (const BO*)fs.o, lognorm, out,
                          lnout)))
 }
 

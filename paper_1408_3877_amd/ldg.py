@@ -375,8 +375,10 @@ class Solver:
         self._check(self.lib.ldg_gnn_set_mode(self.h, int(m)))
 
     def gnn_factor_storage(self, kind):
-        """"f32", "bf16" or "fp8" (default: W in BF16, O in FP8) storage of the factor blocks."""
-        self._check(self.lib.ldg_gnn_factor_storage(self.h, {"f32": 0, "bf16": 1, "fp8": 2}[kind]))
+        """"f32", "bf16", "fp8" (default: W in BF16, O in FP8) or "fp8w" (both in FP8, W with a
+        power-of-two scale per triangle) storage of the factor blocks."""
+        self._check(self.lib.ldg_gnn_factor_storage(
+            self.h, {"f32": 0, "bf16": 1, "fp8": 2, "fp8w": 3}[kind]))
 
     def gnn_factor_omega(self):
         om = self.torch.empty((self.K, 3), dtype=self.torch.float32, device=self.device)

@@ -94,6 +94,28 @@ def test_factor_fp8_storage_rounds_the_blocks():
     assert np.all(np.abs(got - O) <= bo), np.max(np.abs(got - O) / bo)
 
 
+def test_factor_fp8w_storage_rounds_the_scaled_blocks():
+    g, D, dt, sy, s = _setup(8, 4, 707, storage="fp8w")
+    s.gnn_set_params(_theta(sy.N, 707))
+    s.gnn_set_context(D, dt)
+    blk = to_np(s.gnn_factor_export()[0])
+    m = sy.mask
+    Wk, O = sy.Wk, sy.O[m]
+    # W_k = s_k W8_k, s_k = 2^round(log2(max |W_k| / 256)): E4M3 keeps 4 bits for
+    # |W8| >= 2^-6 and spacing 2^-9 below, i.e. |error| <= max(2^-4 |W|, 2^-10 s_k);
+    # s_k is taken one binade up to cover a rounding tie of the exponent
+    sk = 2.0 ** (np.round(np.log2(np.abs(Wk).max(axis=(1, 2)) / 256.0)) + 1)
+    bw = np.maximum(2.0 ** -4 * (1 + 2.0 ** -20) * np.abs(Wk), 2.0 ** -10 * sk[:, None, None]) + 1e-300
+    assert np.all(np.abs(blk[:, 0] - Wk) <= bw), np.max(np.abs(blk[:, 0] - Wk) / bw)
+    # the largest entry of each block is within 2^-4 of itself (normal range)
+    big = np.abs(Wk).reshape(len(Wk), -1).argmax(axis=1)
+    wb = Wk.reshape(len(Wk), -1)[np.arange(len(Wk)), big]
+    gb = blk[:, 0].reshape(len(Wk), -1)[np.arange(len(Wk)), big]
+    assert np.all(np.abs(gb - wb) <= 2.0 ** -4 * np.abs(wb))
+    bo = np.maximum(2.0 ** -4 * (1 + 2.0 ** -20) * np.abs(O), 2.0 ** -10) + 1e-12
+    assert np.all(np.abs(blk[:, 1:][m] - O) <= bo)
+
+
 @pytest.mark.parametrize("n,p,seed", [(7, 2, 711), (4, 3, 712)])
 def test_factor_energy_loss_and_gradient(n, p, seed):
     g, D, dt, sy, s = _setup(n, p, seed)
@@ -144,7 +166,7 @@ def _steps(s, w, pr, C, dt, nsteps):
     return out
 
 
-@pytest.mark.parametrize("weights", ["init", "nan", "init-bf16", "init-fp8"])
+@pytest.mark.parametrize("weights", ["init", "nan", "init-bf16", "init-fp8", "init-fp8w"])
 def test_factor_preconditioner_steps(weights):
     from paper_1408_3877_amd import Solver
     n, p, dt = 12, 2, 0.02
