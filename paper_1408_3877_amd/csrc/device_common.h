@@ -73,6 +73,14 @@ __host__ __device__ inline int64_t bgidx(int64_t k, int s, int g, int ns, int ng
 }
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs; NaN kept quiet)
+// Tile of workgroup b out of nb.  Consecutive workgroups go to the 8 XCDs in
+// turn, each with its own L2; giving each XCD a contiguous range of tiles keeps
+// the neighbours a tile gathers in the L2 that read them as its own.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 __device__ inline bf16 to_bf16(float x) {
   uint32_t u = __float_as_uint(x);
   if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (bf16)0x7fc0;

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
                                               T* __restrict__ Z2) {
   __shared__ __align__(16) T sm[ref_size<N, T>()];
   load_refs<N, T>(sm, refs);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
   T a1[N], a2[N];
 #pragma unroll
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
   __shared__ __align__(16) T sm[ref_size<N, T>()];
   __shared__ double red[4];
   load_refs<N, T>(sm, refs);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (k < g.Kpad) s = div_row<N, T, BT, BLOCKS>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
   if (partials == nullptr) return;
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) k_bj_apply(Geo g, const BT* __restrict__ 
                                                   const T* __restrict__ r, T* __restrict__ z,
                                                   double* __restrict__ partials) {
   __shared__ double red[4];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (k < g.Kpad) {
     T x[N], acc[N];

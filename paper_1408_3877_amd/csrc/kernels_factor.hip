@@ -243,7 +243,7 @@ template <int N, class T, class BW>
 __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BW* __restrict__ fw,
                                                const float* __restrict__ ws,
                                                const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
   T xv[N], acc[N];
   load_vec<N, T>(x, k, xv);
@@ -263,7 +263,7 @@ template <int N, class T, class BW>
 __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restrict__ fw,
                                                 const float* __restrict__ ws,
                                                 const T* __restrict__ x, T* __restrict__ y) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
   T xv[N], acc[N];
   load_vec<N, T>(x, k, xv);
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
                                                const T* __restrict__ r,
                                                double* __restrict__ partials) {
   __shared__ double red[4];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t Kp = g.Kpad;
   double s = 0.0;
   if (k < Kp) {
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BO* __restrict_
                                                     const double* __restrict__ alpha,
                                                     const double* __restrict__ y,
                                                     float* __restrict__ dom) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t Kp = g.Kpad;
   if (k >= Kp) return;
   double ak[N], alk[N];

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_mf_blocks(Geo g, const double* __restri
   __shared__ int sb[2][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, q = lane >> 4;
-  const int64_t k = (int64_t)blockIdx.x * 64 + wave * 16 + col;
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * 64 + wave * 16 + col;
   const bool valid = k < g.K;
   const int64_t Kp = g.Kpad;
   Acc acc = zero_acc<Acc>();
