@@ -6,11 +6,15 @@
  * eq:diffusion:nonmixed) in the mixed form z = -grad c (Sec. 2.2), modal
  * orthonormal bases of order p = 0..4 (Sec. 2.4.1), the global block system
  * eq:timeDepSystem and one implicit Euler step per call (eq:fullSystem):
- *     (W + dt A(t+dt)) Y = W Y^n + dt V(t+dt),   Y = [Z1; Z2; C].
- * The linear system of each step is solved by right-preconditioned restarted
- * GMRES on the system for C obtained by eliminating Z (M is block diagonal,
- * M_k = 2|T_k| I, eq:hatM), stopping on the relative residual of the full
- * 3KN system.
+ *     (W + dt A(t+dt)) Y = W Y^n + dt V(t+dt),   Y = [Z1; Z2; C],
+ * or a two-step backward differentiation step, or the stationary system
+ * A Y = V of Sec. 3.7.  The linear system is solved on the system for C
+ * obtained by eliminating Z (M is block diagonal, M_k = 2|T_k| I, eq:hatM):
+ * preconditioned CG where that system is symmetric positive definite,
+ * right-preconditioned restarted GMRES otherwise, with block-Jacobi or a
+ * learned graph-network preconditioner, in FP64 or in FP32/BF16 with FP64
+ * iterative refinement, stopping on the relative residual of the full 3KN
+ * system.
  *
  * Conventions
  *   - Element k, basis index i (0-based): vectors are "element-major",
