@@ -352,20 +352,25 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BO* __restrict_
   double ak[N], alk[N];
   load_vec<N, double>(a, k, ak);
   load_vec<N, double>(alpha, k, alk);
-#pragma unroll
+#pragma unroll 1   // one edge at a time keeps the gathers' registers short-lived
   for (int n = 0; n < 3; ++n) {
     const int64_t j = k < g.K ? g.nbr[n * Kp + k] : -1;
     double s = 0.0;
     if (j >= 0) {
-      double bj[N], yj[N], u1[N], u2[N];
-      load_vec<N, double>(beta, j, bj);
-      load_vec<N, double>(y, j, yj);
+      // a_k^T (O beta_j), then alpha_k^T (O y_j), through one gather buffer
+      double v[N], u[N];
+      load_vec<N, double>(beta, j, v);
 #pragma unroll
-      for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0.0;
-      block_mv<N, BO, double>(fo, k, n, 3, bj, u1);
-      block_mv<N, BO, double>(fo, k, n, 3, yj, u2);
+      for (int i = 0; i < N; ++i) u[i] = 0.0;
+      block_mv<N, BO, double>(fo, k, n, 3, v, u);
 #pragma unroll
-      for (int i = 0; i < N; ++i) s += ak[i] * u1[i] + alk[i] * u2[i];
+      for (int i = 0; i < N; ++i) s += ak[i] * u[i];
+      load_vec<N, double>(y, j, v);
+#pragma unroll
+      for (int i = 0; i < N; ++i) u[i] = 0.0;
+      block_mv<N, BO, double>(fo, k, n, 3, v, u);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += alk[i] * u[i];
     }
     dom[n * Kp + k] = (float)(-s);
   }
