@@ -1,0 +1,85 @@
+"""The solver options together, against the oracle.
+
+Each option has its own tests; here they are combined on one mesh: the time
+scheme (implicit Euler, BDF2) or the stationary system, the precision (FP64,
+FP32 or BF16 inner solves with FP64 refinement), the preconditioner
+(block-Jacobi, the learned factored one) and the matrix-free apply.  Every
+result must match the oracle's sparse direct solve to 1e-10 relative L2.
+"""
+import numpy as np
+import pytest
+
+from inputs.fields import LOGNORMAL, SMOOTH1, Workload, lognormal_blocks
+from inputs.meshes import NORTH, WEST, square_mesh
+from oracle import gnn_factor as gf
+from oracle.ldg import Problem
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+N_CELLS, SEED = 10, 901
+
+
+def _setup(p, wk, precision, precond, mf):
+    from paper_1408_3877_amd import Solver
+    cV, V0T, kind = square_mesh(N_CELLS, seed=SEED, neumann_sides=(NORTH, WEST))
+    w = (Workload(LOGNORMAL, n_cells=N_CELLS, blocks=lognormal_blocks(N_CELLS, SEED, 1.0, block=2),
+                  block=2) if wk == LOGNORMAL else Workload(wk))
+    pr = Problem(cV, V0T, kind, p)
+    s = Solver(cV, V0T, kind, p, rtol=1e-13, restart=60, max_iters=50000, precision=precision,
+               precond=precond)
+    if precond:
+        s.gnn_set_mode("factor")
+        s.gnn_set_params(gf.init_params(s.N, SEED).astype(np.float32))
+    s.set_matrix_free(mf)
+    return s, pr, w
+
+
+# (p, workload, precision, learned, matrix-free)
+TIME_CASES = [
+    (2, LOGNORMAL, 2, 1, True),
+    (3, LOGNORMAL, 1, 0, True),
+    (4, LOGNORMAL, 2, 1, False),
+    (2, SMOOTH1, 1, 0, True),
+    (3, SMOOTH1, 2, 1, True),   # nonsymmetric: the learned preconditioner falls back
+]
+
+
+@pytest.mark.parametrize("p,wk,precision,learned,mf", TIME_CASES)
+def test_bdf2_with_the_other_options(p, wk, precision, learned, mf):
+    s, pr, w = _setup(p, wk, precision, learned, mf)
+    s.set_time_scheme("bdf2")
+    dT = w.dT
+    s.set_initial_samples(s.sample_workload(wk, 0.0, dT=dT, want=("c0",))["c0"], 0.0)
+    C, Cm, t, dt = pr.initial(w), None, 0.0, 0.015
+    for i in range(3):
+        t += dt
+        smp = s.sample_workload(wk, t, dT=dT)
+        info = s.step_sampled(dt, smp["d"], smp["f"], smp["cD"], smp["gN"])
+        print("[combo] p=%d wk=%d prec=%d learned=%d mf=%s step %d: %s"
+              % (p, wk, precision, learned, mf, i, info), flush=True)
+        assert info["bdf_order"] == (1 if i == 0 else 2) and info["rel_residual"] <= 1e-13
+        if learned and wk == SMOOTH1:
+            assert info["fallback_reason"] == 5 and info["learned_iters"] == 0
+        elif learned:
+            assert info["learned_iters"] == info["iters"]
+        Cn = pr.step(C, t, dt, w)[0] if i == 0 else pr.step_bdf2(C, Cm, t, dt, w)[0]
+        Cm, C = C, Cn
+        assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
+
+
+@pytest.mark.parametrize("p,precision,learned,mf", [(2, 2, 1, True), (3, 1, 0, True),
+                                                    (3, 2, 1, False)])
+def test_stationary_with_the_other_options(p, precision, learned, mf):
+    # the stationary system (no mass term) with the learned preconditioner built
+    # for it, the mixed inner solves and the matrix-free apply
+    s, pr, w = _setup(p, LOGNORMAL, precision, learned, mf)
+    C, Z1, Z2 = pr.solve_stationary(w)
+    smp = s.sample_workload(LOGNORMAL, 0.0, dT=w.dT)
+    info = s.solve_stationary_sampled(smp["d"], smp["f"], smp["cD"], smp["gN"])
+    print("[combo-stat] p=%d prec=%d learned=%d mf=%s: %s" % (p, precision, learned, mf, info),
+          flush=True)
+    assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
+    a = pr.grid.areaT
+    Cg, Z1g, Z2g = (to_np(x) for x in s.get_solution())
+    assert rel_l2(a, Cg, C) < 1e-10 and rel_l2(a, Z1g, Z1) < 1e-10 and rel_l2(a, Z2g, Z2) < 1e-10
