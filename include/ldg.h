@@ -396,10 +396,17 @@ ldg_status ldg_gnn_get_params(ldg_ctx* ctx, float* w, int64_t n);
  * block-Jacobi step; it needs ldg_gnn_set_context after this call, which then
  * also assembles the FP64 blocks of D (overwriting the solver's) and returns
  * LDG_EINVAL unless D is constant on every triangle (S symmetric, the case
- * the learned preconditioner serves).  Unknown values: LDG_EINVAL.
+ * the learned preconditioner serves).  LDG_GNN_LOSS_OPTSTEP (factored network
+ * only): the energy left after one preconditioned step with the best step
+ * length, min_t ||e - t P r||_S^2 / ||e||_S^2 = 1 - (r^T P r)^2 /
+ * ((P r)^T S (P r) e^T r) with r = S e, e = target + rhat; it does not change
+ * when e or P is scaled (as CG's iterates do not), and on smooth errors (the
+ * late errors of the method's own CG solves) its minimum sits where CG's
+ * iteration count has its own.  Unknown values: LDG_EINVAL.
  */
 typedef enum {
-  LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1, LDG_GNN_LOSS_FROBENIUS = 2
+  LDG_GNN_LOSS_MSE = 0, LDG_GNN_LOSS_ENERGY = 1, LDG_GNN_LOSS_FROBENIUS = 2,
+  LDG_GNN_LOSS_OPTSTEP = 3
 } ldg_gnn_loss;
 ldg_status ldg_gnn_set_loss(ldg_ctx* ctx, int loss);
 /* per-triangle and per-edge features from D (device K x N, NULL: last projected) and dt */

@@ -158,23 +158,18 @@ def energy_loss(theta, grid, node, edge, sysm, rhat, target):
     return (d @ (sysm.S @ d)) / (d0 @ (sysm.S @ d0))
 
 
-def energy_loss_grad(theta, grid, node, edge, sysm, rhat, target):
-    """(loss, d loss / d theta) by the chain rule."""
+def _grad_through_z(theta, grid, node, edge, sysm, r, loss_of_z):
+    """(loss, d loss / d theta) for a loss of z = P r: loss_of_z(z) gives (loss,
+    d loss / dz); the chain rule runs through z = W^T (I + F)^T a, a = (I + F) y,
+    y = W r."""
     N = sysm.N
     om, (P, h, acts, sig) = omega(theta, grid, node, edge, sysm, keep=True)
-    S = sysm.S
-    e = (target + rhat).reshape(-1)
-    r = S @ e
     Fm = sysm.F(om)
     I = sp.eye(sysm.K * N)
     y = sysm.Wg @ r
     a = (I + Fm) @ y
     z = sysm.Wg.T @ ((I + Fm).T @ a)
-    d = z - e
-    d0 = sysm.BJg @ r - e
-    den = d0 @ (S @ d0)
-    L = (d @ (S @ d)) / den
-    v = 2.0 * (S @ d) / den                    # dL/dz
+    L, v = loss_of_z(z)                        # v = dL/dz
     beta = sysm.Wg @ v                         # dL/db,  b = (I + F)^T a
     alpha = beta + Fm @ beta                   # dL/da
     # dL/dF_kj = a_k beta_j^T + alpha_k y_j^T ;  dL/domega_kn = -<dL/dF_kj, O_kn>
@@ -189,23 +184,48 @@ def energy_loss_grad(theta, grid, node, edge, sysm, rhat, target):
         Ob = sysm.O[:, n]
         dom[:, n] = -(np.einsum("ki,kij,kj->k", A_, Ob, B_[j])
                       + np.einsum("ki,kij,kj->k", Al, Ob, Y[j]))
-    dom = np.where(sysm.mask, dom, 0.0)
-    da = dom * OMEGA_MAX * sig * (1.0 - sig)   # d loss / d head pre-activation
-    G = {k: np.zeros_like(v_) for k, v_ in P.items()}
-    dh = np.zeros_like(h)
-    for n in range(3):
-        m = sysm.mask[:, n]
-        j = sysm.kp[m, n]
-        dn = da[m, n]
-        G["w_hk"] = G["w_hk"] + h[m].T @ dn
-        G["w_hj"] = G["w_hj"] + h[j].T @ dn
-        G["w_e"] = G["w_e"] + edge[m, n].T @ dn
-        G["w_o"] = G["w_o"] + sysm.lognorm[m, n] @ dn
-        G["b_o"] = G["b_o"] + dn.sum()
-        dh[m] += dn[:, None] * P["w_hk"][None, :]
-        np.add.at(dh, j, dn[:, None] * P["w_hj"][None, :])
-    gnn.trunk_backward(P, grid, edge, acts, dh, G)
-    return L, gnn.pack(G, N, param_shapes(N))
+    return L, _head_backward(theta, grid, edge, sysm, P, h, acts, sig, dom)
+
+
+def energy_loss_grad(theta, grid, node, edge, sysm, rhat, target):
+    """(loss, d loss / d theta) by the chain rule."""
+    S = sysm.S
+    e = (target + rhat).reshape(-1)
+    r = S @ e
+    d0 = sysm.BJg @ r - e
+    den = d0 @ (S @ d0)
+
+    def f(z):
+        d = z - e
+        Sd = S @ d
+        return (d @ Sd) / den, 2.0 * Sd / den
+    return _grad_through_z(theta, grid, node, edge, sysm, r, f)
+
+
+def optstep_loss(theta, grid, node, edge, sysm, rhat, target):
+    """Energy left after one preconditioned step with the best step length,
+    relative to the error's energy:  min_t ||e - t P r||_S^2 / ||e||_S^2
+    = 1 - (r^T P r)^2 / ((P r)^T S (P r) e^T r),  r = S e, e = target + rhat.
+    Scaling e or P leaves it unchanged, as it leaves CG's iterates."""
+    e = (target + rhat).reshape(-1)
+    r = sysm.S @ e
+    z = sysm.P(omega(theta, grid, node, edge, sysm)) @ r
+    return 1.0 - (r @ z) ** 2 / ((z @ (sysm.S @ z)) * (e @ r))
+
+
+def optstep_loss_grad(theta, grid, node, edge, sysm, rhat, target):
+    """(loss, d loss / d theta): with s = r^T z, q = z^T S z, c = e^T r,
+    d loss / dz = -2 s / (q c) r + 2 s^2 / (q^2 c) S z."""
+    S = sysm.S
+    e = (target + rhat).reshape(-1)
+    r = S @ e
+    c = e @ r
+
+    def f(z):
+        Sz = S @ z
+        s_, q = r @ z, z @ Sz
+        return 1.0 - s_ * s_ / (q * c), -2.0 * s_ / (q * c) * r + 2.0 * s_ * s_ / (q * q * c) * Sz
+    return _grad_through_z(theta, grid, node, edge, sysm, r, f)
 
 
 def _head_backward(theta, grid, edge, sysm, P, h, acts, sig, dom):

@@ -1597,8 +1597,10 @@ ldg_status ldg_gnn_factor_export_rows(ldg_ctx* c, const int32_t* elems, int64_t 
 
 ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
   if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY &&
-             loss != LDG_GNN_LOSS_FROBENIUS))
+             loss != LDG_GNN_LOSS_FROBENIUS && loss != LDG_GNN_LOSS_OPTSTEP))
     return fail(c, LDG_EINVAL, "unknown loss");
+  if (loss == LDG_GNN_LOSS_OPTSTEP && c->gmode != LDG_GNN_FACTOR)
+    return fail(c, LDG_EINVAL, "the optimal-step loss is defined for the factored network");
   c->gloss = loss;
   c->g_energy_ready = false;
   return LDG_OK;
@@ -1687,6 +1689,49 @@ ldg_status gnn_factor_loss_grad(ldg_ctx* c, double* loss) {
   return check_launch(c);
 }
 
+// Factored preconditioner, optimal-step loss of a pair (rhat, target), e = target + rhat:
+//   loss = min_t ||e - t P r||_S^2 / ||e||_S^2 = 1 - s^2 / (q c),
+//   r = S e, z = P r, s = <r, z>, q = <z, S z>, c = <e, r>;
+//   d loss / dz = -2 s / (q c) r + 2 s^2 / (q^2 c) S z, then the chain of the energy loss.
+ldg_status gnn_factor_optstep_grad(ldg_ctx* c, double* loss) {
+  if (!c->g_energy_ready) return fail(c, LDG_EINVAL, "no context set");
+  TRY(fac_alloc(c, true));
+  const Level L = level64(c);
+  const int64_t n = c->nvec;
+  const int N = c->N;
+  double** v = c->fac_v;
+  double* hb = c->host_buf;
+  launch_fac_omega(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT, c->fac_om, c->st);
+  launch_cast(VT_F32, VT_F64, n, 1.0, c->g_tgt, v[0], c->st);
+  launch_axpy_into64(VT_F32, n, 1.0, c->g_rhat, v[0], c->st);            // e
+  apply_op(c, L, c->gtau, v[0], false, L.tz1, L.tz2, v[1]);               // r = S e
+  launch_fac_w(N, c->fac, c->geo, v[1], v[2], c->st);                 // y
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, false, v[2], v[3], c->st);  // a
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, true, v[3], v[4], c->st);   // z = P r
+  apply_op(c, L, c->gtau, v[4], false, L.tz1, L.tz2, v[5]);               // S z
+  double sv = 0.0, q = 0.0, cv = 0.0;
+  kdots(c, L, 1, v[1], v[4]);
+  TRY(fetch(c, c->red.result, 1, hb));
+  sv = hb[0];
+  kdots(c, L, 1, v[4], v[5]);
+  TRY(fetch(c, c->red.result, 1, hb));
+  q = hb[0];
+  kdots(c, L, 1, v[0], v[1]);
+  TRY(fetch(c, c->red.result, 1, hb));
+  cv = hb[0];
+  if (!(q > 0.0) || !(cv > 0.0) || !std::isfinite(sv))
+    return fail(c, LDG_ENOCONV, "optimal-step loss: an error or direction without positive energy");
+  launch_axpby(VT_F64, n, -2.0 * sv / (q * cv), v[1], 0.0, v[4], c->st);  // dL/dz
+  launch_axpby(VT_F64, n, 2.0 * sv * sv / (q * q * cv), v[5], 1.0, v[4], c->st);
+  launch_fac_w(N, c->fac, c->geo, v[4], v[6], c->st);                 // beta
+  launch_fac_f(N, c->fac, c->geo, c->fac_om, false, v[6], v[7], c->st);  // alpha
+  launch_fac_domega(N, c->fac, c->geo, v[3], v[6], v[7], v[2], c->fac_dom, c->st);
+  launch_fac_omega_backward(N, c->geo, c->gP, c->gnode, c->gedge, c->fac_lognorm, c->gT,
+                            c->fac_om, c->fac_dom, c->gS, c->gGrad, c->st);
+  *loss = 1.0 - sv * sv / (q * cv);
+  return check_launch(c);
+}
+
 // Factored preconditioner, Frobenius loss for a probe w (the rhat input):
 //   loss = ||(G S G^T - I) w||^2 / ||(W S W^T - I) w||^2,  G = (I + F) W;
 // with u = G^T w, y = W S u, g = 2 ((I + F) y - w) / den and
@@ -1729,9 +1774,11 @@ ldg_status gnn_factor_frob_grad(ldg_ctx* c, double* loss) {
 }
 
 ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
-  if (c->gmode == LDG_GNN_FACTOR)
-    return c->gloss == LDG_GNN_LOSS_FROBENIUS ? gnn_factor_frob_grad(c, loss)
-                                              : gnn_factor_loss_grad(c, loss);
+  if (c->gmode == LDG_GNN_FACTOR) {
+    if (c->gloss == LDG_GNN_LOSS_FROBENIUS) return gnn_factor_frob_grad(c, loss);
+    if (c->gloss == LDG_GNN_LOSS_OPTSTEP) return gnn_factor_optstep_grad(c, loss);
+    return gnn_factor_loss_grad(c, loss);
+  }
   Timed tm(c, LDG_K_GNN, 0.0, 0.0);
   launch_gnn_forward(c->N, c->geo, c->gP, c->gnode, c->gedge, c->g_rhat, c->gT, c->g_out, c->st);
   if (c->gloss == LDG_GNN_LOSS_ENERGY) {

@@ -403,8 +403,9 @@ class Solver:
     def gnn_set_loss(self, kind):
         """0 / "mse": mean squared error; 1 / "energy": energy norm relative to the
         block-Jacobi step's; 2 / "frobenius": probe estimate of ||G S G^T - I||_F^2
-        (factored mode; the probe is passed as rhat)."""
-        k = {"mse": 0, "energy": 1, "frobenius": 2}.get(kind, kind)
+        (factored mode; the probe is passed as rhat); 3 / "optstep": energy left
+        after one preconditioned step with the best step length (factored mode)."""
+        k = {"mse": 0, "energy": 1, "frobenius": 2, "optstep": 3}.get(kind, kind)
         self._check(self.lib.ldg_gnn_set_loss(self.h, int(k)))
 
     def gnn_set_context(self, D, dt):

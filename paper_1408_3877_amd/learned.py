@@ -40,6 +40,8 @@ from inputs.fields import LOGNORMAL, LOGNORMAL_T, lognormal_blocks, triangle_val
 from inputs.meshes import square_mesh  # noqa: E402
 
 SNAPS = [0, 1, 2, 3, 5, 8, 12, 18, 27, 40, 60, 90, 135, 200, 300, 450, 675, 1000, 1500, 2250]
+# the optimal-step loss learns from the smooth late errors, which decide CG's iteration count
+SNAPS_LATE = [90, 135, 200, 300, 450, 675, 1000, 1500]
 
 
 def log(*a):
@@ -226,7 +228,7 @@ def main(argv=None):
                     help="collection rounds (1: block-Jacobi solves only)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=7)
-    ap.add_argument("--loss", choices=("frobenius", "energy", "mse"), default=None,
+    ap.add_argument("--loss", choices=("frobenius", "energy", "mse", "optstep"), default=None,
                     help="default: frobenius (factor mode), energy (correction mode)")
     ap.add_argument("--probes", type=int, default=8, help="probe vectors per system visit")
     ap.add_argument("--mode", choices=("correction", "factor"), default="factor",
@@ -234,13 +236,18 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="skip collection and training, evaluate these")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--snaps", default=None,
+                    help="CG iterations whose errors are collected (comma list; default: every "
+                         "stage, late ones only for the optimal-step loss)")
     a = ap.parse_args(argv)
     global KIND
     KIND = a.kind
     if a.loss is None:
         a.loss = "frobenius" if a.mode == "factor" else "energy"
-    if a.loss == "frobenius" and a.mode != "factor":
-        ap.error("the Frobenius loss belongs to the factored preconditioner")
+    if a.loss in ("frobenius", "optstep") and a.mode != "factor":
+        ap.error("the %s loss belongs to the factored preconditioner" % a.loss)
+    snaps = ([int(x) for x in a.snaps.split(",")] if a.snaps else
+             (SNAPS_LATE if a.loss == "optstep" else SNAPS))
     import torch
 
     from . import Solver
@@ -282,7 +289,7 @@ def main(argv=None):
                 sl.gnn_set_params(w)
                 src = sl
             t0 = time.perf_counter()
-            data += collect(src, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
+            data += collect(src, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt, snaps=snaps)
             t_collect += time.perf_counter() - t0
             sv.gnn_set_params(w)
             sv.gnn_set_loss(a.loss)
@@ -307,7 +314,7 @@ def main(argv=None):
                 pw = rng.standard_normal((sv.K, sv.N)).astype(np.float32)
                 hl.append(sv.gnn_loss_grad(pw, pw)[0])
     else:
-        held = collect(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt)
+        held = collect(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt, snaps=snaps)
         for r, tg, D in held:
             sv.gnn_set_context(D, a.dt)
             hl.append(sv.gnn_loss_grad(r, tg)[0])

@@ -136,6 +136,27 @@ def test_factor_energy_loss_and_gradient(n, p, seed):
     assert np.linalg.norm(Gg - G) <= 2e-3 * np.linalg.norm(G)
 
 
+@pytest.mark.parametrize("n,p,seed", [(7, 2, 751), (5, 4, 752)])
+def test_factor_optstep_loss_and_gradient(n, p, seed):
+    g, D, dt, sy, s = _setup(n, p, seed)
+    N = sy.N
+    th = _theta(N, seed)
+    s.gnn_set_params(th)
+    s.gnn_set_loss("optstep")
+    s.gnn_set_context(D, dt)
+    rng = np.random.default_rng(seed)
+    rhat = rng.standard_normal((sy.K, N)).astype(np.float32)
+    tgt = rng.standard_normal((sy.K, N)).astype(np.float32)
+    node, edge = gnn.features(g, D, dt, 1.0)
+    L, G = gf.optstep_loss_grad(th.astype(np.float64), g, node, edge, sy, rhat.astype(np.float64),
+                                tgt.astype(np.float64))
+    Lg, Gg = s.gnn_loss_grad(rhat, tgt)
+    Gg = to_np(Gg)
+    print("[factor] optstep gpu %.8f oracle %.8f" % (Lg, L), flush=True)
+    assert abs(Lg - L) <= 1e-4 * L
+    assert np.linalg.norm(Gg - G) <= 2e-3 * np.linalg.norm(G)
+
+
 @pytest.mark.parametrize("n,p,seed", [(7, 2, 741), (4, 4, 742)])
 def test_factor_frobenius_loss_and_gradient(n, p, seed):
     g, D, dt, sy, s = _setup(n, p, seed)

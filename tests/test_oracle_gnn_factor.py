@@ -185,3 +185,63 @@ def test_frobenius_loss_is_the_fsai_functional_in_expectation():
     r = Gm @ (Sd @ (Gm.T @ w.reshape(-1))) - w.reshape(-1)
     r0 = W @ (Sd @ (W.T @ w.reshape(-1))) - w.reshape(-1)
     assert abs(gf.frobenius_loss(theta, g, node, edge, sy, w) - (r @ r) / (r0 @ r0)) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_optstep_loss_gradient_matches_finite_differences(p):
+    g, D, dt, sy = _system(4, p, 40 + p)
+    N = sy.N
+    node, edge = gnn.features(g, D, dt, 1.0)
+    rng = np.random.default_rng(15 + p)
+    theta = gf.init_params(N, 7) + 0.05 * rng.standard_normal(gf.n_params(N))
+    rhat = rng.standard_normal((sy.K, N))
+    target = rng.standard_normal((sy.K, N))
+    L, G = gf.optstep_loss_grad(theta, g, node, edge, sy, rhat, target)
+    assert abs(L - gf.optstep_loss(theta, g, node, edge, sy, rhat, target)) <= 1e-12
+    n_head = sum(int(np.prod(s)) for _, s in gf.HEAD)
+    idx = np.concatenate([np.arange(gf.n_params(N) - n_head, gf.n_params(N)),
+                          rng.choice(gf.n_params(N) - n_head, 150, replace=False)])
+    eps = 1e-6
+    worst = 0.0
+    floor = 1e-3 * np.abs(G).max()
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd = (gf.optstep_loss(tp, g, node, edge, sy, rhat, target)
+              - gf.optstep_loss(tm, g, node, edge, sy, rhat, target)) / (2 * eps)
+        worst = max(worst, abs(fd - G[i]) / max(floor, abs(G[i])))
+    assert worst < 1e-5, worst
+    assert np.abs(G).max() > 0.0
+
+
+def test_optstep_loss_is_the_steepest_descent_energy_and_scale_free():
+    # brute force over the step length, invariance under scaling e, the range
+    # [0, 1], and zero where the preconditioner is the exact inverse
+    g, D, dt, sy = _system(4, 2, 51)
+    N = sy.N
+    node, edge = gnn.features(g, D, dt, 1.0)
+    rng = np.random.default_rng(51)
+    theta = gf.init_params(N, 7) + 0.05 * rng.standard_normal(gf.n_params(N))
+    rhat, target = rng.standard_normal((2, sy.K, N))
+    L = gf.optstep_loss(theta, g, node, edge, sy, rhat, target)
+    e = (target + rhat).reshape(-1)
+    z = sy.P(gf.omega(theta, g, node, edge, sy)) @ (sy.S @ e)
+    ts = np.linspace(0.0, 4.0, 40001)
+    en = [(e - t * z) @ (sy.S @ (e - t * z)) for t in ts]
+    assert abs(min(en) / (e @ (sy.S @ e)) - L) < 1e-6
+    assert 0.0 <= L <= 1.0
+    assert abs(gf.optstep_loss(theta, g, node, edge, sy, 3.7 * rhat, 3.7 * target) - L) < 1e-12
+    # a single triangle: no neighbours, P = BJ^{-1} = S^{-1} exactly
+    cV = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    V0T = np.array([[0, 1, 2]], dtype=np.int32)
+    kind = np.ones((1, 3), dtype=np.int8)
+    g1 = Grid(cV, V0T, kind)
+    refs = RefTensors(2)
+    D1 = np.zeros((1, refs.N))
+    D1[0, 0] = 1.3 / np.sqrt(2.0)
+    s1 = gf.System(g1, schur_matrix(Blocks(g1, refs, D1), g1, refs, 1.0, 0.1))
+    node1, edge1 = gnn.features(g1, D1, 0.1, 1.0)
+    th1 = gf.init_params(refs.N, 3)
+    r1, t1 = rng.standard_normal((2, 1, refs.N))
+    assert gf.optstep_loss(th1, g1, node1, edge1, s1, r1, t1) < 1e-12
