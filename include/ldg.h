@@ -52,7 +52,8 @@ typedef enum {
   LDG_EDEVICE = -4,   /* a HIP call failed */
   LDG_ENOCONV = -5,   /* the solver did not reach rtol; the state is not advanced */
   LDG_EUNSUPPORTED = -6,
-  LDG_EIO = -7        /* a file could not be opened, read or written */
+  LDG_EIO = -7,       /* a file could not be opened, read or written */
+  LDG_ECALLBACK = -8  /* a field callback returned non-zero or a non-finite value */
 } ldg_status;
 
 /*
@@ -468,6 +469,44 @@ ldg_status ldg_gnn_train_step(ldg_ctx* ctx, const float* rhat, const float* targ
 ldg_status ldg_gnn_collect(ldg_ctx* ctx, int nsnap, const int32_t* iters, float* rhat_out,
                            float* target_out);
 ldg_status ldg_gnn_collected(ldg_ctx* ctx, int* n);
+
+/* ---- Host field callbacks ---------------------------------------------- */
+
+/*
+ * Fields given as host functions instead of samples.  A field callback fills
+ * out[i] = value at (x[i], y[i]) for i < n, at time t, and returns 0 (non-zero:
+ * the call fails with LDG_ECALLBACK and the state is unchanged).  The Neumann
+ * flux also receives the exterior unit normal (nx[i], ny[i]) of the boundary
+ * edge the point lies on (the Neumann data of Sec. 1.3 is a normal flux).  All
+ * arrays are host memory owned by the library for the duration of the call.
+ * The points are the library's: the volume points of ldg_quad_points kind 0
+ * for d, f, c0; the boundary Gauss points of kind 1 for c_D and g_N.
+ */
+typedef int (*ldg_field_fn)(void* user, double t, const double* x, const double* y, double* out,
+                            int64_t n);
+typedef int (*ldg_flux_fn)(void* user, double t, const double* x, const double* y,
+                           const double* nx, const double* ny, double* out, int64_t n);
+typedef struct {
+  ldg_field_fn d;     /* diffusion coefficient */
+  ldg_field_fn f;     /* source */
+  ldg_field_fn c_D;   /* Dirichlet data (may be NULL without Dirichlet edges) */
+  ldg_flux_fn g_N;    /* Neumann data (may be NULL without Neumann edges) */
+  void* user;         /* passed to every callback */
+} ldg_problem;
+
+/* Initial state: the L2 projection (Sec. 3.4) of c0(x, y) = c0_fn at t = 0; t is set to 0. */
+ldg_status ldg_set_initial(ldg_ctx* ctx, ldg_field_fn c0, void* user);
+/*
+ * One step t -> t + dt as ldg_step_sampled (same scheme, options and error
+ * behaviour), with d, f, c_D, g_N evaluated on the host at t + dt (Sec. 2.5)
+ * by the problem's callbacks.
+ */
+ldg_status ldg_step(ldg_ctx* ctx, double dt, const ldg_problem* problem, ldg_step_info* info);
+/* Initial state from coefficients (K x N, element-major; on_device: device pointer); t = 0. */
+ldg_status ldg_set_initial_dofs(ldg_ctx* ctx, const double* C, int on_device);
+/* Network parameters in and out (the same as ldg_gnn_set_params / ldg_gnn_get_params). */
+ldg_status ldg_gnn_load(ldg_ctx* ctx, const float* w, int64_t n);
+ldg_status ldg_gnn_save(ldg_ctx* ctx, float* w, int64_t n);
 
 /* ---- Input and output -------------------------------------------------- */
 

@@ -99,6 +99,9 @@ struct ldg_ctx {
   bool have_prev = false;
   double dt_prev = 0.0;
   double alpha = 1.0;   // mass coefficient of the operator (0 for the stationary system)
+  // host field callbacks: host copies of the sample points, device sample buffers
+  std::vector<double> cb_x, cb_y, cb_bx, cb_by, cb_nx, cb_ny;
+  double *cb_d = nullptr, *cb_f = nullptr, *cb_cD = nullptr, *cb_gN = nullptr, *cb_c0 = nullptr;
   // matrix-free apply: the block terms contracted from D on the matrix cores
   bool mf = false;
   double* mf64 = nullptr;
@@ -1944,6 +1947,95 @@ ldg_status ldg_edge_kinds_from_ids(int64_t K, const int32_t* edge_id, const int3
   }
   return LDG_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// the sample points on the host and the device sample buffers of the callbacks
+ldg_status cb_alloc(ldg_ctx* c) {
+  if (c->cb_d) return LDG_OK;
+  const int64_t nv = (int64_t)c->R * c->K, nb = (int64_t)c->R1 * c->nbnd;
+  double *px = nullptr, *py = nullptr;
+  TRY(dalloc(c, &px, std::max<int64_t>(nv, nb)));
+  TRY(dalloc(c, &py, std::max<int64_t>(nv, nb)));
+  auto fetch_pts = [&](int kind, int64_t n, std::vector<double>& hx, std::vector<double>& hy) {
+    hx.resize(n);
+    hy.resize(n);
+    if (n == 0) return LDG_OK;
+    ldg_status st = ldg_quad_points(c, kind, px, py);
+    if (st != LDG_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(hx.data(), px, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(hy.data(), py, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    return sync(c);
+  };
+  TRY(fetch_pts(0, nv, c->cb_x, c->cb_y));
+  TRY(fetch_pts(1, nb, c->cb_bx, c->cb_by));
+  TRY(fetch_pts(2, nb, c->cb_nx, c->cb_ny));
+  TRY(dalloc(c, &c->cb_d, std::max<int64_t>(nv, 1)));
+  TRY(dalloc(c, &c->cb_f, std::max<int64_t>(nv, 1)));
+  TRY(dalloc(c, &c->cb_c0, std::max<int64_t>(nv, 1)));
+  TRY(dalloc(c, &c->cb_cD, std::max<int64_t>(nb, 1)));
+  TRY(dalloc(c, &c->cb_gN, std::max<int64_t>(nb, 1)));
+  return LDG_OK;
+}
+
+// evaluate one field on the host and copy it to the device buffer dst
+ldg_status cb_eval(ldg_ctx* c, const char* name, ldg_field_fn fn, ldg_flux_fn flux, void* user,
+                   double t, bool boundary, double* dst) {
+  const std::vector<double>& x = boundary ? c->cb_bx : c->cb_x;
+  const std::vector<double>& y = boundary ? c->cb_by : c->cb_y;
+  const int64_t n = (int64_t)x.size();
+  std::vector<double> out(n, 0.0);
+  const int rc = fn ? fn(user, t, x.data(), y.data(), out.data(), n)
+                    : flux(user, t, x.data(), y.data(), c->cb_nx.data(), c->cb_ny.data(),
+                           out.data(), n);
+  if (rc != 0)
+    return fail(c, LDG_ECALLBACK, std::string("field callback ") + name + " returned " +
+                                      std::to_string(rc));
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(out[i]))
+      return fail(c, LDG_ECALLBACK, std::string("field callback ") + name +
+                                        " produced a non-finite value");
+  if (n > 0)
+    HIPCHK(c, hipMemcpyAsync(dst, out.data(), n * sizeof(double), hipMemcpyHostToDevice, c->st));
+  return sync(c);   // the host buffer ends here
+}
+
+}  // namespace
+
+extern "C" {
+
+ldg_status ldg_set_initial(ldg_ctx* c, ldg_field_fn c0, void* user) {
+  if (!c || !c0) return fail(c, LDG_EINVAL, "bad arguments");
+  TRY(cb_alloc(c));
+  TRY(cb_eval(c, "c0", c0, nullptr, user, 0.0, false, c->cb_c0));
+  return ldg_set_initial_samples(c, c->cb_c0, 0.0);
+}
+
+ldg_status ldg_step(ldg_ctx* c, double dt, const ldg_problem* pb, ldg_step_info* info) {
+  if (!c || !pb || !info || !(dt > 0.0) || !pb->d || !pb->f)
+    return fail(c, LDG_EINVAL, "bad arguments");
+  const bool has_dir = 3 * c->K - c->n_nd > 0, has_neu = 3 * c->K - c->n_sd > 0;
+  if ((has_dir && !pb->c_D) || (has_neu && !pb->g_N))
+    return fail(c, LDG_EINVAL, "the mesh has Dirichlet (Neumann) edges but no c_D (g_N)");
+  TRY(cb_alloc(c));
+  const double t = c->t + dt;   // data at the new time level (Sec. 2.5)
+  TRY(cb_eval(c, "d", pb->d, nullptr, pb->user, t, false, c->cb_d));
+  TRY(cb_eval(c, "f", pb->f, nullptr, pb->user, t, false, c->cb_f));
+  if (has_dir) TRY(cb_eval(c, "c_D", pb->c_D, nullptr, pb->user, t, true, c->cb_cD));
+  if (has_neu) TRY(cb_eval(c, "g_N", nullptr, pb->g_N, pb->user, t, true, c->cb_gN));
+  return ldg_step_sampled(c, dt, c->cb_d, c->cb_f, has_dir ? c->cb_cD : nullptr,
+                          has_neu ? c->cb_gN : nullptr, info);
+}
+
+ldg_status ldg_set_initial_dofs(ldg_ctx* c, const double* C, int on_device) {
+  return ldg_set_state(c, C, on_device, 0.0);
+}
+
+ldg_status ldg_gnn_load(ldg_ctx* c, const float* w, int64_t n) { return ldg_gnn_set_params(c, w, n); }
+
+ldg_status ldg_gnn_save(ldg_ctx* c, float* w, int64_t n) { return ldg_gnn_get_params(c, w, n); }
 
 ldg_status ldg_sample_workload(ldg_ctx* c, int kind, double t, const double* dT, double* d,
                                double* f, double* cD, double* gN, double* c0) {

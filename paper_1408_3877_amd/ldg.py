@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LDG_FP64, LDG_MIXED_FP32, LDG_MIXED_BF16 = 0, 1, 2
 LDG_PC_BLOCK_JACOBI, LDG_PC_GNN = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM", -4: "EDEVICE", -5: "ENOCONV",
-          -6: "EUNSUPPORTED", -7: "EIO"}
+          -6: "EUNSUPPORTED", -7: "EIO", -8: "ECALLBACK"}
 
 
 class LdgError(RuntimeError):
@@ -55,6 +55,46 @@ class StepInfo(C.Structure):
 
 
 _P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+FIELD_FN = C.CFUNCTYPE(C.c_int, _P, C.c_double, _DP, _DP, _DP, C.c_int64)
+FLUX_FN = C.CFUNCTYPE(C.c_int, _P, C.c_double, _DP, _DP, _DP, _DP, _DP, C.c_int64)
+
+
+class Problem(C.Structure):
+    _fields_ = [("d", FIELD_FN), ("f", FIELD_FN), ("c_D", FIELD_FN), ("g_N", FLUX_FN),
+                ("user", _P)]
+
+
+def _field(fn):
+    """C callback from fn(t, x, y) -> values (numpy); an exception returns 1."""
+    if fn is None:
+        return FIELD_FN()
+
+    def cb(user, t, x, y, out, n):
+        try:
+            xs, ys = np.ctypeslib.as_array(x, (n,)), np.ctypeslib.as_array(y, (n,))
+            np.ctypeslib.as_array(out, (n,))[:] = fn(t, xs, ys)
+            return 0
+        except Exception:
+            return 1
+    return FIELD_FN(cb)
+
+
+def _flux(fn):
+    """C callback from fn(t, x, y, nx, ny) -> values (numpy); an exception returns 1."""
+    if fn is None:
+        return FLUX_FN()
+
+    def cb(user, t, x, y, nx, ny, out, n):
+        try:
+            a = [np.ctypeslib.as_array(v, (n,)) for v in (x, y, nx, ny)]
+            np.ctypeslib.as_array(out, (n,))[:] = fn(t, *a)
+            return 0
+        except Exception:
+            return 1
+    return FLUX_FN(cb)
+
+
 _SIGS = {
     "ldg_options_default": [C.POINTER(Options)],
     "ldg_create": [_P, C.c_int64, _P, C.c_int64, _P, C.POINTER(Options), C.POINTER(_P)],
@@ -97,6 +137,11 @@ _SIGS = {
     "ldg_get_kernel_stat": [_P, C.c_int, C.POINTER(KernelStat)],
     "ldg_sample_workload": [_P, C.c_int, C.c_double, _P, _P, _P, _P, _P, _P],
     "ldg_lagrange": [_P, _P, _P, C.POINTER(C.c_int)],
+    "ldg_set_initial": [_P, FIELD_FN, _P],
+    "ldg_step": [_P, C.c_double, C.POINTER(Problem), C.POINTER(StepInfo)],
+    "ldg_set_initial_dofs": [_P, _P, C.c_int],
+    "ldg_gnn_load": [_P, _P, C.c_int64],
+    "ldg_gnn_save": [_P, _P, C.c_int64],
     "ldg_write_vtu": [_P, C.c_char_p, C.c_char_p, _P, C.c_int, C.c_int],
     "ldg_mesh_read_medit": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _P, _P, _P],
     "ldg_edge_kinds_from_ids": [C.c_int64, _P, _P, C.c_int, _P],
@@ -280,6 +325,21 @@ class Solver:
                                  np.float64)
         self._check(self.lib.ldg_write_vtu(self.h, os.fsencode(path), name.encode(), v.ctypes.data,
                                            v.shape[1], int(bool(binary))))
+
+    def set_initial(self, c0):
+        """Initial state from a host function c0(t, x, y) (called with t = 0)."""
+        cb = _field(c0)
+        self._check(self.lib.ldg_set_initial(self.h, cb, None))
+
+    def step(self, dt, d, f, c_D=None, g_N=None):
+        """One step with host field functions d, f, c_D (t, x, y) and g_N
+        (t, x, y, nx, ny) evaluated by the library at its own points at t + dt."""
+        cbs = (_field(d), _field(f), _field(c_D), _flux(g_N))
+        pb = Problem(cbs[0], cbs[1], cbs[2], cbs[3], None)
+        info = StepInfo()
+        code = self.lib.ldg_step(self.h, float(dt), C.byref(pb), C.byref(info))
+        self._check(code)
+        return info.as_dict()
 
     def solve_stationary_sampled(self, d, f, cD=None, gN=None):
         """A Y = V from sampled data (no mass term, no history); the solution
