@@ -78,6 +78,15 @@ typedef enum { LDG_EDGE_INTERIOR = 0, LDG_EDGE_DIRICHLET = 1, LDG_EDGE_NEUMANN =
  * otherwise (or if CG breaks down) restarted GMRES.
  */
 typedef enum { LDG_KRYLOV_AUTO = 0, LDG_KRYLOV_GMRES = 1, LDG_KRYLOV_CG = 2 } ldg_krylov;
+/*
+ * Quadrature of the reference tensors (Sec. 3.6).  LDG_QUAD_EXACT: every
+ * polynomial integrand integrated exactly (the plain definition of the
+ * tensors).  LDG_QUAD_PAPER: the paper's routines' rules, order max(2p, 1) on
+ * the triangle and 2p + 1 on the edges, below the degree 3p of the
+ * three-factor integrands of G_hat and R_hat for p >= 2 (identical for p <= 1).
+ * The projection and boundary-data rules are the paper's in both.
+ */
+typedef enum { LDG_QUAD_EXACT = 0, LDG_QUAD_PAPER = 1 } ldg_quad_policy;
 
 typedef struct {
   int p;              /* polynomial order 0..4 (assert in the main script) */
@@ -91,6 +100,7 @@ typedef struct {
   void* stream;       /* hipStream_t for all device work */
   int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
   double inner_rtol;  /* mixed modes: relative tolerance of each inner solve, default 1e-3 */
+  int quad;           /* ldg_quad_policy of the reference tensors, default LDG_QUAD_EXACT */
 } ldg_options;
 
 typedef struct {

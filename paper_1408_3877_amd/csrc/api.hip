@@ -917,6 +917,7 @@ ldg_status ldg_options_default(ldg_options* o) {
   o->stream = nullptr;
   o->krylov = LDG_KRYLOV_AUTO;
   o->inner_rtol = 1e-3;
+  o->quad = LDG_QUAD_EXACT;
   return LDG_OK;
 }
 
@@ -948,6 +949,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (opt->precision != LDG_FP64 && !(opt->inner_rtol > 0.0 && opt->inner_rtol < 1.0))
     return LDG_EINVAL;
   if (opt->precond != LDG_PC_BLOCK_JACOBI && opt->precond != LDG_PC_GNN) return LDG_EINVAL;
+  if (opt->quad != LDG_QUAD_EXACT && opt->quad != LDG_QUAD_PAPER) return LDG_EINVAL;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
   c->opt = *opt;
@@ -959,7 +961,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (!msg.empty()) return fail(c, mesh_err ? LDG_EMESH : LDG_EINVAL, msg);
   c->h_coordV.assign(coordV, coordV + 2 * numV);
   c->h_V0T.assign(V0T, V0T + 3 * K);
-  c->ref = build_refdata(opt->p);
+  c->ref = build_refdata(opt->p, opt->quad);
   const RefData& rf = c->ref;
   for (int i = 0; i < rf.N; ++i)
     for (int j = 0; j < rf.N; ++j)

@@ -169,16 +169,24 @@ void edge_point(int n, double s, double& x1, double& x2) {
 }
 }  // namespace
 
-RefData build_refdata(int p) {
+RefData build_refdata(int p, int policy) {
   RefData r;
   r.p = p;
   const int N = r.N = num_basis(p);
   const int NN = r.NN = N * N;
-  // exact integration: 12 x 12 collapsed points (degree 22) on the triangle,
-  // 12 Gauss points (degree 23) on edges; integrands have degree <= 3p.
   std::vector<double> q1, q2, w, s, ws;
-  collapsed(12, q1, q2, w);
-  gauss_legendre(12, s, ws);
+  if (policy == LDG_QUAD_PAPER) {
+    // the paper's routines: order max(2p, 1) on the triangle (the projection
+    // rule) and 2p + 1 on edges, below the degree 3p of the three-factor
+    // integrands for p >= 2 (exact for M, H and the two-factor edge terms)
+    projection_rule(p, q1, q2, w);
+    gauss_legendre(p + 1, s, ws);
+  } else {
+    // exact integration: 12 x 12 collapsed points (degree 22) on the triangle,
+    // 12 Gauss points (degree 23) on edges; integrands have degree <= 3p.
+    collapsed(12, q1, q2, w);
+    gauss_legendre(12, s, ws);
+  }
   const int R = (int)w.size();
   std::vector<double> ph(R * N), dph[2];
   dph[0].resize(R * N);

@@ -57,7 +57,7 @@ double dphi_hat(int i, int m, double x1, double x2);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);  // on (0,1)
 void projection_rule(int p, std::vector<double>& q1, std::vector<double>& q2,
                      std::vector<double>& w);
-RefData build_refdata(int p);
+RefData build_refdata(int p, int policy);   // policy: ldg_quad_policy
 
 // host_mesh.cpp
 struct HostMesh {
