@@ -50,7 +50,7 @@ CONFIGS = {
                              field_seed=5000, dt=1e-4),
     # stationary solves of the Table 2 problem (h = 1/96), and the main script's problem
     "table2-p4-96": dict(n=96, p=4, jitter=None, kind=TABLE2, neumann=(SOUTH, NORTH),
-                         stationary=True, dt=0.0, restart=150, max_iters=200000),
+                         stationary=True, dt=0.0, restart=150, max_iters=200000, cpu_cells=16),
     "main-p2-8": dict(n=8, p=2, jitter=None, kind=MAIN, neumann=(SOUTH, NORTH), dt=np.pi / 20),
 }
 DEFAULT = "combined-p4-1024"
@@ -172,11 +172,12 @@ def measured_traffic(config, kernel, precision, precond, matrix_free=False):
 
 def cpu_baseline(cfg, seconds_hint=True):
     """The oracle (direct sparse solve of the full system) on a bounded sample
-    of the same workload family: 16 x 16 cells, same p, same fields, 2 steps."""
+    of the same workload family: 24 x 24 cells (16 x 16 for the stationary
+    workload), same p, same fields, 2 steps; about 10-30 s of one core."""
     from threadpoolctl import threadpool_limits
 
     from oracle.ldg import Problem
-    n = 16
+    n = cfg.get("cpu_cells", 24)
     coordV, V0T, kind = square_mesh(n, seed=cfg["jitter"], neumann_sides=cfg.get("neumann", ()))
     if cfg["kind"] in (LOGNORMAL, LOGNORMAL_T):
         w = Workload(cfg["kind"], n_cells=n,
