@@ -15,12 +15,18 @@ namespace ldg {
 using bf16 = uint16_t;
 using fp8 = uint8_t;   // OCP E4M3 (gfx950 conversions), factor blocks only
 
+// Stored blocks are read once per apply: load them non-temporally so that the
+// stream does not evict the coefficient vectors neighbouring tiles gather.
+typedef double nt_f64x2 __attribute__((ext_vector_type(2)));
+typedef float nt_f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u32x4 __attribute__((ext_vector_type(4)));
+
 template <class BT> struct Blk;
 template <> struct Blk<double> {
   static constexpr int W = 2;
   template <class T>
   __device__ static inline void load(const double* p, T* v) {
-    const double2 x = *reinterpret_cast<const double2*>(p);
+    const nt_f64x2 x = __builtin_nontemporal_load(reinterpret_cast<const nt_f64x2*>(p));
     v[0] = (T)x.x;
     v[1] = (T)x.y;
   }
@@ -29,7 +35,7 @@ template <> struct Blk<float> {
   static constexpr int W = 4;
   template <class T>
   __device__ static inline void load(const float* p, T* v) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
+    const nt_f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const nt_f32x4*>(p));
     v[0] = (T)x.x;
     v[1] = (T)x.y;
     v[2] = (T)x.z;
@@ -40,7 +46,7 @@ template <> struct Blk<bf16> {
   static constexpr int W = 8;
   template <class T>
   __device__ static inline void load(const bf16* p, T* v) {
-    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    const nt_u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const nt_u32x4*>(p));
     const uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -54,7 +60,7 @@ template <> struct Blk<fp8> {
   static constexpr int W = 16;
   template <class T>
   __device__ static inline void load(const fp8* p, T* v) {
-    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    const nt_u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const nt_u32x4*>(p));
     const int w[4] = {(int)x.x, (int)x.y, (int)x.z, (int)x.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

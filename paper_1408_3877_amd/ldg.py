@@ -162,6 +162,10 @@ def load_library():
     path = library_path()
     if not os.path.exists(path):
         raise RuntimeError("libldg.so is not built; run `python -m paper_1408_3877_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so
+    # that the process holds one runtime (loaded the other way round, torch's
+    # runtime reports no device)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, args in _SIGS.items():
         fn = getattr(lib, name)
