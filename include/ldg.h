@@ -439,8 +439,8 @@ ldg_status ldg_gnn_factor_omega(ldg_ctx* ctx, float* omega);
  * positive definite matrix with identity diagonal blocks, lie in [-1, 1]),
  * LDG_FAC_FP8W (both in E4M3; W_k stored as s_k W8_k with the power of two
  * s_k = 2^round(log2(max |W_k| / 256)) per triangle, which keeps the block
- * inside the E4M3 range), LDG_FAC_BF16 (both in BF16) or LDG_FAC_F32.  P
- * stays exactly symmetric positive definite in each, the same rounded blocks
+ * inside the E4M3 range), LDG_FAC_BF16 (both in BF16) or LDG_FAC_F32.  Only
+ * the upper triangle of W_k is stored.  P stays exactly symmetric positive definite in each, the same rounded blocks
  * forming G and G^T; the solution's accuracy is set by the FP64 residual as
  * always.  Takes effect at the next factor build (step or
  * ldg_gnn_set_context).

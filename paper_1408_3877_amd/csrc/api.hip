@@ -596,11 +596,12 @@ ldg_status fac_omega(ldg_ctx* c) {
 
 // z = P r (factored) with <r, z> in red.result[0]
 void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z) {
-  const double NN = (double)c->N * c->N;
+  // W (upper triangular, N(N+1)/2 entries) read twice, the three O blocks twice
+  const double NN = (double)c->N * c->N, NT = 0.5 * c->N * (c->N + 1);
   const double bw = c->fac.wt == BT_F32 ? 4.0 : (c->fac.wt == BT_BF16 ? 2.0 : 1.0);
   const double bo = c->fac.ot == BT_F32 ? 4.0 : (c->fac.ot == BT_BF16 ? 2.0 : 1.0);
-  Timed tm(c, LDG_K_FACTOR, ((2.0 * bw + 6.0 * bo) * NN + 7.0 * L.vbytes * c->N) * c->K,
-           2.0 * 8.0 * NN * c->K);
+  Timed tm(c, LDG_K_FACTOR, (2.0 * bw * NT + 6.0 * bo * NN + 7.0 * L.vbytes * c->N) * c->K,
+           2.0 * (2.0 * NT + 6.0 * NN) * c->K);
   void* y = L.vt == VT_F64 ? (void*)c->fac_v[0] : (void*)c->fac_y32;
   void* a = L.vt == VT_F64 ? (void*)c->fac_v[1] : (void*)c->fac_a32;
   launch_fac_apply(c->N, c->fac, L.vt, c->geo, c->fac_om, r, y, a, z, &c->red, c->st);

@@ -120,7 +120,7 @@ void launch_adam(int64_t n, float* p, const float* gr, float* m, float* v, float
 constexpr int FAC_SLOTS = 4;   // W_k, O_k0, O_k1, O_k2 in the exports
 struct FacStore {
   int wt = BT_BF16, ot = BT_FP8;
-  void* w = nullptr;   // W: Kpad x 1 slot
+  void* w = nullptr;   // W: Kpad x 1 slot, the upper triangle packed row by row
   void* o = nullptr;   // O: Kpad x 3 slots
   float* ws = nullptr; // per-triangle power-of-two scale of W when wt = BT_FP8 (W = ws W8)
 };

@@ -53,6 +53,55 @@ __device__ inline double get64(const double* __restrict__ b, int64_t k, int s, i
   return b[pidx(k, s, f >> 1, ns, NP) + (f & 1)];
 }
 
+// W_k is upper triangular: only its N(N+1)/2 entries W[r][i], i >= r, are
+// stored, packed row by row (entry e = rN - r(r-1)/2 + i - r) in groups of the
+// storage width in the element-fastest tile layout of one block slot.
+template <int N>
+__host__ __device__ constexpr int tri_size() { return N * (N + 1) / 2; }
+template <int N>
+__host__ __device__ constexpr int tri_index(int r, int i) { return r * N - r * (r - 1) / 2 + i - r; }
+
+template <int N, class BW>
+__device__ inline void putw(BW* __restrict__ fw, int64_t k, int r, int i, double v) {
+  constexpr int Wv = Blk<BW>::W;
+  constexpr int NG = (tri_size<N>() + Wv - 1) / Wv;
+  const int e = tri_index<N>(r, i);
+  fw[bgidx(k, 0, e / Wv, 1, NG, Wv) + e % Wv] = from_double<BW>(v);
+}
+
+// W[r][i] as stored (zero below the diagonal), for exports; N at run time
+template <class BW>
+__device__ inline double getw(const BW* __restrict__ fw, int64_t k, int N, int r, int i) {
+  if (i < r) return 0.0;
+  constexpr int Wv = Blk<BW>::W;
+  const int NG = (N * (N + 1) / 2 + Wv - 1) / Wv;
+  const int e = r * N - r * (r - 1) / 2 + i - r;
+  const BW v = fw[bgidx(k, 0, e / Wv, 1, NG, Wv) + e % Wv];
+  if constexpr (sizeof(BW) == 2) return (double)__uint_as_float((uint32_t)v << 16);
+  else if constexpr (sizeof(BW) == 1) return (double)fp8_to_float(v);
+  else return (double)v;
+}
+
+// acc += W_k z  (TRANS false) or acc += W_k^T z  (TRANS true) from the packed
+// triangle, walking it in storage order: a group is loaded where e starts one
+// (all indices are constants once the loops are unrolled)
+template <int N, class BW, class T, bool TRANS>
+__device__ inline void tri_mv(const BW* __restrict__ fw, int64_t k, const T* z, T* acc) {
+  constexpr int Wv = Blk<BW>::W;
+  constexpr int NG = (tri_size<N>() + Wv - 1) / Wv;
+  T v[Wv];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+#pragma unroll
+    for (int i = r; i < N; ++i) {
+      const int e = tri_index<N>(r, i);
+      if (e % Wv == 0) Blk<BW>::load(fw + bgidx(k, 0, e / Wv, 1, NG, Wv), v);
+      if (TRANS) acc[i] += v[e % Wv] * z[r];
+      else acc[r] += v[e % Wv] * z[i];
+    }
+  }
+}
+
 // W stored in FP8 carries a power-of-two scale per triangle (W = s W8); the
 // other storages carry none
 template <class BW>
@@ -113,7 +162,7 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
       const double v = r <= i ? a[r] : 0.0;
       const int f = r * N + i;
       w64[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = v;
-      put<BT>(fb, k, 0, 1, f, N, v * inv_s);
+      if (r <= i) putw<N, BT>(fb, k, r, i, v * inv_s);
     }
   }
 }
@@ -249,7 +298,7 @@ __global__ void __launch_bounds__(256) k_fac_w(int64_t Kpad, const BW* __restric
   load_vec<N, T>(x, k, xv);
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
-  block_mv<N, BW, T>(fw, k, 0, 1, xv, acc);
+  tri_mv<N, BW, T, false>(fw, k, xv, acc);
   if constexpr (sizeof(BW) == 1) {
     const T sc = (T)wscale<BW>(ws, k);
 #pragma unroll
@@ -269,7 +318,7 @@ __global__ void __launch_bounds__(256) k_fac_wt(int64_t Kpad, const BW* __restri
   load_vec<N, T>(x, k, xv);
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0;
-  block_mtv<N, BW, T>(fw, k, 0, 1, xv, acc);
+  tri_mv<N, BW, T, true>(fw, k, xv, acc);
   if constexpr (sizeof(BW) == 1) {
     const T sc = (T)wscale<BW>(ws, k);
 #pragma unroll
@@ -313,7 +362,7 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
       T o[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) o[i] = 0;
-      block_mtv<N, BW, T>(fw, k, 0, 1, acc, o);
+      tri_mv<N, BW, T, true>(fw, k, acc, o);
       if constexpr (sizeof(BW) == 1) {
         const T sc = (T)wscale<BW>(ws, k);
 #pragma unroll
@@ -391,7 +440,7 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
   const int s = (int)((t / NN) % FAC_SLOTS);
   const int64_t r = t / ((int64_t)NN * FAC_SLOTS);
   const int64_t k = elems ? (int64_t)elems[r] : r;
-  out[t] = s == 0 ? get_any<BW>(fw, k, 0, 1, f, N) * (double)wscale<BW>(ws, k)
+  out[t] = s == 0 ? getw<BW>(fw, k, N, f / N, f % N) * (double)wscale<BW>(ws, k)
                   : get_any<BO>(fo, k, s - 1, 3, f, N);
   if (lnout && f == 0 && s < 3) lnout[r * 3 + s] = ln[s * Kpad + k];
 }
