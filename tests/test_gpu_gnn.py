@@ -189,6 +189,28 @@ def test_training_on_method_systems_reduces_loss_and_reports_gain():
     assert rep["learned"]["iters_per_step"] < 0.8 * rep["block_jacobi"]["iters_per_step"]
 
 
+def test_output_bias_calibration_applies_the_best_shift(tmp_path):
+    # the calibration tries each shift of the head's output bias b_o on the
+    # training fields, keeps the one with the fewest CG iterations (ties to the
+    # smallest shift) and saves weights that differ from the input in b_o only
+    from paper_1408_3877_amd import learned
+    w0 = learned.factor_init(6, 7)
+    src, out = tmp_path / "w.npy", tmp_path / "wc.npy"
+    np.save(src, w0)
+    rep = learned.main(["--p", "2", "--n", "16", "--jitter", "631", "--sigma", "1.5",
+                        "--weights", str(src), "--calibrate=-1,0,1.5", "--train-seeds", "4000-4001",
+                        "--eval-seeds", "4100", "--eval-steps", "1", "--dt", "0.002",
+                        "--out", str(out)])
+    print("[learned-calibrate] %s" % rep["calibration"])
+    table = rep["calibration"]
+    assert [d for d, _ in table] == [-1.0, 0.0, 1.5]
+    assert all(it > 0 for _, it in table)
+    best = min(table, key=lambda x: (x[1], abs(x[0])))
+    w = np.load(out)
+    assert np.array_equal(w[:-1], w0[:-1])
+    assert w[-1] == np.float32(w0[-1] + np.float32(best[0]))
+
+
 def test_training_the_correction_network_on_collected_pairs():
     # the residual-correction network: pairs from block-Jacobi CG iterates of the
     # method's steps, energy loss; the loss falls and the steps stay exact
