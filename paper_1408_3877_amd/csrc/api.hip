@@ -30,6 +30,7 @@ struct ldg_ctx {
   int8_t *nbrn = nullptr, *kind = nullptr, *bn = nullptr;
   // reference data
   double* refs = nullptr;
+  float* refs32 = nullptr;
   double *Wvol = nullptr, *qvol = nullptr, *Wb = nullptr, *ws = nullptr, *sb = nullptr;
   // state and work, element-fastest layout
   double *C = nullptr, *Z1 = nullptr, *Z2 = nullptr, *D = nullptr, *F = nullptr;
@@ -269,7 +270,7 @@ void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j
               void* Zx2, void* y, bool dot = false) {
   {
     Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c));
-    launch_grad(c->N, L.vt, c->geo, c->refs, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
+    launch_grad(c->N, L.vt, c->geo, c->refs, c->refs32, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
                 Zx1, Zx2, c->st);
   }
   if (c->mf) {
@@ -1047,6 +1048,11 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(dalloc(c, &c->ws, rf.ws.size()));
   TRY(dalloc(c, &c->sb, rf.s.size()));
   TRY(upload(c, c->refs, refs));
+  {
+    const std::vector<float> r32(refs.begin(), refs.end());
+    TRY(dalloc(c, &c->refs32, r32.size()));
+    TRY(upload(c, c->refs32, r32));
+  }
   TRY(upload(c, c->Wvol, Wvol));
   TRY(upload(c, c->qvol, qv));
   TRY(upload(c, c->Wb, Wb));
@@ -1308,7 +1314,7 @@ ldg_status ldg_apply_full(ldg_ctx* c, double dt, const double* Y, double* out) {
   launch_to_tiled(c->K, c->Kpad, c->N, Y, c->z, c->st);            // Z1
   launch_to_tiled(c->K, c->Kpad, c->N, Y + KN, c->r, c->st);       // Z2
   launch_to_tiled(c->K, c->Kpad, c->N, Y + 2 * KN, c->u, c->st);   // C
-  launch_grad(c->N, VT_F64, c->geo, c->refs, c->u, nullptr, nullptr, c->tZ1, c->tZ2, c->st);
+  launch_grad(c->N, VT_F64, c->geo, c->refs, c->refs32, c->u, nullptr, nullptr, c->tZ1, c->tZ2, c->st);
   launch_zrows(c->geo, c->N, c->z, c->tZ1, dt, c->w, c->st);
   launch_from_tiled(c->K, c->N, c->w, out, c->st);
   launch_zrows(c->geo, c->N, c->r, c->tZ2, dt, c->w, c->st);

@@ -15,8 +15,10 @@ enum { VT_F64 = 0, VT_F32 = 1 };
 enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2, BT_FP8 = 3 };
 
 // kernels_apply.hip
-void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
-                 const void* J2, void* Z1, void* Z2, hipStream_t st);
+// refs: the 14 reference matrices in FP64 (N x N each); refs32: the same in FP32
+void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
+                 const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
+                 hipStream_t st);
 struct Reducer;
 // red (optional): red->result[0] = <C, y> afterwards
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,

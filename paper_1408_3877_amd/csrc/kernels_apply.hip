@@ -56,15 +56,40 @@ __device__ inline void mv_add(const T* __restrict__ A, const T* x, T* acc, T sca
   }
 }
 
+// acc += scale * A x with A (N x N, row-major) in global memory at an address
+// that is the same for every lane of the wave: each entry is one scalar-cache
+// load and the SGPR operand of the vector FMA, so the products need no LDS
+// traffic (broadcast LDS reads of the matrices bound the gradient kernel)
+template <int N, class T>
+__device__ inline void mv_add_s(const T* __restrict__ A, const T* x, T* acc, T scale) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += A[i * N + j] * x[j];
+    acc[i] += scale * s;
+  }
+}
+
 }  // namespace
 
+// The 14 reference matrices (H1, H2, S_diag[3], S_off[3][3]), N x N each: the
+// FP32 kernel reads them through the scalar cache (rT, FP32 copy); the FP64
+// kernel keeps them in LDS (as SGPR operands its products spill registers)
 template <int N, class T>
 __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
+                                              const T* __restrict__ rT,
                                               const T* __restrict__ C, const T* __restrict__ J1,
                                               const T* __restrict__ J2, T* __restrict__ Z1,
                                               T* __restrict__ Z2) {
-  __shared__ __align__(16) T sm[ref_size<N, T>()];
-  load_refs<N, T>(sm, refs);
+  constexpr int NN = N * N;
+  constexpr bool SC = sizeof(T) == 4;
+  __shared__ __align__(16) T sm[SC ? 1 : ref_size<N, T>()];
+  if constexpr (!SC) load_refs<N, T>(sm, refs);
+  auto mv = [&](int ref, const T* x, T* acc, T scale) {
+    if constexpr (SC) mv_add_s<N, T>(rT + ref * NN, x, acc, scale);
+    else mv_add<N, T>(sm + ref * N * row_stride<N, T>(), x, acc, scale);
+  };
   const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
   T a1[N], a2[N];
@@ -84,8 +109,8 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T u1[N], u2[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0;
-    mv_add<N, T>(sm + ref_h(0) * N * row_stride<N, T>(), c, u1, (T)1);
-    mv_add<N, T>(sm + ref_h(1) * N * row_stride<N, T>(), c, u2, (T)1);
+    mv(ref_h(0), c, u1, (T)1);
+    mv(ref_h(1), c, u2, (T)1);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       a1[i] -= B22 * u1[i] - B21 * u2[i];
@@ -101,13 +126,21 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T s[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] = 0;
-    mv_add<N, T>(sm + ref_sd(n) * N * row_stride<N, T>(), c, s, cq);
+    mv(ref_sd(n), c, s, cq);
     if (kind == LDG_EDGE_INTERIOR) {
       const int64_t kp = g.nbr[n * Kp + k];
       const int np = g.nbrn[n * Kp + k];
       T cp[N];
       load_vec<N, T>(C, kp, cp);
-      mv_add<N, T>(sm + ref_so(n, np) * N * row_stride<N, T>(), cp, s, (T)0.5 * L);
+      if constexpr (SC) {
+        // S_off(n, n+) with n+ per lane: one wave-uniform matrix per candidate
+        // (a single candidate on structured meshes; the others are skipped)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (np == b) mv(ref_so(n, b), cp, s, (T)0.5 * L);
+      } else {
+        mv(ref_so(n, np), cp, s, (T)0.5 * L);
+      }
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -311,17 +344,18 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
     default: break;                                             \
   }
 
-void launch_grad(int N, int vt, const Geo& g, const double* refs, const void* C, const void* J1,
-                 const void* J2, void* Z1, void* Z2, hipStream_t st) {
+void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
+                 const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
+                 hipStream_t st) {
   const unsigned nb = nblk(g.Kpad, 256);
   if (vt == VT_F64) {
     LDG_SWITCH_N(N, (k_grad<NT, double><<<nb, 256, 0, st>>>(
-                        g, refs, (const double*)C, (const double*)J1, (const double*)J2,
+                        g, refs, refs, (const double*)C, (const double*)J1, (const double*)J2,
                         (double*)Z1, (double*)Z2)));
   } else {
     LDG_SWITCH_N(N, (k_grad<NT, float><<<nb, 256, 0, st>>>(
-                        g, refs, (const float*)C, (const float*)J1, (const float*)J2, (float*)Z1,
-                        (float*)Z2)));
+                        g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
+                        (float*)Z1, (float*)Z2)));
   }
 }
 
