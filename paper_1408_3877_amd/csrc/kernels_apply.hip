@@ -7,7 +7,8 @@
 // Divergence half: y = alpha M C + tau (eta (S + S_D) C + sum_m B^m Z^m),
 //                  B^m = -G^m + R^m + R^m_D   (eq:timeDepSystem)
 // H, Q, S enter through the reference matrices H_hat, S_hat_diag, S_hat_off
-// (Sec. 3.6.2, 3.6.4, 3.6.5) kept in LDS; G and R through the stored blocks.
+// (Sec. 3.6.2, 3.6.4, 3.6.5), kept in LDS or, in the FP32 gradient kernel, read
+// through the scalar cache; G and R through the stored blocks.
 #include "device_common.h"
 #include "kernels.h"
 
