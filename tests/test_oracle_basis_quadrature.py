@@ -33,6 +33,36 @@ def test_closed_forms_up_to_order_two():
         np.testing.assert_allclose(basis.phi(i, x, y), ref, rtol=0, atol=1e-13)
 
 
+def test_closed_forms_orders_three_and_four():
+    # Sec. 2.4.1: phi_7..phi_15 as the paper's basis routine prints them (nested
+    # Horner form in x1 = x, x2 = y); a sign, scale or within-degree permutation
+    # slip in the oracle's coefficient table fails here
+    x, y = _tri_points(60)
+    s2, s6, s10, s14, s30, s70 = np.sqrt([2.0, 6.0, 10.0, 14.0, 30.0, 70.0])
+    printed = [
+        2 * s2 * (-1 + (15 + (-45 + 35 * x) * x) * x),
+        2 * s6 * (-1 + (13 + (-33 + 21 * x) * x) * x + (2 + (-24 + 42 * x) * x) * y),
+        2 * s10 * (-1 + (9 + (-15 + 7 * x) * x) * x
+                   + (6 + (-48 + 42 * x) * x + (-6 + 42 * x) * y) * y),
+        2 * s14 * (-1 + (3 + (-3 + x) * x) * x
+                   + (12 + (-24 + 12 * x) * x + (-30 + 30 * x + 20 * y) * y) * y),
+        s10 * (1 + (-24 + (126 + (-224 + 126 * x) * x) * x) * x),
+        s30 * (1 + (-22 + (105 + (-168 + 84 * x) * x) * x) * x
+               + (-2 + (42 + (-168 + 168 * x) * x) * x) * y),
+        5 * s2 * (1 + (-18 + (69 + (-88 + 36 * x) * x) * x) * x
+                  + (-6 + (102 + (-312 + 216 * x) * x) * x + (6 + (-96 + 216 * x) * x) * y) * y),
+        s70 * (1 + (-12 + (30 + (-28 + 9 * x) * x) * x) * x
+               + (-12 + (132 + (-228 + 108 * x) * x) * x
+                  + (30 + (-300 + 270 * x) * x + (-20 + 180 * x) * y) * y) * y),
+        3 * s10 * (1 + (-4 + (6 + (-4 + x) * x) * x) * x
+                   + (-20 + (60 + (-60 + 20 * x) * x) * x
+                      + (90 + (-180 + 90 * x) * x + (-140 + 140 * x + 70 * y) * y) * y) * y),
+    ]
+    for j, ref in enumerate(printed):
+        i = 6 + j
+        np.testing.assert_allclose(basis.phi(i, x, y), ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
+
+
 def test_orthonormal_exact_mass():
     # M_hat = identity (eq:hatM, Sec. 2.4.1) with a rule exact for degree 8
     x1, x2, w = collapsed_rule(6)

@@ -318,3 +318,19 @@ def test_step_ignores_the_previous_flux():
         Yn = np.concatenate([zn, C0])
         Ys.append(spla.spsolve((W + 0.02 * A).tocsc(), W @ Yn + 0.02 * V))
     assert np.abs(Ys[0] - Ys[1]).max() == 0.0
+
+
+def test_l2_error_absolute_scale():
+    # Sec. 3.5: ||c_h - c||_{L2(Omega)} on the unit square.  With c_h = 0 and
+    # c = x y the error is (int x^2 y^2)^(1/2) = 1/3; with c = 0 and only the
+    # constant coefficient a set, c_h = a sqrt(2) and the error is a sqrt(2)
+    # (|Omega| = 1).  A constant factor in the rule's weights or the 2|T_k|
+    # scaling fails this, which the convergence orders alone do not see.
+    coordV, V0T, kind = square_mesh(5, seed=3)
+    grid = Grid(coordV, V0T, kind)
+    for p in (0, 2, 4):
+        N = basis.num_basis(p)
+        C = np.zeros((grid.numT, N))
+        assert abs(l2_error(grid, C, lambda x, y: x * y) - 1 / 3) < 1e-13
+        C[:, 0] = 0.7
+        assert abs(l2_error(grid, C, lambda x, y: 0 * x) - 0.7 * np.sqrt(2)) < 1e-13
