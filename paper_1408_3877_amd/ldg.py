@@ -112,6 +112,7 @@ _SIGS = {
     "ldg_get_blocks_rows": [_P, _P, C.c_int64, _P],
     "ldg_get_bj_rows": [_P, _P, C.c_int64, _P],
     "ldg_apply_schur": [_P, C.c_double, _P, _P],
+    "ldg_apply_schur_lowp": [_P, C.c_double, _P, _P],
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
     "ldg_get_bj": [_P, _P],
@@ -264,10 +265,19 @@ class Solver:
         t = self.torch
         if not isinstance(x, t.Tensor):
             x = t.as_tensor(np.asarray(x, dtype=np.float64))
-        x = x.to(device=self.device, dtype=t.float64).contiguous()
-        if shape is not None:
-            assert tuple(x.shape) == tuple(shape), (x.shape, shape)
-        return x
+        if shape is not None and tuple(x.shape) != tuple(shape):
+            raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(x.shape)))
+        if x.dtype not in (t.float64, t.float32):
+            raise TypeError("expected a floating-point array, got %s" % x.dtype)
+        return x.to(device=self.device, dtype=t.float64).contiguous()
+
+    def _sampled_inputs(self, d, f, cD, gN):
+        """Check and place the sampled data of a step: d, f at the R*K volume
+        points, c_D and g_N (optional) at the R1*n_bnd boundary-edge points."""
+        nv, nb = (self.R * self.K,), (self.R1 * self.n_bnd,)
+        return (self._dev(d, nv), self._dev(f, nv),
+                None if cD is None else self._dev(cD, nb),
+                None if gN is None else self._dev(gN, nb))
 
     def _empty(self, *shape):
         return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
@@ -305,6 +315,7 @@ class Solver:
         self._check(self.lib.ldg_set_initial_samples(self.h, _ptr(s), float(t0)))
 
     def step_sampled(self, dt, d, f, cD=None, gN=None):
+        d, f, cD, gN = self._sampled_inputs(d, f, cD, gN)
         info = StepInfo()
         code = self.lib.ldg_step_sampled(self.h, float(dt), _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
                                          C.byref(info))
@@ -349,6 +360,7 @@ class Solver:
     def solve_stationary_sampled(self, d, f, cD=None, gN=None):
         """A Y = V from sampled data (no mass term, no history); the solution
         becomes the state."""
+        d, f, cD, gN = self._sampled_inputs(d, f, cD, gN)
         info = StepInfo()
         code = self.lib.ldg_solve_stationary_sampled(self.h, _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
                                                      C.byref(info))
@@ -402,6 +414,14 @@ class Solver:
         Cd = self._dev(Cm, (self.K, self.N))
         y = self._empty(self.K, self.N)
         self._check(self.lib.ldg_apply_schur(self.h, float(dt), _ptr(Cd), _ptr(y)))
+        return y
+
+    def apply_schur_lowp(self, dt, Cm):
+        """The eliminated operator in the inner precision (FP32 vectors, FP32 or
+        BF16 blocks) of a mixed-precision context, widened to FP64."""
+        Cd = self._dev(Cm, (self.K, self.N))
+        y = self._empty(self.K, self.N)
+        self._check(self.lib.ldg_apply_schur_lowp(self.h, float(dt), _ptr(Cd), _ptr(y)))
         return y
 
     def apply_full(self, dt, Y):

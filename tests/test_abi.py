@@ -28,3 +28,28 @@ def test_binding_covers_every_declared_symbol():
     from paper_1408_3877_amd import ldg
     bound = set(ldg._SIGS) | {"ldg_destroy", "ldg_last_error"}
     assert set(_declared()) <= bound
+
+
+def test_sampled_inputs_are_checked_before_any_library_call():
+    # the sampled-data entry points take raw device pointers: the binding must
+    # reject a wrong length or dtype itself (host-only: a bare binding object
+    # with no context and the CPU as its device)
+    import numpy as np
+    import pytest
+    import torch
+
+    from paper_1408_3877_amd.ldg import Solver
+    s = object.__new__(Solver)
+    s.torch, s.device = torch, torch.device("cpu")
+    s.K, s.N, s.R, s.R1, s.n_bnd = 10, 3, 3, 2, 4
+    good_v, good_b = np.zeros(30), np.zeros(8)
+    d, f, cD, gN = s._sampled_inputs(good_v, torch.zeros(30, dtype=torch.float32), good_b, None)
+    assert d.dtype == f.dtype == cD.dtype == torch.float64 and gN is None
+    with pytest.raises(ValueError):
+        s._sampled_inputs(np.zeros(29), good_v, good_b, good_b)
+    with pytest.raises(ValueError):
+        s._sampled_inputs(good_v, good_v, np.zeros(9), good_b)
+    with pytest.raises(ValueError):
+        s._sampled_inputs(good_v, good_v, None, np.zeros((2, 4)))
+    with pytest.raises(TypeError):
+        s._sampled_inputs(torch.zeros(30, dtype=torch.int64), good_v, None, None)
