@@ -55,6 +55,7 @@ def _workload(cfg):
     ("combined-p4-1024", 0),
     ("combined-p4-1024", 2),
     ("mixed-p4-512", 1),
+    ("mixed-p4-512", 2),
     ("learned-p3-256", 0),
 ])
 def test_fullsize_sampled(name, precision):
@@ -140,8 +141,17 @@ def _step_residual_rows(s, cfg, w, grid, refs, el, dt, eta):
     b3 = a2 * C0 + dt * (eta * KD - KN + a2 * F)
     bnorm = np.sqrt(np.sum(b3 ** 2) + dt ** 2 * (np.sum(J1 ** 2) + np.sum(J2 ** 2)))
     y, Zo = schur_apply_rows(grid, refs, D, C1, dt, eta, el, J=(J1, J2))
-    res_rows = np.abs(b3[el] - y).max()
-    assert res_rows <= 2e-8 * bnorm, (res_rows, bnorm)
+    # each sampled residual row against its own scale: the row of b3, or the
+    # triangle-RMS of the whole right-hand side where that row is small.  A
+    # stopping test ||r|| <= rtol ||b|| spread over K triangles leaves about
+    # rtol * rms per row; 20 x that allows for an uneven spread, while a local
+    # error of 1e-6 relative on a sampled triangle exceeds it.
+    rms = bnorm / np.sqrt(grid.numT)
+    scale = np.maximum(np.linalg.norm(b3[el], axis=1), rms)
+    ratio = np.linalg.norm(b3[el] - y, axis=1) / (1e-8 * scale)
+    print("[fullsize] residual rows / (rtol x own scale): max %.2f median %.2f"
+          % (ratio.max(), np.median(ratio)), flush=True)
+    assert ratio.max() <= 20.0, ratio.max()
     for m, Zg in enumerate((Z1, Z2)):
         assert np.abs(Zg[el] - Zo[m]).max() <= 1e-9 * np.abs(Zo[m]).max()
 
