@@ -162,7 +162,11 @@ const char* ldg_last_error(const ldg_ctx* ctx);
 ldg_status ldg_get_sizes(const ldg_ctx* ctx, ldg_sizes* out);
 
 /*
- * Physical coordinates of the points where the caller samples its data.
+ * Physical coordinates of the points where the caller samples its data: the
+ * points F_k(q_r) of the quadrature rule that the L2 projection of Sec. 3.4
+ * applies on every triangle (order max(2p, 1), the rule the main script of
+ * Sec. 4 projects with), and the Gauss points of the boundary edges that the
+ * boundary integrals of Sec. 3.6.9-3.6.11 use (J_D, K_D, K_N).
  *   kind 0: volume points of the projection rule, layout [R][K]
  *           (point r of triangle k at r*K + k);
  *   kind 1: Gauss points of the boundary edges, layout [R1][n_bnd], the
@@ -230,7 +234,14 @@ typedef enum { LDG_TIME_EULER = 0, LDG_TIME_BDF2 = 1 } ldg_time_scheme;
 ldg_status ldg_set_time_scheme(ldg_ctx* ctx, int scheme);
 ldg_status ldg_set_history(ldg_ctx* ctx, const double* C_prev, double dt_prev);
 
-/* Current C, Z1, Z2 (K x N each, element-major, caller's element order). Any may be NULL. */
+/*
+ * Current solution: the three blocks of Y = [Z1; Z2; C], the unknown vector
+ * of eq:fullSystem (Sec. 2.5), each block ordered as eq:timeDepSystem orders
+ * it, degree of freedom j of triangle k at k*N + j (index (k-1)N + j of the
+ * paper), in the caller's element order and in the basis of Sec. 2.4.1.
+ * C, Z1, Z2: K x N FP64 each, device (on_device = 1) or host, caller-owned;
+ * any may be NULL.  LDG_EINVAL for a NULL context.
+ */
 ldg_status ldg_get_solution(ldg_ctx* ctx, double* C, double* Z1, double* Z2, int on_device);
 
 /*
@@ -314,6 +325,14 @@ ldg_status ldg_get_bj_rows(ldg_ctx* ctx, const int32_t* elems, int64_t n, double
  * C, y: device K x N.
  */
 ldg_status ldg_apply_schur(ldg_ctx* ctx, double dt, const double* C, double* y);
+
+/*
+ * The same operator evaluated as the inner solves of the mixed modes do:
+ * C rounded to FP32, both halves in FP32 arithmetic with the context's FP32
+ * or BF16 copies of the blocks of the last ldg_assemble, y widened to FP64.
+ * C, y: device K x N, element-major.  LDG_EINVAL in an FP64 context.
+ */
+ldg_status ldg_apply_schur_lowp(ldg_ctx* ctx, double dt, const double* C, double* y);
 
 /*
  * Full operator of eq:fullSystem: out = (W + dt A) Y for Y = [Z1; Z2; C]
@@ -512,7 +531,15 @@ ldg_status ldg_set_initial(ldg_ctx* ctx, ldg_field_fn c0, void* user);
  * by the problem's callbacks.
  */
 ldg_status ldg_step(ldg_ctx* ctx, double dt, const ldg_problem* problem, ldg_step_info* info);
-/* Initial state from coefficients (K x N, element-major; on_device: device pointer); t = 0. */
+/*
+ * Initial state from its coefficients: C^0 given directly in the basis of
+ * Sec. 2.4.1 (K x N FP64, element-major as in ldg_get_solution; device
+ * pointer if on_device, else host), instead of the projection of c0 that
+ * the main script of Sec. 4 starts from.  Z1 and Z2 are left as they are
+ * until the next step recomputes them: W has zero Z rows in the step of
+ * Sec. 2.5, so the flux of the initial state never enters a step.  t = 0;
+ * the BDF2 history is cleared.  LDG_EINVAL for NULL arguments.
+ */
 ldg_status ldg_set_initial_dofs(ldg_ctx* ctx, const double* C, int on_device);
 /* Network parameters in and out (the same as ldg_gnn_set_params / ldg_gnn_get_params). */
 ldg_status ldg_gnn_load(ldg_ctx* ctx, const float* w, int64_t n);

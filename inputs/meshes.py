@@ -172,3 +172,41 @@ def write_medit(path, coordV, V0T, side_ids, reverse=(), dim=3, comment=None):
     lines.append("End")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def pair_numbering(V0T, kind):
+    """Renumber the triangles so that most follow a neighbour: walk the triangles
+    in their order and put each unplaced one right after the previous, followed
+    by its first unplaced neighbour (local edges 0, 1, 2).  On fk_square meshes
+    this pairs the two triangles of every cell (the diagonal is local edge 0 of
+    the lower one), cells in their original order.  Returns (V0T, kind, order)
+    with row i of the result = row order[i] of the input."""
+    V0T = np.asarray(V0T)
+    K = V0T.shape[0]
+    owner = {}
+    nbr = -np.ones((K, 3), dtype=np.int64)
+    for k in range(K):
+        for n in range(3):
+            a, b = int(V0T[k, (n + 1) % 3]), int(V0T[k, (n + 2) % 3])
+            key = (min(a, b), max(a, b))
+            if key in owner:
+                j = owner.pop(key)
+                nbr[k, n], nbr[j[0], j[1]] = j[0], k
+            else:
+                owner[key] = (k, n)
+    placed = np.zeros(K, dtype=bool)
+    order = []
+    for k in range(K):
+        if placed[k]:
+            continue
+        placed[k] = True
+        order.append(k)
+        for n in range(3):
+            j = nbr[k, n]
+            if j >= 0 and not placed[j]:
+                placed[j] = True
+                order.append(int(j))
+                break
+    order = np.array(order, dtype=np.int64)
+    return (np.ascontiguousarray(V0T[order]).astype(np.int32),
+            np.ascontiguousarray(np.asarray(kind)[order]).astype(np.int8), order)

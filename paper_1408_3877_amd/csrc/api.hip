@@ -1307,6 +1307,19 @@ ldg_status ldg_apply_schur(ldg_ctx* c, double dt, const double* Cem, double* y) 
   return check_launch(c);
 }
 
+ldg_status ldg_apply_schur_lowp(ldg_ctx* c, double dt, const double* Cem, double* y) {
+  if (!c || !Cem || !y || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  if (c->opt.precision == LDG_FP64) return fail(c, LDG_EINVAL, "context has no low-precision blocks");
+  if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
+  const Level L = level_lo(c, c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32);
+  launch_to_tiled(c->K, c->Kpad, c->N, Cem, c->u, c->st);
+  launch_cast(VT_F64, VT_F32, c->nvec, 1.0, c->u, L.p, c->st);
+  apply_op(c, L, dt, L.p, false, L.tz1, L.tz2, L.q);
+  launch_cast(VT_F32, VT_F64, c->nvec, 1.0, L.q, c->w, c->st);
+  launch_from_tiled(c->K, c->N, c->w, y, c->st);
+  return check_launch(c);
+}
+
 ldg_status ldg_apply_full(ldg_ctx* c, double dt, const double* Y, double* out) {
   if (!c || !Y || !out || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
   if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");

@@ -309,3 +309,63 @@ def test_bdf2_exact_for_quadratic_in_time(torch_mod, p):
         want = project(pr.grid, p, lambda x, y: w.c(t, x, y), pr.refs.hatM, order=2 * p + 2)
         got = to_np(s.get_solution()[0])
         assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def _numbered_mesh(mesh, n, seed):
+    from inputs.meshes import delaunay_square, edge_kinds, pair_numbering
+    if mesh == "delaunay":
+        cV, V0T = delaunay_square(n, seed)
+        kind = edge_kinds(cV, V0T, (SOUTH,))
+    else:
+        cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(SOUTH,))
+    if mesh in ("pairs", "pairs-rotated", "delaunay"):
+        V0T, kind, _ = pair_numbering(V0T, kind)
+    if mesh == "pairs-rotated":
+        V0T, kind = rotate_local_numbering(V0T, kind, seed)
+    return cV, V0T, kind
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (2, 1e-2)])
+@pytest.mark.parametrize("mesh,p", [("paper", 3), ("pairs", 3), ("pairs", 4), ("pairs-rotated", 2),
+                                    ("delaunay", 4)])
+def test_inner_precision_apply(torch_mod, precision, tol, mesh, p):
+    # the operator as the mixed-precision inner solves evaluate it (FP32 vectors,
+    # FP32 / BF16 blocks) against the oracle's FP64 eliminated matrix.  With the
+    # triangles numbered in neighbour pairs, the neighbours beside a triangle in
+    # its tile are read from the lanes beside it (the edges of 64-triangle tiles
+    # and the ragged last tile included: K = 288 or more)
+    cV, V0T, kind = _numbered_mesh(mesh, 12, 611 + p)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(612 + p)
+    K, N = pr.grid.numT, pr.N
+    D = 1.0 + 0.3 * rng.standard_normal((K, N))
+    Cv = rng.standard_normal((K, N))
+    dt = 0.011
+    s = _solver(cV, V0T, kind, p, precision=precision)
+    s.assemble(D)
+    want = (schur_matrix(Blocks(pr.grid, pr.refs, D), pr.grid, pr.refs, 1.0, dt)
+            @ Cv.reshape(-1)).reshape(K, N)
+    got = to_np(s.apply_schur_lowp(dt, Cv))
+    err = rel_l2(pr.grid.areaT, got, want)
+    print("inner-precision apply %s p=%d precision=%d: rel L2 %.2e" % (mesh, p, precision, err))
+    assert err < tol, err
+
+
+def test_inner_precision_apply_is_independent_of_the_numbering(torch_mod):
+    # the same mesh in the paper's numbering and in neighbour pairs: the FP32
+    # apply agrees to FP32 rounding once rows are matched
+    from inputs.meshes import pair_numbering
+    p = 4
+    cV, V0T, kind = square_mesh(10, seed=621, neumann_sides=(NORTH,))
+    V2, k2, order = pair_numbering(V0T, kind)
+    rng = np.random.default_rng(622)
+    K, N = V0T.shape[0], (p + 1) * (p + 2) // 2
+    D = 1.0 + 0.3 * rng.standard_normal((K, N))
+    Cv = rng.standard_normal((K, N))
+    ys = []
+    for (V, k_, perm) in ((V0T, kind, np.arange(K)), (V2, k2, order)):
+        s = _solver(cV, V, k_, p, precision=1)
+        s.assemble(D[perm])
+        ys.append(to_np(s.apply_schur_lowp(0.007, Cv[perm]))[np.argsort(perm)])
+    area = Problem(cV, V0T, kind, p).grid.areaT
+    assert rel_l2(area, ys[1], ys[0]) < 1e-6
