@@ -362,6 +362,42 @@ def step_schur(problem, C, t_new, tau, workload, data=None):
     return Cn, Z1, Z2, dict(data=data, blocks=b)
 
 
+def step_schur_cg(problem, C, t_new, tau, workload, rtol=1e-13, maxiter=200000, data=None):
+    """Implicit Euler step on the eliminated system by preconditioned CG, for
+    meshes too large for the sparse direct solve.
+
+    Valid where the eliminated matrix is symmetric positive definite: d
+    constant on every triangle (then B^m = -(A^m)^T diag(d)).  Block-Jacobi
+    preconditioner (inverses of the N x N diagonal blocks), start from C^n,
+    stop at ||rhs - S C|| <= rtol ||rhs|| in the true residual.
+    Returns (C, Z1, Z2, info) with the CG iteration count in info."""
+    pr = problem
+    if data is None:
+        data = pr.data(workload, t_new)
+    b = Blocks(pr.grid, pr.refs, data["D"])
+    Sm = schur_matrix(b, pr.grid, pr.refs, pr.eta, tau)
+    rhs = schur_rhs(b, pr.grid, pr.refs, pr.eta, tau, C, data)
+    K, N = C.shape
+    diag = np.zeros((K, N, N))
+    Sc = Sm.tocsr()
+    for i in range(N):
+        for j in range(N):
+            diag[:, i, j] = Sc[np.arange(K) * N + i, np.arange(K) * N + j].A1
+    inv = np.linalg.inv(diag)
+    prec = spla.LinearOperator(Sm.shape, matvec=lambda v: np.einsum(
+        "kij,kj->ki", inv, v.reshape(K, N)).reshape(-1), dtype=np.float64)
+    its = [0]
+
+    def count(_):
+        its[0] += 1
+
+    x, flag = spla.cg(Sc, rhs, x0=C.reshape(-1).copy(), rtol=rtol, atol=0.0, maxiter=maxiter,
+                      M=prec, callback=count)
+    res = np.linalg.norm(rhs - Sc @ x) / np.linalg.norm(rhs)
+    Cn = x.reshape(C.shape)
+    Z1, Z2 = recover_z(b, pr.grid, pr.refs, pr.eta, Cn, data)
+    return Cn, Z1, Z2, dict(data=data, blocks=b, iters=its[0], rel_residual=res, flag=flag)
+
 def full_residual(problem, blocks, data, tau, Cn, C, Z1, Z2):
     """||W Y^n + tau V - (W + tau A) Y|| / ||W Y^n + tau V|| of the full 3KN system."""
     A = system(blocks, problem.eta)

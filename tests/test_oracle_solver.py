@@ -61,7 +61,7 @@ class PolyWorkload:
         return self.c(0.0, x, y)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_stationary_patch_exact(p):
     # c in P_p, linear d, consistent data: the LDG solution is c itself
     cV, V0T, kind = square_mesh(3, seed=21, neumann_sides=(SOUTH, EAST))
@@ -74,7 +74,7 @@ def test_stationary_patch_exact(p):
     np.testing.assert_allclose(Z1, Zex, atol=1e-10)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
 def test_implicit_euler_exact_for_linear_in_time(p):
     # c = P(x)(1+t): implicit Euler reproduces c at every step (eq:fullSystem)
     cV, V0T, kind = square_mesh(3, seed=31, neumann_sides=(NORTH,))
@@ -255,6 +255,14 @@ def test_table2_convergence_rates(p, levels):
     assert abs(rate - tab["final_rate"][str(p)]) < 0.35, (errs, rate)
 
 
+def test_order_five_converges_at_order_six():
+    # beyond the paper's orders: the Table 2 problem at p = 5 (basis functions
+    # of degree 5 by recursion) converges at the LDG order p + 1 = 6
+    errs = _table2_errors(5, [0, 1, 2])
+    rate = np.log(errs[-2] / errs[-1]) / np.log(2)
+    assert abs(rate - 6.0) < 0.35, (errs, rate)
+
+
 def test_table2_p0_stagnates():
     # Table 2, p = 0: the error does not decay (stays near 0.1)
     errs = _table2_errors(0, [2, 3, 4])
@@ -278,7 +286,7 @@ def test_fig7_projection_ranges():
         assert abs(vals.min() - lo) < 1e-12 and abs(vals.max() - hi) < 1e-12, (N, vals)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_discrete_functions_do_not_depend_on_the_basis(p):
     # the same method in a Gram-Schmidt basis of the monomials (Sec. 2.4.1):
     # every tensor, projection and block changes, the functions c_h, z_h do not
@@ -334,3 +342,20 @@ def test_l2_error_absolute_scale():
         assert abs(l2_error(grid, C, lambda x, y: x * y) - 1 / 3) < 1e-13
         C[:, 0] = 0.7
         assert abs(l2_error(grid, C, lambda x, y: 0 * x) - 0.7 * np.sqrt(2)) < 1e-13
+
+
+def test_cg_step_matches_the_direct_step_on_spd_systems():
+    # the iterative oracle used at large sizes reaches the direct solve's result
+    # (element-wise constant d: SPD eliminated system)
+    from inputs.fields import LOGNORMAL, lognormal_blocks
+    from oracle.ldg import step_schur_cg
+    n, p = 8, 3
+    coordV, V0T, kind = square_mesh(n, seed=9, neumann_sides=(NORTH,))
+    pr = Problem(coordV, V0T, kind, p)
+    w = Workload(LOGNORMAL, n_cells=n, blocks=lognormal_blocks(n, 17, 1.5, block=2), block=2)
+    C0 = pr.initial(w)
+    Cd, Z1d, Z2d, _ = step_schur(pr, C0, 1e-3, 1e-3, w)
+    Cc, Z1c, Z2c, info = step_schur_cg(pr, C0, 1e-3, 1e-3, w, rtol=1e-14)
+    assert info["flag"] == 0 and info["rel_residual"] <= 1e-14 and info["iters"] > 10
+    for a, b in ((Cc, Cd), (Z1c, Z1d), (Z2c, Z2d)):
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max()
