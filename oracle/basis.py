@@ -9,10 +9,18 @@ gradient formulas in the tests).
 
 Basis index i is 0-based here (the paper's phi_{i+1}).
 
-A second orthonormal basis of the same spaces, obtained by Gram-Schmidt
-orthonormalisation of the monomials (the alternative the paper mentions in
-Sec. 2.4.1), can be selected with `use("gram-schmidt")`; the method's
-discrete functions do not depend on the basis, which the tests use as a pin.
+Orders five and six (N = 21, 28) go beyond the paper's routine, which stops
+at four; Sec. 2.4.1 names Gram-Schmidt orthonormalisation or recursion for
+higher orders.  Here the functions of total degree d = 5, 6 are the
+orthonormal collapsed-coordinate polynomials of the reference triangle,
+    psi_{a,q}(x1, x2) = c_{a,q} P_a(xi) (1 - x2)^a P_q^{(2a+1,0)}(2 x2 - 1),
+    xi = 2 x1 / (1 - x2) - 1,   c_{a,q} = sqrt(2 (2a+1) (a+q+1)),
+with a + q = d and q = 0..d in that order (P_a Legendre, P_q^{(2a+1,0)}
+Jacobi).  Each is orthogonal to every polynomial of lower degree, so they
+are exactly what Gram-Schmidt gives when the paper's fifteen functions are
+followed by these, and unlike a Gram-Schmidt of monomials they evaluate
+without cancellation.  (1 - x2)^a P_a(xi) is a polynomial; at the vertex
+x2 = 1 it equals 1 for a = 0 and 0 otherwise.
 """
 import contextlib
 from math import factorial
@@ -48,7 +56,7 @@ _TABLE = [
                          (1, 4, 0), (20, 3, 1), (90, 2, 2), (140, 1, 3), (70, 0, 4)]),
 ]
 
-MAX_P = 4
+MAX_P = 6
 
 
 def num_basis(p):
@@ -63,16 +71,61 @@ def order_of(N):
     return p
 
 
+def _extension_index(i):
+    """(a, q) of the function i >= 15: total degree d = a + q, q = 0..d."""
+    j = i - len(_TABLE)
+    for d in range(5, MAX_P + 1):
+        if j <= d:
+            return d - j, j
+        j -= d + 1
+    raise IndexError("basis index %d beyond order %d" % (i, MAX_P))
+
+
+def _collapsed(i, x1, x2, m=None):
+    """psi_{a,q} of basis index i >= 15 (m: None value, 0 d/dx1, 1 d/dx2)."""
+    from scipy.special import eval_jacobi, eval_legendre
+    a, q = _extension_index(i)
+    c = np.sqrt(2.0 * (2 * a + 1) * (a + q + 1))
+    x1, x2 = np.broadcast_arrays(np.asarray(x1, np.float64), np.asarray(x2, np.float64))
+    t = 1.0 - x2
+    top = t == 0.0
+    ts = np.where(top, 1.0, t)
+    xi = np.where(top, 0.0, 2.0 * x1 / ts - 1.0)
+    A = np.where(top, 1.0 if a == 0 else 0.0, eval_legendre(a, xi) * ts ** a)
+    B = eval_jacobi(q, 2 * a + 1, 0, 2.0 * x2 - 1.0)
+    if m is None:
+        return c * A * B
+    if np.any(top):
+        raise ValueError("gradients of the order-5/6 functions are not taken at the vertex (0, 1)")
+    # P_n' = (n + alpha + beta + 1)/2 P_{n-1}^{(alpha+1, beta+1)}
+    dL = (a + 1) / 2.0 * eval_jacobi(a - 1, 1, 1, xi) if a > 0 else 0.0 * xi
+    if m == 0:
+        return c * 2.0 * dL * t ** (a - 1) * B if a > 0 else 0.0 * x1
+    dA = (dL * (1.0 + xi) - a * eval_legendre(a, xi)) * t ** (a - 1) if a > 0 else 0.0 * x1
+    dB = (q + 2 * a + 2) / 2.0 * eval_jacobi(q - 1, 2 * a + 2, 1, 2.0 * x2 - 1.0) if q > 0 else 0.0 * x1
+    return c * (dA * B + A * 2.0 * dB)
+
+
+def _entry(i):
+    if i < len(_TABLE):
+        return _TABLE[i]
+    raise IndexError(i)
+
+
 def degree(i):
     """Total polynomial degree of basis function i (0-based)."""
-    return max(a + b for _, a, b in _TABLE[i][1])
+    if i >= len(_TABLE):
+        return sum(_extension_index(i))
+    return max(a + b for _, a, b in _entry(i)[1])
 
 
 def phi(i, x1, x2):
     """phi_hat_{i+1}(x1, x2) on the reference triangle."""
+    if i >= len(_TABLE):
+        return _collapsed(i, x1, x2)
     x1 = np.asarray(x1, dtype=np.float64)
     x2 = np.asarray(x2, dtype=np.float64)
-    s, terms = _TABLE[i]
+    s, terms = _entry(i)
     out = np.zeros(np.broadcast(x1, x2).shape)
     for c, a, b in terms:
         out = out + c * x1 ** a * x2 ** b
@@ -81,9 +134,11 @@ def phi(i, x1, x2):
 
 def grad_phi(i, m, x1, x2):
     """Component m (0 -> d/dx1, 1 -> d/dx2) of grad phi_hat_{i+1}."""
+    if i >= len(_TABLE):
+        return _collapsed(i, x1, x2, m)
     x1 = np.asarray(x1, dtype=np.float64)
     x2 = np.asarray(x2, dtype=np.float64)
-    s, terms = _TABLE[i]
+    s, terms = _entry(i)
     out = np.zeros(np.broadcast(x1, x2).shape)
     for c, a, b in terms:
         if m == 0 and a > 0:

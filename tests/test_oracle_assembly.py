@@ -88,7 +88,7 @@ def _meshes():
     return out
 
 
-@pytest.mark.parametrize("p", [1, 2, 4])
+@pytest.mark.parametrize("p", [1, 2, 4, 5])
 @pytest.mark.parametrize("mi", [0, 1, 2])
 def test_blocks_match_definitions(p, mi):
     cV, V0T, kind = _meshes()[mi]

@@ -64,28 +64,86 @@ def test_closed_forms_orders_three_and_four():
 
 
 def test_orthonormal_exact_mass():
-    # M_hat = identity (eq:hatM, Sec. 2.4.1) with a rule exact for degree 8
+    # M_hat = identity (eq:hatM, Sec. 2.4.1) with a rule exact for degree 8, and
+    # for the order-5/6 functions (against each other and against the paper's
+    # fifteen) with one exact for degree 12
     x1, x2, w = collapsed_rule(6)
     P = basis.phi_all(15, x1, x2)
     np.testing.assert_allclose(P.T @ (w[:, None] * P), np.eye(15), atol=1e-13)
+    x1, x2, w = collapsed_rule(8)
+    P = basis.phi_all(28, x1, x2)
+    np.testing.assert_allclose(P.T @ (w[:, None] * P), np.eye(28), atol=1e-13)
 
 
 def test_degrees_hierarchical():
-    degs = [basis.degree(i) for i in range(15)]
-    assert degs == [0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4]
-    for p in range(5):
+    degs = [basis.degree(i) for i in range(28)]
+    assert degs == [0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4] + [5] * 6 + [6] * 7
+    for p in range(7):
         assert basis.num_basis(p) == (p + 1) * (p + 2) // 2
         assert basis.order_of(basis.num_basis(p)) == p
+
+
+def test_orders_five_and_six_span_the_polynomials():
+    # the 28 functions span P_6 and the first 21 span P_5: least-squares fits of
+    # every monomial of degree <= 6 (<= 5) on many points are exact, and no
+    # degree-6 monomial lies in the span of the first 21
+    x, y = _tri_points(200)
+    P6 = basis.phi_all(28, x, y)
+    P5 = P6[:, :21]
+    for d in range(7):
+        for b in range(d + 1):
+            m = x ** (d - b) * y ** b
+            r6 = m - P6 @ np.linalg.lstsq(P6, m, rcond=None)[0]
+            r5 = m - P5 @ np.linalg.lstsq(P5, m, rcond=None)[0]
+            assert np.abs(r6).max() < 1e-11
+            if d <= 5:
+                assert np.abs(r5).max() < 1e-11
+            else:
+                assert np.abs(r5).max() > 1e-4
+
+
+def test_orders_five_and_six_match_a_symbolic_construction():
+    # the collapsed-coordinate functions built symbolically (sympy's Legendre
+    # and Jacobi polynomials, exact normalisation by symbolic integration over
+    # the triangle, gradients by symbolic differentiation) against the
+    # oracle's numerical evaluation, at interior points and the vertex (0, 1)
+    import sympy as sp
+    X, Y = sp.symbols("x y")
+    x, y = _tri_points(12)
+    x = np.append(x, 0.0)
+    y = np.append(y, 1.0)
+    i = 15
+    for d in (5, 6):
+        for q in range(d + 1):
+            a = d - q
+            s = 2 * X - (1 - Y)                      # (1 - y) xi
+            A = sp.expand(sp.expand_func(sp.legendre(a, sp.Symbol("t"))).subs(
+                sp.Symbol("t"), s / (1 - Y)) * (1 - Y) ** a)
+            A = sp.cancel(A)
+            B = sp.expand_func(sp.jacobi(q, 2 * a + 1, 0, 2 * Y - 1))
+            f = sp.expand(A * B)
+            nrm = sp.integrate(sp.integrate(f ** 2, (X, 0, 1 - Y)), (Y, 0, 1))
+            f = f / sp.sqrt(nrm)
+            fx, fy = sp.diff(f, X), sp.diff(f, Y)
+            for k in range(len(x)):
+                sub = {X: sp.Rational(x[k]), Y: sp.Rational(y[k])}
+                v = float(f.evalf(30, subs=sub))
+                assert abs(basis.phi(i, x[k], y[k]) - v) <= 1e-12 * max(1.0, abs(v)), (i, k)
+                if k < len(x) - 1:
+                    for m, g in enumerate((fx, fy)):
+                        gv = float(g.evalf(30, subs=sub))
+                        assert abs(basis.grad_phi(i, m, x[k], y[k]) - gv) <= 1e-11 * max(1.0, abs(gv))
+            i += 1
 
 
 def test_gradient_is_derivative_of_phi():
     x, y = _tri_points(40)
     h = 1e-6
-    for i in range(15):
+    for i in range(28):
         fd1 = (basis.phi(i, x + h, y) - basis.phi(i, x - h, y)) / (2 * h)
         fd2 = (basis.phi(i, x, y + h) - basis.phi(i, x, y - h)) / (2 * h)
-        np.testing.assert_allclose(basis.grad_phi(i, 0, x, y), fd1, atol=2e-6)
-        np.testing.assert_allclose(basis.grad_phi(i, 1, x, y), fd2, atol=2e-6)
+        np.testing.assert_allclose(basis.grad_phi(i, 0, x, y), fd1, atol=2e-6 * max(1, np.abs(fd1).max()))
+        np.testing.assert_allclose(basis.grad_phi(i, 1, x, y), fd2, atol=2e-6 * max(1, np.abs(fd2).max()))
 
 
 def test_gradient_matches_printed_gradients():

@@ -30,7 +30,7 @@ def test_theta_reverses_orientation():
             np.testing.assert_allclose(y[1], z[1], atol=1e-15)
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5, 6])
 def test_tensor_identities_exact_policy(p):
     r = RefTensors(p, "exact")
     N = r.N
