@@ -4,7 +4,10 @@
  * Method: local discontinuous Galerkin discretisation of the 2D diffusion
  * equation  dt c - div(d grad c) = f  with Dirichlet/Neumann data (Sec. 1.3,
  * eq:diffusion:nonmixed) in the mixed form z = -grad c (Sec. 2.2), modal
- * orthonormal bases of order p = 0..4 (Sec. 2.4.1), the global block system
+ * orthonormal bases of order p = 0..6 (Sec. 2.4.1: the paper's functions up
+ * to p = 4, beyond that orthonormal collapsed-coordinate polynomials by
+ * recursion, the alternative to Gram-Schmidt that Sec. 2.4.1 names), the
+ * global block system
  * eq:timeDepSystem and one implicit Euler step per call (eq:fullSystem):
  *     (W + dt A(t+dt)) Y = W Y^n + dt V(t+dt),   Y = [Z1; Z2; C],
  * or a two-step backward differentiation step, or the stationary system
@@ -46,7 +49,7 @@ typedef struct ldg_ctx ldg_ctx; /* opaque, owned by the library */
 
 typedef enum {
   LDG_OK = 0,
-  LDG_EINVAL = -1,    /* bad argument: NULL pointer, p outside 0..4, eta <= 0, dt <= 0, ... */
+  LDG_EINVAL = -1,    /* bad argument: NULL pointer, p outside 0..6, eta <= 0, dt <= 0, ... */
   LDG_EMESH = -2,     /* orientation, conformity or edge kinds inconsistent */
   LDG_ENOMEM = -3,    /* device allocation failed */
   LDG_EDEVICE = -4,   /* a HIP call failed */
@@ -89,7 +92,9 @@ typedef enum { LDG_KRYLOV_AUTO = 0, LDG_KRYLOV_GMRES = 1, LDG_KRYLOV_CG = 2 } ld
 typedef enum { LDG_QUAD_EXACT = 0, LDG_QUAD_PAPER = 1 } ldg_quad_policy;
 
 typedef struct {
-  int p;              /* polynomial order 0..4 (assert in the main script) */
+  int p;              /* polynomial order 0..6; the paper's routines stop at 4 (assert in
+                         the main script), and so do the learned preconditioner and the
+                         matrix-free apply (LDG_EINVAL for p = 5, 6 with either) */
   double eta;         /* penalty eta > 0 (prob:semidiscrete), default 1 */
   int precision;      /* ldg_precision, default LDG_FP64 */
   int precond;        /* ldg_precond, default LDG_PC_BLOCK_JACOBI */
@@ -285,7 +290,8 @@ ldg_status ldg_set_timing(ldg_ctx* ctx, int on);
  * use FP64 matrix instructions; the FP32 inner solves of the mixed modes use
  * FP32 ones (FP32 operands and sums, more accurate than BF16 blocks).  The
  * stored blocks are still assembled once per step for the block-Jacobi and
- * learned preconditioners.  Takes effect at the next apply.
+ * learned preconditioners.  Takes effect at the next apply.  p <= 4 only
+ * (LDG_EINVAL otherwise).
  */
 ldg_status ldg_set_matrix_free(ldg_ctx* ctx, int on);
 ldg_status ldg_get_kernel_stat(ldg_ctx* ctx, int kernel, ldg_kernel_stat* out);
@@ -370,7 +376,8 @@ ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* d
                                double* f, double* cD, double* gN, double* c0);
 
 /*
- * Learned preconditioner (options.precond = LDG_PC_GNN).  A graph network on
+ * Learned preconditioner (options.precond = LDG_PC_GNN; p <= 4, every
+ * ldg_gnn_* call returns LDG_EINVAL for p = 5, 6).  A graph network on
  * the element graph (nodes: triangles; edges: interior edges, both
  * directions), FP32, width 32: an encoder, three message-passing layers
  * (message relu(h_j W_m + e_kj W_e + b_m) summed over neighbours, residual

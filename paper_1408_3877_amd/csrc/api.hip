@@ -9,6 +9,10 @@
 
 using namespace ldg;
 
+// orders of the learned preconditioner and of the matrix-free apply (their
+// kernels are instantiated for N <= 15); the stored-block path runs to p = 6
+constexpr int kMaxLearnedOrder = 4;
+
 struct ldg_ctx {
   std::string err;
   // host copies of the mesh (file output) and the basis at the Lagrange points
@@ -495,6 +499,13 @@ int64_t gnn_count_max(const ldg_ctx* c) {
   return std::max(fac_num_params(c->N), gnn_num_params(c->N));
 }
 
+// the network and factor kernels exist for p <= 4 (N <= 15)
+ldg_status gnn_order_ok(ldg_ctx* c) {
+  if (c && c->p > kMaxLearnedOrder)
+    return fail(c, LDG_EINVAL, "the learned preconditioner supports p <= 4");
+  return LDG_OK;
+}
+
 ldg_status gnn_alloc(ldg_ctx* c, bool training) {
   const int64_t nf = c->Kpad * GNN_WIDTH;
   c->gnP = gnn_count(c);
@@ -943,7 +954,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (!out) return LDG_EINVAL;
   *out = nullptr;
   if (!coordV || !V0T || !edge_kind || !opt) return LDG_EINVAL;
-  if (opt->p < 0 || opt->p > 4 || !(opt->eta > 0.0) || !(opt->rtol > 0.0) || opt->restart < 1 ||
+  if (opt->p < 0 || opt->p > 6 || !(opt->eta > 0.0) || !(opt->rtol > 0.0) || opt->restart < 1 ||
       opt->restart > 200 || opt->max_iters < 1 || opt->krylov < LDG_KRYLOV_AUTO ||
       opt->krylov > LDG_KRYLOV_CG)
     return LDG_EINVAL;
@@ -951,6 +962,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (opt->precision != LDG_FP64 && !(opt->inner_rtol > 0.0 && opt->inner_rtol < 1.0))
     return LDG_EINVAL;
   if (opt->precond != LDG_PC_BLOCK_JACOBI && opt->precond != LDG_PC_GNN) return LDG_EINVAL;
+  if (opt->precond == LDG_PC_GNN && opt->p > kMaxLearnedOrder) return LDG_EINVAL;
   if (opt->quad != LDG_QUAD_EXACT && opt->quad != LDG_QUAD_PAPER) return LDG_EINVAL;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
@@ -1059,11 +1071,14 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(upload(c, c->ws, rf.ws));
   TRY(upload(c, c->sb, rf.s));
   {
-    // tensors t = G1, G2, Rd0..2, Ro(a,b) as A operands: [t][l<16][f] (FP64, FP32)
-    // and [t][f][l<32] (BF16), zero beyond N and N*N
+    // tensors t = G1, G2, Rd0..2, Ro(a,b) as A operands: [t][l < LR][f] (FP64, FP32,
+    // LR = mfma_lrows(N) >= N) and [t][f][l < 32] (BF16, N <= 28), zero beyond N
+    // and N*N
     const int NFP = (NN + 15) / 16 * 16;
-    std::vector<double> T64((size_t)14 * 16 * NFP, 0.0);
-    std::vector<float> T32((size_t)14 * 16 * NFP, 0.f);
+    const int LR = mfma_lrows(N);
+    if (N > LR || N > 32) return fail(c, LDG_EINVAL, "order beyond the assembly tables");
+    std::vector<double> T64((size_t)14 * LR * NFP, 0.0);
+    std::vector<float> T32((size_t)14 * LR * NFP, 0.f);
     std::vector<uint16_t> T16((size_t)14 * NFP * 32, 0);
     auto tens = [&](int t, int l, int f) -> double {
       if (t < 2) return rf.G[t][(size_t)l * NN + f];
@@ -1075,8 +1090,8 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       for (int l = 0; l < N; ++l)
         for (int f = 0; f < NN; ++f) {
           const double v = tens(t, l, f);
-          T64[((size_t)t * 16 + l) * NFP + f] = v;
-          T32[((size_t)t * 16 + l) * NFP + f] = (float)v;
+          T64[((size_t)t * LR + l) * NFP + f] = v;
+          T32[((size_t)t * LR + l) * NFP + f] = (float)v;
           T16[((size_t)t * NFP + f) * 32 + l] = host_bf16((float)v);
         }
     double* p64 = nullptr;
@@ -1503,12 +1518,14 @@ ldg_status ldg_solve_stationary_sampled(ldg_ctx* c, const double* d, const doubl
 }
 
 ldg_status ldg_gnn_num_params(ldg_ctx* c, int64_t* n) {
+  TRY(gnn_order_ok(c));
   if (!c || !n) return LDG_EINVAL;
   *n = gnn_count(c);
   return LDG_OK;
 }
 
 ldg_status ldg_gnn_set_params(ldg_ctx* c, const float* w, int64_t n) {
+  TRY(gnn_order_ok(c));
   if (!c || !w || n != gnn_count(c)) return fail(c, LDG_EINVAL, "parameter count");
   TRY(gnn_alloc(c, false));
   HIPCHK(c, hipMemcpyAsync(c->gP, w, n * sizeof(float), hipMemcpyHostToDevice, c->st));
@@ -1522,6 +1539,7 @@ ldg_status ldg_gnn_set_params(ldg_ctx* c, const float* w, int64_t n) {
 }
 
 ldg_status ldg_gnn_get_params(ldg_ctx* c, float* w, int64_t n) {
+  TRY(gnn_order_ok(c));
   if (!c || !w || n != gnn_count(c) || !c->gnn_params_set)
     return fail(c, LDG_EINVAL, "parameter count or no parameters");
   HIPCHK(c, hipMemcpyAsync(w, c->gP, n * sizeof(float), hipMemcpyDeviceToHost, c->st));
@@ -1529,6 +1547,7 @@ ldg_status ldg_gnn_get_params(ldg_ctx* c, float* w, int64_t n) {
 }
 
 ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
+  TRY(gnn_order_ok(c));
   if (!c || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
   TRY(gnn_alloc(c, false));
   if (Dem) launch_to_tiled(c->K, c->Kpad, c->N, Dem, c->D, c->st);
@@ -1559,6 +1578,7 @@ ldg_status ldg_gnn_set_context(ldg_ctx* c, const double* Dem, double dt) {
 }
 
 ldg_status ldg_gnn_set_mode(ldg_ctx* c, int mode) {
+  TRY(gnn_order_ok(c));
   if (!c || (mode != LDG_GNN_CORRECTION && mode != LDG_GNN_FACTOR))
     return fail(c, LDG_EINVAL, "unknown network mode");
   if (mode != c->gmode) {
@@ -1571,6 +1591,7 @@ ldg_status ldg_gnn_set_mode(ldg_ctx* c, int mode) {
 }
 
 ldg_status ldg_gnn_factor_storage(ldg_ctx* c, int bt) {
+  TRY(gnn_order_ok(c));
   if (!c || (bt != LDG_FAC_F32 && bt != LDG_FAC_BF16 && bt != LDG_FAC_FP8 && bt != LDG_FAC_FP8W))
     return fail(c, LDG_EINVAL,
                 "factor storage is LDG_FAC_F32, LDG_FAC_BF16, LDG_FAC_FP8 or LDG_FAC_FP8W");
@@ -1621,6 +1642,7 @@ ldg_status ldg_gnn_factor_export_rows(ldg_ctx* c, const int32_t* elems, int64_t 
 }
 
 ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
+  TRY(gnn_order_ok(c));
   if (!c || (loss != LDG_GNN_LOSS_MSE && loss != LDG_GNN_LOSS_ENERGY &&
              loss != LDG_GNN_LOSS_FROBENIUS && loss != LDG_GNN_LOSS_OPTSTEP))
     return fail(c, LDG_EINVAL, "unknown loss");
@@ -1632,6 +1654,7 @@ ldg_status ldg_gnn_set_loss(ldg_ctx* c, int loss) {
 }
 
 ldg_status ldg_gnn_forward(ldg_ctx* c, const float* rhat, float* out) {
+  TRY(gnn_order_ok(c));
   if (!c || !rhat || !out || !c->gnn_params_set) return fail(c, LDG_EINVAL, "bad arguments");
   if (c->gmode != LDG_GNN_CORRECTION)
     return fail(c, LDG_EINVAL, "the factored network maps no residual: ldg_gnn_factor_omega");
@@ -1825,6 +1848,7 @@ ldg_status gnn_loss_grad_tiled(ldg_ctx* c, double* loss) {
 
 ldg_status ldg_gnn_loss_grad(ldg_ctx* c, const float* rhat, const float* target, float* grad,
                              double* loss) {
+  TRY(gnn_order_ok(c));
   if (!c || !rhat || !target || !loss || !c->gnn_params_set)
     return fail(c, LDG_EINVAL, "bad arguments");
   TRY(gnn_alloc(c, true));
@@ -1838,6 +1862,7 @@ ldg_status ldg_gnn_loss_grad(ldg_ctx* c, const float* rhat, const float* target,
 
 ldg_status ldg_gnn_train_step(ldg_ctx* c, const float* rhat, const float* target, double lr,
                               double* loss) {
+  TRY(gnn_order_ok(c));
   if (!c || !rhat || !target || !loss || !c->gnn_params_set || !(lr > 0.0))
     return fail(c, LDG_EINVAL, "bad arguments");
   TRY(gnn_alloc(c, true));
@@ -1851,6 +1876,7 @@ ldg_status ldg_gnn_train_step(ldg_ctx* c, const float* rhat, const float* target
 
 ldg_status ldg_gnn_collect(ldg_ctx* c, int nsnap, const int32_t* iters, float* rhat_out,
                            float* target_out) {
+  TRY(gnn_order_ok(c));
   if (!c || nsnap < 1 || nsnap > 64 || !iters || !rhat_out || !target_out)
     return fail(c, LDG_EINVAL, "bad arguments");
   for (int s = 0; s < nsnap; ++s)
@@ -1887,6 +1913,7 @@ ldg_status ldg_set_timing(ldg_ctx* c, int on) {
 
 ldg_status ldg_set_matrix_free(ldg_ctx* c, int on) {
   if (!c) return LDG_EINVAL;
+  if (on && c->p > kMaxLearnedOrder) return fail(c, LDG_EINVAL, "the matrix-free apply supports p <= 4");
   if (on && !c->mf64) {
     // A-operand tables of the 14 tensors (G1, G2, Rd0..2, Ro(n, n+)), FP64 and FP32
     const RefData& rf = c->ref;

@@ -9,6 +9,32 @@
 
 namespace ldg {
 
+// Kernel instances per N = (p+1)(p+2)/2.  The stored-block path (projection,
+// assembly, block-Jacobi, operator apply, Krylov) runs up to p = 6; the
+// learned preconditioner's network and factor kernels and the matrix-free
+// apply up to p = 4 (the library rejects higher orders for those options).
+// An N outside the list launches nothing.
+#define LDG_SWITCH_N(N, CALL)                                   \
+  switch (N) {                                                  \
+    case 1: { constexpr int NT = 1; CALL; } break;              \
+    case 3: { constexpr int NT = 3; CALL; } break;              \
+    case 6: { constexpr int NT = 6; CALL; } break;              \
+    case 10: { constexpr int NT = 10; CALL; } break;            \
+    case 15: { constexpr int NT = 15; CALL; } break;            \
+    default: break;                                             \
+  }
+#define LDG_SWITCH_N_P6(N, CALL)                                \
+  switch (N) {                                                  \
+    case 1: { constexpr int NT = 1; CALL; } break;              \
+    case 3: { constexpr int NT = 3; CALL; } break;              \
+    case 6: { constexpr int NT = 6; CALL; } break;              \
+    case 10: { constexpr int NT = 10; CALL; } break;            \
+    case 15: { constexpr int NT = 15; CALL; } break;            \
+    case 21: { constexpr int NT = 21; CALL; } break;            \
+    case 28: { constexpr int NT = 28; CALL; } break;            \
+    default: break;                                             \
+  }
+
 // ---- stored N x N blocks: 16 bytes per lane and load ----------------------
 // Block entry f = i*N + j of (triangle k, slot s) lives in group g = f / W at
 //   [k/64][s][g][k%64][f%W],  W = 16 bytes / sizeof(storage type).

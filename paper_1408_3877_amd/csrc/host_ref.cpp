@@ -1,4 +1,5 @@
-// Reference element on the host: modal basis (Sec. 2.4.1), Gauss rules
+// Reference element on the host: modal basis (Sec. 2.4.1; orders 5 and 6 by
+// recursion), Gauss rules
 // (Sec. 3.3), reference tensors (Sec. 3.6), computed once per context.
 #include <cmath>
 #include <stdexcept>
@@ -59,7 +60,83 @@ double ipow(double x, int a) {
 }
 }  // namespace
 
+// Orders 5 and 6 (basis indices 15..27): the orthonormal collapsed-coordinate
+// polynomials of total degree d = a + q, q = 0..d in that order,
+//   psi = c A_a(x1, x2) J_q(2 x2 - 1),  c = sqrt(2 (2a+1) (a+q+1)),
+// A_a = (1 - x2)^a P_a(2 x1 / (1 - x2) - 1) (P_a Legendre), J_q the Jacobi
+// polynomial P_q^{(2a+1,0)}.  Each is orthogonal to all polynomials of lower
+// degree, so the paper's fifteen functions followed by these are orthonormal
+// (the recursion alternative to Gram-Schmidt of Sec. 2.4.1).  Both factors
+// come from three-term recurrences; A_a is carried as a polynomial, so the
+// vertex x2 = 1 needs no special case.
+namespace {
+constexpr int kPaperFunctions = 15;
+
+void collapsed_index(int i, int& a, int& q) {
+  int j = i - kPaperFunctions;
+  for (int d = 5; d <= 6; ++d) {
+    if (j <= d) {
+      a = d - j;
+      q = j;
+      return;
+    }
+    j -= d + 1;
+  }
+  throw std::out_of_range("basis index");
+}
+
+// value v = psi, gradient (gx, gy)
+void collapsed_psi(int i, double x1, double x2, double& v, double& gx, double& gy) {
+  int a, q;
+  collapsed_index(i, a, q);
+  // A_n: (n+1) A_{n+1} = (2n+1) s A_n - n t^2 A_{n-1},  s = 2 x1 - t, t = 1 - x2
+  const double t = 1.0 - x2, s = 2.0 * x1 - t;
+  double A = 1.0, Ax = 0.0, Ay = 0.0;            // A_0
+  if (a >= 1) {
+    double Am = 1.0, Amx = 0.0, Amy = 0.0;       // A_{n-1}
+    A = s; Ax = 2.0; Ay = 1.0;                   // A_1
+    for (int n = 1; n < a; ++n) {
+      const double t2 = t * t, t2y = -2.0 * t;
+      const double An = ((2 * n + 1) * s * A - n * t2 * Am) / (n + 1);
+      const double Anx = ((2 * n + 1) * (2.0 * A + s * Ax) - n * t2 * Amx) / (n + 1);
+      const double Any = ((2 * n + 1) * (A + s * Ay) - n * (t2y * Am + t2 * Amy)) / (n + 1);
+      Am = A; Amx = Ax; Amy = Ay;
+      A = An; Ax = Anx; Ay = Any;
+    }
+  }
+  // J_n = P_n^{(al,0)}(e), e = 2 x2 - 1:
+  // 2n(n+al)(2n+al-2) J_n = (2n+al-1)((2n+al)(2n+al-2) e + al^2) J_{n-1}
+  //                         - 2(n+al-1)(n-1)(2n+al) J_{n-2}
+  const double al = 2.0 * a + 1.0, e = 2.0 * x2 - 1.0;
+  double J = 1.0, Je = 0.0;                      // J_0 and d/de
+  if (q >= 1) {
+    double Jm = 1.0, Jme = 0.0;
+    J = (al + 1.0) + (al + 2.0) * (e - 1.0) / 2.0;
+    Je = (al + 2.0) / 2.0;
+    for (int n = 2; n <= q; ++n) {
+      const double c0 = 2.0 * n * (n + al) * (2 * n + al - 2);
+      const double c1 = (2 * n + al - 1) * (2 * n + al) * (2 * n + al - 2);
+      const double c2 = (2 * n + al - 1) * al * al;
+      const double c3 = 2.0 * (n + al - 1) * (n - 1) * (2 * n + al);
+      const double Jn = ((c1 * e + c2) * J - c3 * Jm) / c0;
+      const double Jne = (c1 * J + (c1 * e + c2) * Je - c3 * Jme) / c0;
+      Jm = J; Jme = Je;
+      J = Jn; Je = Jne;
+    }
+  }
+  const double c = std::sqrt(2.0 * (2 * a + 1) * (a + q + 1));
+  v = c * A * J;
+  gx = c * Ax * J;
+  gy = c * (Ay * J + A * 2.0 * Je);
+}
+}  // namespace
+
 double phi_hat(int i, double x1, double x2) {
+  if (i >= kPaperFunctions) {
+    double v, gx, gy;
+    collapsed_psi(i, x1, x2, v, gx, gy);
+    return v;
+  }
   const Poly& P = poly(i);
   double v = 0.0;
   for (int t = 0; t < P.nt; ++t) v += P.t[t].c * ipow(x1, P.t[t].a) * ipow(x2, P.t[t].b);
@@ -67,6 +144,11 @@ double phi_hat(int i, double x1, double x2) {
 }
 
 double dphi_hat(int i, int m, double x1, double x2) {
+  if (i >= kPaperFunctions) {
+    double v, gx, gy;
+    collapsed_psi(i, x1, x2, v, gx, gy);
+    return m == 0 ? gx : gy;
+  }
   const Poly& P = poly(i);
   double v = 0.0;
   for (int t = 0; t < P.nt; ++t) {
@@ -130,7 +212,7 @@ void collapsed(int n, std::vector<double>& q1, std::vector<double>& q2, std::vec
 
 // Volume rule of order max(2p,1) used for the L2 projection (main script):
 // the printed rules of orders 1, 2, 4 and 6 (Sec. 3.3, quadRule2D) and, for
-// order 8, the 8 x 8 collapsed Gauss rule.
+// the orders 8, 10, 12 of p = 4, 5, 6, the n x n collapsed Gauss rule, n = order.
 void projection_rule(int p, std::vector<double>& q1, std::vector<double>& q2,
                      std::vector<double>& w) {
   const int ord = p == 0 ? 1 : 2 * p;

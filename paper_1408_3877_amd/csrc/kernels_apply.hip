@@ -28,6 +28,9 @@ __device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
 template <class T> constexpr int lds_w() { return sizeof(T) == 4 ? 4 : 1; }
 template <int N, class T> constexpr int row_stride() { return (N + lds_w<T>() - 1) / lds_w<T>() * lds_w<T>(); }
 template <int N, class T> constexpr int ref_size() { return NREF * N * row_stride<N, T>(); }
+// FP64 matrices of N = 28 (86 KiB) exceed 64 KiB of LDS: those kernels read
+// them from global memory, where FP64 rows have the same unpadded layout
+template <int N, class T> constexpr bool refs_in_lds() { return ref_size<N, T>() * sizeof(T) <= 65536; }
 
 template <int N, class T>
 __device__ inline void load_refs(T* sm, const double* __restrict__ g) {
@@ -85,8 +88,13 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
                                               T* __restrict__ Z2) {
   constexpr int NN = N * N;
   constexpr bool SC = sizeof(T) == 4;
-  __shared__ __align__(16) T sm[SC ? 1 : ref_size<N, T>()];
-  if constexpr (!SC) load_refs<N, T>(sm, refs);
+  constexpr bool LDSR = !SC && refs_in_lds<N, T>();
+  __shared__ __align__(16) T smem[LDSR ? ref_size<N, T>() : 1];
+  const T* sm = rT;
+  if constexpr (LDSR) {
+    load_refs<N, T>(smem, refs);
+    sm = smem;
+  }
   auto mv = [&](int ref, const T* x, T* acc, T scale) {
     if constexpr (SC) mv_add_s<N, T>(rT + ref * NN, x, acc, scale);
     else mv_add<N, T>(sm + ref * N * row_stride<N, T>(), x, acc, scale);
@@ -230,9 +238,17 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
                                              const T* __restrict__ Z2, double alpha, double tau,
                                              double eta, T* __restrict__ y,
                                              double* __restrict__ partials) {
-  __shared__ __align__(16) T sm[ref_size<N, T>()];
+  constexpr bool LDSR = refs_in_lds<N, T>();
+  static_assert(LDSR || sizeof(T) == 8, "FP32 reference matrices always fit in LDS");
+  __shared__ __align__(16) T smem[LDSR ? ref_size<N, T>() : 1];
   __shared__ double red[4];
-  load_refs<N, T>(sm, refs);
+  const T* sm;
+  if constexpr (LDSR) {
+    load_refs<N, T>(smem, refs);
+    sm = smem;
+  } else {
+    sm = reinterpret_cast<const T*>(refs);
+  }
   const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (k < g.Kpad) s = div_row<N, T, BT, BLOCKS>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
@@ -335,26 +351,16 @@ namespace {
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }
 
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
                  const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
                  hipStream_t st) {
   const unsigned nb = nblk(g.Kpad, 256);
   if (vt == VT_F64) {
-    LDG_SWITCH_N(N, (k_grad<NT, double><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_grad<NT, double><<<nb, 256, 0, st>>>(
                         g, refs, refs, (const double*)C, (const double*)J1, (const double*)J2,
                         (double*)Z1, (double*)Z2)));
   } else {
-    LDG_SWITCH_N(N, (k_grad<NT, float><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_grad<NT, float><<<nb, 256, 0, st>>>(
                         g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
                         (float*)Z1, (float*)Z2)));
   }
@@ -367,24 +373,24 @@ void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const v
   double* parts = red ? red->partials : nullptr;
   if (blocks == nullptr) {   // matrix-free: the terms without blocks
     if (vt == VT_F64) {
-      LDG_SWITCH_N(N, (k_div<NT, double, double, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, double, double, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const double*)C, (const double*)Z1,
                           (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
     } else {
-      LDG_SWITCH_N(N, (k_div<NT, float, float, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const float*)C, (const float*)Z1, (const float*)Z2,
                           alpha, tau, eta, (float*)y, parts)));
     }
   } else if (vt == VT_F64) {
-    LDG_SWITCH_N(N, (k_div<NT, double, double, true><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, double, double, true><<<nb, 256, 0, st>>>(
                         g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
                         (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
   } else if (bt == BT_F32) {
-    LDG_SWITCH_N(N, (k_div<NT, float, float, true><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true><<<nb, 256, 0, st>>>(
                         g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
                         (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   } else {
-    LDG_SWITCH_N(N, (k_div<NT, float, bf16, true><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true><<<nb, 256, 0, st>>>(
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
                         (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   }
@@ -396,13 +402,13 @@ void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const 
   const unsigned nb = nblk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
   if (vt == VT_F64) {
-    LDG_SWITCH_N(N, (k_bj_apply<NT, double, double><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_bj_apply<NT, double, double><<<nb, 256, 0, st>>>(
                         g, (const double*)bj, (const double*)r, (double*)z, parts)));
   } else if (bt == BT_F32) {
-    LDG_SWITCH_N(N, (k_bj_apply<NT, float, float><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_bj_apply<NT, float, float><<<nb, 256, 0, st>>>(
                         g, (const float*)bj, (const float*)r, (float*)z, parts)));
   } else {
-    LDG_SWITCH_N(N, (k_bj_apply<NT, float, bf16><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_bj_apply<NT, float, bf16><<<nb, 256, 0, st>>>(
                         g, (const bf16*)bj, (const float*)r, (float*)z, parts)));
   }
   if (red) reduce_partials((int)nb, red->partials, red->result, st);

@@ -52,7 +52,7 @@ __device__ inline typename Mfma<PREC>::B b_operand(const double* __restrict__ D,
 }
 
 // A operand: tensor t, k-step ks, 16-row tile ft; layouts
-//   PREC 0, 1: [t][16][NFP] (l-major), PREC 2: [t][NFP][32] (f-major, l contiguous)
+//   PREC 0, 1: [t][mfma_lrows(N)][NFP] (l-major), PREC 2: [t][NFP][32] (f-major, l contiguous)
 template <int N, int PREC>
 __device__ inline typename Mfma<PREC>::A a_operand(const void* __restrict__ T, int t, int ks,
                                                    int ft, int lane) {
@@ -66,7 +66,7 @@ __device__ inline typename Mfma<PREC>::A a_operand(const void* __restrict__ T, i
   } else {
     using A = typename Mfma<PREC>::A;
     const A* p = static_cast<const A*>(T);
-    return p[((int64_t)t * 16 + 4 * ks + q) * NFP + f];
+    return p[((int64_t)t * mfma_lrows(N) + 4 * ks + q) * NFP + f];
   }
 }
 
@@ -217,25 +217,15 @@ namespace {
 inline unsigned nblk64(int64_t Kpad) { return (unsigned)(Kpad / 64); }
 }
 
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 void launch_assemble_mfma(int N, int bt, const Geo& g, const double* D, const void* T, void* blocks,
                           hipStream_t st) {
   const unsigned nb = nblk64(g.Kpad);
   if (bt == BT_F64) {
-    LDG_SWITCH_N(N, (k_assemble_mfma<NT, 0><<<nb, 256, 0, st>>>(g, D, T, (double*)blocks)));
+    LDG_SWITCH_N_P6(N, (k_assemble_mfma<NT, 0><<<nb, 256, 0, st>>>(g, D, T, (double*)blocks)));
   } else if (bt == BT_F32) {
-    LDG_SWITCH_N(N, (k_assemble_mfma<NT, 1><<<nb, 256, 0, st>>>(g, D, T, (float*)blocks)));
+    LDG_SWITCH_N_P6(N, (k_assemble_mfma<NT, 1><<<nb, 256, 0, st>>>(g, D, T, (float*)blocks)));
   } else {
-    LDG_SWITCH_N(N, (k_assemble_mfma<NT, 2><<<nb, 256, 0, st>>>(g, D, T, (bf16*)blocks)));
+    LDG_SWITCH_N_P6(N, (k_assemble_mfma<NT, 2><<<nb, 256, 0, st>>>(g, D, T, (bf16*)blocks)));
   }
 }
 

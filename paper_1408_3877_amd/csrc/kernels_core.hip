@@ -128,9 +128,15 @@ __global__ void __launch_bounds__(256) k_boundary(Geo g, int64_t nbe,
 // Block-Jacobi setup: the diagonal block of the eliminated operator,
 //   P_k = alpha 2|T_k| I + tau [ eta S'_kk - (1/2|T_k|) sum_m B^m_kk A^m_kk
 //                          + sum_{n interior} |E_kn| / (2 * 2|T_k+|) U_kn S_hat_off(:,:,n+,n) ],
-// then its inverse by Gauss-Jordan elimination.  Sixteen lanes per triangle,
-// lane i owns row i; pivot rows travel by lane shuffles.
+// then its inverse by Gauss-Jordan elimination with partial pivoting.  LPT
+// lanes per triangle (16 up to N = 15, 32 for N = 21, 28), lane i owns row i;
+// the pivot search is a max-reduction over the lanes, rows are exchanged and
+// pivot rows broadcast by lane shuffles.  The reference matrices sit in LDS
+// while they fit in 64 KiB (N <= 21), else they are read from global memory.
 // ---------------------------------------------------------------------------
+template <int N> constexpr int bj_lanes() { return N <= 16 ? 16 : 32; }
+template <int N> constexpr bool refs_in_lds() { return NREF * N * N * 8 <= 64 * 1024; }
+
 template <int N>
 __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restrict__ refs,
                                                   const double* __restrict__ blocks, double alpha,
@@ -138,11 +144,16 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
                                                   int* __restrict__ status) {
   constexpr int NN = N * N;
   constexpr int NP = npairs(N);
-  __shared__ double sm[NREF * N * N];
-  load_refs<N>(sm, refs);
+  constexpr int LPT = bj_lanes<N>();
+  __shared__ double smem[refs_in_lds<N>() ? NREF * N * N : 1];
+  const double* sm = refs;
+  if constexpr (refs_in_lds<N>()) {
+    load_refs<N>(smem, refs);
+    sm = smem;
+  }
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k = gid >> 4;
-  const int i = (int)(gid & 15);
+  const int64_t k = gid / LPT;
+  const int i = (int)(gid % LPT);
   const bool elem_ok = k < g.K;
   const bool row_ok = elem_ok && i < N;
   const int64_t Kp = g.Kpad;
@@ -228,28 +239,45 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
 #pragma unroll
     for (int c = 0; c < N; ++c) a[c] = (c == i ? alpha * area2 : 0.0) + tau * acc[c];
   }
-  // Gauss-Jordan without pivoting within the 16-lane group
+  // Gauss-Jordan with partial pivoting within the LPT-lane group.  Every lane
+  // of the wave runs every shuffle; rows i >= N never become pivots.
   bool bad = false;
 #pragma unroll
   for (int c = 0; c < N; ++c) {
-    const double piv = __shfl(a[c], c, 16);
-    bad |= !(fabs(piv) > 0.0);
-    const double ip = 1.0 / piv;
-    double ra[N], rb[N];
+    // pivot: largest |a[c]| over rows c..N-1 (the lowest row among equals)
+    double best = (i >= c && i < N) ? fabs(a[c]) : -1.0;
+    int r = i;
+#pragma unroll
+    for (int off = LPT / 2; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, LPT);
+      const int orow = __shfl_xor(r, off, LPT);
+      if (ob > best || (ob == best && orow < r)) {
+        best = ob;
+        r = orow;
+      }
+    }
+    // exchange rows c and r (a no-op when r == c)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      ra[j] = __shfl(a[j], c, 16) * ip;
-      rb[j] = __shfl(b[j], c, 16) * ip;
+      const double ac = __shfl(a[j], c, LPT), ar = __shfl(a[j], r, LPT);
+      const double bc = __shfl(b[j], c, LPT), br = __shfl(b[j], r, LPT);
+      if (i == c) { a[j] = ar; b[j] = br; }
+      else if (i == r) { a[j] = ac; b[j] = bc; }
     }
+    const double piv = __shfl(a[c], c, LPT);
+    bad |= !(fabs(piv) > 0.0);
+    const double ip = 1.0 / piv;
     const double fct = a[c];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
+      const double pa = __shfl(a[j], c, LPT) * ip;
+      const double pb = __shfl(b[j], c, LPT) * ip;
       if (i == c) {
-        a[j] = ra[j];
-        b[j] = rb[j];
+        a[j] = pa;
+        b[j] = pb;
       } else {
-        a[j] -= fct * ra[j];
-        b[j] -= fct * rb[j];
+        a[j] -= fct * pa;
+        b[j] -= fct * pb;
       }
     }
   }
@@ -421,16 +449,6 @@ namespace {
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }
 
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 void launch_lagrange(int64_t K, int N, int nL, const double* C, bool tiled, const double* phiL,
                      double* out, hipStream_t st) {
   if (K * nL == 0) return;
@@ -439,7 +457,7 @@ void launch_lagrange(int64_t K, int N, int nL, const double* C, bool tiled, cons
 
 void launch_project(int N, int64_t K, int64_t Kpad, int R, const double* samples, const double* W,
                     double* out, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_project<NT><<<nblk(Kpad, 256), 256, R * NT * sizeof(double), st>>>(
+  LDG_SWITCH_N_P6(N, (k_project<NT><<<nblk(Kpad, 256), 256, R * NT * sizeof(double), st>>>(
                       K, Kpad, R, samples, W, out)));
 }
 
@@ -448,7 +466,7 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
                      int64_t nbnd, const double* D, double eta, double* J1, double* J2,
                      double* KDN, hipStream_t st) {
   if (nbe == 0) return;
-  LDG_SWITCH_N(N, (k_boundary<NT><<<nblk(nbe, 256), 256, 0, st>>>(g, nbe, belem, R1, Wb, ws, cD,
+  LDG_SWITCH_N_P6(N, (k_boundary<NT><<<nblk(nbe, 256), 256, 0, st>>>(g, nbe, belem, R1, Wb, ws, cD,
                                                                    gN, nbnd, D, eta, J1, J2, KDN)));
 }
 
@@ -457,7 +475,7 @@ void launch_boundary(int N, const Geo& g, int64_t nbe, const int32_t* belem, int
 
 void launch_bj_setup(int N, const Geo& g, const double* refs, const double* blocks, double alpha,
                      double tau, double eta, double* bj, int* status, hipStream_t st) {
-  LDG_SWITCH_N(N, (k_bj_setup<NT><<<nblk(g.Kpad * 16, 256), 256, 0, st>>>(
+  LDG_SWITCH_N_P6(N, (k_bj_setup<NT><<<nblk(g.Kpad * bj_lanes<NT>(), 256), 256, 0, st>>>(
                       g, refs, blocks, alpha, tau, eta, bj, status)));
 }
 

@@ -448,16 +448,6 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 // W storage BW and O storage BO: (F32, F32), (BF16, BF16), (BF16, FP8), (FP8, FP8)
 #define LDG_SWITCH_FAC(FS, CALL)                                \
   if ((FS).wt == BT_FP8) {                                      \

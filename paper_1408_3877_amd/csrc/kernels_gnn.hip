@@ -572,16 +572,6 @@ namespace {
 inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 }
 
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 // flat parameter layouts: trunk = [W_enc (nin x W), b_enc, 3 layers], then the
 // node decoder [W_dec (W x N), b_dec] (residual correction, nin = 2N + 3) or the
 // edge head [w_hk (W), w_hj (W), w_e (EIN), w_o, b_o] (factored, nin = N + 3)

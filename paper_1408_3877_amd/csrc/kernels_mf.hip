@@ -181,16 +181,6 @@ __global__ void __launch_bounds__(256) k_mf_blocks(Geo g, const double* __restri
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-#define LDG_SWITCH_N(N, CALL)                                   \
-  switch (N) {                                                  \
-    case 1: { constexpr int NT = 1; CALL; } break;              \
-    case 3: { constexpr int NT = 3; CALL; } break;              \
-    case 6: { constexpr int NT = 6; CALL; } break;              \
-    case 10: { constexpr int NT = 10; CALL; } break;            \
-    case 15: { constexpr int NT = 15; CALL; } break;            \
-    default: break;                                             \
-  }
-
 void launch_mf_blocks(int N, int vt, const Geo& g, const double* D, const void* table,
                       const void* C, const void* Z1, const void* Z2, double tau, void* y,
                       const Reducer* red, hipStream_t st) {

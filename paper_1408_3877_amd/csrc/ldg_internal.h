@@ -20,6 +20,10 @@ __host__ __device__ inline int64_t vidx(int64_t k, int i, int N) {
   return (k >> 6) * (int64_t)(TILE * N) + (int64_t)i * TILE + (k & 63);
 }
 __host__ __device__ constexpr int npairs(int N) { return (N * N + 1) / 2; }
+// rows (coefficient index l) of the FP64 / FP32 A-operand tables of the MFMA
+// block assembly: its k-steps of four cover l < 4 ceil(N / 4); 16 rows for
+// N <= 15, 24 for N = 21, 28 for N = 28
+__host__ __device__ constexpr int mfma_lrows(int N) { return N <= 16 ? 16 : (N + 3) / 4 * 4; }
 __host__ __device__ inline int64_t pidx(int64_t k, int s, int pr, int ns, int np) {
   return ((((k >> 6) * ns + s) * (int64_t)np + pr) * TILE + (k & 63)) * 2;
 }
