@@ -341,6 +341,21 @@ ldg_status ldg_apply_schur(ldg_ctx* ctx, double dt, const double* C, double* y);
 ldg_status ldg_apply_schur_lowp(ldg_ctx* ctx, double dt, const double* C, double* y);
 
 /*
+ * ldg_apply_schur without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same operator, same kernels, same result bit for bit.
+ * Its four temporary vectors live in a fixed 64 MiB device workspace that the
+ * library holds on every device it runs on until the process ends, so the
+ * mesh must satisfy 4 * Kpad * N * 8 <= 64 MiB, i.e. Kpad * N <= 2,097,152
+ * (Kpad = K rounded up to a multiple of 64): larger meshes get LDG_EINVAL
+ * before any launch.  The call allocates nothing and frees nothing.  All
+ * contexts on one device share the workspace: calls that can overlap on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller.  C, y: device K x N, element-major, caller-owned.
+ */
+ldg_status ldg_apply_schur_noalloc(ldg_ctx* ctx, double dt, const double* C, double* y);
+
+/*
  * Full operator of eq:fullSystem: out = (W + dt A) Y for Y = [Z1; Z2; C]
  * (device, 3 K N, each part element-major), blocks of the last ldg_assemble.
  */

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -917,6 +918,42 @@ ldg_status fail_noctx(ldg_status s, const std::string& msg) {
 
 extern "C" {
 
+// ---- workspace of the allocation-free operator apply --------------------
+// ldg_apply_schur_noalloc keeps its four tiled FP64 vectors (C, Z1, Z2, y; Kpad*N
+// values each) in this fixed device array instead of the context's buffers.
+// Every device the library runs on holds its own copy until the process ends.
+// In host code `scratch` only names the symbol: its device address is taken
+// once per device (with that device current) by noalloc_setup and kept in
+// g_scratch; kernels receive that address, never the array's name.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;   // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// called by ldg_create with the context's device current
+ldg_status noalloc_setup(ldg_ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return fail(c, LDG_EDEVICE, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[c->device]) return LDG_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(c, LDG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[c->device] = p;
+  return LDG_OK;
+}
+
+void* noalloc_workspace(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
+}  // namespace
+
 ldg_status ldg_options_default(ldg_options* o) {
   if (!o) return LDG_EINVAL;
   std::memset(o, 0, sizeof(*o));
@@ -969,6 +1006,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   c->opt = *opt;
   c->st = static_cast<hipStream_t>(opt->stream);
   HIPCHK(c, hipGetDevice(&c->device));
+  TRY(noalloc_setup(c));
   HostMesh hm;
   bool mesh_err = false;
   const std::string msg = build_mesh(coordV, numV, V0T, K, edge_kind, hm, &mesh_err);
@@ -1332,6 +1370,37 @@ ldg_status ldg_apply_schur_lowp(ldg_ctx* c, double dt, const double* Cem, double
   apply_op(c, L, dt, L.p, false, L.tz1, L.tz2, L.q);
   launch_cast(VT_F32, VT_F64, c->nvec, 1.0, L.q, c->w, c->st);
   launch_from_tiled(c->K, c->N, c->w, y, c->st);
+  return check_launch(c);
+}
+
+ldg_status ldg_apply_schur_noalloc(ldg_ctx* c, double dt, const double* Cem, double* y) {
+  if (!c || !Cem || !y || !(dt > 0.0)) return fail(c, LDG_EINVAL, "bad arguments");
+  if (!c->blocks_ready) return fail(c, LDG_EINVAL, "no blocks assembled");
+  const size_t need = 4 * (size_t)c->nvec * sizeof(double);
+  if (need > kNoAllocBytes)
+    return fail(c, LDG_EINVAL, "mesh too large for the allocation-free apply: it needs " +
+                                   std::to_string(need) + " bytes of workspace, the limit is " +
+                                   std::to_string(kNoAllocBytes) +
+                                   " (Kpad * N <= 2097152, Kpad = K rounded up to 64)");
+  double* ws = static_cast<double*>(noalloc_workspace(c->device));
+  if (!ws) return fail(c, LDG_EDEVICE, "workspace address of this device not set up");
+  double* u = ws;
+  double* z1 = u + c->nvec;
+  double* z2 = z1 + c->nvec;
+  double* w = z2 + c->nvec;
+  // every part of the workspace the kernels read is written first in this call
+  // (padding rows included), so no clearing is needed
+  launch_to_tiled(c->K, c->Kpad, c->N, Cem, u, c->st);
+  launch_grad(c->N, VT_F64, c->geo, c->refs, c->refs32, u, nullptr, nullptr, z1, z2, c->st);
+  if (c->mf) {
+    launch_div(c->N, VT_F64, BT_F64, c->geo, c->refs, nullptr, u, z1, z2, c->alpha, dt,
+               c->opt.eta, w, c->st, nullptr);
+    launch_mf_blocks(c->N, VT_F64, c->geo, c->D, c->mf64, u, z1, z2, dt, w, nullptr, c->st);
+  } else {
+    launch_div(c->N, VT_F64, BT_F64, c->geo, c->refs, c->blocks, u, z1, z2, c->alpha, dt,
+               c->opt.eta, w, c->st, nullptr);
+  }
+  launch_from_tiled(c->K, c->N, w, y, c->st);
   return check_launch(c);
 }
 

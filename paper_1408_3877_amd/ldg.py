@@ -113,6 +113,7 @@ _SIGS = {
     "ldg_get_bj_rows": [_P, _P, C.c_int64, _P],
     "ldg_apply_schur": [_P, C.c_double, _P, _P],
     "ldg_apply_schur_lowp": [_P, C.c_double, _P, _P],
+    "ldg_apply_schur_noalloc": [_P, C.c_double, _P, _P],
     "ldg_apply_full": [_P, C.c_double, _P, _P],
     "ldg_bj_setup": [_P, C.c_double],
     "ldg_get_bj": [_P, _P],
@@ -422,6 +423,17 @@ class Solver:
         Cd = self._dev(Cm, (self.K, self.N))
         y = self._empty(self.K, self.N)
         self._check(self.lib.ldg_apply_schur_lowp(self.h, float(dt), _ptr(Cd), _ptr(y)))
+        return y
+
+    def apply_schur_noalloc(self, dt, Cm, y):
+        """apply_schur into the caller's y (device K x N FP64) through the
+        allocation-free entry point (library workspace, no allocation)."""
+        Cd = self._dev(Cm, (self.K, self.N))
+        t = self.torch
+        if (not isinstance(y, t.Tensor) or tuple(y.shape) != (self.K, self.N) or
+                y.dtype != t.float64 or y.device != self.device or not y.is_contiguous()):
+            raise ValueError("y must be a contiguous float64 device tensor of shape (K, N)")
+        self._check(self.lib.ldg_apply_schur_noalloc(self.h, float(dt), _ptr(Cd), _ptr(y)))
         return y
 
     def apply_full(self, dt, Y):
