@@ -100,7 +100,12 @@ typedef struct {
   int precond;        /* ldg_precond, default LDG_PC_BLOCK_JACOBI */
   double rtol;        /* relative residual of the full system, default 1e-8; FP64 rounding
                          bounds what is reachable near 1e-16 ||A|| ||Y|| / ||V|| */
-  int restart;        /* GMRES restart length m in 1..200, default 30 */
+  int restart;        /* GMRES restart length m in 1..200, default 30.  A GMRES cycle
+                         that runs all m iterations and halves neither its own residual
+                         estimate nor the FP64 residual doubles m for the rest of the
+                         context's life, while 2m stays within the system size K N and
+                         the basis within 2 GiB (indefinite steps, where restarted GMRES
+                         stalls; on large meshes the bound keeps m fixed) */
   int max_iters;      /* total Krylov iterations per step, default 5000 */
   void* stream;       /* hipStream_t for all device work */
   int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
@@ -130,6 +135,7 @@ typedef struct {
                           because <r, P r> < 0.25 <r, BJ^{-1} r> */
   int fallback_reason; /* ldg_fallback of the last fallback taken */
   int bdf_order;       /* 1: implicit Euler step, 2: two-step backward differentiation */
+  int gmres_restart;   /* GMRES restart length after the step (see ldg_options.restart) */
 } ldg_step_info;
 
 /*

@@ -55,7 +55,9 @@ struct ldg_ctx {
   int* status = nullptr;
   Reducer red, red2;
   double* host_buf = nullptr;  // pinned
-  int mmax = 0;
+  int mmax = 0;        // restart length the GMRES buffers hold
+  int restart_cur = 0;  // current GMRES restart length (grows on stagnating cycles)
+  bool gmres_full = false;  // the last GMRES cycle ran restart_cur iterations
   double t = 0.0;
   bool blocks_ready = false;
   // graph-network preconditioner
@@ -147,6 +149,19 @@ ldg_status dalloc(ldg_ctx* c, T** p, size_t n) {
   c->allocs.push_back(q);
   *p = static_cast<T*>(q);
   return LDG_OK;
+}
+
+template <class T>
+void dfree(ldg_ctx* c, T*& p) {
+  if (!p) return;
+  for (auto& q : c->allocs)
+    if (q == static_cast<void*>(p)) {
+      q = c->allocs.back();
+      c->allocs.pop_back();
+      break;
+    }
+  (void)hipFree(p);
+  p = nullptr;
 }
 
 template <class T>
@@ -420,14 +435,67 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   return LDG_OK;
 }
 
+// The GMRES basis (FP64, and FP32 in the mixed modes), the Hessenberg column
+// buffers and the reduction buffers for restart length m; called between
+// cycles (nothing in flight uses the old buffers after the sync).
+constexpr double kGmresBasisBytes = 2.0 * 1024 * 1024 * 1024;
+
+ldg_status krylov_buffers(ldg_ctx* c, int m) {
+  const int64_t nv = c->nvec;
+  const size_t nb = std::max<size_t>(c->red.nblk, gs_nblk(nv));
+  size_t np = (size_t)(m + 2) * nb;
+  const size_t nbj = (size_t)(c->Kpad / 64 + 1);   // per-block partials of the apply kernels
+  if (np < nbj) np = nbj;
+  if (np < 2048) np = 2048;
+  TRY(dalloc(c, &c->V, (size_t)(m + 1) * nv));
+  if (c->opt.precision != LDG_FP64) TRY(dalloc(c, &c->V32, (size_t)(m + 1) * nv));
+  TRY(dalloc(c, &c->hdev, m + 2));
+  TRY(dalloc(c, &c->ydev, m + 2));
+  TRY(dalloc(c, &c->red.partials, np));
+  TRY(dalloc(c, &c->red.result, m + 2));
+  HIPCHK(c, hipHostMalloc((void**)&c->host_buf, (2 * m + 8) * sizeof(double)));
+  c->red.maxv = c->red2.maxv = m + 1;
+  c->mmax = m;
+  return LDG_OK;
+}
+
+// largest restart length allowed by the system size and the basis budget
+int gmres_cap(const ldg_ctx* c) {
+  const double es = c->opt.precision == LDG_FP64 ? 8.0 : 12.0;
+  const double by_mem = kGmresBasisBytes / (es * (double)c->nvec) - 1.0;
+  const double by_dim = (double)c->K * c->N;
+  return (int)std::max(1.0, std::min(by_mem, by_dim));
+}
+
+ldg_status grow_gmres(ldg_ctx* c, int m) {
+  if (m <= c->mmax) {
+    c->restart_cur = m;
+    return LDG_OK;
+  }
+  TRY(sync(c));
+  dfree(c, c->V);
+  dfree(c, c->V32);
+  dfree(c, c->hdev);
+  dfree(c, c->ydev);
+  dfree(c, c->red.partials);
+  dfree(c, c->red.result);
+  if (c->host_buf) (void)hipHostFree(c->host_buf);
+  c->host_buf = nullptr;
+  TRY(krylov_buffers(c, m));
+  c->restart_cur = m;
+  return LDG_OK;
+}
+
 // One cycle of right-preconditioned GMRES(m) with classical Gram-Schmidt and
 // one conditional re-orthogonalisation; rnorm = ||r||.
 ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, double tol_abs,
                        int maxit, int* iters) {
   const int64_t n = c->nvec;
-  const int m = std::min(c->opt.restart, maxit);
+  const int m = std::min(c->restart_cur, maxit);
   const size_t es = L.vt == VT_F64 ? 8 : 4;
-  std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), y(m);
+  // Hessenberg by columns, built as the cycle runs (column j holds rows 0..j+1)
+  std::vector<std::vector<double>> Hc;
+  std::vector<double> cs(m), sn(m), g(m + 1, 0.0), y(m);
   double* hb = c->host_buf;
   char* V = static_cast<char*>(L.V);
   kaxpby(c, L, 1.0 / rnorm, L.r, 0.0, V);
@@ -446,29 +514,31 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
     TRY(sync(c));
     const double wn0 = std::sqrt(hb[j + 1]);
     double wn = std::sqrt(hb[m + 2]);
-    for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i];
+    Hc.emplace_back(j + 2, 0.0);
+    std::vector<double>& h = Hc.back();
+    for (int i = 0; i <= j; ++i) h[i] = hb[i];
     if (wn < 0.7 * wn0) {
       kdots(c, L, j + 1, V, vn);
       kupdate(c, L, j + 1, V, c->red.result, vn);
       HIPCHK(c, hipMemcpyAsync(hb, c->red.result, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
       HIPCHK(c, hipMemcpyAsync(hb + m + 2, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
       TRY(sync(c));
-      for (int i = 0; i <= j; ++i) H[i * m + j] += hb[i];
+      for (int i = 0; i <= j; ++i) h[i] += hb[i];
       wn = std::sqrt(hb[m + 2]);
     }
-    H[(j + 1) * m + j] = wn;
+    h[j + 1] = wn;
     if (wn > 0.0) kaxpby(c, L, 1.0 / wn, vn, 0.0, vn);
     for (int i = 0; i < j; ++i) {
-      const double a = H[i * m + j], b = H[(i + 1) * m + j];
-      H[i * m + j] = cs[i] * a + sn[i] * b;
-      H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      const double a = h[i], b = h[i + 1];
+      h[i] = cs[i] * a + sn[i] * b;
+      h[i + 1] = -sn[i] * a + cs[i] * b;
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double a = h[j], b = h[j + 1];
     const double rr = std::hypot(a, b);
     cs[j] = rr > 0.0 ? a / rr : 1.0;
     sn[j] = rr > 0.0 ? b / rr : 0.0;
-    H[j * m + j] = rr;
-    H[(j + 1) * m + j] = 0.0;
+    h[j] = rr;
+    h[j + 1] = 0.0;
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];
     jend = j + 1;
@@ -477,8 +547,8 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
   }
   for (int i = jend - 1; i >= 0; --i) {
     double s = g[i];
-    for (int k = i + 1; k < jend; ++k) s -= H[i * m + k] * y[k];
-    y[i] = s / H[i * m + i];
+    for (int k = i + 1; k < jend; ++k) s -= Hc[k][i] * y[k];
+    y[i] = s / Hc[i][i];
   }
   HIPCHK(c, hipMemcpyAsync(c->ydev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, c->st));
   {
@@ -488,6 +558,7 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
   bj_apply(c, L, L.u, L.d, false);
   *iters = jend;
   c->inner_rho = jend > 0 ? std::fabs(g[jend]) / rnorm : 1.0;
+  c->gmres_full = jend == c->restart_cur;
   return LDG_OK;
 }
 
@@ -769,7 +840,7 @@ ldg_status inner_solve(ldg_ctx* c, const Level& L, double tau, double tol, int l
 ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_step_info* info) {
   const int64_t n = c->nvec;
   const double target = c->opt.rtol * bnorm;
-  const Level L64 = level64(c);
+  Level L64 = level64(c);
   Level L = c->opt.precision == LDG_FP64
                 ? L64
                 : level_lo(c, c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32);
@@ -777,6 +848,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   int iters = 0, sweeps = 0;
   double beta = 0.0, beta_prev = 0.0;
   bool cg_mode = use_cg;
+  c->gmres_full = false;
   // the learned preconditioner runs inside flexible CG (SPD case); for GMRES
   // problems it is not used and the step counts one fallback
   bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode &&
@@ -796,8 +868,22 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
     beta = std::sqrt(hb[0]);
     if (!std::isfinite(beta)) return fail(c, LDG_ENOCONV, "non-finite residual");
     if (beta <= target || iters >= c->opt.max_iters) break;
-    if (L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev &&
-        beta > 4.0 * c->inner_rho * beta_prev) {
+    bool escalate = L.vt != VT_F64 && sweeps > 0 && beta > 0.5 * beta_prev &&
+                    beta > 4.0 * c->inner_rho * beta_prev;
+    if (!cg_mode && !escalate && sweeps > 0 && beta > 0.5 * beta_prev && c->gmres_full &&
+        c->inner_rho > 0.5 && 2 * c->restart_cur <= gmres_cap(c)) {
+      // the last GMRES cycle ran its full length and, by its own estimate as
+      // well as the FP64 residual, did not halve the residual: restarted GMRES
+      // stagnates (indefinite steps), so double the restart length.  A cycle
+      // whose estimate fell but whose FP64 residual did not is a precision or
+      // rounding limit, not a short restart, and leaves the length alone.
+      TRY(grow_gmres(c, 2 * c->restart_cur));
+      // the basis and the pinned host buffer moved
+      hb = c->host_buf;
+      L64.V = c->V;
+      L.V = L.vt == VT_F64 ? static_cast<void*>(c->V) : static_cast<void*>(c->V32);
+    }
+    if (escalate) {
       // refinement stagnates at this precision (the FP64 residual fell far less
       // than the inner solve reported): BF16 -> FP32 -> FP64
       info->fallbacks += 1;
@@ -838,6 +924,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
     }
   }
   info->iters = iters;
+  info->gmres_restart = c->restart_cur;
   info->restarts = sweeps;
   info->ir_steps = c->opt.precision == LDG_FP64 ? 0 : sweeps;
   info->rel_residual = beta / bnorm;
@@ -1031,7 +1118,6 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   c->nbe = (int64_t)hm.belem.size();
   c->Eint = hm.E_int;
   c->nvec = c->Kpad * c->N;
-  c->mmax = opt->restart;
   for (int64_t k = 0; k < 3 * K; ++k) {
     c->n_sd += edge_kind[k] != LDG_EDGE_NEUMANN;
     c->n_nd += edge_kind[k] != LDG_EDGE_DIRICHLET;
@@ -1157,14 +1243,12 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   }
   TRY(dalloc(c, &c->blocks, (size_t)Kp * NSLOT * c->NP * 2));
   TRY(dalloc(c, &c->bj, (size_t)Kp * c->NP * 2));
-  TRY(dalloc(c, &c->V, (size_t)(c->mmax + 1) * nv));
   if (opt->precision != LDG_FP64) {
     float** v32[] = {&c->r32, &c->z32, &c->p32, &c->q32, &c->d32, &c->u32, &c->tz1_32, &c->tz2_32};
     for (float** v : v32) {
       TRY(dalloc(c, v, nv));
       HIPCHK(c, hipMemsetAsync(*v, 0, nv * sizeof(float), c->st));
     }
-    TRY(dalloc(c, &c->V32, (size_t)(c->mmax + 1) * nv));
     char* p8 = nullptr;
     TRY(dalloc(c, &p8, block_bytes(BT_F32, Kp, N, NSLOT)));
     c->blocks_f32 = p8;
@@ -1175,8 +1259,6 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       c->blocks_bf16 = p8;
     }
   }
-  TRY(dalloc(c, &c->hdev, c->mmax + 2));
-  TRY(dalloc(c, &c->ydev, c->mmax + 2));
   TRY(dalloc(c, &c->status, 1));
   {
     // Lagrange points of Sec. 3.8: the barycentre (p = 0), the vertices
@@ -1195,20 +1277,11 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
     TRY(upload(c, c->phiL, ph));
   }
   c->red.nblk = c->red2.nblk = krylov_nblk(nv);
-  c->red.maxv = c->red2.maxv = c->mmax + 1;
-  {
-    const size_t nb = std::max<size_t>(c->red.nblk, gs_nblk(nv));
-    size_t np = (size_t)(c->mmax + 2) * nb;
-    const size_t nbj = (size_t)(Kp / 64 + 1);   // per-block partials of the apply kernels
-    if (np < nbj) np = nbj;
-    if (np < 2048) np = 2048;
-    TRY(dalloc(c, &c->red.partials, np));
-  }
-  TRY(dalloc(c, &c->red.result, c->mmax + 2));
+  TRY(krylov_buffers(c, opt->restart));
+  c->restart_cur = opt->restart;
   TRY(dalloc(c, &c->red2.partials,
              std::max<size_t>(c->red2.nblk, gs_nblk(nv)) + 2048));
   TRY(dalloc(c, &c->red2.result, 1));
-  HIPCHK(c, hipHostMalloc((void**)&c->host_buf, (2 * c->mmax + 8) * sizeof(double)));
   TRY(sync(c));
   c->t = 0.0;
   c->err.clear();

@@ -48,7 +48,8 @@ class StepInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("ir_steps", C.c_int),
                 ("fallbacks", C.c_int), ("krylov", C.c_int), ("rel_residual", C.c_double),
                 ("t", C.c_double), ("learned_iters", C.c_int), ("guarded_iters", C.c_int),
-                ("fallback_reason", C.c_int), ("bdf_order", C.c_int)]
+                ("fallback_reason", C.c_int), ("bdf_order", C.c_int),
+                ("gmres_restart", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -320,7 +321,11 @@ class Solver:
         info = StepInfo()
         code = self.lib.ldg_step_sampled(self.h, float(dt), _ptr(d), _ptr(f), _ptr(cD), _ptr(gN),
                                          C.byref(info))
-        self._check(code)
+        if code != 0:
+            # the library fills info on LDG_ENOCONV too (state not advanced)
+            err = LdgError(code, self.lib.ldg_last_error(self.h).decode())
+            err.info = info.as_dict()
+            raise err
         return info.as_dict()
 
     def set_matrix_free(self, on=True):

@@ -79,7 +79,7 @@ def test_main_script_run_matches_the_oracle():
 # overshoots and undershoots (for p >= 2 it goes below zero) and the step's
 # operator has an indefinite symmetric part: restarted GMRES then needs a long
 # restart (CPU check, n = 9, p = 4: GMRES(60) stalls near 1e-2, GMRES(200)
-# converges in 4578 iterations)
+# converges in 4578 iterations); the library lengthens the restart itself
 @pytest.mark.parametrize("n,seed,p,restart", [(12, 411, 0, 60), (12, 412, 1, 60), (9, 414, 4, 200)])
 def test_main_problem_on_jittered_meshes(n, seed, p, restart):
     # CG where the projected coefficient happens to be constant on every
@@ -95,18 +95,31 @@ def test_main_problem_mixed_precision():
         assert max(errs) < 1e-10
 
 
+def test_indefinite_steps_converge_with_a_growing_restart():
+    # n = 10, p = 3: the projected coefficient goes below zero where triangles cut
+    # the jump, the step's symmetric part is indefinite and block-Jacobi
+    # GMRES(60) stalls near 1e-1.  Cycles that fail to halve the residual double
+    # the restart length (here up to the system size), and the steps reach the
+    # paper's direct solution
+    out = _run(10, 413, 3, 2, np.pi / 20)
+    for info, errs in out:
+        assert info["krylov"] == 1 and info["rel_residual"] <= 1e-13
+        assert max(errs) < 1e-10
+    assert out[0][0]["gmres_restart"] > 60
+
+
 def test_stalled_step_reports_no_convergence_and_keeps_the_state():
-    # n = 10, p = 3: GMRES(60) with block-Jacobi stalls near 1e-1 (CPU check);
-    # the step returns ENOCONV and leaves the state as it was
+    # the same step bounded at 300 Krylov iterations: ENOCONV, state unchanged
     from paper_1408_3877_amd.ldg import LdgError
     cV, V0T, kind = square_mesh(10, seed=413, neumann_sides=(SOUTH, NORTH))
-    s = _solver(cV, V0T, kind, 3, max_iters=3000)
+    s = _solver(cV, V0T, kind, 3, max_iters=300)
     s.set_initial_samples(s.sample_workload(MAIN, 0.0, want=("c0",))["c0"], 0.0)
     C0 = to_np(s.get_solution()[0])
     smp = s.sample_workload(MAIN, np.pi / 20)
     with pytest.raises(LdgError) as e:
         s.step_sampled(np.pi / 20, smp["d"], smp["f"], smp["cD"], smp["gN"])
-    assert e.value.code == -5
+    assert e.value.code == -5 and e.value.info["iters"] >= 300
+    assert e.value.info["rel_residual"] > 1e-13
     assert np.array_equal(to_np(s.get_solution()[0]), C0)
     smp = s.sample_workload(MAIN, 0.0, want=("c0",))
     assert np.array_equal(to_np(s.project(smp["c0"])), C0)
