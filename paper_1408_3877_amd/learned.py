@@ -228,6 +228,121 @@ def calibrate(solver, w, shifts, n, seeds, sigma, dt):
     return w, table
 
 
+HEAD = 2 * 32 + 13 + 2   # head parameters at the end of the factored network's vector
+
+
+def cg_cases(solver, n, seeds, sigma, dt):
+    """First-step systems of the training fields: device samples of c0 and of
+    the data at t = dt, for repeated solves."""
+    out = []
+    for sd in seeds:
+        dT = field(n, sd, sigma)
+        c0 = solver.sample_workload(KIND, 0.0, dT=dT, want=("c0",))["c0"].clone()
+        smp = solver.sample_workload(KIND, dt, dT=dT)
+        out.append((c0, {k: v.clone() for k, v in smp.items() if v is not None}))
+    return out
+
+
+def cg_objective(solver, w, cases, dt):
+    """Mean log10 of the relative residual of the full system after the
+    solver's max_iters preconditioned CG iterations (FP64), over the cases:
+    how far CG gets with the preconditioner these weights build."""
+    from .ldg import LdgError
+    solver.gnn_set_params(w)
+    vals = []
+    for c0, smp in cases:
+        solver.set_initial_samples(c0, 0.0)
+        try:
+            info = solver.step_sampled(dt, smp["d"], smp["f"], smp.get("cD"), smp.get("gN"))
+        except LdgError as e:
+            if e.code != -5:
+                raise
+            info = e.info
+        if info["fallbacks"]:
+            return np.inf                     # a curvature breakdown: the weights are unusable
+        vals.append(np.log10(max(info["rel_residual"], 1e-300)))
+    return float(np.mean(vals))
+
+
+def with_head(w, head):
+    out = w.copy()
+    out[-HEAD:] = head.astype(np.float32)
+    return out
+
+
+def constant_head(omega, omega_max=0.95):
+    """Head parameters giving omega on every edge: zero weights, the bias alone."""
+    h = np.zeros(HEAD)
+    q = omega / omega_max
+    h[-1] = np.log(q / (1.0 - q))
+    return h
+
+
+def train_head_cg(solver, w, cases, dt, omegas, iters, c, a, seed, from_start=False):
+    """Fit the head (the last HEAD parameters; the trunk stays) to the CG
+    objective: the best constant omega on the grid `omegas` first, then
+    simultaneous-perturbation stochastic approximation (SPSA) from there, with
+    Rademacher perturbations of size c_k = c / (k+1)^0.101 and steps
+    a_k = a / (k+11)^0.602.  Every evaluated head is a candidate; the best
+    one is returned with the history."""
+    rng = np.random.default_rng(seed)
+    hist = {"constant": [], "spsa": []}
+    best_h, best_v = None, np.inf
+    for om in omegas:
+        h = constant_head(om)
+        v = cg_objective(solver, with_head(w, h), cases, dt)
+        hist["constant"].append((float(om), v))
+        log("[cg-head] constant omega %.2f: %.4f" % (om, v))
+        if v < best_v:
+            best_h, best_v = h, v
+    hist["best_constant"] = min(hist["constant"], key=lambda x: x[1])
+    if from_start:
+        best_h = w[-HEAD:].astype(np.float64).copy()
+        best_v = cg_objective(solver, w, cases, dt)
+        hist["start"] = best_v
+        hist.pop("best_at", None)
+        log("[cg-head] start weights: %.4f" % best_v)
+    # the head's inputs differ in scale by orders of magnitude: measure how far
+    # each parameter moves omega (RMS over the interior edges of the first
+    # case's system) and search in coordinates u where a unit step of any one
+    # parameter moves omega by 1 / sqrt(HEAD) in RMS
+    c0, smp = cases[0]
+    solver.gnn_set_context(solver.project(smp["d"]), dt)
+    solver.gnn_set_params(with_head(w, best_h))
+    om0 = solver.gnn_factor_omega().double().cpu().numpy()
+    inner = om0 != 0.0
+    sens = np.zeros(HEAD)
+    eps = 1e-2
+    for i in range(HEAD):
+        h = best_h.copy()
+        h[i] += eps
+        solver.gnn_set_params(with_head(w, h))
+        om = solver.gnn_factor_omega().double().cpu().numpy()
+        sens[i] = np.sqrt(np.mean((om - om0)[inner] ** 2)) / eps
+    scale = 1.0 / (np.maximum(sens, 1e-6 * sens.max()) * np.sqrt(HEAD))
+    hist["sensitivity"] = sens.tolist()
+    u = np.zeros(HEAD)
+    for k in range(iters):
+        ck = c / (k + 1) ** 0.101
+        ak = a / (k + 11) ** 0.602
+        delta = rng.choice([-1.0, 1.0], HEAD)
+        hp, hm = best_h + scale * (u + ck * delta), best_h + scale * (u - ck * delta)
+        vp = cg_objective(solver, with_head(w, hp), cases, dt)
+        vm = cg_objective(solver, with_head(w, hm), cases, dt)
+        for v, h in ((vp, hp), (vm, hm)):
+            if v < best_v:
+                best_v, best_new = v, h.copy()
+                hist["best_at"] = k
+        if np.isfinite(vp) and np.isfinite(vm):
+            g = (vp - vm) / (2 * ck) * delta
+            u = u - np.clip(ak * g, -0.05, 0.05)
+        hist["spsa"].append((vp, vm, best_v))
+        log("[cg-head] spsa %d: %.4f %.4f best %.4f" % (k, vp, vm, best_v))
+    if "best_at" in hist:
+        best_h = best_new
+    return with_head(w, best_h), best_v, hist
+
+
 def seeds_arg(s):
     if "-" in s:
         a, b = s.split("-")
@@ -253,8 +368,30 @@ def main(argv=None):
                     help="collection rounds (1: block-Jacobi solves only)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=7)
-    ap.add_argument("--loss", choices=("frobenius", "energy", "mse", "optstep"), default=None,
-                    help="default: frobenius (factor mode), energy (correction mode)")
+    ap.add_argument("--loss", choices=("frobenius", "energy", "mse", "optstep", "cg"), default=None,
+                    help="default: frobenius (factor mode), energy (correction mode); cg: fit the "
+                         "factored head to CG convergence (after a Frobenius training, or on "
+                         "--start-weights)")
+    ap.add_argument("--start-weights", default=None,
+                    help="cg loss: trunk to keep (\"init\": the untrained initialisation; default: "
+                         "train it on the Frobenius objective)")
+    ap.add_argument("--spsa-from", choices=("constant", "start"), default="constant",
+                    help="cg loss: start the SPSA search at the best constant omega, or at the "
+                         "head of the start weights")
+    ap.add_argument("--cg-iters", type=int, default=150,
+                    help="cg loss: CG iterations after which the residual is scored")
+    ap.add_argument("--cg-omegas", default="0.5,0.6,0.7,0.75,0.8,0.85,0.9",
+                    help="cg loss: constant omegas tried before the SPSA search")
+    ap.add_argument("--spsa-iters", type=int, default=120)
+    ap.add_argument("--spsa-c", type=float, default=0.03,
+                    help="RMS change of omega of a perturbation")
+    ap.add_argument("--spsa-a", type=float, default=0.5)
+    ap.add_argument("--cg-seeds", default=None,
+                    help="cg loss: training fields for the head fit (default: the first six "
+                         "training seeds)")
+    ap.add_argument("--compare", default=None,
+                    help="comma list of extra weight files evaluated on the held-out fields "
+                         "(\"init\": the untrained initialisation)")
     ap.add_argument("--probes", type=int, default=8, help="probe vectors per system visit")
     ap.add_argument("--mode", choices=("correction", "factor"), default="factor",
                     help="per-iteration residual correction, or factored preconditioner")
@@ -274,7 +411,7 @@ def main(argv=None):
     KIND = a.kind
     if a.loss is None:
         a.loss = "frobenius" if a.mode == "factor" else "energy"
-    if a.loss in ("frobenius", "optstep") and a.mode != "factor":
+    if a.loss in ("frobenius", "optstep", "cg") and a.mode != "factor":
         ap.error("the %s loss belongs to the factored preconditioner" % a.loss)
     snaps = ([int(x) for x in a.snaps.split(",")] if a.snaps else
              (SNAPS_LATE if a.loss == "optstep" else SNAPS))
@@ -301,17 +438,20 @@ def main(argv=None):
         w = init(sv.N, a.init_seed)
         data, losses, t_collect, t_train = [], [], 0.0, 0.0
         sl = None
-        if a.loss == "frobenius":
+        if a.loss == "cg" and a.start_weights:
+            w = (init(sv.N, a.init_seed) if a.start_weights == "init" else
+                 np.load(a.start_weights).astype(np.float32))
+        elif a.loss in ("frobenius", "cg"):
             t0 = time.perf_counter()
             data = systems(sv, a.n, seeds_arg(a.train_seeds), a.sigma, a.steps, a.dt)
             t_collect = time.perf_counter() - t0
             sv.gnn_set_params(w)
-            sv.gnn_set_loss(a.loss)
+            sv.gnn_set_loss("frobenius")
             t0 = time.perf_counter()
             losses = train_probes(sv, data, a.epochs, a.probes, a.lr, a.dt, a.init_seed)
             t_train = time.perf_counter() - t0
             w = sv.gnn_get_params()
-        for rd in range(a.rounds if a.loss != "frobenius" else 0):
+        for rd in range(a.rounds if a.loss not in ("frobenius", "cg") else 0):
             src = sv
             if rd > 0:
                 if sl is None:
@@ -330,6 +470,21 @@ def main(argv=None):
         del sl
     n_samples = len(data)
     del data[:]
+    cg_fit = None
+    if a.loss == "cg" and not a.weights:
+        scg = Solver(coordV, V0T, kind, a.p, rtol=1e-14, max_iters=a.cg_iters, precond=1)
+        scg.gnn_set_mode("factor")
+        cseeds = seeds_arg(a.cg_seeds) if a.cg_seeds else seeds_arg(a.train_seeds)[:6]
+        cases = cg_cases(scg, a.n, cseeds, a.sigma, a.dt)
+        t0 = time.perf_counter()
+        w, best, hist = train_head_cg(scg, w, cases, a.dt,
+                                      [float(x) for x in a.cg_omegas.split(",")], a.spsa_iters,
+                                      a.spsa_c, a.spsa_a, a.init_seed,
+                                      from_start=a.spsa_from == "start")
+        cg_fit = {"objective": best, "seconds": time.perf_counter() - t0, "seeds": cseeds,
+                  "cg_iters": a.cg_iters, **hist}
+        t_train += cg_fit["seconds"]
+        del cases, scg
     calib = None
     if a.calibrate:
         if a.mode != "factor":
@@ -346,9 +501,9 @@ def main(argv=None):
         np.save(a.out, w)
     # the training loss on held-out systems (one step per evaluation field)
     sv.gnn_set_params(w)
-    sv.gnn_set_loss(a.loss)
+    sv.gnn_set_loss("frobenius" if a.loss == "cg" else a.loss)
     hl = []
-    if a.loss == "frobenius":
+    if a.loss in ("frobenius", "cg"):
         rng = np.random.default_rng(a.init_seed + 1000)
         for D in systems(sv, a.n, seeds_arg(a.eval_seeds), a.sigma, 1, a.dt):
             sv.gnn_set_context(D, a.dt)
@@ -365,11 +520,23 @@ def main(argv=None):
     sg = learned_solver()
     sg.gnn_set_params(w)
     eg = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
+    extra = {}
+    if a.compare:
+        for f in a.compare.split(","):
+            wc = init(sv.N, a.init_seed) if f == "init" else np.load(f).astype(np.float32)
+            sg.gnn_set_params(wc)
+            extra[f] = evaluate(sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
+    if cg_fit is not None:
+        # the best constant omega of the fit, on the held-out fields
+        sg.gnn_set_params(with_head(w, constant_head(cg_fit["best_constant"][0])))
+        extra["constant omega %.2f" % cg_fit["best_constant"][0]] = evaluate(
+            sg, a.n, seeds_arg(a.eval_seeds), a.sigma, a.eval_steps, a.dt, True)
     rep = {"p": a.p, "n": a.n, "kind": a.kind, "sigma": a.sigma, "dt": a.dt, "K": sv.K, "samples": n_samples, "collect_s": t_collect, "train_s": t_train,
            "epochs": a.epochs, "rounds": a.rounds, "mode": a.mode, "loss": a.loss, "probes": a.probes, "loss_per_epoch": losses,
            "heldout_loss": float(np.mean(hl)), "block_jacobi": ev, "learned": eg,
            "iteration_ratio": eg["iters_per_step"] / ev["iters_per_step"],
-           "time_ratio": eg["s_per_step"] / ev["s_per_step"], "calibration": calib}
+           "time_ratio": eg["s_per_step"] / ev["s_per_step"], "calibration": calib,
+           "cg_fit": cg_fit, "compare": extra}
     print(json.dumps(rep), flush=True)
     if a.report:
         with open(a.report, "w") as fh:

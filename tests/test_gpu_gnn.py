@@ -223,3 +223,36 @@ def test_training_the_correction_network_on_collected_pairs():
     assert rep["samples"] > 20 and rep["loss"] == "energy"
     assert rep["loss_per_epoch"][-1] < rep["loss_per_epoch"][0]
     assert rep["learned"]["steps"] == rep["block_jacobi"]["steps"] == 2
+
+
+@pytest.mark.parametrize("p,n,sigma,jitter,kind,seeds", [
+    (3, 128, 1.5, 1004, 3, "4100,4101"),      # learned-p3 family, held-out fields
+    (4, 128, 1.0, 1005, 4, "5001,5002"),      # combined family, held-out fields
+])
+def test_shipped_weights_beat_their_initialisation_and_a_constant_omega(p, n, sigma, jitter, kind,
+                                                                        seeds):
+    # the shipped factored networks (head fitted to CG convergence on training
+    # fields) against the untrained initialisation (omega ~ 0.6 with small
+    # random variations) and the constant omega = 0.6 on every edge: FP64 CG
+    # iterations per step to 1e-8 on held-out fields, 2 steps each
+    import os
+
+    from paper_1408_3877_amd import Solver, learned
+    learned.KIND = kind
+    N = (p + 1) * (p + 2) // 2
+    coordV, V0T, ek = square_mesh(n, seed=jitter)
+    s = Solver(coordV, V0T, ek, p, rtol=1e-8, max_iters=20000, precond=1)
+    s.gnn_set_mode("factor")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    shipped = np.load(os.path.join(root, "paper_1408_3877_amd", "weights",
+                                   "factor_p%d.npy" % p)).astype(np.float32)
+    init = learned.factor_init(N, 7)
+    const = learned.with_head(init, learned.constant_head(0.6))
+    its = {}
+    for name, w in (("shipped", shipped), ("init", init), ("constant", const)):
+        s.gnn_set_params(w)
+        r = learned.evaluate(s, n, learned.seeds_arg(seeds), sigma, 2, 1e-4, True)
+        assert r["fallbacks"] == 0
+        its[name] = r["iters_per_step"]
+    print("[trained-vs-untrained] p=%d %s" % (p, its))
+    assert its["shipped"] < its["init"] and its["shipped"] < its["constant"], its

@@ -46,3 +46,18 @@ def test_calibration_prefers_no_shift_on_a_flat_curve(monkeypatch):
     w, table = learned.calibrate(FakeSolver(), w0, [1.0, -1.0, 0.0], 8, [1], 1.0, 1e-3)
     assert [it for _, it in table] == [50.0, 50.0, 50.0]
     assert np.array_equal(w, w0)
+
+
+def test_constant_head_gives_the_requested_omega():
+    # the head with zero weights and bias logit(omega / 0.95) gives omega on
+    # every edge; with_head replaces only the head (the last 79 parameters)
+    import numpy as np
+
+    from paper_1408_3877_amd import learned
+    h = learned.constant_head(0.6)
+    assert h.shape == (learned.HEAD,) and np.all(h[:-1] == 0)
+    assert abs(0.95 / (1 + np.exp(-h[-1])) - 0.6) < 1e-12
+    w = learned.factor_init(10, 7)
+    w2 = learned.with_head(w, h)
+    assert np.array_equal(w2[:-learned.HEAD], w[:-learned.HEAD])
+    assert np.allclose(w2[-learned.HEAD:], h)
