@@ -210,3 +210,23 @@ def pair_numbering(V0T, kind):
     order = np.array(order, dtype=np.int64)
     return (np.ascontiguousarray(V0T[order]).astype(np.int32),
             np.ascontiguousarray(np.asarray(kind)[order]).astype(np.int8), order)
+
+
+def split_at_centroids(coordV, V0T, which):
+    """Split the listed triangles at their centroids into three triangles each
+    (counter-clockwise, the new vertex last): every split adds an interior
+    vertex of degree three, whose three triangles are pairwise neighbours.
+    Returns (coordV, V0T) with the unsplit triangles first, in order."""
+    coordV = np.asarray(coordV, dtype=np.float64)
+    V0T = np.asarray(V0T)
+    which = np.asarray(sorted(set(int(k) for k in which)))
+    keep = np.setdiff1d(np.arange(V0T.shape[0]), which)
+    cen = coordV[V0T[which]].mean(axis=1)
+    base = coordV.shape[0]
+    new = []
+    for i, k in enumerate(which):
+        a, b, c = (int(v) for v in V0T[k])
+        m = base + i
+        new += [[a, b, m], [b, c, m], [c, a, m]]
+    return (np.concatenate([coordV, cen]),
+            np.concatenate([V0T[keep], np.array(new, dtype=V0T.dtype).reshape(-1, 3)]).astype(np.int32))
