@@ -234,3 +234,85 @@ def test_factor_nonsymmetric_step_falls_back():
     pr = Problem(cV, V0T, kind, p)
     C, _, _, _ = pr.step(pr.initial(w), dt, dt, w)
     assert rel_l2(pr.grid.areaT, to_np(s.get_solution()[0]), C) < 1e-10
+
+
+def test_factor_blocks_at_degree_three_vertices():
+    # The neighbour blocks S_kj of the eliminated operator gain a path through a
+    # third triangle l adjacent to both k and j: B_kl M_l^{-1} A_lj.  On a mesh
+    # that exists only around interior vertices of degree three, and the
+    # factor kernel leaves it out.  Here such vertices are made by splitting
+    # triangles at their centroids: away from them O_kn matches the oracle's
+    # W_k S_kj W_j^T to FP32 rounding; on the edges that meet them it deviates
+    # by the left-out path (measured and bounded below), and the preconditioner
+    # stays exactly SPD, so steps still reach the oracle's solution.
+    from inputs.meshes import edge_kinds, split_at_centroids
+    from paper_1408_3877_amd import Solver
+    n, p = 6, 3
+    cV0, V00, _ = square_mesh(n, seed=731)
+    rng = np.random.default_rng(731)
+    interior = [k for k in range(V00.shape[0])
+                if np.all((cV0[V00[k]] > 1e-9) & (cV0[V00[k]] < 1 - 1e-9))]
+    cV, V0T = split_at_centroids(cV0, V00, rng.choice(interior, 8, replace=False))
+    kind = edge_kinds(cV, V0T, (NORTH,))
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(p)
+    dT = 10.0 ** rng.uniform(-1.0, 1.0, g.numT)
+    D = np.zeros((g.numT, refs.N))
+    D[:, 0] = dT / np.sqrt(2.0)
+    dt = 6.5 / n ** 2
+    sy = gf.System(g, schur_matrix(Blocks(g, refs, D), g, refs, 1.0, dt))
+    s = Solver(cV, V0T, kind, p)
+    s.gnn_set_mode("factor")
+    s.gnn_factor_storage("f32")
+    s.gnn_set_params(_theta(sy.N, 731))
+    s.gnn_set_context(D, dt)
+    blk = to_np(s.gnn_factor_export()[0])
+    assert np.abs(blk[:, 0] - sy.Wk).max() <= 1e-6 * np.abs(sy.Wk).max()
+    # edges (k, n) whose two triangles have a common neighbour
+    nb = [set(int(j) for j in g.kp[k] if j >= 0) for k in range(g.numT)]
+    third = np.zeros((g.numT, 3), dtype=bool)
+    for k in range(g.numT):
+        for e in range(3):
+            j = g.kp[k, e]
+            third[k, e] = j >= 0 and len(nb[k] & nb[int(j)]) > 0
+    m = sy.mask
+    assert third.sum() >= 8 * 6
+    plain = m & ~third
+    assert np.abs(blk[:, 1:][plain] - sy.O[plain]).max() <= 2e-6 * np.abs(sy.O).max()
+    dev = (np.linalg.norm(blk[:, 1:][third] - sy.O[third], axis=(1, 2)) /
+           np.linalg.norm(sy.O[third], axis=(1, 2)))
+    print("[factor-degree-3] %d edges: relative Frobenius deviation of O_kn max %.3f median %.3f"
+          % (third.sum(), dev.max(), np.median(dev)), flush=True)
+    assert 1e-6 < dev.max() < 1.0
+    # steps with the learned preconditioner on this mesh match the oracle (d
+    # constant on every triangle, so the steps are SPD and run learned CG)
+    smooth = Workload(SMOOTH1)
+
+    class TriangleD(Workload):
+        # d constant per triangle (oracle point arrays are [K x R]); the
+        # forcing and boundary data are those of the smooth workload
+        def d(self, t, x, y):
+            return np.broadcast_to(dT[:, None], np.shape(x)) + 0.0 * t
+
+        def f(self, t, x, y):
+            return smooth.f(t, x, y)
+
+    w = TriangleD(SMOOTH1)
+    pr = Problem(cV, V0T, kind, p)
+    sl = Solver(cV, V0T, kind, p, rtol=1e-13, max_iters=20000, precond=1)
+    sl.gnn_set_mode("factor")
+    sl.gnn_set_params(_theta(sy.N, 731))
+    C = pr.initial(w)
+    sl.set_state(C, 0.0)
+    x, y = (to_np(v) for v in sl.quad_points(0))
+    xb, yb = (to_np(v) for v in sl.quad_points(1))
+    n1, n2 = (to_np(v) for v in sl.quad_points(2))
+    dv = np.tile(dT, len(x) // g.numT)
+    t = 0.0
+    for _ in range(2):
+        t += 0.01
+        info = sl.step_sampled(0.01, dv, w.f(t, x, y), w.c_D(t, xb, yb), w.g_N(t, xb, yb, n1, n2))
+        C, Z1, Z2, _ = pr.step(C, t, 0.01, w)
+        assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
+        assert info["learned_iters"] == info["iters"] > 0 and info["fallbacks"] == 0
+        assert rel_l2(pr.grid.areaT, to_np(sl.get_solution()[0]), C) < 1e-10
