@@ -26,6 +26,12 @@ directed interior edge
 The network runs once per system; every Krylov iteration applies the fixed
 linear P, so preconditioned CG keeps its optimality.
 
+Nonsymmetric steps (a coefficient that varies inside triangles) use the same
+construction on the symmetric part of the operator: W_k from the Cholesky
+factor of (BJ_k^{-1} + BJ_k^{-T}) / 2 and O_kn = W_k (S_kj + S_jk^T) / 2 W_j^T.
+P is then SPD again (where those diagonal factors exist) and serves as a fixed
+right preconditioner of GMRES.
+
 Training losses, both 1 at omega = 0:
 
   Frobenius (the factorised-sparse-approximate-inverse objective): with
@@ -82,14 +88,17 @@ def init_params(N, seed, omega0=0.6):
 class System:
     """The pieces of one system the preconditioner is built from."""
 
-    def __init__(self, grid, S):
+    def __init__(self, grid, S, symmetric_part=False):
         S = sp.csr_matrix(S)
         K = grid.numT
         N = S.shape[0] // K
         self.K, self.N, self.S = K, N, S
-        blk = lambda a, b: S[a * N:(a + 1) * N, b * N:(b + 1) * N].toarray()
-        self.BJinv = np.stack([np.linalg.inv(blk(k, k)) for k in range(K)])
-        self.Wk = np.stack([np.linalg.cholesky(B).T for B in self.BJinv])   # W_k = R_k^T
+        Sb = sp.csr_matrix((S + S.T) * 0.5) if symmetric_part else S
+        blk = lambda a, b: Sb[a * N:(a + 1) * N, b * N:(b + 1) * N].toarray()
+        sblk = lambda a: S[a * N:(a + 1) * N, a * N:(a + 1) * N].toarray()
+        self.BJinv = np.stack([np.linalg.inv(sblk(k)) for k in range(K)])
+        chol_of = (lambda B: 0.5 * (B + B.T)) if symmetric_part else (lambda B: B)
+        self.Wk = np.stack([np.linalg.cholesky(chol_of(B)).T for B in self.BJinv])   # W_k = R_k^T
         self.O = np.zeros((K, 3, N, N))
         self.mask = grid.kp >= 0
         for k in range(K):

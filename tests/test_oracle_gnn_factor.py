@@ -245,3 +245,63 @@ def test_optstep_loss_is_the_steepest_descent_energy_and_scale_free():
     th1 = gf.init_params(refs.N, 3)
     r1, t1 = rng.standard_normal((2, 1, refs.N))
     assert gf.optstep_loss(th1, g1, node1, edge1, s1, r1, t1) < 1e-12
+
+
+def _nonsymmetric_system(n, p, seed, ratio=6.5):
+    # d varying inside the triangles (a random P_p coefficient around 1):
+    # B^m != -(A^m)^T diag(d), the eliminated operator is nonsymmetric
+    cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=(NORTH,))
+    g = Grid(cV, V0T, kind)
+    refs = RefTensors(p)
+    rng = np.random.default_rng(seed)
+    D = 0.3 * rng.standard_normal((g.numT, refs.N)) / np.sqrt(refs.N)
+    D[:, 0] = 1.0 / np.sqrt(2.0) * (1.0 + 0.5 * rng.random(g.numT))
+    dt = ratio / n ** 2
+    return g, D, dt, schur_matrix(Blocks(g, refs, D), g, refs, 1.0, dt)
+
+
+def _gmres_iters(S, b, M, tol=1e-8, restart=30):
+    import scipy.sparse.linalg as spla
+    its = [0]
+    Mop = spla.LinearOperator(S.shape, matvec=lambda v: M @ v)
+    spla.gmres(S, b, rtol=tol, atol=0.0, restart=restart, maxiter=200, M=Mop,
+               callback=lambda _: its.__setitem__(0, its[0] + 1), callback_type="pr_norm")
+    return its[0]
+
+
+def test_symmetric_part_construction():
+    # on an SPD operator the symmetric-part construction is the plain one;
+    # on a nonsymmetric one W_k^T W_k is the symmetric part of BJ_k^{-1}, the
+    # neighbour blocks are those of (S + S^T) / 2 (so O_{k+ n+} = O_kn^T), P is
+    # SPD, and as a right preconditioner of GMRES a constant omega of the
+    # right sign beats block-Jacobi while the wrong sign does not
+    g, D, dt, sy = _system(5, 2, 31)
+    sy2 = gf.System(g, sy.S, symmetric_part=True)
+    assert np.abs(sy2.Wk - sy.Wk).max() <= 1e-12 * np.abs(sy.Wk).max()
+    assert np.abs(sy2.O - sy.O).max() <= 1e-12 * np.abs(sy.O).max()
+    g, D, dt, S = _nonsymmetric_system(6, 2, 32)
+    Sd = S.toarray()
+    assert np.abs(Sd - Sd.T).max() > 1e-3 * np.abs(Sd).max()
+    sy = gf.System(g, S, symmetric_part=True)
+    N = sy.N
+    for k in range(sy.K):
+        sl = slice(k * N, (k + 1) * N)
+        B = np.linalg.inv(Sd[sl, sl])
+        np.testing.assert_allclose(sy.Wk[k].T @ sy.Wk[k], 0.5 * (B + B.T), atol=1e-12 * np.abs(B).max())
+        for n in range(3):
+            j = g.kp[k, n]
+            if j < 0:
+                continue
+            sj = slice(j * N, (j + 1) * N)
+            want = sy.Wk[k] @ (0.5 * (Sd[sl, sj] + Sd[sj, sl].T)) @ sy.Wk[j].T
+            np.testing.assert_allclose(sy.O[k, n], want, atol=1e-12 * np.abs(want).max())
+            np.testing.assert_allclose(sy.O[j, g.np_[k, n]], sy.O[k, n].T, atol=1e-13)
+    om = np.where(sy.mask, 0.6, 0.0)
+    P = sy.P(om).toarray() if hasattr(sy.P(om), "toarray") else sy.P(om)
+    assert np.abs(P - P.T).max() <= 1e-12 * np.abs(P).max()
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+    b = np.random.default_rng(33).standard_normal(S.shape[0])
+    it_bj = _gmres_iters(S, b, sy.P(np.zeros_like(om)))
+    it_p = _gmres_iters(S, b, sy.P(om))
+    it_neg = _gmres_iters(S, b, sy.P(-om))
+    assert it_p < 0.8 * it_bj and it_neg > it_p, (it_bj, it_p, it_neg)
