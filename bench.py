@@ -244,7 +244,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16"],
                     help="inner-solve precision (fp32/bf16: mixed with FP64 refinement)")
     ap.add_argument("--precond", default=None, choices=["bj", "learned"],
-                    help="block-Jacobi, or the learned factored preconditioner (default: learned "
+                    help="block-Jacobi, or the learned factored preconditioner (CG on symmetric "
+                         "steps, GMRES on the symmetric part's factor otherwise; default: learned "
                          "where trained weights exist for the order and the workload steps in "
                          "time, else block-Jacobi)")
     ap.add_argument("--weights", default=None, help="network weights (.npy); default per order")
@@ -279,8 +280,7 @@ def main():
     coordV, V0T, kind, dT = make_inputs(cfg)
     torch.cuda.set_device(0)
     if args.precond is None:
-        args.precond = ("learned" if cfg["p"] in WEIGHTS and not cfg.get("stationary") and
-                        cfg["kind"] in (LOGNORMAL, LOGNORMAL_T) else "bj")
+        args.precond = "learned" if cfg["p"] in WEIGHTS and not cfg.get("stationary") else "bj"
     learned = args.precond == "learned"
     weights = None
     if learned:

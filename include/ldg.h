@@ -142,7 +142,9 @@ typedef struct {
  * Why a step left its first solver: a curvature p^T A p <= 0 (CG, flexible
  * CG), <r, P r> <= 0 with the learned preconditioner, a non-finite residual,
  * no new residual minimum (by 1%) within 200 flexible-CG iterations, a
- * nonsymmetric step (the learned preconditioner serves CG only), or a mixed
+ * nonsymmetric step the learned preconditioner does not serve (the residual
+ * correction network, or a factored preconditioner whose symmetric part has
+ * no Cholesky factor), or a mixed
  * sweep that failed to halve the residual while the inner solve reported a
  * four times larger reduction.
  */
@@ -427,6 +429,11 @@ ldg_status ldg_sample_workload(ldg_ctx* ctx, int kind, double t, const double* d
  * + w_o log ||O_kn||_F + b_o) from the same encoder and three layers fed the
  * node features only (N + 3 inputs).  Plain preconditioned CG keeps its
  * optimality with it; a breakdown returns the step to block-Jacobi CG.
+ * Nonsymmetric steps (d varying inside triangles) build the same operator
+ * from the symmetric part: W_k from the Cholesky factor of (BJ_k^{-1} +
+ * BJ_k^{-T}) / 2 and O_kn = W_k (S_kj + S_jk^T) / 2 W_j^T, SPD again, and apply
+ * it as a fixed right preconditioner of GMRES (where that Cholesky factor
+ * does not exist the step runs block-Jacobi GMRES and counts a fallback).
  * Parameters: the trunk as above with W_enc [(N+3) x 32], then w_hk [32],
  * w_hj [32], w_e [13], w_o, b_o.  Training uses the energy loss of
  * ldg_gnn_set_loss on the collected pairs, with the error e = target + rhat:

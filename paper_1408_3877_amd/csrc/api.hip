@@ -489,7 +489,7 @@ ldg_status grow_gmres(ldg_ctx* c, int m) {
 // One cycle of right-preconditioned GMRES(m) with classical Gram-Schmidt and
 // one conditional re-orthogonalisation; rnorm = ||r||.
 ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, double tol_abs,
-                       int maxit, int* iters) {
+                       int maxit, int* iters, bool factor = false) {
   const int64_t n = c->nvec;
   const int m = std::min(c->restart_cur, maxit);
   const size_t es = L.vt == VT_F64 ? 8 : 4;
@@ -504,7 +504,8 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
   for (int j = 0; j < m; ++j) {
     void* vj = V + (size_t)j * n * es;
     void* vn = V + (size_t)(j + 1) * n * es;
-    bj_apply(c, L, vj, L.z, false);
+    if (factor) fac_apply(c, L, vj, L.z);
+    else bj_apply(c, L, vj, L.z, false);
     apply_op(c, L, tau, L.z, false, L.tz1, L.tz2, vn);
     kdots(c, L, j + 1, V, vn);
     kupdate(c, L, j + 1, V, c->red.result, vn);
@@ -555,7 +556,8 @@ ldg_status inner_gmres(ldg_ctx* c, const Level& L, double tau, double rnorm, dou
     Timed tm(c, LDG_K_KRYLOV, L.vbytes * (jend + 1) * n, 2.0 * jend * n);
     launch_lincomb(L.vt, n, jend, V, n, c->ydev, L.u, c->st);
   }
-  bj_apply(c, L, L.u, L.d, false);
+  if (factor) fac_apply(c, L, L.u, L.d);
+  else bj_apply(c, L, L.u, L.d, false);
   *iters = jend;
   c->inner_rho = jend > 0 ? std::fabs(g[jend]) / rnorm : 1.0;
   c->gmres_full = jend == c->restart_cur;
@@ -651,14 +653,15 @@ ldg_status fac_alloc(ldg_ctx* c, bool training) {
 }
 
 // W, O blocks and log ||O|| of the current FP64 blocks and block-Jacobi inverses
-ldg_status fac_build(ldg_ctx* c, double tau) {
+// sym: build from the symmetric part of the operator (nonsymmetric steps)
+ldg_status fac_build(ldg_ctx* c, double tau, bool sym = false) {
   TRY(fac_alloc(c, false));
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int), c->st));
   {
     const double NN = (double)c->NN;
     Timed tm(c, LDG_K_FACTOR, 8.0 * NN * (8.0 * c->K), 2.0 * NN * c->N * (8.0 * c->Eint));
     launch_fac_setup(c->N, c->fac, c->geo, c->refs, c->blocks, c->bj, tau, c->opt.eta,
-                     c->fac_w64, c->fac_lognorm, c->status, c->st);
+                     c->fac_w64, c->fac_lognorm, c->status, sym, c->st);
   }
   TRY(check_launch(c));
   HIPCHK(c, hipMemcpyAsync(c->host_buf, c->status, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -825,7 +828,11 @@ ldg_status inner_solve(ldg_ctx* c, const Level& L, double tau, double tol, int l
       }
     }
   }
-  if (!*cg_mode && *it == 0) TRY(inner_gmres(c, L, tau, rnorm, tol, left, it));
+  if (!*cg_mode && *it == 0) {
+    const bool factor = *gnn_on && c->fac_on && c->gmode == LDG_GNN_FACTOR;
+    TRY(inner_gmres(c, L, tau, rnorm, tol, left, it, factor));
+    if (factor) info->learned_iters += *it;
+  }
   return LDG_OK;
 }
 
@@ -853,10 +860,15 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   // problems it is not used and the step counts one fallback
   bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode &&
                 (c->gmode == LDG_GNN_CORRECTION || c->fac_on);
-  if (c->opt.precond == LDG_PC_GNN && !cg_mode) {
+  // nonsymmetric steps: GMRES with the factored preconditioner of the
+  // symmetric part where it was built, else block-Jacobi GMRES (a fallback)
+  bool fac_gmres = c->opt.precond == LDG_PC_GNN && !cg_mode && c->fac_on &&
+                   c->gmode == LDG_GNN_FACTOR;
+  if (c->opt.precond == LDG_PC_GNN && !cg_mode && !fac_gmres) {
     info->fallbacks += 1;
     info->fallback_reason = LDG_FB_NONSYMMETRIC;
   }
+  if (fac_gmres) gnn_on = true;
   info->krylov = cg_mode ? LDG_KRYLOV_CG : LDG_KRYLOV_GMRES;
   while (true) {
     apply_op(c, L64, tau, c->X, true, c->tZ1, c->tZ2, c->w);
@@ -1578,10 +1590,19 @@ ldg_status solve_sampled(ldg_ctx* c, double alpha, double tau, const double* Chi
   if (c->opt.krylov == LDG_KRYLOV_AUTO) TRY(coefficient_is_elementwise_constant(c, &use_cg));
   // the factored learned preconditioner of this system (SPD case only)
   c->fac_on = false;
-  if (c->opt.precond == LDG_PC_GNN && c->gmode == LDG_GNN_FACTOR && use_cg) {
-    TRY(fac_build(c, tau));
-    TRY(fac_omega(c));
-    c->fac_on = true;
+  if (c->opt.precond == LDG_PC_GNN && c->gmode == LDG_GNN_FACTOR) {
+    if (use_cg) {
+      TRY(fac_build(c, tau));
+      TRY(fac_omega(c));
+      c->fac_on = true;
+    } else if (fac_build(c, tau, true) == LDG_OK) {
+      // nonsymmetric step: the factored preconditioner of the operator's
+      // symmetric part, a fixed SPD right preconditioner for GMRES
+      TRY(fac_omega(c));
+      c->fac_on = true;
+    } else {
+      c->err.clear();   // no Cholesky factor of the symmetric part: block-Jacobi GMRES
+    }
   }
   if (X0)
     HIPCHK(c, hipMemcpyAsync(c->X, X0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));

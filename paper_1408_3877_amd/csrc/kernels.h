@@ -130,7 +130,7 @@ struct FacStore {
 // operator blocks and block-Jacobi inverses; status |= 2 on a failed Cholesky
 void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* refs,
                       const double* blocks, const double* bj, double tau, double eta, double* w64,
-                      float* lognorm, int* status, hipStream_t st);
+                      float* lognorm, int* status, bool sym, hipStream_t st);
 // z = P r through y, a (work vectors); red: result[0] = <r, z>
 void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const float* om,
                       const void* r, void* y, void* a, void* z, const Reducer* red,

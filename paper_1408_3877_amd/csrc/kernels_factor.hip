@@ -113,12 +113,14 @@ __device__ inline float wscale(const float* __restrict__ ws, int64_t k) {
 }  // namespace
 
 // W_k = R_k^T, BJ_k^{-1} = R_k R_k^T (lower Cholesky), 16 lanes per triangle,
-// lane i owns row i; padding triangles get the identity.
+// lane i owns row i; padding triangles get the identity.  sym: factor the
+// symmetric part (BJ_k^{-1} + BJ_k^{-T}) / 2 instead (nonsymmetric steps; it is
+// positive definite where the symmetric part of the diagonal block is).
 template <int N, class BT>
 __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restrict__ bj,
                                                   double* __restrict__ w64, BT* __restrict__ fb,
                                                   float* __restrict__ ws,
-                                                  int* __restrict__ status) {
+                                                  int* __restrict__ status, bool sym) {
   constexpr int NP = npairs(N);
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = gid >> 4;
@@ -128,7 +130,9 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
   double a[N];
 #pragma unroll
   for (int c = 0; c < N; ++c)
-    a[c] = row_ok ? get64(bj, k, 0, 1, i * N + c, NP) : (c == i ? 1.0 : 0.0);
+    a[c] = row_ok ? (sym ? 0.5 * (get64(bj, k, 0, 1, i * N + c, NP) + get64(bj, k, 0, 1, c * N + i, NP))
+                         : get64(bj, k, 0, 1, i * N + c, NP))
+                  : (c == i ? 1.0 : 0.0);
   // right-looking, branch-free: after column c, lane i holds L[i][c] in a[c] and
   // the updated a[i][j] for j > c (entries with j > i are don't-cares)
   bool bad = false;
@@ -169,13 +173,16 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
 
 // O_kn for every interior edge once (from the triangle with the smaller index),
 // written to (k, n) and transposed to (k+, n+); lognorm = log ||O_kn||_F on both.
-// 64 threads = 4 triangles x 16 lanes; lane i owns row i.
+// 64 threads = 4 triangles x 16 lanes; lane i owns row i.  sym (nonsymmetric
+// steps): S_kj is replaced by the block of the symmetric part of the operator,
+// (S_kj + S_jk^T) / 2, with S_jk from the same formula seen from triangle j
+// (its edge n+, its blocks B^m_jj and U_jn+, the A^m_kk of triangle k).
 template <int N, class BT>
 __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restrict__ refs,
                                                     const double* __restrict__ blocks,
                                                     const double* __restrict__ w64, double tau,
                                                     double eta, BT* __restrict__ fo,
-                                                    float* __restrict__ lognorm) {
+                                                    float* __restrict__ lognorm, bool sym) {
   // every intermediate N x N matrix lives in LDS (one set per triangle of the
   // block); registers hold scalars only
   constexpr int NN = N * N;
@@ -184,6 +191,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
   __shared__ double t1[4][NN];
   __shared__ double t2[4][NN];
   __shared__ double t3[4][NN];
+  __shared__ double t4[4][NN];
   for (int t = threadIdx.x; t < NREF * NN; t += blockDim.x) sm[t] = refs[t];
   __syncthreads();
   const int grp = threadIdx.x >> 4;
@@ -198,6 +206,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
   double* T1 = t1[grp];
   double* T2 = t2[grp];
   double* T3 = t3[grp];
+  double* T4 = t4[grp];
 #pragma unroll 1
   for (int n = 0; n < 3; ++n) {
     const int64_t jn = elem_ok ? g.nbr[n * Kp + kk] : -1;
@@ -245,6 +254,53 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
       }
     }
     __syncthreads();
+    if (sym) {
+      // S_jk: nu_{j n+} = -nu_kn, |E| shared; T1 <- sum_m nu^m_{j n+} A^m_kk,
+      // T2 <- sum_m nu^m_{j n+} B^m_jj, T4 <- S_jk, then T3 <- (T3 + T4^T) / 2
+      {
+        const double B11 = g.B[kk], B12 = g.B[Kp + kk], B21 = g.B[2 * Kp + kk], B22 = g.B[3 * Kp + kk];
+        const double c0 = (nu1 * B22 - nu2 * B12);
+        const double c1 = (-nu1 * B21 + nu2 * B11);
+        double cq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int kd = g.kind[q * Kp + kk];
+          const double w = kd == LDG_EDGE_INTERIOR ? 0.5 : (kd == LDG_EDGE_NEUMANN ? 1.0 : 0.0);
+          cq[q] = -w * (nu1 * g.nu[(2 * q) * Kp + kk] + nu2 * g.nu[(2 * q + 1) * Kp + kk]) *
+                  g.elen[q * Kp + kk];
+        }
+        if (row) {
+#pragma unroll 1
+          for (int c = 0; c < N; ++c) {
+            const int e = ii * N + c;
+            T1[e] = c0 * sm[e] + c1 * sm[NN + e] + cq[0] * sm[2 * NN + e] +
+                    cq[1] * sm[3 * NN + e] + cq[2] * sm[4 * NN + e];
+            T2[e] = -nu1 * get64(blocks, j, 0, NSLOT, e, NP) - nu2 * get64(blocks, j, 1, NSLOT, e, NP);
+          }
+        }
+      }
+      __syncthreads();
+      if (row) {
+        const double* So = sm + ref_so(npl, n) * NN;
+        const double s1 = 0.5 * g.elen[n * Kp + kk] / g.area2[j];
+        const double s2 = 1.0 / area2k;
+#pragma unroll 1
+        for (int c = 0; c < N; ++c) {
+          double acc = -eta * So[ii * N + c];
+#pragma unroll
+          for (int l = 0; l < N; ++l)
+            acc -= s1 * T2[ii * N + l] * So[l * N + c] +
+                   s2 * get64(blocks, j, 2 + npl, NSLOT, ii * N + l, NP) * T1[l * N + c];
+          T4[ii * N + c] = tau * acc;
+        }
+      }
+      __syncthreads();
+      if (row) {
+#pragma unroll 1
+        for (int c = 0; c < N; ++c) T3[ii * N + c] = 0.5 * (T3[ii * N + c] + T4[c * N + ii]);
+      }
+      __syncthreads();
+    }
     // T2 <- W_j;  T1 <- T = S_kj W_j^T
     if (row) {
 #pragma unroll 1
@@ -470,12 +526,12 @@ __global__ void k_fac_export_rows(int64_t n, const int32_t* __restrict__ elems, 
 
 void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* refs,
                       const double* blocks, const double* bj, double tau, double eta, double* w64,
-                      float* lognorm, int* status, hipStream_t st) {
+                      float* lognorm, int* status, bool sym, hipStream_t st) {
   LDG_SWITCH_FAC(fs, {
     LDG_SWITCH_N(N, (k_fac_chol<NT, BW><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
-                        g, bj, w64, (BW*)fs.w, fs.ws, status)));
+                        g, bj, w64, (BW*)fs.w, fs.ws, status, sym)));
     LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO><<<nbk(g.Kpad, 4), 64, 0, st>>>(
-                        g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm)));
+                        g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm, sym)));
   })
 }
 
