@@ -39,6 +39,18 @@ def triangle_values(blocks, n_cells, block=8):
     return np.ascontiguousarray(blocks[ix // block, iy // block], np.float64)
 
 
+def position_values(blocks, n_cells, x, y, block=8):
+    """The block field sampled by position: the value of the block of cells of
+    the unjittered n_cells x n_cells grid that contains (x, y).  On a jittered
+    mesh, triangles then straddle block boundaries and the field jumps inside
+    them (the other reading of the block field)."""
+    nb = blocks.shape[0]
+    h = block / float(n_cells)
+    bx = np.clip(np.floor(np.asarray(x) / h).astype(np.int64), 0, nb - 1)
+    by = np.clip(np.floor(np.asarray(y) / h).astype(np.int64), 0, nb - 1)
+    return np.ascontiguousarray(blocks[bx, by], np.float64)
+
+
 class Workload:
     """Coefficient d, source f, boundary data c_D, g_N and exact c of one problem.
 
