@@ -94,7 +94,7 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
     t0 = time.perf_counter()
     s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
                max_iters=cfg.get("max_iters", 20000), precision=prec, inner_rtol=args.inner_rtol,
-               precond=1 if learned else 0)
+               precond=1 if learned else 0, keep_direction=not args.fresh_cg_sweeps)
     if learned:
         s.gnn_set_mode("factor")
         s.gnn_factor_storage(args.fac_storage)
@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="relative tolerance of each inner solve of the mixed modes (1e-2: fewest "
                          "CG iterations on the combined workload in a sweep over 1e-4 .. 1e-1)")
+    ap.add_argument("--fresh-cg-sweeps", action="store_true",
+                    help="start CG afresh in every refinement sweep instead of continuing "
+                         "from the previous sweep's search direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
@@ -335,7 +338,9 @@ def main():
         args.precision,
         "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
         "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
-        "" if prec == 0 else " + FP64 refinement (inner rtol %g)" % args.inner_rtol)
+        "" if prec == 0 else " + FP64 refinement (inner rtol %g%s)" % (
+            args.inner_rtol, ", fresh CG per sweep" if args.fresh_cg_sweeps
+            else ", CG direction kept across sweeps"))
     stationary = bool(cfg.get("stationary"))
     res = {
         "metric": ("DOF·solves/s of the stationary Table 2 problem to 1e-8 rel res" if stationary

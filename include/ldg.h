@@ -111,6 +111,13 @@ typedef struct {
   int krylov;         /* ldg_krylov, default LDG_KRYLOV_AUTO */
   double inner_rtol;  /* mixed modes: relative tolerance of each inner solve, default 1e-3 */
   int quad;           /* ldg_quad_policy of the reference tensors, default LDG_QUAD_EXACT */
+  int cg_keep_direction; /* mixed modes, CG steps.  1 (default): each refinement sweep
+                         after the first continues from the last search direction of the
+                         sweep before, the FP64 residual replacing the iterated one (as in
+                         reliable-update CG); the first new direction is made conjugate to
+                         the kept one, and its step length minimises along it.  0: every
+                         sweep starts CG afresh from p = P r.  GMRES sweeps always
+                         restart, and so does FP64 CG */
 } ldg_options;
 
 typedef struct {

@@ -100,6 +100,10 @@ struct ldg_ctx {
   ldg_kernel_stat stats[LDG_K_COUNT] = {};
   int64_t n_sd = 0, n_nd = 0;   // local edges that are not Neumann / not Dirichlet
   double inner_rho = 1.0;       // residual reduction the last inner solve reported
+  // CG state kept across the refinement sweeps of one step: the last search
+  // direction and its image (L.p, L.q of the level it ran at) and <p, A p>
+  bool cg_kept = false;
+  double cg_kept_pq = 0.0;
   // time scheme: implicit Euler, or two-step backward differentiation with the
   // state of the previous step (kept after every step) and its step size
   int tscheme = 0;
@@ -386,22 +390,50 @@ ldg_status snapshot(ldg_ctx* c, const Level& L, int it) {
 
 void fac_apply(ldg_ctx* c, const Level& L, const void* r, void* z);
 
+// keep: continue from the direction the previous sweep of this step left in
+// L.p (with A p in L.q and <p, A p> in c->cg_kept_pq) instead of starting
+// from p = P r.  The FP64 residual that replaced the iterated one is not
+// orthogonal to the kept direction, so the new direction is made conjugate to
+// it, p = P r - (<P r, A p_kept> / <p_kept, A p_kept>) p_kept, and the first
+// step length is the minimiser along it, <r, p> / <p, A p>.  Both are free of
+// the scale the refinement gives the residual.
 ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int maxit, int* iters,
-                    bool* not_spd, bool factor = false) {
+                    bool* not_spd, bool factor = false, bool keep = false) {
   double* hb = c->host_buf;
   *not_spd = false;
+  const bool resume = keep && c->cg_kept && c->cg_kept_pq > 0.0;
+  c->cg_kept = false;
   kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
   TRY(snapshot(c, L, 0));
-  double r0 = 0.0, rlast = 0.0;
-  TRY(norm2(c, L, L.r, &r0));
+  double r0 = 0.0, rlast = 0.0, rp_old = 0.0;
+  if (resume) {
+    kdots(c, L, 1, L.p, L.r);   // <p_kept, r>, <r, r>
+    TRY(check_launch(c));
+    TRY(fetch(c, c->red.result, 2, hb));
+    rp_old = hb[0];
+    r0 = hb[1];
+  } else {
+    TRY(norm2(c, L, L.r, &r0));
+  }
   r0 = std::sqrt(r0);
   rlast = r0;
   if (factor) fac_apply(c, L, L.r, L.z);
   else bj_apply(c, L, L.r, L.z, true);
   TRY(fetch(c, c->red.result, 1, hb));
   double rz = hb[0];
-  kaxpby(c, L, 1.0, L.z, 0.0, L.p);
+  double rp = rz;   // <r, p> of the current direction
+  if (resume) {
+    kdots(c, L, 1, L.q, L.z);   // <A p_kept, z>
+    TRY(check_launch(c));
+    TRY(fetch(c, c->red.result, 1, hb));
+    const double b = -hb[0] / c->cg_kept_pq;
+    kaxpby(c, L, 1.0, L.z, b, L.p);
+    rp = rz + b * rp_old;
+  } else {
+    kaxpby(c, L, 1.0, L.z, 0.0, L.p);
+  }
   int it = 0;
+  bool converged = false;
   while (it < maxit) {
     apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>
     TRY(fetch(c, c->red.result, 1, hb));
@@ -410,7 +442,8 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
       *not_spd = true;
       break;
     }
-    const double alpha = rz / pq;
+    c->cg_kept_pq = pq;
+    const double alpha = (it == 0 ? rp : rz) / pq;
     {
       Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
       launch_cg_update(L.vt, c->red2, c->nvec, alpha, L.p, L.q, L.d, L.r, c->st);
@@ -421,7 +454,10 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     const double rn = std::sqrt(hb[0]);
     if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
     rlast = rn;
-    if (rn <= tol_abs) break;
+    if (rn <= tol_abs) {
+      converged = true;
+      break;
+    }
     if (factor) fac_apply(c, L, L.r, L.z);
     else bj_apply(c, L, L.r, L.z, true);
     TRY(fetch(c, c->red.result, 1, hb));
@@ -432,6 +468,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   }
   *iters = it;
   c->inner_rho = r0 > 0.0 ? rlast / r0 : 1.0;
+  c->cg_kept = converged && it > 0;
   return LDG_OK;
 }
 
@@ -801,7 +838,8 @@ ldg_status inner_fcg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int
 // One inner solve at level L (rnorm = ||r|| for GMRES); a breakdown moves the
 // step to the next solver: learned -> block-Jacobi CG, CG -> GMRES.
 ldg_status inner_solve(ldg_ctx* c, const Level& L, double tau, double tol, int left, double rnorm,
-                       bool* cg_mode, bool* gnn_on, ldg_step_info* info, int* it) {
+                       bool* cg_mode, bool* gnn_on, ldg_step_info* info, int* it,
+                       bool keep = false) {
   *it = 0;
   if (*cg_mode && *gnn_on && c->gmode == LDG_GNN_CORRECTION) {
     int broke = LDG_FB_NONE;
@@ -815,7 +853,7 @@ ldg_status inner_solve(ldg_ctx* c, const Level& L, double tau, double tol, int l
   } else if (*cg_mode) {
     const bool factor = *gnn_on;  // the factored preconditioner of this step
     bool not_spd = false;
-    TRY(inner_cg(c, L, tau, tol, left, it, &not_spd, factor));
+    TRY(inner_cg(c, L, tau, tol, left, it, &not_spd, factor, keep));
     if (factor) info->learned_iters += *it;
     if (not_spd) {
       info->fallbacks += 1;
@@ -856,6 +894,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   double beta = 0.0, beta_prev = 0.0;
   bool cg_mode = use_cg;
   c->gmres_full = false;
+  c->cg_kept = false;
   // the learned preconditioner runs inside flexible CG (SPD case); for GMRES
   // problems it is not used and the step counts one fallback
   bool gnn_on = c->opt.precond == LDG_PC_GNN && cg_mode &&
@@ -898,6 +937,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
     if (escalate) {
       // refinement stagnates at this precision (the FP64 residual fell far less
       // than the inner solve reported): BF16 -> FP32 -> FP64
+      c->cg_kept = false;   // the kept direction lives in the old level's vectors
       info->fallbacks += 1;
       info->fallback_reason = LDG_FB_PRECISION;
       if (L.bt == BT_BF16) {
@@ -910,6 +950,11 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
         L = L64;
       }
     }
+    // mixed modes: CG continues from the previous sweep's direction (the FP64
+    // residual replacing the iterated one) unless the options ask for a fresh
+    // start.  In FP64 the residual overwrites that level's A p (L.q), and a
+    // second sweep is rare there.
+    const bool keep = c->opt.cg_keep_direction && sweeps > 0 && cg_mode && L.vt != VT_F64;
     beta_prev = beta;
     ++sweeps;
     int it = 0;
@@ -918,7 +963,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       HIPCHK(c, hipMemcpyAsync(L.r, c->w, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
       scale = 1.0;
       const int left = c->opt.max_iters - iters;
-      TRY(inner_solve(c, L, tau, 0.9 * target, left, beta, &cg_mode, &gnn_on, info, &it));
+      TRY(inner_solve(c, L, tau, 0.9 * target, left, beta, &cg_mode, &gnn_on, info, &it, keep));
     } else {
       {
         Timed tm(c, LDG_K_KRYLOV, 12.0 * n, (double)n);
@@ -927,7 +972,7 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
       scale = beta;
       const double tol = std::max(c->opt.inner_rtol, 0.5 * target / beta);
       const int left = c->opt.max_iters - iters;
-      TRY(inner_solve(c, L, tau, tol, left, 1.0, &cg_mode, &gnn_on, info, &it));
+      TRY(inner_solve(c, L, tau, tol, left, 1.0, &cg_mode, &gnn_on, info, &it, keep));
     }
     iters += it;
     {
@@ -1067,6 +1112,7 @@ ldg_status ldg_options_default(ldg_options* o) {
   o->krylov = LDG_KRYLOV_AUTO;
   o->inner_rtol = 1e-3;
   o->quad = LDG_QUAD_EXACT;
+  o->cg_keep_direction = 1;
   return LDG_OK;
 }
 
@@ -1100,6 +1146,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (opt->precond != LDG_PC_BLOCK_JACOBI && opt->precond != LDG_PC_GNN) return LDG_EINVAL;
   if (opt->precond == LDG_PC_GNN && opt->p > kMaxLearnedOrder) return LDG_EINVAL;
   if (opt->quad != LDG_QUAD_EXACT && opt->quad != LDG_QUAD_PAPER) return LDG_EINVAL;
+  if (opt->cg_keep_direction != 0 && opt->cg_keep_direction != 1) return LDG_EINVAL;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
   c->opt = *opt;

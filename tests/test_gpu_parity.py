@@ -178,12 +178,12 @@ def test_apply_and_preconditioner(torch_mod, n, seed, neu, p):
 
 
 def _run_steps(p, n, seed, neu, wkind, steps, dt, sigma=1.0, block=4, t0=0.0, krylov=0,
-               expect_krylov=None, precision=0, rtol=1e-13, infos=None):
+               expect_krylov=None, precision=0, rtol=1e-13, infos=None, **kw):
     cV, V0T, kind = square_mesh(n, seed=seed, neumann_sides=neu)
     pr = Problem(cV, V0T, kind, p)
     w = workload(wkind, n, seed=seed, sigma=sigma, block=block)
     s = _solver(cV, V0T, kind, p, rtol=rtol, restart=40, max_iters=20000, krylov=krylov,
-                precision=precision)
+                precision=precision, **kw)
     gk = {SMOOTH1: 1, SMOOTH2: 2, LOGNORMAL: 3, LOGNORMAL_T: 4, TABLE2: 5}[wkind]
     dT = getattr(w, "dT", None)
     smp0 = s.sample_workload(gk, t0, dT=dT, want=("c0",))
@@ -247,6 +247,23 @@ def test_mixed_precision_refinement(torch_mod, precision, p, n, seed, neu, wk):
                      infos=infos)
     assert err < 1e-9, err
     assert all(i["ir_steps"] >= 1 for i in infos)
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_cg_sweeps_with_and_without_the_kept_direction(torch_mod, precision):
+    # CG refinement sweeps either continue from the last search direction (the
+    # FP64 residual replacing the iterated one) or start afresh: both reach the
+    # oracle's solution, over several sweeps per step
+    res = {}
+    for keep in (True, False):
+        infos = []
+        err = _run_steps(4, 12, 403, (), LOGNORMAL_T, 2, 0.02, block=3, precision=precision,
+                         rtol=1e-12, infos=infos, keep_direction=keep)
+        assert err < 1e-9, (keep, err)
+        assert all(i["krylov"] == 2 and i["ir_steps"] >= 2 for i in infos), infos
+        res[keep] = [i["iters"] for i in infos]
+    print("[keep-direction] precision %d iterations kept %s fresh %s"
+          % (precision, res[True], res[False]), flush=True)
 
 
 @pytest.mark.parametrize("p,n,seed,neu,wk", [
