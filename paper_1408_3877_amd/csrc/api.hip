@@ -1315,6 +1315,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
     c->bj_f32 = p8;
     if (opt->precision == LDG_MIXED_BF16) {
       TRY(dalloc(c, &p8, block_bytes(BT_BF16, Kp, N, NSLOT)));
+      HIPCHK(c, hipMemsetAsync(p8, 0, block_bytes(BT_BF16, Kp, N, NSLOT), c->st));   // tail padding
       c->blocks_bf16 = p8;
     }
   }

@@ -100,6 +100,26 @@ template <> struct Blk<fp8> {
 
 __host__ __device__ constexpr int ngroups(int N, int W) { return (N * N + W - 1) / W; }
 
+// BF16 operator blocks are packed tighter: the first 8 floor(N^2 / 8) entries of
+// each slot in whole groups of eight, [k/64][s][g][k%64][8], then the other
+// N^2 mod 8 entries of every slot together in tail groups after the slots
+// (N = 15: 28 groups per slot and one tail group holding entry 224 of all five
+// slots, 141 groups per triangle instead of 145).  bp_idx is the storage index
+// of entry f of block s of triangle k.
+__host__ __device__ constexpr int bp_full(int N) { return N * N / 8; }
+__host__ __device__ constexpr int bp_rem(int N) { return N * N % 8; }
+__host__ __device__ constexpr int bp_tail(int N, int ns) { return (ns * bp_rem(N) + 7) / 8; }
+__host__ __device__ constexpr int bp_groups(int N, int ns) { return ns * bp_full(N) + bp_tail(N, ns); }
+__host__ __device__ inline int64_t bp_gidx(int64_t k, int g, int N, int ns) {
+  return (((k >> 6) * bp_groups(N, ns) + g) * TILE + (k & 63)) * 8;
+}
+__host__ __device__ inline int64_t bp_idx(int64_t k, int s, int f, int N, int ns) {
+  const int nf = bp_full(N);
+  if (f < 8 * nf) return bp_gidx(k, s * nf + f / 8, N, ns) + f % 8;
+  const int t = s * bp_rem(N) + (f - 8 * nf);
+  return bp_gidx(k, ns * nf + t / 8, N, ns) + t % 8;
+}
+
 __host__ __device__ inline int64_t bgidx(int64_t k, int s, int g, int ns, int ng, int W) {
   return ((((k >> 6) * ns + s) * (int64_t)ng + g) * TILE + (k & 63)) * W;
 }
@@ -148,6 +168,37 @@ __device__ inline void block_mv(const BT* __restrict__ blocks, int64_t k, int s,
       const int f = g * W + h;
       if (f < NN) acc[f / N] += v[h] * z[f % N];
     }
+  }
+}
+
+// packed BF16 blocks: the tail entries of all ns slots of triangle k, loaded
+// once per triangle, and acc += Blk(k, s) z from the slot's whole groups and
+// its tail entries
+template <int N, class T>
+__device__ inline void bp_tail_load(const bf16* __restrict__ blocks, int64_t k, int ns, T* tail) {
+#pragma unroll
+  for (int g = 0; g < bp_tail(N, ns); ++g)
+    Blk<bf16>::load(blocks + bp_gidx(k, ns * bp_full(N) + g, N, ns), tail + 8 * g);
+}
+
+template <int N, class T>
+__device__ inline void block_mv_bp(const bf16* __restrict__ blocks, int64_t k, int s, int ns,
+                                   const T* tail, const T* z, T* acc) {
+  constexpr int NF = bp_full(N), R = bp_rem(N);
+#pragma unroll
+  for (int g = 0; g < NF; ++g) {
+    T v[8];
+    Blk<bf16>::load(blocks + bp_gidx(k, s * NF + g, N, ns), v);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int f = g * 8 + h;
+      acc[f / N] += v[h] * z[f % N];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int f = 8 * NF + j;
+    acc[f / N] += tail[s * R + j] * z[f % N];
   }
 }
 

@@ -88,13 +88,17 @@ __device__ inline void store_col(typename Mfma<PREC>::Out* __restrict__ blocks, 
       *reinterpret_cast<float4*>(blocks + bgidx(k, s, gi, NSLOT, NG, 4)) =
           make_float4(vf[0], vf[1], vf[2], vf[3]);
   } else {
-    constexpr int NG = ngroups(N, 8);
-    const int gi = 2 * ft + (q >> 1);
-    if (gi < NG) {
+    // packed BF16 layout: rows 16 ft + 4q .. +3 are half a group, or tail entries
+    const int f0 = 16 * ft + 4 * q;
+    if (f0 < 8 * bp_full(N)) {
       uint2 w;
       w.x = (uint32_t)to_bf16(vf[0]) | ((uint32_t)to_bf16(vf[1]) << 16);
       w.y = (uint32_t)to_bf16(vf[2]) | ((uint32_t)to_bf16(vf[3]) << 16);
-      *reinterpret_cast<uint2*>(blocks + bgidx(k, s, gi, NSLOT, NG, 8) + 4 * (q & 1)) = w;
+      *reinterpret_cast<uint2*>(blocks + bp_idx(k, s, f0, N, NSLOT)) = w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (f0 + j < NN) blocks[bp_idx(k, s, f0 + j, N, NSLOT)] = to_bf16(vf[j]);
     }
   }
   (void)NN;
