@@ -1,5 +1,6 @@
 // C ABI of the LDG library: context, data upload, one implicit Euler step
 // (projection, assembly, preconditioner, restarted GMRES, recovery of Z).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -104,6 +105,7 @@ struct ldg_ctx {
   // direction and its image (L.p, L.q of the level it ran at) and <p, A p>
   bool cg_kept = false;
   double cg_kept_pq = 0.0;
+  double* cgs = nullptr;   // CG scalars on the device (CGS_*)
   // time scheme: implicit Euler, or two-step backward differentiation with the
   // state of the previous step (kept after every step) and its step size
   int tscheme = 0;
@@ -405,7 +407,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   c->cg_kept = false;
   kaxpby(c, L, 0.0, L.r, 0.0, L.d);   // d = 0
   TRY(snapshot(c, L, 0));
-  double r0 = 0.0, rlast = 0.0, rp_old = 0.0;
+  double r0 = 0.0, rp_old = 0.0;
   if (resume) {
     kdots(c, L, 1, L.p, L.r);   // <p_kept, r>, <r, r>
     TRY(check_launch(c));
@@ -416,12 +418,12 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     TRY(norm2(c, L, L.r, &r0));
   }
   r0 = std::sqrt(r0);
-  rlast = r0;
+  double rlast = r0;
   if (factor) fac_apply(c, L, L.r, L.z);
   else bj_apply(c, L, L.r, L.z, true);
   TRY(fetch(c, c->red.result, 1, hb));
-  double rz = hb[0];
-  double rp = rz;   // <r, p> of the current direction
+  const double rz = hb[0];
+  double rp = rz;   // <r, p> of the first direction
   if (resume) {
     kdots(c, L, 1, L.q, L.z);   // <A p_kept, z>
     TRY(check_launch(c));
@@ -432,41 +434,68 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   } else {
     kaxpby(c, L, 1.0, L.z, 0.0, L.p);
   }
-  int it = 0;
+  // The step lengths and the coefficients of the directions stay on the
+  // device (launch_cg_alpha / launch_cg_beta in stream order), and the
+  // residual norm is read back only at checks: the next check is placed at
+  // half the iterations the rate so far needs to reach the tolerance (at most
+  // 16 ahead), so the loop syncs a few dozen times per solve instead of three
+  // times per iteration and overshoots the tolerance by an iteration or so.
+  if (!(rz > 0.0) || !std::isfinite(rz)) {   // the preconditioner is not positive on r
+    *not_spd = true;
+    *iters = 0;
+    c->inner_rho = 1.0;
+    return LDG_OK;
+  }
+  launch_cg_start(c->cgs, rz, rp, c->st);
+  int it = 0, next_check = 1;
   bool converged = false;
-  while (it < maxit) {
+  const bool every = c->col_n > 0;   // iterate snapshots: check every iteration
+  while (true) {
     apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>
-    TRY(fetch(c, c->red.result, 1, hb));
-    const double pq = hb[0];
-    if (!(pq > 0.0) || !(rz > 0.0)) {
-      *not_spd = true;
-      break;
-    }
-    c->cg_kept_pq = pq;
-    const double alpha = (it == 0 ? rp : rz) / pq;
+    launch_cg_alpha(c->red.result, c->cgs, c->st);
     {
       Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
-      launch_cg_update(L.vt, c->red2, c->nvec, alpha, L.p, L.q, L.d, L.r, c->st);
-    }
-    TRY(fetch(c, c->red2.result, 1, hb));
-    ++it;
-    TRY(snapshot(c, L, it));
-    const double rn = std::sqrt(hb[0]);
-    if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
-    rlast = rn;
-    if (rn <= tol_abs) {
-      converged = true;
-      break;
+      launch_cg_update(L.vt, c->red2, c->nvec, 0.0, L.p, L.q, L.d, L.r, c->st,
+                       c->cgs + CGS_ALPHA);   // x += a p, r -= a q, <r, r>
     }
     if (factor) fac_apply(c, L, L.r, L.z);
     else bj_apply(c, L, L.r, L.z, true);
-    TRY(fetch(c, c->red.result, 1, hb));
-    const double rz_new = hb[0];
-    const double beta = rz_new / rz;
-    rz = rz_new;
-    kaxpby(c, L, 1.0, L.z, beta, L.p);
+    launch_cg_beta(c->red.result, c->cgs, c->st);
+    ++it;
+    TRY(snapshot(c, L, it));
+    if (every || it >= next_check || it >= maxit) {
+      HIPCHK(c, hipMemcpyAsync(hb, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipMemcpyAsync(hb + 1, c->cgs, CGS_N * sizeof(double), hipMemcpyDeviceToHost,
+                               c->st));
+      TRY(sync(c));
+      const double rn = std::sqrt(hb[0]);
+      if (hb[1 + CGS_FLAG] != 0.0) {
+        // a curvature or <r, z> that was not positive: the updates stopped there
+        *not_spd = true;
+        break;
+      }
+      if (!std::isfinite(rn)) return fail(c, LDG_ENOCONV, "non-finite CG residual");
+      rlast = rn;
+      if (rn <= tol_abs) {
+        converged = true;
+        c->cg_kept_pq = hb[1 + CGS_PQ];
+        break;
+      }
+      if (it >= maxit) break;
+      const double rate = std::pow(rn / r0, 1.0 / it);
+      int gap = 16;
+      if (rate < 1.0 && rate > 0.0) {
+        const double need = std::log(tol_abs / rn) / std::log(rate);
+        gap = (int)std::min(16.0, std::max(1.0, 0.5 * need));
+      }
+      next_check = it + gap;
+    }
+    {
+      Timed tm(c, LDG_K_KRYLOV, 3.0 * L.vbytes * c->nvec, 2.0 * c->nvec);
+      launch_xpby_dev(L.vt, c->nvec, L.z, c->cgs + CGS_BETA, L.p, c->st);   // p = z + b p
+    }
   }
-  *iters = it;
+  *iters = (int)hb[1 + CGS_ITER];   // iterations that updated the iterate
   c->inner_rho = r0 > 0.0 ? rlast / r0 : 1.0;
   c->cg_kept = converged && it > 0;
   return LDG_OK;
@@ -1339,9 +1368,12 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   c->red.nblk = c->red2.nblk = krylov_nblk(nv);
   TRY(krylov_buffers(c, opt->restart));
   c->restart_cur = opt->restart;
+  // red2 also takes the per-block sums of the fused CG update (one per 256 triangles)
   TRY(dalloc(c, &c->red2.partials,
-             std::max<size_t>(c->red2.nblk, gs_nblk(nv)) + 2048));
+             std::max<size_t>({(size_t)c->red2.nblk, (size_t)gs_nblk(nv), (size_t)(Kp / 64 + 1)}) +
+                 2048));
   TRY(dalloc(c, &c->red2.result, 1));
+  TRY(dalloc(c, &c->cgs, CGS_N));
   TRY(sync(c));
   c->t = 0.0;
   c->err.clear();

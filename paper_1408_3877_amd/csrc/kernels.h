@@ -178,9 +178,21 @@ void launch_lincomb(int vt, int64_t n, int nv, const void* V, int64_t ldv, const
                     void* u, hipStream_t st);
 // y = a x + b y
 void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y, hipStream_t st);
-// CG: x += a p, r -= a q; result[0] = <r, r> afterwards
+// CG: x += a p, r -= a q; result[0] = <r, r> afterwards (a = *adev when adev != NULL)
 void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
-                      void* x, void* rv, hipStream_t st);
+                      void* x, void* rv, hipStream_t st, const double* adev = nullptr);
+// CG scalars kept on the device: s[CGS_*], set by one-thread kernels in stream
+// order, so the host reads them only when it checks convergence
+enum { CGS_RZ = 0, CGS_NUM = 1, CGS_PQ = 2, CGS_ALPHA = 3, CGS_BETA = 4, CGS_FLAG = 5, CGS_ITER = 6,
+       CGS_N = 8 };
+void launch_cg_start(double* s, double rz, double num, hipStream_t st);
+// s[ALPHA] = s[NUM] / pq[0] and s[ITER] += 1 (0 and s[FLAG] = 1 on a non-positive
+// curvature; an update with step 0 leaves x and r alone)
+void launch_cg_alpha(const double* pq, double* s, hipStream_t st);
+// s[BETA] = rzn[0] / s[RZ], then s[RZ] = s[NUM] = rzn[0] (flag on rzn <= 0)
+void launch_cg_beta(const double* rzn, double* s, hipStream_t st);
+// y = x + s[BETA] y, the coefficient read on the device
+void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void* y, hipStream_t st);
 // out = a * in across precisions
 void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, void* out,
                  hipStream_t st);

@@ -3,6 +3,8 @@
 // Inner products and norms always accumulate in FP64 with a deterministic
 // two-stage reduction: block partials written in a fixed grid order, then
 // summed by one workgroup in a fixed order.
+#include <cfloat>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -170,22 +172,81 @@ __global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b,
   y[i] = (T)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
 }
 
-// CG: x += a p, r -= a q, partial sums of the new <r, r>
+// y = x + (*bdev) y, KITEMS entries per thread like the CG update
 template <class T>
-__global__ void __launch_bounds__(KB) k_cg_update(int64_t n, double a, const T* __restrict__ p,
+__global__ void __launch_bounds__(KB) k_xpby_dev(int64_t n, const T* __restrict__ x,
+                                                 const double* __restrict__ bdev,
+                                                 T* __restrict__ y) {
+  const double b = *bdev;
+  const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
+#pragma unroll
+  for (int t = 0; t < KITEMS; ++t) {
+    const int64_t i = base + (int64_t)t * KB;
+    if (i < n) y[i] = (T)((double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
+  }
+}
+
+// CG scalars on the device, s[CGS_*] (one thread each).  start: <r, z> and the
+// numerator of the first step length.  alpha: a = num / <p, A p>, or 0 with a
+// flag once a curvature <p, A p> or <r, z> is not positive (every later update
+// then leaves the iterate alone).  beta: b = <r, z>_new / <r, z>, the new
+// <r, z> becoming the numerator of the next step length.
+__global__ void k_cg_start(double* __restrict__ s, double rz, double num) {
+  s[CGS_RZ] = rz;
+  s[CGS_NUM] = num;
+  s[CGS_PQ] = 0.0;
+  s[CGS_ALPHA] = 0.0;
+  s[CGS_BETA] = 0.0;
+  s[CGS_FLAG] = 0.0;
+  s[CGS_ITER] = 0.0;
+}
+
+__global__ void k_cg_alpha(const double* __restrict__ pq, double* __restrict__ s) {
+  const double v = pq[0];
+  s[CGS_PQ] = v;
+  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX) || !(s[CGS_RZ] > 0.0)) {
+    s[CGS_ALPHA] = 0.0;
+    s[CGS_FLAG] = 1.0;
+  } else {
+    s[CGS_ALPHA] = s[CGS_NUM] / v;
+    s[CGS_ITER] += 1.0;
+  }
+}
+
+__global__ void k_cg_beta(const double* __restrict__ rzn, double* __restrict__ s) {
+  const double v = rzn[0];
+  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX)) {
+    s[CGS_BETA] = 0.0;
+    s[CGS_FLAG] = 1.0;
+    return;
+  }
+  s[CGS_BETA] = v / s[CGS_RZ];
+  s[CGS_RZ] = v;
+  s[CGS_NUM] = v;
+}
+
+// CG: x += a p, r -= a q, partial sums of the new <r, r>; with adev the step
+// length is read from the device (CG scalars kept on the device)
+template <class T>
+__global__ void __launch_bounds__(KB) k_cg_update(int64_t n, double a, const double* __restrict__ adev,
+                                                  const T* __restrict__ p,
                                                   const T* __restrict__ q, T* __restrict__ x,
                                                   T* __restrict__ r,
                                                   double* __restrict__ partials) {
   __shared__ double red[KB / 64];
+  if (adev) a = *adev;
   const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < KITEMS; ++t) {
     const int64_t i = base + (int64_t)t * KB;
     if (i < n) {
-      x[i] = (T)((double)x[i] + a * (double)p[i]);
-      const T ri = (T)((double)r[i] - a * (double)q[i]);
-      r[i] = ri;
+      T ri = r[i];
+      if (a != 0.0) {   // a step of 0 (a stopped device-side CG) leaves x and r alone
+        x[i] = (T)((double)x[i] + a * (double)p[i]);
+        ri = (T)((double)ri - a * (double)q[i]);
+        r[i] = ri;
+      }
       s += (double)ri * (double)ri;
     }
   }
@@ -295,11 +356,26 @@ void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y,
 }
 
 void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
-                      void* x, void* rv, hipStream_t st) {
+                      void* x, void* rv, hipStream_t st, const double* adev) {
   const int nb = krylov_nblk(n);
-  LDG_VT(vt, (k_cg_update<T><<<nb, KB, 0, st>>>(n, a, (const T*)p, (const T*)q, (T*)x, (T*)rv,
-                                                r.partials)));
+  LDG_VT(vt, (k_cg_update<T><<<nb, KB, 0, st>>>(n, a, adev, (const T*)p, (const T*)q, (T*)x,
+                                                (T*)rv, r.partials)));
   k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+}
+
+void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void* y,
+                     hipStream_t st) {
+  LDG_VT(vt, (k_xpby_dev<T><<<krylov_nblk(n), KB, 0, st>>>(n, (const T*)x, bdev, (T*)y)));
+}
+
+void launch_cg_start(double* s, double rz, double num, hipStream_t st) {
+  k_cg_start<<<1, 1, 0, st>>>(s, rz, num);
+}
+void launch_cg_alpha(const double* pq, double* s, hipStream_t st) {
+  k_cg_alpha<<<1, 1, 0, st>>>(pq, s);
+}
+void launch_cg_beta(const double* rzn, double* s, hipStream_t st) {
+  k_cg_beta<<<1, 1, 0, st>>>(rzn, s);
 }
 
 void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, void* out,
