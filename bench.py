@@ -339,8 +339,8 @@ def main():
         "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
         "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
         "" if prec == 0 else " + FP64 refinement (inner rtol %g%s)" % (
-            args.inner_rtol, ", fresh CG per sweep" if args.fresh_cg_sweeps
-            else ", CG direction kept across sweeps"))
+            args.inner_rtol, "" if infos[-1]["krylov"] != 2 else
+            ", fresh CG per sweep" if args.fresh_cg_sweeps else ", CG direction kept across sweeps"))
     stationary = bool(cfg.get("stationary"))
     res = {
         "metric": ("DOF·solves/s of the stationary Table 2 problem to 1e-8 rel res" if stationary

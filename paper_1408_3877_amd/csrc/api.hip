@@ -698,6 +698,9 @@ ldg_status fac_alloc(ldg_ctx* c, bool training) {
     float* fo = nullptr;
     TRY(dalloc(c, &fw, per_slot));
     TRY(dalloc(c, &fo, 3 * per_slot));
+    // boundary edges have no O block: their entries (and the unused places of
+    // the shared tail groups) stay zero
+    HIPCHK(c, hipMemsetAsync(fo, 0, 3 * per_slot * sizeof(float), c->st));
     c->fac.w = fw;
     c->fac.o = fo;
     TRY(dalloc(c, &c->fac.ws, (size_t)c->Kpad));

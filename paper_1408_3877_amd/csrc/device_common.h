@@ -100,24 +100,29 @@ template <> struct Blk<fp8> {
 
 __host__ __device__ constexpr int ngroups(int N, int W) { return (N * N + W - 1) / W; }
 
-// BF16 operator blocks are packed tighter: the first 8 floor(N^2 / 8) entries of
-// each slot in whole groups of eight, [k/64][s][g][k%64][8], then the other
-// N^2 mod 8 entries of every slot together in tail groups after the slots
-// (N = 15: 28 groups per slot and one tail group holding entry 224 of all five
-// slots, 141 groups per triangle instead of 145).  bp_idx is the storage index
-// of entry f of block s of triangle k.
-__host__ __device__ constexpr int bp_full(int N) { return N * N / 8; }
-__host__ __device__ constexpr int bp_rem(int N) { return N * N % 8; }
-__host__ __device__ constexpr int bp_tail(int N, int ns) { return (ns * bp_rem(N) + 7) / 8; }
-__host__ __device__ constexpr int bp_groups(int N, int ns) { return ns * bp_full(N) + bp_tail(N, ns); }
-__host__ __device__ inline int64_t bp_gidx(int64_t k, int g, int N, int ns) {
-  return (((k >> 6) * bp_groups(N, ns) + g) * TILE + (k & 63)) * 8;
+// Packed block layout (BF16 operator blocks, and the factor's O blocks in
+// every storage): with W entries per 16-byte group, the first W floor(N^2 / W)
+// entries of each slot in whole groups, [k/64][s][g][k%64][W], then the other
+// N^2 mod W entries of every slot together in tail groups after the slots
+// (BF16, N = 15: 28 groups per slot and one tail group holding entry 224 of all
+// five slots, 141 groups per triangle instead of 145).  bp_idx is the storage
+// index of entry f of block s of triangle k.
+__host__ __device__ constexpr int bp_full(int N, int W = 8) { return N * N / W; }
+__host__ __device__ constexpr int bp_rem(int N, int W = 8) { return N * N % W; }
+__host__ __device__ constexpr int bp_tail(int N, int ns, int W = 8) {
+  return (ns * bp_rem(N, W) + W - 1) / W;
 }
-__host__ __device__ inline int64_t bp_idx(int64_t k, int s, int f, int N, int ns) {
-  const int nf = bp_full(N);
-  if (f < 8 * nf) return bp_gidx(k, s * nf + f / 8, N, ns) + f % 8;
-  const int t = s * bp_rem(N) + (f - 8 * nf);
-  return bp_gidx(k, ns * nf + t / 8, N, ns) + t % 8;
+__host__ __device__ constexpr int bp_groups(int N, int ns, int W = 8) {
+  return ns * bp_full(N, W) + bp_tail(N, ns, W);
+}
+__host__ __device__ inline int64_t bp_gidx(int64_t k, int g, int N, int ns, int W = 8) {
+  return (((k >> 6) * bp_groups(N, ns, W) + g) * TILE + (k & 63)) * W;
+}
+__host__ __device__ inline int64_t bp_idx(int64_t k, int s, int f, int N, int ns, int W = 8) {
+  const int nf = bp_full(N, W);
+  if (f < W * nf) return bp_gidx(k, s * nf + f / W, N, ns, W) + f % W;
+  const int t = s * bp_rem(N, W) + (f - W * nf);
+  return bp_gidx(k, ns * nf + t / W, N, ns, W) + t % W;
 }
 
 __host__ __device__ inline int64_t bgidx(int64_t k, int s, int g, int ns, int ng, int W) {
@@ -171,33 +176,40 @@ __device__ inline void block_mv(const BT* __restrict__ blocks, int64_t k, int s,
   }
 }
 
-// packed BF16 blocks: the tail entries of all ns slots of triangle k, loaded
-// once per triangle, and acc += Blk(k, s) z from the slot's whole groups and
-// its tail entries
-template <int N, class T>
-__device__ inline void bp_tail_load(const bf16* __restrict__ blocks, int64_t k, int ns, T* tail) {
-#pragma unroll
-  for (int g = 0; g < bp_tail(N, ns); ++g)
-    Blk<bf16>::load(blocks + bp_gidx(k, ns * bp_full(N) + g, N, ns), tail + 8 * g);
+// packed blocks: the tail entries of all ns slots of triangle k, loaded once
+// per triangle (TAILN values), and acc += Blk(k, s) z from the slot's whole
+// groups and its tail entries
+template <int N, class BT>
+__host__ __device__ constexpr int bp_tailn(int ns) {
+  return bp_tail(N, ns, Blk<BT>::W) > 0 ? Blk<BT>::W * bp_tail(N, ns, Blk<BT>::W) : 1;
 }
 
-template <int N, class T>
-__device__ inline void block_mv_bp(const bf16* __restrict__ blocks, int64_t k, int s, int ns,
+template <int N, class BT, class T>
+__device__ inline void bp_tail_load(const BT* __restrict__ blocks, int64_t k, int ns, T* tail) {
+  constexpr int W = Blk<BT>::W;
+#pragma unroll
+  for (int g = 0; g < bp_tail(N, ns, W); ++g)
+    Blk<BT>::load(blocks + bp_gidx(k, ns * bp_full(N, W) + g, N, ns, W), tail + W * g);
+}
+
+template <int N, class BT, class T>
+__device__ inline void block_mv_bp(const BT* __restrict__ blocks, int64_t k, int s, int ns,
                                    const T* tail, const T* z, T* acc) {
-  constexpr int NF = bp_full(N), R = bp_rem(N);
+  constexpr int W = Blk<BT>::W;
+  constexpr int NF = bp_full(N, W), R = bp_rem(N, W);
 #pragma unroll
   for (int g = 0; g < NF; ++g) {
-    T v[8];
-    Blk<bf16>::load(blocks + bp_gidx(k, s * NF + g, N, ns), v);
+    T v[W];
+    Blk<BT>::load(blocks + bp_gidx(k, s * NF + g, N, ns, W), v);
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int f = g * 8 + h;
+    for (int h = 0; h < W; ++h) {
+      const int f = g * W + h;
       acc[f / N] += v[h] * z[f % N];
     }
   }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int f = 8 * NF + j;
+    const int f = W * NF + j;
     acc[f / N] += tail[s * R + j] * z[f % N];
   }
 }

@@ -205,13 +205,13 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
   }
   if constexpr (BLOCKS) {
     constexpr bool PACKED = sizeof(BT) == 2;   // BF16: packed layout with tail groups
-    T tail[PACKED && bp_tail(N, NSLOT) > 0 ? 8 * bp_tail(N, NSLOT) : 1];
-    if constexpr (PACKED) bp_tail_load<N, T>(blocks, k, NSLOT, tail);
+    T tail[PACKED ? bp_tailn<N, BT>(NSLOT) : 1];
+    if constexpr (PACKED) bp_tail_load<N, BT, T>(blocks, k, NSLOT, tail);
     load_vec<N, T>(Z1, k, z);
-    if constexpr (PACKED) block_mv_bp<N, T>(blocks, k, 0, NSLOT, tail, z, t);
+    if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 0, NSLOT, tail, z, t);
     else block_mv<N, BT, T>(blocks, k, 0, NSLOT, z, t);
     load_vec<N, T>(Z2, k, z);
-    if constexpr (PACKED) block_mv_bp<N, T>(blocks, k, 1, NSLOT, tail, z, t);
+    if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 1, NSLOT, tail, z, t);
     else block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
     for (int n = 0; n < 3; ++n) {
       const int64_t kp = g.nbr[n * Kp + k];
@@ -219,7 +219,7 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
       const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
 #pragma unroll
       for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
-      if constexpr (PACKED) block_mv_bp<N, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
+      if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
       else block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
     }
   }
@@ -327,7 +327,7 @@ __global__ void k_export_any(int64_t K, int N, int ns, const BT* __restrict__ sr
   const int64_t k = t / (ns * NN);
   const int rem = (int)(t % (ns * NN));
   const int s = rem / NN, f = rem % NN;
-  BT v = sizeof(BT) == 2 ? src[bp_idx(k, s, f, N, ns)] : src[bgidx(k, s, f / W, ns, NG, W) + f % W];
+  BT v = sizeof(BT) == 2 ? src[bp_idx(k, s, f, N, ns, 8)] : src[bgidx(k, s, f / W, ns, NG, W) + f % W];
   if constexpr (sizeof(BT) == 2) {
     dst[t] = (double)__uint_as_float((uint32_t)v << 16);
   } else if constexpr (sizeof(BT) == 1) {
@@ -444,7 +444,7 @@ void launch_export_rows(int64_t n, const int32_t* elems, int N, int ns, const do
 }
 
 size_t block_bytes(int bt, int64_t Kpad, int N, int ns) {
-  if (bt == BT_BF16) return (size_t)(Kpad / TILE) * bp_groups(N, ns) * TILE * 8 * 2;
+  if (bt == BT_BF16) return (size_t)(Kpad / TILE) * bp_groups(N, ns, 8) * TILE * 8 * 2;
   const int W = bt == BT_F64 ? 2 : (bt == BT_F32 ? 4 : 8);
   const size_t es = bt == BT_F64 ? 8 : (bt == BT_F32 ? 4 : 2);
   return (size_t)Kpad * ns * ngroups(N, W) * W * es;

@@ -90,15 +90,15 @@ __device__ inline void store_col(typename Mfma<PREC>::Out* __restrict__ blocks, 
   } else {
     // packed BF16 layout: rows 16 ft + 4q .. +3 are half a group, or tail entries
     const int f0 = 16 * ft + 4 * q;
-    if (f0 < 8 * bp_full(N)) {
+    if (f0 < 8 * bp_full(N, 8)) {
       uint2 w;
       w.x = (uint32_t)to_bf16(vf[0]) | ((uint32_t)to_bf16(vf[1]) << 16);
       w.y = (uint32_t)to_bf16(vf[2]) | ((uint32_t)to_bf16(vf[3]) << 16);
-      *reinterpret_cast<uint2*>(blocks + bp_idx(k, s, f0, N, NSLOT)) = w;
+      *reinterpret_cast<uint2*>(blocks + bp_idx(k, s, f0, N, NSLOT, 8)) = w;
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (f0 + j < NN) blocks[bp_idx(k, s, f0 + j, N, NSLOT)] = to_bf16(vf[j]);
+        if (f0 + j < NN) blocks[bp_idx(k, s, f0 + j, N, NSLOT, 8)] = to_bf16(vf[j]);
     }
   }
   (void)NN;

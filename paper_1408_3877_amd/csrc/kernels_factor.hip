@@ -31,18 +31,15 @@ constexpr int NREF = 14;  // H1, H2, Sd[3], So[3][3]
 __device__ inline int ref_so(int a, int b) { return 5 + 3 * a + b; }
 inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// the O blocks use the packed layout (whole groups per slot, shared tail groups)
 template <class BT>
 __device__ inline void put(BT* __restrict__ fb, int64_t k, int s, int ns, int f, int N, double v) {
-  constexpr int Wv = Blk<BT>::W;
-  const int NG = ngroups(N, Wv);
-  fb[bgidx(k, s, f / Wv, ns, NG, Wv) + f % Wv] = from_double<BT>(v);
+  fb[bp_idx(k, s, f, N, ns, Blk<BT>::W)] = from_double<BT>(v);
 }
 
 template <class BT>
 __device__ inline double get_any(const BT* __restrict__ fb, int64_t k, int s, int ns, int f, int N) {
-  constexpr int Wv = Blk<BT>::W;
-  const int NG = ngroups(N, Wv);
-  const BT v = fb[bgidx(k, s, f / Wv, ns, NG, Wv) + f % Wv];
+  const BT v = fb[bp_idx(k, s, f, N, ns, Blk<BT>::W)];
   if constexpr (sizeof(BT) == 2) return (double)__uint_as_float((uint32_t)v << 16);
   else if constexpr (sizeof(BT) == 1) return (double)fp8_to_float(v);
   else return (double)v;
@@ -173,16 +170,16 @@ __global__ void __launch_bounds__(256) k_fac_chol(Geo g, const double* __restric
 
 // O_kn for every interior edge once (from the triangle with the smaller index),
 // written to (k, n) and transposed to (k+, n+); lognorm = log ||O_kn||_F on both.
-// 64 threads = 4 triangles x 16 lanes; lane i owns row i.  sym (nonsymmetric
+// 64 threads = 4 triangles x 16 lanes; lane i owns row i.  SYM (nonsymmetric
 // steps): S_kj is replaced by the block of the symmetric part of the operator,
 // (S_kj + S_jk^T) / 2, with S_jk from the same formula seen from triangle j
 // (its edge n+, its blocks B^m_jj and U_jn+, the A^m_kk of triangle k).
-template <int N, class BT>
+template <int N, class BT, bool SYM>
 __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restrict__ refs,
                                                     const double* __restrict__ blocks,
                                                     const double* __restrict__ w64, double tau,
                                                     double eta, BT* __restrict__ fo,
-                                                    float* __restrict__ lognorm, bool sym) {
+                                                    float* __restrict__ lognorm) {
   // every intermediate N x N matrix lives in LDS (one set per triangle of the
   // block); registers hold scalars only
   constexpr int NN = N * N;
@@ -191,7 +188,9 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
   __shared__ double t1[4][NN];
   __shared__ double t2[4][NN];
   __shared__ double t3[4][NN];
-  __shared__ double t4[4][NN];
+  // S_jk only for the symmetric part: the plain instance keeps 7 KB less LDS
+  // (three workgroups per CU instead of two)
+  __shared__ double t4[SYM ? 4 : 1][SYM ? NN : 1];
   for (int t = threadIdx.x; t < NREF * NN; t += blockDim.x) sm[t] = refs[t];
   __syncthreads();
   const int grp = threadIdx.x >> 4;
@@ -206,7 +205,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
   double* T1 = t1[grp];
   double* T2 = t2[grp];
   double* T3 = t3[grp];
-  double* T4 = t4[grp];
+  double* T4 = SYM ? t4[grp] : nullptr;
 #pragma unroll 1
   for (int n = 0; n < 3; ++n) {
     const int64_t jn = elem_ok ? g.nbr[n * Kp + kk] : -1;
@@ -254,7 +253,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
       }
     }
     __syncthreads();
-    if (sym) {
+    if constexpr (SYM) {
       // S_jk: nu_{j n+} = -nu_kn, |E| shared; T1 <- sum_m nu^m_{j n+} A^m_kk,
       // T2 <- sum_m nu^m_{j n+} B^m_jj, T4 <- S_jk, then T3 <- (T3 + T4^T) / 2
       {
@@ -402,6 +401,8 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
     T acc[N];
     load_vec<N, T>(x, k, acc);
     if (k < g.K) {
+      T tail[bp_tailn<N, BO>(3)];
+      bp_tail_load<N, BO, T>(fo, k, 3, tail);
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
         const int64_t j = g.nbr[n * Kp + k];
@@ -411,7 +412,7 @@ __global__ void __launch_bounds__(256) k_fac_f(Geo g, const BW* __restrict__ fw,
         load_vec<N, T>(x, j, xj);
 #pragma unroll
         for (int i = 0; i < N; ++i) xj[i] *= -(T)w;
-        block_mv<N, BO, T>(fo, k, n, 3, xj, acc);
+        block_mv_bp<N, BO, T>(fo, k, n, 3, tail, xj, acc);
       }
     }
     if (WT) {
@@ -467,13 +468,21 @@ __global__ void __launch_bounds__(256) k_fac_domega(Geo g, const BO* __restrict_
       load_vec<N, double>(beta, j, v);
 #pragma unroll
       for (int i = 0; i < N; ++i) u[i] = 0.0;
-      block_mv<N, BO, double>(fo, k, n, 3, v, u);
+      {
+        double tl[bp_tailn<N, BO>(3)];
+        bp_tail_load<N, BO, double>(fo, k, 3, tl);
+        block_mv_bp<N, BO, double>(fo, k, n, 3, tl, v, u);
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) s += ak[i] * u[i];
       load_vec<N, double>(y, j, v);
 #pragma unroll
       for (int i = 0; i < N; ++i) u[i] = 0.0;
-      block_mv<N, BO, double>(fo, k, n, 3, v, u);
+      {
+        double tl[bp_tailn<N, BO>(3)];
+        bp_tail_load<N, BO, double>(fo, k, 3, tl);
+        block_mv_bp<N, BO, double>(fo, k, n, 3, tl, v, u);
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) s += alk[i] * u[i];
     }
@@ -530,8 +539,13 @@ void launch_fac_setup(int N, const FacStore& fs, const Geo& g, const double* ref
   LDG_SWITCH_FAC(fs, {
     LDG_SWITCH_N(N, (k_fac_chol<NT, BW><<<nbk(g.Kpad * 16, 256), 256, 0, st>>>(
                         g, bj, w64, (BW*)fs.w, fs.ws, status, sym)));
-    LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO><<<nbk(g.Kpad, 4), 64, 0, st>>>(
-                        g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm, sym)));
+    if (sym) {
+      LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO, true><<<nbk(g.Kpad, 4), 64, 0, st>>>(
+                          g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm)));
+    } else {
+      LDG_SWITCH_N(N, (k_fac_offdiag<NT, BO, false><<<nbk(g.Kpad, 4), 64, 0, st>>>(
+                          g, refs, blocks, w64, tau, eta, (BO*)fs.o, lognorm)));
+    }
   })
 }
 
