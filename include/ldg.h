@@ -284,7 +284,9 @@ typedef enum {
   LDG_K_GNN = 7,       /* graph-network inference and training */
   LDG_K_FACTOR = 8,    /* factored learned preconditioner: setup and application */
   LDG_K_MF = 9,        /* matrix-free block terms of the divergence half */
-  LDG_K_COUNT = 10
+  LDG_K_RESIDUAL = 10, /* the operator applies of the FP64 residual of each refinement sweep
+                          (counted here, not under LDG_K_DIV / LDG_K_GRAD / LDG_K_MF) */
+  LDG_K_COUNT = 11
 } ldg_kernel_id;
 typedef struct {
   int64_t launches;

@@ -32,6 +32,7 @@ struct ldg_ctx {
   std::vector<void*> allocs;
   // geometry
   double *area2 = nullptr, *B = nullptr, *a1 = nullptr, *elen = nullptr, *nu = nullptr;
+  float *ainv32 = nullptr, *B32 = nullptr, *elen32 = nullptr, *nu32 = nullptr;
   int32_t *nbr = nullptr, *bidx = nullptr, *belem = nullptr, *bk = nullptr;
   int8_t *nbrn = nullptr, *kind = nullptr, *bn = nullptr;
   // reference data
@@ -99,6 +100,7 @@ struct ldg_ctx {
   std::vector<hipEvent_t> evpool;
   std::vector<Pending> pending;
   ldg_kernel_stat stats[LDG_K_COUNT] = {};
+  int stat_as = -1;   // >= 0: count the timed launches under this kernel id instead
   int64_t n_sd = 0, n_nd = 0;   // local edges that are not Neumann / not Dirichlet
   double inner_rho = 1.0;       // residual reduction the last inner solve reported
   // CG state kept across the refinement sweeps of one step: the last search
@@ -206,7 +208,8 @@ struct Timed {
   int id;
   double bytes, flops;
   hipEvent_t a = nullptr;
-  Timed(ldg_ctx* c_, int id_, double bytes_, double flops_) : c(c_), id(id_), bytes(bytes_), flops(flops_) {
+  Timed(ldg_ctx* c_, int id_, double bytes_, double flops_)
+      : c(c_), id(c_->stat_as >= 0 ? c_->stat_as : id_), bytes(bytes_), flops(flops_) {
     if (c->timing) {
       a = ev_get(c);
       if (a) (void)hipEventRecord(a, c->st);   // timing is best effort
@@ -256,7 +259,9 @@ struct Level {
 
 double div_bytes(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
-  return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + L.vbytes * 4.0 * c->N * c->K + 74.0 * c->K;
+  // geometry: kind, k+, n+, the normals and |T| (the normals in FP32 for the FP32 kernels)
+  const double geo = L.vbytes == 8.0 ? 74.0 : 50.0;
+  return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + L.vbytes * 4.0 * c->N * c->K + geo * c->K;
 }
 double div_flops(const ldg_ctx* c) {
   const double NN = (double)c->N * c->N;
@@ -283,7 +288,9 @@ double mf_flops(const ldg_ctx* c) {
   return 2.0 * N3 * (5.0 * c->K + 2.0 * c->Eint);
 }
 double grad_bytes(const ldg_ctx* c, const Level& L, bool with_j) {
-  return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + 130.0 * c->K;
+  // geometry: |T|, B, edge lengths, normals, kind, k+, n+ (FP32 copies for the FP32 kernel)
+  const double geo = L.vbytes == 8.0 ? 130.0 : 74.0;
+  return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + geo * c->K;
 }
 double grad_flops(const ldg_ctx* c) {
   const double NN = (double)c->N * c->N;
@@ -942,7 +949,9 @@ ldg_status solve_step(ldg_ctx* c, double tau, double bnorm, bool use_cg, ldg_ste
   if (fac_gmres) gnn_on = true;
   info->krylov = cg_mode ? LDG_KRYLOV_CG : LDG_KRYLOV_GMRES;
   while (true) {
+    c->stat_as = LDG_K_RESIDUAL;   // the sweep's FP64 residual, apart from the inner applies
     apply_op(c, L64, tau, c->X, true, c->tZ1, c->tZ2, c->w);
+    c->stat_as = -1;
     {
       Timed tm(c, LDG_K_KRYLOV, 24.0 * n, 2.0 * n);
       launch_axpby(VT_F64, n, 1.0, c->b3, -1.0, c->w, c->st);   // w = b3 - F(X)
@@ -1245,7 +1254,27 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
     for (int64_t k = 0; k < c->K; ++k) sa += 0.5 * hm.area2[k];
     c->meanA = sa / (double)c->K;
   }
-  c->geo = Geo{c->K, c->Kpad, c->area2, c->B, c->a1, c->elen, c->nu, c->nbr, c->nbrn, c->kind, c->bidx};
+  // FP32 copies of the geometry the FP32 apply kernels read (host vectors kept
+  // until the create's final sync, like the mesh arrays)
+  auto f32 = [](const std::vector<double>& v) {
+    std::vector<float> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+    return o;
+  };
+  std::vector<float> ainv_h(hm.area2.size());
+  for (size_t i = 0; i < ainv_h.size(); ++i)
+    ainv_h[i] = hm.area2[i] != 0.0 ? (float)(-1.0 / hm.area2[i]) : 0.0f;
+  const std::vector<float> B_h = f32(hm.B), elen_h = f32(hm.elen), nu_h = f32(hm.nu);
+  TRY(dalloc(c, &c->ainv32, Kp));
+  TRY(dalloc(c, &c->B32, 4 * Kp));
+  TRY(dalloc(c, &c->elen32, 3 * Kp));
+  TRY(dalloc(c, &c->nu32, 6 * Kp));
+  TRY(upload(c, c->ainv32, ainv_h));
+  TRY(upload(c, c->B32, B_h));
+  TRY(upload(c, c->elen32, elen_h));
+  TRY(upload(c, c->nu32, nu_h));
+  c->geo = Geo{c->K,    c->Kpad, c->area2, c->B,    c->a1,     c->elen, c->nu,     c->nbr,
+               c->nbrn, c->kind, c->bidx,  c->ainv32, c->B32, c->elen32, c->nu32};
   // reference data
   std::vector<double> refs(14 * NN);
   for (int f = 0; f < NN; ++f) {

@@ -112,7 +112,9 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   const int64_t Kp = g.Kpad;
   T c[N];
   load_vec<N, T>(C, k, c);
-  const T B11 = (T)g.B[k], B12 = (T)g.B[Kp + k], B21 = (T)g.B[2 * Kp + k], B22 = (T)g.B[3 * Kp + k];
+  // FP32: the geometry from its FP32 copies (the same values in half the bytes)
+  auto geoB = [&](int q) { if constexpr (SC) return g.B32[q * Kp + k]; else return (T)g.B[q * Kp + k]; };
+  const T B11 = geoB(0), B12 = geoB(1), B21 = geoB(2), B22 = geoB(3);
   {
     // -H^1 = -(B22 H1 - B21 H2), -H^2 = -(-B12 H1 + B11 H2)   (Sec. 3.6.2)
     T u1[N], u2[N];
@@ -129,8 +131,16 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   for (int n = 0; n < 3; ++n) {
     const int kind = g.kind[n * Kp + k];
     if (kind == LDG_EDGE_DIRICHLET) continue;
-    const T L = (T)g.elen[n * Kp + k];
-    const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+    T L, nu1, nu2;
+    if constexpr (SC) {
+      L = g.elen32[n * Kp + k];
+      nu1 = g.nu32[(2 * n) * Kp + k];
+      nu2 = g.nu32[(2 * n + 1) * Kp + k];
+    } else {
+      L = (T)g.elen[n * Kp + k];
+      nu1 = (T)g.nu[(2 * n) * Kp + k];
+      nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+    }
     const T cq = (kind == LDG_EDGE_INTERIOR ? (T)0.5 : (T)1) * L;
     T s[N];
 #pragma unroll
@@ -164,7 +174,9 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
       a2[i] += J2[vidx(k, i, N)];
     }
   }
-  const T inv = (T)(-1.0 / g.area2[k]);
+  T inv;
+  if constexpr (SC) inv = g.ainv32[k];
+  else inv = (T)(-1.0 / g.area2[k]);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     a1[i] *= inv;
@@ -216,7 +228,14 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
     for (int n = 0; n < 3; ++n) {
       const int64_t kp = g.nbr[n * Kp + k];
       if (kp < 0) continue;
-      const T nu1 = (T)g.nu[(2 * n) * Kp + k], nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+      T nu1, nu2;
+      if constexpr (sizeof(T) == 4) {   // the FP32 copies: the same values, half the bytes
+        nu1 = g.nu32[(2 * n) * Kp + k];
+        nu2 = g.nu32[(2 * n + 1) * Kp + k];
+      } else {
+        nu1 = (T)g.nu[(2 * n) * Kp + k];
+        nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+      }
 #pragma unroll
       for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
       if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);

@@ -40,6 +40,12 @@ struct Geo {
   const int8_t* nbrn;    // [3][Kpad]   n+
   const int8_t* kind;    // [3][Kpad]   ldg_edge_kind
   const int32_t* bidx;   // [3][Kpad]   boundary edge index or -1
+  // FP32 copies for the FP32 apply kernels: the values those kernels would
+  // round the FP64 ones to (so the results are the same bits), in half the bytes
+  const float* ainv32;   // [Kpad]      -1 / (2|T_k|)
+  const float* B32;      // [4][Kpad]
+  const float* elen32;   // [3][Kpad]
+  const float* nu32;     // [3][2][Kpad]
 };
 
 // ---- reference data computed on the host --------------------------------

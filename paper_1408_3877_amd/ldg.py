@@ -42,7 +42,7 @@ class KernelStat(C.Structure):
 
 
 KERNELS = ["div", "grad", "bj_apply", "assemble", "bj_setup", "krylov", "project", "gnn", "factor",
-           "mf"]
+           "mf", "residual"]
 
 
 class StepInfo(C.Structure):

@@ -319,7 +319,13 @@ def train_head_cg(solver, w, cases, dt, omegas, iters, c, a, seed, from_start=Fa
         solver.gnn_set_params(with_head(w, h))
         om = solver.gnn_factor_omega().double().cpu().numpy()
         sens[i] = np.sqrt(np.mean((om - om0)[inner] ** 2)) / eps
-    scale = 1.0 / (np.maximum(sens, 1e-6 * sens.max()) * np.sqrt(HEAD))
+    # a parameter that does not move omega on the training systems (an edge
+    # feature that never occurs there, such as an (n, n+) pair the training
+    # meshes lack) stays where it is: the objective cannot see it, and an
+    # unconstrained value would set omega arbitrarily on meshes that have it
+    seen = sens > 1e-9 * sens.max()
+    scale = np.where(seen, 1.0 / (np.maximum(sens, 1e-300) * np.sqrt(HEAD)), 0.0)
+    hist["frozen"] = np.flatnonzero(~seen).tolist()
     hist["sensitivity"] = sens.tolist()
     u = np.zeros(HEAD)
     for k in range(iters):

@@ -61,3 +61,71 @@ def test_constant_head_gives_the_requested_omega():
     w2 = learned.with_head(w, h)
     assert np.array_equal(w2[:-learned.HEAD], w[:-learned.HEAD])
     assert np.allclose(w2[-learned.HEAD:], h)
+
+
+def test_head_fit_freezes_parameters_that_do_not_move_omega(monkeypatch):
+    # SPSA on the CG objective (stubbed here): head parameters whose change does
+    # not move omega on the training systems (edge features absent there) stay
+    # at their starting values; the others move
+    from paper_1408_3877_amd import learned
+    H = learned.HEAD
+    unseen = [67, 71, 75]
+
+    class Arr:
+        def __init__(self, a):
+            self.a = a
+
+        def double(self):
+            return self
+
+        def cpu(self):
+            return self
+
+        def numpy(self):
+            return self.a
+
+    class FakeSolver:
+        def project(self, d):
+            return d
+
+        def gnn_set_context(self, D, dt):
+            pass
+
+        def gnn_set_params(self, w):
+            self.h = np.asarray(w[-H:], dtype=np.float64)
+
+        def gnn_factor_omega(self):
+            h = self.h.copy()
+            h[unseen] = 0.0                   # these features are zero on every edge
+            x = np.linspace(-1.0, 1.0, 40)
+            return Arr(0.95 / (1.0 + np.exp(-(h[:-1].sum() * 0.01 * x + h[-1]))))
+
+    def fake_objective(solver, w, cases, dt):
+        solver.gnn_set_params(w)
+        om = solver.gnn_factor_omega().numpy()
+        return float(np.mean((om - 0.7) ** 2))
+
+    monkeypatch.setattr(learned, "cg_objective", fake_objective)
+    w0 = learned.factor_init(6, 3)
+    cases = [(None, {"d": None})]
+    w, best, hist = learned.train_head_cg(FakeSolver(), w0, cases, 1e-3, [0.6], 30, 0.03, 0.5, 11,
+                                         from_start=True)
+    assert hist["frozen"] == unseen
+    assert np.array_equal(w[-H:][unseen], w0[-H:][unseen])
+    assert not np.array_equal(w[-H:], w0[-H:])
+    assert best <= hist["start"]
+
+
+def test_shipped_heads_stay_near_their_initialisation():
+    # the shipped weights keep the seeded trunk and move the head by less than
+    # two units per parameter (no parameter drifted where the fit could not see it)
+    import os
+
+    from paper_1408_3877_amd import learned
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for p, N in ((3, 10), (4, 15)):
+        w = np.load(os.path.join(root, "paper_1408_3877_amd", "weights", "factor_p%d.npy" % p))
+        init = learned.factor_init(N, 7)
+        assert w.shape == init.shape
+        assert np.array_equal(w[:-learned.HEAD], init[:-learned.HEAD])
+        assert np.abs(w[-learned.HEAD:].astype(np.float64) - init[-learned.HEAD:]).max() < 2.0
