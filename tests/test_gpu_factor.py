@@ -344,3 +344,54 @@ def test_factor_blocks_at_degree_three_vertices():
         assert info["rel_residual"] <= 1e-13 and info["krylov"] == 2
         assert info["learned_iters"] == info["iters"] > 0 and info["fallbacks"] == 0
         assert rel_l2(pr.grid.areaT, to_np(sl.get_solution()[0]), C) < 1e-10
+
+
+@pytest.mark.parametrize("p,precision", [(3, 0), (4, 2)])
+def test_shipped_weights_on_a_delaunay_mesh(p, precision):
+    # An unstructured mesh with its local numbering rotated at random has every
+    # local edge pair (n, n+), including n = n+,
+    # which the training meshes lack: the shipped networks keep the initial
+    # weights on those features, give omega inside (0, 0.95) on every interior
+    # edge, and their preconditioner (of the symmetric part: d varies inside the
+    # triangles) takes GMRES steps to the oracle's solution in fewer iterations
+    # than block-Jacobi
+    import os
+
+    from inputs.meshes import SOUTH, delaunay_square, edge_kinds, rotate_local_numbering
+    from paper_1408_3877_amd import Solver
+    cV, V0T = delaunay_square(10, 761)
+    V0T, kind = rotate_local_numbering(V0T, edge_kinds(cV, V0T, (SOUTH,)), 762)
+    pr = Problem(cV, V0T, kind, p)
+    kp = pr.grid.kp
+    pairs = set()
+    for k in range(pr.grid.numT):
+        for n in range(3):
+            j = kp[k, n]
+            if j >= 0:
+                pairs.add((n, int(np.flatnonzero(kp[j] == k)[0])))
+    assert {(0, 0), (1, 1), (2, 2)} <= pairs
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    th = np.load(os.path.join(root, "paper_1408_3877_amd", "weights", "factor_p%d.npy" % p))
+    w = Workload(SMOOTH1)
+    dt = 0.01
+    runs = {}
+    for name, pc in (("bj", 0), ("learned", 1)):
+        s = Solver(cV, V0T, kind, p, rtol=1e-12, max_iters=20000, precond=pc, precision=precision,
+                   restart=30)
+        if pc:
+            s.gnn_set_mode("factor")
+            s.gnn_factor_storage("fp8")
+            s.gnn_set_params(th)
+        s.set_initial_samples(s.sample_workload(SMOOTH1, 0.0, want=("c0",))["c0"])
+        runs[name] = _steps(s, w, pr, pr.initial(w), dt, 2)
+        for info, err in runs[name]:
+            print("[delaunay-learned] p=%d %s %s err=%.2e" % (p, name, info, err), flush=True)
+            assert info["krylov"] == 1 and info["rel_residual"] <= 1e-12
+            assert err < 1e-9
+        if pc:
+            om = to_np(s.gnn_factor_omega())
+            inner = kp >= 0
+            assert np.all(om[inner] > 0.0) and np.all(om[inner] < 0.95)
+    for (ib, _), (il, _) in zip(runs["bj"], runs["learned"]):
+        assert il["fallbacks"] == 0 and il["learned_iters"] == il["iters"] > 0
+        assert il["iters"] < ib["iters"], (il["iters"], ib["iters"])
