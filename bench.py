@@ -181,6 +181,49 @@ def cpu_model():
     return "unknown"
 
 
+def cpu_extrapolated(cfg, K_target, iters_target, n=48):
+    """The oracle's iterative step (block-Jacobi CG on its explicitly formed
+    eliminated matrix, the solver the FP64 block-Jacobi GPU baseline runs) on
+    an n x n-cell sample of the same family, with one thread, extrapolated to
+    the benchmarked mesh.  The step runs twice, to relative residuals 1e-4 and
+    1e-10: the difference gives the cost of one CG iteration, the rest is the
+    per-step work (assembly of the blocks and the eliminated matrix, the
+    block-Jacobi inverses, the recovery of Z).  Both grow linearly with K
+    (sparse products, blockwise work); the iteration count is the GPU
+    baseline's on the benchmarked mesh.  A model, not a measurement of the
+    whole mesh (one such step would take hours), and labelled as such."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ldg import Problem, step_schur_cg
+    coordV, V0T, kind = square_mesh(n, seed=cfg["jitter"], neumann_sides=cfg.get("neumann", ()))
+    w = Workload(cfg["kind"], n_cells=n,
+                 blocks=lognormal_blocks(n, cfg["field_seed"], cfg["sigma"], block=8), block=8)
+    runs = {}
+    with threadpool_limits(1):
+        pr = Problem(coordV, V0T, kind, cfg["p"])
+        C = pr.initial(w)
+        data = pr.data(w, cfg["dt"])
+        for rtol in (1e-4, 1e-10):
+            t0 = time.perf_counter()
+            _, _, _, info = step_schur_cg(pr, C, cfg["dt"], cfg["dt"], w, rtol=rtol, data=data)
+            runs[rtol] = (time.perf_counter() - t0, info["iters"])
+    (t4, i4), (t8, i8) = runs[1e-4], runs[1e-10]
+    t_iter = max(t8 - t4, 0.0) / max(i8 - i4, 1)
+    t_fixed = max(t8 - i8 * t_iter, 0.0)
+    K_s = pr.grid.numT
+    t_target = (t_fixed + t_iter * iters_target) * K_target / K_s
+    dof = 3 * K_target * pr.N
+    return {"value": dof / t_target, "unit": "DOF*steps/s", "cores": 1,
+            "kind": "oracle, extrapolated per-step",
+            "seconds_per_step": t_target,
+            "sample": "%dx%d cells (K=%d), one step by the oracle's block-Jacobi CG: %.2f s for %d "
+                      "iterations to 1e-4, %.2f s for %d to 1e-10, i.e. %.4f s per iteration and "
+                      "%.2f s per-step work; scaled by K=%d/%d with %d iterations (the FP64 "
+                      "block-Jacobi GPU baseline's on this mesh)" % (
+                          n, n, K_s, t4, i4, t8, i8, t_iter, t_fixed, K_target, K_s,
+                          round(iters_target))}
+
+
 def cpu_baseline(cfg):
     """The oracle (direct sparse solve of the full 3KN system, Sec. 2.5) on a
     bounded sample of the same workload family: 24 x 24 cells (16 x 16 for the
@@ -391,6 +434,10 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(cfg)
+        if base is not None and cfg["kind"] in (LOGNORMAL, LOGNORMAL_T) and not cfg.get("stationary"):
+            log("[bench] cpu baseline, extrapolated (oracle block-Jacobi CG) ...")
+            res["cpu_baseline"]["extrapolated"] = cpu_extrapolated(
+                cfg, s.K, res["baseline_fp64_bj"]["iters_per_step"])
     print(json.dumps(res), flush=True)
 
 
