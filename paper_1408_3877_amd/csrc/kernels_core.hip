@@ -239,13 +239,19 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
 #pragma unroll
     for (int c = 0; c < N; ++c) a[c] = (c == i ? alpha * area2 : 0.0) + tau * acc[c];
   }
-  // Gauss-Jordan with partial pivoting within the LPT-lane group.  Every lane
-  // of the wave runs every shuffle; rows i >= N never become pivots.
+  // Gauss-Jordan with partial pivoting within the LPT-lane group, without
+  // moving rows: column c takes as pivot the unused row (lane) with the largest
+  // |a[c]|, every other row eliminates column c with it, and that lane records
+  // c.  The left side ends as a permutation of the identity, so the lane that
+  // pivoted column c holds row c of the inverse.  Every lane of the wave runs
+  // every shuffle; rows i >= N never become pivots.
   bool bad = false;
+  bool used = i >= N;
+  int col = 0;   // the column this lane pivoted
 #pragma unroll
   for (int c = 0; c < N; ++c) {
-    // pivot: largest |a[c]| over rows c..N-1 (the lowest row among equals)
-    double best = (i >= c && i < N) ? fabs(a[c]) : -1.0;
+    // pivot: largest |a[c]| over the unused rows (the lowest lane among equals)
+    double best = used ? -1.0 : fabs(a[c]);
     int r = i;
 #pragma unroll
     for (int off = LPT / 2; off > 0; off >>= 1) {
@@ -256,23 +262,15 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
         r = orow;
       }
     }
-    // exchange rows c and r (a no-op when r == c)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const double ac = __shfl(a[j], c, LPT), ar = __shfl(a[j], r, LPT);
-      const double bc = __shfl(b[j], c, LPT), br = __shfl(b[j], r, LPT);
-      if (i == c) { a[j] = ar; b[j] = br; }
-      else if (i == r) { a[j] = ac; b[j] = bc; }
-    }
-    const double piv = __shfl(a[c], c, LPT);
+    const double piv = __shfl(a[c], r, LPT);
     bad |= !(fabs(piv) > 0.0);
     const double ip = 1.0 / piv;
     const double fct = a[c];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const double pa = __shfl(a[j], c, LPT) * ip;
-      const double pb = __shfl(b[j], c, LPT) * ip;
-      if (i == c) {
+      const double pa = __shfl(a[j], r, LPT) * ip;
+      const double pb = __shfl(b[j], r, LPT) * ip;
+      if (i == r) {
         a[j] = pa;
         b[j] = pb;
       } else {
@@ -280,12 +278,17 @@ __global__ void __launch_bounds__(256) k_bj_setup(Geo g, const double* __restric
         b[j] -= fct * pb;
       }
     }
+    if (i == r) {
+      used = true;
+      col = c;
+    }
   }
   if (row_ok && bad) atomicOr(status, 1);
   if (k < g.Kpad && i < N) {
+    // row col of the inverse (each row once: the pivots are a permutation)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const int f = i * N + j;
+      const int f = col * N + j;
       bj[pidx(k, 0, f >> 1, 1, NP) + (f & 1)] = elem_ok ? b[j] : 0.0;
     }
     if (i == N - 1 && (NN & 1)) bj[pidx(k, 0, NP - 1, 1, NP) + 1] = 0.0;

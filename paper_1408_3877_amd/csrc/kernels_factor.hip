@@ -212,6 +212,10 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
     const bool act = jn > k;
     const int64_t j = act ? jn : kk;
     const int npl = act ? g.nbrn[n * Kp + kk] : 0;
+    // each interior edge once, by the triangle with the lower index: the other
+    // side and boundary edges skip the arithmetic (every lane still reaches the
+    // barriers and the shuffles)
+    const bool work = row && act;
     const double nu1 = g.nu[(2 * n) * Kp + kk], nu2 = g.nu[(2 * n + 1) * Kp + kk];
     // T1 <- sum_m nu^m_kn A^m_jj;  T2 <- sum_m nu^m_kn B^m_kk (row ii per lane)
     {
@@ -226,7 +230,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
         cq[q] = w * (nu1 * g.nu[(2 * q) * Kp + j] + nu2 * g.nu[(2 * q + 1) * Kp + j]) *
                 g.elen[q * Kp + j];
       }
-      if (row) {
+      if (work) {
 #pragma unroll 1
         for (int c = 0; c < N; ++c) {
           const int e = ii * N + c;
@@ -238,7 +242,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
     }
     __syncthreads();
     // T3 <- S_kj (row ii per lane)
-    if (row) {
+    if (work) {
       const double* So = sm + ref_so(n, npl) * NN;
       const double s1 = 0.5 * g.elen[n * Kp + kk] / area2k;
       const double s2 = 1.0 / g.area2[j];
@@ -268,7 +272,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
           cq[q] = -w * (nu1 * g.nu[(2 * q) * Kp + kk] + nu2 * g.nu[(2 * q + 1) * Kp + kk]) *
                   g.elen[q * Kp + kk];
         }
-        if (row) {
+        if (work) {
 #pragma unroll 1
           for (int c = 0; c < N; ++c) {
             const int e = ii * N + c;
@@ -279,7 +283,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
         }
       }
       __syncthreads();
-      if (row) {
+      if (work) {
         const double* So = sm + ref_so(npl, n) * NN;
         const double s1 = 0.5 * g.elen[n * Kp + kk] / g.area2[j];
         const double s2 = 1.0 / area2k;
@@ -294,19 +298,19 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
         }
       }
       __syncthreads();
-      if (row) {
+      if (work) {
 #pragma unroll 1
         for (int c = 0; c < N; ++c) T3[ii * N + c] = 0.5 * (T3[ii * N + c] + T4[c * N + ii]);
       }
       __syncthreads();
     }
     // T2 <- W_j;  T1 <- T = S_kj W_j^T
-    if (row) {
+    if (work) {
 #pragma unroll 1
       for (int c = 0; c < N; ++c) T2[ii * N + c] = get64(w64, j, 0, 1, ii * N + c, NP);
     }
     __syncthreads();
-    if (row) {
+    if (work) {
 #pragma unroll 1
       for (int c = 0; c < N; ++c) {
         double acc = 0.0;
@@ -318,7 +322,7 @@ __global__ void __launch_bounds__(64) k_fac_offdiag(Geo g, const double* __restr
     __syncthreads();
     // O = W_k T, row ii, straight to both sides; ||O||_F over the 16 lanes
     double nrm = 0.0;
-    if (row) {
+    if (work) {
 #pragma unroll 1
       for (int c = 0; c < N; ++c) {
         double acc = 0.0;
