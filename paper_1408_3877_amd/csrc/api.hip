@@ -442,11 +442,12 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     kaxpby(c, L, 1.0, L.z, 0.0, L.p);
   }
   // The step lengths and the coefficients of the directions stay on the
-  // device (launch_cg_alpha / launch_cg_beta in stream order), and the
-  // residual norm is read back only at checks: the next check is placed at
-  // half the iterations the rate so far needs to reach the tolerance (at most
-  // 16 ahead), so the loop syncs a few dozen times per solve instead of three
-  // times per iteration and overshoots the tolerance by an iteration or so.
+  // device (set by the epilogues of the reductions of <p, A p> and <r, z>,
+  // in stream order), and the residual norm is read back only at checks: the
+  // next check is placed at half the iterations the rate so far needs to
+  // reach the tolerance (at most 16 ahead), so the loop syncs a few dozen
+  // times per solve instead of three times per iteration and overshoots the
+  // tolerance by an iteration or so.
   if (!(rz > 0.0) || !std::isfinite(rz)) {   // the preconditioner is not positive on r
     *not_spd = true;
     *iters = 0;
@@ -457,17 +458,26 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
   int it = 0, next_check = 1;
   bool converged = false;
   const bool every = c->col_n > 0;   // iterate snapshots: check every iteration
+  // the reductions of <p, A p> and <r, z> also set the step length and the
+  // direction coefficient (Reducer::cg_mode), in the same launches
+  struct CgModeReset {
+    Reducer& r;
+    ~CgModeReset() { r.cg = nullptr; r.cg_mode = CG_NONE; }
+  } reset{c->red};
+  c->red.cg = c->cgs;
   while (true) {
-    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>
-    launch_cg_alpha(c->red.result, c->cgs, c->st);
+    c->red.cg_mode = CG_ALPHA;
+    apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>, step
+    c->red.cg_mode = CG_NONE;
     {
       Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
       launch_cg_update(L.vt, c->red2, c->nvec, 0.0, L.p, L.q, L.d, L.r, c->st,
                        c->cgs + CGS_ALPHA);   // x += a p, r -= a q, <r, r>
     }
-    if (factor) fac_apply(c, L, L.r, L.z);
+    c->red.cg_mode = CG_BETA;
+    if (factor) fac_apply(c, L, L.r, L.z);   // z = P r, <r, z>, direction coefficient
     else bj_apply(c, L, L.r, L.z, true);
-    launch_cg_beta(c->red.result, c->cgs, c->st);
+    c->red.cg_mode = CG_NONE;
     ++it;
     TRY(snapshot(c, L, it));
     if (every || it >= next_check || it >= maxit) {

@@ -162,11 +162,18 @@ struct Reducer {
   double* result = nullptr;     // device
   int nblk = 0;
   int maxv = 0;
+  // the single-result reductions of the applies (reduce_partials) can derive
+  // a CG scalar from their result in the same launch: cg_mode CG_ALPHA or
+  // CG_BETA on the scalars cg (CGS_*)
+  double* cg = nullptr;
+  int cg_mode = 0;
 };
 int krylov_nblk(int64_t n);
 // blocks of the Gram-Schmidt kernels (launch_dots, launch_update) for vectors of length n
 int gs_nblk(int64_t n);
-void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st);
+enum { CG_NONE = 0, CG_ALPHA = 1, CG_BETA = 2 };
+void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st,
+                     double* cg = nullptr, int cg_mode = CG_NONE);
 // result[j] = <V_j, w> for j < nv, result[nv] = <w, w>
 void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
                  const void* w, hipStream_t st);
@@ -186,11 +193,10 @@ void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void*
 enum { CGS_RZ = 0, CGS_NUM = 1, CGS_PQ = 2, CGS_ALPHA = 3, CGS_BETA = 4, CGS_FLAG = 5, CGS_ITER = 6,
        CGS_N = 8 };
 void launch_cg_start(double* s, double rz, double num, hipStream_t st);
-// s[ALPHA] = s[NUM] / pq[0] and s[ITER] += 1 (0 and s[FLAG] = 1 on a non-positive
-// curvature; an update with step 0 leaves x and r alone)
-void launch_cg_alpha(const double* pq, double* s, hipStream_t st);
-// s[BETA] = rzn[0] / s[RZ], then s[RZ] = s[NUM] = rzn[0] (flag on rzn <= 0)
-void launch_cg_beta(const double* rzn, double* s, hipStream_t st);
+// (the reductions' CG_ALPHA epilogue: s[ALPHA] = s[NUM] / <p, A p> and
+// s[ITER] += 1, or 0 and s[FLAG] = 1 on a non-positive curvature, an update
+// with step 0 leaving x and r alone; CG_BETA: s[BETA] = <r, z> / s[RZ], then
+// s[RZ] = s[NUM] = <r, z>, the flag on <r, z> <= 0)
 // y = x + s[BETA] y, the coefficient read on the device
 void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void* y, hipStream_t st);
 // out = a * in across precisions

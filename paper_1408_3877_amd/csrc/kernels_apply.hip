@@ -419,7 +419,7 @@ void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const v
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
                         (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   }
-  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+  if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
 }
 
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
@@ -436,7 +436,7 @@ void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const 
     LDG_SWITCH_N_P6(N, (k_bj_apply<NT, float, bf16><<<nb, 256, 0, st>>>(
                         g, (const bf16*)bj, (const float*)r, (float*)z, parts)));
   }
-  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+  if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
 }
 
 void launch_convert_blocks(int bt, int64_t Kpad, int N, int ns, const double* src, void* dst,

@@ -577,7 +577,7 @@ void launch_fac_apply(int N, const FacStore& fs, int vt, const Geo& g, const flo
                           g, fw, fs.ws, fo, om, (const T*)a, (T*)z, (const T*)r, parts)));
     }
   })
-  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+  if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
 }
 
 void launch_fac_w(int N, const FacStore& fs, const Geo& g, const double* x, double* y,

@@ -143,15 +143,55 @@ __global__ void __launch_bounds__(KB) k_update(int64_t n, int nv, const T* __res
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// one block per output: result[j] = sum_b partials[j * nblk + b], fixed order
-__global__ void __launch_bounds__(KB) k_reduce(int nblk, const double* __restrict__ partials,
-                                               double* __restrict__ result) {
-  __shared__ double red[KB / 64];
+// CG scalars from a reduced dot product (one thread): the step length from
+// <p, A p> (CG_ALPHA), or the direction coefficient from the new <r, z>
+// (CG_BETA): a non-positive curvature or <r, z> sets the flag and a step of 0,
+// which every later update honours
+__device__ inline void cg_alpha(double v, double* __restrict__ s) {
+  s[CGS_PQ] = v;
+  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX) || !(s[CGS_RZ] > 0.0)) {
+    s[CGS_ALPHA] = 0.0;
+    s[CGS_FLAG] = 1.0;
+  } else {
+    s[CGS_ALPHA] = s[CGS_NUM] / v;
+    s[CGS_ITER] += 1.0;
+  }
+}
+
+__device__ inline void cg_beta(double v, double* __restrict__ s) {
+  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX)) {
+    s[CGS_BETA] = 0.0;
+    s[CGS_FLAG] = 1.0;
+    return;
+  }
+  s[CGS_BETA] = v / s[CGS_RZ];
+  s[CGS_RZ] = v;
+  s[CGS_NUM] = v;
+}
+
+// one block per output: result[j] = sum_b partials[j * nblk + b], fixed order;
+// RB threads (the partials of one output are few thousand: a wide block keeps
+// each thread's share short).  cg_mode (single output): the CG scalar that
+// follows from the result, in the same launch.
+constexpr int RB = 1024;
+__global__ void __launch_bounds__(RB) k_reduce(int nblk, const double* __restrict__ partials,
+                                               double* __restrict__ result,
+                                               double* __restrict__ cg, int cg_mode) {
+  __shared__ double red[RB / 64];
   const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += KB) s += partials[(int64_t)j * nblk + b];
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) result[j] = s;
+  for (int b = threadIdx.x; b < nblk; b += RB) s += partials[(int64_t)j * nblk + b];
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < RB / 64; ++w) t += red[w];
+    result[j] = t;
+    if (cg_mode == CG_ALPHA) cg_alpha(t, cg);
+    else if (cg_mode == CG_BETA) cg_beta(t, cg);
+  }
 }
 
 template <class T>
@@ -201,29 +241,7 @@ __global__ void k_cg_start(double* __restrict__ s, double rz, double num) {
   s[CGS_ITER] = 0.0;
 }
 
-__global__ void k_cg_alpha(const double* __restrict__ pq, double* __restrict__ s) {
-  const double v = pq[0];
-  s[CGS_PQ] = v;
-  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX) || !(s[CGS_RZ] > 0.0)) {
-    s[CGS_ALPHA] = 0.0;
-    s[CGS_FLAG] = 1.0;
-  } else {
-    s[CGS_ALPHA] = s[CGS_NUM] / v;
-    s[CGS_ITER] += 1.0;
-  }
-}
 
-__global__ void k_cg_beta(const double* __restrict__ rzn, double* __restrict__ s) {
-  const double v = rzn[0];
-  if (s[CGS_FLAG] != 0.0 || !(v > 0.0) || !(v <= DBL_MAX)) {
-    s[CGS_BETA] = 0.0;
-    s[CGS_FLAG] = 1.0;
-    return;
-  }
-  s[CGS_BETA] = v / s[CGS_RZ];
-  s[CGS_RZ] = v;
-  s[CGS_NUM] = v;
-}
 
 // CG: x += a p, r -= a q, partial sums of the new <r, r>; with adev the step
 // length is read from the device (CG scalars kept on the device)
@@ -312,8 +330,9 @@ __global__ void k_zrows(Geo g, int N, const double* __restrict__ Za, const doubl
   if ((vt) == VT_F64) { using T = double; CALL; } \
   else { using T = float; CALL; }
 
-void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st) {
-  k_reduce<<<1, KB, 0, st>>>(nblk, partials, result);
+void reduce_partials(int nblk, const double* partials, double* result, hipStream_t st,
+                     double* cg, int cg_mode) {
+  k_reduce<<<1, RB, 0, st>>>(nblk, partials, result, cg, cg_mode);
 }
 
 int gs_nblk(int64_t n) {
@@ -335,7 +354,7 @@ void launch_dots(int vt, const Reducer& r, int64_t n, int nv, const void* V, int
   const dim3 grid(nb, nv > 0 ? (nv + GS_JB - 1) / GS_JB : 1);   // nv = 0: <w, w> only
   LDG_VT(vt, LDG_GS_IT(n, (k_dots<T, IT><<<grid, KB, 0, st>>>(n, nv, (const T*)V, ldv,
                                                                 (const T*)w, r.partials, nb))));
-  k_reduce<<<nv + 1, KB, 0, st>>>(nb, r.partials, r.result);
+  k_reduce<<<nv + 1, RB, 0, st>>>(nb, r.partials, r.result, nullptr, CG_NONE);
 }
 
 void launch_update(int vt, const Reducer& r, int64_t n, int nv, const void* V, int64_t ldv,
@@ -343,7 +362,7 @@ void launch_update(int vt, const Reducer& r, int64_t n, int nv, const void* V, i
   const int nb = gs_nblk(n);
   LDG_VT(vt, LDG_GS_IT(n, (k_update<T, IT><<<nb, KB, 0, st>>>(n, nv, (const T*)V, ldv, h, (T*)w,
                                                                 r.partials))));
-  k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+  k_reduce<<<1, RB, 0, st>>>(nb, r.partials, r.result, nullptr, CG_NONE);
 }
 
 void launch_lincomb(int vt, int64_t n, int nv, const void* V, int64_t ldv, const double* y,
@@ -360,7 +379,7 @@ void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void*
   const int nb = krylov_nblk(n);
   LDG_VT(vt, (k_cg_update<T><<<nb, KB, 0, st>>>(n, a, adev, (const T*)p, (const T*)q, (T*)x,
                                                 (T*)rv, r.partials)));
-  k_reduce<<<1, KB, 0, st>>>(nb, r.partials, r.result);
+  k_reduce<<<1, RB, 0, st>>>(nb, r.partials, r.result, nullptr, CG_NONE);
 }
 
 void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void* y,
@@ -371,12 +390,7 @@ void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void*
 void launch_cg_start(double* s, double rz, double num, hipStream_t st) {
   k_cg_start<<<1, 1, 0, st>>>(s, rz, num);
 }
-void launch_cg_alpha(const double* pq, double* s, hipStream_t st) {
-  k_cg_alpha<<<1, 1, 0, st>>>(pq, s);
-}
-void launch_cg_beta(const double* rzn, double* s, hipStream_t st) {
-  k_cg_beta<<<1, 1, 0, st>>>(rzn, s);
-}
+
 
 void launch_cast(int vt_in, int vt_out, int64_t n, double a, const void* in, void* out,
                  hipStream_t st) {
@@ -397,7 +411,7 @@ void launch_axpy_into64(int vt, int64_t n, double a, const void* x, double* y, h
 void launch_mode_norms(int N, const Geo& g, const double* D, const Reducer& red, hipStream_t st) {
   const int nb = red.nblk < 1024 ? red.nblk : 1024;
   k_mode_norms<<<nb, KB, 0, st>>>(g.Kpad, N, D, red.partials, nb);
-  k_reduce<<<2, KB, 0, st>>>(nb, red.partials, red.result);
+  k_reduce<<<2, RB, 0, st>>>(nb, red.partials, red.result, nullptr, CG_NONE);
 }
 
 void launch_rhs(const Geo& g, int N, const double* C, const double* KDN, const double* F,

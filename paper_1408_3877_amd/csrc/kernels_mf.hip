@@ -195,7 +195,7 @@ void launch_mf_blocks(int N, int vt, const Geo& g, const double* D, const void* 
                         g, D, (const float*)table, (const float*)C, (const float*)Z1,
                         (const float*)Z2, tau, (float*)y, parts)));
   }
-  if (red) reduce_partials((int)nb, red->partials, red->result, st);
+  if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
 }
 
 }  // namespace ldg
