@@ -469,10 +469,11 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     c->red.cg_mode = CG_ALPHA;
     apply_op(c, L, tau, L.p, false, L.tz1, L.tz2, L.q, true);   // q = A p, <p, q>, step
     c->red.cg_mode = CG_NONE;
+    const bool check = every || it + 1 >= next_check || it + 1 >= maxit;
     {
       Timed tm(c, LDG_K_KRYLOV, 6.0 * L.vbytes * c->nvec, 6.0 * c->nvec);
       launch_cg_update(L.vt, c->red2, c->nvec, 0.0, L.p, L.q, L.d, L.r, c->st,
-                       c->cgs + CGS_ALPHA);   // x += a p, r -= a q, <r, r>
+                       c->cgs + CGS_ALPHA, check);   // x += a p, r -= a q (<r, r> at checks)
     }
     c->red.cg_mode = CG_BETA;
     if (factor) fac_apply(c, L, L.r, L.z);   // z = P r, <r, z>, direction coefficient
@@ -480,7 +481,7 @@ ldg_status inner_cg(ldg_ctx* c, const Level& L, double tau, double tol_abs, int 
     c->red.cg_mode = CG_NONE;
     ++it;
     TRY(snapshot(c, L, it));
-    if (every || it >= next_check || it >= maxit) {
+    if (check) {
       HIPCHK(c, hipMemcpyAsync(hb, c->red2.result, sizeof(double), hipMemcpyDeviceToHost, c->st));
       HIPCHK(c, hipMemcpyAsync(hb + 1, c->cgs, CGS_N * sizeof(double), hipMemcpyDeviceToHost,
                                c->st));

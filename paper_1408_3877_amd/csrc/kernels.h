@@ -185,9 +185,11 @@ void launch_lincomb(int vt, int64_t n, int nv, const void* V, int64_t ldv, const
                     void* u, hipStream_t st);
 // y = a x + b y
 void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y, hipStream_t st);
-// CG: x += a p, r -= a q; result[0] = <r, r> afterwards (a = *adev when adev != NULL)
+// CG: x += a p, r -= a q; result[0] = <r, r> afterwards (a = *adev when adev != NULL;
+// reduce = false leaves the partial sums unreduced)
 void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
-                      void* x, void* rv, hipStream_t st, const double* adev = nullptr);
+                      void* x, void* rv, hipStream_t st, const double* adev = nullptr,
+                      bool reduce = true);
 // CG scalars kept on the device: s[CGS_*], set by one-thread kernels in stream
 // order, so the host reads them only when it checks convergence
 enum { CGS_RZ = 0, CGS_NUM = 1, CGS_PQ = 2, CGS_ALPHA = 3, CGS_BETA = 4, CGS_FLAG = 5, CGS_ITER = 6,

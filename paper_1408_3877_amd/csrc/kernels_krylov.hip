@@ -375,11 +375,11 @@ void launch_axpby(int vt, int64_t n, double a, const void* x, double b, void* y,
 }
 
 void launch_cg_update(int vt, const Reducer& r, int64_t n, double a, const void* p, const void* q,
-                      void* x, void* rv, hipStream_t st, const double* adev) {
+                      void* x, void* rv, hipStream_t st, const double* adev, bool reduce) {
   const int nb = krylov_nblk(n);
   LDG_VT(vt, (k_cg_update<T><<<nb, KB, 0, st>>>(n, a, adev, (const T*)p, (const T*)q, (T*)x,
                                                 (T*)rv, r.partials)));
-  k_reduce<<<1, RB, 0, st>>>(nb, r.partials, r.result, nullptr, CG_NONE);
+  if (reduce) k_reduce<<<1, RB, 0, st>>>(nb, r.partials, r.result, nullptr, CG_NONE);
 }
 
 void launch_xpby_dev(int vt, int64_t n, const void* x, const double* bdev, void* y,
