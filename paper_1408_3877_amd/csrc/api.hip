@@ -50,6 +50,10 @@ struct ldg_ctx {
   float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
   float *u32 = nullptr, *tz1_32 = nullptr, *tz2_32 = nullptr, *V32 = nullptr;
   void *blocks_f32 = nullptr, *blocks_bf16 = nullptr, *bj_f32 = nullptr;
+  // edge-trace form of the off-diagonal edge blocks in the FP32 apply
+  bool tr = false;
+  EdgeTraces etr{};
+  double* trace64 = nullptr;
   // reference tensors in the MFMA operand layouts (FP64, FP32, BF16)
   void *Tm64 = nullptr, *Tm32 = nullptr, *Tm16 = nullptr;
   bool blocks_f32_ready = false;
@@ -252,6 +256,7 @@ struct Level {
   int vt = VT_F64, bt = BT_F64;
   const void* blocks = nullptr;
   const void* bj = nullptr;
+  const EdgeTraces* tr = nullptr;   // FP32 level of a context in the edge-trace form
   void *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *d = nullptr, *u = nullptr;
   void *tz1 = nullptr, *tz2 = nullptr, *V = nullptr;
   double vbytes = 8.0, bbytes = 8.0;   // bytes per vector / block entry
@@ -261,12 +266,20 @@ double div_bytes(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
   // geometry: kind, k+, n+, the normals and |T| (the normals in FP32 for the FP32 kernels)
   const double geo = L.vbytes == 8.0 ? 74.0 : 50.0;
-  return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + L.vbytes * 4.0 * c->N * c->K + geo * c->K;
+  const double vec = L.vbytes * 4.0 * c->N * c->K;
+  if (L.tr) {
+    // the two diagonal blocks, the neighbours' flux traces (Q per interior
+    // edge side) and the FP32 edge lengths
+    const double Q = edge_trace_points(c->N);
+    return L.bbytes * NN * 2.0 * c->K + vec + 4.0 * Q * 2.0 * c->Eint + (geo + 12.0) * c->K;
+  }
+  return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + vec + geo * c->K;
 }
-double div_flops(const ldg_ctx* c) {
+double div_flops(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
-  return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + 2.0 * NN * (c->n_sd + 2.0 * c->Eint) +
-         2.0 * c->N * c->K;
+  const double pen = 2.0 * NN * (c->n_sd + 2.0 * c->Eint) + 2.0 * c->N * c->K;
+  if (L.tr) return 2.0 * NN * 2.0 * c->K + 2.0 * c->N * edge_trace_points(c->N) * 2.0 * c->Eint + pen;
+  return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + pen;
 }
 // matrix-free apply: the divergence kernel without blocks (C own and three
 // neighbours, Z not read, y written), and the block-term kernel: D own and
@@ -288,23 +301,28 @@ double mf_flops(const ldg_ctx* c) {
   return 2.0 * N3 * (5.0 * c->K + 2.0 * c->Eint);
 }
 double grad_bytes(const ldg_ctx* c, const Level& L, bool with_j) {
-  // geometry: |T|, B, edge lengths, normals, kind, k+, n+ (FP32 copies for the FP32 kernel)
+  // geometry: |T|, B, edge lengths, normals, kind, k+, n+ (FP32 copies for the FP32 kernel);
+  // edge-trace form: d_h read and the flux traces written at Q points per interior edge side
   const double geo = L.vbytes == 8.0 ? 130.0 : 74.0;
-  return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + geo * c->K;
+  const double tr = L.tr ? 8.0 * edge_trace_points(c->N) * 2.0 * c->Eint : 0.0;
+  return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + geo * c->K + tr;
 }
-double grad_flops(const ldg_ctx* c) {
+double grad_flops(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
-  return 2.0 * NN * (2.0 * c->K + c->n_nd + 2.0 * c->Eint) + 6.0 * c->N * c->K;
+  const double tr = L.tr ? 2.0 * c->N * (2.0 + edge_trace_points(c->N)) * 2.0 * c->Eint : 0.0;
+  return 2.0 * NN * (2.0 * c->K + c->n_nd + 2.0 * c->Eint) + 6.0 * c->N * c->K + tr;
 }
 
 // y = M x + tau (eta S' x + sum_m B^m Z^m(x)), Z^m(x) = -M^{-1}(A^m x [+ J^m])
 // y = A x; with dot, also <x, y> into red.result[0] (fused into the divergence half)
-void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j, void* Zx1,
+void apply_op(ldg_ctx* c, const Level& L0, double tau, const void* x, bool with_j, void* Zx1,
               void* Zx2, void* y, bool dot = false) {
+  Level L = L0;
+  if (c->mf) L.tr = nullptr;   // the matrix-free apply contracts every block term itself
   {
-    Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c));
+    Timed tm(c, LDG_K_GRAD, grad_bytes(c, L, with_j), grad_flops(c, L));
     launch_grad(c->N, L.vt, c->geo, c->refs, c->refs32, x, with_j ? c->J1 : nullptr, with_j ? c->J2 : nullptr,
-                Zx1, Zx2, c->st);
+                Zx1, Zx2, c->st, L.tr);
   }
   if (c->mf) {
     {
@@ -317,9 +335,9 @@ void apply_op(ldg_ctx* c, const Level& L, double tau, const void* x, bool with_j
                      Zx1, Zx2, tau, y, dot ? &c->red : nullptr, c->st);
     return;
   }
-  Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c));
+  Timed tm(c, LDG_K_DIV, div_bytes(c, L), div_flops(c, L));
   launch_div(c->N, L.vt, L.bt, c->geo, c->refs, L.blocks, x, Zx1, Zx2, c->alpha, tau, c->opt.eta,
-             y, c->st, dot ? &c->red : nullptr);
+             y, c->st, dot ? &c->red : nullptr, L.tr);
 }
 
 void bj_apply(ldg_ctx* c, const Level& L, const void* r, void* z, bool dot) {
@@ -379,6 +397,7 @@ Level level_lo(ldg_ctx* c, int bt) {
   L.bj = c->bj_f32;
   L.r = c->r32; L.z = c->z32; L.p = c->p32; L.q = c->q32; L.d = c->d32; L.u = c->u32;
   L.tz1 = c->tz1_32; L.tz2 = c->tz2_32; L.V = c->V32;
+  L.tr = c->tr ? &c->etr : nullptr;
   L.vbytes = 4.0;
   L.bbytes = bt == BT_BF16 ? 2.0 : 4.0;
   return L;
@@ -1055,6 +1074,7 @@ ldg_status assemble_lowp(ldg_ctx* c) {
              2.0 * NN * c->N * (5.0 * c->K + 2.0 * c->Eint));
     launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
+    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->trace64, const_cast<float*>(c->etr.dE), c->st);
   }
   {
     Timed tm(c, LDG_K_BJ_SETUP, 12.0 * NN * c->K, 0.0);
@@ -1165,6 +1185,7 @@ ldg_status ldg_options_default(ldg_options* o) {
   o->inner_rtol = 1e-3;
   o->quad = LDG_QUAD_EXACT;
   o->cg_keep_direction = 1;
+  o->edge_traces = 1;
   return LDG_OK;
 }
 
@@ -1199,6 +1220,7 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   if (opt->precond == LDG_PC_GNN && opt->p > kMaxLearnedOrder) return LDG_EINVAL;
   if (opt->quad != LDG_QUAD_EXACT && opt->quad != LDG_QUAD_PAPER) return LDG_EINVAL;
   if (opt->cg_keep_direction != 0 && opt->cg_keep_direction != 1) return LDG_EINVAL;
+  if (opt->edge_traces != 0 && opt->edge_traces != 1) return LDG_EINVAL;
   ldg_ctx* c = new ldg_ctx();
   *out = c;
   c->opt = *opt;
@@ -1316,7 +1338,39 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
   TRY(dalloc(c, &c->sb, rf.s.size()));
   TRY(upload(c, c->refs, refs));
   {
-    const std::vector<float> r32(refs.begin(), refs.end());
+    // FP32 gradient kernel: the 14 matrices, then the traces of the basis at the
+    // p + 1 Gauss points of each reference edge, tc[n][q][j] = phi_j(x_q), and
+    // lc[n][q][i] = w_q phi_i(x_q); it skips the entries of H1, H2 that vanish
+    // by degree (phi_j of degree >= that of phi_i), checked here
+    std::vector<float> r32(refs.begin(), refs.end());
+    const int Q = c->p + 1;
+    std::vector<float> tc(3 * Q * N), lc(3 * Q * N);
+    for (int n = 0; n < 3; ++n)
+      for (int q = 0; q < Q; ++q) {
+        const double s = rf.s[q];
+        const double x1 = n == 0 ? 1.0 - s : (n == 1 ? 0.0 : s);
+        const double x2 = n == 0 ? s : (n == 1 ? 1.0 - s : 0.0);
+        for (int i = 0; i < N; ++i) {
+          const double ph = phi_hat(i, x1, x2);
+          tc[(n * Q + q) * N + i] = (float)ph;
+          lc[(n * Q + q) * N + i] = (float)(rf.ws[q] * ph);
+        }
+      }
+    r32.insert(r32.end(), tc.begin(), tc.end());
+    r32.insert(r32.end(), lc.begin(), lc.end());
+    double hmax = 0.0, hskip = 0.0;
+    for (int m = 0; m < 2; ++m)
+      for (int i = 0; i < N; ++i) {
+        int d = 0;
+        while ((d + 1) * (d + 2) / 2 <= i) ++d;
+        for (int j = 0; j < N; ++j) {
+          const double v = std::fabs(rf.H[m][i * N + j]);
+          hmax = std::max(hmax, v);
+          if (j >= d * (d + 1) / 2) hskip = std::max(hskip, v);
+        }
+      }
+    if (!(hskip <= 1e-12 * hmax) || (int)rf.s.size() != Q)
+      return fail(c, LDG_EDEVICE, "internal: reference data do not have the assumed structure");
     TRY(dalloc(c, &c->refs32, r32.size()));
     TRY(upload(c, c->refs32, r32));
   }
@@ -1389,6 +1443,43 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       TRY(dalloc(c, &p8, block_bytes(BT_BF16, Kp, N, NSLOT)));
       HIPCHK(c, hipMemsetAsync(p8, 0, block_bytes(BT_BF16, Kp, N, NSLOT), c->st));   // tail padding
       c->blocks_bf16 = p8;
+    }
+    // the edge-trace form of the off-diagonal edge blocks: exact Gauss rules
+    // on edges, so with the exact reference tensors only (the paper's edge rule
+    // of order 2p + 1 does not integrate the degree-3p products exactly)
+    c->tr = opt->edge_traces && opt->quad == LDG_QUAD_EXACT;
+    if (c->tr) {
+      const int Q = edge_trace_points(N);
+      std::vector<double> sq, wq;
+      gauss_legendre(Q, sq, wq);
+      std::vector<double> tr64(3 * Q * N);
+      std::vector<float> tr32(3 * Q * N), lift32(3 * Q * N);
+      for (int n = 0; n < 3; ++n)
+        for (int q = 0; q < Q; ++q) {
+          // point s_q of reference edge n (from vertex n+1 to vertex n+2)
+          const double s = sq[q];
+          const double x1 = n == 0 ? 1.0 - s : (n == 1 ? 0.0 : s);
+          const double x2 = n == 0 ? s : (n == 1 ? 1.0 - s : 0.0);
+          for (int i = 0; i < N; ++i) {
+            const double ph = phi_hat(i, x1, x2);
+            tr64[(n * Q + q) * N + i] = ph;
+            tr32[(n * Q + q) * N + i] = (float)ph;
+            lift32[(n * Q + q) * N + i] = (float)(wq[q] * ph);
+          }
+        }
+      float *t32 = nullptr, *l32 = nullptr, *dE = nullptr, *sig = nullptr;
+      TRY(dalloc(c, &c->trace64, tr64.size()));
+      TRY(upload(c, c->trace64, tr64));
+      TRY(dalloc(c, &t32, tr32.size()));
+      TRY(upload(c, t32, tr32));
+      TRY(dalloc(c, &l32, lift32.size()));
+      TRY(upload(c, l32, lift32));
+      const size_t ne = (size_t)Kp * 3 * Q;
+      TRY(dalloc(c, &dE, ne));
+      TRY(dalloc(c, &sig, ne));
+      HIPCHK(c, hipMemsetAsync(dE, 0, ne * sizeof(float), c->st));
+      HIPCHK(c, hipMemsetAsync(sig, 0, ne * sizeof(float), c->st));
+      c->etr = EdgeTraces{dE, t32, l32, sig};
     }
   }
   TRY(dalloc(c, &c->status, 1));
@@ -1527,6 +1618,7 @@ ldg_status ldg_assemble(ldg_ctx* c, const double* Dem) {
     const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
     launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
+    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->trace64, const_cast<float*>(c->etr.dE), c->st);
   }
   c->blocks_ready = true;
   return check_launch(c);

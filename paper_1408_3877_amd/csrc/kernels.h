@@ -15,15 +15,35 @@ enum { VT_F64 = 0, VT_F32 = 1 };
 enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2, BT_FP8 = 3 };
 
 // kernels_apply.hip
-// refs: the 14 reference matrices in FP64 (N x N each); refs32: the same in FP32
+// Edge-trace form of the off-diagonal edge blocks (FP32 apply only), with Q =
+// edge_trace_points(N) Gauss points per edge:
+//   dE    [Kpad][3Q] tiled: d_h at the points of the triangle's own edges
+//   trace [3][Q][N]: phi_j at point q of reference edge n;
+//   lift  [3][Q][N]: w_q phi_i at the same points
+//   sig   [Kpad][3Q] tiled: d_h nu.Z_h at those points (written by the
+//         gradient half, gathered by the neighbours in the divergence half)
+struct EdgeTraces {
+  const float* dE;
+  const float* trace;
+  const float* lift;
+  float* sig;
+};
+// refs: the 14 reference matrices in FP64 (N x N each); refs32: the same in FP32;
+// tr (FP32 only, optional): also write the flux traces tr->sig
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
                  const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
-                 hipStream_t st);
+                 hipStream_t st, const EdgeTraces* tr = nullptr);
 struct Reducer;
-// red (optional): red->result[0] = <C, y> afterwards
+// red (optional): red->result[0] = <C, y> afterwards; tr (FP32 with stored
+// blocks, optional): the off-diagonal edge terms from tr->sig, the blocks'
+// diagonal slots only
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
                 const void* C, const void* Z1, const void* Z2, double alpha, double tau,
-                double eta, void* y, hipStream_t st, const Reducer* red = nullptr);
+                double eta, void* y, hipStream_t st, const Reducer* red = nullptr,
+                const EdgeTraces* tr = nullptr);
+// dE of EdgeTraces from the FP64 tiled coefficients D; trace64 as `trace` in FP64
+void launch_edge_d(int N, const Geo& g, const double* D, const double* trace64, float* dE,
+                   hipStream_t st);
 // z = P^{-1} r; with red != NULL also red->result[0] = <r, z>
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
                      const Reducer* red, hipStream_t st);

@@ -75,17 +75,53 @@ __device__ inline void mv_add_s(const T* __restrict__ A, const T* x, T* acc, T s
   }
 }
 
+// acc += A x for A = H1 or H2: row i holds the integrals of d phi_i / d x_m
+// against phi_j, which vanish unless phi_j has a lower degree than phi_i (the
+// derivative has degree deg(i) - 1 and the basis is orthogonal and ordered by
+// degree), so only the columns j < deg(i) (deg(i) + 1) / 2 are read
+__host__ __device__ constexpr int h_cols(int i) {
+  int d = 0;
+  while ((d + 1) * (d + 2) / 2 <= i) ++d;
+  return d * (d + 1) / 2;
+}
+template <int N, class T>
+__device__ inline void mv_add_h(const T* __restrict__ A, const T* x, T* acc) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < h_cols(i); ++j) s += A[i * N + j] * x[j];
+    acc[i] += s;
+  }
+}
+
+// Gauss points per edge of the C traces of the FP32 gradient kernel: p + 1,
+// exact for the degree-2p products of S_diag and S_off
+__host__ __device__ constexpr int c_trace_points(int N) {
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 < N) ++p;
+  return p + 1;
+}
+
 }  // namespace
 
 // The 14 reference matrices (H1, H2, S_diag[3], S_off[3][3]), N x N each: the
 // FP32 kernel reads them through the scalar cache (rT, FP32 copy); the FP64
-// kernel keeps them in LDS (as SGPR operands its products spill registers)
-template <int N, class T>
+// kernel keeps them in LDS (as SGPR operands its products spill registers).
+// TR (FP32 only): also the edge traces of the flux of the divergence half,
+//   sig[k][n][q] = d_h(x_q) (nu_n . Z_h)(x_q)   at the Gauss points x_q of each
+// interior edge n of the triangle (its own parametrisation, trT[n][q][j] =
+// phi_j at point q of reference edge n; dE = d_h at the same points), from
+// which the neighbour forms the off-diagonal edge term of eq:hatRoffdiag
+template <int N, class T, bool TR>
 __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
                                               const T* __restrict__ rT,
                                               const T* __restrict__ C, const T* __restrict__ J1,
                                               const T* __restrict__ J2, T* __restrict__ Z1,
-                                              T* __restrict__ Z2) {
+                                              T* __restrict__ Z2, const float* __restrict__ dE,
+                                              const float* __restrict__ trT,
+                                              float* __restrict__ sig) {
+  static_assert(!TR || sizeof(T) == 4, "edge traces are an FP32 form");
   constexpr int NN = N * N;
   constexpr bool SC = sizeof(T) == 4;
   constexpr bool LDSR = !SC && refs_in_lds<N, T>();
@@ -120,8 +156,13 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T u1[N], u2[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) u1[i] = u2[i] = 0;
-    mv(ref_h(0), c, u1, (T)1);
-    mv(ref_h(1), c, u2, (T)1);
+    if constexpr (SC) {
+      mv_add_h<N, T>(rT + ref_h(0) * NN, c, u1);
+      mv_add_h<N, T>(rT + ref_h(1) * NN, c, u2);
+    } else {
+      mv(ref_h(0), c, u1, (T)1);
+      mv(ref_h(1), c, u2, (T)1);
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       a1[i] -= B22 * u1[i] - B21 * u2[i];
@@ -145,19 +186,56 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     T s[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] = 0;
-    mv(ref_sd(n), c, s, cq);
-    if (kind == LDG_EDGE_INTERIOR) {
-      const int64_t kp = g.nbr[n * Kp + k];
-      const int np = g.nbrn[n * Kp + k];
-      T cp[N];
-      load_vec<N, T>(C, kp, cp);
-      if constexpr (SC) {
-        // S_off(n, n+) with n+ per lane: one wave-uniform matrix per candidate
-        // (a single candidate on structured meshes; the others are skipped)
+    if constexpr (SC) {
+      // S_diag(n) c + S_off(n, n+) c+ through the traces at the p + 1 Gauss
+      // points of the edge: u_q = cq c(x_q) + L/2 c+(x_q), s_i = sum_q w_q
+      // phi_i(x_q) u_q.  x_q is point Q-1-q of the neighbour's edge n+.
+      // rT holds after the 14 matrices tc[3][Q][N] (phi_j at point q of
+      // reference edge n) and lc[3][Q][N] (w_q phi_i at the same points).
+      constexpr int Q = c_trace_points(N);
+      const T* tc = rT + NREF * NN;
+      const T* lc = tc + 3 * Q * N;
+      T u[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        T v = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) v += tc[(n * Q + q) * N + j] * c[j];
+        u[q] = cq * v;
+      }
+      if (kind == LDG_EDGE_INTERIOR) {
+        const int64_t kp = g.nbr[n * Kp + k];
+        const int np = g.nbrn[n * Kp + k];
+        T cp[N];
+        load_vec<N, T>(C, kp, cp);
+        // n+ per lane: one wave-uniform trace matrix per candidate (a single
+        // candidate on structured meshes; the others are skipped)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-          if (np == b) mv(ref_so(n, b), cp, s, (T)0.5 * L);
-      } else {
+          if (np == b) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              T v = 0;
+#pragma unroll
+              for (int j = 0; j < N; ++j) v += tc[(b * Q + Q - 1 - q) * N + j] * cp[j];
+              u[q] += (T)0.5 * L * v;
+            }
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T v = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v += lc[(n * Q + q) * N + i] * u[q];
+        s[i] = v;
+      }
+    } else {
+      mv(ref_sd(n), c, s, cq);
+      if (kind == LDG_EDGE_INTERIOR) {
+        const int64_t kp = g.nbr[n * Kp + k];
+        const int np = g.nbrn[n * Kp + k];
+        T cp[N];
+        load_vec<N, T>(C, kp, cp);
         mv(ref_so(n, np), cp, s, (T)0.5 * L);
       }
     }
@@ -184,15 +262,39 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   }
   store_vec<N, T>(Z1, k, a1);
   store_vec<N, T>(Z2, k, a2);
+  if constexpr (TR) {
+    constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      if (g.kind[n * Kp + k] != LDG_EDGE_INTERIOR) continue;   // read only across interior edges
+      const float nu1 = g.nu32[(2 * n) * Kp + k], nu2 = g.nu32[(2 * n + 1) * Kp + k];
+      float zn[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) zn[j] = nu1 * a1[j] + nu2 * a2[j];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        float v = 0.0f;
+#pragma unroll
+        for (int j = 0; j < N; ++j) v += trT[(n * Q + q) * N + j] * zn[j];
+        sig[vidx(k, n * Q + q, NQ)] = dE[vidx(k, n * Q + q, NQ)] * v;
+      }
+    }
+  }
 }
 
 // one triangle of the divergence half; returns <C_k, y_k> for the fused dot.
 // BLOCKS = false leaves out the block terms (the matrix-free kernel adds them).
-template <int N, class T, class BT, bool BLOCKS>
+// TR: the off-diagonal edge terms from the neighbours' flux traces (sig, as
+// k_grad writes them) instead of the stored blocks U_0..U_2; only the two
+// diagonal blocks are read.  At the point s_q of edge n of T_k the neighbour's
+// trace is its value at 1 - s_q = s_{Q-1-q} of its edge n+, and its normal is
+// -nu; lift[n][q][i] = w_q phi_i at point q of reference edge n.
+template <int N, class T, class BT, bool BLOCKS, bool TR>
 __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
                                  const BT* __restrict__ blocks, const T* __restrict__ C,
                                  const T* __restrict__ Z1, const T* __restrict__ Z2, double alpha,
-                                 double tau, double eta, T* __restrict__ y, int64_t k) {
+                                 double tau, double eta, T* __restrict__ y, int64_t k,
+                                 const float* __restrict__ sig, const float* __restrict__ lift) {
   T t[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = 0;
@@ -225,21 +327,42 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
     load_vec<N, T>(Z2, k, z);
     if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 1, NSLOT, tail, z, t);
     else block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
-    for (int n = 0; n < 3; ++n) {
-      const int64_t kp = g.nbr[n * Kp + k];
-      if (kp < 0) continue;
-      T nu1, nu2;
-      if constexpr (sizeof(T) == 4) {   // the FP32 copies: the same values, half the bytes
-        nu1 = g.nu32[(2 * n) * Kp + k];
-        nu2 = g.nu32[(2 * n + 1) * Kp + k];
-      } else {
-        nu1 = (T)g.nu[(2 * n) * Kp + k];
-        nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
-      }
+    if constexpr (TR) {
+      constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
 #pragma unroll
-      for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
-      if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
-      else block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
+      for (int n = 0; n < 3; ++n) {
+        const int64_t kp = g.nbr[n * Kp + k];
+        if (kp < 0) continue;
+        const int np = g.nbrn[n * Kp + k];
+        const float hl = -0.5f * g.elen32[n * Kp + k];
+        float w[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) w[q] = hl * sig[vidx(kp, np * Q + (Q - 1 - q), NQ)];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          float v = 0.0f;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) v += lift[(n * Q + q) * N + i] * w[q];
+          t[i] += v;
+        }
+      }
+    } else {
+      for (int n = 0; n < 3; ++n) {
+        const int64_t kp = g.nbr[n * Kp + k];
+        if (kp < 0) continue;
+        T nu1, nu2;
+        if constexpr (sizeof(T) == 4) {   // the FP32 copies: the same values, half the bytes
+          nu1 = g.nu32[(2 * n) * Kp + k];
+          nu2 = g.nu32[(2 * n + 1) * Kp + k];
+        } else {
+          nu1 = (T)g.nu[(2 * n) * Kp + k];
+          nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
+        if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
+        else block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
+      }
     }
   }
   const T a2 = (T)(alpha * g.area2[k]);
@@ -256,13 +379,15 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
 
 // y = alpha M C + tau (eta S' C + sum_m B^m Z^m); partials (optional): per-block
 // sums of <C, y>, the CG curvature p^T A p fused into the apply
-template <int N, class T, class BT, bool BLOCKS>
+template <int N, class T, class BT, bool BLOCKS, bool TR>
 __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
                                              const BT* __restrict__ blocks,
                                              const T* __restrict__ C, const T* __restrict__ Z1,
                                              const T* __restrict__ Z2, double alpha, double tau,
                                              double eta, T* __restrict__ y,
-                                             double* __restrict__ partials) {
+                                             double* __restrict__ partials,
+                                             const float* __restrict__ sig,
+                                             const float* __restrict__ lift) {
   constexpr bool LDSR = refs_in_lds<N, T>();
   static_assert(LDSR || sizeof(T) == 8, "FP32 reference matrices always fit in LDS");
   __shared__ __align__(16) T smem[LDSR ? ref_size<N, T>() : 1];
@@ -276,7 +401,8 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
   }
   const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (k < g.Kpad) s = div_row<N, T, BT, BLOCKS>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
+  if (k < g.Kpad)
+    s = div_row<N, T, BT, BLOCKS, TR>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k, sig, lift);
   if (partials == nullptr) return;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -369,6 +495,27 @@ __global__ void k_export_rows(int64_t n, const int32_t* __restrict__ elems, int 
   dst[t] = src[bgidx(elems[i], s, f / 2, ns, NG, 2) + (f & 1)];
 }
 
+// d_h at the Gauss points of the three edges of each triangle, in its own
+// parametrisation: dE[k][n][q] = sum_l D_kl phi_l(point q of reference edge n)
+// (FP64 sums, stored FP32; zero on padding triangles)
+template <int N>
+__global__ void __launch_bounds__(256) k_edge_d(Geo g, const double* __restrict__ D,
+                                                const double* __restrict__ trace64,
+                                                float* __restrict__ dE) {
+  constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.Kpad) return;
+  double d[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) d[l] = k < g.K ? D[vidx(k, l, N)] : 0.0;
+  for (int r = 0; r < NQ; ++r) {
+    double v = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) v += trace64[r * N + l] * d[l];
+    dE[vidx(k, r, NQ)] = (float)v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -378,48 +525,70 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
                  const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
-                 hipStream_t st) {
+                 hipStream_t st, const EdgeTraces* tr) {
   const unsigned nb = nblk(g.Kpad, 256);
   if (vt == VT_F64) {
-    LDG_SWITCH_N_P6(N, (k_grad<NT, double><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_grad<NT, double, false><<<nb, 256, 0, st>>>(
                         g, refs, refs, (const double*)C, (const double*)J1, (const double*)J2,
-                        (double*)Z1, (double*)Z2)));
-  } else {
-    LDG_SWITCH_N_P6(N, (k_grad<NT, float><<<nb, 256, 0, st>>>(
+                        (double*)Z1, (double*)Z2, nullptr, nullptr, nullptr)));
+  } else if (tr) {
+    LDG_SWITCH_N_P6(N, (k_grad<NT, float, true><<<nb, 256, 0, st>>>(
                         g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
-                        (float*)Z1, (float*)Z2)));
+                        (float*)Z1, (float*)Z2, tr->dE, tr->trace, tr->sig)));
+  } else {
+    LDG_SWITCH_N_P6(N, (k_grad<NT, float, false><<<nb, 256, 0, st>>>(
+                        g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
+                        (float*)Z1, (float*)Z2, nullptr, nullptr, nullptr)));
   }
 }
 
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
                 const void* C, const void* Z1, const void* Z2, double alpha, double tau,
-                double eta, void* y, hipStream_t st, const Reducer* red) {
+                double eta, void* y, hipStream_t st, const Reducer* red, const EdgeTraces* tr) {
   const unsigned nb = nblk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
+  const float* sig = tr ? tr->sig : nullptr;
+  const float* lift = tr ? tr->lift : nullptr;
   if (blocks == nullptr) {   // matrix-free: the terms without blocks
     if (vt == VT_F64) {
-      LDG_SWITCH_N_P6(N, (k_div<NT, double, double, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, double, double, false, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const double*)C, (const double*)Z1,
-                          (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
+                          (const double*)Z2, alpha, tau, eta, (double*)y, parts, nullptr,
+                          nullptr)));
     } else {
-      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, false, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const float*)C, (const float*)Z1, (const float*)Z2,
-                          alpha, tau, eta, (float*)y, parts)));
+                          alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
     }
   } else if (vt == VT_F64) {
-    LDG_SWITCH_N_P6(N, (k_div<NT, double, double, true><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, double, double, true, false><<<nb, 256, 0, st>>>(
                         g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
-                        (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
+                        (const double*)Z2, alpha, tau, eta, (double*)y, parts, nullptr, nullptr)));
   } else if (bt == BT_F32) {
-    LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true><<<nb, 256, 0, st>>>(
-                        g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
-  } else {
-    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true><<<nb, 256, 0, st>>>(
+    if (tr) {
+      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true, true><<<nb, 256, 0, st>>>(
+                          g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
+                          (const float*)Z2, alpha, tau, eta, (float*)y, parts, sig, lift)));
+    } else {
+      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true, false><<<nb, 256, 0, st>>>(
+                          g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
+                          (const float*)Z2, alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
+    }
+  } else if (tr) {
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true, true><<<nb, 256, 0, st>>>(
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts, sig, lift)));
+  } else {
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true, false><<<nb, 256, 0, st>>>(
+                        g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
   }
   if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
+}
+
+void launch_edge_d(int N, const Geo& g, const double* D, const double* trace64, float* dE,
+                   hipStream_t st) {
+  LDG_SWITCH_N_P6(N, (k_edge_d<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, D, trace64, dE)));
 }
 
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,

@@ -20,6 +20,14 @@ __host__ __device__ inline int64_t vidx(int64_t k, int i, int N) {
   return (k >> 6) * (int64_t)(TILE * N) + (int64_t)i * TILE + (k & 63);
 }
 __host__ __device__ constexpr int npairs(int N) { return (N * N + 1) / 2; }
+// Gauss points per edge of the edge-trace form of the neighbour blocks: the
+// integrands d phi_i phi_j of the off-diagonal edge terms have degree 3p on
+// the edge, so ceil((3p + 1) / 2) points integrate them exactly
+__host__ __device__ constexpr int edge_trace_points(int N) {
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 < N) ++p;
+  return (3 * p + 2) / 2;
+}
 // rows (coefficient index l) of the FP64 / FP32 A-operand tables of the MFMA
 // block assembly: its k-steps of four cover l < 4 ceil(N / 4); 16 rows for
 // N <= 15, 24 for N = 21, 28 for N = 28

@@ -28,7 +28,7 @@ class Options(C.Structure):
                 ("precond", C.c_int), ("rtol", C.c_double), ("restart", C.c_int),
                 ("max_iters", C.c_int), ("stream", C.c_void_p), ("krylov", C.c_int),
                 ("inner_rtol", C.c_double), ("quad", C.c_int),
-                ("cg_keep_direction", C.c_int)]
+                ("cg_keep_direction", C.c_int), ("edge_traces", C.c_int)]
 
 
 class Sizes(C.Structure):
@@ -225,7 +225,8 @@ class Solver:
 
     def __init__(self, coordV, V0T, edge_kind, p, eta=1.0, precision=LDG_FP64,
                  precond=LDG_PC_BLOCK_JACOBI, rtol=1e-8, restart=30, max_iters=5000,
-                 krylov=0, inner_rtol=1e-3, device=None, quad="exact", keep_direction=True):
+                 krylov=0, inner_rtol=1e-3, device=None, quad="exact", keep_direction=True,
+                 edge_traces=True):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -242,6 +243,7 @@ class Solver:
         opt.inner_rtol = inner_rtol
         opt.quad = {"exact": 0, "paper": 1}.get(quad, quad)
         opt.cg_keep_direction = int(bool(keep_direction))
+        opt.edge_traces = int(bool(edge_traces))
         with torch.cuda.device(self.device):
             opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
             h = C.c_void_p()

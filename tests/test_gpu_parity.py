@@ -342,15 +342,17 @@ def _numbered_mesh(mesh, n, seed):
     return cV, V0T, kind
 
 
+@pytest.mark.parametrize("edge_traces", [True, False])
 @pytest.mark.parametrize("precision,tol", [(1, 2e-5), (2, 1e-2)])
 @pytest.mark.parametrize("mesh,p", [("paper", 3), ("pairs", 3), ("pairs", 4), ("pairs-rotated", 2),
                                     ("delaunay", 4)])
-def test_inner_precision_apply(torch_mod, precision, tol, mesh, p):
+def test_inner_precision_apply(torch_mod, precision, tol, mesh, p, edge_traces):
     # the operator as the mixed-precision inner solves evaluate it (FP32 vectors,
-    # FP32 / BF16 blocks) against the oracle's FP64 eliminated matrix.  With the
-    # triangles numbered in neighbour pairs, the neighbours beside a triangle in
-    # its tile are read from the lanes beside it (the edges of 64-triangle tiles
-    # and the ragged last tile included: K = 288 or more)
+    # FP32 / BF16 blocks; the off-diagonal edge terms from the neighbours' flux
+    # traces, or from the stored blocks) against the oracle's FP64 eliminated
+    # matrix.  With the triangles numbered in neighbour pairs, the neighbours
+    # beside a triangle in its tile are read from the lanes beside it (the edges
+    # of 64-triangle tiles and the ragged last tile included: K = 288 or more)
     cV, V0T, kind = _numbered_mesh(mesh, 12, 611 + p)
     pr = Problem(cV, V0T, kind, p)
     rng = np.random.default_rng(612 + p)
@@ -358,14 +360,42 @@ def test_inner_precision_apply(torch_mod, precision, tol, mesh, p):
     D = 1.0 + 0.3 * rng.standard_normal((K, N))
     Cv = rng.standard_normal((K, N))
     dt = 0.011
-    s = _solver(cV, V0T, kind, p, precision=precision)
+    s = _solver(cV, V0T, kind, p, precision=precision, edge_traces=edge_traces)
     s.assemble(D)
     want = (schur_matrix(Blocks(pr.grid, pr.refs, D), pr.grid, pr.refs, 1.0, dt)
             @ Cv.reshape(-1)).reshape(K, N)
     got = to_np(s.apply_schur_lowp(dt, Cv))
     err = rel_l2(pr.grid.areaT, got, want)
-    print("inner-precision apply %s p=%d precision=%d: rel L2 %.2e" % (mesh, p, precision, err))
+    print("inner-precision apply %s p=%d precision=%d traces=%d: rel L2 %.2e"
+          % (mesh, p, precision, edge_traces, err))
     assert err < tol, err
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+def test_edge_trace_form_of_the_neighbour_blocks(torch_mod, p):
+    # the FP32 apply with the off-diagonal edge terms from the neighbours' flux
+    # traces (ceil((3p+1)/2) Gauss points per edge, exact for the degree-3p
+    # integrands) agrees with the one reading all five stored FP32 blocks to
+    # FP32 rounding, on a mesh whose local edge numbering is rotated at random
+    # (every neighbour edge n+ inside a wave) with Dirichlet and Neumann sides;
+    # d varies inside the triangles, so the traces carry every mode of d_h
+    cV, V0T, kind = _numbered_mesh("pairs-rotated", 11, 631 + p)
+    pr = Problem(cV, V0T, kind, p)
+    rng = np.random.default_rng(632 + p)
+    K, N = pr.grid.numT, pr.N
+    D = 1.0 + 0.3 * rng.standard_normal((K, N))
+    Cv = rng.standard_normal((K, N))
+    ys = []
+    for tr in (True, False):
+        s = _solver(cV, V0T, kind, p, precision=1, edge_traces=tr)
+        s.assemble(D)
+        ys.append(to_np(s.apply_schur_lowp(0.013, Cv)))
+    want = (schur_matrix(Blocks(pr.grid, pr.refs, D), pr.grid, pr.refs, 1.0, 0.013)
+            @ Cv.reshape(-1)).reshape(K, N)
+    e_tr, e_st = (rel_l2(pr.grid.areaT, y, want) for y in ys)
+    d = rel_l2(pr.grid.areaT, ys[0], ys[1])
+    print("edge traces p=%d: vs oracle %.2e (stored blocks %.2e), between %.2e" % (p, e_tr, e_st, d))
+    assert e_tr < 2e-5 and d < 2e-5, (e_tr, d)
 
 
 def test_inner_precision_apply_is_independent_of_the_numbering(torch_mod):
