@@ -354,7 +354,7 @@ def main():
     kv = stats[name]
     per_launch = kv["bytes"] / max(kv["launches"], 1)
     avg_ms = kv["total_ms"] / max(kv["launches"], 1)
-    kernel_desc = {"div": "k_div (operator apply, stored blocks)",
+    kernel_desc = {"div": "k_div (operator apply, divergence half)",
                    "factor": "k_fac_w + k_fac_f (learned factored preconditioner apply)",
                    "bj_apply": "k_bj_apply (block-Jacobi apply)",
                    "grad": "k_grad (operator gradient half)",
