@@ -53,7 +53,6 @@ struct ldg_ctx {
   // edge-trace form of the off-diagonal edge blocks in the FP32 apply
   bool tr = false;
   EdgeTraces etr{};
-  double* trace64 = nullptr;
   // reference tensors in the MFMA operand layouts (FP64, FP32, BF16)
   void *Tm64 = nullptr, *Tm32 = nullptr, *Tm16 = nullptr;
   bool blocks_f32_ready = false;
@@ -268,17 +267,24 @@ double div_bytes(const ldg_ctx* c, const Level& L) {
   const double geo = L.vbytes == 8.0 ? 74.0 : 50.0;
   const double vec = L.vbytes * 4.0 * c->N * c->K;
   if (L.tr) {
-    // the two diagonal blocks, the neighbours' flux traces (Q per interior
-    // edge side) and the FP32 edge lengths
-    const double Q = edge_trace_points(c->N);
-    return L.bbytes * NN * 2.0 * c->K + vec + 4.0 * Q * 2.0 * c->Eint + (geo + 12.0) * c->K;
+    // quadrature form: C, Z^1, Z^2, the penalty rows and y; d_h at the volume
+    // points; the flux traces of the triangle's interior and Dirichlet edges and
+    // of the neighbours (Q per edge side); kind, k+, n+, FP32 B, edge lengths, |T|
+    const double Q = edge_trace_points(c->N), RV = vol_points(c->N);
+    const double n_tr = c->n_sd;   // interior edge sides + Dirichlet edges
+    return 4.0 * 5.0 * c->N * c->K + 4.0 * RV * c->K + 4.0 * Q * (n_tr + 2.0 * c->Eint) +
+           62.0 * c->K;
   }
   return L.bbytes * NN * (2.0 * c->K + 2.0 * c->Eint) + vec + geo * c->K;
 }
 double div_flops(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
   const double pen = 2.0 * NN * (c->n_sd + 2.0 * c->Eint) + 2.0 * c->N * c->K;
-  if (L.tr) return 2.0 * NN * 2.0 * c->K + 2.0 * c->N * edge_trace_points(c->N) * 2.0 * c->Eint + pen;
+  if (L.tr) {
+    // the volume rule (4N per point) and one lift per interior or Dirichlet edge
+    return 2.0 * 4.0 * c->N * vol_points(c->N) * c->K + 2.0 * c->N * edge_trace_points(c->N) * c->n_sd +
+           2.0 * c->N * c->K;
+  }
   return 2.0 * NN * (2.0 * c->K + 2.0 * c->Eint) + pen;
 }
 // matrix-free apply: the divergence kernel without blocks (C own and three
@@ -302,14 +308,16 @@ double mf_flops(const ldg_ctx* c) {
 }
 double grad_bytes(const ldg_ctx* c, const Level& L, bool with_j) {
   // geometry: |T|, B, edge lengths, normals, kind, k+, n+ (FP32 copies for the FP32 kernel);
-  // edge-trace form: d_h read and the flux traces written at Q points per interior edge side
+  // quadrature form: d_h read and the flux traces written at Q points per interior edge
+  // side and Dirichlet edge, the penalty rows written
+  const double n_tr = c->n_sd;   // interior edge sides + Dirichlet edges
   const double geo = L.vbytes == 8.0 ? 130.0 : 74.0;
-  const double tr = L.tr ? 8.0 * edge_trace_points(c->N) * 2.0 * c->Eint : 0.0;
+  const double tr = L.tr ? 8.0 * edge_trace_points(c->N) * n_tr + 4.0 * c->N * c->K : 0.0;
   return L.vbytes * (with_j ? 5.0 : 3.0) * c->N * c->K + geo * c->K + tr;
 }
 double grad_flops(const ldg_ctx* c, const Level& L) {
   const double NN = (double)c->N * c->N;
-  const double tr = L.tr ? 2.0 * c->N * (2.0 + edge_trace_points(c->N)) * 2.0 * c->Eint : 0.0;
+  const double tr = L.tr ? 2.0 * c->N * (2.0 + edge_trace_points(c->N)) * c->n_sd : 0.0;
   return 2.0 * NN * (2.0 * c->K + c->n_nd + 2.0 * c->Eint) + 6.0 * c->N * c->K + tr;
 }
 
@@ -1074,7 +1082,7 @@ ldg_status assemble_lowp(ldg_ctx* c) {
              2.0 * NN * c->N * (5.0 * c->K + 2.0 * c->Eint));
     launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
-    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->trace64, const_cast<float*>(c->etr.dE), c->st);
+    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->etr, c->st);
   }
   {
     Timed tm(c, LDG_K_BJ_SETUP, 12.0 * NN * c->K, 0.0);
@@ -1444,9 +1452,10 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
       HIPCHK(c, hipMemsetAsync(p8, 0, block_bytes(BT_BF16, Kp, N, NSLOT), c->st));   // tail padding
       c->blocks_bf16 = p8;
     }
-    // the edge-trace form of the off-diagonal edge blocks: exact Gauss rules
-    // on edges, so with the exact reference tensors only (the paper's edge rule
-    // of order 2p + 1 does not integrate the degree-3p products exactly)
+    // the quadrature form of the FP32 apply: Gauss rules exact for the
+    // degree-3p edge integrands and the degree-(3p-1) volume integrand, so
+    // with the exact reference tensors only (the paper's rules under-integrate
+    // these terms, and the stored blocks carry that)
     c->tr = opt->edge_traces && opt->quad == LDG_QUAD_EXACT;
     if (c->tr) {
       const int Q = edge_trace_points(N);
@@ -1467,19 +1476,50 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
             lift32[(n * Q + q) * N + i] = (float)(wq[q] * ph);
           }
         }
-      float *t32 = nullptr, *l32 = nullptr, *dE = nullptr, *sig = nullptr;
-      TRY(dalloc(c, &c->trace64, tr64.size()));
-      TRY(upload(c, c->trace64, tr64));
+      // volume rule: Gauss points of the unit square collapsed onto the triangle
+      const int nqu = vol_points_u(N), nqv = vol_points_v(N), RV = nqu * nqv;
+      std::vector<double> vol64(std::max(RV, 1) * N, 0.0);
+      std::vector<float> vtab(std::max(RV, 1) * 3 * N, 0.0f);
+      if (RV > 0) {
+        std::vector<double> gu, gwu, gv, gwv;
+        gauss_legendre(nqu, gu, gwu);
+        gauss_legendre(nqv, gv, gwv);
+        for (int a = 0; a < nqu; ++a)
+          for (int b = 0; b < nqv; ++b) {
+            const int q = a * nqv + b;
+            const double x1 = gu[a], x2 = (1.0 - gu[a]) * gv[b];
+            const double w = gwu[a] * gwv[b] * (1.0 - gu[a]);
+            for (int i = 0; i < N; ++i) {
+              vol64[q * N + i] = w * phi_hat(i, x1, x2);
+              vtab[(q * 3 + 0) * N + i] = (float)phi_hat(i, x1, x2);
+              vtab[(q * 3 + 1) * N + i] = (float)dphi_hat(i, 0, x1, x2);
+              vtab[(q * 3 + 2) * N + i] = (float)dphi_hat(i, 1, x1, x2);
+            }
+          }
+      }
+      float *t32 = nullptr, *l32 = nullptr, *vt32 = nullptr, *dE = nullptr, *dvol = nullptr;
+      float *sig = nullptr, *pen = nullptr;
+      double *t64 = nullptr, *v64 = nullptr;
+      TRY(dalloc(c, &t64, tr64.size()));
+      TRY(upload(c, t64, tr64));
+      TRY(dalloc(c, &v64, vol64.size()));
+      TRY(upload(c, v64, vol64));
       TRY(dalloc(c, &t32, tr32.size()));
       TRY(upload(c, t32, tr32));
       TRY(dalloc(c, &l32, lift32.size()));
       TRY(upload(c, l32, lift32));
-      const size_t ne = (size_t)Kp * 3 * Q;
+      TRY(dalloc(c, &vt32, vtab.size()));
+      TRY(upload(c, vt32, vtab));
+      const size_t ne = (size_t)Kp * 3 * Q, nvq = (size_t)Kp * std::max(RV, 1);
       TRY(dalloc(c, &dE, ne));
       TRY(dalloc(c, &sig, ne));
+      TRY(dalloc(c, &dvol, nvq));
+      TRY(dalloc(c, &pen, nv));
       HIPCHK(c, hipMemsetAsync(dE, 0, ne * sizeof(float), c->st));
       HIPCHK(c, hipMemsetAsync(sig, 0, ne * sizeof(float), c->st));
-      c->etr = EdgeTraces{dE, t32, l32, sig};
+      HIPCHK(c, hipMemsetAsync(dvol, 0, nvq * sizeof(float), c->st));
+      HIPCHK(c, hipMemsetAsync(pen, 0, nv * sizeof(float), c->st));
+      c->etr = EdgeTraces{dE, dvol, t32, l32, vt32, t64, v64, sig, pen, (float)opt->eta};
     }
   }
   TRY(dalloc(c, &c->status, 1));
@@ -1618,7 +1658,7 @@ ldg_status ldg_assemble(ldg_ctx* c, const double* Dem) {
     const int bt = c->opt.precision == LDG_MIXED_BF16 ? BT_BF16 : BT_F32;
     launch_assemble_mfma(c->N, bt, c->geo, c->D, bt == BT_BF16 ? c->Tm16 : c->Tm32,
                          bt == BT_BF16 ? c->blocks_bf16 : c->blocks_f32, c->st);
-    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->trace64, const_cast<float*>(c->etr.dE), c->st);
+    if (c->tr) launch_edge_d(c->N, c->geo, c->D, c->etr, c->st);
   }
   c->blocks_ready = true;
   return check_launch(c);

@@ -15,35 +15,44 @@ enum { VT_F64 = 0, VT_F32 = 1 };
 enum { BT_F64 = 0, BT_F32 = 1, BT_BF16 = 2, BT_FP8 = 3 };
 
 // kernels_apply.hip
-// Edge-trace form of the off-diagonal edge blocks (FP32 apply only), with Q =
-// edge_trace_points(N) Gauss points per edge:
+// Quadrature form of the FP32 apply (no stored blocks), with Q =
+// edge_trace_points(N) Gauss points per edge and RV = vol_points(N) volume points:
 //   dE    [Kpad][3Q] tiled: d_h at the points of the triangle's own edges
-//   trace [3][Q][N]: phi_j at point q of reference edge n;
+//   dvol  [Kpad][RV] tiled: w_q d_h(x_q) at the volume points
+//   trace [3][Q][N]: phi_j at point q of reference edge n (trace64: the same in FP64)
 //   lift  [3][Q][N]: w_q phi_i at the same points
-//   sig   [Kpad][3Q] tiled: d_h nu.Z_h at those points (written by the
-//         gradient half, gathered by the neighbours in the divergence half)
+//   vtab  [RV][3][N]: phi_i, dphi_i/dx1_hat, dphi_i/dx2_hat at x_q
+//   vol64 [RV][N]: w_q phi_l(x_q) in FP64
+//   sig   [Kpad][3Q] tiled: d_h nu.Z_h at the edge points (interior and
+//         Dirichlet edges), written by the gradient half, read by the
+//         triangle itself and its neighbours in the divergence half
+//   pen   [Kpad][N] tiled: the penalty rows, written by the gradient half
 struct EdgeTraces {
-  const float* dE;
+  float* dE;
+  float* dvol;
   const float* trace;
   const float* lift;
+  const float* vtab;
+  const double* trace64;
+  const double* vol64;
   float* sig;
+  float* pen;
+  float eta;
 };
 // refs: the 14 reference matrices in FP64 (N x N each); refs32: the same in FP32;
-// tr (FP32 only, optional): also write the flux traces tr->sig
+// tr (FP32 only, optional): also write the flux traces tr->sig and the penalty rows tr->pen
 void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* refs32,
                  const void* C, const void* J1, const void* J2, void* Z1, void* Z2,
                  hipStream_t st, const EdgeTraces* tr = nullptr);
 struct Reducer;
-// red (optional): red->result[0] = <C, y> afterwards; tr (FP32 with stored
-// blocks, optional): the off-diagonal edge terms from tr->sig, the blocks'
-// diagonal slots only
+// red (optional): red->result[0] = <C, y> afterwards; tr (FP32, optional):
+// the quadrature form, blocks not read
 void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const void* blocks,
                 const void* C, const void* Z1, const void* Z2, double alpha, double tau,
                 double eta, void* y, hipStream_t st, const Reducer* red = nullptr,
                 const EdgeTraces* tr = nullptr);
-// dE of EdgeTraces from the FP64 tiled coefficients D; trace64 as `trace` in FP64
-void launch_edge_d(int N, const Geo& g, const double* D, const double* trace64, float* dE,
-                   hipStream_t st);
+// dE and dvol of EdgeTraces from the FP64 tiled coefficients D
+void launch_edge_d(int N, const Geo& g, const double* D, const EdgeTraces& tr, hipStream_t st);
 // z = P^{-1} r; with red != NULL also red->result[0] = <r, z>
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,
                      const Reducer* red, hipStream_t st);

@@ -108,11 +108,12 @@ __host__ __device__ constexpr int c_trace_points(int N) {
 // The 14 reference matrices (H1, H2, S_diag[3], S_off[3][3]), N x N each: the
 // FP32 kernel reads them through the scalar cache (rT, FP32 copy); the FP64
 // kernel keeps them in LDS (as SGPR operands its products spill registers).
-// TR (FP32 only): also the edge traces of the flux of the divergence half,
-//   sig[k][n][q] = d_h(x_q) (nu_n . Z_h)(x_q)   at the Gauss points x_q of each
-// interior edge n of the triangle (its own parametrisation, trT[n][q][j] =
-// phi_j at point q of reference edge n; dE = d_h at the same points), from
-// which the neighbour forms the off-diagonal edge term of eq:hatRoffdiag
+// TR (FP32 only), for the quadrature form of the divergence half (k_div_q):
+//   sig[k][n][q] = d_h(x_q) (nu_n . Z_h)(x_q)  at the Gauss points x_q of each
+//     interior or Dirichlet edge n (its own parametrisation; trT[n][q][j] =
+//     phi_j at point q of reference edge n, dE = d_h at the same points),
+//   pen[k] = eta (S_diag + S_D) C - eta S_off C+, the penalty rows of the
+//     divergence half, from the C traces the gradient's edge terms use.
 template <int N, class T, bool TR>
 __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ refs,
                                               const T* __restrict__ rT,
@@ -120,7 +121,8 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
                                               const T* __restrict__ J2, T* __restrict__ Z1,
                                               T* __restrict__ Z2, const float* __restrict__ dE,
                                               const float* __restrict__ trT,
-                                              float* __restrict__ sig) {
+                                              float* __restrict__ sig, float* __restrict__ pen,
+                                              float eta) {
   static_assert(!TR || sizeof(T) == 4, "edge traces are an FP32 form");
   constexpr int NN = N * N;
   constexpr bool SC = sizeof(T) == 4;
@@ -132,8 +134,7 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
     sm = smem;
   }
   auto mv = [&](int ref, const T* x, T* acc, T scale) {
-    if constexpr (SC) mv_add_s<N, T>(rT + ref * NN, x, acc, scale);
-    else mv_add<N, T>(sm + ref * N * row_stride<N, T>(), x, acc, scale);
+    mv_add<N, T>(sm + ref * N * row_stride<N, T>(), x, acc, scale);
   };
   const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
@@ -143,6 +144,7 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   if (k >= g.K) {
     store_vec<N, T>(Z1, k, a1);
     store_vec<N, T>(Z2, k, a2);
+    if constexpr (TR) store_vec<N, T>(pen, k, a1);
     return;
   }
   const int64_t Kp = g.Kpad;
@@ -169,9 +171,12 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
       a2[i] -= -B12 * u1[i] + B11 * u2[i];
     }
   }
+  T pv[TR ? N : 1];
+#pragma unroll
+  for (int i = 0; i < (TR ? N : 1); ++i) pv[i] = 0;
   for (int n = 0; n < 3; ++n) {
     const int kind = g.kind[n * Kp + k];
-    if (kind == LDG_EDGE_DIRICHLET) continue;
+    if (kind == LDG_EDGE_DIRICHLET && !TR) continue;
     T L, nu1, nu2;
     if constexpr (SC) {
       L = g.elen32[n * Kp + k];
@@ -187,21 +192,24 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] = 0;
     if constexpr (SC) {
-      // S_diag(n) c + S_off(n, n+) c+ through the traces at the p + 1 Gauss
-      // points of the edge: u_q = cq c(x_q) + L/2 c+(x_q), s_i = sum_q w_q
-      // phi_i(x_q) u_q.  x_q is point Q-1-q of the neighbour's edge n+.
+      // S_diag(n) c and S_off(n, n+) c+ through the traces at the p + 1 Gauss
+      // points of the edge, own_q = c(x_q) and nb_q = c+(x_q); x_q is point
+      // Q-1-q of the neighbour's edge n+.  Gradient (interior and Neumann
+      // edges): s_i = sum_q w_q phi_i(x_q) (cq own_q + L/2 nb_q).  Penalty (TR;
+      // interior and Dirichlet edges): eta sum_q w_q phi_i(x_q) (own_q - nb_q).
       // rT holds after the 14 matrices tc[3][Q][N] (phi_j at point q of
       // reference edge n) and lc[3][Q][N] (w_q phi_i at the same points).
       constexpr int Q = c_trace_points(N);
       const T* tc = rT + NREF * NN;
       const T* lc = tc + 3 * Q * N;
-      T u[Q];
+      T own[Q], nb[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         T v = 0;
 #pragma unroll
         for (int j = 0; j < N; ++j) v += tc[(n * Q + q) * N + j] * c[j];
-        u[q] = cq * v;
+        own[q] = v;
+        nb[q] = 0;
       }
       if (kind == LDG_EDGE_INTERIOR) {
         const int64_t kp = g.nbr[n * Kp + k];
@@ -218,16 +226,30 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
               T v = 0;
 #pragma unroll
               for (int j = 0; j < N; ++j) v += tc[(b * Q + Q - 1 - q) * N + j] * cp[j];
-              u[q] += (T)0.5 * L * v;
-            }
+              nb[q] = v;
+                  }
           }
+      }
+      // both lifts in one pass over the table: the gradient's (interior and
+      // Neumann edges) into s, the penalty's (TR; interior and Dirichlet
+      // edges) into pv
+      const T gw = kind != LDG_EDGE_DIRICHLET ? (T)1 : (T)0;
+      const T pw = TR && kind != LDG_EDGE_NEUMANN ? (T)eta : (T)0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const T u = gw * (cq * own[q] + (T)0.5 * L * nb[q]);
+        const T up = pw * (own[q] - nb[q]);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const T l = lc[(n * Q + q) * N + i];
+          s[i] += l * u;
+          if constexpr (TR) pv[i] += l * up;
+        }
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        T v = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v += lc[(n * Q + q) * N + i] * u[q];
-        s[i] = v;
+        a1[i] += nu1 * s[i];
+        a2[i] += nu2 * s[i];
       }
     } else {
       mv(ref_sd(n), c, s, cq);
@@ -238,11 +260,11 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
         load_vec<N, T>(C, kp, cp);
         mv(ref_so(n, np), cp, s, (T)0.5 * L);
       }
-    }
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      a1[i] += nu1 * s[i];
-      a2[i] += nu2 * s[i];
+      for (int i = 0; i < N; ++i) {
+        a1[i] += nu1 * s[i];
+        a2[i] += nu2 * s[i];
+      }
     }
   }
   if (J1 != nullptr) {
@@ -263,10 +285,11 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   store_vec<N, T>(Z1, k, a1);
   store_vec<N, T>(Z2, k, a2);
   if constexpr (TR) {
+    store_vec<N, T>(pen, k, pv);
     constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-      if (g.kind[n * Kp + k] != LDG_EDGE_INTERIOR) continue;   // read only across interior edges
+      if (g.kind[n * Kp + k] == LDG_EDGE_NEUMANN) continue;   // no flux term there
       const float nu1 = g.nu32[(2 * n) * Kp + k], nu2 = g.nu32[(2 * n + 1) * Kp + k];
       float zn[N];
 #pragma unroll
@@ -282,19 +305,114 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const double* __restrict__ 
   }
 }
 
+// The divergence half in the quadrature form of the FP32 apply (no stored
+// blocks): y = alpha M C + tau (pen + sum_m B^m Z^m) with
+//   -G^m Z^m  (eq:hatG): sum over the exact volume rule of w_q d_h(x_q)
+//       dphi_i/dx_m(x_q) Z^m(x_q), with dvol[k][q] = w_q d_h(x_q) and
+//       vt[q][0..2][.] = phi, dphi/dx1_hat, dphi/dx2_hat at x_q;
+//   R^m, R^m_D (eq:hatRdiag, eq:hatRoffdiag): per interior edge |E| sum_q
+//       w_q phi_i(x_q) (sig_k(x_q) - sig_k+(x_q)) / 2, per Dirichlet edge
+//       |E| sum_q w_q phi_i(x_q) sig_k(x_q), from the flux traces sig that
+//       k_grad wrote (the neighbour's at its point Q-1-q, its normal -nu);
+//   pen: the penalty rows k_grad wrote.
+// partials (optional): per-block sums of <C, y>.
+template <int N>
+__global__ void __launch_bounds__(256) k_div_q(Geo g, const float* __restrict__ C,
+                                               const float* __restrict__ Z1,
+                                               const float* __restrict__ Z2,
+                                               const float* __restrict__ pen, double alpha,
+                                               double tau, float* __restrict__ y,
+                                               double* __restrict__ partials,
+                                               const float* __restrict__ sig,
+                                               const float* __restrict__ dvol,
+                                               const float* __restrict__ vt,
+                                               const float* __restrict__ lift) {
+  constexpr int Q = edge_trace_points(N), NQ = 3 * Q, RV = vol_points(N);
+  __shared__ double red[4];
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t Kp = g.Kpad;
+  double dot = 0.0;
+  if (k < Kp) {
+    float t[N];
+    if (k >= g.K) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) t[i] = 0.0f;
+      store_vec<N, float>(y, k, t);
+    } else {
+      load_vec<N, float>(pen, k, t);
+      if constexpr (RV > 0) {
+        float z1[N], z2[N];
+        load_vec<N, float>(Z1, k, z1);
+        load_vec<N, float>(Z2, k, z2);
+        const float B11 = g.B32[k], B12 = g.B32[Kp + k], B21 = g.B32[2 * Kp + k],
+                    B22 = g.B32[3 * Kp + k];
+        for (int q = 0; q < RV; ++q) {
+          const float* ph = vt + q * 3 * N;
+          float zq1 = 0.0f, zq2 = 0.0f;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            zq1 += ph[j] * z1[j];
+            zq2 += ph[j] * z2[j];
+          }
+          const float dw = dvol[vidx(k, q, RV)];
+          const float g1 = dw * (B22 * zq1 - B12 * zq2), g2 = dw * (B11 * zq2 - B21 * zq1);
+#pragma unroll
+          for (int i = 0; i < N; ++i) t[i] -= ph[N + i] * g1 + ph[2 * N + i] * g2;
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const int kind = g.kind[n * Kp + k];
+        if (kind == LDG_EDGE_NEUMANN) continue;
+        const float L = g.elen32[n * Kp + k];
+        float w[Q];
+        if (kind == LDG_EDGE_INTERIOR) {
+          const int64_t kp = g.nbr[n * Kp + k];
+          const int np = g.nbrn[n * Kp + k];
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            w[q] = 0.5f * L * (sig[vidx(k, n * Q + q, NQ)] - sig[vidx(kp, np * Q + (Q - 1 - q), NQ)]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) w[q] = L * sig[vidx(k, n * Q + q, NQ)];
+        }
+        // one point at a time: each step reads N table entries through the
+        // scalar cache, and the barrier keeps the compiler from hoisting the
+        // loads of all points at once (more SGPRs than a wave has)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) t[i] += lift[(n * Q + q) * N + i] * w[q];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      float c[N];
+      load_vec<N, float>(C, k, c);
+      const float a2 = (float)(alpha * g.area2[k]);
+      const float tt = (float)tau;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        t[i] = a2 * c[i] + tt * t[i];
+        dot += (double)c[i] * (double)t[i];
+      }
+      store_vec<N, float>(y, k, t);
+    }
+  }
+  if (partials == nullptr) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // one triangle of the divergence half; returns <C_k, y_k> for the fused dot.
 // BLOCKS = false leaves out the block terms (the matrix-free kernel adds them).
-// TR: the off-diagonal edge terms from the neighbours' flux traces (sig, as
-// k_grad writes them) instead of the stored blocks U_0..U_2; only the two
-// diagonal blocks are read.  At the point s_q of edge n of T_k the neighbour's
-// trace is its value at 1 - s_q = s_{Q-1-q} of its edge n+, and its normal is
-// -nu; lift[n][q][i] = w_q phi_i at point q of reference edge n.
-template <int N, class T, class BT, bool BLOCKS, bool TR>
+template <int N, class T, class BT, bool BLOCKS>
 __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
                                  const BT* __restrict__ blocks, const T* __restrict__ C,
                                  const T* __restrict__ Z1, const T* __restrict__ Z2, double alpha,
-                                 double tau, double eta, T* __restrict__ y, int64_t k,
-                                 const float* __restrict__ sig, const float* __restrict__ lift) {
+                                 double tau, double eta, T* __restrict__ y, int64_t k) {
   T t[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = 0;
@@ -327,42 +445,21 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
     load_vec<N, T>(Z2, k, z);
     if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 1, NSLOT, tail, z, t);
     else block_mv<N, BT, T>(blocks, k, 1, NSLOT, z, t);
-    if constexpr (TR) {
-      constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
-#pragma unroll
-      for (int n = 0; n < 3; ++n) {
-        const int64_t kp = g.nbr[n * Kp + k];
-        if (kp < 0) continue;
-        const int np = g.nbrn[n * Kp + k];
-        const float hl = -0.5f * g.elen32[n * Kp + k];
-        float w[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) w[q] = hl * sig[vidx(kp, np * Q + (Q - 1 - q), NQ)];
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          float v = 0.0f;
-#pragma unroll
-          for (int q = 0; q < Q; ++q) v += lift[(n * Q + q) * N + i] * w[q];
-          t[i] += v;
-        }
+    for (int n = 0; n < 3; ++n) {
+      const int64_t kp = g.nbr[n * Kp + k];
+      if (kp < 0) continue;
+      T nu1, nu2;
+      if constexpr (sizeof(T) == 4) {   // the FP32 copies: the same values, half the bytes
+        nu1 = g.nu32[(2 * n) * Kp + k];
+        nu2 = g.nu32[(2 * n + 1) * Kp + k];
+      } else {
+        nu1 = (T)g.nu[(2 * n) * Kp + k];
+        nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
       }
-    } else {
-      for (int n = 0; n < 3; ++n) {
-        const int64_t kp = g.nbr[n * Kp + k];
-        if (kp < 0) continue;
-        T nu1, nu2;
-        if constexpr (sizeof(T) == 4) {   // the FP32 copies: the same values, half the bytes
-          nu1 = g.nu32[(2 * n) * Kp + k];
-          nu2 = g.nu32[(2 * n + 1) * Kp + k];
-        } else {
-          nu1 = (T)g.nu[(2 * n) * Kp + k];
-          nu2 = (T)g.nu[(2 * n + 1) * Kp + k];
-        }
 #pragma unroll
-        for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
-        if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
-        else block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
-      }
+      for (int j = 0; j < N; ++j) z[j] = nu1 * Z1[vidx(kp, j, N)] + nu2 * Z2[vidx(kp, j, N)];
+      if constexpr (PACKED) block_mv_bp<N, BT, T>(blocks, k, 2 + n, NSLOT, tail, z, t);
+      else block_mv<N, BT, T>(blocks, k, 2 + n, NSLOT, z, t);
     }
   }
   const T a2 = (T)(alpha * g.area2[k]);
@@ -379,15 +476,13 @@ __device__ inline double div_row(const Geo& g, const T* __restrict__ sm,
 
 // y = alpha M C + tau (eta S' C + sum_m B^m Z^m); partials (optional): per-block
 // sums of <C, y>, the CG curvature p^T A p fused into the apply
-template <int N, class T, class BT, bool BLOCKS, bool TR>
+template <int N, class T, class BT, bool BLOCKS>
 __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ refs,
                                              const BT* __restrict__ blocks,
                                              const T* __restrict__ C, const T* __restrict__ Z1,
                                              const T* __restrict__ Z2, double alpha, double tau,
                                              double eta, T* __restrict__ y,
-                                             double* __restrict__ partials,
-                                             const float* __restrict__ sig,
-                                             const float* __restrict__ lift) {
+                                             double* __restrict__ partials) {
   constexpr bool LDSR = refs_in_lds<N, T>();
   static_assert(LDSR || sizeof(T) == 8, "FP32 reference matrices always fit in LDS");
   __shared__ __align__(16) T smem[LDSR ? ref_size<N, T>() : 1];
@@ -401,8 +496,7 @@ __global__ void __launch_bounds__(256) k_div(Geo g, const double* __restrict__ r
   }
   const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (k < g.Kpad)
-    s = div_row<N, T, BT, BLOCKS, TR>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k, sig, lift);
+  if (k < g.Kpad) s = div_row<N, T, BT, BLOCKS>(g, sm, blocks, C, Z1, Z2, alpha, tau, eta, y, k);
   if (partials == nullptr) return;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -495,14 +589,16 @@ __global__ void k_export_rows(int64_t n, const int32_t* __restrict__ elems, int 
   dst[t] = src[bgidx(elems[i], s, f / 2, ns, NG, 2) + (f & 1)];
 }
 
-// d_h at the Gauss points of the three edges of each triangle, in its own
-// parametrisation: dE[k][n][q] = sum_l D_kl phi_l(point q of reference edge n)
-// (FP64 sums, stored FP32; zero on padding triangles)
+// d_h at the points of the quadrature form, once per step from the FP64 tiled
+// coefficients D (FP64 sums, stored FP32; zero on padding triangles):
+//   dE[k][n][q]  = sum_l D_kl phi_l(point q of reference edge n),
+//   dvol[k][q]   = w_q sum_l D_kl phi_l(x_q)  (the exact volume rule)
 template <int N>
 __global__ void __launch_bounds__(256) k_edge_d(Geo g, const double* __restrict__ D,
                                                 const double* __restrict__ trace64,
-                                                float* __restrict__ dE) {
-  constexpr int Q = edge_trace_points(N), NQ = 3 * Q;
+                                                const double* __restrict__ vol64,
+                                                float* __restrict__ dE, float* __restrict__ dvol) {
+  constexpr int Q = edge_trace_points(N), NQ = 3 * Q, RV = vol_points(N);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.Kpad) return;
   double d[N];
@@ -513,6 +609,12 @@ __global__ void __launch_bounds__(256) k_edge_d(Geo g, const double* __restrict_
 #pragma unroll
     for (int l = 0; l < N; ++l) v += trace64[r * N + l] * d[l];
     dE[vidx(k, r, NQ)] = (float)v;
+  }
+  for (int r = 0; r < RV; ++r) {
+    double v = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) v += vol64[r * N + l] * d[l];
+    dvol[vidx(k, r, RV)] = (float)v;
   }
 }
 
@@ -530,15 +632,15 @@ void launch_grad(int N, int vt, const Geo& g, const double* refs, const float* r
   if (vt == VT_F64) {
     LDG_SWITCH_N_P6(N, (k_grad<NT, double, false><<<nb, 256, 0, st>>>(
                         g, refs, refs, (const double*)C, (const double*)J1, (const double*)J2,
-                        (double*)Z1, (double*)Z2, nullptr, nullptr, nullptr)));
+                        (double*)Z1, (double*)Z2, nullptr, nullptr, nullptr, nullptr, 0.0f)));
   } else if (tr) {
     LDG_SWITCH_N_P6(N, (k_grad<NT, float, true><<<nb, 256, 0, st>>>(
                         g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
-                        (float*)Z1, (float*)Z2, tr->dE, tr->trace, tr->sig)));
+                        (float*)Z1, (float*)Z2, tr->dE, tr->trace, tr->sig, tr->pen, tr->eta)));
   } else {
     LDG_SWITCH_N_P6(N, (k_grad<NT, float, false><<<nb, 256, 0, st>>>(
                         g, refs, refs32, (const float*)C, (const float*)J1, (const float*)J2,
-                        (float*)Z1, (float*)Z2, nullptr, nullptr, nullptr)));
+                        (float*)Z1, (float*)Z2, nullptr, nullptr, nullptr, nullptr, 0.0f)));
   }
 }
 
@@ -547,48 +649,39 @@ void launch_div(int N, int vt, int bt, const Geo& g, const double* refs, const v
                 double eta, void* y, hipStream_t st, const Reducer* red, const EdgeTraces* tr) {
   const unsigned nb = nblk(g.Kpad, 256);
   double* parts = red ? red->partials : nullptr;
-  const float* sig = tr ? tr->sig : nullptr;
-  const float* lift = tr ? tr->lift : nullptr;
-  if (blocks == nullptr) {   // matrix-free: the terms without blocks
+  if (tr) {   // FP32 quadrature form: no stored blocks, penalty from the gradient half
+    LDG_SWITCH_N_P6(N, (k_div_q<NT><<<nb, 256, 0, st>>>(
+                        g, (const float*)C, (const float*)Z1, (const float*)Z2, tr->pen, alpha, tau,
+                        (float*)y, parts, tr->sig, tr->dvol, tr->vtab, tr->lift)));
+  } else if (blocks == nullptr) {   // matrix-free: the terms without blocks
     if (vt == VT_F64) {
-      LDG_SWITCH_N_P6(N, (k_div<NT, double, double, false, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, double, double, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const double*)C, (const double*)Z1,
-                          (const double*)Z2, alpha, tau, eta, (double*)y, parts, nullptr,
-                          nullptr)));
+                          (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
     } else {
-      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, false, false><<<nb, 256, 0, st>>>(
+      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, false><<<nb, 256, 0, st>>>(
                           g, refs, nullptr, (const float*)C, (const float*)Z1, (const float*)Z2,
-                          alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
+                          alpha, tau, eta, (float*)y, parts)));
     }
   } else if (vt == VT_F64) {
-    LDG_SWITCH_N_P6(N, (k_div<NT, double, double, true, false><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, double, double, true><<<nb, 256, 0, st>>>(
                         g, refs, (const double*)blocks, (const double*)C, (const double*)Z1,
-                        (const double*)Z2, alpha, tau, eta, (double*)y, parts, nullptr, nullptr)));
+                        (const double*)Z2, alpha, tau, eta, (double*)y, parts)));
   } else if (bt == BT_F32) {
-    if (tr) {
-      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true, true><<<nb, 256, 0, st>>>(
-                          g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
-                          (const float*)Z2, alpha, tau, eta, (float*)y, parts, sig, lift)));
-    } else {
-      LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true, false><<<nb, 256, 0, st>>>(
-                          g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
-                          (const float*)Z2, alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
-    }
-  } else if (tr) {
-    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true, true><<<nb, 256, 0, st>>>(
-                        g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y, parts, sig, lift)));
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, float, true><<<nb, 256, 0, st>>>(
+                        g, refs, (const float*)blocks, (const float*)C, (const float*)Z1,
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   } else {
-    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true, false><<<nb, 256, 0, st>>>(
+    LDG_SWITCH_N_P6(N, (k_div<NT, float, bf16, true><<<nb, 256, 0, st>>>(
                         g, refs, (const bf16*)blocks, (const float*)C, (const float*)Z1,
-                        (const float*)Z2, alpha, tau, eta, (float*)y, parts, nullptr, nullptr)));
+                        (const float*)Z2, alpha, tau, eta, (float*)y, parts)));
   }
   if (red) reduce_partials((int)nb, red->partials, red->result, st, red->cg, red->cg_mode);
 }
 
-void launch_edge_d(int N, const Geo& g, const double* D, const double* trace64, float* dE,
-                   hipStream_t st) {
-  LDG_SWITCH_N_P6(N, (k_edge_d<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(g, D, trace64, dE)));
+void launch_edge_d(int N, const Geo& g, const double* D, const EdgeTraces& tr, hipStream_t st) {
+  LDG_SWITCH_N_P6(N, (k_edge_d<NT><<<nblk(g.Kpad, 256), 256, 0, st>>>(
+                         g, D, tr.trace64, tr.vol64, tr.dE, tr.dvol)));
 }
 
 void launch_bj_apply(int N, int vt, int bt, const Geo& g, const void* bj, const void* r, void* z,

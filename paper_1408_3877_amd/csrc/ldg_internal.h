@@ -28,6 +28,22 @@ __host__ __device__ constexpr int edge_trace_points(int N) {
   while ((p + 1) * (p + 2) / 2 < N) ++p;
   return (3 * p + 2) / 2;
 }
+// The volume term sum_m G^m Z^m of the same apply as a quadrature: the
+// integrand dphi_i/dx_m d_h Z_h has degree D = 3p - 1, and the Gauss points of
+// the unit square collapsed onto the triangle (x1 = u, x2 = (1 - u) v, weight
+// (1 - u)) integrate it exactly with ceil((D + 2) / 2) points in u and
+// ceil((D + 1) / 2) in v; none at p = 0, where the term vanishes
+__host__ __device__ constexpr int vol_points_u(int N) {
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 < N) ++p;
+  return p == 0 ? 0 : (3 * p - 1 + 3) / 2;
+}
+__host__ __device__ constexpr int vol_points_v(int N) {
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 < N) ++p;
+  return p == 0 ? 0 : (3 * p - 1 + 2) / 2;
+}
+__host__ __device__ constexpr int vol_points(int N) { return vol_points_u(N) * vol_points_v(N); }
 // rows (coefficient index l) of the FP64 / FP32 A-operand tables of the MFMA
 // block assembly: its k-steps of four cover l < 4 ceil(N / 4); 16 rows for
 // N <= 15, 24 for N = 21, 28 for N = 28
