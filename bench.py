@@ -94,7 +94,8 @@ def timed_run(Solver, torch, cfg, coordV, V0T, kind, dT, prec, learned, weights,
     t0 = time.perf_counter()
     s = Solver(coordV, V0T, kind, cfg["p"], rtol=args.rtol, restart=args.restart,
                max_iters=cfg.get("max_iters", 20000), precision=prec, inner_rtol=args.inner_rtol,
-               precond=1 if learned else 0, keep_direction=not args.fresh_cg_sweeps)
+               precond=1 if learned else 0, keep_direction=not args.fresh_cg_sweeps,
+               edge_traces=not args.stored_blocks)
     if learned:
         s.gnn_set_mode("factor")
         s.gnn_factor_storage(args.fac_storage)
@@ -305,6 +306,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="relative tolerance of each inner solve of the mixed modes (1e-2: fewest "
                          "CG iterations on the combined workload in a sweep over 1e-4 .. 1e-1)")
+    ap.add_argument("--stored-blocks", action="store_true",
+                    help="mixed modes: inner solves apply the stored FP32/BF16 blocks instead of "
+                         "the FP32 quadrature form")
     ap.add_argument("--fresh-cg-sweeps", action="store_true",
                     help="start CG afresh in every refinement sweep instead of continuing "
                          "from the previous sweep's search direction")
@@ -359,9 +363,9 @@ def main():
                    "bj_apply": "k_bj_apply (block-Jacobi apply)",
                    "grad": "k_grad (operator gradient half)",
                    "mf": "k_mf_blocks (matrix-free block terms on the matrix cores)"}[name]
-    traffic = measured_traffic(args.config, name, args.precision,
-                               args.precond + ("-" + args.fac_storage if learned else ""),
-                               args.matrix_free)
+    traffic = None if args.stored_blocks else measured_traffic(
+        args.config, name, args.precision, args.precond + ("-" + args.fac_storage if learned else ""),
+        args.matrix_free)
     if name == "mf":
         # bound by the matrix cores: useful flops of the contraction per launch
         flops = kv["flops"] / max(kv["launches"], 1)
@@ -381,8 +385,12 @@ def main():
         args.precision,
         "learned factored (%s factor blocks)" % args.fac_storage if learned else "block-Jacobi",
         "CG" if infos[-1]["krylov"] == 2 else "GMRES(%d)" % args.restart,
-        "" if prec == 0 else " + FP64 refinement (inner rtol %g%s)" % (
-            args.inner_rtol, "" if infos[-1]["krylov"] != 2 else
+        "" if prec == 0 else " + FP64 refinement (inner rtol %g, %s%s)" % (
+            args.inner_rtol,
+            "matrix-free operator" if args.matrix_free else
+            "stored %s operator blocks" % args.precision if args.stored_blocks
+            else "operator in FP32 quadrature form",
+            "" if infos[-1]["krylov"] != 2 else
             ", fresh CG per sweep" if args.fresh_cg_sweeps else ", CG direction kept across sweeps"))
     stationary = bool(cfg.get("stationary"))
     res = {

@@ -118,13 +118,15 @@ typedef struct {
                          the kept one, and its step length minimises along it.  0: every
                          sweep starts CG afresh from p = P r.  GMRES sweeps always
                          restart, and so does FP64 CG */
-  int edge_traces;    /* mixed modes with LDG_QUAD_EXACT.  1 (default): the FP32 apply
-                         forms the off-diagonal edge terms of B^m (eq:hatRoffdiag) from
-                         the neighbours' traces of d_h nu.Z_h at ceil((3p+1)/2) Gauss
-                         points per edge, which integrate them exactly, and reads only
-                         the two diagonal stored blocks of each triangle.  0: all five
-                         stored blocks.  Ignored in FP64, with LDG_QUAD_PAPER and in
-                         the matrix-free apply */
+  int edge_traces;    /* mixed modes with LDG_QUAD_EXACT.  1 (default): the FP32 apply of
+                         the inner solves in quadrature form, with no stored blocks read:
+                         the volume terms of B^m (eq:hatG) from d_h at the points of a
+                         collapsed Gauss rule exact for their degree 3p-1, its edge terms
+                         (eq:hatRdiag, eq:hatRoffdiag) from the traces of d_h nu.Z_h at
+                         ceil((3p+1)/2) Gauss points per edge (exact for degree 3p),
+                         which the gradient half writes and the neighbours read.  0: the
+                         five stored FP32 or BF16 blocks.  Ignored in FP64, with
+                         LDG_QUAD_PAPER and in the matrix-free apply */
 } ldg_options;
 
 typedef struct {
