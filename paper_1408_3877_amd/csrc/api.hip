@@ -1476,19 +1476,20 @@ ldg_status ldg_create(const double* coordV, int64_t numV, const int32_t* V0T, in
             lift32[(n * Q + q) * N + i] = (float)(wq[q] * ph);
           }
         }
-      // volume rule: Gauss points of the unit square collapsed onto the triangle
+      // volume rule: the unit square collapsed onto the triangle, Gauss-Jacobi
+      // points for the weight 1 - u (the Jacobian) in u, Gauss-Legendre in v
       const int nqu = vol_points_u(N), nqv = vol_points_v(N), RV = nqu * nqv;
       std::vector<double> vol64(std::max(RV, 1) * N, 0.0);
       std::vector<float> vtab(std::max(RV, 1) * 3 * N, 0.0f);
       if (RV > 0) {
         std::vector<double> gu, gwu, gv, gwv;
-        gauss_legendre(nqu, gu, gwu);
+        gauss_jacobi10(nqu, gu, gwu);
         gauss_legendre(nqv, gv, gwv);
         for (int a = 0; a < nqu; ++a)
           for (int b = 0; b < nqv; ++b) {
             const int q = a * nqv + b;
             const double x1 = gu[a], x2 = (1.0 - gu[a]) * gv[b];
-            const double w = gwu[a] * gwv[b] * (1.0 - gu[a]);
+            const double w = gwu[a] * gwv[b];
             for (int i = 0; i < N; ++i) {
               vol64[q * N + i] = w * phi_hat(i, x1, x2);
               vtab[(q * 3 + 0) * N + i] = (float)phi_hat(i, x1, x2);

@@ -194,6 +194,45 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+// Gauss-Jacobi on (0,1) for the weight (1 - u): the roots of the Jacobi
+// polynomial P_n^(1,0)(x), x = 2u - 1, by Newton's method from the
+// Gauss-Legendre nodes, with the three-term recurrence
+//   (k+1)(2k-1) P_k = ((2k+1)(2k-1) x + 1) P_{k-1} - (k-1)(2k+1) P_{k-2},
+// P_0 = 1, P_1 = (3x + 1)/2, and the weights 4 / ((1 - x^2) P_n'(x)^2) on
+// (-1,1) for (1 - x), i.e. 1 / ((1 - x^2) P_n'(x)^2) on (0,1) for (1 - u)
+// (Golub and Welsch's weights for this family in closed form).
+void gauss_jacobi10(int n, std::vector<double>& x, std::vector<double>& w) {
+  std::vector<double> g, gw;
+  gauss_legendre(n, g, gw);
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  auto eval = [n](double t, double& P, double& dP) {
+    double p0 = 1.0, d0 = 0.0, p1 = 0.5 * (3.0 * t + 1.0), d1 = 1.5;
+    if (n == 0) { P = p0; dP = d0; return; }
+    for (int k = 2; k <= n; ++k) {
+      const double a = (2.0 * k + 1.0) * (2.0 * k - 1.0), b = (k - 1.0) * (2.0 * k + 1.0);
+      const double c = (k + 1.0) * (2.0 * k - 1.0);
+      const double p2 = ((a * t + 1.0) * p1 - b * p0) / c;
+      const double d2 = (a * p1 + (a * t + 1.0) * d1 - b * d0) / c;
+      p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    P = p1;
+    dP = d1;
+  };
+  for (int k = 0; k < n; ++k) {
+    double t = 2.0 * g[k] - 1.0, P = 0.0, dP = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      eval(t, P, dP);
+      const double dt = P / dP;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    eval(t, P, dP);
+    x[k] = 0.5 * (t + 1.0);
+    w[k] = 1.0 / ((1.0 - t * t) * dP * dP);
+  }
+}
+
 namespace {
 // Gauss points of the unit square collapsed onto the reference triangle:
 // x1 = u, x2 = (1-u) v, Jacobian 1-u, n points per direction.

@@ -346,6 +346,7 @@ __global__ void __launch_bounds__(256) k_div_q(Geo g, const float* __restrict__ 
         load_vec<N, float>(Z2, k, z2);
         const float B11 = g.B32[k], B12 = g.B32[Kp + k], B21 = g.B32[2 * Kp + k],
                     B22 = g.B32[3 * Kp + k];
+#pragma unroll 2
         for (int q = 0; q < RV; ++q) {
           const float* ph = vt + q * 3 * N;
           float zq1 = 0.0f, zq2 = 0.0f;

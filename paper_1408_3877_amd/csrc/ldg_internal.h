@@ -29,14 +29,15 @@ __host__ __device__ constexpr int edge_trace_points(int N) {
   return (3 * p + 2) / 2;
 }
 // The volume term sum_m G^m Z^m of the same apply as a quadrature: the
-// integrand dphi_i/dx_m d_h Z_h has degree D = 3p - 1, and the Gauss points of
-// the unit square collapsed onto the triangle (x1 = u, x2 = (1 - u) v, weight
-// (1 - u)) integrate it exactly with ceil((D + 2) / 2) points in u and
-// ceil((D + 1) / 2) in v; none at p = 0, where the term vanishes
+// integrand dphi_i/dx_m d_h Z_h has degree D = 3p - 1.  The unit square
+// collapsed onto the triangle (x1 = u, x2 = (1 - u) v, Jacobian 1 - u) with
+// Gauss-Jacobi points for the weight 1 - u in u and Gauss-Legendre points in v
+// integrates it exactly with ceil((D + 1) / 2) points in each; none at p = 0,
+// where the term vanishes
 __host__ __device__ constexpr int vol_points_u(int N) {
   int p = 0;
   while ((p + 1) * (p + 2) / 2 < N) ++p;
-  return p == 0 ? 0 : (3 * p - 1 + 3) / 2;
+  return p == 0 ? 0 : (3 * p - 1 + 2) / 2;
 }
 __host__ __device__ constexpr int vol_points_v(int N) {
   int p = 0;
@@ -89,6 +90,7 @@ int num_basis(int p);
 double phi_hat(int i, double x1, double x2);
 double dphi_hat(int i, int m, double x1, double x2);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);  // on (0,1)
+void gauss_jacobi10(int n, std::vector<double>& x, std::vector<double>& w);  // on (0,1), weight 1-u
 void projection_rule(int p, std::vector<double>& q1, std::vector<double>& q2,
                      std::vector<double>& w);
 RefData build_refdata(int p, int policy);   // policy: ldg_quad_policy
