@@ -360,8 +360,10 @@ ldg_status ldg_apply_schur(ldg_ctx* ctx, double dt, const double* C, double* y);
 
 /*
  * The same operator evaluated as the inner solves of the mixed modes do:
- * C rounded to FP32, both halves in FP32 arithmetic with the context's FP32
- * or BF16 copies of the blocks of the last ldg_assemble, y widened to FP64.
+ * C rounded to FP32, both halves in FP32 arithmetic, y widened to FP64.  The
+ * block terms come from the coefficient of the last ldg_assemble: in the
+ * quadrature form of ldg_options.edge_traces (the default with
+ * LDG_QUAD_EXACT), else from the context's FP32 or BF16 copies of its blocks.
  * C, y: device K x N, element-major.  LDG_EINVAL in an FP64 context.
  */
 ldg_status ldg_apply_schur_lowp(ldg_ctx* ctx, double dt, const double* C, double* y);

@@ -37,16 +37,18 @@ def _steps(cV, V0T, kind, p, wkind, nsteps, dt, **kw):
         assert max(errs) < 1e-10, errs
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
-def test_one_triangle(p):
-    # K = 1: one lane of one tile, three Dirichlet edges, no neighbour
+@pytest.mark.parametrize("p,precision", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (0, 2), (3, 2)])
+def test_one_triangle(p, precision):
+    # K = 1: one lane of one tile, three Dirichlet edges, no neighbour (the
+    # mixed mode's quadrature form then has only the triangle's own traces;
+    # at p = 0 no volume points)
     cV = np.array([[0.0, 0.0], [1.0, 0.0], [0.2, 0.9]])
     V0T = np.array([[0, 1, 2]], dtype=np.int32)
     kind = np.array([[1, 1, 1]], dtype=np.int8)
-    _steps(cV, V0T, kind, p, SMOOTH1, 2, 0.05)
+    _steps(cV, V0T, kind, p, SMOOTH1, 2, 0.05, precision=precision)
 
 
-@pytest.mark.parametrize("p,precision", [(1, 0), (2, 0), (4, 0), (4, 2)])
+@pytest.mark.parametrize("p,precision", [(0, 2), (1, 0), (2, 0), (2, 1), (4, 0), (4, 2)])
 def test_two_triangles_with_a_neumann_side(p, precision):
     # the grid of Fig. 6: two triangles sharing the diagonal of the unit square,
     # one Neumann side (local edge 0 of the first triangle, on x = 1)
